@@ -1,0 +1,167 @@
+/*
+ * Plain, single-threaded CPU oracle of the ELAS dense-stereo hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. This code is the parity reference for the HIP
+ * library. It shares no source, header, table or helper with that library,
+ * and nothing in the product path may call it. Only the test-suite, the smoke
+ * check and the benchmark's CPU-baseline leg load it.
+ *
+ * What it computes follows the ELAS description in Section III-A of
+ * Rahnama et al., "Real-Time Dense Stereo Matching with ELAS on FPGA
+ * Accelerated Embedded Devices" (arXiv 1802.07210): gradient (Sobel)
+ * descriptors, sparse support points chosen by a first/second-minimum
+ * ambiguity test (Section VI-B, eq. 1-2), consistency and redundancy filtering
+ * of the support points (Section III-A, Fig. 7A), a Delaunay mesh of the
+ * support points giving a slanted-plane prior remapped to a per-pixel prior
+ * matrix (Section VI-D), grid vectors pooled per region and widened by +-1
+ * (Fig. 2), dense SAD matching restricted to the prior's candidates, and a
+ * final left/right consistency check. Where the paper is silent, the
+ * readings are stated at each function in elas_oracle_*.c.
+ *
+ * Conventions: u is the column, v the row (growing downwards). Left pixel
+ * (u, v) corresponds to right pixel (u - d, v). Disparity maps are int16 with
+ * -1 = invalid. All integer arithmetic is exact. Floating point appears in
+ * three places only: the ratio test (one FP32 multiply), the prior table
+ * (double, rounded to integers) and the plane mean (FP32, fixed order,
+ * no contraction; the build uses -ffp-contract=off).
+ */
+#ifndef ELAS_ORACLE_H
+#define ELAS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_params {
+  int32_t disp_min;            /* smallest disparity (>= 0) */
+  int32_t disp_max;            /* largest disparity; D = max - min + 1 <= 256 */
+  float   support_threshold;   /* ratio test: accept iff m1 < thr * m2 (FP32) */
+  int32_t support_texture;     /* minimum texture of a 64-byte support descriptor */
+  int32_t candidate_stepsize;  /* lattice step s of support candidates */
+  int32_t incon_window_size;   /* half window, in lattice units */
+  int32_t incon_threshold;     /* |d' - d| <= this counts as consistent */
+  int32_t incon_min_support;   /* consistent neighbours needed to keep a point */
+  int32_t redun_max_dist;      /* redundancy search distance, lattice units */
+  int32_t redun_threshold;     /* |d' - d| <= this counts as redundant */
+  int32_t grid_size;           /* grid-vector region size in pixels */
+  float   beta;                /* likelihood scale */
+  float   gamma;               /* prior floor */
+  float   sigma;               /* prior width */
+  int32_t sradius;             /* plane candidates: |d - d_plane| <= sradius */
+  int32_t match_texture;       /* minimum texture of a 16-byte dense descriptor */
+  int32_t lr_threshold;        /* left/right agreement tolerance */
+  int32_t full_search;         /* 1: dense candidates = every admissible d */
+} orc_params;
+
+/* ---- stage 1: gradients and descriptors -------------------------------- */
+void orc_sobel(const uint8_t* img, int32_t w, int32_t h, int32_t stride,
+               int16_t* du, int16_t* dv);
+/* 16 bytes per pixel, row-major [h][w][16]; undefined pixels are all-zero. */
+void orc_descriptors(const uint8_t* img, int32_t w, int32_t h, int32_t stride,
+                     uint8_t* desc);
+
+/* ---- prior table --------------------------------------------------------- */
+void orc_prior_lut(const orc_params* p, int32_t* lut /* D entries */);
+
+/* ---- stage 2: support matching on the candidate lattice ------------------ */
+/* Lattice geometry: columns u = s*k with 4 <= u <= w-5, rows likewise. */
+void orc_lattice(const orc_params* p, int32_t w, int32_t h,
+                 int32_t* lw, int32_t* lh, int32_t* u0, int32_t* v0);
+void orc_support_match(const orc_params* p, const uint8_t* descL,
+                       const uint8_t* descR, int32_t w, int32_t h,
+                       int16_t* dcan /* lh*lw */, int64_t* evals);
+/* Ratio test exposed for unit tests: accept iff (float)m1 < thr*(float)m2. */
+int32_t orc_ratio_accept(float thr, int32_t m1, int32_t m2);
+
+/* ---- stage 3: support filtering ------------------------------------------ */
+void orc_filter_incon(const orc_params* p, const int16_t* in, int32_t lw,
+                      int32_t lh, int16_t* out);
+void orc_filter_redun(const orc_params* p, const int16_t* in, int32_t lw,
+                      int32_t lh, int32_t vertical, int16_t* out);
+
+/* ---- support lists --------------------------------------------------------
+ * ptsL/ptsR receive (u, v, d) triples; capacity lw*lh triples. Returns counts.
+ * corners receive the d of (0,0), (w-1,0), (0,h-1), (w-1,h-1). */
+void orc_support_lists(const orc_params* p, const int16_t* dcan, int32_t lw,
+                       int32_t lh, int32_t w, int32_t h,
+                       int32_t* ptsL, int32_t* nL, int32_t* cornersL,
+                       int32_t* ptsR, int32_t* nR, int32_t* cornersR);
+
+/* ---- triangulation -------------------------------------------------------
+ * pts: n distinct (u, v) pairs. The first four must be the image corners
+ * (0,0), (w-1,0), (0,h-1), (w-1,h-1) and every other point must lie strictly
+ * inside that rectangle. Writes at most 2n triangles as vertex-index triples
+ * (positively oriented) and returns their count, or -1 on bad input. */
+int32_t orc_delaunay(const int32_t* pts, int32_t n, int32_t* tris);
+/* Exact predicates, exposed for unit tests. */
+int64_t orc_orient(const int32_t* a, const int32_t* b, const int32_t* c);
+int64_t orc_incircle(const int32_t* a, const int32_t* b, const int32_t* c,
+                     const int32_t* d);
+
+/* Canonical triangle records: 9 ints (u,v,d) x 3 with vertices sorted by
+ * (v, u), records sorted lexicographically. Planes: 3 floats (a, b, c). */
+void orc_canonical_triangles(const int32_t* pts /* (u,v,d) */, const int32_t* tris,
+                             int32_t ntri, int32_t* recs);
+void orc_plane(const int32_t* rec, float* abc);
+
+/* ---- prior raster: per pixel owner triangle and d_plane -------------------
+ * recs/planes in canonical order; owner receives the index of the owning
+ * triangle (-1 when none); dplane receives the clamped rounded plane mean. */
+void orc_plane_map(const orc_params* p, const int32_t* recs, const float* planes,
+                   int32_t ntri, int32_t w, int32_t h, int32_t* owner,
+                   int16_t* dplane);
+
+/* ---- grid vectors -------------------------------------------------------- */
+void orc_grid_dims(const orc_params* p, int32_t w, int32_t h, int32_t* gw,
+                   int32_t* gh, int32_t* words);
+void orc_grid(const orc_params* p, const int32_t* pts, int32_t n, int32_t w,
+              int32_t h, uint64_t* grid /* gh*gw*words */);
+
+/* ---- dense matching: right_frame = 0 matches the left view against the
+ * right one, 1 the reverse. has_list = 0 means no support points (no plane,
+ * no grid). Returns the number of candidate evaluations. */
+int64_t orc_dense(const orc_params* p, const uint8_t* desc_self,
+                  const uint8_t* desc_other, const int16_t* dplane,
+                  const uint64_t* grid, int32_t has_list, const int32_t* lut,
+                  int32_t w, int32_t h, int32_t right_frame, int16_t* out);
+
+/* ---- final left/right check --------------------------------------------- */
+void orc_lrcheck(const orc_params* p, const int16_t* rawL, const int16_t* rawR,
+                 int32_t w, int32_t h, int16_t* outL, int16_t* outR);
+
+/* ---- whole pipeline with every intermediate ------------------------------ */
+typedef struct orc_trace {
+  int32_t w, h, lw, lh, gw, gh, words, D;
+  uint8_t* descL; uint8_t* descR;             /* h*w*16 */
+  int16_t* dcan_raw; int16_t* dcan_incon;     /* lh*lw */
+  int16_t* dcan_vert; int16_t* dcan_final;
+  int32_t nL, nR;
+  int32_t* ptsL; int32_t* ptsR;               /* (u,v,d) * n */
+  int32_t cornersL[4], cornersR[4];
+  int32_t ntriL, ntriR;
+  int32_t* recL; int32_t* recR;               /* 9 * ntri, canonical order */
+  float* planeL; float* planeR;               /* 3 * ntri */
+  int32_t* ownerL; int32_t* ownerR;           /* h*w */
+  int16_t* dplaneL; int16_t* dplaneR;         /* h*w */
+  uint64_t* gridL; uint64_t* gridR;           /* gh*gw*words */
+  int32_t* lut;                               /* D */
+  int16_t* rawL; int16_t* rawR;               /* h*w */
+  int16_t* outL; int16_t* outR;               /* h*w */
+  int64_t support_evals, dense_evals;
+  double stage_ms[6]; /* descriptor, support+filter, triangulate, raster+grid, dense, lrcheck */
+} orc_trace;
+
+/* Runs every stage; allocates the trace arrays (free with orc_trace_free).
+ * Returns 0, -1 if the inputs violate the preconditions (9 <= w, h <= 8192,
+ * 0 <= disp_min <= disp_max, D <= 256, positive step/grid/beta/gamma/sigma),
+ * or -2 if a triangulation failed its own consistency checks. */
+int32_t orc_process(const orc_params* p, const uint8_t* left, const uint8_t* right,
+                    int32_t w, int32_t h, int32_t stride, orc_trace* t);
+void orc_trace_free(orc_trace* t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
