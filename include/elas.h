@@ -1,0 +1,189 @@
+/*
+ * elas_mi355x: the data-parallel hot path of ELAS dense stereo on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Problem statement (Rahnama et al., arXiv 1802.07210, Sections I and III-A):
+ * a rectified 8-bit grey stereo pair goes in, dense left and right disparity
+ * maps come out. The path: gradient (Sobel) descriptors; sparse support
+ * points matched across the full disparity range and kept by a
+ * first/second-minimum ambiguity test (Section VI-B, eq. 1-2) plus a
+ * reverse check; consistency and redundancy filtering (Section III-A,
+ * Fig. 7A); a Delaunay mesh of the support points turned into an image-sized
+ * matrix of slanted-plane priors and one-hot grid vectors (Section VI-D,
+ * Fig. 2); per-pixel SAD matching over the candidates the prior allows; a
+ * final left/right consistency check. The paper's post-processing is not
+ * part of the path (Section III-A excludes it).
+ *
+ * Conventions: u is the column, v the row. Left pixel (u, v) corresponds to
+ * right pixel (u - d, v). Output maps are int16, row stride w, value -1 for
+ * invalid pixels, otherwise a disparity in [disp_min, disp_max].
+ *
+ * Error behaviour: every entry point returns ELAS_OK (0) or a negative
+ * ELAS_ERR_* code; no C++ exception crosses this interface. After a failure
+ * elas_last_error() describes it.
+ *
+ * Threading: a handle is not thread-safe. Calls on one handle must be
+ * ordered (one host thread, and either one stream or streams the caller
+ * synchronises). Different handles are independent.
+ */
+#ifndef ELAS_MI355X_H
+#define ELAS_MI355X_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define ELAS_API __attribute__((visibility("default")))
+#else
+#define ELAS_API
+#endif
+
+#define ELAS_OK 0
+#define ELAS_ERR_ARG (-1)          /* bad argument or parameter */
+#define ELAS_ERR_OOM (-2)          /* device or pinned host allocation failed */
+#define ELAS_ERR_HIP (-3)          /* a HIP runtime call failed; see elas_last_error */
+#define ELAS_ERR_UNSUPPORTED (-4)  /* parameters outside what the kernels support */
+#define ELAS_ERR_INTERNAL (-5)     /* an internal consistency check failed */
+
+/* Matching parameters. Defaults (elas_params_default) are the values the
+ * workloads use; fields the paper does not fix are the readings stated in
+ * each comment. */
+typedef struct elas_params {
+  int32_t disp_min;            /* smallest disparity, >= 0 (0) */
+  int32_t disp_max;            /* largest disparity; D = max-min+1 in 1..256 (127) */
+  float   support_threshold;   /* ambiguity test, eq. 1-2: keep iff m1 < t*m2 in FP32 (0.85) */
+  int32_t support_texture;     /* min texture of a 512-bit support descriptor (10) */
+  int32_t candidate_stepsize;  /* support candidate lattice step in pixels (5) */
+  int32_t incon_window_size;   /* consistency window half-size, lattice steps (5) */
+  int32_t incon_threshold;     /* |d'-d| <= this is consistent (5) */
+  int32_t incon_min_support;   /* consistent neighbours needed (5) */
+  int32_t redun_max_dist;      /* redundancy search distance, lattice steps (5) */
+  int32_t redun_threshold;     /* |d'-d| <= this is redundant (1) */
+  int32_t grid_size;           /* grid-vector region size in pixels, Fig. 2 (20) */
+  float   beta;                /* likelihood scale of the SAD energy (0.02) */
+  float   gamma;               /* floor of the plane prior (3) */
+  float   sigma;               /* width of the plane prior (1) */
+  int32_t sradius;             /* plane candidates |d - d_plane| <= sradius (2) */
+  int32_t match_texture;       /* min texture of a 128-bit dense descriptor (1) */
+  int32_t lr_threshold;        /* left/right agreement tolerance (2) */
+  int32_t full_search;         /* 1: dense candidates = every admissible d (0) */
+} elas_params;
+
+typedef struct elas_handle elas_handle;
+
+/* Counters of the most recent elas_process call on a handle. */
+typedef struct elas_stats {
+  int64_t support_evals;       /* 512-bit SAD evaluations, both search directions */
+  int64_t dense_evals;         /* candidate evaluations summed over both dense maps */
+  int32_t n_support_left;      /* support points, left view (corners excluded) */
+  int32_t n_support_right;     /* support points, right view */
+  int32_t n_tri_left;          /* triangles of the left-view mesh */
+  int32_t n_tri_right;
+  double  host_mesh_ms;        /* host time spent triangulating (both views) */
+} elas_stats;
+
+/* Fills *p with the default parameters. */
+ELAS_API void elas_params_default(elas_params* p);
+
+/* Validates *p and creates a handle. Computes the prior table; makes no HIP
+ * call (device memory is allocated by the first elas_process per image size).
+ * Returns ELAS_ERR_ARG for invalid values (null pointers, D outside 1..256,
+ * negative windows or thresholds, step or grid size < 1, non-positive or
+ * non-finite beta/gamma/sigma) and ELAS_ERR_UNSUPPORTED when the prior
+ * energies exceed the kernels' packed-key range (|lut[0]| > 2^22). */
+ELAS_API int elas_create(const elas_params* p, elas_handle** out);
+
+/* Frees the handle and everything it owns. Waits for its pending work.
+ * NULL is accepted. */
+ELAS_API int elas_destroy(elas_handle* h);
+
+/* Computes both disparity maps of one pair.
+ *   left, right      device pointers, uint8, h_px rows of `stride` bytes
+ *                    (the first w bytes of each row are used); caller-owned.
+ *   w, h_px          image size, 9..8192 each.
+ *   stride           row pitch of left and right in bytes, >= w.
+ *   stream           HIP stream the work is ordered on (0 = null stream).
+ *   disp_left/right  device pointers, int16, w*h_px elements, row stride w;
+ *                    caller-owned.
+ * Stream-ordered: outputs are valid once `stream` reaches the end of the
+ * enqueued work. The call itself blocks the calling thread while the support
+ * stage finishes, because the triangulation runs on the host between the
+ * support and dense stages (the same CPU/accelerator split the paper uses,
+ * Section IV). Inputs must stay valid until then. Device buffers for the
+ * image size are allocated on first use and cached in the handle. */
+ELAS_API int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right,
+                          int32_t w, int32_t h_px, int32_t stride, hipStream_t stream,
+                          int16_t* disp_left, int16_t* disp_right);
+
+/* Copies the counters of the last elas_process call (synchronises with its
+ * stream first). */
+ELAS_API int elas_get_stats(elas_handle* h, elas_stats* out);
+
+/* Describes the last failure on h (or of elas_create when h is NULL). The
+ * string belongs to the library and stays valid until the next call. */
+ELAS_API const char* elas_last_error(const elas_handle* h);
+
+/* Intermediate results of the last elas_process call, for stage-by-stage
+ * verification. Layouts (row-major; w, h image size; lw, lh lattice size;
+ * gw, gh grid size; n list length; ntri triangle count):
+ *   DESC_*     uint8   [h][w][16]   16-byte descriptor, all-zero if undefined
+ *   DCAN_*     int16   [lh][lw]     support disparity per lattice point or -1
+ *                                   (RAW: matched, INCON: after consistency,
+ *                                   VERT/FINAL: after vertical/horizontal
+ *                                   redundancy)
+ *   SUPPORT_*  int32   [n][3]       (u, v, d); left in lattice order, right
+ *                                   sorted by (v, u)
+ *   CORNERS    int32   [8]          d of (0,0),(w-1,0),(0,h-1),(w-1,h-1),
+ *                                   left view then right view (-1 if no list)
+ *   TRI_*      int32   [ntri][9]    (u,v,d) x 3, vertices sorted by (v,u),
+ *                                   triangles sorted by their vertex triples
+ *   PLANE_*    float   [ntri][3]    (a, b, c) of d = a*u + b*v + c
+ *   OWNER_*    int32   [h][w]       owning triangle index or 0x7FFFFFFF
+ *   DPLANE_*   int16   [h][w]       plane prior disparity or -1
+ *   GRID_*     uint64  [gh][gw][ceil(D/64)]  bit d-disp_min set if allowed
+ *   RAW_*      int16   [h][w]       dense maps before the final check
+ *   LUT        int32   [D]          prior energy by |d - d_plane|
+ * `bytes` is the capacity of dst_host; *needed (if not NULL) receives the
+ * size of the intermediate. Returns ELAS_ERR_ARG if the capacity is too
+ * small or no call has completed. Synchronises with the last call's stream. */
+enum elas_intermediate {
+  ELAS_I_DESC_LEFT = 0, ELAS_I_DESC_RIGHT = 1,
+  ELAS_I_DCAN_RAW = 2, ELAS_I_DCAN_INCON = 3, ELAS_I_DCAN_VERT = 4, ELAS_I_DCAN_FINAL = 5,
+  ELAS_I_SUPPORT_LEFT = 6, ELAS_I_SUPPORT_RIGHT = 7, ELAS_I_CORNERS = 8,
+  ELAS_I_TRI_LEFT = 9, ELAS_I_TRI_RIGHT = 10,
+  ELAS_I_PLANE_LEFT = 11, ELAS_I_PLANE_RIGHT = 12,
+  ELAS_I_OWNER_LEFT = 13, ELAS_I_OWNER_RIGHT = 14,
+  ELAS_I_DPLANE_LEFT = 15, ELAS_I_DPLANE_RIGHT = 16,
+  ELAS_I_GRID_LEFT = 17, ELAS_I_GRID_RIGHT = 18,
+  ELAS_I_RAW_LEFT = 19, ELAS_I_RAW_RIGHT = 20,
+  ELAS_I_LUT = 21,
+  ELAS_I_COUNT = 22
+};
+ELAS_API int elas_get_intermediate(elas_handle* h, int32_t which, void* dst_host,
+                                   int64_t bytes, int64_t* needed);
+
+/* The mesh step on its own, on the host (Section III-A: Delaunay
+ * triangulation of the support points and one slanted plane per triangle;
+ * Section IV leaves this sequential step on the CPU). Makes no HIP call.
+ *   pts      n support points as (u, v, d) int32 triples, distinct, each
+ *            strictly inside the image (0 < u < w-1, 0 < v < h-1).
+ *   corners  d of the image corners (0,0), (w-1,0), (0,h-1), (w-1,h-1).
+ *   recs_out capacity (2n+2)*9 int32: canonical triangles, layout of TRI_*.
+ *   planes_out capacity (2n+2)*3 float: planes, layout of PLANE_*.
+ * The mesh is the Delaunay triangulation of corners + points in which every
+ * set of four or more co-circular points is split as a fan from its
+ * (v, u)-smallest point. Returns the triangle count 2n+2, ELAS_ERR_ARG for
+ * bad input (n < 1, null pointers, points outside, duplicates), or
+ * ELAS_ERR_INTERNAL. */
+ELAS_API int elas_triangulate(const int32_t* pts, int32_t n, const int32_t* corners, int32_t w,
+                              int32_t h, int32_t* recs_out, float* planes_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ELAS_MI355X_H */

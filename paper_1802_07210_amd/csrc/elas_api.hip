@@ -1,0 +1,582 @@
+// C-ABI of elas_mi355x: parameter validation, the prior table, per-size
+// device buffers, and the stage chain of one stereo pair.
+//
+// Stage chain of elas_process on the caller's stream:
+//   k_descriptor (both views) -> k_support -> k_incon -> k_lists
+//   -> [host: wait for the lists, Delaunay meshes of both views (two host
+//       threads), raster records -> one host-to-device copy]
+//   -> k_raster -> k_dense (both views) -> k_lrcheck.
+// The host step sits where the paper's ARM core sits between its two FPGA
+// phases (Section IV, Fig. 3).
+#include <algorithm>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+#include <chrono>
+
+#include "elas.h"
+#include "elas_internal.h"
+
+using namespace elas;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// One background host thread that builds the right view's mesh while the
+// calling thread builds the left one.
+class Worker {
+ public:
+  Worker() : th_([this] { loop(); }) {}
+  ~Worker() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    th_.join();
+  }
+  void submit(std::function<void()> f) {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      job_ = std::move(f);
+      pending_ = true;
+    }
+    cv_.notify_all();
+  }
+  void wait() {
+    std::unique_lock<std::mutex> lk(m_);
+    cv_.wait(lk, [this] { return !pending_; });
+  }
+
+ private:
+  void loop() {
+    std::unique_lock<std::mutex> lk(m_);
+    for (;;) {
+      cv_.wait(lk, [this] { return stop_ || (pending_ && job_); });
+      if (stop_) return;
+      std::function<void()> f = std::move(job_);
+      job_ = nullptr;
+      lk.unlock();
+      f();
+      lk.lock();
+      pending_ = false;
+      cv_.notify_all();
+    }
+  }
+  std::mutex m_;
+  std::condition_variable cv_;
+  std::function<void()> job_;
+  bool pending_ = false, stop_ = false;
+  std::thread th_;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device and pinned host memory for one image size.
+struct Buffers {
+  Geometry g{};
+  void* dev_block = nullptr;     // every fixed-size device array, carved below
+  uint8_t *descL = nullptr, *descR = nullptr;
+  int16_t *dcan_raw = nullptr, *dcan_incon = nullptr, *dcan_vert = nullptr,
+          *dcan_final = nullptr;
+  int32_t *evals = nullptr, *row_scratch = nullptr, *flag_scratch = nullptr;
+  ListHeader* dev_hdr = nullptr;
+  int32_t *dev_ptsL = nullptr, *dev_ptsR = nullptr;
+  uint32_t *gridL = nullptr, *gridR = nullptr;
+  int32_t *ownerL = nullptr, *ownerR = nullptr;
+  int16_t *dplaneL = nullptr, *dplaneR = nullptr, *rawL = nullptr, *rawR = nullptr;
+  int32_t* lut = nullptr;
+  unsigned long long* dense_counter = nullptr;
+  // host-mapped lists written by k_lists
+  void* host_block = nullptr;
+  ListHeader* host_hdr = nullptr;                 // host view
+  int32_t *host_ptsL = nullptr, *host_ptsR = nullptr;
+  ListHeader* host_hdr_dev = nullptr;             // the same memory, device view
+  int32_t *host_ptsL_dev = nullptr, *host_ptsR_dev = nullptr;
+  // raster records + work units: pinned staging and device copy (grown on demand)
+  void* up_host = nullptr;
+  void* up_dev = nullptr;
+  size_t up_cap = 0;
+};
+
+}  // namespace
+
+struct elas_handle {
+  elas_params params{};
+  KParams kp{};
+  std::vector<int32_t> lut;
+  std::map<std::pair<int32_t, int32_t>, Buffers*> cache;
+  Buffers* last = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool have_result = false;
+  std::string err;
+  elas_stats stats{};
+  MeshScratch* meshL = nullptr;
+  MeshScratch* meshR = nullptr;
+  std::vector<int32_t> recsL, recsR;
+  std::vector<float> planesL, planesR;
+  int32_t ntL = 0, ntR = 0;
+  ListHeader hdr{};
+  Worker* worker = nullptr;
+  hipEvent_t ev_lists = nullptr;
+  hipEvent_t ev_upload = nullptr;
+  bool upload_pending = false;
+};
+
+namespace {
+
+int fail(elas_handle* h, int code, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_create_error = msg;
+  return code;
+}
+
+int fail_hip(elas_handle* h, const char* what, hipError_t e) {
+  return fail(h, ELAS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return fail_hip(h, #expr, e_); \
+  } while (0)
+
+void free_buffers(Buffers* b) {
+  if (!b) return;
+  if (b->dev_block) (void)hipFree(b->dev_block);
+  if (b->host_block) (void)hipHostFree(b->host_block);
+  if (b->up_dev) (void)hipFree(b->up_dev);
+  if (b->up_host) (void)hipHostFree(b->up_host);
+  delete b;
+}
+
+Geometry make_geometry(const elas_params& p, int32_t w, int32_t h) {
+  Geometry g{};
+  g.w = w;
+  g.h = h;
+  const int32_t s = p.candidate_stepsize;
+  const int32_t kmin = (4 + s - 1) / s;
+  const int32_t ku = (w - 5) / s, kv = (h - 5) / s;
+  g.step = s;
+  g.lu0 = kmin * s;
+  g.lv0 = kmin * s;
+  g.lw = ku >= kmin ? ku - kmin + 1 : 0;
+  g.lh = kv >= kmin ? kv - kmin + 1 : 0;
+  g.gw = (w + p.grid_size - 1) / p.grid_size;
+  g.gh = (h + p.grid_size - 1) / p.grid_size;
+  const int32_t D = p.disp_max - p.disp_min + 1;
+  g.gwords = 2 * ((D + 63) / 64);
+  return g;
+}
+
+int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
+  const auto key = std::make_pair(w, hp);
+  auto it = h->cache.find(key);
+  if (it != h->cache.end()) {
+    *out = it->second;
+    return ELAS_OK;
+  }
+  Buffers* b = new Buffers();
+  b->g = make_geometry(h->params, w, hp);
+  const Geometry& g = b->g;
+  const size_t npx = (size_t)w * hp;
+  const size_t nlat = std::max<size_t>(1, (size_t)g.lw * g.lh);
+  const size_t ngrid = (size_t)g.gw * g.gh * g.gwords;
+  // carve one device block
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t o_descL = take(npx * 16), o_descR = take(npx * 16);
+  const size_t o_raw0 = take(nlat * 2), o_inc = take(nlat * 2), o_vert = take(nlat * 2),
+               o_fin = take(nlat * 2);
+  const size_t o_evals = take(nlat * 4), o_rows = take(2 * ((size_t)g.lh + 1) * 4 + 4),
+               o_flags = take(nlat * 4);
+  const size_t o_hdr = take(sizeof(ListHeader)), o_pL = take(nlat * 12), o_pR = take(nlat * 12);
+  const size_t o_gL = take(ngrid * 4 + 4), o_gR = take(ngrid * 4 + 4);
+  const size_t o_oL = take(npx * 4), o_oR = take(npx * 4);
+  const size_t o_dpL = take(npx * 2), o_dpR = take(npx * 2), o_rL = take(npx * 2),
+               o_rR = take(npx * 2);
+  const size_t o_lut = take(kMaxD * 4), o_cnt = take(8);
+  hipError_t e = hipMalloc(&b->dev_block, off);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(h, ELAS_ERR_OOM, std::string("hipMalloc of device buffers: ") + hipGetErrorString(e));
+  }
+  uint8_t* base = static_cast<uint8_t*>(b->dev_block);
+  b->descL = base + o_descL;
+  b->descR = base + o_descR;
+  b->dcan_raw = reinterpret_cast<int16_t*>(base + o_raw0);
+  b->dcan_incon = reinterpret_cast<int16_t*>(base + o_inc);
+  b->dcan_vert = reinterpret_cast<int16_t*>(base + o_vert);
+  b->dcan_final = reinterpret_cast<int16_t*>(base + o_fin);
+  b->evals = reinterpret_cast<int32_t*>(base + o_evals);
+  b->row_scratch = reinterpret_cast<int32_t*>(base + o_rows);
+  b->flag_scratch = reinterpret_cast<int32_t*>(base + o_flags);
+  b->dev_hdr = reinterpret_cast<ListHeader*>(base + o_hdr);
+  b->dev_ptsL = reinterpret_cast<int32_t*>(base + o_pL);
+  b->dev_ptsR = reinterpret_cast<int32_t*>(base + o_pR);
+  b->gridL = reinterpret_cast<uint32_t*>(base + o_gL);
+  b->gridR = reinterpret_cast<uint32_t*>(base + o_gR);
+  b->ownerL = reinterpret_cast<int32_t*>(base + o_oL);
+  b->ownerR = reinterpret_cast<int32_t*>(base + o_oR);
+  b->dplaneL = reinterpret_cast<int16_t*>(base + o_dpL);
+  b->dplaneR = reinterpret_cast<int16_t*>(base + o_dpR);
+  b->rawL = reinterpret_cast<int16_t*>(base + o_rL);
+  b->rawR = reinterpret_cast<int16_t*>(base + o_rR);
+  b->lut = reinterpret_cast<int32_t*>(base + o_lut);
+  b->dense_counter = reinterpret_cast<unsigned long long*>(base + o_cnt);
+  // host-mapped lists
+  const size_t hbytes = align_up(sizeof(ListHeader), 256) + 2 * nlat * 12;
+  e = hipHostMalloc(&b->host_block, hbytes, hipHostMallocMapped);
+  if (e != hipSuccess) {
+    free_buffers(b);
+    return fail(h, ELAS_ERR_OOM, std::string("hipHostMalloc of list buffers: ") + hipGetErrorString(e));
+  }
+  uint8_t* hb = static_cast<uint8_t*>(b->host_block);
+  b->host_hdr = reinterpret_cast<ListHeader*>(hb);
+  b->host_ptsL = reinterpret_cast<int32_t*>(hb + align_up(sizeof(ListHeader), 256));
+  b->host_ptsR = b->host_ptsL + 3 * nlat;
+  void* hdev = nullptr;
+  e = hipHostGetDevicePointer(&hdev, b->host_block, 0);
+  if (e != hipSuccess) {
+    free_buffers(b);
+    return fail_hip(h, "hipHostGetDevicePointer of the list buffers", e);
+  }
+  uint8_t* hd8 = static_cast<uint8_t*>(hdev);
+  b->host_hdr_dev = reinterpret_cast<ListHeader*>(hd8);
+  b->host_ptsL_dev = reinterpret_cast<int32_t*>(hd8 + align_up(sizeof(ListHeader), 256));
+  b->host_ptsR_dev = b->host_ptsL_dev + 3 * nlat;
+  e = hipMemcpy(b->lut, h->lut.data(), h->lut.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_buffers(b);
+    return fail_hip(h, "hipMemcpy of the prior table", e);
+  }
+  h->cache[key] = b;
+  *out = b;
+  return ELAS_OK;
+}
+
+int ensure_upload(elas_handle* h, Buffers* b, size_t bytes) {
+  if (bytes <= b->up_cap) return ELAS_OK;
+  const size_t cap = align_up(std::max(bytes, b->up_cap * 3 / 2), 1 << 16);
+  if (b->up_dev) (void)hipFree(b->up_dev);
+  if (b->up_host) (void)hipHostFree(b->up_host);
+  b->up_dev = b->up_host = nullptr;
+  b->up_cap = 0;
+  hipError_t e = hipMalloc(&b->up_dev, cap);
+  if (e != hipSuccess) return fail(h, ELAS_ERR_OOM, "hipMalloc of the mesh upload buffer");
+  e = hipHostMalloc(&b->up_host, cap, hipHostMallocDefault);
+  if (e != hipSuccess) return fail(h, ELAS_ERR_OOM, "hipHostMalloc of the mesh staging buffer");
+  b->up_cap = cap;
+  return ELAS_OK;
+}
+
+bool finite_positive(float x) { return std::isfinite(x) && x > 0.0f; }
+
+}  // namespace
+
+extern "C" {
+
+void elas_params_default(elas_params* p) {
+  if (!p) return;
+  p->disp_min = 0;
+  p->disp_max = 127;
+  p->support_threshold = 0.85f;
+  p->support_texture = 10;
+  p->candidate_stepsize = 5;
+  p->incon_window_size = 5;
+  p->incon_threshold = 5;
+  p->incon_min_support = 5;
+  p->redun_max_dist = 5;
+  p->redun_threshold = 1;
+  p->grid_size = 20;
+  p->beta = 0.02f;
+  p->gamma = 3.0f;
+  p->sigma = 1.0f;
+  p->sradius = 2;
+  p->match_texture = 1;
+  p->lr_threshold = 2;
+  p->full_search = 0;
+}
+
+int elas_create(const elas_params* p, elas_handle** out) {
+  if (!p || !out) return fail(nullptr, ELAS_ERR_ARG, "null argument");
+  *out = nullptr;
+  const int32_t D = p->disp_max - p->disp_min + 1;
+  if (p->disp_min < 0 || p->disp_max < p->disp_min || D > kMaxD)
+    return fail(nullptr, ELAS_ERR_ARG, "disparity range must satisfy 0 <= min <= max, max-min < 256");
+  if (p->candidate_stepsize < 1 || p->grid_size < 1)
+    return fail(nullptr, ELAS_ERR_ARG, "candidate_stepsize and grid_size must be >= 1");
+  if (p->incon_window_size < 0 || p->incon_threshold < 0 || p->incon_min_support < 0 ||
+      p->redun_max_dist < 0 || p->redun_threshold < 0 || p->sradius < 0 ||
+      p->lr_threshold < 0 || p->support_texture < 0 || p->match_texture < 0)
+    return fail(nullptr, ELAS_ERR_ARG, "windows and thresholds must be >= 0");
+  if (!finite_positive(p->beta) || !finite_positive(p->gamma) || !finite_positive(p->sigma) ||
+      !std::isfinite(p->support_threshold))
+    return fail(nullptr, ELAS_ERR_ARG, "beta, gamma, sigma must be finite and > 0");
+  if (p->full_search != 0 && p->full_search != 1)
+    return fail(nullptr, ELAS_ERR_ARG, "full_search must be 0 or 1");
+  // Prior energy of a candidate at distance k from the plane mean: the ELAS
+  // plane prior gamma + exp(-k^2 / (2 sigma^2)) as a negative log, over beta,
+  // offset by log(gamma)/beta so that far candidates cost 0; rounded.
+  std::vector<int32_t> lut(D);
+  const double g = p->gamma, s = p->sigma, b = p->beta;
+  for (int32_t k = 0; k < D; ++k) {
+    const double x = -(std::log(g + std::exp(-(double)k * (double)k / (2.0 * s * s))) -
+                       std::log(g)) / b;
+    if (!(std::fabs(x) < 4.0e6))
+      return fail(nullptr, ELAS_ERR_UNSUPPORTED, "prior energy out of range (beta too small)");
+    lut[k] = (int32_t)std::lround(x);
+  }
+  if (-lut[0] > (1 << 22))
+    return fail(nullptr, ELAS_ERR_UNSUPPORTED, "prior energy out of the packed-key range");
+  elas_handle* h = new (std::nothrow) elas_handle();
+  if (!h) return fail(nullptr, ELAS_ERR_OOM, "out of host memory");
+  h->params = *p;
+  h->lut = std::move(lut);
+  KParams& k = h->kp;
+  k.dmin = p->disp_min;
+  k.dmax = p->disp_max;
+  k.D = D;
+  k.support_threshold = p->support_threshold;
+  k.support_texture = p->support_texture;
+  k.incon_window = p->incon_window_size;
+  k.incon_threshold = p->incon_threshold;
+  k.incon_min_support = p->incon_min_support;
+  k.redun_max_dist = p->redun_max_dist;
+  k.redun_threshold = p->redun_threshold;
+  k.grid_size = p->grid_size;
+  k.sradius = p->sradius;
+  k.match_texture = p->match_texture;
+  k.lr_threshold = p->lr_threshold;
+  k.full_search = p->full_search;
+  k.lut_bias = -h->lut[0];
+  h->meshL = mesh_scratch_create();
+  h->meshR = mesh_scratch_create();
+  *out = h;
+  return ELAS_OK;
+}
+
+int elas_destroy(elas_handle* h) {
+  if (!h) return ELAS_OK;
+  if (h->last_stream || h->have_result) (void)hipStreamSynchronize(h->last_stream);
+  for (auto& kv : h->cache) free_buffers(kv.second);
+  if (h->ev_lists) (void)hipEventDestroy(h->ev_lists);
+  if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
+  delete h->worker;
+  mesh_scratch_destroy(h->meshL);
+  mesh_scratch_destroy(h->meshR);
+  delete h;
+  return ELAS_OK;
+}
+
+const char* elas_last_error(const elas_handle* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int32_t w,
+                 int32_t hp, int32_t stride, hipStream_t stream, int16_t* disp_left,
+                 int16_t* disp_right) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  if (!left || !right || !disp_left || !disp_right)
+    return fail(h, ELAS_ERR_ARG, "null image or output pointer");
+  if (w < 9 || hp < 9 || w > 8192 || hp > 8192)
+    return fail(h, ELAS_ERR_ARG, "image size must be 9..8192 in each dimension");
+  if (stride < w) return fail(h, ELAS_ERR_ARG, "stride must be >= width");
+  if (!h->ev_lists) {
+    HIP_TRY(hipEventCreateWithFlags(&h->ev_lists, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&h->ev_upload, hipEventDisableTiming));
+  }
+  if (!h->worker) h->worker = new Worker();
+  Buffers* b = nullptr;
+  int rc = get_buffers(h, w, hp, &b);
+  if (rc != ELAS_OK) return rc;
+  const Geometry& g = b->g;
+  const KParams& kp = h->kp;
+  h->have_result = false;
+  h->last = b;
+  h->last_stream = stream;
+
+  HIP_TRY(launch_descriptor(left, right, stride, g, b->descL, b->descR, b->ownerL, b->ownerR,
+                            stream));
+  HIP_TRY(launch_support(b->descL, b->descR, g, kp, b->dcan_raw, b->evals, stream));
+  HIP_TRY(launch_incon(b->dcan_raw, g, kp, b->dcan_incon, stream));
+  HIP_TRY(launch_lists(g, kp, b->dcan_incon, b->dcan_vert, b->dcan_final, b->evals,
+                       b->row_scratch, b->flag_scratch, b->dev_hdr, b->dev_ptsL, b->dev_ptsR,
+                       b->host_hdr_dev, b->host_ptsL_dev, b->host_ptsR_dev, b->gridL, b->gridR,
+                       b->dense_counter, stream));
+  HIP_TRY(hipEventRecord(h->ev_lists, stream));
+  HIP_TRY(hipEventSynchronize(h->ev_lists));
+  ListHeader hd;
+  std::memcpy(&hd, b->host_hdr, sizeof(hd));  // written by k_lists; visible after the event
+  h->hdr = hd;
+
+  const auto t0 = std::chrono::steady_clock::now();
+  const int32_t has_list = hd.nL > 0 ? 1 : 0;
+  int32_t ntL = 0, ntR = 0, nunits = 0;
+  const RasterTri* dev_tris = nullptr;
+  const RasterUnit* dev_units = nullptr;
+  if (has_list) {
+    ntL = 2 * hd.nL + 2;
+    ntR = 2 * hd.nR + 2;
+    // the staging buffer of the previous call must have been consumed
+    if (h->upload_pending) HIP_TRY(hipEventSynchronize(h->ev_upload));
+    h->upload_pending = false;
+    const size_t tri_bytes = align_up((size_t)(ntL + ntR) * sizeof(RasterTri), 256);
+    rc = ensure_upload(h, b, tri_bytes);
+    if (rc != ELAS_OK) return rc;
+    h->recsL.resize((size_t)ntL * 9);
+    h->planesL.resize((size_t)ntL * 3);
+    h->recsR.resize((size_t)ntR * 9);
+    h->planesR.resize((size_t)ntR * 3);
+    RasterTri* tris = static_cast<RasterTri*>(b->up_host);
+    int32_t gotR = -1;
+    const int32_t* hptsR = b->host_ptsR;
+    h->worker->submit([&] {
+      gotR = build_mesh(h->meshR, hptsR, hd.nR, hd.cornersR, w, hp, tris + ntL,
+                        h->recsR.data(), h->planesR.data());
+    });
+    const int32_t gotL = build_mesh(h->meshL, b->host_ptsL, hd.nL, hd.cornersL, w, hp, tris,
+                                    h->recsL.data(), h->planesL.data());
+    h->worker->wait();
+    if (gotL != ntL || gotR != ntR)
+      return fail(h, ELAS_ERR_INTERNAL, "host triangulation failed its consistency checks");
+    nunits = raster_units(tris, ntL + ntR, 0, nullptr);
+    const size_t bytes = tri_bytes + (size_t)nunits * sizeof(RasterUnit);
+    if (bytes > b->up_cap) {
+      // grow, keeping the records already written
+      std::vector<RasterTri> keep(tris, tris + ntL + ntR);
+      rc = ensure_upload(h, b, bytes);
+      if (rc != ELAS_OK) return rc;
+      tris = static_cast<RasterTri*>(b->up_host);
+      std::memcpy(tris, keep.data(), keep.size() * sizeof(RasterTri));
+    }
+    RasterUnit* units = reinterpret_cast<RasterUnit*>(static_cast<uint8_t*>(b->up_host) + tri_bytes);
+    raster_units(tris, ntL + ntR, 0, units);
+    HIP_TRY(hipMemcpyAsync(b->up_dev, b->up_host, bytes, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(h->ev_upload, stream));
+    h->upload_pending = true;
+    dev_tris = static_cast<const RasterTri*>(b->up_dev);
+    dev_units = reinterpret_cast<const RasterUnit*>(static_cast<uint8_t*>(b->up_dev) + tri_bytes);
+  } else {
+    h->recsL.clear();
+    h->recsR.clear();
+    h->planesL.clear();
+    h->planesR.clear();
+  }
+  h->ntL = ntL;
+  h->ntR = ntR;
+  const auto t1 = std::chrono::steady_clock::now();
+
+  HIP_TRY(launch_raster(dev_tris, dev_units, nunits, ntL, g, b->ownerL, b->ownerR, stream));
+  HIP_TRY(launch_dense(b->descL, b->descR, b->ownerL, b->ownerR, dev_tris, ntL, b->gridL,
+                       b->gridR, b->lut, has_list, g, kp, b->dplaneL, b->dplaneR, b->rawL,
+                       b->rawR, b->dense_counter, stream));
+  HIP_TRY(launch_lrcheck(b->rawL, b->rawR, g, kp, disp_left, disp_right, stream));
+
+  h->stats.support_evals = hd.support_evals;
+  h->stats.dense_evals = -1;
+  h->stats.n_support_left = hd.nL;
+  h->stats.n_support_right = hd.nR;
+  h->stats.n_tri_left = ntL;
+  h->stats.n_tri_right = ntR;
+  h->stats.host_mesh_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  h->have_result = true;
+  return ELAS_OK;
+}
+
+int elas_get_stats(elas_handle* h, elas_stats* out) {
+  if (!h || !out) return fail(h, ELAS_ERR_ARG, "null argument");
+  if (!h->have_result) return fail(h, ELAS_ERR_ARG, "no completed call");
+  HIP_TRY(hipStreamSynchronize(h->last_stream));
+  unsigned long long cnt = 0;
+  HIP_TRY(hipMemcpy(&cnt, h->last->dense_counter, sizeof(cnt), hipMemcpyDeviceToHost));
+  h->stats.dense_evals = (int64_t)cnt;
+  *out = h->stats;
+  return ELAS_OK;
+}
+
+int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t bytes,
+                          int64_t* needed) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  if (!h->have_result) return fail(h, ELAS_ERR_ARG, "no completed call");
+  Buffers* b = h->last;
+  const Geometry& g = b->g;
+  const int64_t npx = (int64_t)g.w * g.h, nlat = (int64_t)g.lw * g.lh;
+  const void* dsrc = nullptr;
+  const void* hsrc = nullptr;
+  int64_t size = 0;
+  int32_t corners[8];
+  switch (which) {
+    case ELAS_I_DESC_LEFT: dsrc = b->descL; size = npx * 16; break;
+    case ELAS_I_DESC_RIGHT: dsrc = b->descR; size = npx * 16; break;
+    case ELAS_I_DCAN_RAW: dsrc = b->dcan_raw; size = nlat * 2; break;
+    case ELAS_I_DCAN_INCON: dsrc = b->dcan_incon; size = nlat * 2; break;
+    case ELAS_I_DCAN_VERT: dsrc = b->dcan_vert; size = nlat * 2; break;
+    case ELAS_I_DCAN_FINAL: dsrc = b->dcan_final; size = nlat * 2; break;
+    case ELAS_I_SUPPORT_LEFT: dsrc = b->dev_ptsL; size = (int64_t)h->hdr.nL * 12; break;
+    case ELAS_I_SUPPORT_RIGHT: dsrc = b->dev_ptsR; size = (int64_t)h->hdr.nR * 12; break;
+    case ELAS_I_CORNERS:
+      std::memcpy(corners, h->hdr.cornersL, 16);
+      std::memcpy(corners + 4, h->hdr.cornersR, 16);
+      hsrc = corners;
+      size = 32;
+      break;
+    case ELAS_I_TRI_LEFT: hsrc = h->recsL.data(); size = (int64_t)h->ntL * 36; break;
+    case ELAS_I_TRI_RIGHT: hsrc = h->recsR.data(); size = (int64_t)h->ntR * 36; break;
+    case ELAS_I_PLANE_LEFT: hsrc = h->planesL.data(); size = (int64_t)h->ntL * 12; break;
+    case ELAS_I_PLANE_RIGHT: hsrc = h->planesR.data(); size = (int64_t)h->ntR * 12; break;
+    case ELAS_I_OWNER_LEFT: dsrc = b->ownerL; size = npx * 4; break;
+    case ELAS_I_OWNER_RIGHT: dsrc = b->ownerR; size = npx * 4; break;
+    case ELAS_I_DPLANE_LEFT: dsrc = b->dplaneL; size = npx * 2; break;
+    case ELAS_I_DPLANE_RIGHT: dsrc = b->dplaneR; size = npx * 2; break;
+    case ELAS_I_GRID_LEFT: dsrc = b->gridL; size = (int64_t)g.gw * g.gh * g.gwords * 4; break;
+    case ELAS_I_GRID_RIGHT: dsrc = b->gridR; size = (int64_t)g.gw * g.gh * g.gwords * 4; break;
+    case ELAS_I_RAW_LEFT: dsrc = b->rawL; size = npx * 2; break;
+    case ELAS_I_RAW_RIGHT: dsrc = b->rawR; size = npx * 2; break;
+    case ELAS_I_LUT: hsrc = h->lut.data(); size = (int64_t)h->lut.size() * 4; break;
+    default: return fail(h, ELAS_ERR_ARG, "unknown intermediate");
+  }
+  if (needed) *needed = size;
+  if (!dst) return ELAS_OK;
+  if (bytes < size) return fail(h, ELAS_ERR_ARG, "destination too small");
+  if (size == 0) return ELAS_OK;
+  if (hsrc) {
+    std::memcpy(dst, hsrc, (size_t)size);
+    return ELAS_OK;
+  }
+  HIP_TRY(hipStreamSynchronize(h->last_stream));
+  HIP_TRY(hipMemcpy(dst, dsrc, (size_t)size, hipMemcpyDeviceToHost));
+  return ELAS_OK;
+}
+
+int elas_triangulate(const int32_t* pts, int32_t n, const int32_t* corners, int32_t w,
+                     int32_t h, int32_t* recs_out, float* planes_out) {
+  if (!pts || !corners || !recs_out || !planes_out || n < 1 || w < 3 || h < 3 || w > 8192 ||
+      h > 8192)
+    return fail(nullptr, ELAS_ERR_ARG, "bad triangulation arguments");
+  for (int32_t i = 0; i < n; ++i)
+    if (pts[3 * i] <= 0 || pts[3 * i] >= w - 1 || pts[3 * i + 1] <= 0 || pts[3 * i + 1] >= h - 1)
+      return fail(nullptr, ELAS_ERR_ARG, "support point outside the image interior");
+  MeshScratch* s = mesh_scratch_create();
+  std::vector<RasterTri> tris((size_t)2 * n + 2);
+  const int32_t nt = build_mesh(s, pts, n, corners, w, h, tris.data(), recs_out, planes_out);
+  mesh_scratch_destroy(s);
+  if (nt != 2 * n + 2) return fail(nullptr, ELAS_ERR_ARG, "triangulation rejected its input");
+  return nt;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal types shared by the HIP kernels, the host mesh builder and the
+// C-ABI layer of elas_mi355x.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace elas {
+
+constexpr int kMaxD = 256;
+constexpr int32_t kNoOwner = 0x7FFFFFFF;
+constexpr int kRasterChunk = 1024;  // bounding-box pixels per raster work unit
+constexpr int kListsThreads = 1024;
+
+// Image, lattice and grid geometry of one (w, h) for one parameter set.
+struct Geometry {
+  int32_t w, h;
+  int32_t lw, lh;     // support lattice: lw columns, lh rows
+  int32_t lu0, lv0;   // first lattice column / row in pixels
+  int32_t step;       // lattice step in pixels
+  int32_t gw, gh;     // grid-vector regions
+  int32_t gwords;     // 32-bit words per region mask (even: 64-bit aligned masks)
+};
+
+// Parameters as the kernels consume them (passed by value).
+struct KParams {
+  int32_t dmin, dmax, D;
+  float support_threshold;
+  int32_t support_texture;
+  int32_t incon_window, incon_threshold, incon_min_support;
+  int32_t redun_max_dist, redun_threshold;
+  int32_t grid_size, sradius, match_texture, lr_threshold, full_search;
+  int32_t lut_bias;   // -lut[0]: makes every energy non-negative for key packing
+};
+
+// One triangle as the raster and dense kernels read it: integer vertices in
+// positive orientation and the FP32 plane d = a*u + b*v + c.
+struct RasterTri {
+  int16_t u[3];
+  int16_t v[3];
+  float a, b, c;
+};
+static_assert(sizeof(RasterTri) == 24, "RasterTri layout");
+
+// Raster work unit: kRasterChunk pixels of one triangle's bounding box.
+struct RasterUnit {
+  int32_t tri;    // index into the combined (left then right) triangle array
+  int32_t chunk;  // chunk index within the bounding box
+};
+
+// Header the lists kernel writes (device copy and host-mapped copy).
+struct ListHeader {
+  int32_t nL, nR;
+  int32_t cornersL[4];
+  int32_t cornersR[4];
+  int64_t support_evals;
+};
+
+// ---- host mesh builder (elas_mesh.cpp) ----------------------------------
+// pts: n support points (u, v, d), all strictly inside the image; corners: d
+// of the four image corners. Builds the canonical Delaunay mesh of corners +
+// points and writes, in canonical order, exactly 2n + 2 raster records to
+// tri_out and (if not null) 9-int records and 3-float planes for
+// verification. Returns the triangle count (2n + 2) or -1 if an internal
+// consistency check fails.
+struct MeshScratch;
+MeshScratch* mesh_scratch_create();
+void mesh_scratch_destroy(MeshScratch*);
+int32_t build_mesh(MeshScratch* s, const int32_t* pts, int32_t n, const int32_t* corners,
+                   int32_t w, int32_t h, RasterTri* tri_out, int32_t* recs_out,
+                   float* planes_out);
+// Raster work units of ntri records whose indices start at tri_base: one unit
+// per kRasterChunk pixels of each bounding box. Writes to out when not null;
+// returns the count.
+int32_t raster_units(const RasterTri* tris, int32_t ntri, int32_t tri_base, RasterUnit* out);
+
+// ---- kernel launchers (elas_kernels.hip) ---------------------------------
+hipError_t launch_descriptor(const uint8_t* left, const uint8_t* right, int32_t stride,
+                             const Geometry& g, uint8_t* descL, uint8_t* descR,
+                             int32_t* ownerL, int32_t* ownerR, hipStream_t s);
+hipError_t launch_support(const uint8_t* descL, const uint8_t* descR, const Geometry& g,
+                          const KParams& p, int16_t* dcan, int32_t* evals, hipStream_t s);
+hipError_t launch_incon(const int16_t* in, const Geometry& g, const KParams& p, int16_t* out,
+                        hipStream_t s);
+hipError_t launch_lists(const Geometry& g, const KParams& p, const int16_t* dcan_incon,
+                        int16_t* dcan_vert, int16_t* dcan_final, const int32_t* evals,
+                        int32_t* row_scratch, int32_t* flag_scratch, ListHeader* dev_hdr,
+                        int32_t* dev_ptsL, int32_t* dev_ptsR, ListHeader* host_hdr,
+                        int32_t* host_ptsL, int32_t* host_ptsR, uint32_t* gridL,
+                        uint32_t* gridR, unsigned long long* dense_counter, hipStream_t s);
+hipError_t launch_raster(const RasterTri* tris, const RasterUnit* units, int32_t nunits,
+                         int32_t ntL, const Geometry& g, int32_t* ownerL, int32_t* ownerR,
+                         hipStream_t s);
+hipError_t launch_dense(const uint8_t* descL, const uint8_t* descR, const int32_t* ownerL,
+                        const int32_t* ownerR, const RasterTri* tris, int32_t ntL,
+                        const uint32_t* gridL, const uint32_t* gridR, const int32_t* lut,
+                        int32_t has_list, const Geometry& g, const KParams& p,
+                        int16_t* dplaneL, int16_t* dplaneR, int16_t* rawL, int16_t* rawR,
+                        unsigned long long* dense_counter, hipStream_t s);
+hipError_t launch_lrcheck(const int16_t* rawL, const int16_t* rawR, const Geometry& g,
+                          const KParams& p, int16_t* outL, int16_t* outR, hipStream_t s);
+
+}  // namespace elas

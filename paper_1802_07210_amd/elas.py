@@ -1,0 +1,198 @@
+"""Python binding of libelas_mi355x.so (argument marshalling only).
+
+Every stage of the path runs in the library's HIP kernels and host code; this
+module only converts torch tensors and numpy arrays to pointers. PyTorch is
+used for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libelas_mi355x.so")
+
+ELAS_OK = 0
+ERRORS = {-1: "ELAS_ERR_ARG", -2: "ELAS_ERR_OOM", -3: "ELAS_ERR_HIP",
+          -4: "ELAS_ERR_UNSUPPORTED", -5: "ELAS_ERR_INTERNAL"}
+
+EXPORTS = ("elas_params_default", "elas_create", "elas_destroy", "elas_process",
+           "elas_get_stats", "elas_last_error", "elas_get_intermediate", "elas_triangulate")
+
+
+class ElasParams(C.Structure):
+    _fields_ = [
+        ("disp_min", C.c_int32), ("disp_max", C.c_int32),
+        ("support_threshold", C.c_float), ("support_texture", C.c_int32),
+        ("candidate_stepsize", C.c_int32), ("incon_window_size", C.c_int32),
+        ("incon_threshold", C.c_int32), ("incon_min_support", C.c_int32),
+        ("redun_max_dist", C.c_int32), ("redun_threshold", C.c_int32),
+        ("grid_size", C.c_int32), ("beta", C.c_float), ("gamma", C.c_float),
+        ("sigma", C.c_float), ("sradius", C.c_int32), ("match_texture", C.c_int32),
+        ("lr_threshold", C.c_int32), ("full_search", C.c_int32),
+    ]
+
+
+class ElasStats(C.Structure):
+    _fields_ = [
+        ("support_evals", C.c_int64), ("dense_evals", C.c_int64),
+        ("n_support_left", C.c_int32), ("n_support_right", C.c_int32),
+        ("n_tri_left", C.c_int32), ("n_tri_right", C.c_int32),
+        ("host_mesh_ms", C.c_double),
+    ]
+
+
+# name -> (enum value, numpy dtype, trailing shape kind)
+INTERMEDIATES = {
+    "desc_left": (0, np.uint8), "desc_right": (1, np.uint8),
+    "dcan_raw": (2, np.int16), "dcan_incon": (3, np.int16), "dcan_vert": (4, np.int16),
+    "dcan_final": (5, np.int16),
+    "support_left": (6, np.int32), "support_right": (7, np.int32), "corners": (8, np.int32),
+    "tri_left": (9, np.int32), "tri_right": (10, np.int32),
+    "plane_left": (11, np.float32), "plane_right": (12, np.float32),
+    "owner_left": (13, np.int32), "owner_right": (14, np.int32),
+    "dplane_left": (15, np.int16), "dplane_right": (16, np.int16),
+    "grid_left": (17, np.uint64), "grid_right": (18, np.uint64),
+    "raw_left": (19, np.int16), "raw_right": (20, np.int16),
+    "lut": (21, np.int32),
+}
+
+_lib = None
+
+
+class ElasError(RuntimeError):
+    pass
+
+
+def lib() -> C.CDLL:
+    """Loads the HIP library; there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ElasError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.elas_params_default.argtypes = [C.POINTER(ElasParams)]
+        L.elas_params_default.restype = None
+        L.elas_create.argtypes = [C.POINTER(ElasParams), C.POINTER(vp)]
+        L.elas_destroy.argtypes = [vp]
+        L.elas_process.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+        L.elas_get_stats.argtypes = [vp, C.POINTER(ElasStats)]
+        L.elas_last_error.argtypes = [vp]
+        L.elas_last_error.restype = C.c_char_p
+        L.elas_get_intermediate.argtypes = [vp, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.elas_triangulate.argtypes = [vp, C.c_int32, vp, C.c_int32, C.c_int32, vp, vp]
+        for name in EXPORTS:
+            if name not in ("elas_params_default", "elas_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def default_params(**overrides) -> ElasParams:
+    p = ElasParams()
+    lib().elas_params_default(C.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k) or k.startswith("_"):
+            raise KeyError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _check(rc: int, handle=None):
+    if rc < 0:
+        msg = lib().elas_last_error(handle)
+        raise ElasError(f"{ERRORS.get(rc, rc)}: {msg.decode() if msg else ''}")
+    return rc
+
+
+def _np_ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def triangulate(pts: np.ndarray, corners, w: int, h: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Host mesh step: canonical triangles [2n+2, 9] and planes [2n+2, 3]."""
+    pts = np.ascontiguousarray(pts, np.int32).reshape(-1, 3)
+    n = len(pts)
+    corners = np.ascontiguousarray(corners, np.int32)
+    recs = np.zeros((max(1, 2 * n + 2), 9), np.int32)
+    planes = np.zeros((max(1, 2 * n + 2), 3), np.float32)
+    nt = _check(lib().elas_triangulate(_np_ptr(pts), n, _np_ptr(corners), w, h,
+                                       _np_ptr(recs), _np_ptr(planes)))
+    return recs[:nt], planes[:nt]
+
+
+class Elas:
+    """One handle: parameters, the prior table and per-size device buffers."""
+
+    def __init__(self, params: Optional[ElasParams] = None, **overrides):
+        self.params = params if params is not None else default_params(**overrides)
+        h = C.c_void_p()
+        _check(lib().elas_create(C.byref(self.params), C.byref(h)))
+        self._h = h
+        self._shape = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().elas_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def process(self, left, right, out_left=None, out_right=None, stream=None):
+        """left/right: torch.uint8 CUDA tensors [H, W] (rows may be padded:
+        stride(0) >= W, stride(1) == 1, same layout for both). Returns int16
+        [H, W] left and right disparity maps (-1 = invalid)."""
+        import torch
+        if left.dtype != torch.uint8 or right.dtype != torch.uint8:
+            raise TypeError("images must be uint8")
+        if not (left.is_cuda and right.is_cuda):
+            raise TypeError("images must be device tensors")
+        if left.dim() != 2 or left.shape != right.shape:
+            raise ValueError("images must be 2-D and of equal shape")
+        if left.stride(1) != 1 or right.stride(1) != 1 or left.stride(0) != right.stride(0):
+            raise ValueError("images need unit column stride and equal row strides")
+        H, W = left.shape
+        stride = left.stride(0)
+        if out_left is None:
+            out_left = torch.empty((H, W), dtype=torch.int16, device=left.device)
+        if out_right is None:
+            out_right = torch.empty((H, W), dtype=torch.int16, device=left.device)
+        for o in (out_left, out_right):
+            if o.dtype != torch.int16 or not o.is_contiguous() or tuple(o.shape) != (H, W):
+                raise ValueError("outputs must be contiguous int16 [H, W]")
+        if stream is None:
+            stream = torch.cuda.current_stream(left.device)
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().elas_process(self._h, C.c_void_p(left.data_ptr()),
+                                  C.c_void_p(right.data_ptr()), W, H, stride, C.c_void_p(s),
+                                  C.c_void_p(out_left.data_ptr()),
+                                  C.c_void_p(out_right.data_ptr())), self._h)
+        self._shape = (H, W)
+        return out_left, out_right
+
+    def stats(self) -> dict:
+        st = ElasStats()
+        _check(lib().elas_get_stats(self._h, C.byref(st)), self._h)
+        return {k: getattr(st, k) for k, _ in ElasStats._fields_}
+
+    def intermediate(self, name: str) -> np.ndarray:
+        which, dtype = INTERMEDIATES[name]
+        need = C.c_int64(0)
+        _check(lib().elas_get_intermediate(self._h, which, None, 0, C.byref(need)), self._h)
+        nbytes = int(need.value)
+        buf = np.zeros(max(nbytes, 1), np.uint8)
+        _check(lib().elas_get_intermediate(self._h, which, _np_ptr(buf), nbytes, None), self._h)
+        return buf[:nbytes].view(dtype).copy()

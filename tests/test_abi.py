@@ -1,0 +1,133 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol,
+validates arguments without touching a GPU, and its host mesh step agrees
+with the oracle's (independently written) triangulation bit for bit."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def E():
+    import paper_1802_07210_amd as pkg
+    if not os.path.exists(pkg.elas.LIB_PATH):
+        from paper_1802_07210_amd import build
+        build.build()
+    return pkg
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "elas.h")).read()
+    return sorted(set(re.findall(r"ELAS_API\s+[\w\s\*]+?\b(elas_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(E):
+    names = declared_functions()
+    assert len(names) >= 8
+    L = C.CDLL(E.elas.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(E.elas.EXPORTS)
+
+
+def test_defaults_match_the_workload_parameters(E):
+    p = E.default_params()
+    assert (p.disp_min, p.disp_max) == (0, 127)
+    assert p.support_threshold == np.float32(0.85) and p.support_texture == 10
+    assert p.candidate_stepsize == 5 and p.incon_window_size == 5
+    assert p.incon_threshold == 5 and p.incon_min_support == 5
+    assert p.grid_size == 20 and p.beta == np.float32(0.02)
+    assert p.gamma == 3 and p.sigma == 1 and p.sradius == 2
+    assert p.match_texture == 1 and p.lr_threshold == 2 and p.full_search == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(disp_min=-1), dict(disp_min=10, disp_max=9), dict(disp_max=256),
+    dict(candidate_stepsize=0), dict(grid_size=0), dict(beta=0.0), dict(gamma=-1.0),
+    dict(sigma=float("nan")), dict(incon_window_size=-1), dict(full_search=2),
+    dict(sradius=-3),
+])
+def test_create_rejects_bad_parameters(E, bad):
+    with pytest.raises(E.ElasError, match="ELAS_ERR_ARG"):
+        E.Elas(**bad)
+
+
+def test_create_rejects_prior_out_of_key_range(E):
+    with pytest.raises(E.ElasError, match="ELAS_ERR_UNSUPPORTED"):
+        E.Elas(beta=1e-8)   # lut[0] = -ln(4/3)/beta is about -2.9e7
+
+
+def test_create_accepts_edge_parameters(E):
+    for kw in (dict(disp_max=255), dict(disp_min=7, disp_max=7), dict(candidate_stepsize=1),
+               dict(full_search=1), dict(disp_min=3, disp_max=200)):
+        e = E.Elas(**kw)
+        e.close()
+
+
+def test_process_rejects_bad_arguments_before_any_hip_call(E):
+    L = E.elas.lib()
+    e = E.Elas()
+    h = e.handle
+    buf = C.c_void_p(0x1000)    # never dereferenced: validation fails first
+    assert L.elas_process(h, None, buf, 64, 64, 64, None, buf, buf) == -1
+    assert L.elas_process(h, buf, buf, 8, 64, 64, None, buf, buf) == -1
+    assert L.elas_process(h, buf, buf, 64, 8193, 64, None, buf, buf) == -1
+    assert L.elas_process(h, buf, buf, 64, 64, 63, None, buf, buf) == -1
+    assert b"stride" in L.elas_last_error(h)
+    assert L.elas_process(None, buf, buf, 64, 64, 64, None, buf, buf) == -1
+    # no completed call yet
+    st = E.elas.ElasStats()
+    assert L.elas_get_stats(h, C.byref(st)) == -1
+    need = C.c_int64()
+    assert L.elas_get_intermediate(h, 0, None, 0, C.byref(need)) == -1
+    e.close()
+
+
+def test_triangulate_rejects_bad_input(E):
+    with pytest.raises(E.ElasError):
+        E.triangulate(np.array([[0, 5, 3]]), [1, 1, 1, 1], 20, 20)     # on the border
+    with pytest.raises(E.ElasError):
+        E.triangulate(np.array([[5, 5, 3], [5, 5, 4]]), [1, 1, 1, 1], 20, 20)  # duplicate
+    with pytest.raises(E.ElasError):
+        E.triangulate(np.zeros((0, 3)), [1, 1, 1, 1], 20, 20)
+
+
+@pytest.mark.parametrize("shape", list(synth.SHAPES))
+def test_host_mesh_matches_oracle(E, shape):
+    cfg = synth.SHAPES[shape]
+    for seed in range(2):
+        pr = synth.make_pair(cfg.with_seed(seed))
+        t = ref.process(ref.params(disp_max=cfg.disp_range - 1), pr.left, pr.right)
+        for pts, cor, recs, planes in ((t.ptsL, t.cornersL, t.recL, t.planeL),
+                                       (t.ptsR, t.cornersR, t.recR, t.planeR)):
+            r2, p2 = E.triangulate(pts, cor, cfg.width, cfg.height)
+            assert np.array_equal(r2, recs)
+            assert np.array_equal(p2.view(np.uint32), planes.view(np.uint32))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_host_mesh_matches_oracle_on_dense_cocircular_lattices(E, seed):
+    # dense lattice subsets: many co-circular cells, exercises the fan rule
+    rng = np.random.default_rng(seed)
+    W, H = 101, 81
+    cand = [(u, v) for v in range(5, H - 4, 5) for u in range(5, W - 4, 5)]
+    k = int(rng.integers(10, len(cand)))
+    sel = sorted(rng.choice(len(cand), size=k, replace=False))
+    pts = np.array([(cand[i][0], cand[i][1], int(rng.integers(0, 64))) for i in sel], np.int32)
+    corners = rng.integers(0, 64, 4).astype(np.int32)
+    uvd = np.concatenate([np.array([[0, 0, corners[0]], [W - 1, 0, corners[1]],
+                                    [0, H - 1, corners[2]], [W - 1, H - 1, corners[3]]],
+                                   np.int32), pts])
+    tris = ref.delaunay(uvd[:, :2])
+    recs = ref.canonical(uvd, tris)
+    planes = np.array([ref.plane(r) for r in recs], np.float32)
+    r2, p2 = E.triangulate(pts, corners, W, H)
+    assert np.array_equal(r2, recs)
+    assert np.array_equal(p2.view(np.uint32), planes.view(np.uint32))

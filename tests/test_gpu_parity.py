@@ -1,0 +1,216 @@
+"""Parity of the HIP path with the CPU oracle, element by element: every
+intermediate stage and both output maps must match exactly (zero mismatching
+pixels; the arithmetic is integer except the FP32 ratio test and plane mean,
+which both sides evaluate with the same operations in the same order)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_07210_amd as pkg
+    return pkg
+
+
+def run_pair(E, left, right, stride=None, **kw):
+    h, w = left.shape
+    dev = torch.device("cuda:0")
+    if stride is None or stride == w:
+        L = torch.from_numpy(np.ascontiguousarray(left)).to(dev)
+        R = torch.from_numpy(np.ascontiguousarray(right)).to(dev)
+    else:
+        padL = np.full((h, stride), 7, np.uint8)
+        padR = np.full((h, stride), 9, np.uint8)
+        padL[:, :w] = left
+        padR[:, :w] = right
+        L = torch.from_numpy(padL).to(dev)[:, :w]
+        R = torch.from_numpy(padR).to(dev)[:, :w]
+    e = E.Elas(**kw)
+    oL, oR = e.process(L, R)
+    torch.cuda.synchronize()
+    return e, oL.cpu().numpy(), oR.cpu().numpy()
+
+
+def compare(e, t, outL, outR):
+    """Returns a list of (stage, mismatch count) for every stage that differs."""
+    h, w = t.outL.shape
+    bad = []
+
+    def chk(name, got, exp):
+        got = np.asarray(got)
+        exp = np.asarray(exp)
+        if got.shape != exp.shape:
+            bad.append((name, f"shape {got.shape} vs {exp.shape}"))
+            return
+        n = int(np.count_nonzero(got != exp))
+        if n:
+            bad.append((name, n))
+
+    chk("desc_left", e.intermediate("desc_left").reshape(h, w, 16), t.descL)
+    chk("desc_right", e.intermediate("desc_right").reshape(h, w, 16), t.descR)
+    lh, lw = t.dcan_raw.shape
+    for nm, arr in (("dcan_raw", t.dcan_raw), ("dcan_incon", t.dcan_incon),
+                    ("dcan_vert", t.dcan_vert), ("dcan_final", t.dcan_final)):
+        chk(nm, e.intermediate(nm).reshape(lh, lw), arr)
+    chk("support_left", e.intermediate("support_left").reshape(-1, 3), t.ptsL)
+    chk("support_right", e.intermediate("support_right").reshape(-1, 3), t.ptsR)
+    chk("corners", e.intermediate("corners"), np.concatenate([t.cornersL, t.cornersR]))
+    chk("tri_left", e.intermediate("tri_left").reshape(-1, 9), t.recL)
+    chk("tri_right", e.intermediate("tri_right").reshape(-1, 9), t.recR)
+    chk("plane_left", e.intermediate("plane_left").reshape(-1, 3).view(np.uint32),
+        t.planeL.view(np.uint32))
+    chk("plane_right", e.intermediate("plane_right").reshape(-1, 3).view(np.uint32),
+        t.planeR.view(np.uint32))
+    for side, own in (("left", t.ownerL), ("right", t.ownerR)):
+        got = e.intermediate(f"owner_{side}").reshape(h, w)
+        got = np.where(got == 0x7FFFFFFF, -1, got)
+        chk(f"owner_{side}", got, own)
+    chk("dplane_left", e.intermediate("dplane_left").reshape(h, w), t.dplaneL)
+    chk("dplane_right", e.intermediate("dplane_right").reshape(h, w), t.dplaneR)
+    if len(t.ptsL):
+        chk("grid_left", e.intermediate("grid_left").reshape(t.gridL.shape), t.gridL)
+        chk("grid_right", e.intermediate("grid_right").reshape(t.gridR.shape), t.gridR)
+    chk("raw_left", e.intermediate("raw_left").reshape(h, w), t.rawL)
+    chk("raw_right", e.intermediate("raw_right").reshape(h, w), t.rawR)
+    chk("lut", e.intermediate("lut"), t.lut)
+    chk("out_left", outL, t.outL)
+    chk("out_right", outR, t.outR)
+    st = e.stats()
+    chk("support_evals", st["support_evals"], t.support_evals)
+    chk("dense_evals", st["dense_evals"], t.dense_evals)
+    chk("n_support", (st["n_support_left"], st["n_support_right"]), (len(t.ptsL), len(t.ptsR)))
+    chk("n_tri", (st["n_tri_left"], st["n_tri_right"]), (len(t.recL), len(t.recR)))
+    return bad
+
+
+def oracle_params(kw):
+    return ref.params(**kw)
+
+
+@pytest.mark.parametrize("shape", ["320x240", "640x480", "1242x375", "1280x720"])
+def test_workload_shapes_bit_exact(E, shape):
+    cfg = synth.SHAPES[shape]
+    pair = synth.make_pair(cfg)
+    kw = dict(disp_max=cfg.disp_range - 1)
+    e, oL, oR = run_pair(E, pair.left, pair.right, **kw)
+    t = ref.process(oracle_params(kw), pair.left, pair.right)
+    assert compare(e, t, oL, oR) == []
+    assert (oL >= 0).mean() > 0.4
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_qvga_seeds_bit_exact(E, seed):
+    cfg = synth.QVGA.with_seed(seed)
+    pair = synth.make_pair(cfg)
+    kw = dict(disp_max=63)
+    e, oL, oR = run_pair(E, pair.left, pair.right, **kw)
+    assert compare(e, ref.process(oracle_params(kw), pair.left, pair.right), oL, oR) == []
+
+
+SMALL = [
+    # (w, h, D, extra params)
+    (9, 9, 4, {}),
+    (13, 11, 8, {}),
+    (37, 23, 16, {}),
+    (97, 61, 32, {}),
+    (131, 77, 64, {}),
+    (200, 50, 256, {}),
+    (65, 40, 100, {}),                         # D > w
+    (70, 33, 1, {}),                           # a single disparity: no support points
+    (90, 45, 20, dict(disp_min=5)),
+    (96, 48, 24, dict(full_search=1)),
+    (96, 48, 24, dict(candidate_stepsize=1)),
+    (123, 57, 48, dict(candidate_stepsize=3, grid_size=7, sradius=0)),
+    (150, 70, 40, dict(incon_window_size=2, incon_min_support=2, redun_max_dist=2,
+                       redun_threshold=0, lr_threshold=0)),
+    (77, 66, 30, dict(support_threshold=0.95, support_texture=0, match_texture=0)),
+    (111, 64, 33, dict(gamma=1.5, sigma=2.5, beta=0.01)),
+]
+
+
+@pytest.mark.parametrize("w,h,D,extra", SMALL)
+def test_small_and_ragged_sizes(E, w, h, D, extra):
+    dmin = extra.get("disp_min", 0)
+    cfg = synth.SceneConfig(w, h, max(D, 4), 3, 0.05, 1.0, max(2.0, D - 3.0), 2.0, 0.1,
+                            seed=w * 7 + h)
+    pair = synth.make_pair(cfg)
+    kw = dict(extra)
+    kw["disp_max"] = dmin + D - 1
+    e, oL, oR = run_pair(E, pair.left, pair.right, **kw)
+    assert compare(e, ref.process(oracle_params(kw), pair.left, pair.right), oL, oR) == []
+
+
+@pytest.mark.parametrize("stride", [64 + 3, 128, 333])
+def test_padded_rows(E, stride):
+    cfg = synth.SceneConfig(61, 45, 24, 3, 0.05, 2.0, 20.0, 2.0, 0.1, seed=stride)
+    pair = synth.make_pair(cfg)
+    kw = dict(disp_max=23)
+    e, oL, oR = run_pair(E, pair.left, pair.right, stride=stride, **kw)
+    assert compare(e, ref.process(oracle_params(kw), pair.left, pair.right), oL, oR) == []
+
+
+def test_flat_pair(E):
+    L = np.full((40, 64), 90, np.uint8)
+    kw = dict(disp_max=15)
+    e, oL, oR = run_pair(E, L, L, **kw)
+    t = ref.process(oracle_params(kw), L, L)
+    assert compare(e, t, oL, oR) == []
+    assert np.all(oL == -1) and e.stats()["n_support_left"] == 0
+
+
+def test_flat_pair_full_search(E):
+    L, R = synth.shifted_pair(64, 32, 5, seed=2)
+    kw = dict(disp_max=15, support_texture=10 ** 6, full_search=1)
+    e, oL, oR = run_pair(E, L, R, **kw)
+    assert compare(e, ref.process(oracle_params(kw), L, R), oL, oR) == []
+
+
+@pytest.mark.parametrize("d0", [9, 30])
+def test_constant_disparity(E, d0):
+    L, R = synth.shifted_pair(256, 40, d0, seed=d0)
+    kw = dict(disp_max=63)
+    e, oL, oR = run_pair(E, L, R, **kw)
+    assert compare(e, ref.process(oracle_params(kw), L, R), oL, oR) == []
+
+
+def test_handle_reuse_across_sizes_and_determinism(E):
+    dev = torch.device("cuda:0")
+    e = E.Elas(disp_max=63)
+    shapes = [(320, 240), (97, 61), (320, 240), (200, 120)]
+    first = {}
+    for i, (w, h) in enumerate(shapes):
+        cfg = synth.SceneConfig(w, h, 64, 5, 0.05, 4.0, 59.0, 2.0, 0.1, seed=i % 3)
+        pair = synth.make_pair(cfg)
+        L = torch.from_numpy(pair.left).to(dev)
+        R = torch.from_numpy(pair.right).to(dev)
+        oL, oR = e.process(L, R)
+        torch.cuda.synchronize()
+        t = ref.process(ref.params(disp_max=63), pair.left, pair.right)
+        assert compare(e, t, oL.cpu().numpy(), oR.cpu().numpy()) == []
+        key = (w, h, i % 3)
+        if key in first:
+            assert np.array_equal(first[key], oL.cpu().numpy())
+        first[key] = oL.cpu().numpy()
+
+
+def test_nondefault_stream(E):
+    dev = torch.device("cuda:0")
+    pair = synth.make_pair(synth.QVGA.with_seed(9))
+    s = torch.cuda.Stream(device=dev)
+    e = E.Elas(disp_max=63)
+    with torch.cuda.stream(s):
+        L = torch.from_numpy(pair.left).to(dev)
+        R = torch.from_numpy(pair.right).to(dev)
+        oL, oR = e.process(L, R, stream=s)
+    s.synchronize()
+    t = ref.process(ref.params(disp_max=63), pair.left, pair.right)
+    assert compare(e, t, oL.cpu().numpy(), oR.cpu().numpy()) == []
