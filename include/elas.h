@@ -87,6 +87,23 @@ typedef struct elas_stats {
   double  host_mesh_ms;        /* host time spent triangulating (both views) */
 } elas_stats;
 
+/* Per-stage device times of the most recent elas_process call, from HIP
+ * events recorded on the call's stream between stages (only while timing is
+ * enabled with elas_set_timing). */
+typedef struct elas_timing {
+  float descriptor_ms;         /* k_descriptor, both views */
+  float support_ms;            /* k_support (both search directions) */
+  float incon_ms;              /* k_incon */
+  float lists_ms;              /* k_lists: redundancy, lists, corners, grid */
+  float upload_ms;             /* host-to-device copy of the mesh records */
+  float raster_ms;             /* k_raster */
+  float dense_ms;              /* k_dense, both views */
+  float lrcheck_ms;            /* k_lrcheck */
+  float device_span_ms;        /* first stage start to last stage end, host step included */
+  double host_wait_ms;         /* calling thread blocked until the lists were ready */
+  double host_mesh_ms;         /* host triangulation and record building */
+} elas_timing;
+
 /* Fills *p with the default parameters. */
 ELAS_API void elas_params_default(elas_params* p);
 
@@ -95,7 +112,8 @@ ELAS_API void elas_params_default(elas_params* p);
  * Returns ELAS_ERR_ARG for invalid values (null pointers, D outside 1..256,
  * negative windows or thresholds, step or grid size < 1, non-positive or
  * non-finite beta/gamma/sigma) and ELAS_ERR_UNSUPPORTED when the prior
- * energies exceed the kernels' packed-key range (|lut[0]| > 2^22). */
+ * energies exceed the kernels' packed-key range (|lut[0]| > 2^22) or a
+ * filter window exceeds 16 lattice steps (incon_window_size, redun_max_dist). */
 ELAS_API int elas_create(const elas_params* p, elas_handle** out);
 
 /* Frees the handle and everything it owns. Waits for its pending work.
@@ -123,6 +141,14 @@ ELAS_API int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* ri
 /* Copies the counters of the last elas_process call (synchronises with its
  * stream first). */
 ELAS_API int elas_get_stats(elas_handle* h, elas_stats* out);
+
+/* Turns per-stage event timing on (1) or off (0) for later calls. Timing
+ * adds one event record per stage boundary to the stream. */
+ELAS_API int elas_set_timing(elas_handle* h, int32_t enable);
+
+/* Stage times of the last call made with timing on (synchronises with its
+ * stream). ELAS_ERR_ARG if no such call has completed. */
+ELAS_API int elas_get_timing(elas_handle* h, elas_timing* out);
 
 /* Describes the last failure on h (or of elas_create when h is NULL). The
  * string belongs to the library and stays valid until the next call. */

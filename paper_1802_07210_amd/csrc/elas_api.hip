@@ -2,9 +2,10 @@
 // device buffers, and the stage chain of one stereo pair.
 //
 // Stage chain of elas_process on the caller's stream:
-//   k_descriptor (both views) -> k_support -> k_incon -> k_lists
-//   -> [host: wait for the lists, Delaunay meshes of both views (two host
-//       threads), raster records -> one host-to-device copy]
+//   k_descriptor (both views) -> k_support -> k_filter -> k_rows
+//   -> [host: wait for the per-row lists, gather them and pick the corner
+//       disparities, Delaunay meshes of both views (two host threads),
+//       raster records -> one host-to-device copy]
 //   -> k_raster -> k_dense (both views) -> k_lrcheck.
 // The host step sits where the paper's ARM core sits between its two FPGA
 // phases (Section IV, Fig. 3).
@@ -29,6 +30,10 @@ using namespace elas;
 namespace {
 
 thread_local std::string g_create_error;
+
+// Stage boundary events: before descriptor; after descriptor, support, incon,
+// lists; before and after the mesh upload; after raster, dense, lrcheck.
+constexpr int kStageEvents = 10;
 
 // One background host thread that builds the right view's mesh while the
 // calling thread builds the left one.
@@ -87,20 +92,16 @@ struct Buffers {
   uint8_t *descL = nullptr, *descR = nullptr;
   int16_t *dcan_raw = nullptr, *dcan_incon = nullptr, *dcan_vert = nullptr,
           *dcan_final = nullptr;
-  int32_t *evals = nullptr, *row_scratch = nullptr, *flag_scratch = nullptr;
-  ListHeader* dev_hdr = nullptr;
-  int32_t *dev_ptsL = nullptr, *dev_ptsR = nullptr;
+  int32_t* evals = nullptr;
   uint32_t *gridL = nullptr, *gridR = nullptr;
   int32_t *ownerL = nullptr, *ownerR = nullptr;
   int16_t *dplaneL = nullptr, *dplaneR = nullptr, *rawL = nullptr, *rawR = nullptr;
   int32_t* lut = nullptr;
-  unsigned long long* dense_counter = nullptr;
-  // host-mapped lists written by k_lists
+  int32_t* dense_counts = nullptr;  // candidate evaluations per dense block
+  // host-mapped per-row lists written by k_rows: counts [3][lh], rows [lh][lw]
   void* host_block = nullptr;
-  ListHeader* host_hdr = nullptr;                 // host view
-  int32_t *host_ptsL = nullptr, *host_ptsR = nullptr;
-  ListHeader* host_hdr_dev = nullptr;             // the same memory, device view
-  int32_t *host_ptsL_dev = nullptr, *host_ptsR_dev = nullptr;
+  int32_t *hcnt = nullptr, *hrowL = nullptr, *hrowR = nullptr;              // host view
+  int32_t *hcnt_dev = nullptr, *hrowL_dev = nullptr, *hrowR_dev = nullptr;  // device view
   // raster records + work units: pinned staging and device copy (grown on demand)
   void* up_host = nullptr;
   void* up_dev = nullptr;
@@ -121,6 +122,7 @@ struct elas_handle {
   elas_stats stats{};
   MeshScratch* meshL = nullptr;
   MeshScratch* meshR = nullptr;
+  std::vector<int32_t> ptsL, ptsR;     // gathered support lists (u, v, d)
   std::vector<int32_t> recsL, recsR;
   std::vector<float> planesL, planesR;
   int32_t ntL = 0, ntR = 0;
@@ -129,6 +131,11 @@ struct elas_handle {
   hipEvent_t ev_lists = nullptr;
   hipEvent_t ev_upload = nullptr;
   bool upload_pending = false;
+  // stage timing
+  bool timing = false;
+  bool have_timing = false;
+  hipEvent_t tev[kStageEvents] = {};
+  double host_wait_ms = 0.0;
 };
 
 namespace {
@@ -202,14 +209,12 @@ int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   const size_t o_descL = take(npx * 16), o_descR = take(npx * 16);
   const size_t o_raw0 = take(nlat * 2), o_inc = take(nlat * 2), o_vert = take(nlat * 2),
                o_fin = take(nlat * 2);
-  const size_t o_evals = take(nlat * 4), o_rows = take(2 * ((size_t)g.lh + 1) * 4 + 4),
-               o_flags = take(nlat * 4);
-  const size_t o_hdr = take(sizeof(ListHeader)), o_pL = take(nlat * 12), o_pR = take(nlat * 12);
+  const size_t o_evals = take(nlat * 4);
   const size_t o_gL = take(ngrid * 4 + 4), o_gR = take(ngrid * 4 + 4);
   const size_t o_oL = take(npx * 4), o_oR = take(npx * 4);
   const size_t o_dpL = take(npx * 2), o_dpR = take(npx * 2), o_rL = take(npx * 2),
                o_rR = take(npx * 2);
-  const size_t o_lut = take(kMaxD * 4), o_cnt = take(8);
+  const size_t o_lut = take(kMaxD * 4), o_cnt = take((size_t)dense_blocks(g) * 4);
   hipError_t e = hipMalloc(&b->dev_block, off);
   if (e != hipSuccess) {
     delete b;
@@ -223,11 +228,6 @@ int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   b->dcan_vert = reinterpret_cast<int16_t*>(base + o_vert);
   b->dcan_final = reinterpret_cast<int16_t*>(base + o_fin);
   b->evals = reinterpret_cast<int32_t*>(base + o_evals);
-  b->row_scratch = reinterpret_cast<int32_t*>(base + o_rows);
-  b->flag_scratch = reinterpret_cast<int32_t*>(base + o_flags);
-  b->dev_hdr = reinterpret_cast<ListHeader*>(base + o_hdr);
-  b->dev_ptsL = reinterpret_cast<int32_t*>(base + o_pL);
-  b->dev_ptsR = reinterpret_cast<int32_t*>(base + o_pR);
   b->gridL = reinterpret_cast<uint32_t*>(base + o_gL);
   b->gridR = reinterpret_cast<uint32_t*>(base + o_gR);
   b->ownerL = reinterpret_cast<int32_t*>(base + o_oL);
@@ -237,28 +237,27 @@ int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   b->rawL = reinterpret_cast<int16_t*>(base + o_rL);
   b->rawR = reinterpret_cast<int16_t*>(base + o_rR);
   b->lut = reinterpret_cast<int32_t*>(base + o_lut);
-  b->dense_counter = reinterpret_cast<unsigned long long*>(base + o_cnt);
-  // host-mapped lists
-  const size_t hbytes = align_up(sizeof(ListHeader), 256) + 2 * nlat * 12;
-  e = hipHostMalloc(&b->host_block, hbytes, hipHostMallocMapped);
+  b->dense_counts = reinterpret_cast<int32_t*>(base + o_cnt);
+  // host-mapped per-row lists
+  const size_t nrows = std::max<size_t>(1, (size_t)g.lh);
+  const size_t hcount = 3 * nrows + 2 * nlat;
+  e = hipHostMalloc(&b->host_block, hcount * sizeof(int32_t), hipHostMallocMapped);
   if (e != hipSuccess) {
     free_buffers(b);
     return fail(h, ELAS_ERR_OOM, std::string("hipHostMalloc of list buffers: ") + hipGetErrorString(e));
   }
-  uint8_t* hb = static_cast<uint8_t*>(b->host_block);
-  b->host_hdr = reinterpret_cast<ListHeader*>(hb);
-  b->host_ptsL = reinterpret_cast<int32_t*>(hb + align_up(sizeof(ListHeader), 256));
-  b->host_ptsR = b->host_ptsL + 3 * nlat;
   void* hdev = nullptr;
   e = hipHostGetDevicePointer(&hdev, b->host_block, 0);
   if (e != hipSuccess) {
     free_buffers(b);
     return fail_hip(h, "hipHostGetDevicePointer of the list buffers", e);
   }
-  uint8_t* hd8 = static_cast<uint8_t*>(hdev);
-  b->host_hdr_dev = reinterpret_cast<ListHeader*>(hd8);
-  b->host_ptsL_dev = reinterpret_cast<int32_t*>(hd8 + align_up(sizeof(ListHeader), 256));
-  b->host_ptsR_dev = b->host_ptsL_dev + 3 * nlat;
+  b->hcnt = static_cast<int32_t*>(b->host_block);
+  b->hrowL = b->hcnt + 3 * nrows;
+  b->hrowR = b->hrowL + nlat;
+  b->hcnt_dev = static_cast<int32_t*>(hdev);
+  b->hrowL_dev = b->hcnt_dev + 3 * nrows;
+  b->hrowR_dev = b->hrowL_dev + nlat;
   e = hipMemcpy(b->lut, h->lut.data(), h->lut.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_buffers(b);
@@ -285,6 +284,64 @@ int ensure_upload(elas_handle* h, Buffers* b, size_t bytes) {
 }
 
 bool finite_positive(float x) { return std::isfinite(x) && x > 0.0f; }
+
+// Each image corner takes the d of the nearest list point (squared
+// distance; the earlier point in list order on ties).
+void corner_disparities(const std::vector<int32_t>& pts, int32_t n, int32_t w, int32_t hp,
+                        int32_t* out) {
+  const int32_t cu[4] = {0, w - 1, 0, w - 1}, cv[4] = {0, 0, hp - 1, hp - 1};
+  for (int c = 0; c < 4; ++c) {
+    int64_t best = -1;
+    int32_t d = -1;
+    for (int32_t i = 0; i < n; ++i) {
+      const int64_t du = pts[3 * i] - cu[c], dv = pts[3 * i + 1] - cv[c];
+      const int64_t dist = du * du + dv * dv;
+      if (best < 0 || dist < best) {
+        best = dist;
+        d = pts[3 * i + 2];
+      }
+    }
+    out[c] = d;
+  }
+}
+
+// Concatenates k_rows' per-row lists (left: lattice order; right: (v, u)
+// order) into (u, v, d) triples and derives the corner disparities.
+ListHeader gather_lists(elas_handle* h, Buffers* b) {
+  const Geometry& g = b->g;
+  ListHeader hd{};
+  int64_t evals = 0;
+  int32_t nL = 0, nR = 0;
+  for (int32_t l = 0; l < g.lh; ++l) {
+    nL += b->hcnt[l];
+    nR += b->hcnt[g.lh + l];
+    evals += b->hcnt[2 * g.lh + l];
+  }
+  h->ptsL.resize((size_t)3 * std::max(nL, 1));
+  h->ptsR.resize((size_t)3 * std::max(nR, 1));
+  int32_t iL = 0, iR = 0;
+  for (int32_t l = 0; l < g.lh; ++l) {
+    const int32_t v = g.lv0 + l * g.step;
+    const int32_t* rl = b->hrowL + (size_t)l * g.lw;
+    for (int32_t j = 0, n = b->hcnt[l]; j < n; ++j, ++iL) {
+      h->ptsL[3 * iL] = rl[j] & 0xFFFF;
+      h->ptsL[3 * iL + 1] = v;
+      h->ptsL[3 * iL + 2] = rl[j] >> 16;
+    }
+    const int32_t* rr = b->hrowR + (size_t)l * g.lw;
+    for (int32_t j = 0, n = b->hcnt[g.lh + l]; j < n; ++j, ++iR) {
+      h->ptsR[3 * iR] = rr[j] & 0xFFFF;
+      h->ptsR[3 * iR + 1] = v;
+      h->ptsR[3 * iR + 2] = rr[j] >> 16;
+    }
+  }
+  hd.nL = nL;
+  hd.nR = nR;
+  hd.support_evals = evals;
+  corner_disparities(h->ptsL, nL, g.w, g.h, hd.cornersL);
+  corner_disparities(h->ptsR, nR, g.w, g.h, hd.cornersR);
+  return hd;
+}
 
 }  // namespace
 
@@ -327,6 +384,8 @@ int elas_create(const elas_params* p, elas_handle** out) {
   if (!finite_positive(p->beta) || !finite_positive(p->gamma) || !finite_positive(p->sigma) ||
       !std::isfinite(p->support_threshold))
     return fail(nullptr, ELAS_ERR_ARG, "beta, gamma, sigma must be finite and > 0");
+  if (p->incon_window_size > 16 || p->redun_max_dist > 16)
+    return fail(nullptr, ELAS_ERR_UNSUPPORTED, "filter windows above 16 lattice steps");
   if (p->full_search != 0 && p->full_search != 1)
     return fail(nullptr, ELAS_ERR_ARG, "full_search must be 0 or 1");
   // Prior energy of a candidate at distance k from the plane mean: the ELAS
@@ -376,6 +435,8 @@ int elas_destroy(elas_handle* h) {
   for (auto& kv : h->cache) free_buffers(kv.second);
   if (h->ev_lists) (void)hipEventDestroy(h->ev_lists);
   if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
+  for (hipEvent_t& e : h->tev)
+    if (e) (void)hipEventDestroy(e);
   delete h->worker;
   mesh_scratch_destroy(h->meshL);
   mesh_scratch_destroy(h->meshR);
@@ -407,21 +468,33 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   const Geometry& g = b->g;
   const KParams& kp = h->kp;
   h->have_result = false;
+  h->have_timing = false;
   h->last = b;
   h->last_stream = stream;
+  const bool timed = h->timing;
+  if (timed && !h->tev[0])
+    for (hipEvent_t& e : h->tev) HIP_TRY(hipEventCreate(&e));
+#define STAGE_MARK(i) \
+  if (timed) HIP_TRY(hipEventRecord(h->tev[i], stream))
 
+  STAGE_MARK(0);
   HIP_TRY(launch_descriptor(left, right, stride, g, b->descL, b->descR, b->ownerL, b->ownerR,
                             stream));
+  STAGE_MARK(1);
   HIP_TRY(launch_support(b->descL, b->descR, g, kp, b->dcan_raw, b->evals, stream));
-  HIP_TRY(launch_incon(b->dcan_raw, g, kp, b->dcan_incon, stream));
-  HIP_TRY(launch_lists(g, kp, b->dcan_incon, b->dcan_vert, b->dcan_final, b->evals,
-                       b->row_scratch, b->flag_scratch, b->dev_hdr, b->dev_ptsL, b->dev_ptsR,
-                       b->host_hdr_dev, b->host_ptsL_dev, b->host_ptsR_dev, b->gridL, b->gridR,
-                       b->dense_counter, stream));
+  STAGE_MARK(2);
+  HIP_TRY(launch_filter(b->dcan_raw, g, kp, b->dcan_incon, b->dcan_vert, b->dcan_final,
+                        b->gridL, b->gridR, stream));
+  STAGE_MARK(3);
+  HIP_TRY(launch_rows(b->dcan_final, b->evals, g, kp, b->hrowL_dev, b->hrowR_dev, b->hcnt_dev,
+                      b->gridL, b->gridR, stream));
+  STAGE_MARK(4);
+  const auto tw0 = std::chrono::steady_clock::now();
   HIP_TRY(hipEventRecord(h->ev_lists, stream));
   HIP_TRY(hipEventSynchronize(h->ev_lists));
-  ListHeader hd;
-  std::memcpy(&hd, b->host_hdr, sizeof(hd));  // written by k_lists; visible after the event
+  h->host_wait_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tw0).count();
+  const ListHeader hd = gather_lists(h, b);
   h->hdr = hd;
 
   const auto t0 = std::chrono::steady_clock::now();
@@ -444,12 +517,12 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
     h->planesR.resize((size_t)ntR * 3);
     RasterTri* tris = static_cast<RasterTri*>(b->up_host);
     int32_t gotR = -1;
-    const int32_t* hptsR = b->host_ptsR;
+    const int32_t* hptsR = h->ptsR.data();
     h->worker->submit([&] {
       gotR = build_mesh(h->meshR, hptsR, hd.nR, hd.cornersR, w, hp, tris + ntL,
                         h->recsR.data(), h->planesR.data());
     });
-    const int32_t gotL = build_mesh(h->meshL, b->host_ptsL, hd.nL, hd.cornersL, w, hp, tris,
+    const int32_t gotL = build_mesh(h->meshL, h->ptsL.data(), hd.nL, hd.cornersL, w, hp, tris,
                                     h->recsL.data(), h->planesL.data());
     h->worker->wait();
     if (gotL != ntL || gotR != ntR)
@@ -466,12 +539,14 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
     }
     RasterUnit* units = reinterpret_cast<RasterUnit*>(static_cast<uint8_t*>(b->up_host) + tri_bytes);
     raster_units(tris, ntL + ntR, 0, units);
+    STAGE_MARK(5);
     HIP_TRY(hipMemcpyAsync(b->up_dev, b->up_host, bytes, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipEventRecord(h->ev_upload, stream));
     h->upload_pending = true;
     dev_tris = static_cast<const RasterTri*>(b->up_dev);
     dev_units = reinterpret_cast<const RasterUnit*>(static_cast<uint8_t*>(b->up_dev) + tri_bytes);
   } else {
+    STAGE_MARK(5);
     h->recsL.clear();
     h->recsR.clear();
     h->planesL.clear();
@@ -481,11 +556,17 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   h->ntR = ntR;
   const auto t1 = std::chrono::steady_clock::now();
 
+  STAGE_MARK(6);
   HIP_TRY(launch_raster(dev_tris, dev_units, nunits, ntL, g, b->ownerL, b->ownerR, stream));
+  STAGE_MARK(7);
   HIP_TRY(launch_dense(b->descL, b->descR, b->ownerL, b->ownerR, dev_tris, ntL, b->gridL,
                        b->gridR, b->lut, has_list, g, kp, b->dplaneL, b->dplaneR, b->rawL,
-                       b->rawR, b->dense_counter, stream));
+                       b->rawR, b->dense_counts, stream));
+  STAGE_MARK(8);
   HIP_TRY(launch_lrcheck(b->rawL, b->rawR, g, kp, disp_left, disp_right, stream));
+  STAGE_MARK(9);
+#undef STAGE_MARK
+  h->have_timing = timed;
 
   h->stats.support_evals = hd.support_evals;
   h->stats.dense_evals = -1;
@@ -498,13 +579,47 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   return ELAS_OK;
 }
 
+int elas_set_timing(elas_handle* h, int32_t enable) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  h->timing = enable != 0;
+  return ELAS_OK;
+}
+
+int elas_get_timing(elas_handle* h, elas_timing* out) {
+  if (!h || !out) return fail(h, ELAS_ERR_ARG, "null argument");
+  if (!h->have_result || !h->have_timing)
+    return fail(h, ELAS_ERR_ARG, "no completed call with timing enabled");
+  HIP_TRY(hipEventSynchronize(h->tev[kStageEvents - 1]));
+  float ms[kStageEvents - 1];
+  for (int i = 0; i + 1 < kStageEvents; ++i)
+    HIP_TRY(hipEventElapsedTime(&ms[i], h->tev[i], h->tev[i + 1]));
+  float span = 0.f;
+  HIP_TRY(hipEventElapsedTime(&span, h->tev[0], h->tev[kStageEvents - 1]));
+  out->descriptor_ms = ms[0];
+  out->support_ms = ms[1];
+  out->incon_ms = ms[2];
+  out->lists_ms = ms[3];
+  // ms[4] is the host step: the device idles between the lists and the upload
+  out->upload_ms = ms[5];
+  out->raster_ms = ms[6];
+  out->dense_ms = ms[7];
+  out->lrcheck_ms = ms[8];
+  out->device_span_ms = span;
+  out->host_wait_ms = h->host_wait_ms;
+  out->host_mesh_ms = h->stats.host_mesh_ms;
+  return ELAS_OK;
+}
+
 int elas_get_stats(elas_handle* h, elas_stats* out) {
   if (!h || !out) return fail(h, ELAS_ERR_ARG, "null argument");
   if (!h->have_result) return fail(h, ELAS_ERR_ARG, "no completed call");
   HIP_TRY(hipStreamSynchronize(h->last_stream));
-  unsigned long long cnt = 0;
-  HIP_TRY(hipMemcpy(&cnt, h->last->dense_counter, sizeof(cnt), hipMemcpyDeviceToHost));
-  h->stats.dense_evals = (int64_t)cnt;
+  std::vector<int32_t> counts(dense_blocks(h->last->g));
+  HIP_TRY(hipMemcpy(counts.data(), h->last->dense_counts, counts.size() * sizeof(int32_t),
+                    hipMemcpyDeviceToHost));
+  int64_t cnt = 0;
+  for (int32_t c : counts) cnt += c;
+  h->stats.dense_evals = cnt;
   *out = h->stats;
   return ELAS_OK;
 }
@@ -527,8 +642,8 @@ int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t byte
     case ELAS_I_DCAN_INCON: dsrc = b->dcan_incon; size = nlat * 2; break;
     case ELAS_I_DCAN_VERT: dsrc = b->dcan_vert; size = nlat * 2; break;
     case ELAS_I_DCAN_FINAL: dsrc = b->dcan_final; size = nlat * 2; break;
-    case ELAS_I_SUPPORT_LEFT: dsrc = b->dev_ptsL; size = (int64_t)h->hdr.nL * 12; break;
-    case ELAS_I_SUPPORT_RIGHT: dsrc = b->dev_ptsR; size = (int64_t)h->hdr.nR * 12; break;
+    case ELAS_I_SUPPORT_LEFT: hsrc = h->ptsL.data(); size = (int64_t)h->hdr.nL * 12; break;
+    case ELAS_I_SUPPORT_RIGHT: hsrc = h->ptsR.data(); size = (int64_t)h->hdr.nR * 12; break;
     case ELAS_I_CORNERS:
       std::memcpy(corners, h->hdr.cornersL, 16);
       std::memcpy(corners + 4, h->hdr.cornersR, 16);

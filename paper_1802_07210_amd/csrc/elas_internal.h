@@ -11,7 +11,6 @@ namespace elas {
 constexpr int kMaxD = 256;
 constexpr int32_t kNoOwner = 0x7FFFFFFF;
 constexpr int kRasterChunk = 1024;  // bounding-box pixels per raster work unit
-constexpr int kListsThreads = 1024;
 
 // Image, lattice and grid geometry of one (w, h) for one parameter set.
 struct Geometry {
@@ -49,7 +48,7 @@ struct RasterUnit {
   int32_t chunk;  // chunk index within the bounding box
 };
 
-// Header the lists kernel writes (device copy and host-mapped copy).
+// Support lists of one frame as the host gathers them.
 struct ListHeader {
   int32_t nL, nR;
   int32_t cornersL[4];
@@ -81,14 +80,17 @@ hipError_t launch_descriptor(const uint8_t* left, const uint8_t* right, int32_t 
                              int32_t* ownerL, int32_t* ownerR, hipStream_t s);
 hipError_t launch_support(const uint8_t* descL, const uint8_t* descR, const Geometry& g,
                           const KParams& p, int16_t* dcan, int32_t* evals, hipStream_t s);
-hipError_t launch_incon(const int16_t* in, const Geometry& g, const KParams& p, int16_t* out,
-                        hipStream_t s);
-hipError_t launch_lists(const Geometry& g, const KParams& p, const int16_t* dcan_incon,
-                        int16_t* dcan_vert, int16_t* dcan_final, const int32_t* evals,
-                        int32_t* row_scratch, int32_t* flag_scratch, ListHeader* dev_hdr,
-                        int32_t* dev_ptsL, int32_t* dev_ptsR, ListHeader* host_hdr,
-                        int32_t* host_ptsL, int32_t* host_ptsR, uint32_t* gridL,
-                        uint32_t* gridR, unsigned long long* dense_counter, hipStream_t s);
+// Fused consistency + redundancy filters; also clears the grid masks.
+size_t filter_lds_bytes(const KParams& p);
+hipError_t launch_filter(const int16_t* raw, const Geometry& g, const KParams& p,
+                         int16_t* incon, int16_t* vert, int16_t* fin, uint32_t* gridL,
+                         uint32_t* gridR, hipStream_t s);
+// Per-row support lists into host-mapped memory (hrowL/hrowR: [lh][lw] packed
+// u | d << 16; hcnt: left counts, right counts, evaluation counts, lh each)
+// and the grid masks.
+hipError_t launch_rows(const int16_t* fin, const int32_t* evals, const Geometry& g,
+                       const KParams& p, int32_t* hrowL, int32_t* hrowR, int32_t* hcnt,
+                       uint32_t* gridL, uint32_t* gridR, hipStream_t s);
 hipError_t launch_raster(const RasterTri* tris, const RasterUnit* units, int32_t nunits,
                          int32_t ntL, const Geometry& g, int32_t* ownerL, int32_t* ownerR,
                          hipStream_t s);
@@ -97,7 +99,9 @@ hipError_t launch_dense(const uint8_t* descL, const uint8_t* descR, const int32_
                         const uint32_t* gridL, const uint32_t* gridR, const int32_t* lut,
                         int32_t has_list, const Geometry& g, const KParams& p,
                         int16_t* dplaneL, int16_t* dplaneR, int16_t* rawL, int16_t* rawR,
-                        unsigned long long* dense_counter, hipStream_t s);
+                        int32_t* dense_counts, hipStream_t s);
+// Blocks of the dense launch (one candidate-count entry per block).
+int32_t dense_blocks(const Geometry& g);
 hipError_t launch_lrcheck(const int16_t* rawL, const int16_t* rawR, const Geometry& g,
                           const KParams& p, int16_t* outL, int16_t* outR, hipStream_t s);
 

@@ -11,6 +11,8 @@
 // byte differences accumulated per instruction). Minima over disparities use
 // packed keys (energy << 8 | d - dmin), so any evaluation order gives the
 // smallest energy with the smallest disparity on ties.
+#include <algorithm>
+
 #include "elas_internal.h"
 
 namespace elas {
@@ -44,6 +46,16 @@ __device__ __forceinline__ int wave_sum(int x) {
   return x;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b % 8), and each XCD has its own L2. Remapping the launch order so that XCD
+// x gets the x-th contiguous eighth of the logical blocks keeps each image
+// row band, and the descriptors written and read for it, in one L2 across
+// the descriptor, support, dense and check kernels. Bijective on [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // Gradient quantisation: divide by 4 truncating toward zero, clamp to
 // [-127, 127], offset by 128 (bytes 1..255; a negated gradient maps b to 256-b).
 __device__ __forceinline__ uint32_t quantise(int g) {
@@ -73,13 +85,17 @@ __global__ __launch_bounds__(256) void k_descriptor(const uint8_t* __restrict__ 
                                                     uint8_t* __restrict__ descR,
                                                     int32_t* __restrict__ ownerL,
                                                     int32_t* __restrict__ ownerR) {
-  const uint8_t* img = blockIdx.z ? right : left;
-  uint8_t* desc = blockIdx.z ? descR : descL;
-  int32_t* owner = blockIdx.z ? ownerR : ownerL;
+  // logical block: (tile row, tile column, view), views interleaved
+  const int nbx = (g.w + kDescW - 1) / kDescW;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int view = lb & 1, tile_id = lb >> 1;
+  const uint8_t* img = view ? right : left;
+  uint8_t* desc = view ? descR : descL;
+  int32_t* owner = view ? ownerR : ownerL;
   __shared__ uint8_t tile[kDescH + 6][kDescW + 8];
   __shared__ uint8_t qdu[kDescH + 4][kDescW + 4];
   __shared__ uint8_t qdv[kDescH + 4][kDescW + 4];
-  const int u0 = blockIdx.x * kDescW, v0 = blockIdx.y * kDescH;
+  const int u0 = (tile_id % nbx) * kDescW, v0 = (tile_id / nbx) * kDescH;
   const int tid = threadIdx.y * kDescW + threadIdx.x;
   for (int i = tid; i < (kDescH + 6) * (kDescW + 6); i += 256) {
     const int r = i / (kDescW + 6), c = i - r * (kDescW + 6);
@@ -188,7 +204,8 @@ __global__ __launch_bounds__(256) void k_support(const uint8_t* __restrict__ des
                                                  KParams p, int16_t* __restrict__ dcan,
                                                  int32_t* __restrict__ evals) {
   const int lane = threadIdx.x & 63;
-  const int pt = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int pt = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 +
+                                                (threadIdx.x >> 6));
   if (pt >= g.lw * g.lh) return;
   const int l = pt / g.lw, k = pt - l * g.lw;
   const int u = g.lu0 + k * g.step, v = g.lv0 + l * g.step;
@@ -220,241 +237,171 @@ __global__ __launch_bounds__(256) void k_support(const uint8_t* __restrict__ des
 }
 
 // ---------------------------------------------------------------------------
-// Stage 3a: inconsistency filter (Section III-A, Fig. 1(e)). A point survives
-// iff at least incon_min_support other points within +-incon_window lattice
-// steps have |d' - d| <= incon_threshold. Reads only the unfiltered lattice.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_incon(const int16_t* __restrict__ in, Geometry g,
-                                               KParams p, int16_t* __restrict__ out) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= g.lw * g.lh) return;
-  const int l = idx / g.lw, k = idx - l * g.lw;
-  const int d = in[idx];
-  int res = -1;
-  if (d >= 0) {
-    const int r = p.incon_window;
-    const int l0 = max(l - r, 0), l1 = min(l + r, g.lh - 1);
-    const int k0 = max(k - r, 0), k1 = min(k + r, g.lw - 1);
-    int count = 0;
-    for (int ll = l0; ll <= l1; ++ll) {
-      const int16_t* row = in + (size_t)ll * g.lw;
-      for (int kk = k0; kk <= k1; ++kk) {
-        const int e = row[kk];
-        count += (e >= 0 && abs(e - d) <= p.incon_threshold) ? 1 : 0;
-      }
-    }
-    count -= 1;  // the point itself was counted
-    res = count >= p.incon_min_support ? d : -1;
-  }
-  out[idx] = (int16_t)res;
-}
-
-// ---------------------------------------------------------------------------
-// Stage 3b: redundancy filter, support lists, corners and grid vectors, in
-// one workgroup of 1024 threads (the lattice is a few thousand to tens of
-// thousands of points; this stage is latency-, not throughput-bound).
-//  * redundancy (Section III-A: identical values along a row or column;
-//    Fig. 7A: look both backwards and forwards): a point goes iff within
+// Stage 3: support filtering (Section III-A, Fig. 1(e); Fig. 7A), three
+// simultaneous-update passes fused in one kernel over 16 x 16 lattice tiles
+// (1024 threads per tile, so each SIMD has four waves to hide LDS latency):
+//  * consistency: a point survives iff at least incon_min_support other
+//    points within +-incon_window lattice steps have |d' - d| <=
+//    incon_threshold;
+//  * redundancy, vertical then horizontal: a point goes iff within
 //    redun_max_dist steps on both sides along the pass there is a point with
-//    |d' - d| <= redun_threshold; vertical pass, then horizontal pass.
-//  * left list: survivors in lattice order. Right list: each survivor seen at
-//    (u - d, v); on collisions the larger d wins; ordered by (v, u).
-//  * corners: each image corner takes the d of the nearest list point
-//    (squared distance, earlier point on ties).
-//  * grid vectors (Fig. 2; Section VI-D one-hot): region mask bits d-1..d+1
-//    of every list point in the region.
-// The lists go to device memory and to host-mapped memory for the host mesh.
+//    |d' - d| <= redun_threshold.
+// The tile's raw values are staged in LDS with a halo of incon_window +
+// redun_max_dist; each pass is computed on the region the next pass reads
+// (positions outside the lattice count as empty). The kernel also clears the
+// grid masks that k_rows fills.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int redundant(const int16_t* in, const Geometry& g, const KParams& p,
-                                         int idx, bool vertical) {
-  const int l = idx / g.lw, k = idx - l * g.lw;
-  const int d = in[idx];
-  if (d < 0) return -1;
-  bool before = false, after = false;
-  for (int j = 1; j <= p.redun_max_dist; ++j) {
-    if (vertical) {
-      if (l - j >= 0) {
-        const int e = in[idx - j * g.lw];
-        before |= e >= 0 && abs(e - d) <= p.redun_threshold;
-      }
-      if (l + j < g.lh) {
-        const int e = in[idx + j * g.lw];
-        after |= e >= 0 && abs(e - d) <= p.redun_threshold;
-      }
-    } else {
-      if (k - j >= 0) {
-        const int e = in[idx - j];
-        before |= e >= 0 && abs(e - d) <= p.redun_threshold;
-      }
-      if (k + j < g.lw) {
-        const int e = in[idx + j];
-        after |= e >= 0 && abs(e - d) <= p.redun_threshold;
-      }
-    }
-  }
-  return (before && after) ? -1 : d;
-}
+constexpr int kFT = 16;
 
-// Exclusive prefix sum over the 1024 threads of the block; *total gets the sum.
-__device__ int block_exclusive_scan(int x, int* total, int* wsum) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int incl = x;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += y;
-  }
-  if (lane == 63) wsum[wid] = incl;
-  __syncthreads();
-  int before = 0, all = 0;
-#pragma unroll
-  for (int w2 = 0; w2 < kListsThreads / 64; ++w2) {
-    const int s = wsum[w2];
-    before += w2 < wid ? s : 0;
-    all += s;
-  }
-  __syncthreads();
-  *total = all;
-  return before + incl - x;
-}
-
-__global__ __launch_bounds__(kListsThreads) void k_lists(
-    Geometry g, KParams p, const int16_t* __restrict__ incon, int16_t* __restrict__ vert,
-    int16_t* __restrict__ fin, const int32_t* __restrict__ evals, int32_t* row_scratch,
-    int32_t* flag_scratch, ListHeader* dev_hdr, int32_t* dev_ptsL, int32_t* dev_ptsR,
-    ListHeader* host_hdr, int32_t* host_ptsL, int32_t* host_ptsR, uint32_t* gridL,
-    uint32_t* gridR, unsigned long long* dense_counter) {
-  __shared__ int wsum[kListsThreads / 64];
-  __shared__ unsigned long long s_corner[8];
-  __shared__ unsigned long long s_evals;
+__global__ __launch_bounds__(1024) void k_filter(const int16_t* __restrict__ raw, Geometry g,
+                                                KParams p, int16_t* __restrict__ incon_out,
+                                                int16_t* __restrict__ vert_out,
+                                                int16_t* __restrict__ fin_out,
+                                                uint32_t* __restrict__ gridL,
+                                                uint32_t* __restrict__ gridR) {
+  extern __shared__ int16_t smem[];
+  const int ri = p.incon_window, rr = p.redun_max_dist;
+  const int SR = kFT + 2 * (ri + rr), SI = kFT + 2 * rr;
+  int16_t* sraw = smem;            // SR x SR, origin (l0-ri-rr, k0-ri-rr)
+  int16_t* sinc = sraw + SR * SR;  // SI x SI, origin (l0-rr, k0-rr)
+  int16_t* svert = sinc + SI * SI; // kFT x SI, origin (l0, k0-rr)
+  const int k0 = blockIdx.x * kFT, l0 = blockIdx.y * kFT;
   const int tid = threadIdx.x;
-  const int N = g.lw * g.lh;
-  const int gcount = g.gw * g.gh * g.gwords;
-  for (int i = tid; i < gcount; i += kListsThreads) {
-    gridL[i] = 0u;
-    gridR[i] = 0u;
+  // clear the grid masks (grid-stride over all blocks)
+  {
+    const int gcount = g.gw * g.gh * g.gwords;
+    const int nthreads = gridDim.x * gridDim.y * 1024;
+    for (int i = (blockIdx.y * gridDim.x + blockIdx.x) * 1024 + tid; i < gcount; i += nthreads) {
+      gridL[i] = 0u;
+      gridR[i] = 0u;
+    }
   }
-  if (tid < 8) s_corner[tid] = ~0ull;
-  if (tid == 0) {
-    s_evals = 0ull;
-    *dense_counter = 0ull;
+  for (int i = tid; i < SR * SR; i += 1024) {
+    const int y = i / SR, x = i - y * SR;
+    const int l = l0 - ri - rr + y, k = k0 - ri - rr + x;
+    sraw[i] = (l >= 0 && l < g.lh && k >= 0 && k < g.lw) ? raw[(size_t)l * g.lw + k] : (int16_t)-1;
   }
-  for (int i = tid; i < N; i += kListsThreads) vert[i] = (int16_t)redundant(incon, g, p, i, true);
   __syncthreads();
-  for (int i = tid; i < N; i += kListsThreads) fin[i] = (int16_t)redundant(vert, g, p, i, false);
+  for (int i = tid; i < SI * SI; i += 1024) {
+    const int y = i / SI, x = i - y * SI;
+    const int d = sraw[(y + ri) * SR + (x + ri)];
+    int res = -1;
+    if (d >= 0) {
+      int count = 0;
+      for (int yy = y; yy <= y + 2 * ri; ++yy) {
+        const int16_t* row = sraw + yy * SR + x;
+        for (int xx = 0; xx <= 2 * ri; ++xx) {
+          const int e = row[xx];
+          count += (e >= 0 && abs(e - d) <= p.incon_threshold) ? 1 : 0;
+        }
+      }
+      res = (count - 1 >= p.incon_min_support) ? d : -1;  // minus the point itself
+    }
+    sinc[i] = (int16_t)res;
+  }
   __syncthreads();
-
-  // left list: compaction in lattice order; rowStartL[l] = first index of row l
-  int32_t* rowStartL = row_scratch;               // lh + 1 entries
-  int32_t* rowStartR = row_scratch + (g.lh + 1);  // lh + 1 entries
-  int base = 0;
-  for (int c0 = 0; c0 < N; c0 += kListsThreads) {
-    const int idx = c0 + tid;
-    const int d = idx < N ? fin[idx] : -1;
-    int total;
-    const int excl = block_exclusive_scan(d >= 0 ? 1 : 0, &total, wsum);
-    if (idx < N) {
-      const int l = idx / g.lw, k = idx - l * g.lw;
-      if (k == 0) rowStartL[l] = base + excl;
+  for (int i = tid; i < kFT * SI; i += 1024) {
+    const int y = i / SI, x = i - y * SI;
+    const int d = sinc[(y + rr) * SI + x];
+    int res = d;
+    if (d >= 0) {
+      bool before = false, after = false;
+      for (int j = 1; j <= rr; ++j) {
+        const int eb = sinc[(y + rr - j) * SI + x], ea = sinc[(y + rr + j) * SI + x];
+        before |= eb >= 0 && abs(eb - d) <= p.redun_threshold;
+        after |= ea >= 0 && abs(ea - d) <= p.redun_threshold;
+      }
+      if (before && after) res = -1;
+    }
+    svert[i] = (int16_t)res;
+  }
+  __syncthreads();
+  if (tid < kFT * kFT) {
+    const int y = tid / kFT, x = tid - y * kFT;
+    const int l = l0 + y, k = k0 + x;
+    if (l < g.lh && k < g.lw) {
+      const int d = svert[y * SI + x + rr];
+      int res = d;
       if (d >= 0) {
-        const int pos = base + excl;
-        const int u = g.lu0 + k * g.step, v = g.lv0 + l * g.step;
-        dev_ptsL[3 * pos] = u;
-        dev_ptsL[3 * pos + 1] = v;
-        dev_ptsL[3 * pos + 2] = d;
-        host_ptsL[3 * pos] = u;
-        host_ptsL[3 * pos + 1] = v;
-        host_ptsL[3 * pos + 2] = d;
+        bool before = false, after = false;
+        for (int j = 1; j <= rr; ++j) {
+          const int eb = svert[y * SI + x + rr - j], ea = svert[y * SI + x + rr + j];
+          before |= eb >= 0 && abs(eb - d) <= p.redun_threshold;
+          after |= ea >= 0 && abs(ea - d) <= p.redun_threshold;
+        }
+        if (before && after) res = -1;
       }
+      const size_t idx = (size_t)l * g.lw + k;
+      incon_out[idx] = sinc[(y + rr) * SI + x + rr];
+      vert_out[idx] = (int16_t)d;
+      fin_out[idx] = (int16_t)res;
     }
-    base += total;
   }
-  const int nL = base;
-  if (tid == 0) rowStartL[g.lh] = nL;
-  for (int l = tid; l <= g.lh; l += kListsThreads) rowStartR[l] = 0;
-  __syncthreads();
+}
 
-  // right list: a point is dropped if another point of its row lands on the
-  // same right-view pixel with a larger disparity
-  for (int i = tid; i < nL; i += kListsThreads) {
-    const int u = dev_ptsL[3 * i], v = dev_ptsL[3 * i + 1], d = dev_ptsL[3 * i + 2];
-    const int ur = u - d, l = (v - g.lv0) / g.step;
-    bool keep = true;
-    for (int j = rowStartL[l]; j < rowStartL[l + 1]; ++j) {
-      const int dj = dev_ptsL[3 * j + 2];
-      if (j != i && dev_ptsL[3 * j] - dj == ur && dj > d) keep = false;
+// ---------------------------------------------------------------------------
+// Support lists per lattice row, one wavefront per row, written straight to
+// host-mapped memory for the host mesh step, plus the grid vectors.
+//  * left list: the row's survivors in lattice order, packed u | d << 16;
+//  * right list (each point seen from the right view at (u - d, v); on
+//    collisions the larger d, the nearer surface, wins): an LDS slot per
+//    right-view column takes atomicMax of d, then the occupied slots in
+//    column order;
+//  * grid vectors (Fig. 2; one-hot, Section VI-D): bits d-1..d+1 of every
+//    list point are OR-ed into its region's mask, per view;
+//  * the row's support-search evaluation count.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_rows(const int16_t* __restrict__ fin,
+                                             const int32_t* __restrict__ evals, Geometry g,
+                                             KParams p, int32_t* __restrict__ hrowL,
+                                             int32_t* __restrict__ hrowR,
+                                             int32_t* __restrict__ hcnt,
+                                             uint32_t* __restrict__ gridL,
+                                             uint32_t* __restrict__ gridR) {
+  extern __shared__ int32_t slot[];  // one per image column
+  const int l = blockIdx.x, lane = threadIdx.x;
+  const int v = g.lv0 + l * g.step;
+  const int grow = (v / p.grid_size) * g.gw;
+  for (int x = lane; x < g.w; x += 64) slot[x] = -1;
+  __syncthreads();
+  int nL = 0, ev = 0;
+  const int16_t* frow = fin + (size_t)l * g.lw;
+  for (int k0 = 0; k0 < g.lw; k0 += 64) {
+    const int k = k0 + lane;
+    const int d = k < g.lw ? frow[k] : -1;
+    ev += k < g.lw ? evals[(size_t)l * g.lw + k] : 0;
+    const unsigned long long m = __ballot(d >= 0);
+    if (d >= 0) {
+      const int u = g.lu0 + k * g.step;
+      const int pos = nL + __popcll(m & ((1ull << lane) - 1ull));
+      hrowL[(size_t)l * g.lw + pos] = u | (d << 16);
+      atomicMax(&slot[u - d], d);
+      uint32_t* cell = gridL + (grow + u / p.grid_size) * g.gwords;
+      for (int dd = max(d - 1, p.dmin); dd <= min(d + 1, p.dmax); ++dd)
+        atomicOr(&cell[(dd - p.dmin) >> 5], 1u << ((dd - p.dmin) & 31));
     }
-    flag_scratch[i] = keep ? 1 : 0;
-    if (keep) atomicAdd(&rowStartR[l], 1);
+    nL += __popcll(m);
   }
   __syncthreads();
-  // exclusive scan of the per-row counts (in place)
-  int baseR = 0;
-  for (int c0 = 0; c0 <= g.lh; c0 += kListsThreads) {
-    const int idx = c0 + tid;
-    const int x = idx <= g.lh ? rowStartR[idx] : 0;
-    int total;
-    const int excl = block_exclusive_scan(x, &total, wsum);
-    if (idx <= g.lh) rowStartR[idx] = baseR + excl;
-    baseR += total;
-  }
-  const int nR = baseR;
-  __syncthreads();
-  for (int i = tid; i < nL; i += kListsThreads) {
-    if (!flag_scratch[i]) continue;
-    const int u = dev_ptsL[3 * i], v = dev_ptsL[3 * i + 1], d = dev_ptsL[3 * i + 2];
-    const int ur = u - d, l = (v - g.lv0) / g.step;
-    int rank = 0;
-    for (int j = rowStartL[l]; j < rowStartL[l + 1]; ++j)
-      rank += (flag_scratch[j] && dev_ptsL[3 * j] - dev_ptsL[3 * j + 2] < ur) ? 1 : 0;
-    const int pos = rowStartR[l] + rank;
-    dev_ptsR[3 * pos] = ur;
-    dev_ptsR[3 * pos + 1] = v;
-    dev_ptsR[3 * pos + 2] = d;
-    host_ptsR[3 * pos] = ur;
-    host_ptsR[3 * pos + 1] = v;
-    host_ptsR[3 * pos + 2] = d;
-  }
-  __syncthreads();
-
-  // corners and grid vectors of both views
-  const int cu[4] = {0, g.w - 1, 0, g.w - 1}, cv[4] = {0, 0, g.h - 1, g.h - 1};
-  for (int f = 0; f < 2; ++f) {
-    const int n = f ? nR : nL;
-    const int32_t* pts = f ? dev_ptsR : dev_ptsL;
-    uint32_t* grid = f ? gridR : gridL;
-    for (int i = tid; i < n; i += kListsThreads) {
-      const int u = pts[3 * i], v = pts[3 * i + 1], d = pts[3 * i + 2];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const long long du = u - cu[c], dv = v - cv[c];
-        const unsigned long long key =
-            ((unsigned long long)(du * du + dv * dv) << 32) | (unsigned long long)i;
-        atomicMin(&s_corner[4 * f + c], key);
-      }
-      const int cell = (v / p.grid_size) * g.gw + u / p.grid_size;
-      for (int dd = d - 1; dd <= d + 1; ++dd) {
-        if (dd < p.dmin || dd > p.dmax) continue;
-        const int bit = dd - p.dmin;
-        atomicOr(&grid[cell * g.gwords + (bit >> 5)], 1u << (bit & 31));
-      }
+  int nR = 0;
+  for (int x0 = 0; x0 < g.w; x0 += 64) {
+    const int x = x0 + lane;
+    const int d = x < g.w ? slot[x] : -1;
+    const unsigned long long m = __ballot(d >= 0);
+    if (d >= 0) {
+      const int pos = nR + __popcll(m & ((1ull << lane) - 1ull));
+      hrowR[(size_t)l * g.lw + pos] = x | (d << 16);
+      uint32_t* cell = gridR + (grow + x / p.grid_size) * g.gwords;
+      for (int dd = max(d - 1, p.dmin); dd <= min(d + 1, p.dmax); ++dd)
+        atomicOr(&cell[(dd - p.dmin) >> 5], 1u << ((dd - p.dmin) & 31));
     }
+    nR += __popcll(m);
   }
-  unsigned long long ev = 0;
-  for (int i = tid; i < N; i += kListsThreads) ev += (unsigned long long)evals[i];
-  atomicAdd(&s_evals, ev);
-  __syncthreads();
-  if (tid == 0) {
-    ListHeader hd;
-    hd.nL = nL;
-    hd.nR = nR;
-    for (int c = 0; c < 4; ++c) {
-      hd.cornersL[c] = nL > 0 ? dev_ptsL[3 * (int)(s_corner[c] & 0xFFFFFFFFull) + 2] : -1;
-      hd.cornersR[c] = nR > 0 ? dev_ptsR[3 * (int)(s_corner[4 + c] & 0xFFFFFFFFull) + 2] : -1;
-    }
-    hd.support_evals = (int64_t)s_evals;
-    *dev_hdr = hd;
-    *host_hdr = hd;
+  ev = wave_sum(ev);
+  if (lane == 0) {
+    hcnt[l] = nL;
+    hcnt[g.lh + l] = nR;
+    hcnt[2 * g.lh + l] = ev;
   }
 }
 
@@ -498,15 +445,19 @@ __global__ __launch_bounds__(256) void k_raster(const RasterTri* __restrict__ tr
 // floor(mean + 0.5) and clamped. Candidates: the plane window, the grid
 // region's one-hot mask (or every d with full_search), restricted to
 // partners with a defined descriptor. Energy: descriptor SAD plus the prior
-// table at |d - d_plane|. Argmin by packed key.
+// table at |d - d_plane|. Argmin by packed key. Candidates are taken from
+// the 64-bit masks eight at a time so that their descriptor gathers are in
+// flight together.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t bits_between(int a, int b) {
+__device__ __forceinline__ uint64_t bits64_between(int a, int b) {
   a = max(a, 0);
-  b = min(b, 31);
-  if (a > b) return 0u;
-  const uint32_t hi = b == 31 ? 0xFFFFFFFFu : ((2u << b) - 1u);
-  return hi & ~((1u << a) - 1u);
+  b = min(b, 63);
+  if (a > b) return 0ull;
+  const uint64_t hi = b == 63 ? ~0ull : ((2ull << b) - 1ull);
+  return hi & ~((1ull << a) - 1ull);
 }
+
+constexpr int kBatch = 8;  // candidate gathers issued together per lane
 
 __global__ __launch_bounds__(256) void k_dense(
     const uint8_t* __restrict__ descL, const uint8_t* __restrict__ descR,
@@ -515,14 +466,15 @@ __global__ __launch_bounds__(256) void k_dense(
     const uint32_t* __restrict__ gridR, const int32_t* __restrict__ lut, int32_t has_list,
     Geometry g, KParams p, int16_t* __restrict__ dplaneL, int16_t* __restrict__ dplaneR,
     int16_t* __restrict__ rawL, int16_t* __restrict__ rawR,
-    unsigned long long* __restrict__ dense_counter) {
+    int32_t* __restrict__ dense_counts) {
   __shared__ int32_t s_lut[kMaxD];
   __shared__ int s_cnt[4];
   for (int i = threadIdx.x; i < p.D; i += 256) s_lut[i] = lut[i];
   __syncthreads();
-  const bool right = blockIdx.y != 0;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);  // views interleaved per pixel block
+  const bool right = (lb & 1) != 0;
   const int npx = g.w * g.h;
-  const int px = blockIdx.x * 256 + threadIdx.x;
+  const int px = (lb >> 1) * 256 + threadIdx.x;
   int cnt = 0;
   if (px < npx) {
     const int v = px / g.w, u = px - v * g.w;
@@ -549,28 +501,49 @@ __global__ __launch_bounds__(256) void k_dense(
         const int lo = dp >= 0 ? max(dp - p.sradius, p.dmin) - p.dmin : 1;
         const int hi = dp >= 0 ? min(dp + p.sradius, p.dmax) - p.dmin : 0;
         const int top = min(lim, p.D - 1);
-        const uint32_t* cell =
-            has_list ? (right ? gridR : gridL) +
-                           ((size_t)(v / p.grid_size) * g.gw + u / p.grid_size) * g.gwords
+        const int nw = min(g.gwords >> 1, (top >> 6) + 1);  // 64-bit words in play
+        const uint64_t* cell =
+            has_list ? reinterpret_cast<const uint64_t*>(
+                           (right ? gridR : gridL) +
+                           ((size_t)(v / p.grid_size) * g.gw + u / p.grid_size) * g.gwords)
                      : nullptr;
+        uint64_t cw[kMaxD / 64];
+#pragma unroll
+        for (int j = 0; j < kMaxD / 64; ++j) cw[j] = (cell && j < nw) ? cell[j] : 0ull;
         uint32_t best = 0xFFFFFFFFu;
         const uint8_t* orow = other_desc + (size_t)v * g.w * 16;
-        for (int j = 0; j < g.gwords && 32 * j <= top; ++j) {
-          const int base = 32 * j;
-          uint32_t m = p.full_search ? 0xFFFFFFFFu : 0u;
-          if (cell) m |= cell[j];
-          m |= bits_between(lo - base, hi - base);
-          m &= bits_between(0, top - base);
+#pragma unroll
+        for (int j = 0; j < kMaxD / 64; ++j) {
+          if (j >= nw) break;
+          const int base = 64 * j;
+          uint64_t m = (p.full_search ? ~0ull : 0ull) | cw[j] | bits64_between(lo - base, hi - base);
+          m &= bits64_between(0, top - base);
           while (m) {
-            const int b = __builtin_ctz(m);
-            m &= m - 1u;
-            const int dd = base + b;
-            const int d = p.dmin + dd;
-            const int uo = right ? u + d : u - d;
-            int E = (int)sad16(s, ld16(orow + (size_t)uo * 16));
-            if (dp >= 0) E += s_lut[abs(d - dp)];
-            best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd);
-            ++cnt;
+            int dd[kBatch];
+            uint4 o[kBatch];
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+              dd[t] = -1;
+              if (m) {
+                dd[t] = base + __builtin_ctzll(m);
+                m &= m - 1ull;
+              }
+            }
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t)
+              if (dd[t] >= 0) {
+                const int d = p.dmin + dd[t];
+                o[t] = ld16(orow + (size_t)(right ? u + d : u - d) * 16);
+              }
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t)
+              if (dd[t] >= 0) {
+                const int d = p.dmin + dd[t];
+                int E = (int)sad16(s, o[t]);
+                if (dp >= 0) E += s_lut[abs(d - dp)];
+                best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd[t]);
+                ++cnt;
+              }
           }
         }
         if (best != 0xFFFFFFFFu) res = p.dmin + (int)(best & 0xFFu);
@@ -581,10 +554,7 @@ __global__ __launch_bounds__(256) void k_dense(
   cnt = wave_sum(cnt);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-    if (tot) atomicAdd(dense_counter, (unsigned long long)tot);
-  }
+  if (threadIdx.x == 0) dense_counts[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -594,11 +564,12 @@ __global__ __launch_bounds__(256) void k_lrcheck(const int16_t* __restrict__ raw
                                                  const int16_t* __restrict__ rawR, Geometry g,
                                                  KParams p, int16_t* __restrict__ outL,
                                                  int16_t* __restrict__ outR) {
-  const int px = blockIdx.x * 256 + threadIdx.x;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int px = (lb >> 1) * 256 + threadIdx.x;
   if (px >= g.w * g.h) return;
   const int v = px / g.w, u = px - v * g.w;
   const size_t row = (size_t)v * g.w;
-  if (blockIdx.y == 0) {
+  if ((lb & 1) == 0) {
     const int d = rawL[px];
     int r = -1;
     if (d >= 0 && u - d >= 0) {
@@ -624,7 +595,7 @@ inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) /
 hipError_t launch_descriptor(const uint8_t* left, const uint8_t* right, int32_t stride,
                              const Geometry& g, uint8_t* descL, uint8_t* descR,
                              int32_t* ownerL, int32_t* ownerR, hipStream_t s) {
-  dim3 grid(cdiv(g.w, kDescW), cdiv(g.h, kDescH), 2), block(kDescW, kDescH, 1);
+  dim3 grid(2 * cdiv(g.w, kDescW) * cdiv(g.h, kDescH)), block(kDescW, kDescH, 1);
   hipLaunchKernelGGL(k_descriptor, grid, block, 0, s, left, right, stride, g, descL, descR,
                      ownerL, ownerR);
   return hipGetLastError();
@@ -639,23 +610,26 @@ hipError_t launch_support(const uint8_t* descL, const uint8_t* descR, const Geom
   return hipGetLastError();
 }
 
-hipError_t launch_incon(const int16_t* in, const Geometry& g, const KParams& p, int16_t* out,
-                        hipStream_t s) {
-  const int n = g.lw * g.lh;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_incon, dim3(cdiv(n, 256)), dim3(256), 0, s, in, g, p, out);
+size_t filter_lds_bytes(const KParams& p) {
+  const int SR = kFT + 2 * (p.incon_window + p.redun_max_dist), SI = kFT + 2 * p.redun_max_dist;
+  return sizeof(int16_t) * (size_t)(SR * SR + SI * SI + kFT * SI);
+}
+
+hipError_t launch_filter(const int16_t* raw, const Geometry& g, const KParams& p,
+                         int16_t* incon, int16_t* vert, int16_t* fin, uint32_t* gridL,
+                         uint32_t* gridR, hipStream_t s) {
+  const dim3 grid(std::max(1u, cdiv(g.lw, kFT)), std::max(1u, cdiv(g.lh, kFT)));
+  hipLaunchKernelGGL(k_filter, grid, dim3(1024), filter_lds_bytes(p), s, raw, g, p, incon, vert,
+                     fin, gridL, gridR);
   return hipGetLastError();
 }
 
-hipError_t launch_lists(const Geometry& g, const KParams& p, const int16_t* dcan_incon,
-                        int16_t* dcan_vert, int16_t* dcan_final, const int32_t* evals,
-                        int32_t* row_scratch, int32_t* flag_scratch, ListHeader* dev_hdr,
-                        int32_t* dev_ptsL, int32_t* dev_ptsR, ListHeader* host_hdr,
-                        int32_t* host_ptsL, int32_t* host_ptsR, uint32_t* gridL,
-                        uint32_t* gridR, unsigned long long* dense_counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_lists, dim3(1), dim3(kListsThreads), 0, s, g, p, dcan_incon, dcan_vert,
-                     dcan_final, evals, row_scratch, flag_scratch, dev_hdr, dev_ptsL, dev_ptsR,
-                     host_hdr, host_ptsL, host_ptsR, gridL, gridR, dense_counter);
+hipError_t launch_rows(const int16_t* fin, const int32_t* evals, const Geometry& g,
+                       const KParams& p, int32_t* hrowL, int32_t* hrowR, int32_t* hcnt,
+                       uint32_t* gridL, uint32_t* gridR, hipStream_t s) {
+  if (g.lh == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows, dim3(g.lh), dim3(64), sizeof(int32_t) * (size_t)g.w, s, fin, evals,
+                     g, p, hrowL, hrowR, hcnt, gridL, gridR);
   return hipGetLastError();
 }
 
@@ -673,17 +647,19 @@ hipError_t launch_dense(const uint8_t* descL, const uint8_t* descR, const int32_
                         const uint32_t* gridL, const uint32_t* gridR, const int32_t* lut,
                         int32_t has_list, const Geometry& g, const KParams& p,
                         int16_t* dplaneL, int16_t* dplaneR, int16_t* rawL, int16_t* rawR,
-                        unsigned long long* dense_counter, hipStream_t s) {
-  dim3 grid(cdiv((long long)g.w * g.h, 256), 2);
+                        int32_t* dense_counts, hipStream_t s) {
+  dim3 grid(dense_blocks(g));
   hipLaunchKernelGGL(k_dense, grid, dim3(256), 0, s, descL, descR, ownerL, ownerR, tris, ntL,
                      gridL, gridR, lut, has_list, g, p, dplaneL, dplaneR, rawL, rawR,
-                     dense_counter);
+                     dense_counts);
   return hipGetLastError();
 }
 
+int32_t dense_blocks(const Geometry& g) { return 2 * (int32_t)cdiv((long long)g.w * g.h, 256); }
+
 hipError_t launch_lrcheck(const int16_t* rawL, const int16_t* rawR, const Geometry& g,
                           const KParams& p, int16_t* outL, int16_t* outR, hipStream_t s) {
-  dim3 grid(cdiv((long long)g.w * g.h, 256), 2);
+  dim3 grid(2 * cdiv((long long)g.w * g.h, 256));
   hipLaunchKernelGGL(k_lrcheck, grid, dim3(256), 0, s, rawL, rawR, g, p, outL, outR);
   return hipGetLastError();
 }

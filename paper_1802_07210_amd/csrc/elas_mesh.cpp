@@ -62,6 +62,8 @@ struct MeshScratch {
   std::vector<Tri> tris;
   std::vector<std::pair<int32_t, int32_t>> todo;  // (triangle, index of the new point)
   std::vector<std::array<int32_t, 9>> recs;
+  std::vector<int32_t> rank, order, bucket, sorted;
+  std::vector<std::pair<int32_t, int64_t>> key;
   int32_t last = 0;
 };
 
@@ -206,12 +208,6 @@ bool insert(MeshScratch& s, int32_t ip) {
   return true;
 }
 
-inline int cmp_vu(const int32_t* a, const int32_t* b) {
-  if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;
-  if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
-  return 0;
-}
-
 }  // namespace
 
 int32_t build_mesh(MeshScratch* sp, const int32_t* list, int32_t n, const int32_t* corners,
@@ -245,26 +241,50 @@ int32_t build_mesh(MeshScratch* sp, const int32_t* list, int32_t n, const int32_
   const int32_t ntri = (int32_t)s.tris.size();
   if (ntri != 2 * total - 6) return -1;
 
-  // canonical records: vertices by (v, u), triangles by their vertex triples
+  // canonical records: vertices by (v, u), triangles by their vertex triples.
+  // Rank every vertex in (v, u) order, then order triangles by their sorted
+  // rank triples: a counting sort on the smallest rank, and an insertion sort
+  // of the few triangles that share it.
+  const int32_t nv = total;
+  s.rank.resize(nv);
+  s.order.resize(nv);
+  for (int32_t i = 0; i < nv; ++i) s.order[i] = i;
+  std::sort(s.order.begin(), s.order.end(),
+            [&](int32_t x, int32_t y) { return vu_less(s.pts[x], s.pts[y]); });
+  for (int32_t i = 0; i < nv; ++i) s.rank[s.order[i]] = i;
+  s.key.resize(ntri);
+  s.bucket.assign(nv + 1, 0);
+  for (int32_t t = 0; t < ntri; ++t) {
+    int32_t r0 = s.rank[s.tris[t].v[0]], r1 = s.rank[s.tris[t].v[1]], r2 = s.rank[s.tris[t].v[2]];
+    if (r0 > r1) std::swap(r0, r1);
+    if (r1 > r2) std::swap(r1, r2);
+    if (r0 > r1) std::swap(r0, r1);
+    s.key[t] = {r0, ((int64_t)r1 << 32) | (uint32_t)r2};
+    ++s.bucket[r0 + 1];
+  }
+  for (int32_t i = 0; i < nv; ++i) s.bucket[i + 1] += s.bucket[i];
+  s.sorted.resize(ntri);
+  for (int32_t t = 0; t < ntri; ++t) s.sorted[s.bucket[s.key[t].first]++] = t;
+  for (int32_t lo = 0, i = 0; i <= ntri; ++i) {
+    if (i == ntri || s.key[s.sorted[i]].first != s.key[s.sorted[lo]].first) {
+      for (int32_t a = lo + 1; a < i; ++a)
+        for (int32_t b = a; b > lo && s.key[s.sorted[b]].second < s.key[s.sorted[b - 1]].second; --b)
+          std::swap(s.sorted[b], s.sorted[b - 1]);
+      lo = i;
+    }
+  }
   s.recs.resize(ntri);
   for (int32_t t = 0; t < ntri; ++t) {
     std::array<int32_t, 9>& r = s.recs[t];
-    int32_t ids[3] = {s.tris[t].v[0], s.tris[t].v[1], s.tris[t].v[2]};
-    std::sort(ids, ids + 3, [&](int32_t x, int32_t y) { return vu_less(s.pts[x], s.pts[y]); });
-    for (int k = 0; k < 3; ++k) {
-      r[3 * k] = s.pts[ids[k]].u;
-      r[3 * k + 1] = s.pts[ids[k]].v;
-      r[3 * k + 2] = s.disp[ids[k]];
+    const auto& k = s.key[s.sorted[t]];
+    const int32_t ids[3] = {s.order[k.first], s.order[(int32_t)(k.second >> 32)],
+                            s.order[(int32_t)(k.second & 0xFFFFFFFF)]};
+    for (int q = 0; q < 3; ++q) {
+      r[3 * q] = s.pts[ids[q]].u;
+      r[3 * q + 1] = s.pts[ids[q]].v;
+      r[3 * q + 2] = s.disp[ids[q]];
     }
   }
-  std::sort(s.recs.begin(), s.recs.end(),
-            [](const std::array<int32_t, 9>& x, const std::array<int32_t, 9>& y) {
-              for (int k = 0; k < 3; ++k) {
-                const int c = cmp_vu(x.data() + 3 * k, y.data() + 3 * k);
-                if (c) return c < 0;
-              }
-              return false;
-            });
 
   for (int32_t t = 0; t < ntri; ++t) {
     const std::array<int32_t, 9>& r = s.recs[t];

@@ -20,7 +20,8 @@ ERRORS = {-1: "ELAS_ERR_ARG", -2: "ELAS_ERR_OOM", -3: "ELAS_ERR_HIP",
           -4: "ELAS_ERR_UNSUPPORTED", -5: "ELAS_ERR_INTERNAL"}
 
 EXPORTS = ("elas_params_default", "elas_create", "elas_destroy", "elas_process",
-           "elas_get_stats", "elas_last_error", "elas_get_intermediate", "elas_triangulate")
+           "elas_get_stats", "elas_last_error", "elas_get_intermediate", "elas_triangulate",
+           "elas_set_timing", "elas_get_timing")
 
 
 class ElasParams(C.Structure):
@@ -42,6 +43,15 @@ class ElasStats(C.Structure):
         ("n_support_left", C.c_int32), ("n_support_right", C.c_int32),
         ("n_tri_left", C.c_int32), ("n_tri_right", C.c_int32),
         ("host_mesh_ms", C.c_double),
+    ]
+
+
+class ElasTiming(C.Structure):
+    _fields_ = [
+        ("descriptor_ms", C.c_float), ("support_ms", C.c_float), ("incon_ms", C.c_float),
+        ("lists_ms", C.c_float), ("upload_ms", C.c_float), ("raster_ms", C.c_float),
+        ("dense_ms", C.c_float), ("lrcheck_ms", C.c_float), ("device_span_ms", C.c_float),
+        ("host_wait_ms", C.c_double), ("host_mesh_ms", C.c_double),
     ]
 
 
@@ -85,6 +95,8 @@ def lib() -> C.CDLL:
         L.elas_last_error.restype = C.c_char_p
         L.elas_get_intermediate.argtypes = [vp, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.elas_triangulate.argtypes = [vp, C.c_int32, vp, C.c_int32, C.c_int32, vp, vp]
+        L.elas_set_timing.argtypes = [vp, C.c_int32]
+        L.elas_get_timing.argtypes = [vp, C.POINTER(ElasTiming)]
         for name in EXPORTS:
             if name not in ("elas_params_default", "elas_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -187,6 +199,14 @@ class Elas:
         st = ElasStats()
         _check(lib().elas_get_stats(self._h, C.byref(st)), self._h)
         return {k: getattr(st, k) for k, _ in ElasStats._fields_}
+
+    def set_timing(self, enable: bool):
+        _check(lib().elas_set_timing(self._h, int(bool(enable))), self._h)
+
+    def timing(self) -> dict:
+        t = ElasTiming()
+        _check(lib().elas_get_timing(self._h, C.byref(t)), self._h)
+        return {k: getattr(t, k) for k, _ in ElasTiming._fields_}
 
     def intermediate(self, name: str) -> np.ndarray:
         which, dtype = INTERMEDIATES[name]
