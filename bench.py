@@ -34,9 +34,9 @@ METRIC = "fps & pixel·disparity evals/s at 640×480 D=128; served p50/p99 laten
 PEAK_HBM_GBS = 8000.0
 PEAK_SAD_TOPS = 256 * 64 * 2.4e9 * 4 / 1e12    # 157.3 T byte-|diff| per second
 
-STAGES = ["descriptor", "support", "incon", "lists", "upload", "raster", "dense", "lrcheck"]
-KERNEL_NAMES = {"descriptor": "k_descriptor", "support": "k_support", "incon": "k_incon",
-                "lists": "k_lists", "raster": "k_raster", "dense": "k_dense",
+STAGES = ["descriptor", "support", "filter", "rows", "mesh", "raster", "dense", "lrcheck"]
+KERNEL_NAMES = {"descriptor": "k_descriptor", "support": "k_support", "filter": "k_filter",
+                "rows": "k_rows", "mesh": "k_mesh", "raster": "k_raster", "dense": "k_dense",
                 "lrcheck": "k_lrcheck"}
 
 
@@ -53,10 +53,13 @@ def algorithmic_work(stage: str, w: int, h: int, st: dict):
         return "hbm", 2 * npx * 6, "B"
     if stage == "raster":       # one 4 B owner update per covered pixel, 2 views
         return "hbm", 2 * npx * 4, "B"
-    if stage == "incon":        # lattice read + write
-        return "hbm", 4 * max(1, st.get("lattice", 0)), "B"
-    if stage == "lists":
+    if stage == "filter":       # lattice read + three lattice writes
+        return "hbm", 8 * max(1, st.get("lattice", 0)), "B"
+    if stage == "rows":         # final lattice + evaluation counts read, lists written
         return "hbm", 6 * max(1, st.get("lattice", 0)), "B"
+    if stage == "mesh":         # support points in, raster records out (24 B per triangle)
+        n = st["n_support_left"] + st["n_support_right"]
+        return "hbm", 12 * n + 24 * (st["n_tri_left"] + st["n_tri_right"]), "B"
     return "hbm", 0, "B"
 
 
@@ -96,6 +99,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
+    ap.add_argument("--mesh-on-host", action="store_true",
+                    help="triangulate on the host between the GPU phases (the paper's split)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the ELAS path runs on a single MI355X "
@@ -114,7 +119,7 @@ def main():
     R = torch.from_numpy(pair.right).to(dev)
     oL = torch.empty((H, W), dtype=torch.int16, device=dev)
     oR = torch.empty((H, W), dtype=torch.int16, device=dev)
-    e = Elas(disp_max=D - 1)
+    e = Elas(disp_max=D - 1, mesh_on_host=int(args.mesh_on_host))
     stream = torch.cuda.current_stream(dev)
 
     for _ in range(args.warmup):
@@ -169,7 +174,8 @@ def main():
         "config": {"workload": f"{W}x{H} D={D}, one stereo pair per step, seeded synthetic "
                                f"piecewise-planar scene ({cfg.planes} planes)",
                    "width": W, "height": H, "disp_range": D, "pairs_per_step": 1,
-                   "seed": args.seed},
+                   "seed": args.seed,
+                   "mesh": "host" if args.mesh_on_host else "device"},
         "evals_per_frame": evals,
         "evals_per_s_algorithmic": round(evals * fps, 1),
         "evals_per_s_nominal": round(nominal * fps, 1),

@@ -72,6 +72,9 @@ typedef struct elas_params {
   int32_t match_texture;       /* min texture of a 128-bit dense descriptor (1) */
   int32_t lr_threshold;        /* left/right agreement tolerance (2) */
   int32_t full_search;         /* 1: dense candidates = every admissible d (0) */
+  int32_t mesh_on_host;        /* 1: triangulate on the host between the two GPU
+                                  phases, as the paper's CPU/FPGA split does
+                                  (Section IV); 0: on the device (0) */
 } elas_params;
 
 typedef struct elas_handle elas_handle;
@@ -93,9 +96,10 @@ typedef struct elas_stats {
 typedef struct elas_timing {
   float descriptor_ms;         /* k_descriptor, both views */
   float support_ms;            /* k_support (both search directions) */
-  float incon_ms;              /* k_incon */
-  float lists_ms;              /* k_lists: redundancy, lists, corners, grid */
-  float upload_ms;             /* host-to-device copy of the mesh records */
+  float filter_ms;             /* k_filter: consistency and redundancy filters */
+  float rows_ms;               /* k_rows: support lists and grid vectors */
+  float mesh_ms;               /* device mesh kernel, or (mesh_on_host) the host
+                                  step and the upload of its records */
   float raster_ms;             /* k_raster */
   float dense_ms;              /* k_dense, both views */
   float lrcheck_ms;            /* k_lrcheck */
@@ -129,11 +133,13 @@ ELAS_API int elas_destroy(elas_handle* h);
  *   disp_left/right  device pointers, int16, w*h_px elements, row stride w;
  *                    caller-owned.
  * Stream-ordered: outputs are valid once `stream` reaches the end of the
- * enqueued work. The call itself blocks the calling thread while the support
- * stage finishes, because the triangulation runs on the host between the
- * support and dense stages (the same CPU/accelerator split the paper uses,
- * Section IV). Inputs must stay valid until then. Device buffers for the
- * image size are allocated on first use and cached in the handle. */
+ * enqueued work; with the default device mesh the call only enqueues work.
+ * With mesh_on_host the call blocks the calling thread until the support
+ * stage has finished, triangulates on the host, then enqueues the rest (the
+ * CPU/accelerator split of the paper, Section IV). Inputs must stay valid
+ * until the stream passes the work. Device buffers for the image size are
+ * allocated on first use and cached in the handle (first call per size
+ * synchronises the device). */
 ELAS_API int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right,
                           int32_t w, int32_t h_px, int32_t stride, hipStream_t stream,
                           int16_t* disp_left, int16_t* disp_right);

@@ -2,14 +2,16 @@
 // device buffers, and the stage chain of one stereo pair.
 //
 // Stage chain of elas_process on the caller's stream:
-//   k_descriptor (both views) -> k_support -> k_filter -> k_rows
-//   -> [host: wait for the per-row lists, gather them and pick the corner
-//       disparities, Delaunay meshes of both views (two host threads),
-//       raster records -> one host-to-device copy]
+//   k_descriptor (both views) -> k_support -> k_filter -> k_rows -> mesh
 //   -> k_raster -> k_dense (both views) -> k_lrcheck.
-// The host step sits where the paper's ARM core sits between its two FPGA
-// phases (Section IV, Fig. 3).
+// The mesh step runs either on the device (k_mesh, the default: the frame
+// never returns to the host, so the call only enqueues work) or, with
+// mesh_on_host, on the host between the two GPU phases as in the paper's
+// CPU/FPGA split (Section IV, Fig. 3): wait for the per-row lists, gather
+// them, pick the corner disparities, mesh both views on two host threads,
+// upload the raster records.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
@@ -20,7 +22,6 @@
 #include <string>
 #include <thread>
 #include <vector>
-#include <chrono>
 
 #include "elas.h"
 #include "elas_internal.h"
@@ -31,12 +32,13 @@ namespace {
 
 thread_local std::string g_create_error;
 
-// Stage boundary events: before descriptor; after descriptor, support, incon,
-// lists; before and after the mesh upload; after raster, dense, lrcheck.
-constexpr int kStageEvents = 10;
+// Stage boundary events: before the descriptor; after descriptor, support,
+// filter, rows, mesh (device kernel, or host step + upload), raster, dense,
+// check.
+constexpr int kStageEvents = 9;
 
 // One background host thread that builds the right view's mesh while the
-// calling thread builds the left one.
+// calling thread builds the left one (host mesh mode).
 class Worker {
  public:
   Worker() : th_([this] { loop(); }) {}
@@ -88,7 +90,8 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Device and pinned host memory for one image size.
 struct Buffers {
   Geometry g{};
-  void* dev_block = nullptr;     // every fixed-size device array, carved below
+  int32_t ntmax = 0;             // triangle capacity per view (2 * lattice + 2)
+  void* dev_block = nullptr;     // every device array, carved below
   uint8_t *descL = nullptr, *descR = nullptr;
   int16_t *dcan_raw = nullptr, *dcan_incon = nullptr, *dcan_vert = nullptr,
           *dcan_final = nullptr;
@@ -98,13 +101,20 @@ struct Buffers {
   int16_t *dplaneL = nullptr, *dplaneR = nullptr, *rawL = nullptr, *rawR = nullptr;
   int32_t* lut = nullptr;
   int32_t* dense_counts = nullptr;  // candidate evaluations per dense block
-  // host-mapped per-row lists written by k_rows: counts [3][lh], rows [lh][lw]
+  // per-row lists (device copy for the device mesh)
+  int32_t *rowsL = nullptr, *rowsR = nullptr, *cnt = nullptr;
+  // mesh outputs
+  MeshHeader* hdr = nullptr;
+  int32_t *ptsL = nullptr, *ptsR = nullptr, *recsL = nullptr, *recsR = nullptr;
+  float *planesL = nullptr, *planesR = nullptr;
+  RasterTri* tris = nullptr;
+  char* mesh_scratch = nullptr;
+  // host-mapped per-row lists (host mesh mode): counts [3][lh], rows [lh][lw]
   void* host_block = nullptr;
   int32_t *hcnt = nullptr, *hrowL = nullptr, *hrowR = nullptr;              // host view
   int32_t *hcnt_dev = nullptr, *hrowL_dev = nullptr, *hrowR_dev = nullptr;  // device view
-  // raster records + work units: pinned staging and device copy (grown on demand)
+  // pinned staging of the host mesh's raster records + header
   void* up_host = nullptr;
-  void* up_dev = nullptr;
   size_t up_cap = 0;
 };
 
@@ -118,24 +128,22 @@ struct elas_handle {
   Buffers* last = nullptr;
   hipStream_t last_stream = nullptr;
   bool have_result = false;
+  bool last_on_host = false;
   std::string err;
-  elas_stats stats{};
+  double host_mesh_ms = 0.0, host_wait_ms = 0.0;
   MeshScratch* meshL = nullptr;
   MeshScratch* meshR = nullptr;
-  std::vector<int32_t> ptsL, ptsR;     // gathered support lists (u, v, d)
+  std::vector<int32_t> ptsL, ptsR;     // host mesh mode: gathered lists (u, v, d)
   std::vector<int32_t> recsL, recsR;
   std::vector<float> planesL, planesR;
-  int32_t ntL = 0, ntR = 0;
-  ListHeader hdr{};
+  MeshHeader hhdr{};
   Worker* worker = nullptr;
   hipEvent_t ev_lists = nullptr;
   hipEvent_t ev_upload = nullptr;
   bool upload_pending = false;
-  // stage timing
   bool timing = false;
   bool have_timing = false;
   hipEvent_t tev[kStageEvents] = {};
-  double host_wait_ms = 0.0;
 };
 
 namespace {
@@ -152,9 +160,9 @@ int fail_hip(elas_handle* h, const char* what, hipError_t e) {
   return fail(h, ELAS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr)                                  \
-  do {                                                 \
-    hipError_t e_ = (expr);                            \
+#define HIP_TRY(expr)                                    \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
     if (e_ != hipSuccess) return fail_hip(h, #expr, e_); \
   } while (0)
 
@@ -162,7 +170,6 @@ void free_buffers(Buffers* b) {
   if (!b) return;
   if (b->dev_block) (void)hipFree(b->dev_block);
   if (b->host_block) (void)hipHostFree(b->host_block);
-  if (b->up_dev) (void)hipFree(b->up_dev);
   if (b->up_host) (void)hipHostFree(b->up_host);
   delete b;
 }
@@ -198,8 +205,10 @@ int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   const Geometry& g = b->g;
   const size_t npx = (size_t)w * hp;
   const size_t nlat = std::max<size_t>(1, (size_t)g.lw * g.lh);
+  const size_t nrows = std::max<size_t>(1, (size_t)g.lh);
   const size_t ngrid = (size_t)g.gw * g.gh * g.gwords;
-  // carve one device block
+  b->ntmax = (int32_t)(2 * nlat + 2);
+  const size_t ntmax = (size_t)b->ntmax;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -210,41 +219,62 @@ int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   const size_t o_raw0 = take(nlat * 2), o_inc = take(nlat * 2), o_vert = take(nlat * 2),
                o_fin = take(nlat * 2);
   const size_t o_evals = take(nlat * 4);
-  const size_t o_gL = take(ngrid * 4 + 4), o_gR = take(ngrid * 4 + 4);
+  const size_t o_gL = take(ngrid * 4 + 8), o_gR = take(ngrid * 4 + 8);
   const size_t o_oL = take(npx * 4), o_oR = take(npx * 4);
   const size_t o_dpL = take(npx * 2), o_dpR = take(npx * 2), o_rL = take(npx * 2),
                o_rR = take(npx * 2);
   const size_t o_lut = take(kMaxD * 4), o_cnt = take((size_t)dense_blocks(g) * 4);
+  const size_t o_rowsL = take(nlat * 4), o_rowsR = take(nlat * 4), o_rc = take(3 * nrows * 4);
+  const size_t o_hdr = take(sizeof(MeshHeader));
+  const size_t o_pL = take(nlat * 12), o_pR = take(nlat * 12);
+  const size_t o_recL = take(ntmax * 36), o_recR = take(ntmax * 36);
+  const size_t o_plL = take(ntmax * 12), o_plR = take(ntmax * 12);
+  const size_t o_tris = take(2 * ntmax * sizeof(RasterTri));
+  const size_t o_ms = take(2 * mesh_global_scratch_per_view(g));
   hipError_t e = hipMalloc(&b->dev_block, off);
   if (e != hipSuccess) {
     delete b;
-    return fail(h, ELAS_ERR_OOM, std::string("hipMalloc of device buffers: ") + hipGetErrorString(e));
+    return fail(h, ELAS_ERR_OOM,
+                std::string("hipMalloc of device buffers: ") + hipGetErrorString(e));
   }
   uint8_t* base = static_cast<uint8_t*>(b->dev_block);
-  b->descL = base + o_descL;
-  b->descR = base + o_descR;
-  b->dcan_raw = reinterpret_cast<int16_t*>(base + o_raw0);
-  b->dcan_incon = reinterpret_cast<int16_t*>(base + o_inc);
-  b->dcan_vert = reinterpret_cast<int16_t*>(base + o_vert);
-  b->dcan_final = reinterpret_cast<int16_t*>(base + o_fin);
-  b->evals = reinterpret_cast<int32_t*>(base + o_evals);
-  b->gridL = reinterpret_cast<uint32_t*>(base + o_gL);
-  b->gridR = reinterpret_cast<uint32_t*>(base + o_gR);
-  b->ownerL = reinterpret_cast<int32_t*>(base + o_oL);
-  b->ownerR = reinterpret_cast<int32_t*>(base + o_oR);
-  b->dplaneL = reinterpret_cast<int16_t*>(base + o_dpL);
-  b->dplaneR = reinterpret_cast<int16_t*>(base + o_dpR);
-  b->rawL = reinterpret_cast<int16_t*>(base + o_rL);
-  b->rawR = reinterpret_cast<int16_t*>(base + o_rR);
-  b->lut = reinterpret_cast<int32_t*>(base + o_lut);
-  b->dense_counts = reinterpret_cast<int32_t*>(base + o_cnt);
-  // host-mapped per-row lists
-  const size_t nrows = std::max<size_t>(1, (size_t)g.lh);
+  auto at = [&](size_t o) { return static_cast<void*>(base + o); };
+  b->descL = static_cast<uint8_t*>(at(o_descL));
+  b->descR = static_cast<uint8_t*>(at(o_descR));
+  b->dcan_raw = static_cast<int16_t*>(at(o_raw0));
+  b->dcan_incon = static_cast<int16_t*>(at(o_inc));
+  b->dcan_vert = static_cast<int16_t*>(at(o_vert));
+  b->dcan_final = static_cast<int16_t*>(at(o_fin));
+  b->evals = static_cast<int32_t*>(at(o_evals));
+  b->gridL = static_cast<uint32_t*>(at(o_gL));
+  b->gridR = static_cast<uint32_t*>(at(o_gR));
+  b->ownerL = static_cast<int32_t*>(at(o_oL));
+  b->ownerR = static_cast<int32_t*>(at(o_oR));
+  b->dplaneL = static_cast<int16_t*>(at(o_dpL));
+  b->dplaneR = static_cast<int16_t*>(at(o_dpR));
+  b->rawL = static_cast<int16_t*>(at(o_rL));
+  b->rawR = static_cast<int16_t*>(at(o_rR));
+  b->lut = static_cast<int32_t*>(at(o_lut));
+  b->dense_counts = static_cast<int32_t*>(at(o_cnt));
+  b->rowsL = static_cast<int32_t*>(at(o_rowsL));
+  b->rowsR = static_cast<int32_t*>(at(o_rowsR));
+  b->cnt = static_cast<int32_t*>(at(o_rc));
+  b->hdr = static_cast<MeshHeader*>(at(o_hdr));
+  b->ptsL = static_cast<int32_t*>(at(o_pL));
+  b->ptsR = static_cast<int32_t*>(at(o_pR));
+  b->recsL = static_cast<int32_t*>(at(o_recL));
+  b->recsR = static_cast<int32_t*>(at(o_recR));
+  b->planesL = static_cast<float*>(at(o_plL));
+  b->planesR = static_cast<float*>(at(o_plR));
+  b->tris = static_cast<RasterTri*>(at(o_tris));
+  b->mesh_scratch = static_cast<char*>(at(o_ms));
+  // host-mapped per-row lists for the host mesh mode
   const size_t hcount = 3 * nrows + 2 * nlat;
   e = hipHostMalloc(&b->host_block, hcount * sizeof(int32_t), hipHostMallocMapped);
   if (e != hipSuccess) {
     free_buffers(b);
-    return fail(h, ELAS_ERR_OOM, std::string("hipHostMalloc of list buffers: ") + hipGetErrorString(e));
+    return fail(h, ELAS_ERR_OOM,
+                std::string("hipHostMalloc of list buffers: ") + hipGetErrorString(e));
   }
   void* hdev = nullptr;
   e = hipHostGetDevicePointer(&hdev, b->host_block, 0);
@@ -271,13 +301,10 @@ int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
 int ensure_upload(elas_handle* h, Buffers* b, size_t bytes) {
   if (bytes <= b->up_cap) return ELAS_OK;
   const size_t cap = align_up(std::max(bytes, b->up_cap * 3 / 2), 1 << 16);
-  if (b->up_dev) (void)hipFree(b->up_dev);
   if (b->up_host) (void)hipHostFree(b->up_host);
-  b->up_dev = b->up_host = nullptr;
+  b->up_host = nullptr;
   b->up_cap = 0;
-  hipError_t e = hipMalloc(&b->up_dev, cap);
-  if (e != hipSuccess) return fail(h, ELAS_ERR_OOM, "hipMalloc of the mesh upload buffer");
-  e = hipHostMalloc(&b->up_host, cap, hipHostMallocDefault);
+  const hipError_t e = hipHostMalloc(&b->up_host, cap, hipHostMallocDefault);
   if (e != hipSuccess) return fail(h, ELAS_ERR_OOM, "hipHostMalloc of the mesh staging buffer");
   b->up_cap = cap;
   return ELAS_OK;
@@ -305,11 +332,10 @@ void corner_disparities(const std::vector<int32_t>& pts, int32_t n, int32_t w, i
   }
 }
 
-// Concatenates k_rows' per-row lists (left: lattice order; right: (v, u)
-// order) into (u, v, d) triples and derives the corner disparities.
-ListHeader gather_lists(elas_handle* h, Buffers* b) {
+// Host mesh mode: concatenates k_rows' per-row lists (left: lattice order;
+// right: (v, u) order) into (u, v, d) triples and derives the corners.
+void gather_lists(elas_handle* h, Buffers* b, MeshHeader* hd) {
   const Geometry& g = b->g;
-  ListHeader hd{};
   int64_t evals = 0;
   int32_t nL = 0, nR = 0;
   for (int32_t l = 0; l < g.lh; ++l) {
@@ -335,12 +361,74 @@ ListHeader gather_lists(elas_handle* h, Buffers* b) {
       h->ptsR[3 * iR + 2] = rr[j] >> 16;
     }
   }
-  hd.nL = nL;
-  hd.nR = nR;
-  hd.support_evals = evals;
-  corner_disparities(h->ptsL, nL, g.w, g.h, hd.cornersL);
-  corner_disparities(h->ptsR, nR, g.w, g.h, hd.cornersR);
-  return hd;
+  *hd = MeshHeader{};
+  hd->n[0] = nL;
+  hd->n[1] = nR;
+  hd->ntri[0] = nL > 0 ? 2 * nL + 2 : 0;
+  hd->ntri[1] = nR > 0 ? 2 * nR + 2 : 0;
+  hd->support_evals = evals;
+  corner_disparities(h->ptsL, nL, g.w, g.h, hd->corners);
+  corner_disparities(h->ptsR, nR, g.w, g.h, hd->corners + 4);
+}
+
+// Host mesh mode, after k_rows: wait, gather, mesh both views, upload the
+// raster records and the header.
+int host_mesh_step(elas_handle* h, Buffers* b, hipStream_t stream) {
+  const Geometry& g = b->g;
+  const auto tw0 = std::chrono::steady_clock::now();
+  HIP_TRY(hipEventRecord(h->ev_lists, stream));
+  HIP_TRY(hipEventSynchronize(h->ev_lists));
+  const auto t0 = std::chrono::steady_clock::now();
+  h->host_wait_ms = std::chrono::duration<double, std::milli>(t0 - tw0).count();
+  MeshHeader hd;
+  gather_lists(h, b, &hd);
+  const int32_t ntL = hd.ntri[0], ntR = hd.ntri[1];
+  // the staging buffer of the previous call must have been consumed
+  if (h->upload_pending) HIP_TRY(hipEventSynchronize(h->ev_upload));
+  h->upload_pending = false;
+  const size_t tri_bytes = align_up((size_t)(ntL + ntR) * sizeof(RasterTri), 256);
+  int rc = ensure_upload(h, b, tri_bytes + sizeof(MeshHeader));
+  if (rc != ELAS_OK) return rc;
+  RasterTri* tris = static_cast<RasterTri*>(b->up_host);
+  h->recsL.assign((size_t)ntL * 9, 0);
+  h->planesL.assign((size_t)ntL * 3, 0.f);
+  h->recsR.assign((size_t)ntR * 9, 0);
+  h->planesR.assign((size_t)ntR * 3, 0.f);
+  if (hd.n[0] > 0) {
+    int32_t gotR = -1;
+    h->worker->submit([&] {
+      gotR = build_mesh(h->meshR, h->ptsR.data(), hd.n[1], hd.corners + 4, g.w, g.h,
+                        tris + ntL, h->recsR.data(), h->planesR.data());
+    });
+    const int32_t gotL = build_mesh(h->meshL, h->ptsL.data(), hd.n[0], hd.corners, g.w, g.h,
+                                    tris, h->recsL.data(), h->planesL.data());
+    h->worker->wait();
+    if (gotL != ntL || gotR != ntR)
+      return fail(h, ELAS_ERR_INTERNAL, "host triangulation failed its consistency checks");
+  }
+  std::memcpy(static_cast<uint8_t*>(b->up_host) + tri_bytes, &hd, sizeof(hd));
+  h->hhdr = hd;
+  if (ntL + ntR > 0)
+    HIP_TRY(hipMemcpyAsync(b->tris, b->up_host, (size_t)(ntL + ntR) * sizeof(RasterTri),
+                           hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(b->hdr, static_cast<uint8_t*>(b->up_host) + tri_bytes,
+                         sizeof(MeshHeader), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(h->ev_upload, stream));
+  h->upload_pending = true;
+  h->host_mesh_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return ELAS_OK;
+}
+
+// Header of the last call (device mesh: copied back; host mesh: kept).
+int last_header(elas_handle* h, MeshHeader* out) {
+  if (h->last_on_host) {
+    *out = h->hhdr;
+    return ELAS_OK;
+  }
+  HIP_TRY(hipStreamSynchronize(h->last_stream));
+  HIP_TRY(hipMemcpy(out, h->last->hdr, sizeof(MeshHeader), hipMemcpyDeviceToHost));
+  return ELAS_OK;
 }
 
 }  // namespace
@@ -367,6 +455,7 @@ void elas_params_default(elas_params* p) {
   p->match_texture = 1;
   p->lr_threshold = 2;
   p->full_search = 0;
+  p->mesh_on_host = 0;
 }
 
 int elas_create(const elas_params* p, elas_handle** out) {
@@ -374,7 +463,8 @@ int elas_create(const elas_params* p, elas_handle** out) {
   *out = nullptr;
   const int32_t D = p->disp_max - p->disp_min + 1;
   if (p->disp_min < 0 || p->disp_max < p->disp_min || D > kMaxD)
-    return fail(nullptr, ELAS_ERR_ARG, "disparity range must satisfy 0 <= min <= max, max-min < 256");
+    return fail(nullptr, ELAS_ERR_ARG,
+                "disparity range must satisfy 0 <= min <= max, max-min < 256");
   if (p->candidate_stepsize < 1 || p->grid_size < 1)
     return fail(nullptr, ELAS_ERR_ARG, "candidate_stepsize and grid_size must be >= 1");
   if (p->incon_window_size < 0 || p->incon_threshold < 0 || p->incon_min_support < 0 ||
@@ -384,18 +474,20 @@ int elas_create(const elas_params* p, elas_handle** out) {
   if (!finite_positive(p->beta) || !finite_positive(p->gamma) || !finite_positive(p->sigma) ||
       !std::isfinite(p->support_threshold))
     return fail(nullptr, ELAS_ERR_ARG, "beta, gamma, sigma must be finite and > 0");
-  if (p->incon_window_size > 16 || p->redun_max_dist > 16)
-    return fail(nullptr, ELAS_ERR_UNSUPPORTED, "filter windows above 16 lattice steps");
   if (p->full_search != 0 && p->full_search != 1)
     return fail(nullptr, ELAS_ERR_ARG, "full_search must be 0 or 1");
+  if (p->mesh_on_host != 0 && p->mesh_on_host != 1)
+    return fail(nullptr, ELAS_ERR_ARG, "mesh_on_host must be 0 or 1");
+  if (p->incon_window_size > 16 || p->redun_max_dist > 16)
+    return fail(nullptr, ELAS_ERR_UNSUPPORTED, "filter windows above 16 lattice steps");
   // Prior energy of a candidate at distance k from the plane mean: the ELAS
   // plane prior gamma + exp(-k^2 / (2 sigma^2)) as a negative log, over beta,
   // offset by log(gamma)/beta so that far candidates cost 0; rounded.
   std::vector<int32_t> lut(D);
   const double g = p->gamma, s = p->sigma, b = p->beta;
   for (int32_t k = 0; k < D; ++k) {
-    const double x = -(std::log(g + std::exp(-(double)k * (double)k / (2.0 * s * s))) -
-                       std::log(g)) / b;
+    const double x =
+        -(std::log(g + std::exp(-(double)k * (double)k / (2.0 * s * s))) - std::log(g)) / b;
     if (!(std::fabs(x) < 4.0e6))
       return fail(nullptr, ELAS_ERR_UNSUPPORTED, "prior energy out of range (beta too small)");
     lut[k] = (int32_t)std::lround(x);
@@ -431,7 +523,7 @@ int elas_create(const elas_params* p, elas_handle** out) {
 
 int elas_destroy(elas_handle* h) {
   if (!h) return ELAS_OK;
-  if (h->last_stream || h->have_result) (void)hipStreamSynchronize(h->last_stream);
+  if (h->have_result) (void)hipStreamSynchronize(h->last_stream);
   for (auto& kv : h->cache) free_buffers(kv.second);
   if (h->ev_lists) (void)hipEventDestroy(h->ev_lists);
   if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
@@ -457,11 +549,12 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   if (w < 9 || hp < 9 || w > 8192 || hp > 8192)
     return fail(h, ELAS_ERR_ARG, "image size must be 9..8192 in each dimension");
   if (stride < w) return fail(h, ELAS_ERR_ARG, "stride must be >= width");
-  if (!h->ev_lists) {
+  const bool on_host = h->params.mesh_on_host != 0;
+  if (on_host && !h->ev_lists) {
     HIP_TRY(hipEventCreateWithFlags(&h->ev_lists, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&h->ev_upload, hipEventDisableTiming));
   }
-  if (!h->worker) h->worker = new Worker();
+  if (on_host && !h->worker) h->worker = new Worker();
   Buffers* b = nullptr;
   int rc = get_buffers(h, w, hp, &b);
   if (rc != ELAS_OK) return rc;
@@ -471,6 +564,8 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   h->have_timing = false;
   h->last = b;
   h->last_stream = stream;
+  h->last_on_host = on_host;
+  h->host_mesh_ms = h->host_wait_ms = 0.0;
   const bool timed = h->timing;
   if (timed && !h->tev[0])
     for (hipEvent_t& e : h->tev) HIP_TRY(hipEventCreate(&e));
@@ -486,95 +581,30 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   HIP_TRY(launch_filter(b->dcan_raw, g, kp, b->dcan_incon, b->dcan_vert, b->dcan_final,
                         b->gridL, b->gridR, stream));
   STAGE_MARK(3);
-  HIP_TRY(launch_rows(b->dcan_final, b->evals, g, kp, b->hrowL_dev, b->hrowR_dev, b->hcnt_dev,
-                      b->gridL, b->gridR, stream));
-  STAGE_MARK(4);
-  const auto tw0 = std::chrono::steady_clock::now();
-  HIP_TRY(hipEventRecord(h->ev_lists, stream));
-  HIP_TRY(hipEventSynchronize(h->ev_lists));
-  h->host_wait_ms =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tw0).count();
-  const ListHeader hd = gather_lists(h, b);
-  h->hdr = hd;
-
-  const auto t0 = std::chrono::steady_clock::now();
-  const int32_t has_list = hd.nL > 0 ? 1 : 0;
-  int32_t ntL = 0, ntR = 0, nunits = 0;
-  const RasterTri* dev_tris = nullptr;
-  const RasterUnit* dev_units = nullptr;
-  if (has_list) {
-    ntL = 2 * hd.nL + 2;
-    ntR = 2 * hd.nR + 2;
-    // the staging buffer of the previous call must have been consumed
-    if (h->upload_pending) HIP_TRY(hipEventSynchronize(h->ev_upload));
-    h->upload_pending = false;
-    const size_t tri_bytes = align_up((size_t)(ntL + ntR) * sizeof(RasterTri), 256);
-    rc = ensure_upload(h, b, tri_bytes);
+  if (on_host) {
+    HIP_TRY(launch_rows(b->dcan_final, b->evals, g, kp, b->hrowL_dev, b->hrowR_dev, b->hcnt_dev,
+                        b->gridL, b->gridR, stream));
+    STAGE_MARK(4);
+    rc = host_mesh_step(h, b, stream);
     if (rc != ELAS_OK) return rc;
-    h->recsL.resize((size_t)ntL * 9);
-    h->planesL.resize((size_t)ntL * 3);
-    h->recsR.resize((size_t)ntR * 9);
-    h->planesR.resize((size_t)ntR * 3);
-    RasterTri* tris = static_cast<RasterTri*>(b->up_host);
-    int32_t gotR = -1;
-    const int32_t* hptsR = h->ptsR.data();
-    h->worker->submit([&] {
-      gotR = build_mesh(h->meshR, hptsR, hd.nR, hd.cornersR, w, hp, tris + ntL,
-                        h->recsR.data(), h->planesR.data());
-    });
-    const int32_t gotL = build_mesh(h->meshL, h->ptsL.data(), hd.nL, hd.cornersL, w, hp, tris,
-                                    h->recsL.data(), h->planesL.data());
-    h->worker->wait();
-    if (gotL != ntL || gotR != ntR)
-      return fail(h, ELAS_ERR_INTERNAL, "host triangulation failed its consistency checks");
-    nunits = raster_units(tris, ntL + ntR, 0, nullptr);
-    const size_t bytes = tri_bytes + (size_t)nunits * sizeof(RasterUnit);
-    if (bytes > b->up_cap) {
-      // grow, keeping the records already written
-      std::vector<RasterTri> keep(tris, tris + ntL + ntR);
-      rc = ensure_upload(h, b, bytes);
-      if (rc != ELAS_OK) return rc;
-      tris = static_cast<RasterTri*>(b->up_host);
-      std::memcpy(tris, keep.data(), keep.size() * sizeof(RasterTri));
-    }
-    RasterUnit* units = reinterpret_cast<RasterUnit*>(static_cast<uint8_t*>(b->up_host) + tri_bytes);
-    raster_units(tris, ntL + ntR, 0, units);
-    STAGE_MARK(5);
-    HIP_TRY(hipMemcpyAsync(b->up_dev, b->up_host, bytes, hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipEventRecord(h->ev_upload, stream));
-    h->upload_pending = true;
-    dev_tris = static_cast<const RasterTri*>(b->up_dev);
-    dev_units = reinterpret_cast<const RasterUnit*>(static_cast<uint8_t*>(b->up_dev) + tri_bytes);
   } else {
-    STAGE_MARK(5);
-    h->recsL.clear();
-    h->recsR.clear();
-    h->planesL.clear();
-    h->planesR.clear();
+    HIP_TRY(launch_rows(b->dcan_final, b->evals, g, kp, b->rowsL, b->rowsR, b->cnt, b->gridL,
+                        b->gridR, stream));
+    STAGE_MARK(4);
+    HIP_TRY(launch_mesh(b->rowsL, b->rowsR, b->cnt, g, b->hdr, b->ptsL, b->ptsR, b->recsL,
+                        b->recsR, b->planesL, b->planesR, b->tris, b->mesh_scratch, stream));
   }
-  h->ntL = ntL;
-  h->ntR = ntR;
-  const auto t1 = std::chrono::steady_clock::now();
-
+  STAGE_MARK(5);
+  HIP_TRY(launch_raster(b->tris, b->hdr, g, b->ownerL, b->ownerR, stream));
   STAGE_MARK(6);
-  HIP_TRY(launch_raster(dev_tris, dev_units, nunits, ntL, g, b->ownerL, b->ownerR, stream));
+  HIP_TRY(launch_dense(b->descL, b->descR, b->ownerL, b->ownerR, b->tris, b->hdr, b->gridL,
+                       b->gridR, b->lut, g, kp, b->dplaneL, b->dplaneR, b->rawL, b->rawR,
+                       b->dense_counts, stream));
   STAGE_MARK(7);
-  HIP_TRY(launch_dense(b->descL, b->descR, b->ownerL, b->ownerR, dev_tris, ntL, b->gridL,
-                       b->gridR, b->lut, has_list, g, kp, b->dplaneL, b->dplaneR, b->rawL,
-                       b->rawR, b->dense_counts, stream));
-  STAGE_MARK(8);
   HIP_TRY(launch_lrcheck(b->rawL, b->rawR, g, kp, disp_left, disp_right, stream));
-  STAGE_MARK(9);
+  STAGE_MARK(8);
 #undef STAGE_MARK
   h->have_timing = timed;
-
-  h->stats.support_evals = hd.support_evals;
-  h->stats.dense_evals = -1;
-  h->stats.n_support_left = hd.nL;
-  h->stats.n_support_right = hd.nR;
-  h->stats.n_tri_left = ntL;
-  h->stats.n_tri_right = ntR;
-  h->stats.host_mesh_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   h->have_result = true;
   return ELAS_OK;
 }
@@ -597,30 +627,39 @@ int elas_get_timing(elas_handle* h, elas_timing* out) {
   HIP_TRY(hipEventElapsedTime(&span, h->tev[0], h->tev[kStageEvents - 1]));
   out->descriptor_ms = ms[0];
   out->support_ms = ms[1];
-  out->incon_ms = ms[2];
-  out->lists_ms = ms[3];
-  // ms[4] is the host step: the device idles between the lists and the upload
-  out->upload_ms = ms[5];
-  out->raster_ms = ms[6];
-  out->dense_ms = ms[7];
-  out->lrcheck_ms = ms[8];
+  out->filter_ms = ms[2];
+  out->rows_ms = ms[3];
+  out->mesh_ms = ms[4];
+  out->raster_ms = ms[5];
+  out->dense_ms = ms[6];
+  out->lrcheck_ms = ms[7];
   out->device_span_ms = span;
   out->host_wait_ms = h->host_wait_ms;
-  out->host_mesh_ms = h->stats.host_mesh_ms;
+  out->host_mesh_ms = h->host_mesh_ms;
   return ELAS_OK;
 }
 
 int elas_get_stats(elas_handle* h, elas_stats* out) {
   if (!h || !out) return fail(h, ELAS_ERR_ARG, "null argument");
   if (!h->have_result) return fail(h, ELAS_ERR_ARG, "no completed call");
+  MeshHeader hd;
+  int rc = last_header(h, &hd);
+  if (rc != ELAS_OK) return rc;
   HIP_TRY(hipStreamSynchronize(h->last_stream));
   std::vector<int32_t> counts(dense_blocks(h->last->g));
   HIP_TRY(hipMemcpy(counts.data(), h->last->dense_counts, counts.size() * sizeof(int32_t),
                     hipMemcpyDeviceToHost));
   int64_t cnt = 0;
   for (int32_t c : counts) cnt += c;
-  h->stats.dense_evals = cnt;
-  *out = h->stats;
+  if (hd.status[0] || hd.status[1])
+    return fail(h, ELAS_ERR_INTERNAL, "device mesh did not converge");
+  out->support_evals = hd.support_evals;
+  out->dense_evals = cnt;
+  out->n_support_left = hd.n[0];
+  out->n_support_right = hd.n[1];
+  out->n_tri_left = hd.ntri[0];
+  out->n_tri_right = hd.ntri[1];
+  out->host_mesh_ms = h->host_mesh_ms;
   return ELAS_OK;
 }
 
@@ -630,11 +669,14 @@ int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t byte
   if (!h->have_result) return fail(h, ELAS_ERR_ARG, "no completed call");
   Buffers* b = h->last;
   const Geometry& g = b->g;
+  MeshHeader hd;
+  int rc = last_header(h, &hd);
+  if (rc != ELAS_OK) return rc;
+  const bool hm = h->last_on_host;
   const int64_t npx = (int64_t)g.w * g.h, nlat = (int64_t)g.lw * g.lh;
   const void* dsrc = nullptr;
   const void* hsrc = nullptr;
   int64_t size = 0;
-  int32_t corners[8];
   switch (which) {
     case ELAS_I_DESC_LEFT: dsrc = b->descL; size = npx * 16; break;
     case ELAS_I_DESC_RIGHT: dsrc = b->descR; size = npx * 16; break;
@@ -642,18 +684,31 @@ int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t byte
     case ELAS_I_DCAN_INCON: dsrc = b->dcan_incon; size = nlat * 2; break;
     case ELAS_I_DCAN_VERT: dsrc = b->dcan_vert; size = nlat * 2; break;
     case ELAS_I_DCAN_FINAL: dsrc = b->dcan_final; size = nlat * 2; break;
-    case ELAS_I_SUPPORT_LEFT: hsrc = h->ptsL.data(); size = (int64_t)h->hdr.nL * 12; break;
-    case ELAS_I_SUPPORT_RIGHT: hsrc = h->ptsR.data(); size = (int64_t)h->hdr.nR * 12; break;
-    case ELAS_I_CORNERS:
-      std::memcpy(corners, h->hdr.cornersL, 16);
-      std::memcpy(corners + 4, h->hdr.cornersR, 16);
-      hsrc = corners;
-      size = 32;
+    case ELAS_I_SUPPORT_LEFT:
+      size = (int64_t)hd.n[0] * 12;
+      if (hm) hsrc = h->ptsL.data(); else dsrc = b->ptsL;
       break;
-    case ELAS_I_TRI_LEFT: hsrc = h->recsL.data(); size = (int64_t)h->ntL * 36; break;
-    case ELAS_I_TRI_RIGHT: hsrc = h->recsR.data(); size = (int64_t)h->ntR * 36; break;
-    case ELAS_I_PLANE_LEFT: hsrc = h->planesL.data(); size = (int64_t)h->ntL * 12; break;
-    case ELAS_I_PLANE_RIGHT: hsrc = h->planesR.data(); size = (int64_t)h->ntR * 12; break;
+    case ELAS_I_SUPPORT_RIGHT:
+      size = (int64_t)hd.n[1] * 12;
+      if (hm) hsrc = h->ptsR.data(); else dsrc = b->ptsR;
+      break;
+    case ELAS_I_CORNERS: hsrc = hd.corners; size = 32; break;
+    case ELAS_I_TRI_LEFT:
+      size = (int64_t)hd.ntri[0] * 36;
+      if (hm) hsrc = h->recsL.data(); else dsrc = b->recsL;
+      break;
+    case ELAS_I_TRI_RIGHT:
+      size = (int64_t)hd.ntri[1] * 36;
+      if (hm) hsrc = h->recsR.data(); else dsrc = b->recsR;
+      break;
+    case ELAS_I_PLANE_LEFT:
+      size = (int64_t)hd.ntri[0] * 12;
+      if (hm) hsrc = h->planesL.data(); else dsrc = b->planesL;
+      break;
+    case ELAS_I_PLANE_RIGHT:
+      size = (int64_t)hd.ntri[1] * 12;
+      if (hm) hsrc = h->planesR.data(); else dsrc = b->planesR;
+      break;
     case ELAS_I_OWNER_LEFT: dsrc = b->ownerL; size = npx * 4; break;
     case ELAS_I_OWNER_RIGHT: dsrc = b->ownerR; size = npx * 4; break;
     case ELAS_I_DPLANE_LEFT: dsrc = b->dplaneL; size = npx * 2; break;
@@ -684,7 +739,8 @@ int elas_triangulate(const int32_t* pts, int32_t n, const int32_t* corners, int3
       h > 8192)
     return fail(nullptr, ELAS_ERR_ARG, "bad triangulation arguments");
   for (int32_t i = 0; i < n; ++i)
-    if (pts[3 * i] <= 0 || pts[3 * i] >= w - 1 || pts[3 * i + 1] <= 0 || pts[3 * i + 1] >= h - 1)
+    if (pts[3 * i] <= 0 || pts[3 * i] >= w - 1 || pts[3 * i + 1] <= 0 ||
+        pts[3 * i + 1] >= h - 1)
       return fail(nullptr, ELAS_ERR_ARG, "support point outside the image interior");
   MeshScratch* s = mesh_scratch_create();
   std::vector<RasterTri> tris((size_t)2 * n + 2);

@@ -10,7 +10,7 @@ namespace elas {
 
 constexpr int kMaxD = 256;
 constexpr int32_t kNoOwner = 0x7FFFFFFF;
-constexpr int kRasterChunk = 1024;  // bounding-box pixels per raster work unit
+constexpr int kMeshLdsBytes = 160 * 1024 - 2048;  // dynamic LDS of one mesh workgroup
 
 // Image, lattice and grid geometry of one (w, h) for one parameter set.
 struct Geometry {
@@ -42,18 +42,14 @@ struct RasterTri {
 };
 static_assert(sizeof(RasterTri) == 24, "RasterTri layout");
 
-// Raster work unit: kRasterChunk pixels of one triangle's bounding box.
-struct RasterUnit {
-  int32_t tri;    // index into the combined (left then right) triangle array
-  int32_t chunk;  // chunk index within the bounding box
-};
-
-// Support lists of one frame as the host gathers them.
-struct ListHeader {
-  int32_t nL, nR;
-  int32_t cornersL[4];
-  int32_t cornersR[4];
-  int64_t support_evals;
+// Per-frame mesh summary in device memory, written by the device mesh
+// kernel or uploaded by the host mesh step; read by raster and dense.
+struct MeshHeader {
+  int32_t n[2];          // support points, left and right view
+  int32_t ntri[2];       // triangles (2n + 2, or 0 without support points)
+  int32_t corners[8];    // d of the four image corners, left then right view
+  int64_t support_evals; // support-search evaluations of the frame
+  int32_t status[2];     // 0, or 1 if a view's flip rounds hit their limit
 };
 
 // ---- host mesh builder (elas_mesh.cpp) ----------------------------------
@@ -69,10 +65,6 @@ void mesh_scratch_destroy(MeshScratch*);
 int32_t build_mesh(MeshScratch* s, const int32_t* pts, int32_t n, const int32_t* corners,
                    int32_t w, int32_t h, RasterTri* tri_out, int32_t* recs_out,
                    float* planes_out);
-// Raster work units of ntri records whose indices start at tri_base: one unit
-// per kRasterChunk pixels of each bounding box. Writes to out when not null;
-// returns the count.
-int32_t raster_units(const RasterTri* tris, int32_t ntri, int32_t tri_base, RasterUnit* out);
 
 // ---- kernel launchers (elas_kernels.hip) ---------------------------------
 hipError_t launch_descriptor(const uint8_t* left, const uint8_t* right, int32_t stride,
@@ -91,13 +83,22 @@ hipError_t launch_filter(const int16_t* raw, const Geometry& g, const KParams& p
 hipError_t launch_rows(const int16_t* fin, const int32_t* evals, const Geometry& g,
                        const KParams& p, int32_t* hrowL, int32_t* hrowR, int32_t* hcnt,
                        uint32_t* gridL, uint32_t* gridR, hipStream_t s);
-hipError_t launch_raster(const RasterTri* tris, const RasterUnit* units, int32_t nunits,
-                         int32_t ntL, const Geometry& g, int32_t* ownerL, int32_t* ownerR,
-                         hipStream_t s);
+// Device mesh of both views (elas_mesh_device.hip). rowsL/rowsR/cnt as
+// written by k_rows; outputs the header, the gathered lists (ptsL/ptsR,
+// (u,v,d) triples), canonical records and planes per view, and the combined
+// raster records (left view first). gscratch: 2 * mesh_global_scratch_per_view
+// bytes, used only when a view does not fit in LDS.
+size_t mesh_global_scratch_per_view(const Geometry& g);
+hipError_t launch_mesh(const int32_t* rowsL, const int32_t* rowsR, const int32_t* cnt,
+                       const Geometry& g, MeshHeader* hdr, int32_t* ptsL, int32_t* ptsR,
+                       int32_t* recsL, int32_t* recsR, float* planesL, float* planesR,
+                       RasterTri* tris, char* gscratch, hipStream_t s);
+hipError_t launch_raster(const RasterTri* tris, const MeshHeader* hdr, const Geometry& g,
+                         int32_t* ownerL, int32_t* ownerR, hipStream_t s);
 hipError_t launch_dense(const uint8_t* descL, const uint8_t* descR, const int32_t* ownerL,
-                        const int32_t* ownerR, const RasterTri* tris, int32_t ntL,
+                        const int32_t* ownerR, const RasterTri* tris, const MeshHeader* hdr,
                         const uint32_t* gridL, const uint32_t* gridR, const int32_t* lut,
-                        int32_t has_list, const Geometry& g, const KParams& p,
+                        const Geometry& g, const KParams& p,
                         int16_t* dplaneL, int16_t* dplaneR, int16_t* rawL, int16_t* rawR,
                         int32_t* dense_counts, hipStream_t s);
 // Blocks of the dense launch (one candidate-count entry per block).

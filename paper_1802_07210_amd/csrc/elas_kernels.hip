@@ -407,34 +407,91 @@ __global__ __launch_bounds__(64) void k_rows(const int16_t* __restrict__ fin,
 
 // ---------------------------------------------------------------------------
 // Prior raster (Section VI-D: the mesh becomes an image-sized matrix of
-// priors). One workgroup per kRasterChunk pixels of a triangle's bounding
-// box; a pixel inside the closed triangle takes the smallest canonical rank
-// of the triangles containing it (atomicMin, order-independent).
+// priors). Workgroups stride over the triangles of both views. For each row
+// of a triangle the exact integer span of pixels inside the closed triangle
+// is computed from its three edge functions; the spans of up to 256 rows are
+// prefix-summed and their pixels spread over the threads. A pixel takes the
+// smallest canonical rank of the triangles containing it (atomicMin, so the
+// result does not depend on the order).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int floordiv_pos(int a, int b) {  // b > 0
+  return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+// Narrows [lo, hi] to the u with k*u + c >= 0.
+__device__ __forceinline__ void clip_edge(int k, int c, int* lo, int* hi) {
+  if (k > 0) {
+    *lo = max(*lo, -floordiv_pos(c, k));  // u >= ceil(-c / k)
+  } else if (k < 0) {
+    *hi = min(*hi, floordiv_pos(c, -k));  // u <= floor(c / -k)
+  } else if (c < 0) {
+    *hi = *lo - 1;
+  }
+}
+
+constexpr int kRasterBlocks = 1024;
+
 __global__ __launch_bounds__(256) void k_raster(const RasterTri* __restrict__ tris,
-                                                const RasterUnit* __restrict__ units,
-                                                int32_t ntL, Geometry g,
+                                                const MeshHeader* __restrict__ hdr, Geometry g,
                                                 int32_t* __restrict__ ownerL,
                                                 int32_t* __restrict__ ownerR) {
-  const RasterUnit wu = units[blockIdx.x];
-  const RasterTri t = tris[wu.tri];
-  const bool right = wu.tri >= ntL;
-  const int rank = right ? wu.tri - ntL : wu.tri;
-  int32_t* owner = right ? ownerR : ownerL;
-  const int au = t.u[0], av = t.v[0], bu = t.u[1], bv = t.v[1], cu = t.u[2], cv = t.v[2];
-  const int umin = min(au, min(bu, cu)), umax = max(au, max(bu, cu));
-  const int vmin = min(av, min(bv, cv)), vmax = max(av, max(bv, cv));
-  const int bw = umax - umin + 1;
-  const int area = bw * (vmax - vmin + 1);
-  const int start = wu.chunk * kRasterChunk;
-  const int end = min(start + kRasterChunk, area);
-  for (int i = start + (int)threadIdx.x; i < end; i += 256) {
-    const int y = i / bw, x = i - y * bw;
-    const int u = umin + x, v = vmin + y;
-    const int e0 = (bu - au) * (v - av) - (bv - av) * (u - au);
-    const int e1 = (cu - bu) * (v - bv) - (cv - bv) * (u - bu);
-    const int e2 = (au - cu) * (v - cv) - (av - cv) * (u - cu);
-    if (e0 >= 0 && e1 >= 0 && e2 >= 0) atomicMin(&owner[(size_t)v * g.w + u], rank);
+  __shared__ int s_lo[256];
+  __shared__ int s_off[257];
+  __shared__ int s_w[4];
+  const int tid = threadIdx.x;
+  const int ntL = hdr->ntri[0], nt = ntL + hdr->ntri[1];
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const RasterTri T = tris[t];
+    const bool right = t >= ntL;
+    const int rank = right ? t - ntL : t;
+    int32_t* owner = right ? ownerR : ownerL;
+    // vertices lie in the image; the clamp only keeps every write inside it
+    const int umin = max(0, min(T.u[0], min(T.u[1], T.u[2])));
+    const int umax = min(g.w - 1, max(T.u[0], max(T.u[1], T.u[2])));
+    const int vmin = max(0, min(T.v[0], min(T.v[1], T.v[2])));
+    const int vmax = min(g.h - 1, max(T.v[0], max(T.v[1], T.v[2])));
+    for (int r0 = vmin; r0 <= vmax; r0 += 256) {
+      const int v = r0 + tid;
+      int lo = umin, hi = umax;
+      if (v <= vmax) {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int au = T.u[e], av = T.v[e], bu = T.u[(e + 1) % 3], bv = T.v[(e + 1) % 3];
+          // orient(A, B, (u, v)) = (av - bv) * u + (bu - au)(v - av) + (bv - av) au
+          clip_edge(av - bv, (bu - au) * (v - av) + (bv - av) * au, &lo, &hi);
+        }
+      } else {
+        hi = lo - 1;
+      }
+      const int len = max(0, hi - lo + 1);
+      // exclusive scan of the span lengths over the 256 rows
+      int incl = len;
+      const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      if (lane == 63) s_w[wid] = incl;
+      __syncthreads();
+      int before = 0;
+      for (int w2 = 0; w2 < wid; ++w2) before += s_w[w2];
+      const int total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+      s_lo[tid] = lo;
+      s_off[tid] = before + incl - len;
+      if (tid == 0) s_off[256] = total;
+      __syncthreads();
+      for (int i = tid; i < total; i += 256) {
+        int a = 0, b = 255;  // largest k with s_off[k] <= i
+        while (a < b) {
+          const int mid = (a + b + 1) >> 1;
+          if (s_off[mid] <= i) a = mid; else b = mid - 1;
+        }
+        const int u = s_lo[a] + (i - s_off[a]);
+        atomicMin(&owner[(size_t)(r0 + a) * g.w + u], rank);
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -462,9 +519,10 @@ constexpr int kBatch = 8;  // candidate gathers issued together per lane
 __global__ __launch_bounds__(256) void k_dense(
     const uint8_t* __restrict__ descL, const uint8_t* __restrict__ descR,
     const int32_t* __restrict__ ownerL, const int32_t* __restrict__ ownerR,
-    const RasterTri* __restrict__ tris, int32_t ntL, const uint32_t* __restrict__ gridL,
-    const uint32_t* __restrict__ gridR, const int32_t* __restrict__ lut, int32_t has_list,
-    Geometry g, KParams p, int16_t* __restrict__ dplaneL, int16_t* __restrict__ dplaneR,
+    const RasterTri* __restrict__ tris, const MeshHeader* __restrict__ hdr,
+    const uint32_t* __restrict__ gridL, const uint32_t* __restrict__ gridR,
+    const int32_t* __restrict__ lut, Geometry g, KParams p, int16_t* __restrict__ dplaneL,
+    int16_t* __restrict__ dplaneR,
     int16_t* __restrict__ rawL, int16_t* __restrict__ rawR,
     int32_t* __restrict__ dense_counts) {
   __shared__ int32_t s_lut[kMaxD];
@@ -473,6 +531,8 @@ __global__ __launch_bounds__(256) void k_dense(
   __syncthreads();
   const int lb = xcd_remap(blockIdx.x, gridDim.x);  // views interleaved per pixel block
   const bool right = (lb & 1) != 0;
+  const int ntL = hdr->ntri[0];
+  const bool has_list = hdr->n[0] > 0;
   const int npx = g.w * g.h;
   const int px = (lb >> 1) * 256 + threadIdx.x;
   int cnt = 0;
@@ -633,25 +693,22 @@ hipError_t launch_rows(const int16_t* fin, const int32_t* evals, const Geometry&
   return hipGetLastError();
 }
 
-hipError_t launch_raster(const RasterTri* tris, const RasterUnit* units, int32_t nunits,
-                         int32_t ntL, const Geometry& g, int32_t* ownerL, int32_t* ownerR,
-                         hipStream_t s) {
-  if (nunits <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_raster, dim3(nunits), dim3(256), 0, s, tris, units, ntL, g, ownerL,
+hipError_t launch_raster(const RasterTri* tris, const MeshHeader* hdr, const Geometry& g,
+                         int32_t* ownerL, int32_t* ownerR, hipStream_t s) {
+  hipLaunchKernelGGL(k_raster, dim3(kRasterBlocks), dim3(256), 0, s, tris, hdr, g, ownerL,
                      ownerR);
   return hipGetLastError();
 }
 
 hipError_t launch_dense(const uint8_t* descL, const uint8_t* descR, const int32_t* ownerL,
-                        const int32_t* ownerR, const RasterTri* tris, int32_t ntL,
+                        const int32_t* ownerR, const RasterTri* tris, const MeshHeader* hdr,
                         const uint32_t* gridL, const uint32_t* gridR, const int32_t* lut,
-                        int32_t has_list, const Geometry& g, const KParams& p,
+                        const Geometry& g, const KParams& p,
                         int16_t* dplaneL, int16_t* dplaneR, int16_t* rawL, int16_t* rawR,
                         int32_t* dense_counts, hipStream_t s) {
   dim3 grid(dense_blocks(g));
-  hipLaunchKernelGGL(k_dense, grid, dim3(256), 0, s, descL, descR, ownerL, ownerR, tris, ntL,
-                     gridL, gridR, lut, has_list, g, p, dplaneL, dplaneR, rawL, rawR,
-                     dense_counts);
+  hipLaunchKernelGGL(k_dense, grid, dim3(256), 0, s, descL, descR, ownerL, ownerR, tris, hdr,
+                     gridL, gridR, lut, g, p, dplaneL, dplaneR, rawL, rawR, dense_counts);
   return hipGetLastError();
 }
 

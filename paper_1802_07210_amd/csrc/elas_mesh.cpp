@@ -325,21 +325,4 @@ int32_t build_mesh(MeshScratch* sp, const int32_t* list, int32_t n, const int32_
   return ntri;
 }
 
-int32_t raster_units(const RasterTri* tris, int32_t ntri, int32_t tri_base, RasterUnit* out) {
-  int32_t nu = 0;
-  for (int32_t t = 0; t < ntri; ++t) {
-    const RasterTri& r = tris[t];
-    const int32_t umin = std::min({r.u[0], r.u[1], r.u[2]});
-    const int32_t umax = std::max({r.u[0], r.u[1], r.u[2]});
-    const int32_t vmin = std::min({r.v[0], r.v[1], r.v[2]});
-    const int32_t vmax = std::max({r.v[0], r.v[1], r.v[2]});
-    const int64_t area = (int64_t)(umax - umin + 1) * (vmax - vmin + 1);
-    const int32_t chunks = (int32_t)((area + kRasterChunk - 1) / kRasterChunk);
-    if (out)
-      for (int32_t k = 0; k < chunks; ++k) out[nu + k] = RasterUnit{tri_base + t, k};
-    nu += chunks;
-  }
-  return nu;
-}
-
 }  // namespace elas

@@ -34,6 +34,7 @@ class ElasParams(C.Structure):
         ("grid_size", C.c_int32), ("beta", C.c_float), ("gamma", C.c_float),
         ("sigma", C.c_float), ("sradius", C.c_int32), ("match_texture", C.c_int32),
         ("lr_threshold", C.c_int32), ("full_search", C.c_int32),
+        ("mesh_on_host", C.c_int32),
     ]
 
 
@@ -48,8 +49,8 @@ class ElasStats(C.Structure):
 
 class ElasTiming(C.Structure):
     _fields_ = [
-        ("descriptor_ms", C.c_float), ("support_ms", C.c_float), ("incon_ms", C.c_float),
-        ("lists_ms", C.c_float), ("upload_ms", C.c_float), ("raster_ms", C.c_float),
+        ("descriptor_ms", C.c_float), ("support_ms", C.c_float), ("filter_ms", C.c_float),
+        ("rows_ms", C.c_float), ("mesh_ms", C.c_float), ("raster_ms", C.c_float),
         ("dense_ms", C.c_float), ("lrcheck_ms", C.c_float), ("device_span_ms", C.c_float),
         ("host_wait_ms", C.c_double), ("host_mesh_ms", C.c_double),
     ]

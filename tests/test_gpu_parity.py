@@ -40,6 +40,11 @@ def run_pair(E, left, right, stride=None, **kw):
     return e, oL.cpu().numpy(), oR.cpu().numpy()
 
 
+def run_and_compare(E, left, right, **kw):
+    e, oL, oR = run_pair(E, left, right, **kw)
+    return compare(e, ref.process(oracle_params(kw), left, right), oL, oR)
+
+
 def compare(e, t, outL, outR):
     """Returns a list of (stage, mismatch count) for every stage that differs."""
     h, w = t.outL.shape
@@ -93,15 +98,16 @@ def compare(e, t, outL, outR):
 
 
 def oracle_params(kw):
-    return ref.params(**kw)
+    return ref.params(**{k: v for k, v in kw.items() if k != "mesh_on_host"})
 
 
+@pytest.mark.parametrize("mesh_on_host", [0, 1])
 @pytest.mark.parametrize("shape", ["320x240", "640x480", "1242x375", "1280x720"])
-def test_workload_shapes_bit_exact(E, shape):
+def test_workload_shapes_bit_exact(E, shape, mesh_on_host):
     cfg = synth.SHAPES[shape]
     pair = synth.make_pair(cfg)
     kw = dict(disp_max=cfg.disp_range - 1)
-    e, oL, oR = run_pair(E, pair.left, pair.right, **kw)
+    e, oL, oR = run_pair(E, pair.left, pair.right, mesh_on_host=mesh_on_host, **kw)
     t = ref.process(oracle_params(kw), pair.left, pair.right)
     assert compare(e, t, oL, oR) == []
     assert (oL >= 0).mean() > 0.4
@@ -137,15 +143,16 @@ SMALL = [
 ]
 
 
+@pytest.mark.parametrize("mesh_on_host", [0, 1])
 @pytest.mark.parametrize("w,h,D,extra", SMALL)
-def test_small_and_ragged_sizes(E, w, h, D, extra):
+def test_small_and_ragged_sizes(E, w, h, D, extra, mesh_on_host):
     dmin = extra.get("disp_min", 0)
     cfg = synth.SceneConfig(w, h, max(D, 4), 3, 0.05, 1.0, max(2.0, D - 3.0), 2.0, 0.1,
                             seed=w * 7 + h)
     pair = synth.make_pair(cfg)
     kw = dict(extra)
     kw["disp_max"] = dmin + D - 1
-    e, oL, oR = run_pair(E, pair.left, pair.right, **kw)
+    e, oL, oR = run_pair(E, pair.left, pair.right, mesh_on_host=mesh_on_host, **kw)
     assert compare(e, ref.process(oracle_params(kw), pair.left, pair.right), oL, oR) == []
 
 
@@ -214,3 +221,23 @@ def test_nondefault_stream(E):
     s.synchronize()
     t = ref.process(ref.params(disp_max=63), pair.left, pair.right)
     assert compare(e, t, oL.cpu().numpy(), oR.cpu().numpy()) == []
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dense_support_sets_exercise_the_device_mesh(E, seed):
+    # weak filtering keeps most lattice points: thousands of support points,
+    # long runs of co-circular lattice squares, the global-memory mesh path
+    # for the larger cases
+    cfg = synth.SceneConfig(320 + 64 * seed, 240, 64, 6, 0.05, 4.0, 59.0, 2.0, 0.05, seed=seed)
+    pair = synth.make_pair(cfg)
+    kw = dict(disp_max=63, incon_min_support=0, redun_max_dist=0,
+              candidate_stepsize=[5, 4, 3, 5, 4, 6][seed])
+    assert run_and_compare(E, pair.left, pair.right, **kw) == []
+
+
+@pytest.mark.parametrize("mesh_on_host", [0, 1])
+def test_unit_lattice_both_mesh_modes(E, mesh_on_host):
+    cfg = synth.SceneConfig(96, 72, 32, 4, 0.05, 4.0, 27.0, 2.0, 0.05, seed=5)
+    pair = synth.make_pair(cfg)
+    kw = dict(disp_max=31, candidate_stepsize=1, mesh_on_host=mesh_on_host)
+    assert run_and_compare(E, pair.left, pair.right, **kw) == []
