@@ -136,10 +136,13 @@ ELAS_API int elas_destroy(elas_handle* h);
  * enqueued work; with the default device mesh the call only enqueues work.
  * With mesh_on_host the call blocks the calling thread until the support
  * stage has finished, triangulates on the host, then enqueues the rest (the
- * CPU/accelerator split of the paper, Section IV). Inputs must stay valid
- * until the stream passes the work. Device buffers for the image size are
- * allocated on first use and cached in the handle (first call per size
- * synchronises the device). */
+ * CPU/accelerator split of the paper, Section IV); frames wider or taller
+ * than 4096 pixels are always triangulated this way. Inputs must stay valid
+ * until the stream passes the work. Device buffers are kept per (image size,
+ * stream): they are allocated on the first call for that pair (which
+ * synchronises the device) and reused by later calls on the same stream, so
+ * frames issued on different streams run concurrently on the device. A
+ * handle is used by one host thread at a time. */
 ELAS_API int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right,
                           int32_t w, int32_t h_px, int32_t stride, hipStream_t stream,
                           int16_t* disp_left, int16_t* disp_right);

@@ -21,6 +21,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "elas.h"
@@ -124,7 +125,9 @@ struct elas_handle {
   elas_params params{};
   KParams kp{};
   std::vector<int32_t> lut;
-  std::map<std::pair<int32_t, int32_t>, Buffers*> cache;
+  // device buffers per (width, height, stream): calls on different streams
+  // use disjoint buffers, so their frames can run concurrently
+  std::map<std::tuple<int32_t, int32_t, hipStream_t>, Buffers*> cache;
   Buffers* last = nullptr;
   hipStream_t last_stream = nullptr;
   bool have_result = false;
@@ -193,8 +196,8 @@ Geometry make_geometry(const elas_params& p, int32_t w, int32_t h) {
   return g;
 }
 
-int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
-  const auto key = std::make_pair(w, hp);
+int get_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, Buffers** out) {
+  const auto key = std::make_tuple(w, hp, stream);
   auto it = h->cache.find(key);
   if (it != h->cache.end()) {
     *out = it->second;
@@ -230,7 +233,9 @@ int get_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   const size_t o_recL = take(ntmax * 36), o_recR = take(ntmax * 36);
   const size_t o_plL = take(ntmax * 12), o_plR = take(ntmax * 12);
   const size_t o_tris = take(2 * ntmax * sizeof(RasterTri));
-  const size_t o_ms = take(2 * mesh_global_scratch_per_view(g));
+  // frames above the device mesh limit are always meshed on the host
+  const bool dev_mesh = w <= kDeviceMeshMaxSide && hp <= kDeviceMeshMaxSide;
+  const size_t o_ms = take(dev_mesh ? 2 * mesh_global_scratch_per_view(g) : 0);
   hipError_t e = hipMalloc(&b->dev_block, off);
   if (e != hipSuccess) {
     delete b;
@@ -406,13 +411,13 @@ int host_mesh_step(elas_handle* h, Buffers* b, hipStream_t stream) {
     if (gotL != ntL || gotR != ntR)
       return fail(h, ELAS_ERR_INTERNAL, "host triangulation failed its consistency checks");
   }
-  std::memcpy(static_cast<uint8_t*>(b->up_host) + tri_bytes, &hd, sizeof(hd));
+  uint8_t* hdr_host = static_cast<uint8_t*>(b->up_host) + tri_bytes;
+  std::memcpy(hdr_host, &hd, sizeof(hd));
   h->hhdr = hd;
   if (ntL + ntR > 0)
     HIP_TRY(hipMemcpyAsync(b->tris, b->up_host, (size_t)(ntL + ntR) * sizeof(RasterTri),
                            hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(b->hdr, static_cast<uint8_t*>(b->up_host) + tri_bytes,
-                         sizeof(MeshHeader), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(b->hdr, hdr_host, sizeof(MeshHeader), hipMemcpyHostToDevice, stream));
   HIP_TRY(hipEventRecord(h->ev_upload, stream));
   h->upload_pending = true;
   h->host_mesh_ms =
@@ -549,14 +554,15 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   if (w < 9 || hp < 9 || w > 8192 || hp > 8192)
     return fail(h, ELAS_ERR_ARG, "image size must be 9..8192 in each dimension");
   if (stride < w) return fail(h, ELAS_ERR_ARG, "stride must be >= width");
-  const bool on_host = h->params.mesh_on_host != 0;
+  const bool on_host =
+      h->params.mesh_on_host != 0 || w > kDeviceMeshMaxSide || hp > kDeviceMeshMaxSide;
   if (on_host && !h->ev_lists) {
     HIP_TRY(hipEventCreateWithFlags(&h->ev_lists, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&h->ev_upload, hipEventDisableTiming));
   }
   if (on_host && !h->worker) h->worker = new Worker();
   Buffers* b = nullptr;
-  int rc = get_buffers(h, w, hp, &b);
+  int rc = get_buffers(h, w, hp, stream, &b);
   if (rc != ELAS_OK) return rc;
   const Geometry& g = b->g;
   const KParams& kp = h->kp;
@@ -573,8 +579,7 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   if (timed) HIP_TRY(hipEventRecord(h->tev[i], stream))
 
   STAGE_MARK(0);
-  HIP_TRY(launch_descriptor(left, right, stride, g, b->descL, b->descR, b->ownerL, b->ownerR,
-                            stream));
+  HIP_TRY(launch_descriptor(left, right, stride, g, b->descL, b->descR, stream));
   STAGE_MARK(1);
   HIP_TRY(launch_support(b->descL, b->descR, g, kp, b->dcan_raw, b->evals, stream));
   STAGE_MARK(2);
@@ -591,8 +596,9 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
     HIP_TRY(launch_rows(b->dcan_final, b->evals, g, kp, b->rowsL, b->rowsR, b->cnt, b->gridL,
                         b->gridR, stream));
     STAGE_MARK(4);
-    HIP_TRY(launch_mesh(b->rowsL, b->rowsR, b->cnt, g, b->hdr, b->ptsL, b->ptsR, b->recsL,
-                        b->recsR, b->planesL, b->planesR, b->tris, b->mesh_scratch, stream));
+    HIP_TRY(launch_mesh(b->rowsL, b->rowsR, b->cnt, g, kp.dmin, b->hdr, b->ptsL, b->ptsR,
+                        b->recsL, b->recsR, b->planesL, b->planesR, b->tris,
+                        b->mesh_scratch, stream));
   }
   STAGE_MARK(5);
   HIP_TRY(launch_raster(b->tris, b->hdr, g, b->ownerL, b->ownerR, stream));

@@ -11,6 +11,10 @@ namespace elas {
 constexpr int kMaxD = 256;
 constexpr int32_t kNoOwner = 0x7FFFFFFF;
 constexpr int kMeshLdsBytes = 160 * 1024 - 2048;  // dynamic LDS of one mesh workgroup
+// Frames meshed on the device have both sides at most this long: the mesh
+// packs a point into a 32-bit key with 12-bit coordinates, and its fp64
+// in-circle test is exact only for coordinates below 2^12.
+constexpr int kDeviceMeshMaxSide = 4096;
 
 // Image, lattice and grid geometry of one (w, h) for one parameter set.
 struct Geometry {
@@ -49,7 +53,8 @@ struct MeshHeader {
   int32_t ntri[2];       // triangles (2n + 2, or 0 without support points)
   int32_t corners[8];    // d of the four image corners, left then right view
   int64_t support_evals; // support-search evaluations of the frame
-  int32_t status[2];     // 0, or 1 if a view's flip rounds hit their limit
+  int32_t status[2];     // 0; 1 if a view's flip rounds hit their limit; 2 if its
+                         // initial triangulation failed a consistency check
 };
 
 // ---- host mesh builder (elas_mesh.cpp) ----------------------------------
@@ -68,8 +73,7 @@ int32_t build_mesh(MeshScratch* s, const int32_t* pts, int32_t n, const int32_t*
 
 // ---- kernel launchers (elas_kernels.hip) ---------------------------------
 hipError_t launch_descriptor(const uint8_t* left, const uint8_t* right, int32_t stride,
-                             const Geometry& g, uint8_t* descL, uint8_t* descR,
-                             int32_t* ownerL, int32_t* ownerR, hipStream_t s);
+                             const Geometry& g, uint8_t* descL, uint8_t* descR, hipStream_t s);
 hipError_t launch_support(const uint8_t* descL, const uint8_t* descR, const Geometry& g,
                           const KParams& p, int16_t* dcan, int32_t* evals, hipStream_t s);
 // Fused consistency + redundancy filters; also clears the grid masks.
@@ -83,16 +87,18 @@ hipError_t launch_filter(const int16_t* raw, const Geometry& g, const KParams& p
 hipError_t launch_rows(const int16_t* fin, const int32_t* evals, const Geometry& g,
                        const KParams& p, int32_t* hrowL, int32_t* hrowR, int32_t* hcnt,
                        uint32_t* gridL, uint32_t* gridR, hipStream_t s);
-// Device mesh of both views (elas_mesh_device.hip). rowsL/rowsR/cnt as
-// written by k_rows; outputs the header, the gathered lists (ptsL/ptsR,
-// (u,v,d) triples), canonical records and planes per view, and the combined
-// raster records (left view first). gscratch: 2 * mesh_global_scratch_per_view
-// bytes, used only when a view does not fit in LDS.
+// Device mesh of both views (elas_mesh_device.hip), for frames with both
+// sides at most kDeviceMeshMaxSide. rowsL/rowsR/cnt as written by k_rows;
+// outputs the header, the gathered lists (ptsL/ptsR, (u,v,d) triples),
+// canonical records and planes per view, and the combined raster records
+// (left view first). gscratch: 2 * mesh_global_scratch_per_view bytes, used
+// only when a view does not fit in LDS.
 size_t mesh_global_scratch_per_view(const Geometry& g);
 hipError_t launch_mesh(const int32_t* rowsL, const int32_t* rowsR, const int32_t* cnt,
-                       const Geometry& g, MeshHeader* hdr, int32_t* ptsL, int32_t* ptsR,
-                       int32_t* recsL, int32_t* recsR, float* planesL, float* planesR,
-                       RasterTri* tris, char* gscratch, hipStream_t s);
+                       const Geometry& g, int32_t dmin, MeshHeader* hdr, int32_t* ptsL,
+                       int32_t* ptsR, int32_t* recsL, int32_t* recsR, float* planesL,
+                       float* planesR, RasterTri* tris, char* gscratch, hipStream_t s);
+// Owner maps of both views (every pixel written; kNoOwner where no triangle).
 hipError_t launch_raster(const RasterTri* tris, const MeshHeader* hdr, const Geometry& g,
                          int32_t* ownerL, int32_t* ownerR, hipStream_t s);
 hipError_t launch_dense(const uint8_t* descL, const uint8_t* descR, const int32_t* ownerL,

@@ -70,7 +70,7 @@ __device__ __forceinline__ uint32_t quantise(int g) {
 // Block = 64 x 4 pixels. The image tile with a 3-pixel halo is staged in LDS,
 // the quantised gradients of the tile with a 2-pixel halo are computed once
 // into LDS, and each thread gathers its 16 bytes and writes one 16-byte
-// store (a wave writes 1 KiB contiguous). Also resets the pixel's owner.
+// store (a wave writes 1 KiB contiguous).
 // Sample pattern (column, row offsets): du at (-2,0) (-1,0) (1,0) (2,0)
 // (-1,-2) (1,-2) (-1,2) (1,2); dv at (0,-2) (0,-1) (0,1) (0,2) (-2,-1) (2,-1)
 // (-2,1) (2,1). Descriptors are defined for 2 <= u <= w-3, 2 <= v <= h-3 and
@@ -82,16 +82,13 @@ __global__ __launch_bounds__(256) void k_descriptor(const uint8_t* __restrict__ 
                                                     const uint8_t* __restrict__ right,
                                                     int32_t stride, Geometry g,
                                                     uint8_t* __restrict__ descL,
-                                                    uint8_t* __restrict__ descR,
-                                                    int32_t* __restrict__ ownerL,
-                                                    int32_t* __restrict__ ownerR) {
+                                                    uint8_t* __restrict__ descR) {
   // logical block: (tile row, tile column, view), views interleaved
   const int nbx = (g.w + kDescW - 1) / kDescW;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int view = lb & 1, tile_id = lb >> 1;
   const uint8_t* img = view ? right : left;
   uint8_t* desc = view ? descR : descL;
-  int32_t* owner = view ? ownerR : ownerL;
   __shared__ uint8_t tile[kDescH + 6][kDescW + 8];
   __shared__ uint8_t qdu[kDescH + 4][kDescW + 4];
   __shared__ uint8_t qdv[kDescH + 4][kDescW + 4];
@@ -135,7 +132,6 @@ __global__ __launch_bounds__(256) void k_descriptor(const uint8_t* __restrict__ 
   }
   const size_t px = (size_t)v * g.w + u;
   *reinterpret_cast<uint4*>(desc + px * 16) = out;
-  owner[px] = kNoOwner;
 }
 
 // ---------------------------------------------------------------------------
@@ -407,12 +403,15 @@ __global__ __launch_bounds__(64) void k_rows(const int16_t* __restrict__ fin,
 
 // ---------------------------------------------------------------------------
 // Prior raster (Section VI-D: the mesh becomes an image-sized matrix of
-// priors). Workgroups stride over the triangles of both views. For each row
-// of a triangle the exact integer span of pixels inside the closed triangle
-// is computed from its three edge functions; the spans of up to 256 rows are
-// prefix-summed and their pixels spread over the threads. A pixel takes the
-// smallest canonical rank of the triangles containing it (atomicMin, so the
-// result does not depend on the order).
+// priors). A pixel takes the smallest canonical rank of the triangles whose
+// closed area contains it, or kNoOwner. One workgroup owns a band of pixel
+// rows of one view and keeps its owners in an LDS tile: it gathers the
+// triangles whose rows overlap the band into LDS (canonical order sorts
+// triangles by their top vertex, so the scan stops at the first triangle
+// starting below the band), computes the exact integer span of each of their
+// band rows from the three edge functions, spreads the span pixels over the
+// threads, resolves each pixel with an LDS atomicMin, and finally writes the
+// whole tile with coalesced stores. Every pixel of the image is written.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int floordiv_pos(int a, int b) {  // b > 0
   return a >= 0 ? a / b : -((-a + b - 1) / b);
@@ -429,70 +428,142 @@ __device__ __forceinline__ void clip_edge(int k, int c, int* lo, int* hi) {
   }
 }
 
-constexpr int kRasterBlocks = 1024;
+constexpr int kRasterThreads = 256;
+constexpr int kRasterTile = 8192;  // LDS owner tile: band rows x width
+constexpr int kRasterList = 512;   // triangles gathered per pass
+constexpr int kBandRowsMax = 4;
 
-__global__ __launch_bounds__(256) void k_raster(const RasterTri* __restrict__ tris,
-                                                const MeshHeader* __restrict__ hdr, Geometry g,
-                                                int32_t* __restrict__ ownerL,
-                                                int32_t* __restrict__ ownerR) {
-  __shared__ int s_lo[256];
-  __shared__ int s_off[257];
-  __shared__ int s_w[4];
-  const int tid = threadIdx.x;
-  const int ntL = hdr->ntri[0], nt = ntL + hdr->ntri[1];
-  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-    const RasterTri T = tris[t];
-    const bool right = t >= ntL;
-    const int rank = right ? t - ntL : t;
-    int32_t* owner = right ? ownerR : ownerL;
-    // vertices lie in the image; the clamp only keeps every write inside it
-    const int umin = max(0, min(T.u[0], min(T.u[1], T.u[2])));
-    const int umax = min(g.w - 1, max(T.u[0], max(T.u[1], T.u[2])));
-    const int vmin = max(0, min(T.v[0], min(T.v[1], T.v[2])));
-    const int vmax = min(g.h - 1, max(T.v[0], max(T.v[1], T.v[2])));
-    for (int r0 = vmin; r0 <= vmax; r0 += 256) {
-      const int v = r0 + tid;
-      int lo = umin, hi = umax;
-      if (v <= vmax) {
-#pragma unroll
-        for (int e = 0; e < 3; ++e) {
-          const int au = T.u[e], av = T.v[e], bu = T.u[(e + 1) % 3], bv = T.v[(e + 1) % 3];
-          // orient(A, B, (u, v)) = (av - bv) * u + (bu - au)(v - av) + (bv - av) au
-          clip_edge(av - bv, (bu - au) * (v - av) + (bv - av) * au, &lo, &hi);
+// Band height for an image width: at most four rows, tile within kRasterTile.
+inline int raster_band_rows(int w) { return std::max(1, std::min(kBandRowsMax, 4096 / w)); }
+
+__global__ __launch_bounds__(kRasterThreads) void k_raster(const RasterTri* __restrict__ tris,
+                                                           const MeshHeader* __restrict__ hdr,
+                                                           Geometry g, int band_rows,
+                                                           int32_t* __restrict__ ownerL,
+                                                           int32_t* __restrict__ ownerR) {
+  __shared__ int32_t tile[kRasterTile];
+  __shared__ RasterTri list[kRasterList];
+  __shared__ int32_t lrank[kRasterList];
+  __shared__ int32_t pre[kRasterThreads + 1];
+  __shared__ int32_t sp_lo[kBandRowsMax][kRasterThreads];
+  __shared__ int32_t sp_len[kBandRowsMax][kRasterThreads];
+  __shared__ int32_t sp_rank[kRasterThreads];
+  __shared__ int32_t wsum[kRasterThreads / 64];
+  __shared__ int s_cnt, s_done;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nb = (g.h + band_rows - 1) / band_rows;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int view = lb >= nb ? 1 : 0, band = lb - view * nb;
+  const int v0 = band * band_rows, v1 = min(g.h - 1, v0 + band_rows - 1);
+  const int rows = v1 - v0 + 1;
+  const int ntL = hdr->ntri[0], nt = view ? hdr->ntri[1] : ntL, base = view ? ntL : 0;
+  for (int i = tid; i < rows * g.w; i += kRasterThreads) tile[i] = kNoOwner;
+  int r0 = 0;
+  for (;;) {
+    // gather the next triangles overlapping the band
+    if (tid == 0) {
+      s_cnt = 0;
+      s_done = 0;
+    }
+    __syncthreads();
+    int cnt = 0, done = 0;
+    while (r0 < nt) {
+      const int r = r0 + tid;
+      if (r < nt) {
+        const RasterTri T = tris[base + r];
+        const int vmin = min((int)T.v[0], min((int)T.v[1], (int)T.v[2]));
+        const int vmax = max((int)T.v[0], max((int)T.v[1], (int)T.v[2]));
+        if (vmin > v1) {
+          s_done = 1;  // so does every later triangle
+        } else if (vmax >= v0) {
+          const int slot = atomicAdd(&s_cnt, 1);
+          list[slot] = T;
+          lrank[slot] = r;
         }
-      } else {
-        hi = lo - 1;
       }
-      const int len = max(0, hi - lo + 1);
-      // exclusive scan of the span lengths over the 256 rows
-      int incl = len;
-      const int lane = tid & 63, wid = tid >> 6;
+      r0 += kRasterThreads;
+      __syncthreads();
+      cnt = s_cnt;
+      done = s_done;
+      __syncthreads();
+      if (done || cnt > kRasterList - kRasterThreads) break;
+    }
+    // rasterise the gathered triangles into the tile
+    for (int e0 = 0; e0 < cnt; e0 += kRasterThreads) {
+      const int e = e0 + tid;
+      int lo[kBandRowsMax], len[kBandRowsMax], tot = 0, rank = 0;
+#pragma unroll
+      for (int q = 0; q < kBandRowsMax; ++q) {
+        lo[q] = 0;
+        len[q] = 0;
+      }
+      if (e < cnt) {
+        const RasterTri T = list[e];
+        rank = lrank[e];
+        // vertices lie in the image; the clamp only keeps every write inside it
+        const int umin = max(0, min((int)T.u[0], min((int)T.u[1], (int)T.u[2])));
+        const int umax = min(g.w - 1, max((int)T.u[0], max((int)T.u[1], (int)T.u[2])));
+        const int vmin = min((int)T.v[0], min((int)T.v[1], (int)T.v[2]));
+        const int vmax = max((int)T.v[0], max((int)T.v[1], (int)T.v[2]));
+#pragma unroll
+        for (int q = 0; q < kBandRowsMax; ++q) {
+          const int v = v0 + q;
+          if (q >= rows || v < vmin || v > vmax) continue;
+          int slo = umin, shi = umax;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const int au = T.u[k], av = T.v[k], bu = T.u[(k + 1) % 3], bv = T.v[(k + 1) % 3];
+            // orient(A, B, (u, v)) = (av - bv) * u + (bu - au)(v - av) + (bv - av) au
+            clip_edge(av - bv, (bu - au) * (v - av) + (bv - av) * au, &slo, &shi);
+          }
+          lo[q] = slo;
+          len[q] = max(0, shi - slo + 1);
+          tot += len[q];
+        }
+      }
+      // exclusive scan of the per-thread pixel counts
+      int incl = tot;
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         const int y = __shfl_up(incl, off, 64);
         if (lane >= off) incl += y;
       }
-      if (lane == 63) s_w[wid] = incl;
+      if (lane == 63) wsum[wid] = incl;
       __syncthreads();
-      int before = 0;
-      for (int w2 = 0; w2 < wid; ++w2) before += s_w[w2];
-      const int total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-      s_lo[tid] = lo;
-      s_off[tid] = before + incl - len;
-      if (tid == 0) s_off[256] = total;
+      int before = 0, all = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < kRasterThreads / 64; ++w2) {
+        before += w2 < wid ? wsum[w2] : 0;
+        all += wsum[w2];
+      }
+      pre[tid] = before + incl - tot;
+#pragma unroll
+      for (int q = 0; q < kBandRowsMax; ++q) {
+        sp_lo[q][tid] = lo[q];
+        sp_len[q][tid] = len[q];
+      }
+      sp_rank[tid] = rank;
       __syncthreads();
-      for (int i = tid; i < total; i += 256) {
-        int a = 0, b = 255;  // largest k with s_off[k] <= i
+      for (int i = tid; i < all; i += kRasterThreads) {
+        int a = 0, b = kRasterThreads - 1;  // last thread whose pixels start at or before i
         while (a < b) {
           const int mid = (a + b + 1) >> 1;
-          if (s_off[mid] <= i) a = mid; else b = mid - 1;
+          if (pre[mid] <= i) a = mid; else b = mid - 1;
         }
-        const int u = s_lo[a] + (i - s_off[a]);
-        atomicMin(&owner[(size_t)(r0 + a) * g.w + u], rank);
+        int off = i - pre[a], q = 0;
+        while (off >= sp_len[q][a]) {
+          off -= sp_len[q][a];
+          ++q;
+        }
+        atomicMin(&tile[q * g.w + sp_lo[q][a] + off], sp_rank[a]);
       }
       __syncthreads();
     }
+    if (done || r0 >= nt) break;
   }
+  __syncthreads();
+  int32_t* owner = (view ? ownerR : ownerL) + (size_t)v0 * g.w;
+  for (int i = tid; i < rows * g.w; i += kRasterThreads) owner[i] = tile[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -653,11 +724,9 @@ inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) /
 }  // namespace
 
 hipError_t launch_descriptor(const uint8_t* left, const uint8_t* right, int32_t stride,
-                             const Geometry& g, uint8_t* descL, uint8_t* descR,
-                             int32_t* ownerL, int32_t* ownerR, hipStream_t s) {
+                             const Geometry& g, uint8_t* descL, uint8_t* descR, hipStream_t s) {
   dim3 grid(2 * cdiv(g.w, kDescW) * cdiv(g.h, kDescH)), block(kDescW, kDescH, 1);
-  hipLaunchKernelGGL(k_descriptor, grid, block, 0, s, left, right, stride, g, descL, descR,
-                     ownerL, ownerR);
+  hipLaunchKernelGGL(k_descriptor, grid, block, 0, s, left, right, stride, g, descL, descR);
   return hipGetLastError();
 }
 
@@ -695,8 +764,10 @@ hipError_t launch_rows(const int16_t* fin, const int32_t* evals, const Geometry&
 
 hipError_t launch_raster(const RasterTri* tris, const MeshHeader* hdr, const Geometry& g,
                          int32_t* ownerL, int32_t* ownerR, hipStream_t s) {
-  hipLaunchKernelGGL(k_raster, dim3(kRasterBlocks), dim3(256), 0, s, tris, hdr, g, ownerL,
-                     ownerR);
+  const int rows = raster_band_rows(g.w);
+  const int nb = (g.h + rows - 1) / rows;
+  hipLaunchKernelGGL(k_raster, dim3(2 * nb), dim3(kRasterThreads), 0, s, tris, hdr, g, rows,
+                     ownerL, ownerR);
   return hipGetLastError();
 }
 

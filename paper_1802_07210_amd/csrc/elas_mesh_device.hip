@@ -1,31 +1,44 @@
 // Device-resident mesh step (Section III-A: Delaunay triangulation of the
-// support points, one slanted plane per triangle; Section IV leaves this
-// sequential step on the CPU, here it runs on the GPU so the frame needs no
-// host round trip).
+// support points, one slanted plane per triangle). The paper's CPU/FPGA split
+// (Section IV) leaves this sequential step to the CPU; here it runs on the
+// GPU so that a frame needs no host round trip.
 //
 // One 1024-thread workgroup per view:
-//  1. gather the per-row support lists into points ranked in (v, u) order:
-//     index 0 = (0,0), 1 = (w-1,0), 2..n+1 = the list, n+2 = (0,h-1),
-//     n+3 = (w-1,h-1); the corners take the d of the nearest list point;
-//  2. initial triangulation: the support points lie on lattice rows, so the
-//     region between two consecutive non-empty rows (with the image's top and
-//     bottom edges as extra rows) is a trapezoid, triangulated by a zipper
-//     over the two sorted rows (one thread per strip); the two side pockets
-//     between the rows' end points and the image border are v-monotone
-//     polygons, triangulated by the stack method (one thread per side);
-//  3. adjacency from vertex-to-triangle incidence lists;
+//  1. gather the per-row support lists into points in (v, u) rank order:
+//     rank 0 = (0,0), 1 = (w-1,0), 2..n+1 = the lists, n+2 = (0,h-1),
+//     n+3 = (w-1,h-1); each corner takes the d of the nearest list point.
+//     A point is one 32-bit key v<<20 | u<<8 | (d - dmin): key order is rank
+//     order, so triangles carry keys and need no vertex ids.
+//  2. initial triangulation. Support points lie on lattice rows, so the
+//     region between two consecutive non-empty rows (the image's top and
+//     bottom edges act as extra rows) is a trapezoid, triangulated by a
+//     zipper over the two sorted rows (one thread per strip). The two side
+//     pockets between the rows' end points and the image border are
+//     polygons monotone in v with one straight side. Their stack
+//     triangulation has a closed form that is evaluated in parallel: the
+//     point below a chain point on the stack is the earlier point at the
+//     extreme angle seen from it (the later one on ties); the point that pops
+//     it is the first later chain point strictly across that segment (none:
+//     the bottom corner). Each chain point gives one triangle.
+//  3. adjacency: half-edges bucketed by origin vertex, each matched with its
+//     reverse; a neighbour is stored as 4 * triangle + local vertex index.
 //  4. Lawson flips in synchronous rounds until every edge is legal under the
 //     canonical rule (strictly outside the circumcircle, or exactly on it and
-//     the (v, u)-smallest of the four points is an endpoint of the edge):
-//     each illegal edge claims its two triangles (atomicMin of the edge key),
-//     winners flip from the round's state, then every triangle re-points the
-//     neighbours it had across edges that moved to the flip partner. Only
-//     edges of triangles changed in the previous round are re-tested. The
-//     canonical rule is a consistent symbolic perturbation of the lifted
-//     points, so the flips terminate at the unique canonical triangulation,
-//     whatever the starting mesh;
-//  5. canonical order (counting sort on the smallest vertex rank, insertion
-//     sort inside each bucket), exact planes, raster records.
+//     the (v, u)-smallest of the four points is an endpoint of the edge).
+//     A round tests the edges of the triangles flipped in the previous round
+//     and keeps the previous candidates whose two triangles did not change
+//     (an edge with unchanged triangles keeps its verdict). Each candidate
+//     claims its two triangles with an atomic max of a round-stamped,
+//     inverted edge key, so the smallest key wins and no claim is ever
+//     reset; winners flip, then every flipped triangle re-links its outer
+//     neighbours. The canonical rule is a consistent perturbation of the
+//     lifted points, so the flips end at the unique canonical triangulation
+//     whatever the starting mesh.
+//  5. canonical order (bucket by smallest vertex, position within the
+//     bucket), exact planes and raster records.
+// The predicates are exact: orientation in int32, and the in-circle
+// determinant in fp64 from int32 minors below 2^26, so every product and sum
+// is an integer below 2^53; this needs coordinates below 4096.
 // Arrays live in LDS (16-bit indices) when they fit, else in a global
 // scratch area (32-bit indices); both paths run the same template.
 #include <algorithm>
@@ -36,21 +49,52 @@
 namespace elas {
 namespace {
 
-constexpr int kMT = 1024;  // threads per mesh workgroup
+constexpr int kMT = 1024;          // threads per mesh workgroup
+constexpr int kMaxRounds = 32000;  // flip rounds before a view reports status 1
 
-__device__ __forceinline__ long long orient2(int au, int av, int bu, int bv, int cu, int cv) {
-  return (long long)(bu - au) * (cv - av) - (long long)(bv - av) * (cu - au);
+// ---- point keys and exact predicates --------------------------------------
+__device__ __forceinline__ int key_u(uint32_t k) { return (int)((k >> 8) & 0xFFFu); }
+__device__ __forceinline__ int key_v(uint32_t k) { return (int)(k >> 20); }
+__device__ __forceinline__ int key_dd(uint32_t k) { return (int)(k & 0xFFu); }
+__device__ __forceinline__ uint32_t make_key(int u, int v, int dd) {
+  return ((uint32_t)v << 20) | ((uint32_t)u << 8) | (uint32_t)dd;
 }
 
-__device__ __forceinline__ long long incircle2(int au, int av, int bu, int bv, int cu, int cv,
-                                               int du, int dv) {
-  const long long ax = au - du, ay = av - dv, bx = bu - du, by = bv - dv;
-  const long long cx = cu - du, cy = cv - dv;
-  return (ax * ax + ay * ay) * (bx * cy - by * cx) + (bx * bx + by * by) * (cx * ay - cy * ax) +
-         (cx * cx + cy * cy) * (ax * by - ay * bx);
+// > 0 if (a, b, c) turns counter-clockwise in (u, v); |value| < 2^25.
+__device__ __forceinline__ int orient_k(uint32_t a, uint32_t b, uint32_t c) {
+  const int au = key_u(a), av = key_v(a);
+  return (key_u(b) - au) * (key_v(c) - av) - (key_v(b) - av) * (key_u(c) - au);
 }
 
-// Exclusive scan over the workgroup (kMT threads); *total receives the sum.
+// > 0 if d lies inside the circle through the counter-clockwise a, b, c.
+__device__ __forceinline__ double incircle_k(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const int du = key_u(d), dv = key_v(d);
+  const int ax = key_u(a) - du, ay = key_v(a) - dv;
+  const int bx = key_u(b) - du, by = key_v(b) - dv;
+  const int cx = key_u(c) - du, cy = key_v(c) - dv;
+  const int la = ax * ax + ay * ay, lb = bx * bx + by * by, lc = cx * cx + cy * cy;
+  const int xa = bx * cy - by * cx, xb = cx * ay - cy * ax, xc = ax * by - ay * bx;
+  return (double)la * (double)xa + (double)lb * (double)xb + (double)lc * (double)xc;
+}
+
+// Edge (a, b) of the counter-clockwise triangle (p, a, b) against the apex q
+// of the triangle across it.
+__device__ __forceinline__ bool edge_illegal(uint32_t p, uint32_t a, uint32_t b, uint32_t q) {
+  const double ic = incircle_k(p, a, b, q);
+  if (ic != 0.0) return ic > 0.0;
+  // co-circular: legal iff the (v, u)-smallest point is an endpoint
+  const uint32_t mn = min(min(p, q), min(a, b));
+  return !(mn == a || mn == b);
+}
+
+__device__ __forceinline__ void sort3(uint32_t& a, uint32_t& b, uint32_t& c) {
+  if (a > b) { const uint32_t t = a; a = b; b = t; }
+  if (b > c) { const uint32_t t = b; b = c; c = t; }
+  if (a > b) { const uint32_t t = a; a = b; b = t; }
+}
+
+// ---- workgroup scans --------------------------------------------------------
+// Exclusive scan over the workgroup; *total receives the sum.
 __device__ int scan_excl(int x, int* total, int* wsum) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int incl = x;
@@ -73,8 +117,8 @@ __device__ int scan_excl(int x, int* total, int* wsum) {
   return before + incl - x;
 }
 
-// In-place exclusive scan of a[0..n) (int32); returns the total.
-__device__ int scan_array(int* a, int n, int* wsum) {
+// In-place exclusive scan of a[0..n); returns the total.
+__device__ int scan_array(int32_t* a, int n, int* wsum) {
   int base = 0;
   for (int c0 = 0; c0 < n; c0 += kMT) {
     const int i = c0 + threadIdx.x;
@@ -88,210 +132,323 @@ __device__ int scan_array(int* a, int n, int* wsum) {
   return base;
 }
 
-__device__ int block_sum(int x, int* wsum) {
-  int tot;
-  (void)scan_excl(x, &tot, wsum);
-  return tot;
+// ---- memory layout ----------------------------------------------------------
+// Claim words: round << shift | (mask - edge key). The 16-bit variant has
+// fewer than 8192 triangles (keys below 2^15) and fewer than 2^15 rounds.
+template <typename I>
+struct ClaimT;
+template <>
+struct ClaimT<int16_t> {
+  typedef uint32_t T;
+  static constexpr int kShift = 17;
+};
+template <>
+struct ClaimT<int32_t> {
+  typedef unsigned long long T;
+  static constexpr int kShift = 32;
+};
+
+template <typename I>
+__device__ __forceinline__ typename ClaimT<I>::T claim_stamp(int round, int key) {
+  typedef typename ClaimT<I>::T C;
+  const C mask = (C(1) << ClaimT<I>::kShift) - 1;
+  return (C(round) << ClaimT<I>::kShift) | (mask - (C)(unsigned)key);
 }
 
 template <typename I>
 struct MeshMem {
-  int16_t *pu, *pv, *pd;   // NP points in rank order
-  I* tv;                   // 3*NT vertex ids, positive orientation
-  I* tn;                   // 3*NT neighbour across the edge opposite vertex k (-1: border)
-  int32_t* claim;          // NT
-  I* partner;              // NT flip partner of the current round (-1: none)
-  uint8_t* cand;           // NT candidate-edge bits of the current round
-  uint8_t* dirty;          // NT changed in the previous round
-  int32_t* cnt;            // NP+1 slot starts (incidence lists, sort buckets)
-  int32_t* cur;            // NP+1 fill cursors
-  I* inc;                  // 3*NT incidence lists, then the canonical order
-  int32_t* rowStart;       // lh+1
-  int32_t* rowNE;          // lh   non-empty lattice rows
-  int32_t* stripOff;       // lh+2
-  int32_t* stack;          // 2*(lh+2)
-  int NT;                  // triangle count 2n + 2
-  int* overflow;           // set if construction would write past NT
+  typedef typename ClaimT<I>::T C;
+  // rows and side chains (sized by the lattice height only)
+  int32_t* rowStart;     // lh + 1: first point of each lattice row, then n
+  int32_t* rowNE;        // lh + 1: non-empty lattice rows in order
+  int32_t* stripOff;     // lh + 2: first triangle of each strip
+  uint32_t *chainK0, *chainK1;  // lh + 1: key of the first / last point of each non-empty row
+  int32_t *chainI0, *chainI1;   // lh + 1: its rank
+  // points and triangles
+  uint32_t* pk;          // NP keys in rank order
+  uint32_t* tk;          // 3 NT vertex keys, counter-clockwise
+  I* tn;                 // 3 NT neighbour across the edge opposite vertex k: 4 t + k', or -1
+  // construction and adjacency (aliases: hbuck in tk, the rest in the flip state)
+  I* hbuck;              // 3 NT half-edges grouped by origin vertex
+  I* tv;                 // 3 NT vertex ranks
+  int32_t* vcnt;         // NP + 1 bucket starts
+  int32_t* vcur;         // NP + 1 fill cursors
+  // flip state
+  C* claim;              // NT
+  I* partner;            // NT flip partner of the last flip
+  uint16_t* flipr;       // NT round of the last flip (0: none)
+  I *lf0, *lf1;          // NT flipped triangles of a round, by round parity
+  I *cl0, *cl1;          // ncand candidate edge keys of a round, by round parity
+  // canonical order (aliases of the flip state)
+  int32_t* scnt;         // NP + 1 bucket starts by smallest vertex rank
+  int32_t* scur;         // NP + 1 fill cursors
+  I* slist;              // NT triangles grouped by smallest vertex
+  int NP, NT, ncand;
 };
 
-__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-template <typename I>
-__host__ __device__ inline size_t mesh_bytes(int n, int lh) {
-  const size_t NP = (size_t)n + 4, NT = 2 * (size_t)n + 2, L = (size_t)lh;
-  return 3 * align16(NP * 2) + 2 * align16(3 * NT * sizeof(I)) + align16(NT * 4) +
-         align16(NT * sizeof(I)) + 2 * align16(NT) + 2 * align16((NP + 1) * 4) +
-         align16(3 * NT * sizeof(I)) + align16((L + 1) * 4) + align16(L * 4 + 4) +
-         align16((L + 2) * 4) + align16(2 * (L + 2) * 4);
-}
-
-template <typename I>
-__device__ MeshMem<I> carve(char* base, int n, int lh) {
-  const size_t NP = (size_t)n + 4, NT = 2 * (size_t)n + 2, L = (size_t)lh;
-  MeshMem<I> m;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    char* p = base + o;
-    o += align16(bytes);
+struct Carver {
+  char* base;
+  size_t off;
+  __host__ __device__ __forceinline__ char* take(size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += a16(bytes);
     return p;
-  };
-  m.pu = reinterpret_cast<int16_t*>(take(NP * 2));
-  m.pv = reinterpret_cast<int16_t*>(take(NP * 2));
-  m.pd = reinterpret_cast<int16_t*>(take(NP * 2));
-  m.tv = reinterpret_cast<I*>(take(3 * NT * sizeof(I)));
-  m.tn = reinterpret_cast<I*>(take(3 * NT * sizeof(I)));
-  m.claim = reinterpret_cast<int32_t*>(take(NT * 4));
-  m.partner = reinterpret_cast<I*>(take(NT * sizeof(I)));
-  m.cand = reinterpret_cast<uint8_t*>(take(NT));
-  m.dirty = reinterpret_cast<uint8_t*>(take(NT));
-  m.cnt = reinterpret_cast<int32_t*>(take((NP + 1) * 4));
-  m.cur = reinterpret_cast<int32_t*>(take((NP + 1) * 4));
-  m.inc = reinterpret_cast<I*>(take(3 * NT * sizeof(I)));
-  m.rowStart = reinterpret_cast<int32_t*>(take((L + 1) * 4));
-  m.rowNE = reinterpret_cast<int32_t*>(take(L * 4 + 4));
-  m.stripOff = reinterpret_cast<int32_t*>(take((L + 2) * 4));
-  m.stack = reinterpret_cast<int32_t*>(take(2 * (L + 2) * 4));
-  return m;
+  }
+};
+
+// Lays the arrays of one view out from base (base == nullptr: sizes only)
+// into m; returns the bytes used. The row arrays come first, at offsets that do not
+// depend on n.
+template <typename I>
+__host__ __device__ __forceinline__ size_t carve(char* base, int n, int lh, MeshMem<I>& m) {
+  typedef typename ClaimT<I>::T C;
+  const size_t NP = (size_t)n + 4, NT = 2 * (size_t)n + 2, L = (size_t)lh + 2;
+  const size_t ncand = 3 * NT / 2 + 2;
+  Carver c{base, 0};
+  MeshMem<I> t{};
+  t.rowStart = reinterpret_cast<int32_t*>(c.take(L * 4));
+  t.rowNE = reinterpret_cast<int32_t*>(c.take(L * 4));
+  t.stripOff = reinterpret_cast<int32_t*>(c.take(L * 4));
+  t.chainK0 = reinterpret_cast<uint32_t*>(c.take(L * 4));
+  t.chainI0 = reinterpret_cast<int32_t*>(c.take(L * 4));
+  t.chainK1 = reinterpret_cast<uint32_t*>(c.take(L * 4));
+  t.chainI1 = reinterpret_cast<int32_t*>(c.take(L * 4));
+  t.pk = reinterpret_cast<uint32_t*>(c.take(NP * 4));
+  char* r1 = c.take(3 * NT * 4);
+  t.tk = reinterpret_cast<uint32_t*>(r1);
+  t.hbuck = reinterpret_cast<I*>(r1);
+  t.tn = reinterpret_cast<I*>(c.take(3 * NT * sizeof(I)));
+  // region of the flip state, shared with construction and final order
+  const size_t flip_bytes = a16(NT * sizeof(C)) + a16(NT * sizeof(I)) + a16(NT * 2) +
+                            2 * a16(NT * sizeof(I)) + 2 * a16(ncand * sizeof(I));
+  const size_t adj_bytes = a16(3 * NT * sizeof(I)) + 2 * a16((NP + 1) * 4);
+  const size_t fin_bytes = 2 * a16((NP + 1) * 4) + a16(NT * sizeof(I));
+  size_t d_bytes = flip_bytes;
+  if (adj_bytes > d_bytes) d_bytes = adj_bytes;
+  if (fin_bytes > d_bytes) d_bytes = fin_bytes;
+  char* rd = c.take(d_bytes);
+  {
+    Carver d{rd, 0};
+    t.claim = reinterpret_cast<C*>(d.take(NT * sizeof(C)));
+    t.partner = reinterpret_cast<I*>(d.take(NT * sizeof(I)));
+    t.flipr = reinterpret_cast<uint16_t*>(d.take(NT * 2));
+    t.lf0 = reinterpret_cast<I*>(d.take(NT * sizeof(I)));
+    t.lf1 = reinterpret_cast<I*>(d.take(NT * sizeof(I)));
+    t.cl0 = reinterpret_cast<I*>(d.take(ncand * sizeof(I)));
+    t.cl1 = reinterpret_cast<I*>(d.take(ncand * sizeof(I)));
+  }
+  {
+    Carver d{rd, 0};
+    t.tv = reinterpret_cast<I*>(d.take(3 * NT * sizeof(I)));
+    t.vcnt = reinterpret_cast<int32_t*>(d.take((NP + 1) * 4));
+    t.vcur = reinterpret_cast<int32_t*>(d.take((NP + 1) * 4));
+  }
+  {
+    Carver d{rd, 0};
+    t.scnt = reinterpret_cast<int32_t*>(d.take((NP + 1) * 4));
+    t.scur = reinterpret_cast<int32_t*>(d.take((NP + 1) * 4));
+    t.slist = reinterpret_cast<I*>(d.take(NT * sizeof(I)));
+  }
+  t.NP = (int)NP;
+  t.NT = (int)NT;
+  t.ncand = (int)ncand;
+  m = t;
+  return c.off;
 }
 
+struct MeshShared {
+  int wsum[kMT / 64];
+  unsigned long long corner[4];
+  int ncand[2];   // candidates appended in a round, by parity
+  int nflip[2];   // flipped triangles appended in a round, by parity
+  int err;        // 2: the initial triangulation failed a consistency check
+  int border;     // half-edges without a twin (4 for a valid mesh)
+};
+
+// Writes triangle k with ranks (a, b, c) and keys (ka, kb, kc), turned
+// counter-clockwise.
 template <typename I>
-__device__ __forceinline__ void put_tri(MeshMem<I>& M, int k, int a, int b, int c) {
-  if (k < 0 || k >= M.NT) {
-    *M.overflow = 1;
+__device__ __forceinline__ void put_tri(I* tv, int NT, int k, int a, int b, int c, uint32_t ka,
+                                        uint32_t kb, uint32_t kc, int* err) {
+  const int o = orient_k(ka, kb, kc);
+  if (k < 0 || k >= NT || o == 0) {
+    *err = 2;
     return;
   }
-  if (orient2(M.pu[a], M.pv[a], M.pu[b], M.pv[b], M.pu[c], M.pv[c]) < 0) {
+  if (o < 0) {
     const int t = b;
     b = c;
     c = t;
   }
-  M.tv[3 * k] = (I)a;
-  M.tv[3 * k + 1] = (I)b;
-  M.tv[3 * k + 2] = (I)c;
+  tv[3 * k] = (I)a;
+  tv[3 * k + 1] = (I)b;
+  tv[3 * k + 2] = (I)c;
 }
 
-// Stack triangulation of one side pocket: the v-monotone polygon between the
-// end points of the non-empty rows (top to bottom) and the image border from
-// corner `top` to corner `bottom`. side < 0: left pocket (rows' first
-// points), side > 0: right pocket (last points). Emits exactly m triangles
-// from index k.
+// One side pocket point: chain index k in 1..m of side s (0: the rows' first
+// points against the left border, 1: last points against the right border).
 template <typename I>
-__device__ void pocket(MeshMem<I>& M, int m, int top, int bottom, int side, int* S, int k) {
-  int L = 0;
-  S[L++] = top;
-  for (int r = 0; r < m; ++r) {
-    const int l = M.rowNE[r];
-    const int p = side < 0 ? 2 + M.rowStart[l] : 2 + M.rowStart[l + 1] - 1;
-    while (L >= 2) {
-      const int a = S[L - 2], b = S[L - 1];
-      const long long o = orient2(M.pu[a], M.pv[a], M.pu[b], M.pv[b], M.pu[p], M.pv[p]);
-      if ((side < 0 && o > 0) || (side > 0 && o < 0)) {
-        put_tri(M, k++, a, b, p);
-        --L;
-      } else {
-        break;
-      }
+__device__ __forceinline__ void pocket_point(const uint32_t* pk, const uint32_t* ck,
+                                             const int32_t* ci, I* tv, int NT, int s, int k, int m,
+                                             int n, int slot0, int* err) {
+  const int T = s == 0 ? 0 : 1, B = s == 0 ? n + 2 : n + 3;
+  const uint32_t c = ck[k - 1];
+  // below c on the stack: the earlier point at the extreme angle from c
+  uint32_t q = pk[T];
+  int qi = T;
+  for (int x = 1; x < k; ++x) {
+    const uint32_t kx = ck[x - 1];
+    const int o = orient_k(q, c, kx);
+    if (s == 0 ? o >= 0 : o <= 0) {
+      q = kx;
+      qi = ci[x - 1];
     }
-    S[L++] = p;
   }
-  // the remaining chain is reflex as seen from the pocket: fan from the
-  // bottom corner, except that chain points collinear with that corner at the
-  // end of the chain are fanned from the last point before them
-  int j = L - 1;
-  while (j >= 1 && orient2(M.pu[S[j - 1]], M.pv[S[j - 1]], M.pu[S[j]], M.pv[S[j]], M.pu[bottom],
-                           M.pv[bottom]) == 0)
-    --j;
-  for (int i = 0; i < j; ++i) put_tri(M, k++, S[i], S[i + 1], bottom);
-  if (j < L - 1) {
-    for (int i = j; i + 1 < L; ++i) put_tri(M, k++, S[j - 1], S[i], S[i + 1]);
-    put_tri(M, k++, S[j - 1], S[L - 1], bottom);
+  // the point that pops c: the first later point strictly across (q, c)
+  uint32_t p = pk[B];
+  int pi = B;
+  for (int y = k + 1; y <= m; ++y) {
+    const uint32_t ky = ck[y - 1];
+    const int o = orient_k(q, c, ky);
+    if (s == 0 ? o > 0 : o < 0) {
+      p = ky;
+      pi = ci[y - 1];
+      break;
+    }
+  }
+  put_tri(tv, NT, slot0 + k - 1, qi, ci[k - 1], pi, q, c, p, err);
+}
+
+// Zipper over one strip between the upper row (ranks fa.., ca points) and
+// the lower row (fb.., cb points), writing ca + cb - 2 triangles from slot k.
+template <typename I>
+__device__ __forceinline__ void zipper(const uint32_t* pk, I* tv, int NT, int fa, int ca, int fb,
+                                       int cb, int k, int* err) {
+  int i = 0, j = 0;
+  uint32_t A0 = pk[fa], A1 = ca > 1 ? pk[fa + 1] : 0u;
+  uint32_t B0 = pk[fb], B1 = cb > 1 ? pk[fb + 1] : 0u;
+  while (i + 1 < ca || j + 1 < cb) {
+    bool adv_i;
+    if (i + 1 >= ca)
+      adv_i = false;
+    else if (j + 1 >= cb)
+      adv_i = true;
+    else
+      adv_i = !(incircle_k(A0, A1, B0, B1) > 0.0);
+    if (k >= NT) {
+      *err = 2;
+      return;
+    }
+    // the upper row lies above the lower one and both run left to right, so
+    // these vertex orders are counter-clockwise
+    if (adv_i) {
+      tv[3 * k] = (I)(fa + i);
+      tv[3 * k + 1] = (I)(fa + i + 1);
+      tv[3 * k + 2] = (I)(fb + j);
+      ++i;
+      A0 = A1;
+      A1 = i + 1 < ca ? pk[fa + i + 1] : 0u;
+    } else {
+      tv[3 * k] = (I)(fa + i);
+      tv[3 * k + 1] = (I)(fb + j + 1);
+      tv[3 * k + 2] = (I)(fb + j);
+      ++j;
+      B0 = B1;
+      B1 = j + 1 < cb ? pk[fb + j + 1] : 0u;
+    }
+    ++k;
+  }
+}
+
+// Rank of key s in the sorted point keys (s is present).
+__device__ __forceinline__ int rank_of(const uint32_t* pk, int np, uint32_t s) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pk[mid] < s)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename I>
+__device__ void mesh_fail(MeshHeader* hdr, int view, int status) {
+  if (threadIdx.x == 0) {
+    hdr->status[view] = status;
+    hdr->ntri[view] = 0;
   }
 }
 
 template <typename I>
-__device__ __forceinline__ bool has_vertex(const MeshMem<I>& M, int t, int v) {
-  return (int)M.tv[3 * t] == v || (int)M.tv[3 * t + 1] == v || (int)M.tv[3 * t + 2] == v;
-}
-
-template <typename I>
-__device__ __forceinline__ int back_index(const MeshMem<I>& M, int o, int t) {
-  return (int)M.tn[3 * o] == t ? 0 : ((int)M.tn[3 * o + 1] == t ? 1 : 2);
-}
-
-// Edge i of triangle t (apex p) against neighbour o (apex q at index j).
-template <typename I>
-__device__ bool edge_illegal(const MeshMem<I>& M, int t, int i, int o, int j) {
-  const int p = M.tv[3 * t + i], a = M.tv[3 * t + (i + 1) % 3], b = M.tv[3 * t + (i + 2) % 3];
-  const int q = M.tv[3 * o + j];
-  const long long ic = incircle2(M.pu[p], M.pv[p], M.pu[a], M.pv[a], M.pu[b], M.pv[b], M.pu[q],
-                                 M.pv[q]);
-  if (ic != 0) return ic > 0;
-  // co-circular: indices are ranks in (v, u) order, so the smallest index is
-  // the (v, u)-smallest point; the edge is legal iff it is an endpoint
-  const int mn = min(min(p, q), min(a, b));
-  return !(mn == a || mn == b);
-}
-
-__device__ __forceinline__ void sort3(int& a, int& b, int& c) {
-  if (a > b) { const int t = a; a = b; b = t; }
-  if (b > c) { const int t = b; b = c; c = t; }
-  if (a > b) { const int t = a; a = b; b = t; }
-}
-
-template <typename I>
-__device__ void mesh_run(char* base, const int32_t* __restrict__ rows,
-                         const int32_t* __restrict__ cnt_view, int n, int tri_base,
-                         const Geometry& g, MeshHeader* hdr, int view, int32_t* out_pts,
-                         int32_t* out_recs, float* out_planes, RasterTri* out_tris, int* wsum,
-                         unsigned long long* s_corner, int* s_flag) {
+__device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__ rows,
+                         const int32_t* __restrict__ cnt_view, int c_first, int n, int tri_base,
+                         const Geometry& g, int dmin, MeshHeader* hdr, int view,
+                         int32_t* out_pts, int32_t* out_recs, float* out_planes,
+                         RasterTri* out_tris, MeshShared& sh) {
+  typedef typename ClaimT<I>::T C;
   const int tid = threadIdx.x;
-  const int NP = n + 4, NT = 2 * n + 2;
-  MeshMem<I> M = carve<I>(base, n, g.lh);
-  M.NT = NT;
-  M.overflow = s_flag;
-  if (tid == 0) *s_flag = 0;
+  MeshMem<I> M;
+  carve<I>(base, n, g.lh, M);
+  int32_t* const rowStart = M.rowStart;
+  int32_t* const rowNE = M.rowNE;
+  int32_t* const stripOff = M.stripOff;
+  uint32_t* const chainK0 = M.chainK0;
+  uint32_t* const chainK1 = M.chainK1;
+  int32_t* const chainI0 = M.chainI0;
+  int32_t* const chainI1 = M.chainI1;
+  uint32_t* const pk = M.pk;
+  uint32_t* const tk = M.tk;
+  I* const tn = M.tn;
+  I* const hbuck = M.hbuck;
+  I* const tv = M.tv;
+  int32_t* const vcnt = M.vcnt;
+  int32_t* const vcur = M.vcur;
+  C* const claim = M.claim;
+  I* const partner = M.partner;
+  uint16_t* const flipr = M.flipr;
+  I* const lf0 = M.lf0;
+  I* const lf1 = M.lf1;
+  I* const cl0 = M.cl0;
+  I* const cl1 = M.cl1;
+  int32_t* const scnt = M.scnt;
+  int32_t* const scur = M.scur;
+  I* const slist = M.slist;
+  const int NP = M.NP, NT = M.NT, ncand = M.ncand;
 
-  // ---- 1. points in rank order, corners --------------------------------
-  for (int l = tid; l < g.lh; l += kMT) M.rowStart[l] = cnt_view[l];
-  if (tid == 0) M.rowStart[g.lh] = 0;
-  if (tid < 4) s_corner[tid] = ~0ull;
+  // ---- 1. points in rank order, corners ----------------------------------
+  for (int l = tid; l < g.lh; l += kMT) rowStart[l] = l < kMT ? c_first : cnt_view[l];
+  if (tid == 0) rowStart[g.lh] = 0;
+  if (tid < 4) sh.corner[tid] = ~0ull;
   __syncthreads();
-  scan_array(M.rowStart, g.lh + 1, wsum);
-  for (int l = tid; l < g.lh; l += kMT) {
-    const int s0 = M.rowStart[l], c = M.rowStart[l + 1] - s0;
-    const int v = g.lv0 + l * g.step;
-    for (int j = 0; j < c; ++j) {
-      const int e = rows[(size_t)l * g.lw + j];
-      const int idx = 2 + s0 + j;
-      M.pu[idx] = (int16_t)(e & 0xFFFF);
-      M.pv[idx] = (int16_t)v;
-      M.pd[idx] = (int16_t)(e >> 16);
-      out_pts[3 * (s0 + j)] = e & 0xFFFF;
-      out_pts[3 * (s0 + j) + 1] = v;
-      out_pts[3 * (s0 + j) + 2] = e >> 16;
-    }
-  }
-  if (tid == 0) {
-    M.pu[0] = 0;
-    M.pv[0] = 0;
-    M.pu[1] = (int16_t)(g.w - 1);
-    M.pv[1] = 0;
-    M.pu[n + 2] = 0;
-    M.pv[n + 2] = (int16_t)(g.h - 1);
-    M.pu[n + 3] = (int16_t)(g.w - 1);
-    M.pv[n + 3] = (int16_t)(g.h - 1);
-  }
-  __syncthreads();
+  scan_array(rowStart, g.lh + 1, sh.wsum);
   {
-    const int cu[4] = {0, g.w - 1, 0, g.w - 1}, cvv[4] = {0, 0, g.h - 1, g.h - 1};
+    const int cu[4] = {0, g.w - 1, 0, g.w - 1}, cv[4] = {0, 0, g.h - 1, g.h - 1};
     unsigned long long best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
-    for (int i = tid; i < n; i += kMT) {
-      const int u = M.pu[2 + i], v = M.pv[2 + i];
+    for (int k = tid; k < n; k += kMT) {
+      // lattice row of point k: the last row starting at or before k
+      int lo = 0, hi = g.lh - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rowStart[mid] <= k)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const int e = rows[(size_t)lo * g.lw + (k - rowStart[lo])];
+      const int u = e & 0xFFFF, d = e >> 16, v = g.lv0 + lo * g.step;
+      pk[2 + k] = make_key(u, v, d - dmin);
+      out_pts[3 * k] = u;
+      out_pts[3 * k + 1] = v;
+      out_pts[3 * k + 2] = d;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const long long du = u - cu[c], dv = v - cvv[c];
+        const long long du = u - cu[c], dv = v - cv[c];
         const unsigned long long key =
-            ((unsigned long long)(du * du + dv * dv) << 32) | (unsigned long long)(unsigned)i;
+            ((unsigned long long)(du * du + dv * dv) << 32) | (unsigned long long)(unsigned)k;
         best[c] = key < best[c] ? key : best[c];
       }
     }
@@ -302,247 +459,297 @@ __device__ void mesh_run(char* base, const int32_t* __restrict__ rows,
         const unsigned long long o = __shfl_xor(b, off, 64);
         b = o < b ? o : b;
       }
-      if ((tid & 63) == 0) atomicMin(&s_corner[c], b);
+      if ((tid & 63) == 0) atomicMin(&sh.corner[c], b);
     }
   }
   // non-empty rows, in order
   int m = 0;
   for (int c0 = 0; c0 < g.lh; c0 += kMT) {
     const int l = c0 + tid;
-    const int f = (l < g.lh && M.rowStart[l + 1] > M.rowStart[l]) ? 1 : 0;
+    const int f = (l < g.lh && rowStart[l + 1] > rowStart[l]) ? 1 : 0;
     int tot;
-    const int e = scan_excl(f, &tot, wsum);
-    if (f) M.rowNE[m + e] = l;
+    const int e = scan_excl(f, &tot, sh.wsum);
+    if (f) rowNE[m + e] = l;
     m += tot;
   }
   if (tid < 4) {
-    const int src = 2 + (int)(s_corner[tid] & 0xFFFFFFFFull);
-    const int ci = tid < 2 ? tid : n + tid;  // corner ranks 0, 1, n+2, n+3
-    M.pd[ci] = M.pd[src];
-    hdr->corners[4 * view + tid] = M.pd[src];
+    const int src = (int)(sh.corner[tid] & 0xFFFFFFFFull);
+    const int dd = key_dd(pk[2 + src]);
+    const int rank = tid < 2 ? tid : n + tid;  // ranks 0, 1, n+2, n+3
+    const int cu = (tid & 1) ? g.w - 1 : 0, cv = tid < 2 ? 0 : g.h - 1;
+    pk[rank] = make_key(cu, cv, dd);
+    hdr->corners[4 * view + tid] = dd + dmin;
   }
   __syncthreads();
+  for (int r = tid; r < m; r += kMT) {
+    const int l = rowNE[r];
+    const int i0 = 2 + rowStart[l], i1 = 1 + rowStart[l + 1];
+    chainI0[r] = i0;
+    chainI1[r] = i1;
+    chainK0[r] = pk[i0];
+    chainK1[r] = pk[i1];
+  }
+  // strips: s = 0 between the top corners and the first row, s = m between
+  // the last row and the bottom corners
+  for (int s = tid; s <= m; s += kMT) {
+    const int ca = s == 0 ? 2 : rowStart[rowNE[s - 1] + 1] - rowStart[rowNE[s - 1]];
+    const int cb = s == m ? 2 : rowStart[rowNE[s] + 1] - rowStart[rowNE[s]];
+    stripOff[s] = ca + cb - 2;
+  }
+  if (tid == 0) stripOff[m + 1] = 0;
+  __syncthreads();
+  const int strip_tris = scan_array(stripOff, m + 2, sh.wsum);
 
-  // ---- 2. initial triangulation ------------------------------------------
-  // rows r = 0 (top edge: ranks 0, 1), 1..m (non-empty lattice rows),
-  // m + 1 (bottom edge: ranks n+2, n+3); ranks inside a row are contiguous
-  for (int s = tid; s <= m; s += kMT) {
-    const int ca = s == 0 ? 2 : M.rowStart[M.rowNE[s - 1] + 1] - M.rowStart[M.rowNE[s - 1]];
-    const int cb = s == m ? 2 : M.rowStart[M.rowNE[s] + 1] - M.rowStart[M.rowNE[s]];
-    M.stripOff[s] = ca + cb - 2;
-  }
-  if (tid == 0) M.stripOff[m + 1] = 0;
-  __syncthreads();
-  const int strip_tris = scan_array(M.stripOff, m + 2, wsum);
-  for (int s = tid; s <= m; s += kMT) {
-    const int fa = s == 0 ? 0 : 2 + M.rowStart[M.rowNE[s - 1]];
-    const int ca = s == 0 ? 2 : M.rowStart[M.rowNE[s - 1] + 1] - M.rowStart[M.rowNE[s - 1]];
-    const int fb = s == m ? n + 2 : 2 + M.rowStart[M.rowNE[s]];
-    const int cb = s == m ? 2 : M.rowStart[M.rowNE[s] + 1] - M.rowStart[M.rowNE[s]];
-    int i = 0, j = 0, k = M.stripOff[s];
-    while (i + 1 < ca || j + 1 < cb) {
-      bool adv_i;
-      if (i + 1 >= ca) {
-        adv_i = false;
-      } else if (j + 1 >= cb) {
-        adv_i = true;
-      } else {
-        const int a0 = fa + i, a1 = fa + i + 1, b0 = fb + j, b1 = fb + j + 1;
-        adv_i = !(incircle2(M.pu[a0], M.pv[a0], M.pu[a1], M.pv[a1], M.pu[b0], M.pv[b0], M.pu[b1],
-                            M.pv[b1]) > 0);
-      }
-      // the upper row is above the lower one and both are sorted by u, so
-      // these vertex orders are positively oriented
-      if (k >= NT) {
-        *s_flag = 1;
-        break;
-      }
-      if (adv_i) {
-        M.tv[3 * k] = (I)(fa + i);
-        M.tv[3 * k + 1] = (I)(fa + i + 1);
-        M.tv[3 * k + 2] = (I)(fb + j);
-        ++i;
-      } else {
-        M.tv[3 * k] = (I)(fa + i);
-        M.tv[3 * k + 1] = (I)(fb + j + 1);
-        M.tv[3 * k + 2] = (I)(fb + j);
-        ++j;
-      }
-      ++k;
+  // ---- 2. initial triangulation: strips and both pockets concurrently ------
+  if (tid < kMT / 2) {
+    for (int s = tid; s <= m; s += kMT / 2) {
+      const int fa = s == 0 ? 0 : 2 + rowStart[rowNE[s - 1]];
+      const int ca = s == 0 ? 2 : rowStart[rowNE[s - 1] + 1] - rowStart[rowNE[s - 1]];
+      const int fb = s == m ? n + 2 : 2 + rowStart[rowNE[s]];
+      const int cb = s == m ? 2 : rowStart[rowNE[s] + 1] - rowStart[rowNE[s]];
+      zipper(pk, tv, NT, fa, ca, fb, cb, stripOff[s], &sh.err);
     }
+  } else {
+    const int side = (tid - kMT / 2) / (kMT / 4), lt = (tid - kMT / 2) % (kMT / 4);
+    for (int k = 1 + lt; k <= m; k += kMT / 4)
+      pocket_point(pk, side == 0 ? chainK0 : chainK1, side == 0 ? chainI0 : chainI1, tv, NT,
+                   side, k, m, n, strip_tris + side * m, &sh.err);
   }
-  if (tid == 0) pocket(M, m, 0, n + 2, -1, M.stack, strip_tris);
-  if (tid == 64) pocket(M, m, 1, n + 3, +1, M.stack + (g.lh + 2), strip_tris + m);
+  if (tid == 0 && strip_tris + 2 * m != NT) sh.err = 2;
   __syncthreads();
-  if (*s_flag) {  // cannot happen for valid lists; report, and leave no triangles
-    if (tid == 0) {
-      hdr->status[view] = 2;
-      hdr->ntri[view] = 0;
-    }
+  if (sh.err) {
+    mesh_fail<I>(hdr, view, 2);
     return;
   }
-  __syncthreads();
 
-  // ---- 3. adjacency through vertex incidence lists ------------------------
-  for (int v = tid; v <= NP; v += kMT) M.cnt[v] = 0;
-  __syncthreads();
-  for (int e = tid; e < 3 * NT; e += kMT) atomicAdd(&M.cnt[(int)M.tv[e]], 1);
-  __syncthreads();
-  scan_array(M.cnt, NP + 1, wsum);
-  for (int v = tid; v <= NP; v += kMT) M.cur[v] = M.cnt[v];
-  __syncthreads();
-  for (int e = tid; e < 3 * NT; e += kMT) M.inc[atomicAdd(&M.cur[(int)M.tv[e]], 1)] = (I)(e / 3);
+  // ---- 3. adjacency -------------------------------------------------------
+  for (int v = tid; v <= NP; v += kMT) vcnt[v] = 0;
   __syncthreads();
   for (int e = tid; e < 3 * NT; e += kMT) {
     const int t = e / 3, k = e - 3 * t;
-    const int a = M.tv[3 * t + (k + 1) % 3], b = M.tv[3 * t + (k + 2) % 3];
+    atomicAdd(&vcnt[(int)tv[3 * t + (k == 2 ? 0 : k + 1)]], 1);
+  }
+  __syncthreads();
+  scan_array(vcnt, NP + 1, sh.wsum);
+  for (int v = tid; v <= NP; v += kMT) vcur[v] = vcnt[v];
+  __syncthreads();
+  for (int e = tid; e < 3 * NT; e += kMT) {
+    const int t = e / 3, k = e - 3 * t;
+    const int a = tv[3 * t + (k == 2 ? 0 : k + 1)];
+    hbuck[atomicAdd(&vcur[a], 1)] = (I)e;
+  }
+  __syncthreads();
+  for (int e = tid; e < 3 * NT; e += kMT) {
+    // half-edge a -> b opposite vertex k; its twin runs b -> a
+    const int t = e / 3, k = e - 3 * t;
+    const int a = tv[3 * t + (k == 2 ? 0 : k + 1)], b = tv[3 * t + (k == 0 ? 2 : k - 1)];
     int nb = -1;
-    for (int s = M.cnt[b], s1 = M.cnt[b + 1]; s < s1; ++s) {
-      const int x = M.inc[s];
-      if (x != t && has_vertex(M, x, a)) {
-        nb = x;
+    for (int s = vcnt[b], s1 = vcnt[b + 1]; s < s1; ++s) {
+      const int e2 = hbuck[s];
+      const int t2 = e2 / 3, k2 = e2 - 3 * t2;
+      if ((int)tv[3 * t2 + (k2 == 0 ? 2 : k2 - 1)] == a) {
+        nb = 4 * t2 + k2;
         break;
       }
     }
-    M.tn[e] = (I)nb;
+    tn[e] = (I)nb;
+    if (nb < 0) atomicAdd(&sh.border, 1);
   }
+  __syncthreads();
+  if (sh.border != 4) {  // only the four image sides lack a twin
+    mesh_fail<I>(hdr, view, 2);
+    return;
+  }
+  // vertex keys (over the buckets, which are no longer needed)
+  for (int e = tid; e < 3 * NT; e += kMT) tk[e] = pk[(int)tv[e]];
+  __syncthreads();
+  // flip state (over the vertex ranks, which are no longer needed)
   for (int t = tid; t < NT; t += kMT) {
-    M.claim[t] = INT_MAX;
-    M.partner[t] = (I)-1;
-    M.cand[t] = 0;
-    M.dirty[t] = 1;
+    claim[t] = C(0);
+    flipr[t] = 0;
+  }
+  if (tid == 0) {
+    sh.ncand[0] = sh.ncand[1] = 0;
+    sh.nflip[0] = sh.nflip[1] = 0;
   }
   __syncthreads();
 
   // ---- 4. Lawson flips in synchronous rounds ------------------------------
-  int rounds = 0;
-  const int max_rounds = 4 * NT + 64;
-  for (;;) {
-    if (tid == 0) *s_flag = 0;
-    __syncthreads();
-    for (int t = tid; t < NT; t += kMT) {
-      M.partner[t] = (I)-1;
-      uint8_t cb = 0;
+  for (int r = 1;; ++r) {
+    const int cur = r & 1, prev = cur ^ 1;
+    I* const lf_cur = cur ? lf1 : lf0;
+    const I* const lf_prev = cur ? lf0 : lf1;
+    I* const cl_cur = cur ? cl1 : cl0;
+    const I* const cl_prev = cur ? cl0 : cl1;
+    const int n_test = r == 1 ? NT : sh.nflip[prev];
+    const int n_old = r == 1 ? 0 : sh.ncand[prev];
+    // edges of the triangles flipped last round (every triangle in round 1);
+    // an edge between two such triangles is tested by the smaller one
+    for (int idx = tid; idx < n_test; idx += kMT) {
+      const int t = r == 1 ? idx : (int)lf_prev[idx];
+      const uint32_t kk[3] = {tk[3 * t], tk[3 * t + 1], tk[3 * t + 2]};
+      const int ee[3] = {tn[3 * t], tn[3 * t + 1], tn[3 * t + 2]};
+#pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const int o = M.tn[3 * t + i];
-        if (o <= t || (!M.dirty[t] && !M.dirty[o])) continue;
-        if (edge_illegal(M, t, i, o, back_index(M, o, t))) {
-          cb |= (uint8_t)(1u << i);
-          const int key = 4 * t + i;
-          atomicMin(&M.claim[t], key);
-          atomicMin(&M.claim[o], key);
+        const int e = ee[i];
+        if (e < 0) continue;
+        const int o = e >> 2, j = e & 3;
+        if (o < t && (int)flipr[o] == r - 1) continue;
+        if (edge_illegal(kk[i], kk[(i + 1) % 3], kk[(i + 2) % 3], tk[3 * o + j])) {
+          const int key = t < o ? 4 * t + i : 4 * o + j;
+          const C st = claim_stamp<I>(r, key);
+          atomicMax(&claim[t], st);
+          atomicMax(&claim[o], st);
+          const int slot = atomicAdd(&sh.ncand[cur], 1);
+          if (slot < ncand)
+            cl_cur[slot] = (I)key;
+          else
+            sh.err = 2;
         }
       }
-      M.cand[t] = cb;
-      if (cb) *s_flag = 1;
+    }
+    // last round's candidates whose two triangles did not flip
+    for (int idx = tid; idx < n_old; idx += kMT) {
+      const int key = cl_prev[idx];
+      const int t = key >> 2, i = key & 3;
+      if ((int)flipr[t] == r - 1) continue;
+      const int o = (int)tn[3 * t + i] >> 2;
+      if ((int)flipr[o] == r - 1) continue;
+      const C st = claim_stamp<I>(r, key);
+      atomicMax(&claim[t], st);
+      atomicMax(&claim[o], st);
+      const int slot = atomicAdd(&sh.ncand[cur], 1);
+      if (slot < ncand)
+        cl_cur[slot] = (I)key;
+      else
+        sh.err = 2;
     }
     __syncthreads();
-    if (*s_flag == 0) break;
-    if (++rounds > max_rounds) {
-      if (tid == 0) hdr->status[view] = 1;
-      break;
+    const int nc = sh.ncand[cur];
+    if (nc == 0) break;
+    if (sh.err || r >= kMaxRounds) {
+      mesh_fail<I>(hdr, view, sh.err ? sh.err : 1);
+      return;
     }
-    for (int t = tid; t < NT; t += kMT) {
-      const uint8_t cb = M.cand[t];
-      if (!cb) continue;
-      for (int i = 0; i < 3; ++i) {
-        if (!((cb >> i) & 1u)) continue;
-        const int key = 4 * t + i;
-        const int o = M.tn[3 * t + i];
-        if (M.claim[t] != key || M.claim[o] != key) continue;
-        const int j = back_index(M, o, t);
-        const int p = M.tv[3 * t + i], a = M.tv[3 * t + (i + 1) % 3];
-        const int b = M.tv[3 * t + (i + 2) % 3], q = M.tv[3 * o + j];
-        const int t_bp = M.tn[3 * t + (i + 1) % 3], t_pa = M.tn[3 * t + (i + 2) % 3];
-        const int o_aq = M.tn[3 * o + (j + 1) % 3], o_qb = M.tn[3 * o + (j + 2) % 3];
-        M.tv[3 * t] = (I)p;
-        M.tv[3 * t + 1] = (I)a;
-        M.tv[3 * t + 2] = (I)q;
-        M.tn[3 * t] = (I)o_aq;
-        M.tn[3 * t + 1] = (I)o;
-        M.tn[3 * t + 2] = (I)t_pa;
-        M.tv[3 * o] = (I)p;
-        M.tv[3 * o + 1] = (I)q;
-        M.tv[3 * o + 2] = (I)b;
-        M.tn[3 * o] = (I)o_qb;
-        M.tn[3 * o + 1] = (I)t_bp;
-        M.tn[3 * o + 2] = (I)t;
-        M.partner[t] = (I)o;
-        M.partner[o] = (I)t;
-        break;
-      }
+    if (tid == 0) {  // counters of the next round
+      sh.ncand[prev] = 0;
+      sh.nflip[prev] = 0;
+    }
+    // winners flip: (p, a, b) + (q, b, a) -> (p, a, q) + (p, q, b)
+    for (int idx = tid; idx < nc; idx += kMT) {
+      const int key = cl_cur[idx];
+      const int t = key >> 2, i = key & 3;
+      const C st = claim_stamp<I>(r, key);
+      if (claim[t] != st) continue;
+      const int e = tn[3 * t + i];
+      const int o = e >> 2, j = e & 3;
+      if (claim[o] != st) continue;
+      const int i1 = i == 2 ? 0 : i + 1, i2 = i == 0 ? 2 : i - 1;
+      const int j1 = j == 2 ? 0 : j + 1, j2 = j == 0 ? 2 : j - 1;
+      const uint32_t p = tk[3 * t + i], a = tk[3 * t + i1], b = tk[3 * t + i2];
+      const uint32_t q = tk[3 * o + j];
+      const I t_bp = tn[3 * t + i1], t_pa = tn[3 * t + i2];
+      const I o_aq = tn[3 * o + j1], o_qb = tn[3 * o + j2];
+      tk[3 * t] = p;
+      tk[3 * t + 1] = a;
+      tk[3 * t + 2] = q;
+      tn[3 * t] = o_aq;
+      tn[3 * t + 1] = (I)(4 * o + 2);
+      tn[3 * t + 2] = t_pa;
+      tk[3 * o] = p;
+      tk[3 * o + 1] = q;
+      tk[3 * o + 2] = b;
+      tn[3 * o] = o_qb;
+      tn[3 * o + 1] = t_bp;
+      tn[3 * o + 2] = (I)(4 * t + 1);
+      flipr[t] = (uint16_t)r;
+      flipr[o] = (uint16_t)r;
+      partner[t] = (I)o;
+      partner[o] = (I)t;
+      const int slot = atomicAdd(&sh.nflip[cur], 2);
+      lf_cur[slot] = (I)t;
+      lf_cur[slot + 1] = (I)o;
     }
     __syncthreads();
-    // neighbours across edges that moved to the flip partner
-    for (int x = tid; x < NT; x += kMT) {
+    // re-link: an unflipped neighbour is pointed back at the flipped
+    // triangle; across a flipped one the edge now lies in it or its partner
+    const int nf = sh.nflip[cur];
+    for (int idx = tid; idx < nf; idx += kMT) {
+      const int x = lf_cur[idx];
+      const int px = partner[x];
+#pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const int y = M.tn[3 * x + k];
-        if (y < 0 || (int)M.partner[y] < 0) continue;
-        const int a = M.tv[3 * x + (k + 1) % 3], b = M.tv[3 * x + (k + 2) % 3];
-        if (!(has_vertex(M, y, a) && has_vertex(M, y, b))) M.tn[3 * x + k] = M.partner[y];
+        const int e = tn[3 * x + k];
+        if (e < 0) continue;
+        int z = e >> 2;
+        if (z == px) continue;
+        if ((int)flipr[z] != r) {
+          tn[3 * z + (e & 3)] = (I)(4 * x + k);
+          continue;
+        }
+        const uint32_t ea = tk[3 * x + (k == 2 ? 0 : k + 1)];
+        const uint32_t eb = tk[3 * x + (k == 0 ? 2 : k - 1)];
+        uint32_t z0 = tk[3 * z], z1 = tk[3 * z + 1], z2 = tk[3 * z + 2];
+        const bool has_a = z0 == ea || z1 == ea || z2 == ea;
+        const bool has_b = z0 == eb || z1 == eb || z2 == eb;
+        if (!(has_a && has_b)) {
+          z = partner[z];
+          z0 = tk[3 * z];
+          z1 = tk[3 * z + 1];
+          z2 = tk[3 * z + 2];
+        }
+        const int jj = (z0 != ea && z0 != eb) ? 0 : ((z1 != ea && z1 != eb) ? 1 : 2);
+        tn[3 * x + k] = (I)(4 * z + jj);
       }
-      M.dirty[x] = (int)M.partner[x] >= 0 ? 1 : 0;
-      M.claim[x] = INT_MAX;
     }
     __syncthreads();
   }
 
-  // ---- 5. canonical order, planes, raster records --------------------------
-  for (int v = tid; v <= NP; v += kMT) M.cnt[v] = 0;
+  // ---- 5. canonical order, planes, raster records -------------------------
+  for (int v = tid; v <= NP; v += kMT) scnt[v] = 0;
   __syncthreads();
   for (int t = tid; t < NT; t += kMT) {
-    int a = M.tv[3 * t], b = M.tv[3 * t + 1], c = M.tv[3 * t + 2];
-    sort3(a, b, c);
-    atomicAdd(&M.cnt[a], 1);
+    uint32_t s0 = tk[3 * t], s1 = tk[3 * t + 1], s2 = tk[3 * t + 2];
+    sort3(s0, s1, s2);
+    atomicAdd(&scnt[rank_of(pk, NP, s0)], 1);
   }
   __syncthreads();
-  scan_array(M.cnt, NP + 1, wsum);
-  for (int v = tid; v <= NP; v += kMT) M.cur[v] = M.cnt[v];
+  scan_array(scnt, NP + 1, sh.wsum);
+  for (int v = tid; v <= NP; v += kMT) scur[v] = scnt[v];
   __syncthreads();
   for (int t = tid; t < NT; t += kMT) {
-    int a = M.tv[3 * t], b = M.tv[3 * t + 1], c = M.tv[3 * t + 2];
-    sort3(a, b, c);
-    M.inc[atomicAdd(&M.cur[a], 1)] = (I)t;
+    uint32_t s0 = tk[3 * t], s1 = tk[3 * t + 1], s2 = tk[3 * t + 2];
+    sort3(s0, s1, s2);
+    slist[atomicAdd(&scur[rank_of(pk, NP, s0)], 1)] = (I)t;
   }
   __syncthreads();
-  for (int v = tid; v < NP; v += kMT) {
-    const int s0 = M.cnt[v], s1 = M.cnt[v + 1];
-    for (int x = s0 + 1; x < s1; ++x) {
-      for (int y = x; y > s0; --y) {
-        int a1 = M.tv[3 * (int)M.inc[y]], b1 = M.tv[3 * (int)M.inc[y] + 1],
-            c1 = M.tv[3 * (int)M.inc[y] + 2];
-        int a0 = M.tv[3 * (int)M.inc[y - 1]], b0 = M.tv[3 * (int)M.inc[y - 1] + 1],
-            c0 = M.tv[3 * (int)M.inc[y - 1] + 2];
-        sort3(a1, b1, c1);
-        sort3(a0, b0, c0);
-        if (b1 < b0 || (b1 == b0 && c1 < c0)) {
-          const I tmp = M.inc[y];
-          M.inc[y] = M.inc[y - 1];
-          M.inc[y - 1] = tmp;
-        } else {
-          break;
-        }
-      }
+  for (int t = tid; t < NT; t += kMT) {
+    uint32_t s0 = tk[3 * t], s1 = tk[3 * t + 1], s2 = tk[3 * t + 2];
+    sort3(s0, s1, s2);
+    const int a = rank_of(pk, NP, s0);
+    // position: bucket start + triangles of the bucket with a smaller
+    // (middle, largest) vertex pair
+    int pos = scnt[a];
+    for (int qq = scnt[a], q1 = scnt[a + 1]; qq < q1; ++qq) {
+      const int t2 = slist[qq];
+      if (t2 == t) continue;
+      uint32_t r0 = tk[3 * t2], r1 = tk[3 * t2 + 1], r2 = tk[3 * t2 + 2];
+      sort3(r0, r1, r2);
+      pos += (r1 < s1 || (r1 == s1 && r2 < s2)) ? 1 : 0;
     }
-  }
-  __syncthreads();
-  for (int r = tid; r < NT; r += kMT) {
-    const int t = M.inc[r];
-    int i0 = M.tv[3 * t], i1 = M.tv[3 * t + 1], i2 = M.tv[3 * t + 2];
-    sort3(i0, i1, i2);
-    const int vid[3] = {i0, i1, i2};
-    int32_t* rec = out_recs + 9 * (size_t)r;
+    const uint32_t sv[3] = {s0, s1, s2};
+    int32_t* rec = out_recs + 9 * (size_t)pos;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      rec[3 * q] = M.pu[vid[q]];
-      rec[3 * q + 1] = M.pv[vid[q]];
-      rec[3 * q + 2] = M.pd[vid[q]];
+      rec[3 * q] = key_u(sv[q]);
+      rec[3 * q + 1] = key_v(sv[q]);
+      rec[3 * q + 2] = key_dd(sv[q]) + dmin;
     }
     // plane through the three points: exact Cramer numerators relative to the
     // first vertex, one correctly rounded double division each, then FP32
-    const long long u1 = M.pu[i0], v1 = M.pv[i0], d1 = M.pd[i0];
-    const long long du2 = M.pu[i1] - u1, dv2 = M.pv[i1] - v1, dd2 = M.pd[i1] - d1;
-    const long long du3 = M.pu[i2] - u1, dv3 = M.pv[i2] - v1, dd3 = M.pd[i2] - d1;
+    const long long u1 = key_u(s0), v1 = key_v(s0), d1 = key_dd(s0) + dmin;
+    const long long du2 = key_u(s1) - u1, dv2 = key_v(s1) - v1, dd2 = key_dd(s1) + dmin - d1;
+    const long long du3 = key_u(s2) - u1, dv3 = key_v(s2) - v1, dd3 = key_dd(s2) + dmin - d1;
     const long long den = du2 * dv3 - du3 * dv2;
     const long long na = dd2 * dv3 - dd3 * dv2;
     const long long nb = du2 * dd3 - du3 * dd2;
@@ -550,57 +757,82 @@ __device__ void mesh_run(char* base, const int32_t* __restrict__ rows,
     const float pa = (float)__ddiv_rn((double)na, (double)den);
     const float pb = (float)__ddiv_rn((double)nb, (double)den);
     const float pc = (float)__ddiv_rn((double)nc, (double)den);
-    out_planes[3 * (size_t)r] = pa;
-    out_planes[3 * (size_t)r + 1] = pb;
-    out_planes[3 * (size_t)r + 2] = pc;
-    int o1 = i1, o2 = i2;
-    if (orient2(M.pu[i0], M.pv[i0], M.pu[i1], M.pv[i1], M.pu[i2], M.pv[i2]) < 0) {
-      o1 = i2;
-      o2 = i1;
+    out_planes[3 * (size_t)pos] = pa;
+    out_planes[3 * (size_t)pos + 1] = pb;
+    out_planes[3 * (size_t)pos + 2] = pc;
+    uint32_t o1 = s1, o2 = s2;
+    if (orient_k(s0, s1, s2) < 0) {
+      o1 = s2;
+      o2 = s1;
     }
     RasterTri rt;
-    rt.u[0] = M.pu[i0];
-    rt.v[0] = M.pv[i0];
-    rt.u[1] = M.pu[o1];
-    rt.v[1] = M.pv[o1];
-    rt.u[2] = M.pu[o2];
-    rt.v[2] = M.pv[o2];
+    rt.u[0] = (int16_t)key_u(s0);
+    rt.v[0] = (int16_t)key_v(s0);
+    rt.u[1] = (int16_t)key_u(o1);
+    rt.v[1] = (int16_t)key_v(o1);
+    rt.u[2] = (int16_t)key_u(o2);
+    rt.v[2] = (int16_t)key_v(o2);
     rt.a = pa;
     rt.b = pb;
     rt.c = pc;
-    out_tris[tri_base + r] = rt;
+    out_tris[tri_base + pos] = rt;
   }
 }
 
 __global__ __launch_bounds__(kMT) void k_mesh(const int32_t* __restrict__ rowsL,
                                               const int32_t* __restrict__ rowsR,
                                               const int32_t* __restrict__ cnt, Geometry g,
-                                              MeshHeader* hdr, int32_t* ptsL, int32_t* ptsR,
-                                              int32_t* recsL, int32_t* recsR, float* planesL,
-                                              float* planesR, RasterTri* tris, char* gscratch,
-                                              size_t gscratch_per_view, int lds_bytes) {
+                                              int dmin, MeshHeader* hdr, int32_t* ptsL,
+                                              int32_t* ptsR, int32_t* recsL, int32_t* recsR,
+                                              float* planesL, float* planesR, RasterTri* tris,
+                                              char* gscratch, size_t gscratch_per_view,
+                                              int lds_bytes) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ int wsum[kMT / 64];
-  __shared__ unsigned long long s_corner[4];
-  __shared__ int s_flag;
+  __shared__ MeshShared sh;
+  __shared__ int part[3][kMT / 64];
   const int view = blockIdx.x;
   const int tid = threadIdx.x;
-  int x = 0, xl = 0, ev = 0;
+  // point counts of both views and the support evaluations in one pass
+  int x = 0, xl = 0, ev = 0, c_first = 0;
   for (int l = tid; l < g.lh; l += kMT) {
-    x += cnt[view * g.lh + l];
+    const int cv = cnt[view * g.lh + l];
+    if (l == tid) c_first = cv;
+    x += cv;
     xl += cnt[l];
     ev += cnt[2 * g.lh + l];
   }
-  const int n = block_sum(x, wsum);
-  const int nL = block_sum(xl, wsum);
-  const int evals = block_sum(ev, wsum);
+  const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    x += __shfl_xor(x, off, 64);
+    xl += __shfl_xor(xl, off, 64);
+    ev += __shfl_xor(ev, off, 64);
+  }
+  if (lane == 0) {
+    part[0][wid] = x;
+    part[1][wid] = xl;
+    part[2][wid] = ev;
+  }
+  if (tid == 0) {
+    sh.err = 0;
+    sh.border = 0;
+  }
+  __syncthreads();
+  int n = 0, nL = 0, evals = 0;
+#pragma unroll
+  for (int w = 0; w < kMT / 64; ++w) {
+    n += part[0][w];
+    nL += part[1][w];
+    evals += part[2][w];
+  }
   if (tid == 0) {
     hdr->n[view] = n;
     hdr->ntri[view] = n > 0 ? 2 * n + 2 : 0;
     hdr->status[view] = 0;
     if (view == 0) hdr->support_evals = evals;
-    if (n == 0)
+    if (n == 0) {
       for (int c = 0; c < 4; ++c) hdr->corners[4 * view + c] = -1;
+    }
   }
   if (n == 0) return;
   const int tri_base = view ? 2 * nL + 2 : 0;
@@ -608,28 +840,31 @@ __global__ __launch_bounds__(kMT) void k_mesh(const int32_t* __restrict__ rowsL,
   int32_t* pts = view ? ptsR : ptsL;
   int32_t* recs = view ? recsR : recsL;
   float* planes = view ? planesR : planesL;
-  if (2 * n + 2 <= 32767 && mesh_bytes<int16_t>(n, g.lh) <= (size_t)lds_bytes)
-    mesh_run<int16_t>(smem, rows, cnt + view * g.lh, n, tri_base, g, hdr, view, pts, recs,
-                      planes, tris, wsum, s_corner, &s_flag);
+  MeshMem<int16_t> probe;
+  if (2 * n + 2 < 8192 && carve<int16_t>(nullptr, n, g.lh, probe) <= (size_t)lds_bytes)
+    mesh_run<int16_t>(smem, rows, cnt + view * g.lh, c_first, n, tri_base, g, dmin, hdr, view,
+                      pts, recs, planes, tris, sh);
   else
-    mesh_run<int32_t>(gscratch + view * gscratch_per_view, rows, cnt + view * g.lh, n, tri_base,
-                      g, hdr, view, pts, recs, planes, tris, wsum, s_corner, &s_flag);
+    mesh_run<int32_t>(gscratch + view * gscratch_per_view, rows, cnt + view * g.lh, c_first,
+                      n, tri_base, g, dmin, hdr, view, pts, recs, planes, tris, sh);
 }
 
 }  // namespace
 
 size_t mesh_global_scratch_per_view(const Geometry& g) {
   const int nmax = std::max(1, g.lw * g.lh);
-  return align16(mesh_bytes<int32_t>(nmax, g.lh));
+  MeshMem<int32_t> probe;
+  return a16(carve<int32_t>(nullptr, nmax, g.lh, probe));
 }
 
 hipError_t launch_mesh(const int32_t* rowsL, const int32_t* rowsR, const int32_t* cnt,
-                       const Geometry& g, MeshHeader* hdr, int32_t* ptsL, int32_t* ptsR,
-                       int32_t* recsL, int32_t* recsR, float* planesL, float* planesR,
-                       RasterTri* tris, char* gscratch, hipStream_t s) {
+                       const Geometry& g, int32_t dmin, MeshHeader* hdr, int32_t* ptsL,
+                       int32_t* ptsR, int32_t* recsL, int32_t* recsR, float* planesL,
+                       float* planesR, RasterTri* tris, char* gscratch, hipStream_t s) {
+  if (g.w > kDeviceMeshMaxSide || g.h > kDeviceMeshMaxSide) return hipErrorInvalidValue;
   const int lds = kMeshLdsBytes;
-  hipLaunchKernelGGL(k_mesh, dim3(2), dim3(kMT), lds, s, rowsL, rowsR, cnt, g, hdr, ptsL, ptsR,
-                     recsL, recsR, planesL, planesR, tris, gscratch,
+  hipLaunchKernelGGL(k_mesh, dim3(2), dim3(kMT), lds, s, rowsL, rowsR, cnt, g, dmin, hdr, ptsL,
+                     ptsR, recsL, recsR, planesL, planesR, tris, gscratch,
                      mesh_global_scratch_per_view(g), lds);
   return hipGetLastError();
 }

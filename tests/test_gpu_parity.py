@@ -241,3 +241,25 @@ def test_unit_lattice_both_mesh_modes(E, mesh_on_host):
     pair = synth.make_pair(cfg)
     kw = dict(disp_max=31, candidate_stepsize=1, mesh_on_host=mesh_on_host)
     assert run_and_compare(E, pair.left, pair.right, **kw) == []
+
+
+def test_concurrent_streams_each_frame_bit_exact(E):
+    # frames on different streams use separate buffers and overlap on the
+    # device; each result must equal the oracle's for its own pair
+    dev = torch.device("cuda:0")
+    e = E.Elas(disp_max=63)
+    cfgs = [synth.QVGA.with_seed(s) for s in (11, 12, 13)]
+    pairs = [synth.make_pair(c) for c in cfgs]
+    streams = [torch.cuda.Stream(device=dev) for _ in pairs]
+    ins = [(torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev)) for p in pairs]
+    outs = [(torch.empty(p.left.shape, dtype=torch.int16, device=dev),
+             torch.empty(p.left.shape, dtype=torch.int16, device=dev)) for p in pairs]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for (L, R), s, (oL, oR) in zip(ins, streams, outs):
+            e.process(L, R, oL, oR, stream=s)
+    torch.cuda.synchronize()
+    for p, (oL, oR) in zip(pairs, outs):
+        t = ref.process(ref.params(disp_max=63), p.left, p.right)
+        assert np.array_equal(oL.cpu().numpy(), t.outL)
+        assert np.array_equal(oR.cpu().numpy(), t.outR)
