@@ -406,12 +406,12 @@ __global__ __launch_bounds__(64) void k_rows(const int16_t* __restrict__ fin,
 // priors). A pixel takes the smallest canonical rank of the triangles whose
 // closed area contains it, or kNoOwner. One workgroup owns a band of pixel
 // rows of one view and keeps its owners in an LDS tile: it gathers the
-// triangles whose rows overlap the band into LDS (canonical order sorts
-// triangles by their top vertex, so the scan stops at the first triangle
-// starting below the band), computes the exact integer span of each of their
-// band rows from the three edge functions, spreads the span pixels over the
-// threads, resolves each pixel with an LDS atomicMin, and finally writes the
-// whole tile with coalesced stores. Every pixel of the image is written.
+// triangles whose rows overlap the band (canonical order sorts triangles by
+// their top vertex, so the scan stops at the first triangle starting below
+// the band), computes the exact integer span of each of their band rows from
+// the three edge functions, spreads each wave's span pixels evenly over its
+// lanes, resolves each pixel with an LDS atomicMin, and finally writes the
+// whole tile with coalesced stores. Every pixel is written.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int floordiv_pos(int a, int b) {  // b > 0
   return a >= 0 ? a / b : -((-a + b - 1) / b);
@@ -429,9 +429,11 @@ __device__ __forceinline__ void clip_edge(int k, int c, int* lo, int* hi) {
 }
 
 constexpr int kRasterThreads = 256;
-constexpr int kRasterTile = 8192;  // LDS owner tile: band rows x width
-constexpr int kRasterList = 512;   // triangles gathered per pass
+constexpr int kRasterTile = 8192;   // LDS owner tile: band rows x width
+constexpr int kRasterScan = 8;      // triangles tested per thread and gather step
+constexpr int kRasterList = 4096;   // ranks of gathered triangles per pass
 constexpr int kBandRowsMax = 4;
+constexpr int kWaveSpan = 64 * (2 + 2 * kBandRowsMax);  // per-wave span table in LDS
 
 // Band height for an image width: at most four rows, tile within kRasterTile.
 inline int raster_band_rows(int w) { return std::max(1, std::min(kBandRowsMax, 4096 / w)); }
@@ -442,13 +444,8 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(const RasterTri* __re
                                                            int32_t* __restrict__ ownerL,
                                                            int32_t* __restrict__ ownerR) {
   __shared__ int32_t tile[kRasterTile];
-  __shared__ RasterTri list[kRasterList];
-  __shared__ int32_t lrank[kRasterList];
-  __shared__ int32_t pre[kRasterThreads + 1];
-  __shared__ int32_t sp_lo[kBandRowsMax][kRasterThreads];
-  __shared__ int32_t sp_len[kBandRowsMax][kRasterThreads];
-  __shared__ int32_t sp_rank[kRasterThreads];
-  __shared__ int32_t wsum[kRasterThreads / 64];
+  __shared__ int32_t rlist[kRasterList];
+  __shared__ int32_t wspan[(kRasterThreads / 64) * kWaveSpan];
   __shared__ int s_cnt, s_done;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int nb = (g.h + band_rows - 1) / band_rows;
@@ -456,11 +453,12 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(const RasterTri* __re
   const int view = lb >= nb ? 1 : 0, band = lb - view * nb;
   const int v0 = band * band_rows, v1 = min(g.h - 1, v0 + band_rows - 1);
   const int rows = v1 - v0 + 1;
-  const int ntL = hdr->ntri[0], nt = view ? hdr->ntri[1] : ntL, base = view ? ntL : 0;
+  const int ntL = hdr->ntri[0], nt = view ? hdr->ntri[1] : ntL;
+  const RasterTri* vt = tris + (view ? ntL : 0);
   for (int i = tid; i < rows * g.w; i += kRasterThreads) tile[i] = kNoOwner;
   int r0 = 0;
   for (;;) {
-    // gather the next triangles overlapping the band
+    // gather the ranks of the next triangles whose rows overlap the band
     if (tid == 0) {
       s_cnt = 0;
       s_done = 0;
@@ -468,29 +466,38 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(const RasterTri* __re
     __syncthreads();
     int cnt = 0, done = 0;
     while (r0 < nt) {
-      const int r = r0 + tid;
-      if (r < nt) {
-        const RasterTri T = tris[base + r];
-        const int vmin = min((int)T.v[0], min((int)T.v[1], (int)T.v[2]));
-        const int vmax = max((int)T.v[0], max((int)T.v[1], (int)T.v[2]));
-        if (vmin > v1) {
-          s_done = 1;  // so does every later triangle
-        } else if (vmax >= v0) {
-          const int slot = atomicAdd(&s_cnt, 1);
-          list[slot] = T;
-          lrank[slot] = r;
+      int16_t tv[kRasterScan][3];
+#pragma unroll
+      for (int k = 0; k < kRasterScan; ++k) {
+        const int r = r0 + k * kRasterThreads + tid;
+        if (r < nt) {
+          tv[k][0] = vt[r].v[0];
+          tv[k][1] = vt[r].v[1];
+          tv[k][2] = vt[r].v[2];
         }
       }
-      r0 += kRasterThreads;
+#pragma unroll
+      for (int k = 0; k < kRasterScan; ++k) {
+        const int r = r0 + k * kRasterThreads + tid;
+        if (r >= nt) continue;
+        const int vmin = min((int)tv[k][0], min((int)tv[k][1], (int)tv[k][2]));
+        const int vmax = max((int)tv[k][0], max((int)tv[k][1], (int)tv[k][2]));
+        if (vmin > v1)
+          s_done = 1;  // so does every later triangle
+        else if (vmax >= v0)
+          rlist[atomicAdd(&s_cnt, 1)] = r;
+      }
+      r0 += kRasterScan * kRasterThreads;
       __syncthreads();
       cnt = s_cnt;
       done = s_done;
       __syncthreads();
-      if (done || cnt > kRasterList - kRasterThreads) break;
+      if (done || cnt > kRasterList - kRasterScan * kRasterThreads) break;
     }
-    // rasterise the gathered triangles into the tile
+    // rasterise the gathered triangles into the tile; consecutive entries go
+    // to different waves
     for (int e0 = 0; e0 < cnt; e0 += kRasterThreads) {
-      const int e = e0 + tid;
+      const int e = e0 + (lane << 2) + wid;
       int lo[kBandRowsMax], len[kBandRowsMax], tot = 0, rank = 0;
 #pragma unroll
       for (int q = 0; q < kBandRowsMax; ++q) {
@@ -498,8 +505,8 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(const RasterTri* __re
         len[q] = 0;
       }
       if (e < cnt) {
-        const RasterTri T = list[e];
-        rank = lrank[e];
+        rank = rlist[e];
+        const RasterTri T = vt[rank];
         // vertices lie in the image; the clamp only keeps every write inside it
         const int umin = max(0, min((int)T.u[0], min((int)T.u[1], (int)T.u[2])));
         const int umax = min(g.w - 1, max((int)T.u[0], max((int)T.u[1], (int)T.u[2])));
@@ -521,43 +528,60 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(const RasterTri* __re
           tot += len[q];
         }
       }
-      // exclusive scan of the per-thread pixel counts
+      // the wave's spans, lane by lane and row by row, form one pixel range;
+      // each lane takes a contiguous share of it, finds its first span with
+      // a binary search over the lanes' offsets and walks on from there
       int incl = tot;
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         const int y = __shfl_up(incl, off, 64);
         if (lane >= off) incl += y;
       }
-      if (lane == 63) wsum[wid] = incl;
-      __syncthreads();
-      int before = 0, all = 0;
-#pragma unroll
-      for (int w2 = 0; w2 < kRasterThreads / 64; ++w2) {
-        before += w2 < wid ? wsum[w2] : 0;
-        all += wsum[w2];
-      }
-      pre[tid] = before + incl - tot;
+      const int P = __shfl(incl, 63, 64);
+      int32_t* W = wspan + wid * kWaveSpan;  // [offsets 64][lo 64x4][len 64x4][rank 64]
+      W[lane] = incl - tot;
 #pragma unroll
       for (int q = 0; q < kBandRowsMax; ++q) {
-        sp_lo[q][tid] = lo[q];
-        sp_len[q][tid] = len[q];
+        W[64 + 4 * lane + q] = lo[q];
+        W[320 + 4 * lane + q] = len[q];
       }
-      sp_rank[tid] = rank;
-      __syncthreads();
-      for (int i = tid; i < all; i += kRasterThreads) {
-        int a = 0, b = kRasterThreads - 1;  // last thread whose pixels start at or before i
+      W[576 + lane] = rank;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int C = (P + 63) >> 6;
+      int i = lane * C;
+      const int iend = min(P, i + C);
+      if (i < iend) {
+        int a = 0, b = 63;  // last lane whose pixels start at or before i
         while (a < b) {
           const int mid = (a + b + 1) >> 1;
-          if (pre[mid] <= i) a = mid; else b = mid - 1;
+          if (W[mid] <= i) a = mid; else b = mid - 1;
         }
-        int off = i - pre[a], q = 0;
-        while (off >= sp_len[q][a]) {
-          off -= sp_len[q][a];
+        int j = a, off = i - W[a], q = 0;
+        while (off >= W[320 + 4 * j + q]) {
+          off -= W[320 + 4 * j + q];
           ++q;
         }
-        atomicMin(&tile[q * g.w + sp_lo[q][a] + off], sp_rank[a]);
+        int L = W[320 + 4 * j + q], S = W[64 + 4 * j + q], R = W[576 + j];
+        for (;;) {
+          atomicMin(&tile[q * g.w + S + off], R);
+          if (++i >= iend) break;
+          if (++off == L) {  // on to the next non-empty span (one exists: i < P)
+            off = 0;
+            do {
+              if (++q == kBandRowsMax) {
+                q = 0;
+                ++j;
+              }
+              L = W[320 + 4 * j + q];
+            } while (L == 0);
+            S = W[64 + 4 * j + q];
+            R = W[576 + j];
+          }
+        }
       }
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
     }
     if (done || r0 >= nt) break;
   }
