@@ -147,6 +147,52 @@ ELAS_API int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* ri
                           int32_t w, int32_t h_px, int32_t stride, hipStream_t stream,
                           int16_t* disp_left, int16_t* disp_right);
 
+/* One stereo pair of a batch (all pointers device memory, caller-owned). */
+typedef struct elas_pair {
+  const uint8_t* left;          /* uint8, h rows of `stride` bytes */
+  const uint8_t* right;
+  int32_t w, h, stride;         /* as for elas_process */
+  int16_t* disp_left;           /* int16 [h][w] outputs */
+  int16_t* disp_right;
+  elas_handle* params;          /* NULL: the batch handle's parameters; otherwise
+                                   this handle's (e.g. another disparity range) */
+} elas_pair;
+
+/* Flags of elas_process_batch (elas_set_batch_flags; both set by default). */
+enum elas_batch_flags {
+  ELAS_BATCH_GRAPH = 1,         /* capture each batch shape's launches in a HIP graph
+                                   once and replay it */
+  ELAS_BATCH_AUTOTUNE = 2       /* on the first batch with a new (w, h, D), time the
+                                   descriptor (4/8/16 rows per block) and dense (4/8/16
+                                   gathers in flight) tile variants on its frames and
+                                   keep the fastest; results are identical for all */
+};
+ELAS_API int elas_set_batch_flags(elas_handle* h, int32_t flags);
+
+/* Computes n pairs of possibly different sizes and disparity ranges with one
+ * launch per stage (and tile variant) for the whole batch: every stage's
+ * kernel covers the workgroups of all frames, a workgroup finds its frame in
+ * a device table (uploaded by the call from pinned memory), and the two mesh
+ * workgroups of every frame run side by side. Equivalent, pair by pair, to
+ * elas_process with the pair's parameters; bit-identical outputs. Buffers
+ * come from per-(size, stream) pools in the pair's parameter handle, so
+ * batches on different streams run concurrently; a batch reuses them only
+ * after the stream has passed the previous batch. Pairs the device mesh
+ * cannot take (a side above 4096, or mesh_on_host) are processed by
+ * elas_process on the same stream first. Stream-ordered; the call returns
+ * after enqueueing, except for the autotuning pass (synchronous, once per new
+ * size). The handle is used by one host thread at a time.
+ * Errors: ELAS_ERR_ARG (null handle, n < 0, a null pointer or bad size in a
+ * pair, with the pair's index in elas_last_error), ELAS_ERR_OOM, ELAS_ERR_HIP. */
+ELAS_API int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs,
+                                hipStream_t stream);
+
+/* Tile variants the autotuner chose for (w, h) at this handle's disparity
+ * count: descriptor rows per block and dense gathers in flight.
+ * ELAS_ERR_ARG if none has been chosen yet. */
+ELAS_API int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t h_px,
+                                     int32_t* desc_rows, int32_t* dense_batch);
+
 /* Copies the counters of the last elas_process call (synchronises with its
  * stream first). */
 ELAS_API int elas_get_stats(elas_handle* h, elas_stats* out);

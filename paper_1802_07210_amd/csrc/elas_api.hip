@@ -119,6 +119,23 @@ struct Buffers {
   size_t up_cap = 0;
 };
 
+// Per (handle, stream) state of batched calls: the device frame tables and
+// launch prefixes, two pinned staging buffers (each reused only after its
+// upload has run), a capture stream and the graphs captured per batch shape.
+struct BatchCtx {
+  void* dev = nullptr;
+  size_t dev_cap = 0;
+  void* host[2] = {nullptr, nullptr};
+  size_t host_cap[2] = {0, 0};
+  hipEvent_t done[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+  int next = 0;
+  hipStream_t capture = nullptr;
+  std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+  void* tune_dev = nullptr;
+  size_t tune_cap = 0;
+};
+
 }  // namespace
 
 struct elas_handle {
@@ -147,6 +164,13 @@ struct elas_handle {
   bool timing = false;
   bool have_timing = false;
   hipEvent_t tev[kStageEvents] = {};
+  // batches: per-stream frame tables and graphs, per-(size, stream) buffer
+  // pools, tile variants chosen by the autotuner per (w, h, D)
+  int32_t batch_flags = ELAS_BATCH_GRAPH | ELAS_BATCH_AUTOTUNE;
+  std::map<hipStream_t, BatchCtx*> batch;
+  std::map<std::tuple<int32_t, int32_t, hipStream_t>, std::vector<Buffers*>> pool;
+  std::map<std::tuple<int32_t, int32_t, int32_t>, std::pair<int, int>> tuned;
+  hipStream_t tune_stream = nullptr;
 };
 
 namespace {
@@ -196,13 +220,7 @@ Geometry make_geometry(const elas_params& p, int32_t w, int32_t h) {
   return g;
 }
 
-int get_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, Buffers** out) {
-  const auto key = std::make_tuple(w, hp, stream);
-  auto it = h->cache.find(key);
-  if (it != h->cache.end()) {
-    *out = it->second;
-    return ELAS_OK;
-  }
+int alloc_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   Buffers* b = new Buffers();
   b->g = make_geometry(h->params, w, hp);
   const Geometry& g = b->g;
@@ -298,9 +316,94 @@ int get_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, Buffe
     free_buffers(b);
     return fail_hip(h, "hipMemcpy of the prior table", e);
   }
-  h->cache[key] = b;
   *out = b;
   return ELAS_OK;
+}
+
+// The buffers of single calls on one stream.
+int get_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, Buffers** out) {
+  const auto key = std::make_tuple(w, hp, stream);
+  auto it = h->cache.find(key);
+  if (it != h->cache.end()) {
+    *out = it->second;
+    return ELAS_OK;
+  }
+  const int rc = alloc_buffers(h, w, hp, out);
+  if (rc == ELAS_OK) h->cache[key] = *out;
+  return rc;
+}
+
+// The slot-th buffer set of a batch for one (size, stream).
+int pool_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, size_t slot,
+                 Buffers** out) {
+  std::vector<Buffers*>& v = h->pool[std::make_tuple(w, hp, stream)];
+  while (v.size() <= slot) {
+    Buffers* b = nullptr;
+    const int rc = alloc_buffers(h, w, hp, &b);
+    if (rc != ELAS_OK) return rc;
+    v.push_back(b);
+  }
+  *out = v[slot];
+  return ELAS_OK;
+}
+
+// Tile variants (descriptor, dense) for a frame size and disparity count:
+// the autotuner's choice, else the defaults.
+std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp, int32_t D) {
+  auto it = h->tuned.find(std::make_tuple(w, hp, D));
+  return it != h->tuned.end() ? it->second : std::make_pair(0, 1);
+}
+
+std::pair<int, int> variants_for(const elas_handle* h, int32_t w, int32_t hp) {
+  return variants_lookup(h, w, hp, h->kp.D);
+}
+
+Frame make_frame(const elas_handle* h, const Buffers* b, const uint8_t* left,
+                 const uint8_t* right, int32_t stride, int16_t* outL, int16_t* outR,
+                 bool host_lists) {
+  Frame f{};
+  f.g = b->g;
+  f.p = h->kp;
+  f.stride = stride;
+  f.raster_rows = raster_band_rows(b->g.w);
+  f.left = left;
+  f.right = right;
+  f.descL = b->descL;
+  f.descR = b->descR;
+  f.dcan_raw = b->dcan_raw;
+  f.dcan_incon = b->dcan_incon;
+  f.dcan_vert = b->dcan_vert;
+  f.dcan_final = b->dcan_final;
+  f.evals = b->evals;
+  f.gridL = b->gridL;
+  f.gridR = b->gridR;
+  f.rowsL = host_lists ? b->hrowL_dev : b->rowsL;
+  f.rowsR = host_lists ? b->hrowR_dev : b->rowsR;
+  f.cnt = host_lists ? b->hcnt_dev : b->cnt;
+  f.hdr = b->hdr;
+  f.ptsL = b->ptsL;
+  f.ptsR = b->ptsR;
+  f.recsL = b->recsL;
+  f.recsR = b->recsR;
+  f.planesL = b->planesL;
+  f.planesR = b->planesR;
+  f.tris = b->tris;
+  f.mesh_scratch = b->mesh_scratch;
+  f.mesh_scratch_per_view =
+      (b->g.w <= kDeviceMeshMaxSide && b->g.h <= kDeviceMeshMaxSide)
+          ? mesh_global_scratch_per_view(b->g)
+          : 0;
+  f.ownerL = b->ownerL;
+  f.ownerR = b->ownerR;
+  f.dplaneL = b->dplaneL;
+  f.dplaneR = b->dplaneR;
+  f.rawL = b->rawL;
+  f.rawR = b->rawR;
+  f.lut = b->lut;
+  f.dense_counts = b->dense_counts;
+  f.outL = outL;
+  f.outR = outR;
+  return f;
 }
 
 int ensure_upload(elas_handle* h, Buffers* b, size_t bytes) {
@@ -528,8 +631,22 @@ int elas_create(const elas_params* p, elas_handle** out) {
 
 int elas_destroy(elas_handle* h) {
   if (!h) return ELAS_OK;
-  if (h->have_result) (void)hipStreamSynchronize(h->last_stream);
+  if (!h->cache.empty() || !h->pool.empty()) (void)hipDeviceSynchronize();
   for (auto& kv : h->cache) free_buffers(kv.second);
+  for (auto& kv : h->pool)
+    for (Buffers* b : kv.second) free_buffers(b);
+  for (auto& kv : h->batch) {
+    BatchCtx* c = kv.second;
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    for (int k = 0; k < 2; ++k) {
+      if (c->done[k]) (void)hipEventDestroy(c->done[k]);
+      if (c->host[k]) (void)hipHostFree(c->host[k]);
+    }
+    if (c->dev) (void)hipFree(c->dev);
+    if (c->tune_dev) (void)hipFree(c->tune_dev);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    delete c;
+  }
   if (h->ev_lists) (void)hipEventDestroy(h->ev_lists);
   if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
   for (hipEvent_t& e : h->tev)
@@ -564,8 +681,6 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   Buffers* b = nullptr;
   int rc = get_buffers(h, w, hp, stream, &b);
   if (rc != ELAS_OK) return rc;
-  const Geometry& g = b->g;
-  const KParams& kp = h->kp;
   h->have_result = false;
   h->have_timing = false;
   h->last = b;
@@ -578,42 +693,313 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
 #define STAGE_MARK(i) \
   if (timed) HIP_TRY(hipEventRecord(h->tev[i], stream))
 
+  const Frame F = make_frame(h, b, left, right, stride, disp_left, disp_right, on_host);
+  const std::pair<int, int> var = variants_for(h, w, hp);
   STAGE_MARK(0);
-  HIP_TRY(launch_descriptor(left, right, stride, g, b->descL, b->descR, stream));
+  HIP_TRY(launch_stage(kStageDescriptor, F, var.first, stream));
   STAGE_MARK(1);
-  HIP_TRY(launch_support(b->descL, b->descR, g, kp, b->dcan_raw, b->evals, stream));
+  HIP_TRY(launch_stage(kStageSupport, F, 0, stream));
   STAGE_MARK(2);
-  HIP_TRY(launch_filter(b->dcan_raw, g, kp, b->dcan_incon, b->dcan_vert, b->dcan_final,
-                        b->gridL, b->gridR, stream));
+  HIP_TRY(launch_stage(kStageFilter, F, 0, stream));
   STAGE_MARK(3);
+  HIP_TRY(launch_stage(kStageRows, F, 0, stream));
+  STAGE_MARK(4);
   if (on_host) {
-    HIP_TRY(launch_rows(b->dcan_final, b->evals, g, kp, b->hrowL_dev, b->hrowR_dev, b->hcnt_dev,
-                        b->gridL, b->gridR, stream));
-    STAGE_MARK(4);
     rc = host_mesh_step(h, b, stream);
     if (rc != ELAS_OK) return rc;
   } else {
-    HIP_TRY(launch_rows(b->dcan_final, b->evals, g, kp, b->rowsL, b->rowsR, b->cnt, b->gridL,
-                        b->gridR, stream));
-    STAGE_MARK(4);
-    HIP_TRY(launch_mesh(b->rowsL, b->rowsR, b->cnt, g, kp.dmin, b->hdr, b->ptsL, b->ptsR,
-                        b->recsL, b->recsR, b->planesL, b->planesR, b->tris,
-                        b->mesh_scratch, stream));
+    HIP_TRY(launch_stage(kStageMesh, F, 0, stream));
   }
   STAGE_MARK(5);
-  HIP_TRY(launch_raster(b->tris, b->hdr, g, b->ownerL, b->ownerR, stream));
+  HIP_TRY(launch_stage(kStageRaster, F, 0, stream));
   STAGE_MARK(6);
-  HIP_TRY(launch_dense(b->descL, b->descR, b->ownerL, b->ownerR, b->tris, b->hdr, b->gridL,
-                       b->gridR, b->lut, g, kp, b->dplaneL, b->dplaneR, b->rawL, b->rawR,
-                       b->dense_counts, stream));
+  HIP_TRY(launch_stage(kStageDense, F, var.second, stream));
   STAGE_MARK(7);
-  HIP_TRY(launch_lrcheck(b->rawL, b->rawR, g, kp, disp_left, disp_right, stream));
+  HIP_TRY(launch_stage(kStageCheck, F, 0, stream));
   STAGE_MARK(8);
 #undef STAGE_MARK
   h->have_timing = timed;
   h->have_result = true;
   return ELAS_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// One launch of a batch: a stage (and tile variant) over a table of frames.
+struct LaunchRec {
+  int32_t stage, variant, nf, total;
+  size_t table_off, starts_off, lds;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int batch_ctx(elas_handle* h, hipStream_t stream, BatchCtx** out) {
+  auto it = h->batch.find(stream);
+  if (it != h->batch.end()) {
+    *out = it->second;
+    return ELAS_OK;
+  }
+  BatchCtx* c = new BatchCtx();
+  for (int k = 0; k < 2; ++k)
+    HIP_TRY(hipEventCreateWithFlags(&c->done[k], hipEventDisableTiming));
+  HIP_TRY(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+  h->batch[stream] = c;
+  *out = c;
+  return ELAS_OK;
+}
+
+// Frame tables and block prefixes of every launch, in one blob.
+void plan_batch(const std::vector<Frame>& frames, const std::vector<std::pair<int, int>>& var,
+                std::vector<LaunchRec>* recs, std::vector<uint8_t>* blob) {
+  recs->clear();
+  blob->clear();
+  auto put = [&](const void* p, size_t bytes) {
+    const size_t off = blob->size();
+    blob->resize(align256(off + bytes));
+    std::memcpy(blob->data() + off, p, bytes);
+    return off;
+  };
+  const size_t main_table = put(frames.data(), frames.size() * sizeof(Frame));
+  for (int32_t st = 0; st < kStageCount; ++st) {
+    const bool tiled = st == kStageDescriptor || st == kStageDense;
+    for (int v = 0; v < (tiled ? 3 : 1); ++v) {
+      std::vector<Frame> sub;
+      std::vector<int32_t> starts(1, 0);
+      size_t lds = 0;
+      for (size_t i = 0; i < frames.size(); ++i) {
+        const int fv = st == kStageDescriptor ? var[i].first : var[i].second;
+        if (tiled && fv != v) continue;
+        const int dv = st == kStageDescriptor ? v : 0;
+        sub.push_back(frames[i]);
+        starts.push_back(starts.back() + stage_blocks(st, frames[i].g, dv));
+        lds = std::max(lds, stage_lds(st, frames[i].g, frames[i].p));
+      }
+      if (sub.empty()) continue;
+      LaunchRec r{};
+      r.stage = st;
+      r.variant = v;
+      r.nf = (int32_t)sub.size();
+      r.total = starts.back();
+      r.lds = lds;
+      r.table_off = tiled ? put(sub.data(), sub.size() * sizeof(Frame)) : main_table;
+      r.starts_off = put(starts.data(), starts.size() * sizeof(int32_t));
+      recs->push_back(r);
+    }
+  }
+}
+
+hipError_t enqueue_batch(const std::vector<LaunchRec>& recs, uint8_t* dev, hipStream_t s) {
+  for (const LaunchRec& r : recs) {
+    const hipError_t e = launch_stage_batch(
+        r.stage, reinterpret_cast<const Frame*>(dev + r.table_off),
+        reinterpret_cast<const int32_t*>(dev + r.starts_off), r.nf, r.total, r.lds, r.variant, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Times the descriptor and dense tile variants on this batch's frames of one
+// (w, h, D) and keeps the fastest of each (the stages recompute identical
+// outputs, so the batch's results are unaffected).
+int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
+             hipStream_t stream, std::pair<int, int>* best) {
+  HIP_TRY(hipStreamSynchronize(stream));
+  const size_t need = align256(frames.size() * sizeof(Frame)) + align256((frames.size() + 1) * 4);
+  if (need > c->tune_cap) {
+    if (c->tune_dev) HIP_TRY(hipFree(c->tune_dev));
+    c->tune_dev = nullptr;
+    c->tune_cap = 0;
+    HIP_TRY(hipMalloc(&c->tune_dev, need));
+    c->tune_cap = need;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int choice[2] = {0, 1};
+  const int32_t stages[2] = {kStageDescriptor, kStageDense};
+  for (int k = 0; k < 2; ++k) {
+    float best_ms = 1e30f;
+    for (int v = 0; v < 3; ++v) {
+      std::vector<int32_t> starts(1, 0);
+      for (const Frame& f : frames)
+        starts.push_back(starts.back() + stage_blocks(stages[k], f.g, k == 0 ? v : 0));
+      uint8_t* dev = static_cast<uint8_t*>(c->tune_dev);
+      const size_t soff = align256(frames.size() * sizeof(Frame));
+      HIP_TRY(hipMemcpy(dev, frames.data(), frames.size() * sizeof(Frame), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(dev + soff, starts.data(), starts.size() * 4, hipMemcpyHostToDevice));
+      size_t lds = 0;
+      for (const Frame& f : frames) lds = std::max(lds, stage_lds(stages[k], f.g, f.p));
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIP_TRY(hipEventRecord(e0, stream));
+        HIP_TRY(launch_stage_batch(stages[k], reinterpret_cast<const Frame*>(dev),
+                                   reinterpret_cast<const int32_t*>(dev + soff),
+                                   (int32_t)frames.size(), starts.back(), lds, v, stream));
+        HIP_TRY(hipEventRecord(e1, stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms_min = std::min(ms_min, ms);
+      }
+      if (ms_min < best_ms) {
+        best_ms = ms_min;
+        choice[k] = v;
+      }
+    }
+  }
+  HIP_TRY(hipEventDestroy(e0));
+  HIP_TRY(hipEventDestroy(e1));
+  *best = std::make_pair(choice[0], choice[1]);
+  return ELAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int elas_set_batch_flags(elas_handle* h, int32_t flags) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  if (flags & ~(ELAS_BATCH_GRAPH | ELAS_BATCH_AUTOTUNE))
+    return fail(h, ELAS_ERR_ARG, "unknown batch flags");
+  h->batch_flags = flags;
+  return ELAS_OK;
+}
+
+int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStream_t stream) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  if (n < 0 || (n > 0 && !pairs)) return fail(h, ELAS_ERR_ARG, "bad pair array");
+  for (int32_t i = 0; i < n; ++i) {
+    const elas_pair& q = pairs[i];
+    if (!q.left || !q.right || !q.disp_left || !q.disp_right)
+      return fail(h, ELAS_ERR_ARG, "null image or output pointer in pair " + std::to_string(i));
+    if (q.w < 9 || q.h < 9 || q.w > 8192 || q.h > 8192 || q.stride < q.w)
+      return fail(h, ELAS_ERR_ARG, "bad size or stride in pair " + std::to_string(i));
+  }
+  // pairs the device mesh cannot take go through single calls (host mesh)
+  std::vector<int32_t> dev_idx;
+  for (int32_t i = 0; i < n; ++i) {
+    const elas_pair& q = pairs[i];
+    elas_handle* ph = q.params ? q.params : h;
+    if (ph->params.mesh_on_host || q.w > kDeviceMeshMaxSide || q.h > kDeviceMeshMaxSide) {
+      const int rc = elas_process(ph, q.left, q.right, q.w, q.h, q.stride, stream, q.disp_left,
+                                  q.disp_right);
+      if (rc != ELAS_OK) return fail(h, rc, std::string("pair ") + std::to_string(i) + ": " +
+                                                elas_last_error(ph));
+    } else {
+      dev_idx.push_back(i);
+    }
+  }
+  if (dev_idx.empty()) return ELAS_OK;
+  std::vector<Frame> frames;
+  std::vector<std::pair<int, int>> var;
+  std::map<std::tuple<elas_handle*, int32_t, int32_t>, size_t> slots;
+  for (int32_t i : dev_idx) {
+    const elas_pair& q = pairs[i];
+    elas_handle* ph = q.params ? q.params : h;
+    size_t& slot = slots[std::make_tuple(ph, q.w, q.h)];
+    Buffers* b = nullptr;
+    int rc = pool_buffers(ph, q.w, q.h, stream, slot++, &b);
+    if (rc != ELAS_OK) return fail(h, rc, elas_last_error(ph));
+    frames.push_back(make_frame(ph, b, q.left, q.right, q.stride, q.disp_left, q.disp_right,
+                                false));
+    var.push_back(variants_lookup(h, q.w, q.h, ph->kp.D));
+  }
+  BatchCtx* c = nullptr;
+  int rc = batch_ctx(h, stream, &c);
+  if (rc != ELAS_OK) return rc;
+  std::vector<LaunchRec> recs;
+  std::vector<uint8_t> blob;
+  plan_batch(frames, var, &recs, &blob);
+  if (blob.size() > c->dev_cap) {  // grow the device tables; captured graphs refer to them
+    HIP_TRY(hipDeviceSynchronize());
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    if (c->dev) HIP_TRY(hipFree(c->dev));
+    c->dev = nullptr;
+    c->dev_cap = 0;
+    const size_t cap = align256(blob.size() * 2);
+    HIP_TRY(hipMalloc(&c->dev, cap));
+    c->dev_cap = cap;
+  }
+  const int k = c->next;
+  c->next ^= 1;
+  if (c->pending[k]) HIP_TRY(hipEventSynchronize(c->done[k]));
+  c->pending[k] = false;
+  if (blob.size() > c->host_cap[k]) {
+    if (c->host[k]) HIP_TRY(hipHostFree(c->host[k]));
+    c->host[k] = nullptr;
+    c->host_cap[k] = 0;
+    const size_t cap = align256(blob.size() * 2);
+    HIP_TRY(hipHostMalloc(&c->host[k], cap, hipHostMallocDefault));
+    c->host_cap[k] = cap;
+  }
+  std::memcpy(c->host[k], blob.data(), blob.size());
+  HIP_TRY(hipMemcpyAsync(c->dev, c->host[k], blob.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(c->done[k], stream));
+  c->pending[k] = true;
+  uint8_t* dev = static_cast<uint8_t*>(c->dev);
+  if (h->batch_flags & ELAS_BATCH_GRAPH) {
+    std::vector<int64_t> sig;
+    sig.push_back((int64_t)(uintptr_t)dev);
+    for (const LaunchRec& r : recs) {
+      sig.push_back(r.stage);
+      sig.push_back(r.variant);
+      sig.push_back(r.nf);
+      sig.push_back(r.total);
+      sig.push_back((int64_t)r.lds);
+      sig.push_back((int64_t)r.table_off);
+      sig.push_back((int64_t)r.starts_off);
+    }
+    auto it = c->graphs.find(sig);
+    if (it == c->graphs.end()) {
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+      const hipError_t le = enqueue_batch(recs, dev, c->capture);
+      const hipError_t ce = hipStreamEndCapture(c->capture, &graph);
+      if (le != hipSuccess) return fail_hip(h, "batch launch during capture", le);
+      if (ce != hipSuccess) return fail_hip(h, "hipStreamEndCapture", ce);
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) return fail_hip(h, "hipGraphInstantiate", ie);
+      it = c->graphs.emplace(sig, exec).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, stream));
+  } else {
+    HIP_TRY(enqueue_batch(recs, dev, stream));
+  }
+  if (h->batch_flags & ELAS_BATCH_AUTOTUNE) {
+    std::map<std::tuple<int32_t, int32_t, int32_t>, std::vector<Frame>> groups;
+    for (const Frame& f : frames) {
+      const auto key = std::make_tuple(f.g.w, f.g.h, f.p.D);
+      if (!h->tuned.count(key)) groups[key].push_back(f);
+    }
+    for (auto& kv : groups) {
+      std::pair<int, int> best;
+      rc = autotune(h, c, kv.second, stream, &best);
+      if (rc != ELAS_OK) return rc;
+      h->tuned[kv.first] = best;
+    }
+  }
+  return ELAS_OK;
+}
+
+int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t hp, int32_t* desc_rows,
+                            int32_t* dense_batch) {
+  if (!h || !desc_rows || !dense_batch) return fail(h, ELAS_ERR_ARG, "null argument");
+  auto it = h->tuned.find(std::make_tuple(w, hp, h->kp.D));
+  if (it == h->tuned.end()) return fail(h, ELAS_ERR_ARG, "no tuned variants for this size");
+  static const int32_t rows[3] = {4, 8, 16}, batch[3] = {4, 8, 16};
+  *desc_rows = rows[it->second.first];
+  *dense_batch = batch[it->second.second];
+  return ELAS_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 int elas_set_timing(elas_handle* h, int32_t enable) {
   if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");

@@ -71,45 +71,137 @@ int32_t build_mesh(MeshScratch* s, const int32_t* pts, int32_t n, const int32_t*
                    int32_t w, int32_t h, RasterTri* tri_out, int32_t* recs_out,
                    float* planes_out);
 
-// ---- kernel launchers (elas_kernels.hip) ---------------------------------
-hipError_t launch_descriptor(const uint8_t* left, const uint8_t* right, int32_t stride,
-                             const Geometry& g, uint8_t* descL, uint8_t* descR, hipStream_t s);
-hipError_t launch_support(const uint8_t* descL, const uint8_t* descR, const Geometry& g,
-                          const KParams& p, int16_t* dcan, int32_t* evals, hipStream_t s);
-// Fused consistency + redundancy filters; also clears the grid masks.
-size_t filter_lds_bytes(const KParams& p);
-hipError_t launch_filter(const int16_t* raw, const Geometry& g, const KParams& p,
-                         int16_t* incon, int16_t* vert, int16_t* fin, uint32_t* gridL,
-                         uint32_t* gridR, hipStream_t s);
-// Per-row support lists into host-mapped memory (hrowL/hrowR: [lh][lw] packed
-// u | d << 16; hcnt: left counts, right counts, evaluation counts, lh each)
-// and the grid masks.
-hipError_t launch_rows(const int16_t* fin, const int32_t* evals, const Geometry& g,
-                       const KParams& p, int32_t* hrowL, int32_t* hrowR, int32_t* hcnt,
-                       uint32_t* gridL, uint32_t* gridR, hipStream_t s);
-// Device mesh of both views (elas_mesh_device.hip), for frames with both
-// sides at most kDeviceMeshMaxSide. rowsL/rowsR/cnt as written by k_rows;
-// outputs the header, the gathered lists (ptsL/ptsR, (u,v,d) triples),
-// canonical records and planes per view, and the combined raster records
-// (left view first). gscratch: 2 * mesh_global_scratch_per_view bytes, used
-// only when a view does not fit in LDS.
+// ---- one frame as the kernels see it -------------------------------------
+// Sizes, parameters and every device array of one stereo pair. Passed by
+// value to the single-frame kernels and read from a device table by the
+// batched ones.
+struct Frame {
+  Geometry g;
+  KParams p;
+  int32_t stride;        // row pitch of the input images
+  int32_t raster_rows;   // band height of the raster
+  const uint8_t* left;
+  const uint8_t* right;
+  uint8_t* descL;
+  uint8_t* descR;
+  int16_t* dcan_raw;
+  int16_t* dcan_incon;
+  int16_t* dcan_vert;
+  int16_t* dcan_final;
+  int32_t* evals;
+  uint32_t* gridL;
+  uint32_t* gridR;
+  int32_t* rowsL;        // per-row lists [lh][lw], packed u | d << 16
+  int32_t* rowsR;
+  int32_t* cnt;          // left counts, right counts, evaluation counts [3][lh]
+  MeshHeader* hdr;
+  int32_t* ptsL;
+  int32_t* ptsR;
+  int32_t* recsL;
+  int32_t* recsR;
+  float* planesL;
+  float* planesR;
+  RasterTri* tris;
+  char* mesh_scratch;
+  uint64_t mesh_scratch_per_view;
+  int32_t* ownerL;
+  int32_t* ownerR;
+  int16_t* dplaneL;
+  int16_t* dplaneR;
+  int16_t* rawL;
+  int16_t* rawR;
+  const int32_t* lut;
+  int32_t* dense_counts;  // candidate evaluations per dense block
+  int16_t* outL;
+  int16_t* outR;
+};
+
+// Pointers read from the frame table are rebuilt as offsets from the table's
+// own address (a kernel argument, so a global-memory pointer): the compiler
+// then emits global rather than flat memory instructions for them.
+template <class T>
+__device__ __forceinline__ T* rebase(const char* base, T* p) {
+  return reinterpret_cast<T*>(const_cast<char*>(base) + ((uintptr_t)p - (uintptr_t)base));
+}
+
+__device__ __forceinline__ Frame global_frame(const Frame& t, const char* base) {
+  Frame F = t;
+  F.left = rebase(base, F.left);
+  F.right = rebase(base, F.right);
+  F.descL = rebase(base, F.descL);
+  F.descR = rebase(base, F.descR);
+  F.dcan_raw = rebase(base, F.dcan_raw);
+  F.dcan_incon = rebase(base, F.dcan_incon);
+  F.dcan_vert = rebase(base, F.dcan_vert);
+  F.dcan_final = rebase(base, F.dcan_final);
+  F.evals = rebase(base, F.evals);
+  F.gridL = rebase(base, F.gridL);
+  F.gridR = rebase(base, F.gridR);
+  F.rowsL = rebase(base, F.rowsL);
+  F.rowsR = rebase(base, F.rowsR);
+  F.cnt = rebase(base, F.cnt);
+  F.hdr = rebase(base, F.hdr);
+  F.ptsL = rebase(base, F.ptsL);
+  F.ptsR = rebase(base, F.ptsR);
+  F.recsL = rebase(base, F.recsL);
+  F.recsR = rebase(base, F.recsR);
+  F.planesL = rebase(base, F.planesL);
+  F.planesR = rebase(base, F.planesR);
+  F.tris = rebase(base, F.tris);
+  F.mesh_scratch = rebase(base, F.mesh_scratch);
+  F.ownerL = rebase(base, F.ownerL);
+  F.ownerR = rebase(base, F.ownerR);
+  F.dplaneL = rebase(base, F.dplaneL);
+  F.dplaneR = rebase(base, F.dplaneR);
+  F.rawL = rebase(base, F.rawL);
+  F.rawR = rebase(base, F.rawR);
+  F.lut = rebase(base, F.lut);
+  F.dense_counts = rebase(base, F.dense_counts);
+  F.outL = rebase(base, F.outL);
+  F.outR = rebase(base, F.outR);
+  return F;
+}
+
+// Stages of the path, in launch order.
+enum Stage : int32_t {
+  kStageDescriptor = 0,
+  kStageSupport,
+  kStageFilter,
+  kStageRows,
+  kStageMesh,
+  kStageRaster,
+  kStageDense,
+  kStageCheck,
+  kStageCount
+};
+
+// Tile variants the autotuner chooses between (identical results).
+constexpr int kDescVariants = 3;   // descriptor rows per block: 4, 8, 16
+constexpr int kDenseVariants = 3;  // dense candidate gathers in flight: 4, 8, 16
+
+// Workgroups one frame needs for a stage (descriptor variant dv).
+int32_t stage_blocks(int32_t stage, const Geometry& g, int dv);
+// Dynamic LDS bytes of a stage for a frame (0 if none).
+size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p);
+// Band height of the raster for an image width.
+int32_t raster_band_rows(int32_t w);
+
+// One stage of one frame.
+hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t s);
+// One stage of nf frames in one launch: frames and starts (nf + 1 prefix of
+// the per-frame block counts) in device memory; lds: the largest per-frame
+// dynamic LDS.
+hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
+                              int32_t nf, int32_t total_blocks, size_t lds, int variant,
+                              hipStream_t s);
+
+// The mesh stage (elas_mesh_device.hip): two workgroups per frame, for
+// frames with both sides at most kDeviceMeshMaxSide.
+hipError_t launch_mesh_frame(const Frame& f, hipStream_t s);
+hipError_t launch_mesh_batch(const Frame* frames, int32_t nf, hipStream_t s);
+// Device mesh scratch per view (views that do not fit in LDS).
 size_t mesh_global_scratch_per_view(const Geometry& g);
-hipError_t launch_mesh(const int32_t* rowsL, const int32_t* rowsR, const int32_t* cnt,
-                       const Geometry& g, int32_t dmin, MeshHeader* hdr, int32_t* ptsL,
-                       int32_t* ptsR, int32_t* recsL, int32_t* recsR, float* planesL,
-                       float* planesR, RasterTri* tris, char* gscratch, hipStream_t s);
-// Owner maps of both views (every pixel written; kNoOwner where no triangle).
-hipError_t launch_raster(const RasterTri* tris, const MeshHeader* hdr, const Geometry& g,
-                         int32_t* ownerL, int32_t* ownerR, hipStream_t s);
-hipError_t launch_dense(const uint8_t* descL, const uint8_t* descR, const int32_t* ownerL,
-                        const int32_t* ownerR, const RasterTri* tris, const MeshHeader* hdr,
-                        const uint32_t* gridL, const uint32_t* gridR, const int32_t* lut,
-                        const Geometry& g, const KParams& p,
-                        int16_t* dplaneL, int16_t* dplaneR, int16_t* rawL, int16_t* rawR,
-                        int32_t* dense_counts, hipStream_t s);
 // Blocks of the dense launch (one candidate-count entry per block).
 int32_t dense_blocks(const Geometry& g);
-hipError_t launch_lrcheck(const int16_t* rawL, const int16_t* rawR, const Geometry& g,
-                          const KParams& p, int16_t* outL, int16_t* outR, hipStream_t s);
 
 }  // namespace elas

@@ -1,6 +1,6 @@
 // HIP kernels of the ELAS hot path for gfx950 (MI355X).
 //
-// Data layout in HBM, per image size (one handle, one size):
+// Data layout in HBM, per frame (arrays carved from one allocation):
 //   images       uint8  [h][stride]            caller-owned
 //   descriptors  uint8  [h][w][16]             one 16-byte descriptor per pixel
 //   lattice      int16  [lh][lw]               support disparity per candidate
@@ -11,12 +11,19 @@
 // byte differences accumulated per instruction). Minima over disparities use
 // packed keys (energy << 8 | d - dmin), so any evaluation order gives the
 // smallest energy with the smallest disparity on ties.
+//
+// Every stage is a device function of (frame, frame-local block index). Two
+// kernels call it: one for a single frame (the frame passed by value), one
+// for a batch of frames in a single launch (frames in a device table; a
+// block finds its frame in the prefix of the per-frame block counts).
 #include <algorithm>
 
 #include "elas_internal.h"
 
 namespace elas {
 namespace {
+
+extern __shared__ __align__(16) char dyn_smem[];
 
 __device__ __forceinline__ uint4 ld16(const uint8_t* p) {
   return *reinterpret_cast<const uint4*>(p);
@@ -56,6 +63,19 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
+// Frame of logical block b in a batch: the last frame starting at or before b.
+__device__ __forceinline__ int frame_of(const int32_t* __restrict__ starts, int nf, int b) {
+  int lo = 0, hi = nf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (starts[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+__host__ __device__ __forceinline__ int cdivd(int a, int b) { return (a + b - 1) / b; }
+
 // Gradient quantisation: divide by 4 truncating toward zero, clamp to
 // [-127, 127], offset by 128 (bytes 1..255; a negated gradient maps b to 256-b).
 __device__ __forceinline__ uint32_t quantise(int g) {
@@ -67,40 +87,38 @@ __device__ __forceinline__ uint32_t quantise(int g) {
 // ---------------------------------------------------------------------------
 // Stage 1: 3x3 Sobel gradients and the 16-byte descriptor (Section III-A,
 // Fig. 1(b); Section VI-A: a 16-byte subset of the window's gradients).
-// Block = 64 x 4 pixels. The image tile with a 3-pixel halo is staged in LDS,
-// the quantised gradients of the tile with a 2-pixel halo are computed once
-// into LDS, and each thread gathers its 16 bytes and writes one 16-byte
-// store (a wave writes 1 KiB contiguous).
+// Block = 64 columns x TH rows (256 threads, TH/4 rows each). The image tile
+// with a 3-pixel halo is staged in LDS, the quantised gradients of the tile
+// with a 2-pixel halo are computed once into LDS, and each thread gathers its
+// 16 bytes and writes one 16-byte store (a wave writes 1 KiB contiguous).
 // Sample pattern (column, row offsets): du at (-2,0) (-1,0) (1,0) (2,0)
 // (-1,-2) (1,-2) (-1,2) (1,2); dv at (0,-2) (0,-1) (0,1) (0,2) (-2,-1) (2,-1)
 // (-2,1) (2,1). Descriptors are defined for 2 <= u <= w-3, 2 <= v <= h-3 and
 // all-zero elsewhere.
 // ---------------------------------------------------------------------------
-constexpr int kDescW = 64, kDescH = 4;
+constexpr int kDescW = 64;
+constexpr int kDescRows[kDescVariants] = {4, 8, 16};
 
-__global__ __launch_bounds__(256) void k_descriptor(const uint8_t* __restrict__ left,
-                                                    const uint8_t* __restrict__ right,
-                                                    int32_t stride, Geometry g,
-                                                    uint8_t* __restrict__ descL,
-                                                    uint8_t* __restrict__ descR) {
-  // logical block: (tile row, tile column, view), views interleaved
-  const int nbx = (g.w + kDescW - 1) / kDescW;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int view = lb & 1, tile_id = lb >> 1;
-  const uint8_t* img = view ? right : left;
-  uint8_t* desc = view ? descR : descL;
-  __shared__ uint8_t tile[kDescH + 6][kDescW + 8];
-  __shared__ uint8_t qdu[kDescH + 4][kDescW + 4];
-  __shared__ uint8_t qdv[kDescH + 4][kDescW + 4];
-  const int u0 = (tile_id % nbx) * kDescW, v0 = (tile_id / nbx) * kDescH;
-  const int tid = threadIdx.y * kDescW + threadIdx.x;
-  for (int i = tid; i < (kDescH + 6) * (kDescW + 6); i += 256) {
+template <int TH>
+__device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
+  const Geometry g = F.g;
+  const int nbx = cdivd(g.w, kDescW);
+  const int view = lb & 1, tile_id = lb >> 1;  // views interleaved
+  const uint8_t* img = view ? F.right : F.left;
+  uint8_t* desc = view ? F.descR : F.descL;
+  const int stride = F.stride;
+  __shared__ uint8_t tile[TH + 6][kDescW + 8];
+  __shared__ uint8_t qdu[TH + 4][kDescW + 4];
+  __shared__ uint8_t qdv[TH + 4][kDescW + 4];
+  const int u0 = (tile_id % nbx) * kDescW, v0 = (tile_id / nbx) * TH;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < (TH + 6) * (kDescW + 6); i += 256) {
     const int r = i / (kDescW + 6), c = i - r * (kDescW + 6);
     const int y = v0 - 3 + r, x = u0 - 3 + c;
     tile[r][c] = (x >= 0 && x < g.w && y >= 0 && y < g.h) ? img[(size_t)y * stride + x] : 0;
   }
   __syncthreads();
-  for (int i = tid; i < (kDescH + 4) * (kDescW + 4); i += 256) {
+  for (int i = tid; i < (TH + 4) * (kDescW + 4); i += 256) {
     const int r = i / (kDescW + 4), c = i - r * (kDescW + 4);
     const int y = v0 - 2 + r, x = u0 - 2 + c;
     int gx = 0, gy = 0;
@@ -116,22 +134,28 @@ __global__ __launch_bounds__(256) void k_descriptor(const uint8_t* __restrict__ 
     qdv[r][c] = (uint8_t)quantise(gy);
   }
   __syncthreads();
-  const int u = u0 + threadIdx.x, v = v0 + threadIdx.y;
-  if (u >= g.w || v >= g.h) return;
-  uint4 out = make_uint4(0u, 0u, 0u, 0u);
-  if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
-    const int r = threadIdx.y + 2, c = threadIdx.x + 2;
-    out.x = qdu[r][c - 2] | (qdu[r][c - 1] << 8) | (qdu[r][c + 1] << 16) |
-            ((uint32_t)qdu[r][c + 2] << 24);
-    out.y = qdu[r - 2][c - 1] | (qdu[r - 2][c + 1] << 8) | (qdu[r + 2][c - 1] << 16) |
-            ((uint32_t)qdu[r + 2][c + 1] << 24);
-    out.z = qdv[r - 2][c] | (qdv[r - 1][c] << 8) | (qdv[r + 1][c] << 16) |
-            ((uint32_t)qdv[r + 2][c] << 24);
-    out.w = qdv[r - 1][c - 2] | (qdv[r - 1][c + 2] << 8) | (qdv[r + 1][c - 2] << 16) |
-            ((uint32_t)qdv[r + 1][c + 2] << 24);
+  const int tx = tid & 63;
+  const int u = u0 + tx;
+  if (u >= g.w) return;
+#pragma unroll
+  for (int ty = tid >> 6; ty < TH; ty += 4) {
+    const int v = v0 + ty;
+    if (v >= g.h) break;
+    uint4 out = make_uint4(0u, 0u, 0u, 0u);
+    if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
+      const int r = ty + 2, c = tx + 2;
+      out.x = qdu[r][c - 2] | (qdu[r][c - 1] << 8) | (qdu[r][c + 1] << 16) |
+              ((uint32_t)qdu[r][c + 2] << 24);
+      out.y = qdu[r - 2][c - 1] | (qdu[r - 2][c + 1] << 8) | (qdu[r + 2][c - 1] << 16) |
+              ((uint32_t)qdu[r + 2][c + 1] << 24);
+      out.z = qdv[r - 2][c] | (qdv[r - 1][c] << 8) | (qdv[r + 1][c] << 16) |
+              ((uint32_t)qdv[r + 2][c] << 24);
+      out.w = qdv[r - 1][c - 2] | (qdv[r - 1][c + 2] << 8) | (qdv[r + 1][c - 2] << 16) |
+              ((uint32_t)qdv[r + 1][c + 2] << 24);
+    }
+    const size_t px = (size_t)v * g.w + u;
+    *reinterpret_cast<uint4*>(desc + px * 16) = out;
   }
-  const size_t px = (size_t)v * g.w + u;
-  *reinterpret_cast<uint4*>(desc + px * 16) = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -165,9 +189,10 @@ __device__ __forceinline__ uint32_t texture64(const Desc64& a) {
 // Full search of one point over d = dmin..dhi (at least two values); the
 // partner column is u + dir*d. Returns whether the ratio test accepts and the
 // best disparity. Control flow is wavefront-uniform.
-__device__ bool support_search(const Desc64& self, const uint8_t* __restrict__ other, int w,
-                               int u, int v, int dir, int dhi, const KParams& p, int lane,
-                               int* d_best) {
+__device__ __forceinline__ bool support_search(const Desc64& self,
+                                               const uint8_t* __restrict__ other, int w, int u,
+                                               int v, int dir, int dhi, const KParams& p,
+                                               int lane, int* d_best) {
   uint32_t cost[kMaxD / 64];
   uint32_t best = 0xFFFFFFFFu;
   const int nj = (dhi - p.dmin + 64) >> 6;
@@ -195,16 +220,16 @@ __device__ bool support_search(const Desc64& self, const uint8_t* __restrict__ o
   return (float)m1 < __fmul_rn(p.support_threshold, (float)m2);
 }
 
-__global__ __launch_bounds__(256) void k_support(const uint8_t* __restrict__ descL,
-                                                 const uint8_t* __restrict__ descR, Geometry g,
-                                                 KParams p, int16_t* __restrict__ dcan,
-                                                 int32_t* __restrict__ evals) {
+__device__ __forceinline__ void support_body(const Frame& F, int lb) {
+  const Geometry g = F.g;
+  const KParams p = F.p;
   const int lane = threadIdx.x & 63;
-  const int pt = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 +
-                                                (threadIdx.x >> 6));
+  const int pt = __builtin_amdgcn_readfirstlane(lb * 4 + (threadIdx.x >> 6));
   if (pt >= g.lw * g.lh) return;
   const int l = pt / g.lw, k = pt - l * g.lw;
   const int u = g.lu0 + k * g.step, v = g.lv0 + l * g.step;
+  const uint8_t* descL = F.descL;
+  const uint8_t* descR = F.descR;
   int result = -1, ev = 0;
   const Desc64 ls = load_support(descL, g.w, u, v);
   if ((int)texture64(ls) >= p.support_texture) {
@@ -227,8 +252,8 @@ __global__ __launch_bounds__(256) void k_support(const uint8_t* __restrict__ des
     }
   }
   if (lane == 0) {
-    dcan[pt] = (int16_t)result;
-    evals[pt] = ev;
+    F.dcan_raw[pt] = (int16_t)result;
+    F.evals[pt] = ev;
   }
 }
 
@@ -245,29 +270,36 @@ __global__ __launch_bounds__(256) void k_support(const uint8_t* __restrict__ des
 // The tile's raw values are staged in LDS with a halo of incon_window +
 // redun_max_dist; each pass is computed on the region the next pass reads
 // (positions outside the lattice count as empty). The kernel also clears the
-// grid masks that k_rows fills.
+// grid masks that the rows stage fills.
 // ---------------------------------------------------------------------------
 constexpr int kFT = 16;
 
-__global__ __launch_bounds__(1024) void k_filter(const int16_t* __restrict__ raw, Geometry g,
-                                                KParams p, int16_t* __restrict__ incon_out,
-                                                int16_t* __restrict__ vert_out,
-                                                int16_t* __restrict__ fin_out,
-                                                uint32_t* __restrict__ gridL,
-                                                uint32_t* __restrict__ gridR) {
-  extern __shared__ int16_t smem[];
+__host__ __device__ __forceinline__ int filter_tiles_x(const Geometry& g) {
+  return g.lw > 0 ? cdivd(g.lw, kFT) : 1;
+}
+__host__ __device__ __forceinline__ int filter_tiles_y(const Geometry& g) {
+  return g.lh > 0 ? cdivd(g.lh, kFT) : 1;
+}
+
+__device__ __forceinline__ void filter_body(const Frame& F, int lb) {
+  const Geometry g = F.g;
+  const KParams p = F.p;
+  int16_t* smem = reinterpret_cast<int16_t*>(dyn_smem);
   const int ri = p.incon_window, rr = p.redun_max_dist;
   const int SR = kFT + 2 * (ri + rr), SI = kFT + 2 * rr;
   int16_t* sraw = smem;            // SR x SR, origin (l0-ri-rr, k0-ri-rr)
   int16_t* sinc = sraw + SR * SR;  // SI x SI, origin (l0-rr, k0-rr)
   int16_t* svert = sinc + SI * SI; // kFT x SI, origin (l0, k0-rr)
-  const int k0 = blockIdx.x * kFT, l0 = blockIdx.y * kFT;
+  const int ntx = filter_tiles_x(g), nblk = ntx * filter_tiles_y(g);
+  const int k0 = (lb % ntx) * kFT, l0 = (lb / ntx) * kFT;
   const int tid = threadIdx.x;
-  // clear the grid masks (grid-stride over all blocks)
+  const int16_t* raw = F.dcan_raw;
+  // clear the grid masks (grid-stride over the frame's blocks)
   {
     const int gcount = g.gw * g.gh * g.gwords;
-    const int nthreads = gridDim.x * gridDim.y * 1024;
-    for (int i = (blockIdx.y * gridDim.x + blockIdx.x) * 1024 + tid; i < gcount; i += nthreads) {
+    uint32_t* gridL = F.gridL;
+    uint32_t* gridR = F.gridR;
+    for (int i = lb * 1024 + tid; i < gcount; i += nblk * 1024) {
       gridL[i] = 0u;
       gridR[i] = 0u;
     }
@@ -328,16 +360,16 @@ __global__ __launch_bounds__(1024) void k_filter(const int16_t* __restrict__ raw
         if (before && after) res = -1;
       }
       const size_t idx = (size_t)l * g.lw + k;
-      incon_out[idx] = sinc[(y + rr) * SI + x + rr];
-      vert_out[idx] = (int16_t)d;
-      fin_out[idx] = (int16_t)res;
+      F.dcan_incon[idx] = sinc[(y + rr) * SI + x + rr];
+      F.dcan_vert[idx] = (int16_t)d;
+      F.dcan_final[idx] = (int16_t)res;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Support lists per lattice row, one wavefront per row, written straight to
-// host-mapped memory for the host mesh step, plus the grid vectors.
+// Support lists per lattice row, one wavefront per row (for the mesh step;
+// host-mapped memory when the host triangulates), plus the grid vectors.
 //  * left list: the row's survivors in lattice order, packed u | d << 16;
 //  * right list (each point seen from the right view at (u - d, v); on
 //    collisions the larger d, the nearer surface, wins): an LDS slot per
@@ -347,25 +379,26 @@ __global__ __launch_bounds__(1024) void k_filter(const int16_t* __restrict__ raw
 //    list point are OR-ed into its region's mask, per view;
 //  * the row's support-search evaluation count.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_rows(const int16_t* __restrict__ fin,
-                                             const int32_t* __restrict__ evals, Geometry g,
-                                             KParams p, int32_t* __restrict__ hrowL,
-                                             int32_t* __restrict__ hrowR,
-                                             int32_t* __restrict__ hcnt,
-                                             uint32_t* __restrict__ gridL,
-                                             uint32_t* __restrict__ gridR) {
-  extern __shared__ int32_t slot[];  // one per image column
-  const int l = blockIdx.x, lane = threadIdx.x;
+__device__ __forceinline__ void rows_body(const Frame& F, int lb) {
+  const Geometry g = F.g;
+  const KParams p = F.p;
+  int32_t* slot = reinterpret_cast<int32_t*>(dyn_smem);  // one per image column
+  const int l = lb, lane = threadIdx.x;
   const int v = g.lv0 + l * g.step;
   const int grow = (v / p.grid_size) * g.gw;
+  int32_t* hrowL = F.rowsL;
+  int32_t* hrowR = F.rowsR;
+  uint32_t* gridL = F.gridL;
+  uint32_t* gridR = F.gridR;
   for (int x = lane; x < g.w; x += 64) slot[x] = -1;
   __syncthreads();
   int nL = 0, ev = 0;
-  const int16_t* frow = fin + (size_t)l * g.lw;
+  const int16_t* frow = F.dcan_final + (size_t)l * g.lw;
+  const int32_t* erow = F.evals + (size_t)l * g.lw;
   for (int k0 = 0; k0 < g.lw; k0 += 64) {
     const int k = k0 + lane;
     const int d = k < g.lw ? frow[k] : -1;
-    ev += k < g.lw ? evals[(size_t)l * g.lw + k] : 0;
+    ev += k < g.lw ? erow[k] : 0;
     const unsigned long long m = __ballot(d >= 0);
     if (d >= 0) {
       const int u = g.lu0 + k * g.step;
@@ -395,9 +428,9 @@ __global__ __launch_bounds__(64) void k_rows(const int16_t* __restrict__ fin,
   }
   ev = wave_sum(ev);
   if (lane == 0) {
-    hcnt[l] = nL;
-    hcnt[g.lh + l] = nR;
-    hcnt[2 * g.lh + l] = ev;
+    F.cnt[l] = nL;
+    F.cnt[g.lh + l] = nR;
+    F.cnt[2 * g.lh + l] = ev;
   }
 }
 
@@ -435,26 +468,20 @@ constexpr int kRasterList = 4096;   // ranks of gathered triangles per pass
 constexpr int kBandRowsMax = 4;
 constexpr int kWaveSpan = 64 * (2 + 2 * kBandRowsMax);  // per-wave span table in LDS
 
-// Band height for an image width: at most four rows, tile within kRasterTile.
-inline int raster_band_rows(int w) { return std::max(1, std::min(kBandRowsMax, 4096 / w)); }
-
-__global__ __launch_bounds__(kRasterThreads) void k_raster(const RasterTri* __restrict__ tris,
-                                                           const MeshHeader* __restrict__ hdr,
-                                                           Geometry g, int band_rows,
-                                                           int32_t* __restrict__ ownerL,
-                                                           int32_t* __restrict__ ownerR) {
+__device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   __shared__ int32_t tile[kRasterTile];
   __shared__ int32_t rlist[kRasterList];
   __shared__ int32_t wspan[(kRasterThreads / 64) * kWaveSpan];
   __shared__ int s_cnt, s_done;
+  const Geometry g = F.g;
+  const int band_rows = F.raster_rows;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int nb = (g.h + band_rows - 1) / band_rows;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int nb = cdivd(g.h, band_rows);
   const int view = lb >= nb ? 1 : 0, band = lb - view * nb;
   const int v0 = band * band_rows, v1 = min(g.h - 1, v0 + band_rows - 1);
   const int rows = v1 - v0 + 1;
-  const int ntL = hdr->ntri[0], nt = view ? hdr->ntri[1] : ntL;
-  const RasterTri* vt = tris + (view ? ntL : 0);
+  const int ntL = F.hdr->ntri[0], nt = view ? F.hdr->ntri[1] : ntL;
+  const RasterTri* vt = F.tris + (view ? ntL : 0);
   for (int i = tid; i < rows * g.w; i += kRasterThreads) tile[i] = kNoOwner;
   int r0 = 0;
   for (;;) {
@@ -586,19 +613,19 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(const RasterTri* __re
     if (done || r0 >= nt) break;
   }
   __syncthreads();
-  int32_t* owner = (view ? ownerR : ownerL) + (size_t)v0 * g.w;
+  int32_t* owner = (view ? F.ownerR : F.ownerL) + (size_t)v0 * g.w;
   for (int i = tid; i < rows * g.w; i += kRasterThreads) owner[i] = tile[i];
 }
 
 // ---------------------------------------------------------------------------
-// Dense matching (Section III-A, Fig. 1(h)). One thread per pixel; blockIdx.y
-// selects the view. The prior disparity is the owning triangle's plane mean
-// ((a*u) + (b*v)) + c in FP32 without contraction, rounded as
-// floor(mean + 0.5) and clamped. Candidates: the plane window, the grid
-// region's one-hot mask (or every d with full_search), restricted to
+// Dense matching (Section III-A, Fig. 1(h)). One thread per pixel, views
+// interleaved per 256-pixel block. The prior disparity is the owning
+// triangle's plane mean ((a*u) + (b*v)) + c in FP32 without contraction,
+// rounded as floor(mean + 0.5) and clamped. Candidates: the plane window, the
+// grid region's one-hot mask (or every d with full_search), restricted to
 // partners with a defined descriptor. Energy: descriptor SAD plus the prior
 // table at |d - d_plane|. Argmin by packed key. Candidates are taken from
-// the 64-bit masks eight at a time so that their descriptor gathers are in
+// the 64-bit masks KB at a time so that their descriptor gathers are in
 // flight together.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t bits64_between(int a, int b) {
@@ -609,37 +636,30 @@ __device__ __forceinline__ uint64_t bits64_between(int a, int b) {
   return hi & ~((1ull << a) - 1ull);
 }
 
-constexpr int kBatch = 8;  // candidate gathers issued together per lane
-
-__global__ __launch_bounds__(256) void k_dense(
-    const uint8_t* __restrict__ descL, const uint8_t* __restrict__ descR,
-    const int32_t* __restrict__ ownerL, const int32_t* __restrict__ ownerR,
-    const RasterTri* __restrict__ tris, const MeshHeader* __restrict__ hdr,
-    const uint32_t* __restrict__ gridL, const uint32_t* __restrict__ gridR,
-    const int32_t* __restrict__ lut, Geometry g, KParams p, int16_t* __restrict__ dplaneL,
-    int16_t* __restrict__ dplaneR,
-    int16_t* __restrict__ rawL, int16_t* __restrict__ rawR,
-    int32_t* __restrict__ dense_counts) {
+template <int KB>
+__device__ __forceinline__ void dense_body(const Frame& F, int lb) {
   __shared__ int32_t s_lut[kMaxD];
   __shared__ int s_cnt[4];
+  const Geometry g = F.g;
+  const KParams p = F.p;
+  const int32_t* lut = F.lut;
   for (int i = threadIdx.x; i < p.D; i += 256) s_lut[i] = lut[i];
   __syncthreads();
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);  // views interleaved per pixel block
   const bool right = (lb & 1) != 0;
-  const int ntL = hdr->ntri[0];
-  const bool has_list = hdr->n[0] > 0;
+  const int ntL = F.hdr->ntri[0];
+  const bool has_list = F.hdr->n[0] > 0;
   const int npx = g.w * g.h;
   const int px = (lb >> 1) * 256 + threadIdx.x;
   int cnt = 0;
   if (px < npx) {
     const int v = px / g.w, u = px - v * g.w;
-    const uint8_t* self_desc = right ? descR : descL;
-    const uint8_t* other_desc = right ? descL : descR;
+    const uint8_t* self_desc = right ? F.descR : F.descL;
+    const uint8_t* other_desc = right ? F.descL : F.descR;
     int dp = -1;
     if (has_list) {
-      const int o = (right ? ownerR : ownerL)[px];
+      const int o = (right ? F.ownerR : F.ownerL)[px];
       if (o != kNoOwner) {
-        const RasterTri t = tris[o + (right ? ntL : 0)];
+        const RasterTri t = F.tris[o + (right ? ntL : 0)];
         const float au = __fmul_rn(t.a, (float)u);
         const float bv = __fmul_rn(t.b, (float)v);
         const float mu = __fadd_rn(__fadd_rn(au, bv), t.c);
@@ -647,7 +667,7 @@ __global__ __launch_bounds__(256) void k_dense(
         dp = f < (float)p.dmin ? p.dmin : (f > (float)p.dmax ? p.dmax : (int)f);
       }
     }
-    (right ? dplaneR : dplaneL)[px] = (int16_t)dp;
+    (right ? F.dplaneR : F.dplaneL)[px] = (int16_t)dp;
     int res = -1;
     if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
       const uint4 s = ld16(self_desc + (size_t)px * 16);
@@ -659,7 +679,7 @@ __global__ __launch_bounds__(256) void k_dense(
         const int nw = min(g.gwords >> 1, (top >> 6) + 1);  // 64-bit words in play
         const uint64_t* cell =
             has_list ? reinterpret_cast<const uint64_t*>(
-                           (right ? gridR : gridL) +
+                           (right ? F.gridR : F.gridL) +
                            ((size_t)(v / p.grid_size) * g.gw + u / p.grid_size) * g.gwords)
                      : nullptr;
         uint64_t cw[kMaxD / 64];
@@ -674,10 +694,10 @@ __global__ __launch_bounds__(256) void k_dense(
           uint64_t m = (p.full_search ? ~0ull : 0ull) | cw[j] | bits64_between(lo - base, hi - base);
           m &= bits64_between(0, top - base);
           while (m) {
-            int dd[kBatch];
-            uint4 o[kBatch];
+            int dd[KB];
+            uint4 o[KB];
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t) {
+            for (int t = 0; t < KB; ++t) {
               dd[t] = -1;
               if (m) {
                 dd[t] = base + __builtin_ctzll(m);
@@ -685,13 +705,13 @@ __global__ __launch_bounds__(256) void k_dense(
               }
             }
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t)
+            for (int t = 0; t < KB; ++t)
               if (dd[t] >= 0) {
                 const int d = p.dmin + dd[t];
                 o[t] = ld16(orow + (size_t)(right ? u + d : u - d) * 16);
               }
 #pragma unroll
-            for (int t = 0; t < kBatch; ++t)
+            for (int t = 0; t < KB; ++t)
               if (dd[t] >= 0) {
                 const int d = p.dmin + dd[t];
                 int E = (int)sad16(s, o[t]);
@@ -704,115 +724,187 @@ __global__ __launch_bounds__(256) void k_dense(
         if (best != 0xFFFFFFFFu) res = p.dmin + (int)(best & 0xFFu);
       }
     }
-    (right ? rawR : rawL)[px] = (int16_t)res;
+    (right ? F.rawR : F.rawL)[px] = (int16_t)res;
   }
   cnt = wave_sum(cnt);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
-  if (threadIdx.x == 0) dense_counts[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+  if (threadIdx.x == 0) F.dense_counts[lb] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
 }
 
 // ---------------------------------------------------------------------------
 // Final left/right consistency check (Section III-A: occlusions invalidated).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_lrcheck(const int16_t* __restrict__ rawL,
-                                                 const int16_t* __restrict__ rawR, Geometry g,
-                                                 KParams p, int16_t* __restrict__ outL,
-                                                 int16_t* __restrict__ outR) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void check_body(const Frame& F, int lb) {
+  const Geometry g = F.g;
+  const int thr = F.p.lr_threshold;
   const int px = (lb >> 1) * 256 + threadIdx.x;
   if (px >= g.w * g.h) return;
   const int v = px / g.w, u = px - v * g.w;
   const size_t row = (size_t)v * g.w;
   if ((lb & 1) == 0) {
-    const int d = rawL[px];
+    const int d = F.rawL[px];
     int r = -1;
     if (d >= 0 && u - d >= 0) {
-      const int e = rawR[row + u - d];
-      if (e >= 0 && abs(e - d) <= p.lr_threshold) r = d;
+      const int e = F.rawR[row + u - d];
+      if (e >= 0 && abs(e - d) <= thr) r = d;
     }
-    outL[px] = (int16_t)r;
+    F.outL[px] = (int16_t)r;
   } else {
-    const int d = rawR[px];
+    const int d = F.rawR[px];
     int r = -1;
     if (d >= 0 && u + d < g.w) {
-      const int e = rawL[row + u + d];
-      if (e >= 0 && abs(e - d) <= p.lr_threshold) r = d;
+      const int e = F.rawL[row + u + d];
+      if (e >= 0 && abs(e - d) <= thr) r = d;
     }
-    outR[px] = (int16_t)r;
+    F.outR[px] = (int16_t)r;
   }
 }
 
-inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+// ---- kernels: one frame, or a batch in one launch --------------------------
+#define ELAS_STAGE_KERNELS(NAME, BODY, THREADS)                                         \
+  __global__ __launch_bounds__(THREADS) void NAME(Frame F) {                            \
+    BODY(F, xcd_remap(blockIdx.x, gridDim.x));                                          \
+  }                                                                                     \
+  __global__ __launch_bounds__(THREADS) void NAME##_batch(                              \
+      const Frame* __restrict__ frames, const int32_t* __restrict__ starts, int nf) {   \
+    const int b = xcd_remap(blockIdx.x, gridDim.x);                                     \
+    const int f = frame_of(starts, nf, b);                                              \
+    const Frame F = global_frame(frames[f], reinterpret_cast<const char*>(frames));     \
+    BODY(F, b - starts[f]);                                                             \
+  }
 
-}  // namespace
+ELAS_STAGE_KERNELS(k_descriptor4, descriptor_body<4>, 256)
+ELAS_STAGE_KERNELS(k_descriptor8, descriptor_body<8>, 256)
+ELAS_STAGE_KERNELS(k_descriptor16, descriptor_body<16>, 256)
+ELAS_STAGE_KERNELS(k_support, support_body, 256)
+ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
+ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
+ELAS_STAGE_KERNELS(k_raster, raster_body, kRasterThreads)
+ELAS_STAGE_KERNELS(k_dense4, dense_body<4>, 256)
+ELAS_STAGE_KERNELS(k_dense8, dense_body<8>, 256)
+ELAS_STAGE_KERNELS(k_dense16, dense_body<16>, 256)
+ELAS_STAGE_KERNELS(k_check, check_body, 256)
 
-hipError_t launch_descriptor(const uint8_t* left, const uint8_t* right, int32_t stride,
-                             const Geometry& g, uint8_t* descL, uint8_t* descR, hipStream_t s) {
-  dim3 grid(2 * cdiv(g.w, kDescW) * cdiv(g.h, kDescH)), block(kDescW, kDescH, 1);
-  hipLaunchKernelGGL(k_descriptor, grid, block, 0, s, left, right, stride, g, descL, descR);
-  return hipGetLastError();
-}
-
-hipError_t launch_support(const uint8_t* descL, const uint8_t* descR, const Geometry& g,
-                          const KParams& p, int16_t* dcan, int32_t* evals, hipStream_t s) {
-  const int n = g.lw * g.lh;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_support, dim3(cdiv(n, 4)), dim3(256), 0, s, descL, descR, g, p, dcan,
-                     evals);
-  return hipGetLastError();
-}
+#undef ELAS_STAGE_KERNELS
 
 size_t filter_lds_bytes(const KParams& p) {
   const int SR = kFT + 2 * (p.incon_window + p.redun_max_dist), SI = kFT + 2 * p.redun_max_dist;
   return sizeof(int16_t) * (size_t)(SR * SR + SI * SI + kFT * SI);
 }
 
-hipError_t launch_filter(const int16_t* raw, const Geometry& g, const KParams& p,
-                         int16_t* incon, int16_t* vert, int16_t* fin, uint32_t* gridL,
-                         uint32_t* gridR, hipStream_t s) {
-  const dim3 grid(std::max(1u, cdiv(g.lw, kFT)), std::max(1u, cdiv(g.lh, kFT)));
-  hipLaunchKernelGGL(k_filter, grid, dim3(1024), filter_lds_bytes(p), s, raw, g, p, incon, vert,
-                     fin, gridL, gridR);
+int stage_threads(int32_t stage) {
+  switch (stage) {
+    case kStageFilter: return 1024;
+    case kStageRows: return 64;
+    case kStageRaster: return kRasterThreads;
+    default: return 256;
+  }
+}
+
+}  // namespace
+
+int32_t raster_band_rows(int32_t w) { return std::max(1, std::min(kBandRowsMax, 4096 / w)); }
+
+int32_t dense_blocks(const Geometry& g) { return 2 * cdiv((long long)g.w * g.h, 256); }
+
+int32_t stage_blocks(int32_t stage, const Geometry& g, int dv) {
+  switch (stage) {
+    case kStageDescriptor:
+      return 2 * cdiv(g.w, kDescW) * cdiv(g.h, kDescRows[std::min(std::max(dv, 0), 2)]);
+    case kStageSupport: return cdiv((long long)g.lw * g.lh, 4);
+    case kStageFilter: return filter_tiles_x(g) * filter_tiles_y(g);
+    case kStageRows: return g.lh;
+    case kStageMesh: return 2;
+    case kStageRaster: return 2 * cdiv(g.h, raster_band_rows(g.w));
+    case kStageDense: return dense_blocks(g);
+    case kStageCheck: return 2 * cdiv((long long)g.w * g.h, 256);
+    default: return 0;
+  }
+}
+
+size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p) {
+  switch (stage) {
+    case kStageFilter: return filter_lds_bytes(p);
+    case kStageRows: return sizeof(int32_t) * (size_t)g.w;
+    case kStageMesh: return kMeshLdsBytes;
+    default: return 0;
+  }
+}
+
+hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t s) {
+  if (stage == kStageMesh) return launch_mesh_frame(f, s);
+  const int nb = stage_blocks(stage, f.g, variant);
+  if (nb <= 0) return hipSuccess;
+  const dim3 grid(nb), block(stage_threads(stage));
+  const size_t lds = stage_lds(stage, f.g, f.p);
+  switch (stage) {
+    case kStageDescriptor:
+      if (variant == 1)
+        hipLaunchKernelGGL(k_descriptor8, grid, block, 0, s, f);
+      else if (variant == 2)
+        hipLaunchKernelGGL(k_descriptor16, grid, block, 0, s, f);
+      else
+        hipLaunchKernelGGL(k_descriptor4, grid, block, 0, s, f);
+      break;
+    case kStageSupport: hipLaunchKernelGGL(k_support, grid, block, 0, s, f); break;
+    case kStageFilter: hipLaunchKernelGGL(k_filter, grid, block, lds, s, f); break;
+    case kStageRows: hipLaunchKernelGGL(k_rows, grid, block, lds, s, f); break;
+    case kStageRaster: hipLaunchKernelGGL(k_raster, grid, block, 0, s, f); break;
+    case kStageDense:
+      if (variant == 0)
+        hipLaunchKernelGGL(k_dense4, grid, block, 0, s, f);
+      else if (variant == 2)
+        hipLaunchKernelGGL(k_dense16, grid, block, 0, s, f);
+      else
+        hipLaunchKernelGGL(k_dense8, grid, block, 0, s, f);
+      break;
+    case kStageCheck: hipLaunchKernelGGL(k_check, grid, block, 0, s, f); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_rows(const int16_t* fin, const int32_t* evals, const Geometry& g,
-                       const KParams& p, int32_t* hrowL, int32_t* hrowR, int32_t* hcnt,
-                       uint32_t* gridL, uint32_t* gridR, hipStream_t s) {
-  if (g.lh == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows, dim3(g.lh), dim3(64), sizeof(int32_t) * (size_t)g.w, s, fin, evals,
-                     g, p, hrowL, hrowR, hcnt, gridL, gridR);
-  return hipGetLastError();
-}
-
-hipError_t launch_raster(const RasterTri* tris, const MeshHeader* hdr, const Geometry& g,
-                         int32_t* ownerL, int32_t* ownerR, hipStream_t s) {
-  const int rows = raster_band_rows(g.w);
-  const int nb = (g.h + rows - 1) / rows;
-  hipLaunchKernelGGL(k_raster, dim3(2 * nb), dim3(kRasterThreads), 0, s, tris, hdr, g, rows,
-                     ownerL, ownerR);
-  return hipGetLastError();
-}
-
-hipError_t launch_dense(const uint8_t* descL, const uint8_t* descR, const int32_t* ownerL,
-                        const int32_t* ownerR, const RasterTri* tris, const MeshHeader* hdr,
-                        const uint32_t* gridL, const uint32_t* gridR, const int32_t* lut,
-                        const Geometry& g, const KParams& p,
-                        int16_t* dplaneL, int16_t* dplaneR, int16_t* rawL, int16_t* rawR,
-                        int32_t* dense_counts, hipStream_t s) {
-  dim3 grid(dense_blocks(g));
-  hipLaunchKernelGGL(k_dense, grid, dim3(256), 0, s, descL, descR, ownerL, ownerR, tris, hdr,
-                     gridL, gridR, lut, g, p, dplaneL, dplaneR, rawL, rawR, dense_counts);
-  return hipGetLastError();
-}
-
-int32_t dense_blocks(const Geometry& g) { return 2 * (int32_t)cdiv((long long)g.w * g.h, 256); }
-
-hipError_t launch_lrcheck(const int16_t* rawL, const int16_t* rawR, const Geometry& g,
-                          const KParams& p, int16_t* outL, int16_t* outR, hipStream_t s) {
-  dim3 grid(2 * cdiv((long long)g.w * g.h, 256));
-  hipLaunchKernelGGL(k_lrcheck, grid, dim3(256), 0, s, rawL, rawR, g, p, outL, outR);
+hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
+                              int32_t nf, int32_t total_blocks, size_t lds, int variant,
+                              hipStream_t s) {
+  if (stage == kStageMesh) return launch_mesh_batch(frames, nf, s);
+  if (total_blocks <= 0 || nf <= 0) return hipSuccess;
+  const dim3 grid(total_blocks), block(stage_threads(stage));
+  switch (stage) {
+    case kStageDescriptor:
+      if (variant == 1)
+        hipLaunchKernelGGL(k_descriptor8_batch, grid, block, 0, s, frames, starts, nf);
+      else if (variant == 2)
+        hipLaunchKernelGGL(k_descriptor16_batch, grid, block, 0, s, frames, starts, nf);
+      else
+        hipLaunchKernelGGL(k_descriptor4_batch, grid, block, 0, s, frames, starts, nf);
+      break;
+    case kStageSupport:
+      hipLaunchKernelGGL(k_support_batch, grid, block, 0, s, frames, starts, nf);
+      break;
+    case kStageFilter:
+      hipLaunchKernelGGL(k_filter_batch, grid, block, lds, s, frames, starts, nf);
+      break;
+    case kStageRows:
+      hipLaunchKernelGGL(k_rows_batch, grid, block, lds, s, frames, starts, nf);
+      break;
+    case kStageRaster:
+      hipLaunchKernelGGL(k_raster_batch, grid, block, 0, s, frames, starts, nf);
+      break;
+    case kStageDense:
+      if (variant == 0)
+        hipLaunchKernelGGL(k_dense4_batch, grid, block, 0, s, frames, starts, nf);
+      else if (variant == 2)
+        hipLaunchKernelGGL(k_dense16_batch, grid, block, 0, s, frames, starts, nf);
+      else
+        hipLaunchKernelGGL(k_dense8_batch, grid, block, 0, s, frames, starts, nf);
+      break;
+    case kStageCheck:
+      hipLaunchKernelGGL(k_check_batch, grid, block, 0, s, frames, starts, nf);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

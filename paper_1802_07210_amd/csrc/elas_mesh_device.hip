@@ -779,18 +779,13 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kMT) void k_mesh(const int32_t* __restrict__ rowsL,
-                                              const int32_t* __restrict__ rowsR,
-                                              const int32_t* __restrict__ cnt, Geometry g,
-                                              int dmin, MeshHeader* hdr, int32_t* ptsL,
-                                              int32_t* ptsR, int32_t* recsL, int32_t* recsR,
-                                              float* planesL, float* planesR, RasterTri* tris,
-                                              char* gscratch, size_t gscratch_per_view,
-                                              int lds_bytes) {
+__device__ __forceinline__ void mesh_body(const Frame& F, int view) {
   extern __shared__ __align__(16) char smem[];
   __shared__ MeshShared sh;
   __shared__ int part[3][kMT / 64];
-  const int view = blockIdx.x;
+  const Geometry g = F.g;
+  const int32_t* __restrict__ cnt = F.cnt;
+  MeshHeader* hdr = F.hdr;
   const int tid = threadIdx.x;
   // point counts of both views and the support evaluations in one pass
   int x = 0, xl = 0, ev = 0, c_first = 0;
@@ -836,17 +831,28 @@ __global__ __launch_bounds__(kMT) void k_mesh(const int32_t* __restrict__ rowsL,
   }
   if (n == 0) return;
   const int tri_base = view ? 2 * nL + 2 : 0;
-  const int32_t* rows = view ? rowsR : rowsL;
-  int32_t* pts = view ? ptsR : ptsL;
-  int32_t* recs = view ? recsR : recsL;
-  float* planes = view ? planesR : planesL;
+  const int32_t* rows = view ? F.rowsR : F.rowsL;
+  int32_t* pts = view ? F.ptsR : F.ptsL;
+  int32_t* recs = view ? F.recsR : F.recsL;
+  float* planes = view ? F.planesR : F.planesL;
+  const int dmin = F.p.dmin;
   MeshMem<int16_t> probe;
-  if (2 * n + 2 < 8192 && carve<int16_t>(nullptr, n, g.lh, probe) <= (size_t)lds_bytes)
+  if (2 * n + 2 < 8192 && carve<int16_t>(nullptr, n, g.lh, probe) <= (size_t)kMeshLdsBytes)
     mesh_run<int16_t>(smem, rows, cnt + view * g.lh, c_first, n, tri_base, g, dmin, hdr, view,
-                      pts, recs, planes, tris, sh);
+                      pts, recs, planes, F.tris, sh);
   else
-    mesh_run<int32_t>(gscratch + view * gscratch_per_view, rows, cnt + view * g.lh, c_first,
-                      n, tri_base, g, dmin, hdr, view, pts, recs, planes, tris, sh);
+    mesh_run<int32_t>(F.mesh_scratch + view * F.mesh_scratch_per_view, rows,
+                      cnt + view * g.lh, c_first, n, tri_base, g, dmin, hdr, view, pts, recs,
+                      planes, F.tris, sh);
+}
+
+__global__ __launch_bounds__(kMT) void k_mesh(Frame F) { mesh_body(F, blockIdx.x); }
+
+__global__ __launch_bounds__(kMT) void k_mesh_batch(const Frame* __restrict__ frames, int nf) {
+  const int f = blockIdx.x >> 1;
+  if (f >= nf) return;
+  const Frame F = global_frame(frames[f], reinterpret_cast<const char*>(frames));
+  mesh_body(F, blockIdx.x & 1);
 }
 
 }  // namespace
@@ -857,15 +863,15 @@ size_t mesh_global_scratch_per_view(const Geometry& g) {
   return a16(carve<int32_t>(nullptr, nmax, g.lh, probe));
 }
 
-hipError_t launch_mesh(const int32_t* rowsL, const int32_t* rowsR, const int32_t* cnt,
-                       const Geometry& g, int32_t dmin, MeshHeader* hdr, int32_t* ptsL,
-                       int32_t* ptsR, int32_t* recsL, int32_t* recsR, float* planesL,
-                       float* planesR, RasterTri* tris, char* gscratch, hipStream_t s) {
-  if (g.w > kDeviceMeshMaxSide || g.h > kDeviceMeshMaxSide) return hipErrorInvalidValue;
-  const int lds = kMeshLdsBytes;
-  hipLaunchKernelGGL(k_mesh, dim3(2), dim3(kMT), lds, s, rowsL, rowsR, cnt, g, dmin, hdr, ptsL,
-                     ptsR, recsL, recsR, planesL, planesR, tris, gscratch,
-                     mesh_global_scratch_per_view(g), lds);
+hipError_t launch_mesh_frame(const Frame& f, hipStream_t s) {
+  if (f.g.w > kDeviceMeshMaxSide || f.g.h > kDeviceMeshMaxSide) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mesh, dim3(2), dim3(kMT), kMeshLdsBytes, s, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_batch(const Frame* frames, int32_t nf, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mesh_batch, dim3(2 * nf), dim3(kMT), kMeshLdsBytes, s, frames, nf);
   return hipGetLastError();
 }
 

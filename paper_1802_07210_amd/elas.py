@@ -21,7 +21,11 @@ ERRORS = {-1: "ELAS_ERR_ARG", -2: "ELAS_ERR_OOM", -3: "ELAS_ERR_HIP",
 
 EXPORTS = ("elas_params_default", "elas_create", "elas_destroy", "elas_process",
            "elas_get_stats", "elas_last_error", "elas_get_intermediate", "elas_triangulate",
-           "elas_set_timing", "elas_get_timing")
+           "elas_set_timing", "elas_get_timing", "elas_set_batch_flags", "elas_process_batch",
+           "elas_get_tuned_variants")
+
+BATCH_GRAPH = 1
+BATCH_AUTOTUNE = 2
 
 
 class ElasParams(C.Structure):
@@ -53,6 +57,15 @@ class ElasTiming(C.Structure):
         ("rows_ms", C.c_float), ("mesh_ms", C.c_float), ("raster_ms", C.c_float),
         ("dense_ms", C.c_float), ("lrcheck_ms", C.c_float), ("device_span_ms", C.c_float),
         ("host_wait_ms", C.c_double), ("host_mesh_ms", C.c_double),
+    ]
+
+
+class ElasPair(C.Structure):
+    _fields_ = [
+        ("left", C.c_void_p), ("right", C.c_void_p),
+        ("w", C.c_int32), ("h", C.c_int32), ("stride", C.c_int32),
+        ("disp_left", C.c_void_p), ("disp_right", C.c_void_p),
+        ("params", C.c_void_p),
     ]
 
 
@@ -98,6 +111,10 @@ def lib() -> C.CDLL:
         L.elas_triangulate.argtypes = [vp, C.c_int32, vp, C.c_int32, C.c_int32, vp, vp]
         L.elas_set_timing.argtypes = [vp, C.c_int32]
         L.elas_get_timing.argtypes = [vp, C.POINTER(ElasTiming)]
+        L.elas_set_batch_flags.argtypes = [vp, C.c_int32]
+        L.elas_process_batch.argtypes = [vp, C.c_int32, C.POINTER(ElasPair), vp]
+        L.elas_get_tuned_variants.argtypes = [vp, C.c_int32, C.c_int32,
+                                              C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         for name in EXPORTS:
             if name not in ("elas_params_default", "elas_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -195,6 +212,45 @@ class Elas:
                                   C.c_void_p(out_right.data_ptr())), self._h)
         self._shape = (H, W)
         return out_left, out_right
+
+    def set_batch_flags(self, graph: bool = True, autotune: bool = True):
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_AUTOTUNE if autotune else 0)
+        _check(lib().elas_set_batch_flags(self._h, flags), self._h)
+
+    def process_batch(self, items, stream=None):
+        """items: sequence of (left, right, out_left, out_right) or
+        (left, right, out_left, out_right, params_elas) with torch uint8 [H, W]
+        images and int16 [H, W] outputs on the device; params_elas (an Elas)
+        supplies that pair's parameters. All pairs run in one batched call."""
+        import torch
+        arr = (ElasPair * max(1, len(items)))()
+        keep = []
+        for i, it in enumerate(items):
+            left, right, ol, orr = it[:4]
+            ph = it[4].handle if len(it) > 4 and it[4] is not None else None
+            for t in (left, right):
+                if t.dtype != torch.uint8 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+                    raise ValueError("images must be uint8 [H, W] device tensors with unit column stride")
+            if left.shape != right.shape or left.stride(0) != right.stride(0):
+                raise ValueError("left and right must share shape and row stride")
+            H, W = left.shape
+            for o in (ol, orr):
+                if o.dtype != torch.int16 or not o.is_contiguous() or tuple(o.shape) != (H, W):
+                    raise ValueError("outputs must be contiguous int16 [H, W]")
+            arr[i] = ElasPair(left.data_ptr(), right.data_ptr(), W, H, left.stride(0),
+                              ol.data_ptr(), orr.data_ptr(), ph)
+            keep.append(it)
+        if stream is None:
+            dev = items[0][0].device if items else torch.device("cuda:0")
+            stream = torch.cuda.current_stream(dev)
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib().elas_process_batch(self._h, len(items), arr, C.c_void_p(s)), self._h)
+        return [(it[2], it[3]) for it in keep]
+
+    def tuned_variants(self, w: int, h: int):
+        r, b = C.c_int32(), C.c_int32()
+        _check(lib().elas_get_tuned_variants(self._h, w, h, C.byref(r), C.byref(b)), self._h)
+        return r.value, b.value
 
     def stats(self) -> dict:
         st = ElasStats()

@@ -1,0 +1,161 @@
+"""Batched processing (one launch per stage for many pairs of mixed sizes and
+disparity ranges, graph capture and replay, tile autotuning): every pair's
+maps must equal the oracle's for that pair, exactly."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_07210_amd as pkg
+    return pkg
+
+
+# (w, h, D, seed): sizes, ragged tiles and several disparity ranges
+MIX = [(320, 240, 64, 0), (97, 61, 64, 1), (200, 120, 32, 2), (320, 240, 64, 3),
+       (131, 77, 128, 4), (256, 96, 256, 5), (97, 61, 64, 6)]
+
+
+def make_mix(seed_shift=0):
+    pairs = []
+    for w, h, D, seed in MIX:
+        cfg = synth.SceneConfig(w, h, D, 4, 0.05, 4.0, max(5.0, D - 5.0), 2.0, 0.1,
+                                seed=seed + seed_shift)
+        pairs.append((synth.make_pair(cfg), D))
+    return pairs
+
+
+def run_batch(E, pairs, graph, autotune, reps=1, stream=None, handles=None):
+    dev = torch.device("cuda:0")
+    base = E.Elas(disp_max=63) if handles is None else handles[64]
+    base.set_batch_flags(graph=graph, autotune=autotune)
+    hs = handles if handles is not None else {D: E.Elas(disp_max=D - 1) for D in {64, 32, 128, 256}}
+    items, outs = [], []
+    for p, D in pairs:
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        oL = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        oR = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        items.append((L, R, oL, oR, hs[D]))
+        outs.append((oL, oR))
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        base.process_batch(items, stream=stream)
+    torch.cuda.synchronize()
+    return [(a.cpu().numpy(), b.cpu().numpy()) for a, b in outs], base, hs
+
+
+def check(pairs, got):
+    for (p, D), (oL, oR) in zip(pairs, got):
+        t = ref.process(ref.params(disp_max=D - 1), p.left, p.right)
+        assert np.array_equal(oL, t.outL), (p.left.shape, D)
+        assert np.array_equal(oR, t.outR), (p.left.shape, D)
+
+
+@pytest.mark.parametrize("graph,autotune", [(False, False), (True, False), (False, True),
+                                            (True, True)])
+def test_batch_mixed_sizes_bit_exact(E, graph, autotune):
+    pairs = make_mix()
+    got, base, hs = run_batch(E, pairs, graph, autotune, reps=2)
+    check(pairs, got)
+    if autotune:  # the batch handle keeps the choice per (w, h, D); it has D = 64
+        for p, D in pairs:
+            if D == 64:
+                h, w = p.left.shape
+                rows, batch = base.tuned_variants(w, h)
+                assert rows in (4, 8, 16) and batch in (4, 8, 16)
+
+
+def test_batch_graph_replay_with_new_inputs(E):
+    # the same batch shape replays its captured graph; the frame table is
+    # uploaded per call, so new images and outputs are picked up
+    dev = torch.device("cuda:0")
+    hs = {D: E.Elas(disp_max=D - 1) for D in {64, 32, 128, 256}}
+    for shift in (0, 100, 200):
+        pairs = make_mix(shift)
+        got, _, _ = run_batch(E, pairs, True, shift > 0, handles=hs)
+        check(pairs, got)
+
+
+def test_batch_equals_single_calls(E):
+    dev = torch.device("cuda:0")
+    pairs = make_mix(7)
+    got, _, hs = run_batch(E, pairs, True, True)
+    for (p, D), (oL, oR) in zip(pairs, got):
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        sL, sR = hs[D].process(L, R)
+        torch.cuda.synchronize()
+        assert np.array_equal(sL.cpu().numpy(), oL)
+        assert np.array_equal(sR.cpu().numpy(), oR)
+
+
+def test_batch_with_host_mesh_pairs(E):
+    # a pair wider than the device mesh limit goes through the host mesh path
+    dev = torch.device("cuda:0")
+    wide = synth.SceneConfig(4100, 12, 32, 3, 0.05, 2.0, 27.0, 2.0, 0.1, seed=3)
+    small = synth.SceneConfig(96, 64, 32, 3, 0.05, 2.0, 27.0, 2.0, 0.1, seed=4)
+    pairs = [(synth.make_pair(wide), 32), (synth.make_pair(small), 32)]
+    hs = {32: E.Elas(disp_max=31)}
+    base = hs[32]
+    base.set_batch_flags(graph=True, autotune=False)
+    items, outs = [], []
+    for p, D in pairs:
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        oL = torch.empty(p.left.shape, dtype=torch.int16, device=dev)
+        oR = torch.empty(p.left.shape, dtype=torch.int16, device=dev)
+        items.append((L, R, oL, oR))
+        outs.append((oL, oR))
+    base.process_batch(items)
+    torch.cuda.synchronize()
+    check(pairs, [(a.cpu().numpy(), b.cpu().numpy()) for a, b in outs])
+
+
+def test_batches_on_two_streams_concurrently(E):
+    dev = torch.device("cuda:0")
+    hs = {D: E.Elas(disp_max=D - 1) for D in {64, 32, 128, 256}}
+    s1, s2 = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+    p1, p2 = make_mix(11), make_mix(12)
+    base = hs[64]
+    base.set_batch_flags(graph=True, autotune=False)
+
+    def items_of(pairs):
+        its, outs = [], []
+        for p, D in pairs:
+            L = torch.from_numpy(p.left).to(dev)
+            R = torch.from_numpy(p.right).to(dev)
+            oL = torch.empty(p.left.shape, dtype=torch.int16, device=dev)
+            oR = torch.empty(p.left.shape, dtype=torch.int16, device=dev)
+            its.append((L, R, oL, oR, hs[D]))
+            outs.append((oL, oR))
+        return its, outs
+
+    i1, o1 = items_of(p1)
+    i2, o2 = items_of(p2)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        base.process_batch(i1, stream=s1)
+        base.process_batch(i2, stream=s2)
+    torch.cuda.synchronize()
+    check(p1, [(a.cpu().numpy(), b.cpu().numpy()) for a, b in o1])
+    check(p2, [(a.cpu().numpy(), b.cpu().numpy()) for a, b in o2])
+
+
+def test_batch_argument_errors(E):
+    e = E.Elas(disp_max=63)
+    with pytest.raises(E.ElasError):
+        e.process_batch([(torch.zeros((4, 4), dtype=torch.uint8, device="cuda:0"),
+                          torch.zeros((4, 4), dtype=torch.uint8, device="cuda:0"),
+                          torch.zeros((4, 4), dtype=torch.int16, device="cuda:0"),
+                          torch.zeros((4, 4), dtype=torch.int16, device="cuda:0"))])
+    e.process_batch([])  # an empty batch is a no-op
