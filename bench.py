@@ -15,6 +15,9 @@ roofline        the kernel with the largest share of chip time (duration x the
                 CU per view), its algorithmic work per launch over its mean
                 duration (HIP events on the stream the library launches on),
                 against the MI355X peak
+batch           96 pairs of mixed resolutions and disparity ranges (seeded
+                synthetic, pair i from seed i), one batched call each repetition,
+                against 96 sequential plain calls
 cpu_baseline    the CPU oracle (single-threaded C) on a bounded sample of the
                 same workload, on this host
 """
@@ -78,7 +81,7 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(left, right, disp_max, budget_s=12.0, max_frames=30):
+def cpu_baseline(left, right, disp_max, budget_s=12.0, max_frames=200):
     from oracle import ref   # the CPU oracle, timed as a reported baseline
     p = ref.params(disp_max=disp_max)
     ref.process(p, left[:64, :64].copy(), right[:64, :64].copy())  # load + warm
@@ -95,6 +98,76 @@ def cpu_baseline(left, right, disp_max, budget_s=12.0, max_frames=30):
                       f"{dt:.1f} s, single-threaded C oracle (-O2), {cpu_model()}"}
 
 
+def batch_c4(torch, Elas, reps=5, n=96):
+    """C4: n pairs, resolutions uniform over the four shapes (index stream
+    seeded 0), pair i generated from seed i; one batched call per repetition
+    against n sequential plain calls on one stream."""
+    import synth
+    names = synth.batch_shapes(n, 0)
+    dev = torch.device("cuda:0")
+    hs = {}
+    items, seq_outs, mix = [], [], {}
+    for i, nm in enumerate(names):
+        cfg = synth.SHAPES[nm].with_seed(i)
+        pair = synth.make_pair(cfg)
+        D = cfg.disp_range
+        if D not in hs:
+            hs[D] = Elas(disp_max=D - 1)
+        L = torch.from_numpy(pair.left).to(dev)
+        R = torch.from_numpy(pair.right).to(dev)
+        H, W = pair.left.shape
+        mk = lambda: torch.empty((H, W), dtype=torch.int16, device=dev)
+        items.append((L, R, mk(), mk(), hs[D]))
+        seq_outs.append((mk(), mk()))
+        mix[nm] = mix.get(nm, 0) + 1
+    base = hs[128] if 128 in hs else next(iter(hs.values()))
+    base.set_batch_flags(graph=True, autotune=True)
+    s0 = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    base.process_batch(items, stream=s0)      # autotunes new sizes, captures the graph
+    base.process_batch(items, stream=s0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        base.process_batch(items, stream=s0)
+    torch.cuda.synchronize()
+    fps_batch = reps * n / (time.perf_counter() - t0)
+
+    def sequential():
+        for (L, R, _, _, e), (oL, oR) in zip(items, seq_outs):
+            e.process(L, R, oL, oR, stream=s0)
+
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sequential()
+    torch.cuda.synchronize()
+    fps_seq = reps * n / (time.perf_counter() - t0)
+    same = all(torch.equal(a[2], b[0]) and torch.equal(a[3], b[1])
+               for a, b in zip(items, seq_outs))
+    evals = 0
+    for (L, R, _, _, e), (oL, oR) in zip(items, seq_outs):
+        e.process(L, R, oL, oR, stream=s0)
+        st = e.stats()
+        evals += st["support_evals"] + st["dense_evals"]
+    tuned = {}
+    for nm in mix:
+        cfg = synth.SHAPES[nm]
+        try:
+            tuned[nm] = list(base.tuned_variants(cfg.width, cfg.height)) \
+                if cfg.disp_range == 128 else None
+        except Exception:
+            tuned[nm] = None
+    return {"pairs": n, "mix": mix, "reps": reps, "value": round(fps_batch, 2),
+            "unit": "frames/s", "sequential_fps": round(fps_seq, 2),
+            "speedup_vs_sequential": round(fps_batch / fps_seq, 3),
+            "evals_per_s_algorithmic": round(evals * fps_batch / n, 1),
+            "identical_to_sequential": bool(same),
+            "graph": True, "autotune": True,
+            "tuned_desc_rows_dense_batch_at_D128": tuned}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +179,13 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--streams", type=int, default=4,
                     help="frames in flight: steps are issued round-robin on this many streams")
+    ap.add_argument("--mode", choices=["frame", "serve"], default="frame",
+                    help="frame: the 640x480 frame rate (default); serve: the camera-stream "
+                         "serving sweep (batched and plain servers)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds per arrival-rate level in --mode serve")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 96-pair batched measurement")
     ap.add_argument("--mesh-on-host", action="store_true",
                     help="triangulate on the host between the GPU phases (the paper's split)")
     args = ap.parse_args()
@@ -117,6 +197,25 @@ def main():
     import torch
     import synth
     from paper_1802_07210_amd import Elas
+
+    if args.mode == "serve":
+        from paper_1802_07210_amd import serve
+        cams, handles = serve.build_cameras()
+        batched = serve.run_sweep(seconds=args.serve_seconds, cams=cams, handles=handles)
+        plain = serve.run_sweep(seconds=args.serve_seconds, plain=True, cams=cams,
+                                handles=handles)
+        top = batched["levels"][-1]
+        print(json.dumps({
+            "metric": METRIC, "mode": "serve", "value": top["sustained_pairs_per_s"],
+            "unit": "pairs/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+            "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "16 camera streams, camera j at shape j mod 4 (320x240 D64, "
+                                   "640x480 D128, 1242x375 D256, 1280x720 D192), Poisson "
+                                   "arrivals swept over aggregate rates, seconds per level "
+                                   f"{args.serve_seconds}", "cameras": 16, "pool_per_camera": 4},
+            "p50_ms_at_top_rate": top["p50_ms"], "p99_ms_at_top_rate": top["p99_ms"],
+            "batched": batched, "plain": plain}), flush=True)
+        return
 
     cfg = synth.SHAPES[args.workload].with_seed(args.seed)
     pair = synth.make_pair(cfg)
@@ -206,6 +305,8 @@ def main():
         "host_ms": {k: round(float(np.mean(v)), 5) for k, v in host.items()},
         "roofline": roof,
     }
+    if not args.no_batch:
+        out["batch"] = batch_c4(torch, Elas)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair.left, pair.right, D - 1)
     print(json.dumps(out), flush=True)

@@ -193,6 +193,56 @@ ELAS_API int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pair
 ELAS_API int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t h_px,
                                      int32_t* desc_rows, int32_t* dense_batch);
 
+/* Device bytes of the buffers one pair of size (w, h_px) needs with h's
+ * parameters (descriptors, lattice, grid, mesh, maps); what a server admits
+ * against its memory budget. No HIP call. */
+ELAS_API int elas_frame_bytes(elas_handle* h, int32_t w, int32_t h_px, int64_t* bytes);
+
+/* ---- serving: continuous batching of pairs from many cameras ----------
+ * A server owns a worker thread and max_inflight streams. elas_server_submit
+ * queues a pair (device images and outputs, caller-owned until the ticket
+ * completes) and returns a ticket at once. Whenever a stream is free and
+ * pairs wait, the worker launches the longest-waiting ones (up to max_batch,
+ * and only while the footprint of all pairs in flight stays within
+ * memory_budget) as one elas_process_batch call; pairs that arrive while
+ * others run are admitted as streams and memory free up, and overlap on the
+ * device with the batches already running. With plain = 1 the server runs
+ * one pair at a time through elas_process (the unbatched baseline). Results
+ * are identical to elas_process of the same pair. Latency = submission to
+ * the worker observing the batch's completion (host clock). The handle h and
+ * every pair's parameter handle belong to the worker while the server
+ * exists; nothing else may use them. */
+typedef struct elas_server elas_server;
+typedef struct elas_server_config {
+  int32_t max_batch;            /* pairs per launch, 1..1024 (32) */
+  int32_t max_inflight;         /* batches on the device at once, 1..16 (4) */
+  int64_t memory_budget;        /* device bytes of the pairs in flight (32 GiB) */
+  int32_t plain;                /* 1: one pair at a time via elas_process (0) */
+} elas_server_config;
+typedef struct elas_server_stats {
+  int64_t submitted, completed;
+  int64_t batches, batched_pairs;  /* launches and the pairs they carried */
+  int64_t peak_bytes_in_flight;
+  int64_t queued;                  /* waiting now */
+  int64_t bytes_in_flight;         /* admitted now */
+} elas_server_stats;
+ELAS_API void elas_server_config_default(elas_server_config* c);
+/* ELAS_ERR_ARG for out-of-range settings, ELAS_ERR_HIP if streams fail. */
+ELAS_API int elas_server_create(elas_handle* h, const elas_server_config* cfg,
+                                elas_server** out);
+/* ELAS_ERR_ARG for a bad pair or one larger than the whole budget. */
+ELAS_API int elas_server_submit(elas_server* s, const elas_pair* pair, int64_t* ticket);
+/* Blocks until the ticket completes; *latency_ms (optional) receives its
+ * latency. Returns the pair's status (a ticket is reported once). */
+ELAS_API int elas_server_wait(elas_server* s, int64_t ticket, double* latency_ms);
+/* Non-blocking: *done = 1 and the status and latency once complete. */
+ELAS_API int elas_server_poll(elas_server* s, int64_t ticket, int32_t* done,
+                              double* latency_ms);
+ELAS_API int elas_server_get_stats(elas_server* s, elas_server_stats* out);
+ELAS_API const char* elas_server_last_error(const elas_server* s);
+/* Finishes every queued and running pair, then frees the server. */
+ELAS_API int elas_server_destroy(elas_server* s);
+
 /* Copies the counters of the last elas_process call (synchronises with its
  * stream first). */
 ELAS_API int elas_get_stats(elas_handle* h, elas_stats* out);

@@ -3,4 +3,4 @@
 The compute lives in libelas_mi355x.so (HIP kernels + host mesh step behind
 the C-ABI of include/elas.h); `elas` is its ctypes binding.
 """
-from .elas import Elas, ElasError, default_params, triangulate  # noqa: F401
+from .elas import Elas, ElasError, Server, default_params, triangulate  # noqa: F401

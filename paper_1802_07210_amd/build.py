@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 ARCH = os.environ.get("ELAS_OFFLOAD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["elas_kernels.hip", "elas_mesh_device.hip", "elas_api.hip", "elas_mesh.cpp"]
+SOURCES = ["elas_kernels.hip", "elas_mesh_device.hip", "elas_api.hip", "elas_mesh.cpp",
+           "elas_server.cpp"]
 HEADERS = [os.path.join(CSRC, "elas_internal.h"), os.path.join(INCLUDE, "elas.h")]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-fvisibility=hidden",

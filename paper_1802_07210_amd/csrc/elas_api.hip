@@ -220,40 +220,85 @@ Geometry make_geometry(const elas_params& p, int32_t w, int32_t h) {
   return g;
 }
 
-int alloc_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
-  Buffers* b = new Buffers();
-  b->g = make_geometry(h->params, w, hp);
-  const Geometry& g = b->g;
+// Offsets of every device array of one buffer set (256-byte aligned).
+struct BufLayout {
+  Geometry g{};
+  size_t nlat = 0, nrows = 0;
+  int32_t ntmax = 0;
+  size_t descL, descR, raw0, inc, vert, fin, evals, gL, gR, oL, oR, dpL, dpR, rL, rR, lut, cnt,
+      rowsL, rowsR, rc, hdr, pL, pR, recL, recR, plL, plR, tris, ms;
+  size_t total = 0;
+};
+
+BufLayout buffer_layout(const elas_params& p, int32_t w, int32_t hp) {
+  BufLayout L;
+  L.g = make_geometry(p, w, hp);
+  const Geometry& g = L.g;
   const size_t npx = (size_t)w * hp;
   const size_t nlat = std::max<size_t>(1, (size_t)g.lw * g.lh);
   const size_t nrows = std::max<size_t>(1, (size_t)g.lh);
   const size_t ngrid = (size_t)g.gw * g.gh * g.gwords;
-  b->ntmax = (int32_t)(2 * nlat + 2);
-  const size_t ntmax = (size_t)b->ntmax;
+  L.nlat = nlat;
+  L.nrows = nrows;
+  L.ntmax = (int32_t)(2 * nlat + 2);
+  const size_t ntmax = (size_t)L.ntmax;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off = align_up(off + bytes, 256);
     return o;
   };
-  const size_t o_descL = take(npx * 16), o_descR = take(npx * 16);
-  const size_t o_raw0 = take(nlat * 2), o_inc = take(nlat * 2), o_vert = take(nlat * 2),
-               o_fin = take(nlat * 2);
-  const size_t o_evals = take(nlat * 4);
-  const size_t o_gL = take(ngrid * 4 + 8), o_gR = take(ngrid * 4 + 8);
-  const size_t o_oL = take(npx * 4), o_oR = take(npx * 4);
-  const size_t o_dpL = take(npx * 2), o_dpR = take(npx * 2), o_rL = take(npx * 2),
-               o_rR = take(npx * 2);
-  const size_t o_lut = take(kMaxD * 4), o_cnt = take((size_t)dense_blocks(g) * 4);
-  const size_t o_rowsL = take(nlat * 4), o_rowsR = take(nlat * 4), o_rc = take(3 * nrows * 4);
-  const size_t o_hdr = take(sizeof(MeshHeader));
-  const size_t o_pL = take(nlat * 12), o_pR = take(nlat * 12);
-  const size_t o_recL = take(ntmax * 36), o_recR = take(ntmax * 36);
-  const size_t o_plL = take(ntmax * 12), o_plR = take(ntmax * 12);
-  const size_t o_tris = take(2 * ntmax * sizeof(RasterTri));
+  L.descL = take(npx * 16);
+  L.descR = take(npx * 16);
+  L.raw0 = take(nlat * 2);
+  L.inc = take(nlat * 2);
+  L.vert = take(nlat * 2);
+  L.fin = take(nlat * 2);
+  L.evals = take(nlat * 4);
+  L.gL = take(ngrid * 4 + 8);
+  L.gR = take(ngrid * 4 + 8);
+  L.oL = take(npx * 4);
+  L.oR = take(npx * 4);
+  L.dpL = take(npx * 2);
+  L.dpR = take(npx * 2);
+  L.rL = take(npx * 2);
+  L.rR = take(npx * 2);
+  L.lut = take(kMaxD * 4);
+  L.cnt = take((size_t)dense_blocks(g) * 4);
+  L.rowsL = take(nlat * 4);
+  L.rowsR = take(nlat * 4);
+  L.rc = take(3 * nrows * 4);
+  L.hdr = take(sizeof(MeshHeader));
+  L.pL = take(nlat * 12);
+  L.pR = take(nlat * 12);
+  L.recL = take(ntmax * 36);
+  L.recR = take(ntmax * 36);
+  L.plL = take(ntmax * 12);
+  L.plR = take(ntmax * 12);
+  L.tris = take(2 * ntmax * sizeof(RasterTri));
   // frames above the device mesh limit are always meshed on the host
   const bool dev_mesh = w <= kDeviceMeshMaxSide && hp <= kDeviceMeshMaxSide;
-  const size_t o_ms = take(dev_mesh ? 2 * mesh_global_scratch_per_view(g) : 0);
+  L.ms = take(dev_mesh ? 2 * mesh_global_scratch_per_view(g) : 0);
+  L.total = off;
+  return L;
+}
+
+int alloc_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
+  Buffers* b = new Buffers();
+  const BufLayout Lo = buffer_layout(h->params, w, hp);
+  b->g = Lo.g;
+  const Geometry& g = b->g;
+  const size_t nlat = Lo.nlat, nrows = Lo.nrows;
+  b->ntmax = Lo.ntmax;
+  const size_t off = Lo.total;
+  const size_t o_descL = Lo.descL, o_descR = Lo.descR, o_raw0 = Lo.raw0, o_inc = Lo.inc,
+               o_vert = Lo.vert, o_fin = Lo.fin, o_evals = Lo.evals, o_gL = Lo.gL, o_gR = Lo.gR,
+               o_oL = Lo.oL, o_oR = Lo.oR, o_dpL = Lo.dpL, o_dpR = Lo.dpR, o_rL = Lo.rL,
+               o_rR = Lo.rR, o_lut = Lo.lut, o_cnt = Lo.cnt, o_rowsL = Lo.rowsL,
+               o_rowsR = Lo.rowsR, o_rc = Lo.rc, o_hdr = Lo.hdr, o_pL = Lo.pL, o_pR = Lo.pR,
+               o_recL = Lo.recL, o_recR = Lo.recR, o_plL = Lo.plL, o_plR = Lo.plR,
+               o_tris = Lo.tris, o_ms = Lo.ms;
+  (void)g;
   hipError_t e = hipMalloc(&b->dev_block, off);
   if (e != hipSuccess) {
     delete b;
@@ -983,6 +1028,14 @@ int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStr
       h->tuned[kv.first] = best;
     }
   }
+  return ELAS_OK;
+}
+
+int elas_frame_bytes(elas_handle* h, int32_t w, int32_t hp, int64_t* bytes) {
+  if (!h || !bytes) return fail(h, ELAS_ERR_ARG, "null argument");
+  if (w < 9 || hp < 9 || w > 8192 || hp > 8192)
+    return fail(h, ELAS_ERR_ARG, "image size must be 9..8192 in each dimension");
+  *bytes = (int64_t)buffer_layout(h->params, w, hp).total;
   return ELAS_OK;
 }
 

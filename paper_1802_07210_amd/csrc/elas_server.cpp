@@ -1,0 +1,324 @@
+// Serving loop of elas_mi355x: continuous batching of stereo pairs that
+// arrive from many cameras.
+//
+// Callers submit pairs (device images and outputs of any supported size) and
+// get a ticket back at once. One worker thread owns the device side: it
+// keeps up to max_inflight batches on the device, each on its own stream,
+// and whenever a stream is free and requests are waiting it takes the
+// longest-waiting requests, as many as max_batch and the memory budget
+// admit, and launches them as one elas_process_batch call. Requests that
+// arrive while others run are therefore admitted as soon as a stream and
+// memory free up, and their work overlaps the batches already on the device.
+// The memory budget bounds the device footprint (elas_frame_bytes) of the
+// requests in flight; the buffers themselves stay resident in the handles'
+// per-(size, stream) pools between batches. Latency is measured on the host
+// from submission to the worker seeing the batch's completion event.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "elas.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class State { Pending, Done, Failed };
+
+struct Request {
+  int64_t ticket;
+  elas_pair pair;
+  int64_t bytes;
+};
+
+struct Result {
+  State state = State::Pending;
+  Clock::time_point submitted, finished;
+  int code = ELAS_OK;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<int64_t> tickets;
+  int64_t bytes = 0;
+};
+
+}  // namespace
+
+struct elas_server {
+  elas_handle* h = nullptr;
+  elas_server_config cfg{};
+  std::mutex m;
+  std::condition_variable work;  // submissions and shutdown
+  std::condition_variable done;  // completions
+  std::deque<Request> queue;
+  std::vector<Slot> slots;
+  std::unordered_map<int64_t, Result> results;
+  std::map<std::tuple<elas_handle*, int32_t, int32_t>, int64_t> footprint;
+  int64_t next_ticket = 1;
+  int64_t in_flight = 0;
+  elas_server_stats stats{};
+  bool stop = false;
+  std::string err;
+  std::thread worker;
+};
+
+namespace {
+
+thread_local std::string g_server_error;
+
+int server_fail(elas_server* s, int code, const std::string& msg) {
+  if (s) {
+    std::lock_guard<std::mutex> lk(s->m);
+    s->err = msg;
+  } else {
+    g_server_error = msg;
+  }
+  return code;
+}
+
+void finish(elas_server* S, Slot& sl, State st, int code, Clock::time_point now) {
+  for (int64_t t : sl.tickets) {
+    auto it = S->results.find(t);
+    if (it == S->results.end()) continue;
+    it->second.state = st;
+    it->second.code = code;
+    it->second.finished = now;
+  }
+  S->stats.completed += (int64_t)sl.tickets.size();
+  S->in_flight -= sl.bytes;
+  sl.tickets.clear();
+  sl.bytes = 0;
+  sl.busy = false;
+}
+
+void worker_loop(elas_server* S) {
+  std::unique_lock<std::mutex> lk(S->m);
+  for (;;) {
+    // completions
+    bool any_done = false, any_busy = false;
+    for (Slot& sl : S->slots) {
+      if (!sl.busy) continue;
+      const hipError_t q = hipEventQuery(sl.done);
+      if (q == hipSuccess) {
+        finish(S, sl, State::Done, ELAS_OK, Clock::now());
+        any_done = true;
+      } else if (q != hipErrorNotReady) {
+        S->err = std::string("batch failed on the device: ") + hipGetErrorString(q);
+        finish(S, sl, State::Failed, ELAS_ERR_HIP, Clock::now());
+        any_done = true;
+      } else {
+        any_busy = true;
+      }
+    }
+    if (any_done) S->done.notify_all();
+    // launches: oldest requests first, while a stream is free and they fit
+    for (Slot& sl : S->slots) {
+      if (sl.busy || S->queue.empty()) continue;
+      const int maxb = S->cfg.plain ? 1 : S->cfg.max_batch;
+      std::vector<elas_pair> pairs;
+      std::vector<int64_t> tickets;
+      int64_t bytes = 0;
+      while (!S->queue.empty() && (int)pairs.size() < maxb &&
+             S->in_flight + bytes + S->queue.front().bytes <= S->cfg.memory_budget) {
+        pairs.push_back(S->queue.front().pair);
+        tickets.push_back(S->queue.front().ticket);
+        bytes += S->queue.front().bytes;
+        S->queue.pop_front();
+      }
+      if (pairs.empty()) break;  // the oldest request waits for memory
+      sl.busy = true;
+      sl.tickets = tickets;
+      sl.bytes = bytes;
+      S->in_flight += bytes;
+      S->stats.peak_bytes_in_flight = std::max(S->stats.peak_bytes_in_flight, S->in_flight);
+      S->stats.batches += 1;
+      S->stats.batched_pairs += (int64_t)pairs.size();
+      lk.unlock();
+      int rc;
+      if (S->cfg.plain) {
+        const elas_pair& q = pairs[0];
+        rc = elas_process(q.params ? q.params : S->h, q.left, q.right, q.w, q.h, q.stride,
+                          sl.stream, q.disp_left, q.disp_right);
+      } else {
+        rc = elas_process_batch(S->h, (int32_t)pairs.size(), pairs.data(), sl.stream);
+      }
+      const hipError_t re = rc == ELAS_OK ? hipEventRecord(sl.done, sl.stream) : hipSuccess;
+      lk.lock();
+      if (rc != ELAS_OK || re != hipSuccess) {
+        S->err = rc != ELAS_OK ? std::string(elas_last_error(S->h))
+                               : std::string("hipEventRecord: ") + hipGetErrorString(re);
+        finish(S, sl, State::Failed, rc != ELAS_OK ? rc : ELAS_ERR_HIP, Clock::now());
+        S->done.notify_all();
+      } else {
+        any_busy = true;
+      }
+    }
+    if (S->stop && S->queue.empty() && !any_busy) break;
+    if (!any_busy && S->queue.empty())
+      S->work.wait(lk);
+    else
+      S->work.wait_for(lk, std::chrono::microseconds(20));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void elas_server_config_default(elas_server_config* c) {
+  if (!c) return;
+  c->max_batch = 32;
+  c->max_inflight = 4;
+  c->memory_budget = (int64_t)32 << 30;
+  c->plain = 0;
+}
+
+int elas_server_create(elas_handle* h, const elas_server_config* cfg, elas_server** out) {
+  if (!h || !cfg || !out) return server_fail(nullptr, ELAS_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (cfg->max_batch < 1 || cfg->max_batch > 1024 || cfg->max_inflight < 1 ||
+      cfg->max_inflight > 16 || cfg->memory_budget <= 0 || (cfg->plain != 0 && cfg->plain != 1))
+    return server_fail(nullptr, ELAS_ERR_ARG,
+                       "max_batch 1..1024, max_inflight 1..16, memory_budget > 0, plain 0/1");
+  elas_server* S = new elas_server();
+  S->h = h;
+  S->cfg = *cfg;
+  S->slots.resize(cfg->plain ? 1 : cfg->max_inflight);
+  for (Slot& sl : S->slots) {
+    hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (Slot& x : S->slots) {
+        if (x.done) (void)hipEventDestroy(x.done);
+        if (x.stream) (void)hipStreamDestroy(x.stream);
+      }
+      delete S;
+      return server_fail(nullptr, ELAS_ERR_HIP, std::string("stream setup: ") + hipGetErrorString(e));
+    }
+  }
+  S->worker = std::thread(worker_loop, S);
+  *out = S;
+  return ELAS_OK;
+}
+
+int elas_server_submit(elas_server* s, const elas_pair* pair, int64_t* ticket) {
+  if (!s || !pair || !ticket) return server_fail(s, ELAS_ERR_ARG, "null argument");
+  if (!pair->left || !pair->right || !pair->disp_left || !pair->disp_right || pair->w < 9 ||
+      pair->h < 9 || pair->w > 8192 || pair->h > 8192 || pair->stride < pair->w)
+    return server_fail(s, ELAS_ERR_ARG, "bad pair");
+  elas_handle* ph = pair->params ? pair->params : s->h;
+  int64_t bytes = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->m);
+    auto key = std::make_tuple(ph, pair->w, pair->h);
+    auto it = s->footprint.find(key);
+    if (it != s->footprint.end()) bytes = it->second;
+  }
+  if (bytes == 0) {
+    const int rc = elas_frame_bytes(ph, pair->w, pair->h, &bytes);
+    if (rc != ELAS_OK) return server_fail(s, rc, "footprint of the pair");
+  }
+  std::lock_guard<std::mutex> lk(s->m);
+  s->footprint[std::make_tuple(ph, pair->w, pair->h)] = bytes;
+  if (bytes > s->cfg.memory_budget) {
+    s->err = "pair needs more device memory than the whole budget";
+    return ELAS_ERR_ARG;
+  }
+  if (s->stop) {
+    s->err = "server is shutting down";
+    return ELAS_ERR_ARG;
+  }
+  const int64_t t = s->next_ticket++;
+  Result r;
+  r.submitted = Clock::now();
+  s->results.emplace(t, r);
+  s->queue.push_back(Request{t, *pair, bytes});
+  s->stats.submitted += 1;
+  *ticket = t;
+  s->work.notify_one();
+  return ELAS_OK;
+}
+
+static int take_result(elas_server* s, std::unordered_map<int64_t, Result>::iterator it,
+                       double* latency_ms) {
+  const Result r = it->second;
+  s->results.erase(it);
+  if (latency_ms)
+    *latency_ms = std::chrono::duration<double, std::milli>(r.finished - r.submitted).count();
+  return r.state == State::Done ? ELAS_OK : r.code;
+}
+
+int elas_server_poll(elas_server* s, int64_t ticket, int32_t* done, double* latency_ms) {
+  if (!s || !done) return server_fail(s, ELAS_ERR_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->m);
+  auto it = s->results.find(ticket);
+  if (it == s->results.end()) {
+    s->err = "unknown ticket";
+    return ELAS_ERR_ARG;
+  }
+  *done = it->second.state != State::Pending;
+  if (!*done) return ELAS_OK;
+  return take_result(s, it, latency_ms);
+}
+
+int elas_server_wait(elas_server* s, int64_t ticket, double* latency_ms) {
+  if (!s) return server_fail(nullptr, ELAS_ERR_ARG, "null server");
+  std::unique_lock<std::mutex> lk(s->m);
+  auto it = s->results.find(ticket);
+  if (it == s->results.end()) {
+    s->err = "unknown ticket";
+    return ELAS_ERR_ARG;
+  }
+  // submissions may rehash the table while this thread waits: look up again
+  s->done.wait(lk, [&] {
+    auto i = s->results.find(ticket);
+    return i == s->results.end() || i->second.state != State::Pending;
+  });
+  it = s->results.find(ticket);
+  if (it == s->results.end()) {
+    s->err = "unknown ticket";
+    return ELAS_ERR_ARG;
+  }
+  return take_result(s, it, latency_ms);
+}
+
+int elas_server_get_stats(elas_server* s, elas_server_stats* out) {
+  if (!s || !out) return server_fail(s, ELAS_ERR_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->m);
+  *out = s->stats;
+  out->queued = (int64_t)s->queue.size();
+  out->bytes_in_flight = s->in_flight;
+  return ELAS_OK;
+}
+
+const char* elas_server_last_error(const elas_server* s) {
+  return s ? s->err.c_str() : g_server_error.c_str();
+}
+
+int elas_server_destroy(elas_server* s) {
+  if (!s) return ELAS_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->m);
+    s->stop = true;
+  }
+  s->work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (Slot& sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  delete s;
+  return ELAS_OK;
+}
+
+}  // extern "C"

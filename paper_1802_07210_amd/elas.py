@@ -22,7 +22,9 @@ ERRORS = {-1: "ELAS_ERR_ARG", -2: "ELAS_ERR_OOM", -3: "ELAS_ERR_HIP",
 EXPORTS = ("elas_params_default", "elas_create", "elas_destroy", "elas_process",
            "elas_get_stats", "elas_last_error", "elas_get_intermediate", "elas_triangulate",
            "elas_set_timing", "elas_get_timing", "elas_set_batch_flags", "elas_process_batch",
-           "elas_get_tuned_variants")
+           "elas_get_tuned_variants", "elas_frame_bytes", "elas_server_config_default",
+           "elas_server_create", "elas_server_submit", "elas_server_wait", "elas_server_poll",
+           "elas_server_get_stats", "elas_server_last_error", "elas_server_destroy")
 
 BATCH_GRAPH = 1
 BATCH_AUTOTUNE = 2
@@ -67,6 +69,17 @@ class ElasPair(C.Structure):
         ("disp_left", C.c_void_p), ("disp_right", C.c_void_p),
         ("params", C.c_void_p),
     ]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("max_inflight", C.c_int32),
+                ("memory_budget", C.c_int64), ("plain", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("batched_pairs", C.c_int64), ("peak_bytes_in_flight", C.c_int64),
+                ("queued", C.c_int64), ("bytes_in_flight", C.c_int64)]
 
 
 # name -> (enum value, numpy dtype, trailing shape kind)
@@ -115,8 +128,21 @@ def lib() -> C.CDLL:
         L.elas_process_batch.argtypes = [vp, C.c_int32, C.POINTER(ElasPair), vp]
         L.elas_get_tuned_variants.argtypes = [vp, C.c_int32, C.c_int32,
                                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.elas_frame_bytes.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
+        L.elas_server_config_default.argtypes = [C.POINTER(ServerConfig)]
+        L.elas_server_config_default.restype = None
+        L.elas_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
+        L.elas_server_submit.argtypes = [vp, C.POINTER(ElasPair), C.POINTER(C.c_int64)]
+        L.elas_server_wait.argtypes = [vp, C.c_int64, C.POINTER(C.c_double)]
+        L.elas_server_poll.argtypes = [vp, C.c_int64, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double)]
+        L.elas_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.elas_server_last_error.argtypes = [vp]
+        L.elas_server_last_error.restype = C.c_char_p
+        L.elas_server_destroy.argtypes = [vp]
         for name in EXPORTS:
-            if name not in ("elas_params_default", "elas_last_error"):
+            if name not in ("elas_params_default", "elas_last_error",
+                            "elas_server_config_default", "elas_server_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -247,6 +273,11 @@ class Elas:
         _check(lib().elas_process_batch(self._h, len(items), arr, C.c_void_p(s)), self._h)
         return [(it[2], it[3]) for it in keep]
 
+    def frame_bytes(self, w: int, h: int) -> int:
+        b = C.c_int64()
+        _check(lib().elas_frame_bytes(self._h, w, h, C.byref(b)), self._h)
+        return b.value
+
     def tuned_variants(self, w: int, h: int):
         r, b = C.c_int32(), C.c_int32()
         _check(lib().elas_get_tuned_variants(self._h, w, h, C.byref(r), C.byref(b)), self._h)
@@ -273,3 +304,83 @@ class Elas:
         buf = np.zeros(max(nbytes, 1), np.uint8)
         _check(lib().elas_get_intermediate(self._h, which, _np_ptr(buf), nbytes, None), self._h)
         return buf[:nbytes].view(dtype).copy()
+
+
+def _pair_of(left, right, out_left, out_right, params=None) -> ElasPair:
+    import torch
+    for t in (left, right):
+        if t.dtype != torch.uint8 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError("images must be uint8 [H, W] device tensors with unit column stride")
+    if left.shape != right.shape or left.stride(0) != right.stride(0):
+        raise ValueError("left and right must share shape and row stride")
+    H, W = left.shape
+    for o in (out_left, out_right):
+        if o.dtype != torch.int16 or not o.is_contiguous() or tuple(o.shape) != (H, W):
+            raise ValueError("outputs must be contiguous int16 [H, W]")
+    return ElasPair(left.data_ptr(), right.data_ptr(), W, H, left.stride(0),
+                    out_left.data_ptr(), out_right.data_ptr(),
+                    params.handle if params is not None else None)
+
+
+class Server:
+    """Continuous-batching server over one handle (the handle and every
+    parameter handle of submitted pairs belong to the server until close)."""
+
+    def __init__(self, elas: "Elas", max_batch: int = 32, max_inflight: int = 4,
+                 memory_budget: int = 32 << 30, plain: bool = False):
+        cfg = ServerConfig()
+        lib().elas_server_config_default(C.byref(cfg))
+        cfg.max_batch, cfg.max_inflight = max_batch, max_inflight
+        cfg.memory_budget, cfg.plain = memory_budget, int(bool(plain))
+        s = C.c_void_p()
+        rc = lib().elas_server_create(elas.handle, C.byref(cfg), C.byref(s))
+        if rc < 0:
+            raise ElasError(f"{ERRORS.get(rc, rc)}: {lib().elas_server_last_error(None).decode()}")
+        self._s = s
+        self._elas = elas
+        self._keep = {}
+
+    def _check(self, rc):
+        if rc < 0:
+            msg = lib().elas_server_last_error(self._s)
+            raise ElasError(f"{ERRORS.get(rc, rc)}: {msg.decode() if msg else ''}")
+        return rc
+
+    def submit(self, left, right, out_left, out_right, params: "Elas" = None) -> int:
+        pr = _pair_of(left, right, out_left, out_right, params)
+        t = C.c_int64()
+        self._check(lib().elas_server_submit(self._s, C.byref(pr), C.byref(t)))
+        self._keep[t.value] = (left, right, out_left, out_right)
+        return t.value
+
+    def wait(self, ticket: int) -> float:
+        ms = C.c_double()
+        rc = lib().elas_server_wait(self._s, ticket, C.byref(ms))
+        self._keep.pop(ticket, None)
+        self._check(rc)
+        return ms.value
+
+    def poll(self, ticket: int):
+        done, ms = C.c_int32(), C.c_double()
+        rc = lib().elas_server_poll(self._s, ticket, C.byref(done), C.byref(ms))
+        if done.value:
+            self._keep.pop(ticket, None)
+        self._check(rc)
+        return (ms.value if done.value else None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._check(lib().elas_server_get_stats(self._s, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().elas_server_destroy(self._s)
+            self._s = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
