@@ -53,6 +53,15 @@ typedef struct orc_params {
   int32_t match_texture;       /* minimum texture of a 16-byte dense descriptor */
   int32_t lr_threshold;        /* left/right agreement tolerance */
   int32_t full_search;         /* 1: dense candidates = every admissible d */
+  /* Section VI variant and optional steps (0/1 defaults give the pipeline
+   * above). */
+  int32_t descriptor;          /* 0: Sobel descriptors + SAD; 1: census + Hamming */
+  int32_t census_support_window; /* support census window W (odd, 3..13) */
+  int32_t census_dense_window; /* dense census window W (odd, 3..7) */
+  int32_t ambiguity;           /* 0: ratio test (eq. 1-2); 1: shift-sum (eq. 3) */
+  int32_t redundancy;          /* 0: two-sided (Fig. 7A); 1: past-only (Fig. 7B) */
+  int32_t support_subsample;   /* keep every k-th support point (k >= 1) */
+  int32_t median_window;       /* 0 or 1: off; 3 or 5: median post-filter */
 } orc_params;
 
 /* ---- stage 1: gradients and descriptors -------------------------------- */
@@ -83,7 +92,9 @@ void orc_filter_redun(const orc_params* p, const int16_t* in, int32_t lw,
 
 /* ---- support lists --------------------------------------------------------
  * ptsL/ptsR receive (u, v, d) triples; capacity lw*lh triples. Returns counts.
- * corners receive the d of (0,0), (w-1,0), (0,h-1), (w-1,h-1). */
+ * corners receive the d of (0,0), (w-1,0), (0,h-1), (w-1,h-1). The left list
+ * is down-sampled (support_subsample) before the right list and the corners
+ * are built from it; *nL is the kept count. */
 void orc_support_lists(const orc_params* p, const int16_t* dcan, int32_t lw,
                        int32_t lh, int32_t w, int32_t h,
                        int32_t* ptsL, int32_t* nL, int32_t* cornersL,
@@ -131,6 +142,37 @@ int64_t orc_dense(const orc_params* p, const uint8_t* desc_self,
 void orc_lrcheck(const orc_params* p, const int16_t* rawL, const int16_t* rawR,
                  int32_t w, int32_t h, int16_t* outL, int16_t* outR);
 
+/* ---- Section VI variant (elas_oracle_variant.c) -------------------------
+ * Census descriptors: `words` 32-bit words per pixel, row-major [h][w][words];
+ * bit i (word i/32, bit i%32) is the i-th window offset in row-major order,
+ * set iff that neighbour is inside the image and darker than the centre. */
+void orc_census(const uint8_t* img, int32_t w, int32_t h, int32_t stride, int32_t win,
+                uint32_t* out, int32_t words);
+int32_t orc_hamming(const uint32_t* a, const uint32_t* b, int32_t words);
+int32_t orc_census_texture(const uint32_t* a, int32_t words);
+/* eq. 3: m2/2 + m2/4 + m2/8 + m2/32 with truncating shifts; accept iff
+ * m1 <= that. orc_support_accept applies the test params->ambiguity names. */
+int32_t orc_shiftsum_threshold(int32_t m2);
+int32_t orc_shiftsum_accept(int32_t m1, int32_t m2);
+int32_t orc_support_accept(const orc_params* p, int32_t m1, int32_t m2);
+/* Support matching on census descriptors of the support window (csL/csR
+ * computed on the whole image with `words` words per pixel). */
+void orc_support_match_census(const orc_params* p, const uint32_t* csL,
+                              const uint32_t* csR, int32_t words, int32_t w, int32_t h,
+                              int16_t* dcan, int64_t* evals);
+/* Past-only redundancy pass along columns (vertical) or rows. */
+void orc_filter_redun_past(const orc_params* p, const int16_t* in, int32_t lw, int32_t lh,
+                           int32_t vertical, int16_t* out);
+/* Keeps every k-th (u, v, d) triple, in place; returns the new count. */
+int32_t orc_subsample(int32_t* pts, int32_t n, int32_t k);
+/* Dense matching on census descriptors of the dense window. */
+int64_t orc_dense_census(const orc_params* p, const uint32_t* cself, const uint32_t* cother,
+                         int32_t words, const int16_t* dplane, const uint64_t* grid,
+                         int32_t has_list, const int32_t* lut, int32_t w, int32_t h,
+                         int32_t right_frame, int16_t* out);
+/* Median post-filter of a checked map (win 3 or 5; 0 or 1 copies). */
+void orc_median(int32_t win, const int16_t* in, int32_t w, int32_t h, int16_t* out);
+
 /* ---- whole pipeline with every intermediate ------------------------------ */
 typedef struct orc_trace {
   int32_t w, h, lw, lh, gw, gh, words, D;
@@ -151,11 +193,18 @@ typedef struct orc_trace {
   int16_t* outL; int16_t* outR;               /* h*w */
   int64_t support_evals, dense_evals;
   double stage_ms[6]; /* descriptor, support+filter, triangulate, raster+grid, dense, lrcheck */
+  int32_t swords, dwords;                     /* census words per pixel (census mode) */
+  uint32_t* csupL; uint32_t* csupR;           /* h*w*swords, support census */
+  uint32_t* cdenL; uint32_t* cdenR;           /* h*w*dwords, dense census */
+  int16_t* chkL; int16_t* chkR;               /* h*w, checked maps before the median */
+  int32_t nL_all;                             /* left list size before down-sampling */
 } orc_trace;
 
 /* Runs every stage; allocates the trace arrays (free with orc_trace_free).
  * Returns 0, -1 if the inputs violate the preconditions (9 <= w, h <= 8192,
- * 0 <= disp_min <= disp_max, D <= 256, positive step/grid/beta/gamma/sigma),
+ * 0 <= disp_min <= disp_max, D <= 256, positive step/grid/beta/gamma/sigma,
+ * descriptor/ambiguity/redundancy 0 or 1, census windows odd within their
+ * ranges, 1 <= support_subsample <= 64, median_window 0, 1, 3 or 5),
  * or -2 if a triangulation failed its own consistency checks. */
 int32_t orc_process(const orc_params* p, const uint8_t* left, const uint8_t* right,
                     int32_t w, int32_t h, int32_t stride, orc_trace* t);

@@ -189,7 +189,7 @@ static int search(const orc_params* p, const uint8_t* dself, const uint8_t* doth
   for (int32_t d = p->disp_min; d <= dhi; ++d)
     if (d != d1 && cost[d - p->disp_min] < m2) m2 = cost[d - p->disp_min];
   *evals += n;
-  if (!orc_ratio_accept(p->support_threshold, m1, m2)) return 0;
+  if (!orc_support_accept(p, m1, m2)) return 0;
   *d_out = d1;
   return 1;
 }
@@ -307,7 +307,9 @@ void orc_filter_redun(const orc_params* p, const int16_t* in, int32_t lw,
  * where two land on the same pixel the larger disparity (the nearer surface)
  * is kept; ordered by (v, u). Image corners (reading): each corner takes the
  * d of the nearest list point by squared distance, the earlier point in list
- * order on ties. With an empty list the corners are -1.
+ * order on ties. With an empty list the corners are -1. Down-sampling
+ * (orc_subsample) thins the left list first; everything after uses the kept
+ * points only.
  * ---------------------------------------------------------------------- */
 static int cmp_right(const void* a, const void* b) {
   const int32_t* x = (const int32_t*)a;
@@ -354,6 +356,7 @@ void orc_support_lists(const orc_params* p, const int16_t* dcan, int32_t lw,
       ptsL[3 * n + 2] = d;
       ++n;
     }
+  n = orc_subsample(ptsL, n, p->support_subsample);
   *nL = n;
   int32_t* tmp = (int32_t*)malloc(sizeof(int32_t) * 3 * (n > 0 ? n : 1));
   for (int32_t i = 0; i < n; ++i) {

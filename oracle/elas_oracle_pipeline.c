@@ -1,6 +1,7 @@
 /*
- * Oracle, whole pipeline: the stages of Section III-A in order, keeping every
- * intermediate for stage-by-stage comparison.
+ * Oracle, whole pipeline: the stages of Section III-A in order (with the
+ * Section VI variant and the optional steps when the parameters ask for
+ * them), keeping every intermediate for stage-by-stage comparison.
  * TEST INFRASTRUCTURE ONLY (see elas_oracle.h).
  */
 #define _POSIX_C_SOURCE 199309L
@@ -60,7 +61,16 @@ int32_t orc_process(const orc_params* p, const uint8_t* left, const uint8_t* rig
   if (w < 9 || h < 9 || stride < w || p->disp_min < 0 || p->disp_max < p->disp_min ||
       p->disp_max - p->disp_min + 1 > 256 || p->candidate_stepsize <= 0 ||
       p->grid_size <= 0 || !(p->beta > 0) || !(p->gamma > 0) || !(p->sigma > 0) ||
-      w > 8192 || h > 8192)
+      w > 8192 || h > 8192 || (p->descriptor != 0 && p->descriptor != 1) ||
+      (p->ambiguity != 0 && p->ambiguity != 1) || (p->redundancy != 0 && p->redundancy != 1) ||
+      p->support_subsample < 1 || p->support_subsample > 64 ||
+      (p->median_window != 0 && p->median_window != 1 && p->median_window != 3 &&
+       p->median_window != 5))
+    return -1;
+  if (p->descriptor == 1 &&
+      (p->census_support_window < 3 || p->census_support_window > 13 ||
+       p->census_support_window % 2 == 0 || p->census_dense_window < 3 ||
+       p->census_dense_window > 7 || p->census_dense_window % 2 == 0))
     return -1;
   memset(t, 0, sizeof(*t));
   t->w = w;
@@ -69,10 +79,26 @@ int32_t orc_process(const orc_params* p, const uint8_t* left, const uint8_t* rig
   size_t npx = (size_t)w * h;
 
   double t0 = now_ms();
-  t->descL = (uint8_t*)malloc(npx * 16);
-  t->descR = (uint8_t*)malloc(npx * 16);
-  orc_descriptors(left, w, h, stride, t->descL);
-  orc_descriptors(right, w, h, stride, t->descR);
+  const int census = p->descriptor == 1;
+  if (census) {
+    /* Section VI-A: census descriptors of the support and dense windows */
+    int32_t ws = p->census_support_window, wd = p->census_dense_window;
+    t->swords = (ws * ws + 31) / 32;
+    t->dwords = (wd * wd + 31) / 32;
+    t->csupL = (uint32_t*)malloc(npx * t->swords * sizeof(uint32_t));
+    t->csupR = (uint32_t*)malloc(npx * t->swords * sizeof(uint32_t));
+    t->cdenL = (uint32_t*)malloc(npx * t->dwords * sizeof(uint32_t));
+    t->cdenR = (uint32_t*)malloc(npx * t->dwords * sizeof(uint32_t));
+    orc_census(left, w, h, stride, ws, t->csupL, t->swords);
+    orc_census(right, w, h, stride, ws, t->csupR, t->swords);
+    orc_census(left, w, h, stride, wd, t->cdenL, t->dwords);
+    orc_census(right, w, h, stride, wd, t->cdenR, t->dwords);
+  } else {
+    t->descL = (uint8_t*)malloc(npx * 16);
+    t->descR = (uint8_t*)malloc(npx * 16);
+    orc_descriptors(left, w, h, stride, t->descL);
+    orc_descriptors(right, w, h, stride, t->descR);
+  }
   double t1 = now_ms();
 
   int32_t u0, v0;
@@ -83,10 +109,21 @@ int32_t orc_process(const orc_params* p, const uint8_t* left, const uint8_t* rig
   t->dcan_incon = (int16_t*)malloc(nlc * sizeof(int16_t));
   t->dcan_vert = (int16_t*)malloc(nlc * sizeof(int16_t));
   t->dcan_final = (int16_t*)malloc(nlc * sizeof(int16_t));
-  orc_support_match(p, t->descL, t->descR, w, h, t->dcan_raw, &t->support_evals);
+  if (census)
+    orc_support_match_census(p, t->csupL, t->csupR, t->swords, w, h, t->dcan_raw,
+                             &t->support_evals);
+  else
+    orc_support_match(p, t->descL, t->descR, w, h, t->dcan_raw, &t->support_evals);
   orc_filter_incon(p, t->dcan_raw, t->lw, t->lh, t->dcan_incon);
-  orc_filter_redun(p, t->dcan_incon, t->lw, t->lh, 1, t->dcan_vert);
-  orc_filter_redun(p, t->dcan_vert, t->lw, t->lh, 0, t->dcan_final);
+  if (p->redundancy == 1) { /* Section VI-C, Fig. 7B */
+    orc_filter_redun_past(p, t->dcan_incon, t->lw, t->lh, 1, t->dcan_vert);
+    orc_filter_redun_past(p, t->dcan_vert, t->lw, t->lh, 0, t->dcan_final);
+  } else {
+    orc_filter_redun(p, t->dcan_incon, t->lw, t->lh, 1, t->dcan_vert);
+    orc_filter_redun(p, t->dcan_vert, t->lw, t->lh, 0, t->dcan_final);
+  }
+  t->nL_all = 0;
+  for (size_t i = 0; i < nl; ++i) t->nL_all += t->dcan_final[i] >= 0;
   t->ptsL = (int32_t*)malloc(nlc * 3 * sizeof(int32_t));
   t->ptsR = (int32_t*)malloc(nlc * 3 * sizeof(int32_t));
   orc_support_lists(p, t->dcan_final, t->lw, t->lh, w, h, t->ptsL, &t->nL, t->cornersL,
@@ -125,14 +162,26 @@ int32_t orc_process(const orc_params* p, const uint8_t* left, const uint8_t* rig
 
   t->rawL = (int16_t*)malloc(npx * sizeof(int16_t));
   t->rawR = (int16_t*)malloc(npx * sizeof(int16_t));
-  t->dense_evals = orc_dense(p, t->descL, t->descR, t->dplaneL, t->gridL, has_list, t->lut,
-                             w, h, 0, t->rawL);
-  t->dense_evals += orc_dense(p, t->descR, t->descL, t->dplaneR, t->gridR, has_list, t->lut,
-                              w, h, 1, t->rawR);
+  if (census) {
+    t->dense_evals = orc_dense_census(p, t->cdenL, t->cdenR, t->dwords, t->dplaneL, t->gridL,
+                                      has_list, t->lut, w, h, 0, t->rawL);
+    t->dense_evals += orc_dense_census(p, t->cdenR, t->cdenL, t->dwords, t->dplaneR,
+                                       t->gridR, has_list, t->lut, w, h, 1, t->rawR);
+  } else {
+    t->dense_evals = orc_dense(p, t->descL, t->descR, t->dplaneL, t->gridL, has_list, t->lut,
+                               w, h, 0, t->rawL);
+    t->dense_evals += orc_dense(p, t->descR, t->descL, t->dplaneR, t->gridR, has_list,
+                                t->lut, w, h, 1, t->rawR);
+  }
   double t5 = now_ms();
+  t->chkL = (int16_t*)malloc(npx * sizeof(int16_t));
+  t->chkR = (int16_t*)malloc(npx * sizeof(int16_t));
   t->outL = (int16_t*)malloc(npx * sizeof(int16_t));
   t->outR = (int16_t*)malloc(npx * sizeof(int16_t));
-  orc_lrcheck(p, t->rawL, t->rawR, w, h, t->outL, t->outR);
+  orc_lrcheck(p, t->rawL, t->rawR, w, h, t->chkL, t->chkR);
+  /* Section VIII: optional median post-filter of the checked maps */
+  orc_median(p->median_window, t->chkL, w, h, t->outL);
+  orc_median(p->median_window, t->chkR, w, h, t->outR);
   double t6 = now_ms();
   t->stage_ms[0] = t1 - t0;
   t->stage_ms[1] = t2 - t1;
@@ -147,7 +196,8 @@ void orc_trace_free(orc_trace* t) {
   void* ptrs[] = {t->descL, t->descR, t->dcan_raw, t->dcan_incon, t->dcan_vert,
                   t->dcan_final, t->ptsL, t->ptsR, t->recL, t->recR, t->planeL,
                   t->planeR, t->ownerL, t->ownerR, t->dplaneL, t->dplaneR, t->gridL,
-                  t->gridR, t->lut, t->rawL, t->rawR, t->outL, t->outR};
+                  t->gridR, t->lut, t->rawL, t->rawR, t->outL, t->outR,
+                  t->csupL, t->csupR, t->cdenL, t->cdenR, t->chkL, t->chkR};
   for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(ptrs[i]);
   memset(t, 0, sizeof(*t));
 }

@@ -13,14 +13,17 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liborc_elas.so")
-SOURCES = ["elas_oracle_match.c", "elas_oracle_mesh.c", "elas_oracle_pipeline.c"]
+SOURCES = ["elas_oracle_match.c", "elas_oracle_mesh.c", "elas_oracle_pipeline.c",
+           "elas_oracle_variant.c"]
 
 DEFAULTS = dict(
     disp_min=0, disp_max=127, support_threshold=0.85, support_texture=10,
     candidate_stepsize=5, incon_window_size=5, incon_threshold=5,
     incon_min_support=5, redun_max_dist=5, redun_threshold=1, grid_size=20,
     beta=0.02, gamma=3.0, sigma=1.0, sradius=2, match_texture=1,
-    lr_threshold=2, full_search=0)
+    lr_threshold=2, full_search=0, descriptor=0, census_support_window=9,
+    census_dense_window=5, ambiguity=0, redundancy=0, support_subsample=1,
+    median_window=0)
 
 
 class OrcParams(C.Structure):
@@ -33,6 +36,10 @@ class OrcParams(C.Structure):
         ("grid_size", C.c_int32), ("beta", C.c_float), ("gamma", C.c_float),
         ("sigma", C.c_float), ("sradius", C.c_int32), ("match_texture", C.c_int32),
         ("lr_threshold", C.c_int32), ("full_search", C.c_int32),
+        ("descriptor", C.c_int32), ("census_support_window", C.c_int32),
+        ("census_dense_window", C.c_int32), ("ambiguity", C.c_int32),
+        ("redundancy", C.c_int32), ("support_subsample", C.c_int32),
+        ("median_window", C.c_int32),
     ]
 
 
@@ -60,6 +67,11 @@ class OrcTrace(C.Structure):
         ("outL", _P16), ("outR", _P16),
         ("support_evals", C.c_int64), ("dense_evals", C.c_int64),
         ("stage_ms", C.c_double * 6),
+        ("swords", C.c_int32), ("dwords", C.c_int32),
+        ("csupL", C.POINTER(C.c_uint32)), ("csupR", C.POINTER(C.c_uint32)),
+        ("cdenL", C.POINTER(C.c_uint32)), ("cdenR", C.POINTER(C.c_uint32)),
+        ("chkL", _P16), ("chkR", _P16),
+        ("nL_all", C.c_int32),
     ]
 
 
@@ -120,6 +132,27 @@ def lib():
                                   C.c_int32, C.POINTER(OrcTrace)]
         L.orc_process.restype = C.c_int32
         L.orc_trace_free.argtypes = [C.POINTER(OrcTrace)]
+        L.orc_census.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int32]
+        L.orc_hamming.argtypes = [vp, vp, C.c_int32]
+        L.orc_hamming.restype = C.c_int32
+        L.orc_census_texture.argtypes = [vp, C.c_int32]
+        L.orc_census_texture.restype = C.c_int32
+        L.orc_shiftsum_threshold.argtypes = [C.c_int32]
+        L.orc_shiftsum_threshold.restype = C.c_int32
+        L.orc_shiftsum_accept.argtypes = [C.c_int32, C.c_int32]
+        L.orc_shiftsum_accept.restype = C.c_int32
+        L.orc_support_accept.argtypes = [C.POINTER(OrcParams), C.c_int32, C.c_int32]
+        L.orc_support_accept.restype = C.c_int32
+        L.orc_support_match_census.argtypes = [C.POINTER(OrcParams), vp, vp, C.c_int32,
+                                               C.c_int32, C.c_int32, vp, vp]
+        L.orc_filter_redun_past.argtypes = [C.POINTER(OrcParams), vp, C.c_int32, C.c_int32,
+                                            C.c_int32, vp]
+        L.orc_subsample.argtypes = [vp, C.c_int32, C.c_int32]
+        L.orc_subsample.restype = C.c_int32
+        L.orc_dense_census.argtypes = [C.POINTER(OrcParams), vp, vp, C.c_int32, vp, vp,
+                                       C.c_int32, vp, C.c_int32, C.c_int32, C.c_int32, vp]
+        L.orc_dense_census.restype = C.c_int64
+        L.orc_median.argtypes = [C.c_int32, vp, C.c_int32, C.c_int32, vp]
         _lib = L
     return _lib
 
@@ -291,6 +324,89 @@ def lrcheck(p: OrcParams, rawL, rawR):
     return oL, oR
 
 
+# ---------------------------------------------------------------- Section VI variant
+def census_words(win: int) -> int:
+    return (win * win + 31) // 32
+
+
+def census(img: np.ndarray, win: int) -> np.ndarray:
+    """[h, w, words] uint32 census descriptors of a win x win window."""
+    img = np.ascontiguousarray(img, np.uint8)
+    h, w = img.shape
+    words = census_words(win)
+    out = np.zeros((h, w, words), np.uint32)
+    lib().orc_census(_ptr(img), w, h, w, win, _ptr(out), words)
+    return out
+
+
+def hamming(a: np.ndarray, b: np.ndarray) -> int:
+    a = np.ascontiguousarray(a, np.uint32)
+    b = np.ascontiguousarray(b, np.uint32)
+    return int(lib().orc_hamming(_ptr(a), _ptr(b), a.size))
+
+
+def census_texture(a: np.ndarray) -> int:
+    a = np.ascontiguousarray(a, np.uint32)
+    return int(lib().orc_census_texture(_ptr(a), a.size))
+
+
+def shiftsum_threshold(m2: int) -> int:
+    return int(lib().orc_shiftsum_threshold(m2))
+
+
+def shiftsum_accept(m1: int, m2: int) -> bool:
+    return bool(lib().orc_shiftsum_accept(m1, m2))
+
+
+def support_accept(p: OrcParams, m1: int, m2: int) -> bool:
+    return bool(lib().orc_support_accept(C.byref(p), m1, m2))
+
+
+def support_match_census(p: OrcParams, csL: np.ndarray, csR: np.ndarray):
+    h, w, words = csL.shape
+    lw, lh, _, _ = lattice(p, w, h)
+    out = np.zeros((lh, lw), np.int16)
+    ev = np.zeros(1, np.int64)
+    lib().orc_support_match_census(C.byref(p), _ptr(np.ascontiguousarray(csL, np.uint32)),
+                                   _ptr(np.ascontiguousarray(csR, np.uint32)), words, w, h,
+                                   _ptr(out), _ptr(ev))
+    return out, int(ev[0])
+
+
+def filter_redun_past(p: OrcParams, dcan: np.ndarray, vertical: bool) -> np.ndarray:
+    dcan = np.ascontiguousarray(dcan, np.int16)
+    out = np.zeros_like(dcan)
+    lib().orc_filter_redun_past(C.byref(p), _ptr(dcan), dcan.shape[1], dcan.shape[0],
+                                int(vertical), _ptr(out))
+    return out
+
+
+def subsample(pts: np.ndarray, k: int) -> np.ndarray:
+    pts = np.array(pts, np.int32).reshape(-1, 3)
+    n = lib().orc_subsample(_ptr(pts), len(pts), k)
+    return pts[:n].copy()
+
+
+def dense_census(p: OrcParams, c_self, c_other, dplane, grid_, has_list: bool, lut,
+                 right_frame: bool):
+    h, w, words = c_self.shape
+    out = np.zeros((h, w), np.int16)
+    ev = lib().orc_dense_census(C.byref(p), _ptr(np.ascontiguousarray(c_self, np.uint32)),
+                                _ptr(np.ascontiguousarray(c_other, np.uint32)), words,
+                                _ptr(np.ascontiguousarray(dplane, np.int16)),
+                                _ptr(np.ascontiguousarray(grid_, np.uint64)), int(has_list),
+                                _ptr(np.ascontiguousarray(lut, np.int32)), w, h,
+                                int(right_frame), _ptr(out))
+    return out, int(ev)
+
+
+def median(win: int, disp: np.ndarray) -> np.ndarray:
+    disp = np.ascontiguousarray(disp, np.int16)
+    out = np.zeros_like(disp)
+    lib().orc_median(win, _ptr(disp), disp.shape[1], disp.shape[0], _ptr(out))
+    return out
+
+
 # ---------------------------------------------------------------- pipeline
 @dataclass
 class Trace:
@@ -324,6 +440,13 @@ class Trace:
     support_evals: int
     dense_evals: int
     stage_ms: tuple
+    csupL: np.ndarray
+    csupR: np.ndarray
+    cdenL: np.ndarray
+    cdenR: np.ndarray
+    chkL: np.ndarray
+    chkR: np.ndarray
+    nL_all: int
 
 
 def _arr(ptr, shape, dtype):
@@ -366,6 +489,12 @@ def process(p: OrcParams, left: np.ndarray, right: np.ndarray) -> Trace:
             outL=_arr(t.outL, (h, w), np.int16), outR=_arr(t.outR, (h, w), np.int16),
             support_evals=int(t.support_evals), dense_evals=int(t.dense_evals),
             stage_ms=tuple(t.stage_ms[:]),
+            csupL=_arr(t.csupL, (h, w, t.swords), np.uint32),
+            csupR=_arr(t.csupR, (h, w, t.swords), np.uint32),
+            cdenL=_arr(t.cdenL, (h, w, t.dwords), np.uint32),
+            cdenR=_arr(t.cdenR, (h, w, t.dwords), np.uint32),
+            chkL=_arr(t.chkL, (h, w), np.int16), chkR=_arr(t.chkR, (h, w), np.int16),
+            nL_all=int(t.nL_all),
         )
     finally:
         lib().orc_trace_free(C.byref(t))
