@@ -75,6 +75,28 @@ typedef struct elas_params {
   int32_t mesh_on_host;        /* 1: triangulate on the host between the two GPU
                                   phases, as the paper's CPU/FPGA split does
                                   (Section IV); 0: on the device (0) */
+  /* The embedded variant (Section VI) and the optional steps. */
+  int32_t descriptor;          /* 0: Sobel descriptors + SAD; 1: census descriptors
+                                  + Hamming distance, Section VI-A (0). Census bit i
+                                  = i-th window offset in row-major order, set iff
+                                  that neighbour is inside the image and darker than
+                                  the centre; texture = number of set bits */
+  int32_t census_support_window; /* support census window, odd 3..13 (9) */
+  int32_t census_dense_window; /* dense census window, odd 3..7 (5) */
+  int32_t ambiguity;           /* 0: eq. 1-2 ratio test; 1: eq. 3 shift-sum, keep iff
+                                  m1 <= m2/2 + m2/4 + m2/8 + m2/32 (truncating) (0) */
+  int32_t redundancy;          /* 0: two-sided redundancy (Fig. 7A); 1: past-only
+                                  (Section VI-C, Fig. 7B): down each lattice column,
+                                  then along each row, a point goes iff a point that
+                                  survived the pass lies within redun_max_dist
+                                  earlier positions with |d'-d| <= redun_threshold (0) */
+  int32_t support_subsample;   /* 1..64: keep the support points whose index in
+                                  lattice order is a multiple of k, before the right
+                                  list, corners and grid vectors (Section VII-B) (1) */
+  int32_t median_window;       /* 0 or 1: none; 3 or 5: median of the checked maps
+                                  (Section VIII): invalid pixels stay invalid, valid
+                                  ones take the lower median of the valid values in
+                                  the window clipped to the image (0) */
 } elas_params;
 
 typedef struct elas_handle elas_handle;
@@ -293,7 +315,14 @@ enum elas_intermediate {
   ELAS_I_GRID_LEFT = 17, ELAS_I_GRID_RIGHT = 18,
   ELAS_I_RAW_LEFT = 19, ELAS_I_RAW_RIGHT = 20,
   ELAS_I_LUT = 21,
-  ELAS_I_COUNT = 22
+  /* census mode: dense census, one uint64 per pixel [h][w]; support census of
+   * the lattice rows [lh][w][4 * q] uint32 words, q = 1 for windows up to 11,
+   * 2 for 13 (zero-padded) */
+  ELAS_I_CENSUS_DENSE_LEFT = 22, ELAS_I_CENSUS_DENSE_RIGHT = 23,
+  ELAS_I_CENSUS_SUPPORT_LEFT = 24, ELAS_I_CENSUS_SUPPORT_RIGHT = 25,
+  /* median mode: the checked maps before the median [h][w] int16 */
+  ELAS_I_CHECKED_LEFT = 26, ELAS_I_CHECKED_RIGHT = 27,
+  ELAS_I_COUNT = 28
 };
 ELAS_API int elas_get_intermediate(elas_handle* h, int32_t which, void* dst_host,
                                    int64_t bytes, int64_t* needed);

@@ -2,8 +2,9 @@
 // device buffers, and the stage chain of one stereo pair.
 //
 // Stage chain of elas_process on the caller's stream:
-//   k_descriptor (both views) -> k_support -> k_filter -> k_rows -> mesh
-//   -> k_raster -> k_dense (both views) -> k_lrcheck.
+//   k_descriptor (both views; Sobel or census) -> k_support -> k_filter
+//   [-> k_redun, past-only redundancy] -> k_rows -> mesh -> k_raster
+//   -> k_dense (both views) -> k_lrcheck [-> k_median].
 // The mesh step runs either on the device (k_mesh, the default: the frame
 // never returns to the host, so the call only enqueues work) or, with
 // mesh_on_host, on the host between the two GPU phases as in the paper's
@@ -94,6 +95,9 @@ struct Buffers {
   int32_t ntmax = 0;             // triangle capacity per view (2 * lattice + 2)
   void* dev_block = nullptr;     // every device array, carved below
   uint8_t *descL = nullptr, *descR = nullptr;
+  uint4 *csupL = nullptr, *csupR = nullptr;  // census mode: support census
+  int16_t *chkL = nullptr, *chkR = nullptr;  // median mode: checked maps
+  size_t desc_bytes = 0, csup_bytes = 0;
   int16_t *dcan_raw = nullptr, *dcan_incon = nullptr, *dcan_vert = nullptr,
           *dcan_final = nullptr;
   int32_t* evals = nullptr;
@@ -225,8 +229,9 @@ struct BufLayout {
   Geometry g{};
   size_t nlat = 0, nrows = 0;
   int32_t ntmax = 0;
-  size_t descL, descR, raw0, inc, vert, fin, evals, gL, gR, oL, oR, dpL, dpR, rL, rR, lut, cnt,
-      rowsL, rowsR, rc, hdr, pL, pR, recL, recR, plL, plR, tris, ms;
+  size_t descL, descR, csL, csR, raw0, inc, vert, fin, evals, gL, gR, oL, oR, dpL, dpR, rL, rR,
+      lut, cnt, rowsL, rowsR, rc, hdr, pL, pR, recL, recR, plL, plR, tris, ms, chL, chR;
+  size_t desc_bytes = 0, csup_bytes = 0;
   size_t total = 0;
 };
 
@@ -248,8 +253,17 @@ BufLayout buffer_layout(const elas_params& p, int32_t w, int32_t hp) {
     off = align_up(off + bytes, 256);
     return o;
   };
-  L.descL = take(npx * 16);
-  L.descR = take(npx * 16);
+  // descriptors: 16 bytes per pixel, or one uint64 of dense census per pixel
+  // plus the support census of the lattice rows
+  const bool census = p.descriptor == 1;
+  const int32_t sw = p.census_support_window;
+  const size_t cs_q = (sw * sw + 31) / 32 <= 4 ? 1 : 2;
+  L.desc_bytes = npx * (census ? 8 : 16);
+  L.csup_bytes = census ? (size_t)g.lh * w * cs_q * 16 : 0;
+  L.descL = take(L.desc_bytes);
+  L.descR = take(L.desc_bytes);
+  L.csL = take(L.csup_bytes);
+  L.csR = take(L.csup_bytes);
   L.raw0 = take(nlat * 2);
   L.inc = take(nlat * 2);
   L.vert = take(nlat * 2);
@@ -279,6 +293,9 @@ BufLayout buffer_layout(const elas_params& p, int32_t w, int32_t hp) {
   // frames above the device mesh limit are always meshed on the host
   const bool dev_mesh = w <= kDeviceMeshMaxSide && hp <= kDeviceMeshMaxSide;
   L.ms = take(dev_mesh ? 2 * mesh_global_scratch_per_view(g) : 0);
+  const size_t nchk = p.median_window > 1 ? npx * 2 : 0;
+  L.chL = take(nchk);
+  L.chR = take(nchk);
   L.total = off;
   return L;
 }
@@ -309,6 +326,12 @@ int alloc_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   auto at = [&](size_t o) { return static_cast<void*>(base + o); };
   b->descL = static_cast<uint8_t*>(at(o_descL));
   b->descR = static_cast<uint8_t*>(at(o_descR));
+  b->desc_bytes = Lo.desc_bytes;
+  b->csup_bytes = Lo.csup_bytes;
+  b->csupL = Lo.csup_bytes ? static_cast<uint4*>(at(Lo.csL)) : nullptr;
+  b->csupR = Lo.csup_bytes ? static_cast<uint4*>(at(Lo.csR)) : nullptr;
+  b->chkL = h->params.median_window > 1 ? static_cast<int16_t*>(at(Lo.chL)) : nullptr;
+  b->chkR = h->params.median_window > 1 ? static_cast<int16_t*>(at(Lo.chR)) : nullptr;
   b->dcan_raw = static_cast<int16_t*>(at(o_raw0));
   b->dcan_incon = static_cast<int16_t*>(at(o_inc));
   b->dcan_vert = static_cast<int16_t*>(at(o_vert));
@@ -415,6 +438,10 @@ Frame make_frame(const elas_handle* h, const Buffers* b, const uint8_t* left,
   f.right = right;
   f.descL = b->descL;
   f.descR = b->descR;
+  f.csupL = b->csupL;
+  f.csupR = b->csupR;
+  f.chkL = b->chkL;
+  f.chkR = b->chkR;
   f.dcan_raw = b->dcan_raw;
   f.dcan_incon = b->dcan_incon;
   f.dcan_vert = b->dcan_vert;
@@ -609,6 +636,13 @@ void elas_params_default(elas_params* p) {
   p->lr_threshold = 2;
   p->full_search = 0;
   p->mesh_on_host = 0;
+  p->descriptor = 0;
+  p->census_support_window = 9;
+  p->census_dense_window = 5;
+  p->ambiguity = 0;
+  p->redundancy = 0;
+  p->support_subsample = 1;
+  p->median_window = 0;
 }
 
 int elas_create(const elas_params* p, elas_handle** out) {
@@ -633,6 +667,20 @@ int elas_create(const elas_params* p, elas_handle** out) {
     return fail(nullptr, ELAS_ERR_ARG, "mesh_on_host must be 0 or 1");
   if (p->incon_window_size > 16 || p->redun_max_dist > 16)
     return fail(nullptr, ELAS_ERR_UNSUPPORTED, "filter windows above 16 lattice steps");
+  if ((p->descriptor != 0 && p->descriptor != 1) || (p->ambiguity != 0 && p->ambiguity != 1) ||
+      (p->redundancy != 0 && p->redundancy != 1))
+    return fail(nullptr, ELAS_ERR_ARG, "descriptor, ambiguity and redundancy must be 0 or 1");
+  if (p->descriptor == 1 &&
+      (p->census_support_window < 3 || p->census_support_window > 13 ||
+       p->census_support_window % 2 == 0 || p->census_dense_window < 3 ||
+       p->census_dense_window > 7 || p->census_dense_window % 2 == 0))
+    return fail(nullptr, ELAS_ERR_ARG,
+                "census windows must be odd: support 3..13, dense 3..7");
+  if (p->support_subsample < 1 || p->support_subsample > 64)
+    return fail(nullptr, ELAS_ERR_ARG, "support_subsample must be 1..64");
+  if (p->median_window != 0 && p->median_window != 1 && p->median_window != 3 &&
+      p->median_window != 5)
+    return fail(nullptr, ELAS_ERR_ARG, "median_window must be 0, 1, 3 or 5");
   // Prior energy of a candidate at distance k from the plane mean: the ELAS
   // plane prior gamma + exp(-k^2 / (2 sigma^2)) as a negative log, over beta,
   // offset by log(gamma)/beta so that far candidates cost 0; rounded.
@@ -668,6 +716,14 @@ int elas_create(const elas_params* p, elas_handle** out) {
   k.lr_threshold = p->lr_threshold;
   k.full_search = p->full_search;
   k.lut_bias = -h->lut[0];
+  k.descriptor = p->descriptor;
+  k.cs_win = p->census_support_window;
+  k.cd_win = p->census_dense_window;
+  k.cs_q = (k.cs_win * k.cs_win + 31) / 32 <= 4 ? 1 : 2;
+  k.ambiguity = p->ambiguity;
+  k.redundancy = p->redundancy;
+  k.subsample = p->support_subsample;
+  k.median = p->median_window > 1 ? p->median_window : 0;
   h->meshL = mesh_scratch_create();
   h->meshR = mesh_scratch_create();
   *out = h;
@@ -746,6 +802,7 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   HIP_TRY(launch_stage(kStageSupport, F, 0, stream));
   STAGE_MARK(2);
   HIP_TRY(launch_stage(kStageFilter, F, 0, stream));
+  HIP_TRY(launch_stage(kStageRedun, F, 0, stream));
   STAGE_MARK(3);
   HIP_TRY(launch_stage(kStageRows, F, 0, stream));
   STAGE_MARK(4);
@@ -761,6 +818,7 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   HIP_TRY(launch_stage(kStageDense, F, var.second, stream));
   STAGE_MARK(7);
   HIP_TRY(launch_stage(kStageCheck, F, 0, stream));
+  HIP_TRY(launch_stage(kStageMedian, F, 0, stream));
   STAGE_MARK(8);
 #undef STAGE_MARK
   h->have_timing = timed;
@@ -818,7 +876,7 @@ void plan_batch(const std::vector<Frame>& frames, const std::vector<std::pair<in
         if (tiled && fv != v) continue;
         const int dv = st == kStageDescriptor ? v : 0;
         sub.push_back(frames[i]);
-        starts.push_back(starts.back() + stage_blocks(st, frames[i].g, dv));
+        starts.push_back(starts.back() + stage_blocks(st, frames[i].g, frames[i].p, dv));
         lds = std::max(lds, stage_lds(st, frames[i].g, frames[i].p));
       }
       if (sub.empty()) continue;
@@ -869,7 +927,7 @@ int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
     for (int v = 0; v < 3; ++v) {
       std::vector<int32_t> starts(1, 0);
       for (const Frame& f : frames)
-        starts.push_back(starts.back() + stage_blocks(stages[k], f.g, k == 0 ? v : 0));
+        starts.push_back(starts.back() + stage_blocks(stages[k], f.g, f.p, k == 0 ? v : 0));
       uint8_t* dev = static_cast<uint8_t*>(c->tune_dev);
       const size_t soff = align256(frames.size() * sizeof(Frame));
       HIP_TRY(hipMemcpy(dev, frames.data(), frames.size() * sizeof(Frame), hipMemcpyHostToDevice));
@@ -1123,8 +1181,30 @@ int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t byte
   const void* hsrc = nullptr;
   int64_t size = 0;
   switch (which) {
-    case ELAS_I_DESC_LEFT: dsrc = b->descL; size = npx * 16; break;
-    case ELAS_I_DESC_RIGHT: dsrc = b->descR; size = npx * 16; break;
+    case ELAS_I_DESC_LEFT:
+      if (h->params.descriptor) return fail(h, ELAS_ERR_ARG, "census mode has no gradient descriptors");
+      dsrc = b->descL; size = npx * 16; break;
+    case ELAS_I_DESC_RIGHT:
+      if (h->params.descriptor) return fail(h, ELAS_ERR_ARG, "census mode has no gradient descriptors");
+      dsrc = b->descR; size = npx * 16; break;
+    case ELAS_I_CENSUS_DENSE_LEFT:
+    case ELAS_I_CENSUS_DENSE_RIGHT:
+      if (!h->params.descriptor) return fail(h, ELAS_ERR_ARG, "not in census mode");
+      dsrc = which == ELAS_I_CENSUS_DENSE_LEFT ? b->descL : b->descR;
+      size = npx * 8;
+      break;
+    case ELAS_I_CENSUS_SUPPORT_LEFT:
+    case ELAS_I_CENSUS_SUPPORT_RIGHT:
+      if (!h->params.descriptor) return fail(h, ELAS_ERR_ARG, "not in census mode");
+      dsrc = which == ELAS_I_CENSUS_SUPPORT_LEFT ? (const void*)b->csupL : (const void*)b->csupR;
+      size = (int64_t)b->csup_bytes;
+      break;
+    case ELAS_I_CHECKED_LEFT:
+    case ELAS_I_CHECKED_RIGHT:
+      if (h->params.median_window <= 1) return fail(h, ELAS_ERR_ARG, "no median filter set");
+      dsrc = which == ELAS_I_CHECKED_LEFT ? b->chkL : b->chkR;
+      size = npx * 2;
+      break;
     case ELAS_I_DCAN_RAW: dsrc = b->dcan_raw; size = nlat * 2; break;
     case ELAS_I_DCAN_INCON: dsrc = b->dcan_incon; size = nlat * 2; break;
     case ELAS_I_DCAN_VERT: dsrc = b->dcan_vert; size = nlat * 2; break;

@@ -35,6 +35,15 @@ struct KParams {
   int32_t redun_max_dist, redun_threshold;
   int32_t grid_size, sradius, match_texture, lr_threshold, full_search;
   int32_t lut_bias;   // -lut[0]: makes every energy non-negative for key packing
+  // Section VI variant and optional steps
+  int32_t descriptor;   // 0: Sobel descriptors + SAD; 1: census + Hamming
+  int32_t cs_win;       // support census window (odd, 3..13)
+  int32_t cd_win;       // dense census window (odd, 3..7)
+  int32_t cs_q;         // 16-byte words per support census descriptor (1 or 2)
+  int32_t ambiguity;    // 0: ratio test (eq. 1-2); 1: shift-sum (eq. 3)
+  int32_t redundancy;   // 0: two-sided; 1: past-only
+  int32_t subsample;    // keep every k-th support point
+  int32_t median;       // 0: no median; 3 or 5: median window
 };
 
 // One triangle as the raster and dense kernels read it: integer vertices in
@@ -82,8 +91,10 @@ struct Frame {
   int32_t raster_rows;   // band height of the raster
   const uint8_t* left;
   const uint8_t* right;
-  uint8_t* descL;
+  uint8_t* descL;        // gradient: 16 bytes per pixel; census: one uint64 per pixel
   uint8_t* descR;
+  uint4* csupL;          // census mode: support census of the lattice rows [lh][w][cs_q]
+  uint4* csupR;
   int16_t* dcan_raw;
   int16_t* dcan_incon;
   int16_t* dcan_vert;
@@ -114,6 +125,8 @@ struct Frame {
   int32_t* dense_counts;  // candidate evaluations per dense block
   int16_t* outL;
   int16_t* outR;
+  int16_t* chkL;         // median mode: checked maps before the median
+  int16_t* chkR;
 };
 
 // Pointers read from the frame table are rebuilt as offsets from the table's
@@ -130,6 +143,8 @@ __device__ __forceinline__ Frame global_frame(const Frame& t, const char* base) 
   F.right = rebase(base, F.right);
   F.descL = rebase(base, F.descL);
   F.descR = rebase(base, F.descR);
+  F.csupL = rebase(base, F.csupL);
+  F.csupR = rebase(base, F.csupR);
   F.dcan_raw = rebase(base, F.dcan_raw);
   F.dcan_incon = rebase(base, F.dcan_incon);
   F.dcan_vert = rebase(base, F.dcan_vert);
@@ -159,19 +174,25 @@ __device__ __forceinline__ Frame global_frame(const Frame& t, const char* base) 
   F.dense_counts = rebase(base, F.dense_counts);
   F.outL = rebase(base, F.outL);
   F.outR = rebase(base, F.outR);
+  F.chkL = rebase(base, F.chkL);
+  F.chkR = rebase(base, F.chkR);
   return F;
 }
 
 // Stages of the path, in launch order.
+// kStageRedun (past-only redundancy) and kStageMedian have no blocks unless
+// the parameters select them.
 enum Stage : int32_t {
   kStageDescriptor = 0,
   kStageSupport,
   kStageFilter,
+  kStageRedun,
   kStageRows,
   kStageMesh,
   kStageRaster,
   kStageDense,
   kStageCheck,
+  kStageMedian,
   kStageCount
 };
 
@@ -180,7 +201,7 @@ constexpr int kDescVariants = 3;   // descriptor rows per block: 4, 8, 16
 constexpr int kDenseVariants = 3;  // dense candidate gathers in flight: 4, 8, 16
 
 // Workgroups one frame needs for a stage (descriptor variant dv).
-int32_t stage_blocks(int32_t stage, const Geometry& g, int dv);
+int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv);
 // Dynamic LDS bytes of a stage for a frame (0 if none).
 size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p);
 // Band height of the raster for an image width.

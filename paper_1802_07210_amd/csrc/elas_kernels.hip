@@ -159,10 +159,103 @@ __device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2: support matching (Section III-A; ambiguity test of Section VI-B,
-// eq. 1-2) with a reverse check. One wavefront per lattice point; lane k
-// evaluates d = dmin + k + 64 j. The 512-bit support descriptor is the four
-// 16-byte descriptors at (u-2, v-2), (u+2, v-2), (u-2, v+2), (u+2, v+2).
+// Stage 1, census variant (Section VI-A: census descriptors over the whole
+// window, compared by Hamming distance). Same 64 x TH tiling; the tile is
+// staged with a 6-pixel halo (13 x 13 windows), positions outside the image
+// holding 255 so that they never count as darker. Bit i of a descriptor is
+// the i-th window offset in row-major order, set iff that neighbour is darker
+// than the centre; a window row of W bits is placed at bit W*dy.
+//  * dense census (window cd_win <= 7, at most 49 bits): one uint64 per pixel,
+//    every pixel;
+//  * support census (window cs_win <= 13, at most 169 bits): lattice rows
+//    only (the support search never reads other rows), cs_q 16-byte words
+//    per pixel, zero-padded.
+// ---------------------------------------------------------------------------
+constexpr int kCensusHalo = 6;
+
+// Bits of rb (at most 13) moved to bit offset s of a 64-bit word (s may be
+// negative: the part of a window row that spills into this word).
+__device__ __forceinline__ uint64_t place_bits(uint32_t rb, int s) {
+  if (s >= 64 || s <= -32) return 0ull;
+  return s >= 0 ? ((uint64_t)rb << s) : (uint64_t)(rb >> (-s));
+}
+
+template <int TH>
+__device__ __forceinline__ void census_body(const Frame& F, int lb) {
+  const Geometry g = F.g;
+  const KParams p = F.p;
+  const int nbx = cdivd(g.w, kDescW);
+  const int view = lb & 1, tile_id = lb >> 1;
+  const uint8_t* img = view ? F.right : F.left;
+  uint64_t* dcen = reinterpret_cast<uint64_t*>(view ? F.descR : F.descL);
+  uint4* scen = view ? F.csupR : F.csupL;
+  const int stride = F.stride;
+  constexpr int H = kCensusHalo, TW = kDescW + 2 * H;
+  __shared__ uint8_t tile[TH + 2 * H][TW];
+  const int u0 = (tile_id % nbx) * kDescW, v0 = (tile_id / nbx) * TH;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < (TH + 2 * H) * TW; i += 256) {
+    const int r = i / TW, c = i - r * TW;
+    const int y = v0 - H + r, x = u0 - H + c;
+    tile[r][c] = (x >= 0 && x < g.w && y >= 0 && y < g.h) ? img[(size_t)y * stride + x] : 255;
+  }
+  __syncthreads();
+  const int tx = tid & 63;
+  const int u = u0 + tx;
+  if (u >= g.w) return;
+  for (int ty = tid >> 6; ty < TH; ty += 4) {
+    const int v = v0 + ty;
+    if (v >= g.h) break;
+    const uint32_t c = tile[ty + H][tx + H];
+    {
+      const int W = p.cd_win, r = W >> 1;
+      uint64_t acc = 0ull;
+      for (int dy = 0; dy < W; ++dy) {
+        const uint8_t* row = &tile[ty + H - r + dy][tx + H - r];
+        uint32_t rb = 0u;
+        for (int dx = 0; dx < W; ++dx) rb |= (uint32_t)(row[dx] < c) << dx;
+        acc |= (uint64_t)rb << (dy * W);
+      }
+      dcen[(size_t)v * g.w + u] = acc;
+    }
+    const int dv = v - g.lv0;
+    if (dv >= 0 && dv % g.step == 0 && dv / g.step < g.lh) {
+      const int l = dv / g.step;
+      const int W = p.cs_win, r = W >> 1;
+      uint64_t a0 = 0ull, a1 = 0ull, a2 = 0ull;
+      for (int dy = 0; dy < W; ++dy) {
+        const uint8_t* row = &tile[ty + H - r + dy][tx + H - r];
+        uint32_t rb = 0u;
+        for (int dx = 0; dx < W; ++dx) rb |= (uint32_t)(row[dx] < c) << dx;
+        const int o = dy * W;
+        a0 |= place_bits(rb, o);
+        a1 |= place_bits(rb, o - 64);
+        a2 |= place_bits(rb, o - 128);
+      }
+      uint4* dst = scen + ((size_t)l * g.w + u) * p.cs_q;
+      dst[0] = make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32));
+      if (p.cs_q == 2) dst[1] = make_uint4((uint32_t)a2, (uint32_t)(a2 >> 32), 0u, 0u);
+    }
+  }
+}
+
+template <int TH>
+__device__ __forceinline__ void stage1_body(const Frame& F, int lb) {
+  if (F.p.descriptor)
+    census_body<TH>(F, lb);
+  else
+    descriptor_body<TH>(F, lb);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: support matching (Section III-A) with a reverse check. One
+// wavefront per lattice point; lane k evaluates d = dmin + k + 64 j.
+// Ambiguity test: eq. 1-2 (m1 < t*m2 in FP32) or the shift-sum of eq. 3
+// (m1 <= m2/2 + m2/4 + m2/8 + m2/32 with truncating shifts). Descriptors:
+//  * gradient: the 512-bit support descriptor is the four 16-byte descriptors
+//    at (u-2, v-2), (u+2, v-2), (u-2, v+2), (u+2, v+2); cost = SAD;
+//  * census: the support-window census of the pixel; cost = Hamming distance;
+//    texture = number of set bits.
 // ---------------------------------------------------------------------------
 struct Desc64 {
   uint4 q[4];
@@ -186,12 +279,62 @@ __device__ __forceinline__ uint32_t texture64(const Desc64& a) {
   return texture16(a.q[0]) + texture16(a.q[1]) + texture16(a.q[2]) + texture16(a.q[3]);
 }
 
+__device__ __forceinline__ bool support_accept(const KParams& p, uint32_t m1, uint32_t m2) {
+  if (p.ambiguity) return m1 <= (m2 >> 1) + (m2 >> 2) + (m2 >> 3) + (m2 >> 5);
+  return (float)m1 < __fmul_rn(p.support_threshold, (float)m2);
+}
+
+// Descriptor sources of the support search: load(x) = descriptor of column x
+// on the point's row; cost(a, b); texture(a).
+struct GradSrc {
+  typedef Desc64 T;
+  const uint8_t* desc;
+  int w, v;
+  __device__ __forceinline__ T load(int x) const { return load_support(desc, w, x, v); }
+  __device__ __forceinline__ static uint32_t cost(const T& a, const T& b) { return sad64(a, b); }
+  __device__ __forceinline__ static uint32_t texture(const T& a) { return texture64(a); }
+};
+
+__device__ __forceinline__ uint32_t popc4(const uint4 a) {
+  return __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
+}
+__device__ __forceinline__ uint4 xor4(const uint4 a, const uint4 b) {
+  return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w);
+}
+
+template <int NQ>
+struct CensusSrc {
+  struct T {
+    uint4 q[NQ];
+  };
+  const uint4* row;  // the lattice row's census, NQ words per column
+  __device__ __forceinline__ T load(int x) const {
+    T r;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) r.q[i] = row[(size_t)x * NQ + i];
+    return r;
+  }
+  __device__ __forceinline__ static uint32_t cost(const T& a, const T& b) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) c += popc4(xor4(a.q[i], b.q[i]));
+    return c;
+  }
+  __device__ __forceinline__ static uint32_t texture(const T& a) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) c += popc4(a.q[i]);
+    return c;
+  }
+};
+
 // Full search of one point over d = dmin..dhi (at least two values); the
-// partner column is u + dir*d. Returns whether the ratio test accepts and the
-// best disparity. Control flow is wavefront-uniform.
-__device__ __forceinline__ bool support_search(const Desc64& self,
-                                               const uint8_t* __restrict__ other, int w, int u,
-                                               int v, int dir, int dhi, const KParams& p,
+// partner column is u + dir*d. Returns whether the ambiguity test accepts and
+// the best disparity (smallest cost, smallest d on ties). Control flow is
+// wavefront-uniform.
+template <class S>
+__device__ __forceinline__ bool support_search(const typename S::T& self, const S& other,
+                                               int u, int dir, int dhi, const KParams& p,
                                                int lane, int* d_best) {
   uint32_t cost[kMaxD / 64];
   uint32_t best = 0xFFFFFFFFu;
@@ -201,7 +344,7 @@ __device__ __forceinline__ bool support_search(const Desc64& self,
     cost[j] = 0xFFFFFFFFu;
     const int d = p.dmin + lane + 64 * j;
     if (j < nj && d <= dhi) {
-      const uint32_t c = sad64(self, load_support(other, w, u + dir * d, v));
+      const uint32_t c = S::cost(self, other.load(u + dir * d));
       cost[j] = c;
       best = min(best, (c << 8) | (uint32_t)(d - p.dmin));
     }
@@ -217,7 +360,29 @@ __device__ __forceinline__ bool support_search(const Desc64& self,
   }
   m2 = wave_min(m2);
   *d_best = d1;
-  return (float)m1 < __fmul_rn(p.support_threshold, (float)m2);
+  return support_accept(p, m1, m2);
+}
+
+// One lattice point with descriptor sources sL (left view) and sR (right).
+template <class S>
+__device__ __forceinline__ int support_point(const S& sL, const S& sR, int u, int w,
+                                             const KParams& p, int lane, int* ev) {
+  const typename S::T ls = sL.load(u);
+  if ((int)S::texture(ls) < p.support_texture) return -1;
+  const int dhi = min(p.dmax, u - 4);
+  if (dhi - p.dmin + 1 < 2) return -1;
+  *ev += dhi - p.dmin + 1;
+  int d1;
+  if (!support_search(ls, sR, u, -1, dhi, p, lane, &d1)) return -1;
+  const int ur = u - d1;
+  const typename S::T rs = sR.load(ur);
+  const int dhi2 = min(p.dmax, w - 5 - ur);
+  if ((int)S::texture(rs) < p.support_texture || dhi2 - p.dmin + 1 < 2) return -1;
+  *ev += dhi2 - p.dmin + 1;
+  int d2;
+  if (support_search(rs, sL, ur, +1, dhi2, p, lane, &d2) && abs(d2 - d1) <= p.lr_threshold)
+    return d1;
+  return -1;
 }
 
 __device__ __forceinline__ void support_body(const Frame& F, int lb) {
@@ -228,28 +393,18 @@ __device__ __forceinline__ void support_body(const Frame& F, int lb) {
   if (pt >= g.lw * g.lh) return;
   const int l = pt / g.lw, k = pt - l * g.lw;
   const int u = g.lu0 + k * g.step, v = g.lv0 + l * g.step;
-  const uint8_t* descL = F.descL;
-  const uint8_t* descR = F.descR;
-  int result = -1, ev = 0;
-  const Desc64 ls = load_support(descL, g.w, u, v);
-  if ((int)texture64(ls) >= p.support_texture) {
-    const int dhi = min(p.dmax, u - 4);
-    if (dhi - p.dmin + 1 >= 2) {
-      ev += dhi - p.dmin + 1;
-      int d1;
-      if (support_search(ls, descR, g.w, u, v, -1, dhi, p, lane, &d1)) {
-        const int ur = u - d1;
-        const Desc64 rs = load_support(descR, g.w, ur, v);
-        const int dhi2 = min(p.dmax, g.w - 5 - ur);
-        if ((int)texture64(rs) >= p.support_texture && dhi2 - p.dmin + 1 >= 2) {
-          ev += dhi2 - p.dmin + 1;
-          int d2;
-          if (support_search(rs, descL, g.w, ur, v, +1, dhi2, p, lane, &d2) &&
-              abs(d2 - d1) <= p.lr_threshold)
-            result = d1;
-        }
-      }
-    }
+  int result, ev = 0;
+  if (p.descriptor == 0) {
+    result = support_point(GradSrc{F.descL, g.w, v}, GradSrc{F.descR, g.w, v}, u, g.w, p, lane,
+                           &ev);
+  } else {
+    const size_t row = (size_t)l * g.w * p.cs_q;
+    const uint4* cL = F.csupL;
+    const uint4* cR = F.csupR;
+    if (p.cs_q == 1)
+      result = support_point(CensusSrc<1>{cL + row}, CensusSrc<1>{cR + row}, u, g.w, p, lane, &ev);
+    else
+      result = support_point(CensusSrc<2>{cL + row}, CensusSrc<2>{cR + row}, u, g.w, p, lane, &ev);
   }
   if (lane == 0) {
     F.dcan_raw[pt] = (int16_t)result;
@@ -270,7 +425,8 @@ __device__ __forceinline__ void support_body(const Frame& F, int lb) {
 // The tile's raw values are staged in LDS with a halo of incon_window +
 // redun_max_dist; each pass is computed on the region the next pass reads
 // (positions outside the lattice count as empty). The kernel also clears the
-// grid masks that the rows stage fills.
+// grid masks that the rows stage fills. With past-only redundancy only the
+// consistency pass runs here.
 // ---------------------------------------------------------------------------
 constexpr int kFT = 16;
 
@@ -328,6 +484,14 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
     sinc[i] = (int16_t)res;
   }
   __syncthreads();
+  if (p.redundancy) {  // past-only redundancy runs in its own stage
+    if (tid < kFT * kFT) {
+      const int y = tid / kFT, x = tid - y * kFT;
+      const int l = l0 + y, k = k0 + x;
+      if (l < g.lh && k < g.lw) F.dcan_incon[(size_t)l * g.lw + k] = sinc[(y + rr) * SI + x + rr];
+    }
+    return;
+  }
   for (int i = tid; i < kFT * SI; i += 1024) {
     const int y = i / SI, x = i - y * SI;
     const int d = sinc[(y + rr) * SI + x];
@@ -368,9 +532,75 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
 }
 
 // ---------------------------------------------------------------------------
+// Past-only redundancy (Section VI-C, Fig. 7B): along each lattice column from
+// the top, then along each row from the left, a point is removed iff one of
+// the previous redun_max_dist positions holds a point that survived the same
+// pass with |d' - d| <= redun_threshold. Each line is a sequential chain, so
+// one thread walks one line; the outputs of the last R positions are kept in
+// a register shift ring (R a compile-time bound >= redun_max_dist, so the
+// ring is never indexed at run time). One workgroup per frame: the vertical
+// pass over every column, a barrier, the horizontal pass over every row.
+// Inputs are prefetched eight positions at a time.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void redun_line(const int16_t* __restrict__ in,
+                                           int16_t* __restrict__ out, int n, size_t step,
+                                           int r, int t) {
+  int last[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) last[j] = -1;
+  for (int b0 = 0; b0 < n; b0 += 8) {
+    int x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = b0 + i < n ? in[(size_t)(b0 + i) * step] : -1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (b0 + i >= n) break;
+      const int d = x[i];
+      bool hit = false;
+#pragma unroll
+      for (int j = 0; j < R; ++j) hit |= j < r && last[j] >= 0 && abs(last[j] - d) <= t;
+      const int res = (d >= 0 && hit) ? -1 : d;
+#pragma unroll
+      for (int j = R - 1; j > 0; --j) last[j] = last[j - 1];
+      last[0] = res;
+      out[(size_t)(b0 + i) * step] = (int16_t)res;
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void redun_passes(const Frame& F) {
+  const Geometry g = F.g;
+  const int r = F.p.redun_max_dist, t = F.p.redun_threshold;
+  const int16_t* inc = F.dcan_incon;
+  int16_t* vert = F.dcan_vert;
+  int16_t* fin = F.dcan_final;
+  for (int k = threadIdx.x; k < g.lw; k += blockDim.x)
+    redun_line<R>(inc + k, vert + k, g.lh, (size_t)g.lw, r, t);
+  __syncthreads();
+  for (int l = threadIdx.x; l < g.lh; l += blockDim.x)
+    redun_line<R>(vert + (size_t)l * g.lw, fin + (size_t)l * g.lw, g.lw, 1, r, t);
+}
+
+__device__ __forceinline__ void redun_body(const Frame& F, int lb) {
+  (void)lb;
+  const int r = F.p.redun_max_dist;
+  if (r <= 4)
+    redun_passes<4>(F);
+  else if (r <= 8)
+    redun_passes<8>(F);
+  else
+    redun_passes<16>(F);
+}
+
+// ---------------------------------------------------------------------------
 // Support lists per lattice row, one wavefront per row (for the mesh step;
 // host-mapped memory when the host triangulates), plus the grid vectors.
 //  * left list: the row's survivors in lattice order, packed u | d << 16;
+//    with down-sampling by k (Section VII-B) only the survivors whose index
+//    in the whole lattice-order list is a multiple of k (the row first counts
+//    the survivors of the rows above);
 //  * right list (each point seen from the right view at (u - d, v); on
 //    collisions the larger d, the nearer surface, wins): an LDS slot per
 //    right-view column takes atomicMax of d, then the occupied slots in
@@ -392,17 +622,31 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
   uint32_t* gridR = F.gridR;
   for (int x = lane; x < g.w; x += 64) slot[x] = -1;
   __syncthreads();
-  int nL = 0, ev = 0;
-  const int16_t* frow = F.dcan_final + (size_t)l * g.lw;
+  int nL = 0, nV = 0, ev = 0;
+  const int16_t* fin = F.dcan_final;
+  const int16_t* frow = fin + (size_t)l * g.lw;
   const int32_t* erow = F.evals + (size_t)l * g.lw;
+  const int ks = p.subsample;
+  int base = 0;  // survivors in the rows above (global list index of this row's first)
+  if (ks > 1) {
+    const int n = l * g.lw;
+    int c = 0;
+    for (int i = lane; i < n; i += 64) c += fin[i] >= 0 ? 1 : 0;
+    base = wave_sum(c);
+  }
+  const unsigned long long below = (1ull << lane) - 1ull;
   for (int k0 = 0; k0 < g.lw; k0 += 64) {
     const int k = k0 + lane;
-    const int d = k < g.lw ? frow[k] : -1;
+    const int dv = k < g.lw ? frow[k] : -1;
     ev += k < g.lw ? erow[k] : 0;
+    const unsigned long long vm = __ballot(dv >= 0);
+    const int gi = base + nV + __popcll(vm & below);
+    const int d = (dv >= 0 && (ks <= 1 || gi % ks == 0)) ? dv : -1;
+    nV += __popcll(vm);
     const unsigned long long m = __ballot(d >= 0);
     if (d >= 0) {
       const int u = g.lu0 + k * g.step;
-      const int pos = nL + __popcll(m & ((1ull << lane) - 1ull));
+      const int pos = nL + __popcll(m & below);
       hrowL[(size_t)l * g.lw + pos] = u | (d << 16);
       atomicMax(&slot[u - d], d);
       uint32_t* cell = gridL + (grow + u / p.grid_size) * g.gwords;
@@ -623,8 +867,9 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
 // triangle's plane mean ((a*u) + (b*v)) + c in FP32 without contraction,
 // rounded as floor(mean + 0.5) and clamped. Candidates: the plane window, the
 // grid region's one-hot mask (or every d with full_search), restricted to
-// partners with a defined descriptor. Energy: descriptor SAD plus the prior
-// table at |d - d_plane|. Argmin by packed key. Candidates are taken from
+// partners with a defined descriptor. Energy: descriptor SAD (or census
+// Hamming distance) plus the prior table at |d - d_plane|. Argmin by packed
+// key. Candidates are taken from
 // the 64-bit masks KB at a time so that their descriptor gathers are in
 // flight together.
 // ---------------------------------------------------------------------------
@@ -634,6 +879,90 @@ __device__ __forceinline__ uint64_t bits64_between(int a, int b) {
   if (a > b) return 0ull;
   const uint64_t hi = b == 63 ? ~0ull : ((2ull << b) - 1ull);
   return hi & ~((1ull << a) - 1ull);
+}
+
+// Dense descriptors: 16-byte gradient descriptors compared by SAD, or 64-bit
+// census descriptors (Section VI-A) compared by Hamming distance; texture is
+// the distance from the flat descriptor or the number of set bits.
+struct GradDense {
+  typedef uint4 T;
+  __device__ __forceinline__ static T load(const uint8_t* base, size_t px) {
+    return ld16(base + px * 16);
+  }
+  __device__ __forceinline__ static uint32_t cost(const T a, const T b) { return sad16(a, b); }
+  __device__ __forceinline__ static uint32_t texture(const T a) { return texture16(a); }
+};
+
+struct CensusDense {
+  typedef uint64_t T;
+  __device__ __forceinline__ static T load(const uint8_t* base, size_t px) {
+    return reinterpret_cast<const uint64_t*>(base)[px];
+  }
+  __device__ __forceinline__ static uint32_t cost(const T a, const T b) {
+    return (uint32_t)__popcll(a ^ b);
+  }
+  __device__ __forceinline__ static uint32_t texture(const T a) { return (uint32_t)__popcll(a); }
+};
+
+// Argmin over the candidates of one pixel (descriptors defined there).
+template <int KB, class DD>
+__device__ __forceinline__ int dense_pixel(const Frame& F, const Geometry& g, const KParams& p,
+                                           bool right, bool has_list, int u, int v, int dp,
+                                           const int32_t* s_lut, int* cnt) {
+  const uint8_t* self_desc = right ? F.descR : F.descL;
+  const uint8_t* other_desc = right ? F.descL : F.descR;
+  const typename DD::T s = DD::load(self_desc, (size_t)v * g.w + u);
+  const int lim = (right ? (g.w - 3 - u) : (u - 2)) - p.dmin;  // largest admissible d-dmin
+  if ((int)DD::texture(s) < p.match_texture || lim < 0) return -1;
+  const int lo = dp >= 0 ? max(dp - p.sradius, p.dmin) - p.dmin : 1;
+  const int hi = dp >= 0 ? min(dp + p.sradius, p.dmax) - p.dmin : 0;
+  const int top = min(lim, p.D - 1);
+  const int nw = min(g.gwords >> 1, (top >> 6) + 1);  // 64-bit words in play
+  const uint64_t* cell =
+      has_list ? reinterpret_cast<const uint64_t*>(
+                     (right ? F.gridR : F.gridL) +
+                     ((size_t)(v / p.grid_size) * g.gw + u / p.grid_size) * g.gwords)
+               : nullptr;
+  uint64_t cw[kMaxD / 64];
+#pragma unroll
+  for (int j = 0; j < kMaxD / 64; ++j) cw[j] = (cell && j < nw) ? cell[j] : 0ull;
+  uint32_t best = 0xFFFFFFFFu;
+  const size_t orow = (size_t)v * g.w;
+#pragma unroll
+  for (int j = 0; j < kMaxD / 64; ++j) {
+    if (j >= nw) break;
+    const int base = 64 * j;
+    uint64_t m = (p.full_search ? ~0ull : 0ull) | cw[j] | bits64_between(lo - base, hi - base);
+    m &= bits64_between(0, top - base);
+    while (m) {
+      int dd[KB];
+      typename DD::T o[KB];
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        dd[t] = -1;
+        if (m) {
+          dd[t] = base + __builtin_ctzll(m);
+          m &= m - 1ull;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < KB; ++t)
+        if (dd[t] >= 0) {
+          const int d = p.dmin + dd[t];
+          o[t] = DD::load(other_desc, orow + (right ? u + d : u - d));
+        }
+#pragma unroll
+      for (int t = 0; t < KB; ++t)
+        if (dd[t] >= 0) {
+          const int d = p.dmin + dd[t];
+          int E = (int)DD::cost(s, o[t]);
+          if (dp >= 0) E += s_lut[abs(d - dp)];
+          best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd[t]);
+          ++*cnt;
+        }
+    }
+  }
+  return best != 0xFFFFFFFFu ? p.dmin + (int)(best & 0xFFu) : -1;
 }
 
 template <int KB>
@@ -653,8 +982,6 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
   int cnt = 0;
   if (px < npx) {
     const int v = px / g.w, u = px - v * g.w;
-    const uint8_t* self_desc = right ? F.descR : F.descL;
-    const uint8_t* other_desc = right ? F.descL : F.descR;
     int dp = -1;
     if (has_list) {
       const int o = (right ? F.ownerR : F.ownerL)[px];
@@ -670,59 +997,10 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
     (right ? F.dplaneR : F.dplaneL)[px] = (int16_t)dp;
     int res = -1;
     if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
-      const uint4 s = ld16(self_desc + (size_t)px * 16);
-      const int lim = (right ? (g.w - 3 - u) : (u - 2)) - p.dmin;  // largest admissible d-dmin
-      if ((int)texture16(s) >= p.match_texture && lim >= 0) {
-        const int lo = dp >= 0 ? max(dp - p.sradius, p.dmin) - p.dmin : 1;
-        const int hi = dp >= 0 ? min(dp + p.sradius, p.dmax) - p.dmin : 0;
-        const int top = min(lim, p.D - 1);
-        const int nw = min(g.gwords >> 1, (top >> 6) + 1);  // 64-bit words in play
-        const uint64_t* cell =
-            has_list ? reinterpret_cast<const uint64_t*>(
-                           (right ? F.gridR : F.gridL) +
-                           ((size_t)(v / p.grid_size) * g.gw + u / p.grid_size) * g.gwords)
-                     : nullptr;
-        uint64_t cw[kMaxD / 64];
-#pragma unroll
-        for (int j = 0; j < kMaxD / 64; ++j) cw[j] = (cell && j < nw) ? cell[j] : 0ull;
-        uint32_t best = 0xFFFFFFFFu;
-        const uint8_t* orow = other_desc + (size_t)v * g.w * 16;
-#pragma unroll
-        for (int j = 0; j < kMaxD / 64; ++j) {
-          if (j >= nw) break;
-          const int base = 64 * j;
-          uint64_t m = (p.full_search ? ~0ull : 0ull) | cw[j] | bits64_between(lo - base, hi - base);
-          m &= bits64_between(0, top - base);
-          while (m) {
-            int dd[KB];
-            uint4 o[KB];
-#pragma unroll
-            for (int t = 0; t < KB; ++t) {
-              dd[t] = -1;
-              if (m) {
-                dd[t] = base + __builtin_ctzll(m);
-                m &= m - 1ull;
-              }
-            }
-#pragma unroll
-            for (int t = 0; t < KB; ++t)
-              if (dd[t] >= 0) {
-                const int d = p.dmin + dd[t];
-                o[t] = ld16(orow + (size_t)(right ? u + d : u - d) * 16);
-              }
-#pragma unroll
-            for (int t = 0; t < KB; ++t)
-              if (dd[t] >= 0) {
-                const int d = p.dmin + dd[t];
-                int E = (int)sad16(s, o[t]);
-                if (dp >= 0) E += s_lut[abs(d - dp)];
-                best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd[t]);
-                ++cnt;
-              }
-          }
-        }
-        if (best != 0xFFFFFFFFu) res = p.dmin + (int)(best & 0xFFu);
-      }
+      if (p.descriptor)
+        res = dense_pixel<KB, CensusDense>(F, g, p, right, has_list, u, v, dp, s_lut, &cnt);
+      else
+        res = dense_pixel<KB, GradDense>(F, g, p, right, has_list, u, v, dp, s_lut, &cnt);
     }
     (right ? F.rawR : F.rawL)[px] = (int16_t)res;
   }
@@ -738,27 +1016,119 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
 __device__ __forceinline__ void check_body(const Frame& F, int lb) {
   const Geometry g = F.g;
   const int thr = F.p.lr_threshold;
+  const bool med = F.p.median != 0;
+  const int16_t* rawL = F.rawL;
+  const int16_t* rawR = F.rawR;
+  int16_t* outL = F.outL;
+  int16_t* outR = F.outR;
+  int16_t* chkL = F.chkL;
+  int16_t* chkR = F.chkR;
   const int px = (lb >> 1) * 256 + threadIdx.x;
   if (px >= g.w * g.h) return;
   const int v = px / g.w, u = px - v * g.w;
   const size_t row = (size_t)v * g.w;
   if ((lb & 1) == 0) {
-    const int d = F.rawL[px];
+    const int d = rawL[px];
     int r = -1;
     if (d >= 0 && u - d >= 0) {
-      const int e = F.rawR[row + u - d];
+      const int e = rawR[row + u - d];
       if (e >= 0 && abs(e - d) <= thr) r = d;
     }
-    F.outL[px] = (int16_t)r;
+    if (med)
+      chkL[px] = (int16_t)r;
+    else
+      outL[px] = (int16_t)r;
   } else {
-    const int d = F.rawR[px];
+    const int d = rawR[px];
     int r = -1;
     if (d >= 0 && u + d < g.w) {
-      const int e = F.rawL[row + u + d];
+      const int e = rawL[row + u + d];
       if (e >= 0 && abs(e - d) <= thr) r = d;
     }
-    F.outR[px] = (int16_t)r;
+    if (med)
+      chkR[px] = (int16_t)r;
+    else
+      outR[px] = (int16_t)r;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Median post-filter (Section VIII) of the checked maps, window 3 or 5
+// clipped to the image: an invalid pixel stays invalid, a valid one takes
+// the lower median of the valid values in its window. Block = 64 x 4 pixels
+// of one view with a 2-pixel halo in LDS (outside the image reads as
+// invalid). The window's values, invalid ones replaced by a sentinel above
+// every disparity, are sorted by a Batcher odd-even merge network over the
+// next power of two (fully unrolled: the values stay in registers), and the
+// ((n-1)/2)-th of the n valid values is selected.
+// ---------------------------------------------------------------------------
+constexpr int kMedW = 64, kMedH = 4, kMedHalo = 2;
+
+template <int N>
+__device__ __forceinline__ void oddeven_merge_sort(int (&a)[N]) {
+#pragma unroll
+  for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+    for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+      for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+        for (int i = 0; i < k; ++i)
+          if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+            const int x = a[i + j], y = a[i + j + k];
+            a[i + j] = min(x, y);
+            a[i + j + k] = max(x, y);
+          }
+}
+
+template <int W, int N>
+__device__ __forceinline__ int median_pixel(const int16_t (*t)[kMedW + 2 * kMedHalo], int ty,
+                                            int tx) {
+  constexpr int r = W / 2;
+  constexpr int kInvalid = 0x7FFF;
+  int a[N];
+  int n = 0;
+#pragma unroll
+  for (int dy = 0; dy < W; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < W; ++dx) {
+      const int e = t[ty + kMedHalo - r + dy][tx + kMedHalo - r + dx];
+      a[dy * W + dx] = e >= 0 ? e : kInvalid;
+      n += e >= 0 ? 1 : 0;
+    }
+#pragma unroll
+  for (int i = W * W; i < N; ++i) a[i] = kInvalid;
+  oddeven_merge_sort<N>(a);
+  const int k = (n - 1) >> 1;
+  int res = -1;
+#pragma unroll
+  for (int i = 0; i < W * W; ++i) res = i == k ? a[i] : res;
+  return res;
+}
+
+__device__ __forceinline__ void median_body(const Frame& F, int lb) {
+  const Geometry g = F.g;
+  const int win = F.p.median;
+  const int nbx = cdivd(g.w, kMedW);
+  const int view = lb & 1, tile_id = lb >> 1;
+  const int16_t* in = view ? F.chkR : F.chkL;
+  int16_t* out = view ? F.outR : F.outL;
+  constexpr int TW = kMedW + 2 * kMedHalo;
+  __shared__ int16_t t[kMedH + 2 * kMedHalo][TW];
+  const int u0 = (tile_id % nbx) * kMedW, v0 = (tile_id / nbx) * kMedH;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < (kMedH + 2 * kMedHalo) * TW; i += 256) {
+    const int r = i / TW, c = i - r * TW;
+    const int y = v0 - kMedHalo + r, x = u0 - kMedHalo + c;
+    t[r][c] = (x >= 0 && x < g.w && y >= 0 && y < g.h) ? in[(size_t)y * g.w + x] : (int16_t)-1;
+  }
+  __syncthreads();
+  const int tx = tid & 63, ty = tid >> 6;
+  const int u = u0 + tx, v = v0 + ty;
+  if (u >= g.w || v >= g.h) return;
+  int res = t[ty + kMedHalo][tx + kMedHalo];
+  if (res >= 0) res = win == 3 ? median_pixel<3, 16>(t, ty, tx) : median_pixel<5, 32>(t, ty, tx);
+  out[(size_t)v * g.w + u] = (int16_t)res;
 }
 
 // ---- kernels: one frame, or a batch in one launch --------------------------
@@ -774,9 +1144,9 @@ __device__ __forceinline__ void check_body(const Frame& F, int lb) {
     BODY(F, b - starts[f]);                                                             \
   }
 
-ELAS_STAGE_KERNELS(k_descriptor4, descriptor_body<4>, 256)
-ELAS_STAGE_KERNELS(k_descriptor8, descriptor_body<8>, 256)
-ELAS_STAGE_KERNELS(k_descriptor16, descriptor_body<16>, 256)
+ELAS_STAGE_KERNELS(k_descriptor4, stage1_body<4>, 256)
+ELAS_STAGE_KERNELS(k_descriptor8, stage1_body<8>, 256)
+ELAS_STAGE_KERNELS(k_descriptor16, stage1_body<16>, 256)
 ELAS_STAGE_KERNELS(k_support, support_body, 256)
 ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
 ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
@@ -785,6 +1155,8 @@ ELAS_STAGE_KERNELS(k_dense4, dense_body<4>, 256)
 ELAS_STAGE_KERNELS(k_dense8, dense_body<8>, 256)
 ELAS_STAGE_KERNELS(k_dense16, dense_body<16>, 256)
 ELAS_STAGE_KERNELS(k_check, check_body, 256)
+ELAS_STAGE_KERNELS(k_redun, redun_body, 1024)
+ELAS_STAGE_KERNELS(k_median, median_body, 256)
 
 #undef ELAS_STAGE_KERNELS
 
@@ -796,6 +1168,7 @@ size_t filter_lds_bytes(const KParams& p) {
 int stage_threads(int32_t stage) {
   switch (stage) {
     case kStageFilter: return 1024;
+    case kStageRedun: return 1024;
     case kStageRows: return 64;
     case kStageRaster: return kRasterThreads;
     default: return 256;
@@ -808,17 +1181,19 @@ int32_t raster_band_rows(int32_t w) { return std::max(1, std::min(kBandRowsMax, 
 
 int32_t dense_blocks(const Geometry& g) { return 2 * cdiv((long long)g.w * g.h, 256); }
 
-int32_t stage_blocks(int32_t stage, const Geometry& g, int dv) {
+int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv) {
   switch (stage) {
     case kStageDescriptor:
       return 2 * cdiv(g.w, kDescW) * cdiv(g.h, kDescRows[std::min(std::max(dv, 0), 2)]);
     case kStageSupport: return cdiv((long long)g.lw * g.lh, 4);
     case kStageFilter: return filter_tiles_x(g) * filter_tiles_y(g);
+    case kStageRedun: return p.redundancy ? 1 : 0;
     case kStageRows: return g.lh;
     case kStageMesh: return 2;
     case kStageRaster: return 2 * cdiv(g.h, raster_band_rows(g.w));
     case kStageDense: return dense_blocks(g);
     case kStageCheck: return 2 * cdiv((long long)g.w * g.h, 256);
+    case kStageMedian: return p.median ? 2 * cdiv(g.w, kMedW) * cdiv(g.h, kMedH) : 0;
     default: return 0;
   }
 }
@@ -834,7 +1209,7 @@ size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p) {
 
 hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t s) {
   if (stage == kStageMesh) return launch_mesh_frame(f, s);
-  const int nb = stage_blocks(stage, f.g, variant);
+  const int nb = stage_blocks(stage, f.g, f.p, variant);
   if (nb <= 0) return hipSuccess;
   const dim3 grid(nb), block(stage_threads(stage));
   const size_t lds = stage_lds(stage, f.g, f.p);
@@ -860,6 +1235,8 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
         hipLaunchKernelGGL(k_dense8, grid, block, 0, s, f);
       break;
     case kStageCheck: hipLaunchKernelGGL(k_check, grid, block, 0, s, f); break;
+    case kStageRedun: hipLaunchKernelGGL(k_redun, grid, block, 0, s, f); break;
+    case kStageMedian: hipLaunchKernelGGL(k_median, grid, block, 0, s, f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -902,6 +1279,12 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
       break;
     case kStageCheck:
       hipLaunchKernelGGL(k_check_batch, grid, block, 0, s, frames, starts, nf);
+      break;
+    case kStageRedun:
+      hipLaunchKernelGGL(k_redun_batch, grid, block, 0, s, frames, starts, nf);
+      break;
+    case kStageMedian:
+      hipLaunchKernelGGL(k_median_batch, grid, block, 0, s, frames, starts, nf);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -41,6 +41,10 @@ class ElasParams(C.Structure):
         ("sigma", C.c_float), ("sradius", C.c_int32), ("match_texture", C.c_int32),
         ("lr_threshold", C.c_int32), ("full_search", C.c_int32),
         ("mesh_on_host", C.c_int32),
+        ("descriptor", C.c_int32), ("census_support_window", C.c_int32),
+        ("census_dense_window", C.c_int32), ("ambiguity", C.c_int32),
+        ("redundancy", C.c_int32), ("support_subsample", C.c_int32),
+        ("median_window", C.c_int32),
     ]
 
 
@@ -95,6 +99,9 @@ INTERMEDIATES = {
     "grid_left": (17, np.uint64), "grid_right": (18, np.uint64),
     "raw_left": (19, np.int16), "raw_right": (20, np.int16),
     "lut": (21, np.int32),
+    "census_dense_left": (22, np.uint64), "census_dense_right": (23, np.uint64),
+    "census_support_left": (24, np.uint32), "census_support_right": (25, np.uint32),
+    "checked_left": (26, np.int16), "checked_right": (27, np.int16),
 }
 
 _lib = None

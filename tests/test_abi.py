@@ -46,13 +46,29 @@ def test_defaults_match_the_workload_parameters(E):
     assert p.grid_size == 20 and p.beta == np.float32(0.02)
     assert p.gamma == 3 and p.sigma == 1 and p.sradius == 2
     assert p.match_texture == 1 and p.lr_threshold == 2 and p.full_search == 0
+    # the embedded variant and the optional steps are off by default
+    assert (p.descriptor, p.ambiguity, p.redundancy) == (0, 0, 0)
+    assert (p.census_support_window, p.census_dense_window) == (9, 5)
+    assert p.support_subsample == 1 and p.median_window == 0
+
+
+def test_param_struct_mirrors_the_oracle_fields():
+    # every oracle parameter exists in the C-ABI struct under the same name
+    from oracle import ref
+    import paper_1802_07210_amd.elas as el
+    names = {n for n, _ in el.ElasParams._fields_}
+    assert set(ref.DEFAULTS) <= names
 
 
 @pytest.mark.parametrize("bad", [
     dict(disp_min=-1), dict(disp_min=10, disp_max=9), dict(disp_max=256),
     dict(candidate_stepsize=0), dict(grid_size=0), dict(beta=0.0), dict(gamma=-1.0),
     dict(sigma=float("nan")), dict(incon_window_size=-1), dict(full_search=2),
-    dict(sradius=-3),
+    dict(sradius=-3), dict(descriptor=2), dict(ambiguity=-1), dict(redundancy=2),
+    dict(descriptor=1, census_support_window=8), dict(descriptor=1, census_support_window=15),
+    dict(descriptor=1, census_dense_window=1), dict(descriptor=1, census_dense_window=9),
+    dict(support_subsample=0), dict(support_subsample=65), dict(median_window=2),
+    dict(median_window=7),
 ])
 def test_create_rejects_bad_parameters(E, bad):
     with pytest.raises(E.ElasError, match="ELAS_ERR_ARG"):
@@ -66,7 +82,11 @@ def test_create_rejects_prior_out_of_key_range(E):
 
 def test_create_accepts_edge_parameters(E):
     for kw in (dict(disp_max=255), dict(disp_min=7, disp_max=7), dict(candidate_stepsize=1),
-               dict(full_search=1), dict(disp_min=3, disp_max=200)):
+               dict(full_search=1), dict(disp_min=3, disp_max=200),
+               dict(descriptor=1, census_support_window=13, census_dense_window=7),
+               dict(descriptor=1, census_support_window=3, census_dense_window=3),
+               dict(ambiguity=1, redundancy=1, support_subsample=64, median_window=5),
+               dict(median_window=1), dict(redundancy=1, redun_max_dist=16)):
         e = E.Elas(**kw)
         e.close()
 

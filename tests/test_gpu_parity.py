@@ -60,9 +60,29 @@ def compare(e, t, outL, outR):
         if n:
             bad.append((name, n))
 
-    chk("desc_left", e.intermediate("desc_left").reshape(h, w, 16), t.descL)
-    chk("desc_right", e.intermediate("desc_right").reshape(h, w, 16), t.descR)
     lh, lw = t.dcan_raw.shape
+    prm = e.params
+    if prm.descriptor == 1:
+        # dense census: one uint64 per pixel; support census: the lattice rows,
+        # 4*q words per pixel, zero-padded beyond the oracle's words
+        for side, cden, csup in (("left", t.cdenL, t.csupL), ("right", t.cdenR, t.csupR)):
+            exp = cden[..., 0].astype(np.uint64)
+            if cden.shape[-1] > 1:
+                exp |= cden[..., 1].astype(np.uint64) << np.uint64(32)
+            chk(f"census_dense_{side}", e.intermediate(f"census_dense_{side}").reshape(h, w), exp)
+            if lh:
+                step = prm.candidate_stepsize
+                rows = ((4 + step - 1) // step) * step + step * np.arange(lh)
+                got = e.intermediate(f"census_support_{side}").reshape(lh, w, -1)
+                nw = csup.shape[-1]
+                chk(f"census_support_{side}", got[..., :nw], csup[rows])
+                chk(f"census_support_pad_{side}", got[..., nw:], np.zeros_like(got[..., nw:]))
+    else:
+        chk("desc_left", e.intermediate("desc_left").reshape(h, w, 16), t.descL)
+        chk("desc_right", e.intermediate("desc_right").reshape(h, w, 16), t.descR)
+    if prm.median_window > 1:
+        chk("checked_left", e.intermediate("checked_left").reshape(h, w), t.chkL)
+        chk("checked_right", e.intermediate("checked_right").reshape(h, w), t.chkR)
     for nm, arr in (("dcan_raw", t.dcan_raw), ("dcan_incon", t.dcan_incon),
                     ("dcan_vert", t.dcan_vert), ("dcan_final", t.dcan_final)):
         chk(nm, e.intermediate(nm).reshape(lh, lw), arr)
