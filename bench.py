@@ -18,12 +18,26 @@ roofline        the kernel with the largest share of chip time (duration x the
 batch           96 pairs of mixed resolutions and disparity ranges (seeded
                 synthetic, pair i from seed i), one batched call each repetition,
                 against 96 sequential plain calls
+serve           16 camera streams with Poisson arrivals at three aggregate
+                rates: p50/p99 latency and sustained pairs/s of the batching
+                server and of the one-pair-at-a-time server
+variants        frames/s of the same pair under the embedded variant and the
+                optional steps (census descriptors, eq. 3, past-only redundancy,
+                support down-sampling, median filter), each bit-exact to the
+                oracle in the test-suite
 cpu_baseline    the CPU oracle (single-threaded C) on a bounded sample of the
                 same workload, on this host
+
+--mode calib runs a plain device copy of a known size (reads and writes
+COPY_BYTES per launch) so that rocprofv3's FETCH_SIZE / WRITE_SIZE counters
+can be scaled to bytes; profiles/ keeps the scaled per-launch traffic of the
+dominant kernel together with a hash of the kernel source it was taken on,
+and roofline.traffic reports it only while that source is unchanged.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -43,32 +57,132 @@ PEAK_HBM_GBS = 8000.0
 PEAK_SAD_TOPS = 256 * 64 * 2.4e9 * 4 / 1e12    # 157.3 T byte-|diff| per second
 
 STAGES = ["descriptor", "support", "filter", "rows", "mesh", "raster", "dense", "lrcheck"]
-KERNEL_NAMES = {"descriptor": "k_descriptor", "support": "k_support", "filter": "k_filter",
-                "rows": "k_rows", "mesh": "k_mesh", "raster": "k_raster", "dense": "k_dense",
-                "lrcheck": "k_lrcheck"}
+KERNEL_NAMES = {"descriptor": "k_descriptor4", "support": "k_support", "filter": "k_filter",
+                "rows": "k_rows", "mesh": "k_mesh", "raster": "k_raster", "dense": "k_dense8",
+                "lrcheck": "k_check"}
+
+
+COPY_BYTES = 256 << 20
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1802_07210_amd", "csrc", "elas_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_640x480_D128.json")
+
+# Variants measured beside the headline configuration (parameter overrides).
+VARIANTS = {
+    "census_9x9_5x5": dict(descriptor=1, census_support_window=9, census_dense_window=5),
+    "census_13x13_7x7": dict(descriptor=1, census_support_window=13, census_dense_window=7),
+    "shiftsum_eq3": dict(ambiguity=1),
+    "past_only_redundancy": dict(redundancy=1),
+    "support_1_of_8": dict(support_subsample=8),
+    "support_1_of_32": dict(support_subsample=32),
+    "median_5x5": dict(median_window=5),
+    "embedded_best": dict(descriptor=1, census_support_window=9, census_dense_window=5,
+                          ambiguity=1, redundancy=1, support_subsample=8, median_window=5),
+}
+
+
+def source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    """Per-launch HBM bytes of `kernel` from the committed counter runs, or
+    None when they were taken on another version of the kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("source_sha256_16") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration(torch, reps: int = 20):
+    """A plain copy kernel of known size (neg of a float32 buffer: COPY_BYTES
+    read and COPY_BYTES written per launch)."""
+    dev = torch.device("cuda:0")
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "calib", "copy_bytes_read": COPY_BYTES,
+                      "copy_bytes_written": COPY_BYTES, "launches": reps}), flush=True)
+
+
+def variant_fps(torch, Elas, L, R, D, steps: int, streams):
+    """Frames/s of each variant on the bench pair, same stream round-robin."""
+    H, W = L.shape
+    dev = L.device
+    K = len(streams)
+    outs = [(torch.empty((H, W), dtype=torch.int16, device=dev),
+             torch.empty((H, W), dtype=torch.int16, device=dev)) for _ in range(K)]
+    res = {}
+    for name, kw in VARIANTS.items():
+        e = Elas(disp_max=D - 1, **kw)
+        for i in range(max(8, K)):
+            e.process(L, R, outs[i % K][0], outs[i % K][1], stream=streams[i % K])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            e.process(L, R, outs[i % K][0], outs[i % K][1], stream=streams[i % K])
+        torch.cuda.synchronize()
+        fps = steps / (time.perf_counter() - t0)
+        st = e.stats()
+        res[name] = {"fps": round(fps, 1), "params": kw,
+                     "support_points": [st["n_support_left"], st["n_support_right"]],
+                     "evals_per_frame": st["support_evals"] + st["dense_evals"]}
+        e.close()
+    return res
 
 
 def algorithmic_work(stage: str, w: int, h: int, st: dict):
-    """(bound, amount per launch, unit, per-unit description) of a kernel."""
+    """(HBM bytes, byte-|diff| ops) one launch of a stage's kernel must move
+    and compute, counted from the algorithm (not from the counters)."""
     npx = w * h
-    if stage == "descriptor":   # read 1 B, write 16 B descriptor + 4 B owner reset, 2 views
-        return "hbm", 2 * npx * (1 + 16 + 4), "B"
-    if stage == "support":      # 64 byte-|diff| per 512-bit SAD evaluation
-        return "alu", 64 * st["support_evals"], "ops"
-    if stage == "dense":        # 16 byte-|diff| per candidate evaluation
-        return "alu", 16 * st["dense_evals"], "ops"
+    if stage == "descriptor":   # read 1 B image, write a 16 B descriptor; 2 views
+        return 2 * npx * (1 + 16), 0
+    if stage == "support":      # descriptors of the lattice rows; 64 byte-|diff| per eval
+        return 2 * 16 * w * 5 * max(1, st.get("lattice_rows", 0)), 64 * st["support_evals"]
+    if stage == "dense":        # own descriptor 16 B + prior 2 B read, raw 2 B written;
+        return 2 * npx * (16 + 2 + 2), 16 * st["dense_evals"]       # 2 views
     if stage == "lrcheck":      # read 2 B + partner 2 B, write 2 B per pixel, 2 views
-        return "hbm", 2 * npx * 6, "B"
-    if stage == "raster":       # one 4 B owner update per covered pixel, 2 views
-        return "hbm", 2 * npx * 4, "B"
+        return 2 * npx * 6, 0
+    if stage == "raster":       # a 4 B owner and a 2 B prior per pixel, 2 views
+        return 2 * npx * 6, 0
     if stage == "filter":       # lattice read + three lattice writes
-        return "hbm", 8 * max(1, st.get("lattice", 0)), "B"
+        return 8 * max(1, st.get("lattice", 0)), 0
     if stage == "rows":         # final lattice + evaluation counts read, lists written
-        return "hbm", 6 * max(1, st.get("lattice", 0)), "B"
+        return 6 * max(1, st.get("lattice", 0)), 0
     if stage == "mesh":         # support points in, raster records out (24 B per triangle)
         n = st["n_support_left"] + st["n_support_right"]
-        return "hbm", 12 * n + 24 * (st["n_tri_left"] + st["n_tri_right"]), "B"
-    return "hbm", 0, "B"
+        return 12 * n + 24 * (st["n_tri_left"] + st["n_tri_right"]), 0
+    return 0, 0
+
+
+def roofline_of(stage: str, w: int, h: int, st: dict, ms: float, kernel: str) -> dict:
+    """The binding roofline of one kernel: the resource whose floor (work over
+    peak) is the larger; achieved = that work over the kernel's mean duration."""
+    nbytes, ops = algorithmic_work(stage, w, h, st)
+    dur_s = ms / 1e3
+    t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+    t_alu = ops / (PEAK_SAD_TOPS * 1e12)
+    if t_alu > t_hbm:
+        achieved, peak, unit, bound, work, wunit = (ops / dur_s / 1e12, PEAK_SAD_TOPS, "Tops/s",
+                                                    "alu", ops, "byte-|diff| (v_sad_u8: 4 per lane)")
+    else:
+        achieved, peak, unit, bound, work, wunit = (nbytes / dur_s / 1e9, PEAK_HBM_GBS, "GB/s",
+                                                    "hbm", nbytes, "bytes")
+    roof = {"bound": bound, "achieved": round(achieved, 4), "peak": round(peak, 1),
+            "unit": unit, "frac": round(achieved / peak, 6), "traffic": stored_traffic(kernel),
+            "kernel": kernel, "kernel_ms": round(ms, 5), "work_per_launch": work,
+            "work_unit": wunit}
+    if bound == "hbm" and ops:
+        roof["alu_view"] = {"achieved": round(ops / dur_s / 1e12, 4), "peak": round(PEAK_SAD_TOPS, 1),
+                            "unit": "Tops/s", "frac": round(ops / dur_s / 1e12 / PEAK_SAD_TOPS, 6),
+                            "work_per_launch": ops}
+    return roof
 
 
 def cpu_model() -> str:
@@ -179,9 +293,14 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--streams", type=int, default=4,
                     help="frames in flight: steps are issued round-robin on this many streams")
-    ap.add_argument("--mode", choices=["frame", "serve"], default="frame",
+    ap.add_argument("--mode", choices=["frame", "serve", "calib"], default="frame",
                     help="frame: the 640x480 frame rate (default); serve: the camera-stream "
-                         "serving sweep (batched and plain servers)")
+                         "serving sweep (batched and plain servers); calib: a plain copy "
+                         "kernel of known size for scaling the PMC byte counters")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the per-variant frame rates")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the short serving sweep of the default run")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds per arrival-rate level in --mode serve")
     ap.add_argument("--no-batch", action="store_true",
@@ -197,6 +316,10 @@ def main():
     import torch
     import synth
     from paper_1802_07210_amd import Elas
+
+    if args.mode == "calib":
+        copy_calibration(torch)
+        return
 
     if args.mode == "serve":
         from paper_1802_07210_amd import serve
@@ -267,24 +390,13 @@ def main():
         for k in host:
             host[k].append(tm[k])
     e.set_timing(False)
-    stage_ms = {s: float(np.mean(v)) for s, v in acc.items()}
+    stage_ms = {s: float(np.mean(v)) if v else float("nan") for s, v in acc.items()}
     kernel_ms = {s: stage_ms[s] for s in KERNEL_NAMES}
     # share of chip time: the mesh kernel runs one workgroup (one CU) per view
     chip_ms = {s: v * (2.0 / 256.0 if s == "mesh" else 1.0) for s, v in kernel_ms.items()}
-    dom = max(chip_ms, key=chip_ms.get)
-    bound, amount, unit = algorithmic_work(dom, W, H, st)
-    dur_s = kernel_ms[dom] / 1e3
-    if bound == "alu":
-        achieved = amount / dur_s / 1e12
-        peak, runit = PEAK_SAD_TOPS, "Tops/s"
-    else:
-        achieved = amount / dur_s / 1e9
-        peak, runit = PEAK_HBM_GBS, "GB/s"
-    roof = {"bound": bound, "achieved": round(achieved, 4), "peak": round(peak, 1),
-            "unit": runit, "frac": round(achieved / peak, 6), "traffic": None,
-            "kernel": KERNEL_NAMES[dom], "kernel_ms": round(kernel_ms[dom], 5),
-            "work_per_launch": amount,
-            "work_unit": "byte-|diff| (v_sad_u8 lanes x 4)" if bound == "alu" else "bytes"}
+    dom = max(chip_ms, key=lambda k: chip_ms[k] if chip_ms[k] == chip_ms[k] else -1.0)
+    st["lattice_rows"] = (H - 5) // 5
+    roof = roofline_of(dom, W, H, st, kernel_ms[dom], KERNEL_NAMES[dom])
 
     out = {
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
@@ -302,11 +414,28 @@ def main():
         "evals_per_s_nominal": round(nominal * fps, 1),
         "support_points": [st["n_support_left"], st["n_support_right"]],
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
-        "host_ms": {k: round(float(np.mean(v)), 5) for k, v in host.items()},
+        "host_ms": {k: round(float(np.mean(v)), 5) if v else None for k, v in host.items()},
         "roofline": roof,
     }
+    if not args.no_variants:
+        out["variants"] = variant_fps(torch, Elas, L, R, D, min(args.steps, 200), streams)
     if not args.no_batch:
         out["batch"] = batch_c4(torch, Elas)
+    if not args.no_serve:
+        # a short serving sweep (three arrival rates, 3 s each; --mode serve runs
+        # the full one): p50/p99 latency of the batched server and the plain one
+        from paper_1802_07210_amd import serve
+        cams, handles = serve.build_cameras()
+        rates = (200, 1000, 2000)
+        sb = serve.run_sweep(rates=rates, seconds=3.0, cams=cams, handles=handles)
+        sp = serve.run_sweep(rates=rates, seconds=3.0, plain=True, cams=cams, handles=handles)
+        out["serve"] = {"cameras": 16, "seconds_per_rate": 3.0,
+                        "batched": [{k: lv[k] for k in ("rate", "sustained_pairs_per_s", "p50_ms",
+                                                        "p99_ms", "mean_batch")}
+                                    for lv in sb["levels"]],
+                        "plain": [{k: lv[k] for k in ("rate", "sustained_pairs_per_s", "p50_ms",
+                                                      "p99_ms")} for lv in sp["levels"]],
+                        "peak_bytes_in_flight": sb["peak_bytes_in_flight"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair.left, pair.right, D - 1)
     print(json.dumps(out), flush=True)

@@ -112,20 +112,24 @@ typedef struct elas_stats {
   double  host_mesh_ms;        /* host time spent triangulating (both views) */
 } elas_stats;
 
-/* Per-stage device times of the most recent elas_process call, from HIP
- * events recorded on the call's stream between stages (only while timing is
- * enabled with elas_set_timing). */
+/* Per-kernel device times of the most recent elas_process call (only while
+ * timing is enabled with elas_set_timing): each kernel is launched with
+ * hipExtLaunchKernel start/stop events, which take the kernel's own start and
+ * end, so the figures exclude launch gaps and match a profiler's kernel
+ * durations. */
 typedef struct elas_timing {
-  float descriptor_ms;         /* k_descriptor, both views */
+  float descriptor_ms;         /* k_descriptor (Sobel or census), both views */
   float support_ms;            /* k_support (both search directions) */
-  float filter_ms;             /* k_filter: consistency and redundancy filters */
+  float filter_ms;             /* k_filter (consistency, two-sided redundancy) plus
+                                  k_redun when past-only redundancy is set */
   float rows_ms;               /* k_rows: support lists and grid vectors */
   float mesh_ms;               /* device mesh kernel, or (mesh_on_host) the host
                                   step and the upload of its records */
   float raster_ms;             /* k_raster */
   float dense_ms;              /* k_dense, both views */
-  float lrcheck_ms;            /* k_lrcheck */
-  float device_span_ms;        /* first stage start to last stage end, host step included */
+  float lrcheck_ms;            /* k_check, plus k_median when a median is set */
+  float device_span_ms;        /* first kernel start to last kernel end, gaps and
+                                  host step included */
   double host_wait_ms;         /* calling thread blocked until the lists were ready */
   double host_mesh_ms;         /* host triangulation and record building */
 } elas_timing;

@@ -34,10 +34,11 @@ namespace {
 
 thread_local std::string g_create_error;
 
-// Stage boundary events: before the descriptor; after descriptor, support,
-// filter, rows, mesh (device kernel, or host step + upload), raster, dense,
-// check.
-constexpr int kStageEvents = 9;
+// Timed kernels of elas_process, each with a start/stop event pair taken by
+// hipExtLaunchKernel from the kernel's own dispatch: descriptor, support,
+// filter, past-only redundancy, rows, mesh (host mode: events around the host
+// step and its upload), raster, dense, check, median.
+constexpr int kTimed = 10;
 
 // One background host thread that builds the right view's mesh while the
 // calling thread builds the left one (host mesh mode).
@@ -167,7 +168,8 @@ struct elas_handle {
   bool upload_pending = false;
   bool timing = false;
   bool have_timing = false;
-  hipEvent_t tev[kStageEvents] = {};
+  hipEvent_t kev[kTimed][2] = {};
+  bool kev_used[kTimed] = {};
   // batches: per-stream frame tables and graphs, per-(size, stream) buffer
   // pools, tile variants chosen by the autotuner per (w, h, D)
   int32_t batch_flags = ELAS_BATCH_GRAPH | ELAS_BATCH_AUTOTUNE;
@@ -750,8 +752,9 @@ int elas_destroy(elas_handle* h) {
   }
   if (h->ev_lists) (void)hipEventDestroy(h->ev_lists);
   if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
-  for (hipEvent_t& e : h->tev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& pr : h->kev)
+    for (hipEvent_t& e : pr)
+      if (e) (void)hipEventDestroy(e);
   delete h->worker;
   mesh_scratch_destroy(h->meshL);
   mesh_scratch_destroy(h->meshR);
@@ -789,38 +792,39 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   h->last_on_host = on_host;
   h->host_mesh_ms = h->host_wait_ms = 0.0;
   const bool timed = h->timing;
-  if (timed && !h->tev[0])
-    for (hipEvent_t& e : h->tev) HIP_TRY(hipEventCreate(&e));
-#define STAGE_MARK(i) \
-  if (timed) HIP_TRY(hipEventRecord(h->tev[i], stream))
+  if (timed && !h->kev[0][0])
+    for (auto& pr : h->kev)
+      for (hipEvent_t& e : pr) HIP_TRY(hipEventCreate(&e));
+  for (bool& u : h->kev_used) u = false;
 
   const Frame F = make_frame(h, b, left, right, stride, disp_left, disp_right, on_host);
   const std::pair<int, int> var = variants_for(h, w, hp);
-  STAGE_MARK(0);
-  HIP_TRY(launch_stage(kStageDescriptor, F, var.first, stream));
-  STAGE_MARK(1);
-  HIP_TRY(launch_stage(kStageSupport, F, 0, stream));
-  STAGE_MARK(2);
-  HIP_TRY(launch_stage(kStageFilter, F, 0, stream));
-  HIP_TRY(launch_stage(kStageRedun, F, 0, stream));
-  STAGE_MARK(3);
-  HIP_TRY(launch_stage(kStageRows, F, 0, stream));
-  STAGE_MARK(4);
+  // one stage; while timing, kernel k records its start/stop events
+  auto run = [&](int k, int32_t stage, int variant) -> hipError_t {
+    if (!timed) return launch_stage(stage, F, variant, stream);
+    if (stage == kStageMesh || stage_blocks(stage, F.g, F.p, variant) > 0) h->kev_used[k] = true;
+    return launch_stage(stage, F, variant, stream, h->kev[k][0], h->kev[k][1]);
+  };
+  HIP_TRY(run(0, kStageDescriptor, var.first));
+  HIP_TRY(run(1, kStageSupport, 0));
+  HIP_TRY(run(2, kStageFilter, 0));
+  HIP_TRY(run(3, kStageRedun, 0));
+  HIP_TRY(run(4, kStageRows, 0));
   if (on_host) {
+    if (timed) HIP_TRY(hipEventRecord(h->kev[5][0], stream));
     rc = host_mesh_step(h, b, stream);
     if (rc != ELAS_OK) return rc;
+    if (timed) {
+      HIP_TRY(hipEventRecord(h->kev[5][1], stream));
+      h->kev_used[5] = true;
+    }
   } else {
-    HIP_TRY(launch_stage(kStageMesh, F, 0, stream));
+    HIP_TRY(run(5, kStageMesh, 0));
   }
-  STAGE_MARK(5);
-  HIP_TRY(launch_stage(kStageRaster, F, 0, stream));
-  STAGE_MARK(6);
-  HIP_TRY(launch_stage(kStageDense, F, var.second, stream));
-  STAGE_MARK(7);
-  HIP_TRY(launch_stage(kStageCheck, F, 0, stream));
-  HIP_TRY(launch_stage(kStageMedian, F, 0, stream));
-  STAGE_MARK(8);
-#undef STAGE_MARK
+  HIP_TRY(run(6, kStageRaster, 0));
+  HIP_TRY(run(7, kStageDense, var.second));
+  HIP_TRY(run(8, kStageCheck, 0));
+  HIP_TRY(run(9, kStageMedian, 0));
   h->have_timing = timed;
   h->have_result = true;
   return ELAS_OK;
@@ -1122,20 +1126,23 @@ int elas_get_timing(elas_handle* h, elas_timing* out) {
   if (!h || !out) return fail(h, ELAS_ERR_ARG, "null argument");
   if (!h->have_result || !h->have_timing)
     return fail(h, ELAS_ERR_ARG, "no completed call with timing enabled");
-  HIP_TRY(hipEventSynchronize(h->tev[kStageEvents - 1]));
-  float ms[kStageEvents - 1];
-  for (int i = 0; i + 1 < kStageEvents; ++i)
-    HIP_TRY(hipEventElapsedTime(&ms[i], h->tev[i], h->tev[i + 1]));
+  int last = 0;
+  for (int k = 0; k < kTimed; ++k)
+    if (h->kev_used[k]) last = k;
+  HIP_TRY(hipEventSynchronize(h->kev[last][1]));
+  float ms[kTimed] = {};
+  for (int k = 0; k < kTimed; ++k)
+    if (h->kev_used[k]) HIP_TRY(hipEventElapsedTime(&ms[k], h->kev[k][0], h->kev[k][1]));
   float span = 0.f;
-  HIP_TRY(hipEventElapsedTime(&span, h->tev[0], h->tev[kStageEvents - 1]));
+  HIP_TRY(hipEventElapsedTime(&span, h->kev[0][0], h->kev[last][1]));
   out->descriptor_ms = ms[0];
   out->support_ms = ms[1];
-  out->filter_ms = ms[2];
-  out->rows_ms = ms[3];
-  out->mesh_ms = ms[4];
-  out->raster_ms = ms[5];
-  out->dense_ms = ms[6];
-  out->lrcheck_ms = ms[7];
+  out->filter_ms = ms[2] + ms[3];
+  out->rows_ms = ms[4];
+  out->mesh_ms = ms[5];
+  out->raster_ms = ms[6];
+  out->dense_ms = ms[7];
+  out->lrcheck_ms = ms[8] + ms[9];
   out->device_span_ms = span;
   out->host_wait_ms = h->host_wait_ms;
   out->host_mesh_ms = h->host_mesh_ms;

@@ -207,8 +207,10 @@ size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p);
 // Band height of the raster for an image width.
 int32_t raster_band_rows(int32_t w);
 
-// One stage of one frame.
-hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t s);
+// One stage of one frame. With start/stop events (hipExtLaunchKernel) the
+// events take the kernel's own start and end times.
+hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t s,
+                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // One stage of nf frames in one launch: frames and starts (nf + 1 prefix of
 // the per-frame block counts) in device memory; lds: the largest per-frame
 // dynamic LDS.
@@ -218,7 +220,8 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
 
 // The mesh stage (elas_mesh_device.hip): two workgroups per frame, for
 // frames with both sides at most kDeviceMeshMaxSide.
-hipError_t launch_mesh_frame(const Frame& f, hipStream_t s);
+hipError_t launch_mesh_frame(const Frame& f, hipStream_t s, hipEvent_t start = nullptr,
+                             hipEvent_t stop = nullptr);
 hipError_t launch_mesh_batch(const Frame* frames, int32_t nf, hipStream_t s);
 // Device mesh scratch per view (views that do not fit in LDS).
 size_t mesh_global_scratch_per_view(const Geometry& g);

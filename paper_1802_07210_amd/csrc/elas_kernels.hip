@@ -18,6 +18,8 @@
 // block finds its frame in the prefix of the per-frame block counts).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "elas_internal.h"
 
 namespace elas {
@@ -688,7 +690,8 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
 // the band), computes the exact integer span of each of their band rows from
 // the three edge functions, spreads each wave's span pixels evenly over its
 // lanes, resolves each pixel with an LDS atomicMin, and finally writes the
-// whole tile with coalesced stores. Every pixel is written.
+// whole tile with coalesced stores, together with each pixel's prior
+// disparity (the owning plane's mean). Every pixel is written.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int floordiv_pos(int a, int b) {  // b > 0
   return a >= 0 ? a / b : -((-a + b - 1) / b);
@@ -857,15 +860,31 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
     if (done || r0 >= nt) break;
   }
   __syncthreads();
+  // owners and the prior disparity of every pixel: the owning triangle's
+  // plane mean ((a*u) + (b*v)) + c in FP32 without contraction, rounded as
+  // floor(mean + 0.5) and clamped to the disparity range; -1 without owner
   int32_t* owner = (view ? F.ownerR : F.ownerL) + (size_t)v0 * g.w;
-  for (int i = tid; i < rows * g.w; i += kRasterThreads) owner[i] = tile[i];
+  int16_t* dpl = (view ? F.dplaneR : F.dplaneL) + (size_t)v0 * g.w;
+  const int dmin = F.p.dmin, dmax = F.p.dmax;
+  for (int i = tid; i < rows * g.w; i += kRasterThreads) {
+    const int o = tile[i];
+    owner[i] = o;
+    int dp = -1;
+    if (o != kNoOwner) {
+      const int q = i / g.w, u = i - q * g.w, v = v0 + q;
+      const float a = vt[o].a, b = vt[o].b, c = vt[o].c;
+      const float mu = __fadd_rn(__fadd_rn(__fmul_rn(a, (float)u), __fmul_rn(b, (float)v)), c);
+      const float f = floorf(__fadd_rn(mu, 0.5f));
+      dp = f < (float)dmin ? dmin : (f > (float)dmax ? dmax : (int)f);
+    }
+    dpl[i] = (int16_t)dp;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Dense matching (Section III-A, Fig. 1(h)). One thread per pixel, views
-// interleaved per 256-pixel block. The prior disparity is the owning
-// triangle's plane mean ((a*u) + (b*v)) + c in FP32 without contraction,
-// rounded as floor(mean + 0.5) and clamped. Candidates: the plane window, the
+// interleaved per 256-pixel block. The prior disparity comes from the raster
+// (the owning plane's rounded mean, -1 without a plane). Candidates: the plane window, the
 // grid region's one-hot mask (or every d with full_search), restricted to
 // partners with a defined descriptor. Energy: descriptor SAD (or census
 // Hamming distance) plus the prior table at |d - d_plane|. Argmin by packed
@@ -975,26 +994,13 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
   for (int i = threadIdx.x; i < p.D; i += 256) s_lut[i] = lut[i];
   __syncthreads();
   const bool right = (lb & 1) != 0;
-  const int ntL = F.hdr->ntri[0];
   const bool has_list = F.hdr->n[0] > 0;
   const int npx = g.w * g.h;
   const int px = (lb >> 1) * 256 + threadIdx.x;
   int cnt = 0;
   if (px < npx) {
     const int v = px / g.w, u = px - v * g.w;
-    int dp = -1;
-    if (has_list) {
-      const int o = (right ? F.ownerR : F.ownerL)[px];
-      if (o != kNoOwner) {
-        const RasterTri t = F.tris[o + (right ? ntL : 0)];
-        const float au = __fmul_rn(t.a, (float)u);
-        const float bv = __fmul_rn(t.b, (float)v);
-        const float mu = __fadd_rn(__fadd_rn(au, bv), t.c);
-        const float f = floorf(__fadd_rn(mu, 0.5f));
-        dp = f < (float)p.dmin ? p.dmin : (f > (float)p.dmax ? p.dmax : (int)f);
-      }
-    }
-    (right ? F.dplaneR : F.dplaneL)[px] = (int16_t)dp;
+    const int dp = (right ? F.dplaneR : F.dplaneL)[px];  // -1 without a plane
     int res = -1;
     if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
       if (p.descriptor)
@@ -1207,36 +1213,44 @@ size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p) {
   }
 }
 
-hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t s) {
-  if (stage == kStageMesh) return launch_mesh_frame(f, s);
+hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t s,
+                        hipEvent_t start, hipEvent_t stop) {
+  if (stage == kStageMesh) return launch_mesh_frame(f, s, start, stop);
   const int nb = stage_blocks(stage, f.g, f.p, variant);
   if (nb <= 0) return hipSuccess;
   const dim3 grid(nb), block(stage_threads(stage));
-  const size_t lds = stage_lds(stage, f.g, f.p);
+  const uint32_t lds = (uint32_t)stage_lds(stage, f.g, f.p);
+  const bool timed = start || stop;
+  auto go = [&](auto kernel) {
+    if (timed)
+      hipExtLaunchKernelGGL(kernel, grid, block, lds, s, start, stop, 0u, f);
+    else
+      hipLaunchKernelGGL(kernel, grid, block, lds, s, f);
+  };
   switch (stage) {
     case kStageDescriptor:
       if (variant == 1)
-        hipLaunchKernelGGL(k_descriptor8, grid, block, 0, s, f);
+        go(k_descriptor8);
       else if (variant == 2)
-        hipLaunchKernelGGL(k_descriptor16, grid, block, 0, s, f);
+        go(k_descriptor16);
       else
-        hipLaunchKernelGGL(k_descriptor4, grid, block, 0, s, f);
+        go(k_descriptor4);
       break;
-    case kStageSupport: hipLaunchKernelGGL(k_support, grid, block, 0, s, f); break;
-    case kStageFilter: hipLaunchKernelGGL(k_filter, grid, block, lds, s, f); break;
-    case kStageRows: hipLaunchKernelGGL(k_rows, grid, block, lds, s, f); break;
-    case kStageRaster: hipLaunchKernelGGL(k_raster, grid, block, 0, s, f); break;
+    case kStageSupport: go(k_support); break;
+    case kStageFilter: go(k_filter); break;
+    case kStageRedun: go(k_redun); break;
+    case kStageRows: go(k_rows); break;
+    case kStageRaster: go(k_raster); break;
     case kStageDense:
       if (variant == 0)
-        hipLaunchKernelGGL(k_dense4, grid, block, 0, s, f);
+        go(k_dense4);
       else if (variant == 2)
-        hipLaunchKernelGGL(k_dense16, grid, block, 0, s, f);
+        go(k_dense16);
       else
-        hipLaunchKernelGGL(k_dense8, grid, block, 0, s, f);
+        go(k_dense8);
       break;
-    case kStageCheck: hipLaunchKernelGGL(k_check, grid, block, 0, s, f); break;
-    case kStageRedun: hipLaunchKernelGGL(k_redun, grid, block, 0, s, f); break;
-    case kStageMedian: hipLaunchKernelGGL(k_median, grid, block, 0, s, f); break;
+    case kStageCheck: go(k_check); break;
+    case kStageMedian: go(k_median); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -44,6 +44,8 @@
 #include <algorithm>
 #include <climits>
 
+#include <hip/hip_ext.h>
+
 #include "elas_internal.h"
 
 namespace elas {
@@ -863,9 +865,12 @@ size_t mesh_global_scratch_per_view(const Geometry& g) {
   return a16(carve<int32_t>(nullptr, nmax, g.lh, probe));
 }
 
-hipError_t launch_mesh_frame(const Frame& f, hipStream_t s) {
+hipError_t launch_mesh_frame(const Frame& f, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   if (f.g.w > kDeviceMeshMaxSide || f.g.h > kDeviceMeshMaxSide) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_mesh, dim3(2), dim3(kMT), kMeshLdsBytes, s, f);
+  if (start || stop)
+    hipExtLaunchKernelGGL(k_mesh, dim3(2), dim3(kMT), kMeshLdsBytes, s, start, stop, 0u, f);
+  else
+    hipLaunchKernelGGL(k_mesh, dim3(2), dim3(kMT), kMeshLdsBytes, s, f);
   return hipGetLastError();
 }
 
