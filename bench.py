@@ -58,7 +58,7 @@ PEAK_SAD_TOPS = 256 * 64 * 2.4e9 * 4 / 1e12    # 157.3 T byte-|diff| per second
 
 STAGES = ["descriptor", "support", "filter", "rows", "mesh", "raster", "dense", "lrcheck"]
 KERNEL_NAMES = {"descriptor": "k_descriptor4", "support": "k_support", "filter": "k_filter",
-                "rows": "k_rows", "mesh": "k_mesh", "raster": "k_raster", "dense": "k_dense8",
+                "rows": "k_rows", "mesh": "k_mesh", "raster": "k_raster", "dense": "k_dense2",
                 "lrcheck": "k_check"}
 
 

@@ -189,8 +189,8 @@ enum elas_batch_flags {
   ELAS_BATCH_GRAPH = 1,         /* capture each batch shape's launches in a HIP graph
                                    once and replay it */
   ELAS_BATCH_AUTOTUNE = 2       /* on the first batch with a new (w, h, D), time the
-                                   descriptor (4/8/16 rows per block) and dense (4/8/16
-                                   gathers in flight) tile variants on its frames and
+                                   descriptor (4/8/16 rows per block) and dense (1/2/4
+                                   grid candidates per batch) variants on its frames and
                                    keep the fastest; results are identical for all */
 };
 ELAS_API int elas_set_batch_flags(elas_handle* h, int32_t flags);
@@ -214,7 +214,7 @@ ELAS_API int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pair
                                 hipStream_t stream);
 
 /* Tile variants the autotuner chose for (w, h) at this handle's disparity
- * count: descriptor rows per block and dense gathers in flight.
+ * count: descriptor rows per block and dense grid candidates per batch.
  * ELAS_ERR_ARG if none has been chosen yet. */
 ELAS_API int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t h_px,
                                      int32_t* desc_rows, int32_t* dense_batch);

@@ -1106,7 +1106,7 @@ int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t hp, int32_t* desc
   if (!h || !desc_rows || !dense_batch) return fail(h, ELAS_ERR_ARG, "null argument");
   auto it = h->tuned.find(std::make_tuple(w, hp, h->kp.D));
   if (it == h->tuned.end()) return fail(h, ELAS_ERR_ARG, "no tuned variants for this size");
-  static const int32_t rows[3] = {4, 8, 16}, batch[3] = {4, 8, 16};
+  static const int32_t rows[3] = {4, 8, 16}, batch[3] = {1, 2, 4};
   *desc_rows = rows[it->second.first];
   *dense_batch = batch[it->second.second];
   return ELAS_OK;

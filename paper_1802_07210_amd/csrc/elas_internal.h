@@ -198,7 +198,7 @@ enum Stage : int32_t {
 
 // Tile variants the autotuner chooses between (identical results).
 constexpr int kDescVariants = 3;   // descriptor rows per block: 4, 8, 16
-constexpr int kDenseVariants = 3;  // dense candidate gathers in flight: 4, 8, 16
+constexpr int kDenseVariants = 3;  // dense grid candidates per batch: 1, 2, 4
 
 // Workgroups one frame needs for a stage (descriptor variant dv).
 int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv);

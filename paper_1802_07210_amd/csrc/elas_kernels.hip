@@ -78,6 +78,26 @@ __device__ __forceinline__ int frame_of(const int32_t* __restrict__ starts, int 
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 __host__ __device__ __forceinline__ int cdivd(int a, int b) { return (a + b - 1) / b; }
 
+// Stages count elements into LDS: element i = load(i) goes to store(i, .).
+// A plain strided loop waits for each global load before its LDS write, one
+// memory round trip per iteration; here the first N * THREADS loads are all
+// issued before the first write (a loop finishes any remainder).
+template <int N, int THREADS, class Load, class Store>
+__device__ __forceinline__ void stage_copy(int count, const Load& load, const Store& store) {
+  decltype(load(0)) v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int i = (int)threadIdx.x + k * THREADS;
+    if (i < count) v[k] = load(i);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int i = (int)threadIdx.x + k * THREADS;
+    if (i < count) store(i, v[k]);
+  }
+  for (int i = (int)threadIdx.x + N * THREADS; i < count; i += THREADS) store(i, load(i));
+}
+
 // Gradient quantisation: divide by 4 truncating toward zero, clamp to
 // [-127, 127], offset by 128 (bytes 1..255; a negated gradient maps b to 256-b).
 __device__ __forceinline__ uint32_t quantise(int g) {
@@ -114,11 +134,18 @@ __device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
   __shared__ uint8_t qdv[TH + 4][kDescW + 4];
   const int u0 = (tile_id % nbx) * kDescW, v0 = (tile_id / nbx) * TH;
   const int tid = threadIdx.x;
-  for (int i = tid; i < (TH + 6) * (kDescW + 6); i += 256) {
-    const int r = i / (kDescW + 6), c = i - r * (kDescW + 6);
-    const int y = v0 - 3 + r, x = u0 - 3 + c;
-    tile[r][c] = (x >= 0 && x < g.w && y >= 0 && y < g.h) ? img[(size_t)y * stride + x] : 0;
-  }
+  constexpr int kTile = (TH + 6) * (kDescW + 6);
+  stage_copy<(kTile + 255) / 256, 256>(
+      kTile,
+      [&](int i) -> uint32_t {
+        const int r = i / (kDescW + 6), c = i - r * (kDescW + 6);
+        const int y = v0 - 3 + r, x = u0 - 3 + c;
+        return (x >= 0 && x < g.w && y >= 0 && y < g.h) ? img[(size_t)y * stride + x] : 0u;
+      },
+      [&](int i, uint32_t x) {
+        const int r = i / (kDescW + 6), c = i - r * (kDescW + 6);
+        tile[r][c] = (uint8_t)x;
+      });
   __syncthreads();
   for (int i = tid; i < (TH + 4) * (kDescW + 4); i += 256) {
     const int r = i / (kDescW + 4), c = i - r * (kDescW + 4);
@@ -196,11 +223,18 @@ __device__ __forceinline__ void census_body(const Frame& F, int lb) {
   __shared__ uint8_t tile[TH + 2 * H][TW];
   const int u0 = (tile_id % nbx) * kDescW, v0 = (tile_id / nbx) * TH;
   const int tid = threadIdx.x;
-  for (int i = tid; i < (TH + 2 * H) * TW; i += 256) {
-    const int r = i / TW, c = i - r * TW;
-    const int y = v0 - H + r, x = u0 - H + c;
-    tile[r][c] = (x >= 0 && x < g.w && y >= 0 && y < g.h) ? img[(size_t)y * stride + x] : 255;
-  }
+  constexpr int kTile = (TH + 2 * H) * TW;
+  stage_copy<(kTile + 255) / 256, 256>(
+      kTile,
+      [&](int i) -> uint32_t {
+        const int r = i / TW, c = i - r * TW;
+        const int y = v0 - H + r, x = u0 - H + c;
+        return (x >= 0 && x < g.w && y >= 0 && y < g.h) ? img[(size_t)y * stride + x] : 255u;
+      },
+      [&](int i, uint32_t x) {
+        const int r = i / TW, c = i - r * TW;
+        tile[r][c] = (uint8_t)x;
+      });
   __syncthreads();
   const int tx = tid & 63;
   const int u = u0 + tx;
@@ -462,11 +496,14 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
       gridR[i] = 0u;
     }
   }
-  for (int i = tid; i < SR * SR; i += 1024) {
-    const int y = i / SR, x = i - y * SR;
-    const int l = l0 - ri - rr + y, k = k0 - ri - rr + x;
-    sraw[i] = (l >= 0 && l < g.lh && k >= 0 && k < g.lw) ? raw[(size_t)l * g.lw + k] : (int16_t)-1;
-  }
+  stage_copy<2, 1024>(
+      SR * SR,
+      [&](int i) -> int {
+        const int y = i / SR, x = i - y * SR;
+        const int l = l0 - ri - rr + y, k = k0 - ri - rr + x;
+        return (l >= 0 && l < g.lh && k >= 0 && k < g.lw) ? (int)raw[(size_t)l * g.lw + k] : -1;
+      },
+      [&](int i, int x) { sraw[i] = (int16_t)x; });
   __syncthreads();
   for (int i = tid; i < SI * SI; i += 1024) {
     const int y = i / SI, x = i - y * SI;
@@ -882,24 +919,16 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
 }
 
 // ---------------------------------------------------------------------------
-// Dense matching (Section III-A, Fig. 1(h)). One thread per pixel, views
-// interleaved per 256-pixel block. The prior disparity comes from the raster
-// (the owning plane's rounded mean, -1 without a plane). Candidates: the plane window, the
+// Dense matching (Section III-A, Fig. 1(h)). One thread per pixel; a block is
+// a 256-pixel row segment of one view (views interleaved), with the other
+// view's reachable descriptors staged in LDS. The prior disparity comes from
+// the raster (the owning plane's rounded mean, -1 without a plane).
+// Candidates: the plane window, the
 // grid region's one-hot mask (or every d with full_search), restricted to
 // partners with a defined descriptor. Energy: descriptor SAD (or census
 // Hamming distance) plus the prior table at |d - d_plane|. Argmin by packed
-// key. Candidates are taken from
-// the 64-bit masks KB at a time so that their descriptor gathers are in
-// flight together.
+// key.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t bits64_between(int a, int b) {
-  a = max(a, 0);
-  b = min(b, 63);
-  if (a > b) return 0ull;
-  const uint64_t hi = b == 63 ? ~0ull : ((2ull << b) - 1ull);
-  return hi & ~((1ull << a) - 1ull);
-}
-
 // Dense descriptors: 16-byte gradient descriptors compared by SAD, or 64-bit
 // census descriptors (Section VI-A) compared by Hamming distance; texture is
 // the distance from the flat descriptor or the number of set bits.
@@ -923,93 +952,213 @@ struct CensusDense {
   __device__ __forceinline__ static uint32_t texture(const T a) { return (uint32_t)__popcll(a); }
 };
 
-// Argmin over the candidates of one pixel (descriptors defined there).
+// A workgroup matches kDenseSeg consecutive pixels of kDenseRows rows of one
+// view. The other view's descriptors of every column the segment can reach
+// (kDenseSeg + D - 1 per row) are staged in LDS once with coalesced loads, so
+// each candidate costs an LDS read instead of a global gather.
+constexpr int kDenseSeg = 256;
+constexpr int kDenseRows = 2;
+constexpr int kWinBatch = 5;  // the whole plane window at the default sradius (2)
+constexpr int kDenseStage = kDenseSeg + kMaxD - 1;
+
+__host__ __device__ __forceinline__ int dense_segments(const Geometry& g) {
+  return cdivd(g.w, kDenseSeg);
+}
+
+__device__ __forceinline__ uint32_t bits32_between(int a, int b) {
+  a = max(a, 0);
+  b = min(b, 31);
+  if (a > b) return 0u;
+  const uint32_t hi = b == 31 ? 0xFFFFFFFFu : ((2u << b) - 1u);
+  return hi & ~((1u << a) - 1u);
+}
+
+// Argmin over the candidates of one pixel (descriptors defined there); st
+// holds the other view's descriptors of columns base .. base + n - 1; s_lut
+// has a zero entry at kMaxD for pixels without a plane. The plane window is
+// evaluated as a range, the grid bits outside it (every admissible d with
+// full_search) from 32-bit mask words, KB at a time; a batch's unused slots
+// repeat its first candidate, so every slot is evaluated without branches
+// (a repeat cannot change the argmin) and the count comes from popcounts.
 template <int KB, class DD>
-__device__ __forceinline__ int dense_pixel(const Frame& F, const Geometry& g, const KParams& p,
-                                           bool right, bool has_list, int u, int v, int dp,
-                                           const int32_t* s_lut, int* cnt) {
-  const uint8_t* self_desc = right ? F.descR : F.descL;
-  const uint8_t* other_desc = right ? F.descL : F.descR;
-  const typename DD::T s = DD::load(self_desc, (size_t)v * g.w + u);
+__device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, bool right, int u,
+                                           int dp, const uint32_t (&cw)[kMaxD / 32],
+                                           const typename DD::T s, const typename DD::T* st,
+                                           int base, const int32_t* s_lut, int* cnt) {
   const int lim = (right ? (g.w - 3 - u) : (u - 2)) - p.dmin;  // largest admissible d-dmin
   if ((int)DD::texture(s) < p.match_texture || lim < 0) return -1;
-  const int lo = dp >= 0 ? max(dp - p.sradius, p.dmin) - p.dmin : 1;
-  const int hi = dp >= 0 ? min(dp + p.sradius, p.dmax) - p.dmin : 0;
   const int top = min(lim, p.D - 1);
-  const int nw = min(g.gwords >> 1, (top >> 6) + 1);  // 64-bit words in play
-  const uint64_t* cell =
-      has_list ? reinterpret_cast<const uint64_t*>(
-                     (right ? F.gridR : F.gridL) +
-                     ((size_t)(v / p.grid_size) * g.gw + u / p.grid_size) * g.gwords)
-               : nullptr;
-  uint64_t cw[kMaxD / 64];
-#pragma unroll
-  for (int j = 0; j < kMaxD / 64; ++j) cw[j] = (cell && j < nw) ? cell[j] : 0ull;
+  int wlo = 1, whi = 0;  // plane window in d - dmin units, clipped to [0, top]
+  if (dp >= 0) {
+    wlo = max(dp - p.sradius, p.dmin) - p.dmin;
+    whi = min(min(dp + p.sradius, p.dmax) - p.dmin, top);
+  }
+  const int slot0 = (right ? u + p.dmin : u - p.dmin) - base;
+  const int dir = right ? 1 : -1;
+  const int lut_off = p.dmin - dp;  // |dd + lut_off| = |d - dp|
   uint32_t best = 0xFFFFFFFFu;
-  const size_t orow = (size_t)v * g.w;
+  int n = max(0, whi - wlo + 1);
+  // the window, kWinBatch candidates at a time (the last batch repeats whi),
+  // every LDS read of a batch issued before its arithmetic
+  for (int b = wlo; b <= whi; b += kWinBatch) {
+    int dd[kWinBatch];
+    typename DD::T o[kWinBatch];
+    int lv[kWinBatch];
 #pragma unroll
-  for (int j = 0; j < kMaxD / 64; ++j) {
-    if (j >= nw) break;
-    const int base = 64 * j;
-    uint64_t m = (p.full_search ? ~0ull : 0ull) | cw[j] | bits64_between(lo - base, hi - base);
-    m &= bits64_between(0, top - base);
-    while (m) {
-      int dd[KB];
-      typename DD::T o[KB];
+    for (int t = 0; t < kWinBatch; ++t) dd[t] = min(b + t, whi);
 #pragma unroll
-      for (int t = 0; t < KB; ++t) {
-        dd[t] = -1;
-        if (m) {
-          dd[t] = base + __builtin_ctzll(m);
-          m &= m - 1ull;
-        }
-      }
+    for (int t = 0; t < kWinBatch; ++t) {
+      o[t] = st[slot0 + dir * dd[t]];
+      lv[t] = s_lut[abs(dd[t] + lut_off)];  // a window exists only with a plane
+    }
 #pragma unroll
-      for (int t = 0; t < KB; ++t)
-        if (dd[t] >= 0) {
-          const int d = p.dmin + dd[t];
-          o[t] = DD::load(other_desc, orow + (right ? u + d : u - d));
-        }
-#pragma unroll
-      for (int t = 0; t < KB; ++t)
-        if (dd[t] >= 0) {
-          const int d = p.dmin + dd[t];
-          int E = (int)DD::cost(s, o[t]);
-          if (dp >= 0) E += s_lut[abs(d - dp)];
-          best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd[t]);
-          ++*cnt;
-        }
+    for (int t = 0; t < kWinBatch; ++t) {
+      const int E = (int)DD::cost(s, o[t]) + lv[t];
+      best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd[t]);
     }
   }
+  const int nw = (top >> 5) + 1;  // 32-bit words in play
+#pragma unroll
+  for (int j = 0; j < kMaxD / 32; ++j) {
+    if (j >= nw) break;
+    const int wb = 32 * j;
+    uint32_t m = (p.full_search ? 0xFFFFFFFFu : cw[j]) & bits32_between(0, top - wb) &
+                 ~bits32_between(wlo - wb, whi - wb);
+    n += __popc(m);
+    while (m) {
+      int dd[KB];
+      dd[0] = wb + __builtin_ctz(m);
+      m &= m - 1u;
+#pragma unroll
+      for (int t = 1; t < KB; ++t) {
+        dd[t] = m ? wb + __builtin_ctz(m) : dd[0];
+        m &= m - 1u;
+      }
+      typename DD::T o[KB];
+      int lv[KB];
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        o[t] = st[slot0 + dir * dd[t]];
+        lv[t] = s_lut[dp >= 0 ? abs(dd[t] + lut_off) : kMaxD];
+      }
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        const int E = (int)DD::cost(s, o[t]) + lv[t];
+        best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd[t]);
+      }
+    }
+  }
+  *cnt += n;
   return best != 0xFFFFFFFFu ? p.dmin + (int)(best & 0xFFu) : -1;
+}
+
+// One workgroup: kDenseRows rows x kDenseSeg columns of one view, a thread
+// per column and row. Every global load (the other view's reachable
+// descriptors, staged in LDS; the own descriptor, prior and grid-region mask
+// of each pixel) is issued before the one barrier, so a wave waits on memory
+// once.
+template <int KB, class DD>
+__device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, const KParams& p,
+                                           bool right, int v0, int u0, int32_t* s_lut,
+                                           typename DD::T* st, int* cnt) {
+  const int32_t* lut = F.lut;
+  // fields copied to locals first, so that no pointer is selected by
+  // indexing the frame struct (which would put it in scratch memory)
+  const uint8_t* descL = F.descL;
+  const uint8_t* descR = F.descR;
+  const int16_t* dplL = F.dplaneL;
+  const int16_t* dplR = F.dplaneR;
+  const uint32_t* gridL = F.gridL;
+  const uint32_t* gridR = F.gridR;
+  int16_t* rawL = F.rawL;
+  int16_t* rawR = F.rawR;
+  const uint8_t* self_desc = right ? descR : descL;
+  const uint8_t* other_desc = right ? descL : descR;
+  const int16_t* dplane = right ? dplR : dplL;
+  const uint32_t* grid = right ? gridR : gridL;
+  int16_t* raw = right ? rawR : rawL;
+  const bool has_list = F.hdr->n[0] > 0;
+  // other-view columns a pixel of this segment can reach
+  const int base = right ? u0 + p.dmin : u0 - p.dmax;
+  const int n = kDenseSeg + p.D - 1;
+  const int c0 = max(0, base), c1 = min(g.w - 1, base + n - 1);
+  const int u = u0 + (int)threadIdx.x;
+  const bool in_u = u < g.w;
+  // issue every global load first, each from an in-bounds address whether
+  // or not its value is used (a conditional load would make the compiler
+  // wait for it at the branch join): the reachable other-view columns of the
+  // block's rows (at most kDenseStage per row: two per thread and row), the
+  // prior table, then each pixel's prior, descriptor and region mask
+  const int nc = c1 - c0 + 1, rows = min(kDenseRows, g.h - v0);
+  const int nst = nc * rows;
+  typename DD::T sv[kDenseRows * 2];
+#pragma unroll
+  for (int k = 0; k < kDenseRows * 2; ++k) {
+    const int i = min((int)threadIdx.x + 256 * k, nst - 1);
+    const int r = i / nc, c = c0 + (i - r * nc);
+    sv[k] = DD::load(other_desc, (size_t)(v0 + r) * g.w + c);
+  }
+  const int32_t lv = lut[min((int)threadIdx.x, p.D - 1)];
+  const int uc = min(u, g.w - 1);
+  const int gwp = g.gwords >> 1;  // 64-bit words of a region mask
+  int dpv[kDenseRows];
+  typename DD::T s[kDenseRows];
+  uint2 cw2[kDenseRows][kMaxD / 64];
+#pragma unroll
+  for (int r = 0; r < kDenseRows; ++r) {
+    const int vc = min(v0 + r, g.h - 1);
+    dpv[r] = dplane[(size_t)vc * g.w + uc];
+    s[r] = DD::load(self_desc, (size_t)vc * g.w + uc);
+    const uint2* cell = reinterpret_cast<const uint2*>(
+        grid + ((size_t)(vc / p.grid_size) * g.gw + uc / p.grid_size) * g.gwords);
+#pragma unroll
+    for (int j = 0; j < kMaxD / 64; ++j) cw2[r][j] = cell[min(j, gwp - 1)];
+  }
+#pragma unroll
+  for (int k = 0; k < kDenseRows * 2; ++k) {
+    const int i = (int)threadIdx.x + 256 * k;
+    const int r = i / nc, c = c0 + (i - r * nc);
+    if (i < nst) st[r * kDenseStage + (c - base)] = sv[k];
+  }
+  if ((int)threadIdx.x < p.D) s_lut[threadIdx.x] = lv;
+  if (threadIdx.x == 0) s_lut[kMaxD] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kDenseRows; ++r) {
+    const int v = v0 + r;
+    if (!in_u || v >= g.h) continue;
+    int res = -1;
+    if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
+      uint32_t cw[kMaxD / 32];
+#pragma unroll
+      for (int j = 0; j < kMaxD / 64; ++j) {
+        cw[2 * j] = has_list ? cw2[r][j].x : 0u;
+        cw[2 * j + 1] = has_list ? cw2[r][j].y : 0u;
+      }
+      res = dense_pixel<KB, DD>(g, p, right, u, dpv[r], cw, s[r], st + r * kDenseStage, base,
+                                s_lut, cnt);
+    }
+    raw[(size_t)v * g.w + u] = (int16_t)res;
+  }
 }
 
 template <int KB>
 __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
-  __shared__ int32_t s_lut[kMaxD];
+  __shared__ int32_t s_lut[kMaxD + 1];  // entry kMaxD: 0, the prior of pixels without a plane
   __shared__ int s_cnt[4];
+  __shared__ uint4 s_stage[kDenseRows * kDenseStage];
   const Geometry g = F.g;
   const KParams p = F.p;
-  const int32_t* lut = F.lut;
-  for (int i = threadIdx.x; i < p.D; i += 256) s_lut[i] = lut[i];
-  __syncthreads();
   const bool right = (lb & 1) != 0;
-  const bool has_list = F.hdr->n[0] > 0;
-  const int npx = g.w * g.h;
-  const int px = (lb >> 1) * 256 + threadIdx.x;
+  const int nseg = dense_segments(g);
+  const int rs = lb >> 1, band = rs / nseg, u0 = (rs - band * nseg) * kDenseSeg;
+  const int v0 = band * kDenseRows;
   int cnt = 0;
-  if (px < npx) {
-    const int v = px / g.w, u = px - v * g.w;
-    const int dp = (right ? F.dplaneR : F.dplaneL)[px];  // -1 without a plane
-    int res = -1;
-    if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
-      if (p.descriptor)
-        res = dense_pixel<KB, CensusDense>(F, g, p, right, has_list, u, v, dp, s_lut, &cnt);
-      else
-        res = dense_pixel<KB, GradDense>(F, g, p, right, has_list, u, v, dp, s_lut, &cnt);
-    }
-    (right ? F.rawR : F.rawL)[px] = (int16_t)res;
-  }
+  if (p.descriptor)
+    dense_rows<KB, CensusDense>(F, g, p, right, v0, u0, s_lut,
+                                reinterpret_cast<uint64_t*>(s_stage), &cnt);
+  else
+    dense_rows<KB, GradDense>(F, g, p, right, v0, u0, s_lut, s_stage, &cnt);
   cnt = wave_sum(cnt);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
@@ -1123,11 +1272,18 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
   __shared__ int16_t t[kMedH + 2 * kMedHalo][TW];
   const int u0 = (tile_id % nbx) * kMedW, v0 = (tile_id / nbx) * kMedH;
   const int tid = threadIdx.x;
-  for (int i = tid; i < (kMedH + 2 * kMedHalo) * TW; i += 256) {
-    const int r = i / TW, c = i - r * TW;
-    const int y = v0 - kMedHalo + r, x = u0 - kMedHalo + c;
-    t[r][c] = (x >= 0 && x < g.w && y >= 0 && y < g.h) ? in[(size_t)y * g.w + x] : (int16_t)-1;
-  }
+  constexpr int kTile = (kMedH + 2 * kMedHalo) * TW;
+  stage_copy<(kTile + 255) / 256, 256>(
+      kTile,
+      [&](int i) -> int {
+        const int r = i / TW, c = i - r * TW;
+        const int y = v0 - kMedHalo + r, x = u0 - kMedHalo + c;
+        return (x >= 0 && x < g.w && y >= 0 && y < g.h) ? (int)in[(size_t)y * g.w + x] : -1;
+      },
+      [&](int i, int x) {
+        const int r = i / TW, c = i - r * TW;
+        t[r][c] = (int16_t)x;
+      });
   __syncthreads();
   const int tx = tid & 63, ty = tid >> 6;
   const int u = u0 + tx, v = v0 + ty;
@@ -1157,9 +1313,9 @@ ELAS_STAGE_KERNELS(k_support, support_body, 256)
 ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
 ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
 ELAS_STAGE_KERNELS(k_raster, raster_body, kRasterThreads)
+ELAS_STAGE_KERNELS(k_dense1, dense_body<1>, 256)
+ELAS_STAGE_KERNELS(k_dense2, dense_body<2>, 256)
 ELAS_STAGE_KERNELS(k_dense4, dense_body<4>, 256)
-ELAS_STAGE_KERNELS(k_dense8, dense_body<8>, 256)
-ELAS_STAGE_KERNELS(k_dense16, dense_body<16>, 256)
 ELAS_STAGE_KERNELS(k_check, check_body, 256)
 ELAS_STAGE_KERNELS(k_redun, redun_body, 1024)
 ELAS_STAGE_KERNELS(k_median, median_body, 256)
@@ -1185,7 +1341,9 @@ int stage_threads(int32_t stage) {
 
 int32_t raster_band_rows(int32_t w) { return std::max(1, std::min(kBandRowsMax, 4096 / w)); }
 
-int32_t dense_blocks(const Geometry& g) { return 2 * cdiv((long long)g.w * g.h, 256); }
+int32_t dense_blocks(const Geometry& g) {
+  return 2 * cdiv(g.h, kDenseRows) * dense_segments(g);
+}
 
 int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv) {
   switch (stage) {
@@ -1243,11 +1401,11 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
     case kStageRaster: go(k_raster); break;
     case kStageDense:
       if (variant == 0)
-        go(k_dense4);
+        go(k_dense1);
       else if (variant == 2)
-        go(k_dense16);
+        go(k_dense4);
       else
-        go(k_dense8);
+        go(k_dense2);
       break;
     case kStageCheck: go(k_check); break;
     case kStageMedian: go(k_median); break;
@@ -1285,11 +1443,11 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
       break;
     case kStageDense:
       if (variant == 0)
-        hipLaunchKernelGGL(k_dense4_batch, grid, block, 0, s, frames, starts, nf);
+        hipLaunchKernelGGL(k_dense1_batch, grid, block, 0, s, frames, starts, nf);
       else if (variant == 2)
-        hipLaunchKernelGGL(k_dense16_batch, grid, block, 0, s, frames, starts, nf);
+        hipLaunchKernelGGL(k_dense4_batch, grid, block, 0, s, frames, starts, nf);
       else
-        hipLaunchKernelGGL(k_dense8_batch, grid, block, 0, s, frames, starts, nf);
+        hipLaunchKernelGGL(k_dense2_batch, grid, block, 0, s, frames, starts, nf);
       break;
     case kStageCheck:
       hipLaunchKernelGGL(k_check_batch, grid, block, 0, s, frames, starts, nf);

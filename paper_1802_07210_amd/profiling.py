@@ -51,7 +51,7 @@ def _col(row: dict, *names: str) -> str:
 
 
 def short_name(name: str) -> str:
-    """Kernel name without namespaces and arguments (k_dense8, k_mesh, ...)."""
+    """Kernel name without namespaces and arguments (k_dense2, k_mesh, ...)."""
     base = name.replace("(anonymous namespace)::", "").split("(")[0]
     return base.split("::")[-1].strip()
 
