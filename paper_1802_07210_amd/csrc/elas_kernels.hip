@@ -751,6 +751,7 @@ constexpr int kRasterScan = 8;      // triangles tested per thread and gather st
 constexpr int kRasterList = 4096;   // ranks of gathered triangles per pass
 constexpr int kBandRowsMax = 4;
 constexpr int kWaveSpan = 64 * (2 + 2 * kBandRowsMax);  // per-wave span table in LDS
+constexpr int kRasterOut = 8;       // output pixels per thread and step
 
 __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   __shared__ int32_t tile[kRasterTile];
@@ -780,12 +781,10 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
       int16_t tv[kRasterScan][3];
 #pragma unroll
       for (int k = 0; k < kRasterScan; ++k) {
-        const int r = r0 + k * kRasterThreads + tid;
-        if (r < nt) {
-          tv[k][0] = vt[r].v[0];
-          tv[k][1] = vt[r].v[1];
-          tv[k][2] = vt[r].v[2];
-        }
+        const int r = min(r0 + k * kRasterThreads + tid, nt - 1);  // in bounds: nt > 0 here
+        tv[k][0] = vt[r].v[0];
+        tv[k][1] = vt[r].v[1];
+        tv[k][2] = vt[r].v[2];
       }
 #pragma unroll
       for (int k = 0; k < kRasterScan; ++k) {
@@ -900,21 +899,43 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   // owners and the prior disparity of every pixel: the owning triangle's
   // plane mean ((a*u) + (b*v)) + c in FP32 without contraction, rounded as
   // floor(mean + 0.5) and clamped to the disparity range; -1 without owner
-  int32_t* owner = (view ? F.ownerR : F.ownerL) + (size_t)v0 * g.w;
-  int16_t* dpl = (view ? F.dplaneR : F.dplaneL) + (size_t)v0 * g.w;
+  int32_t* ownL = F.ownerL;
+  int32_t* ownR = F.ownerR;
+  int16_t* dplL = F.dplaneL;
+  int16_t* dplR = F.dplaneR;
+  int32_t* owner = (view ? ownR : ownL) + (size_t)v0 * g.w;
+  int16_t* dpl = (view ? dplR : dplL) + (size_t)v0 * g.w;
   const int dmin = F.p.dmin, dmax = F.p.dmax;
-  for (int i = tid; i < rows * g.w; i += kRasterThreads) {
-    const int o = tile[i];
-    owner[i] = o;
-    int dp = -1;
-    if (o != kNoOwner) {
-      const int q = i / g.w, u = i - q * g.w, v = v0 + q;
-      const float a = vt[o].a, b = vt[o].b, c = vt[o].c;
-      const float mu = __fadd_rn(__fadd_rn(__fmul_rn(a, (float)u), __fmul_rn(b, (float)v)), c);
-      const float f = floorf(__fadd_rn(mu, 0.5f));
-      dp = f < (float)dmin ? dmin : (f > (float)dmax ? dmax : (int)f);
+  const int npx = rows * g.w;
+  // kRasterOut pixels per thread at a time: their plane loads (from an
+  // in-bounds triangle even without an owner) are all in flight together
+  for (int i0 = 0; i0 < npx; i0 += kRasterOut * kRasterThreads) {
+    int o[kRasterOut];
+    float a[kRasterOut], b[kRasterOut], c[kRasterOut];
+#pragma unroll
+    for (int k = 0; k < kRasterOut; ++k) {
+      const int i = i0 + k * kRasterThreads + tid;
+      o[k] = i < npx ? tile[i] : kNoOwner;
+      const int t = (o[k] != kNoOwner) ? o[k] : 0;
+      a[k] = vt[t].a;
+      b[k] = vt[t].b;
+      c[k] = vt[t].c;
     }
-    dpl[i] = (int16_t)dp;
+#pragma unroll
+    for (int k = 0; k < kRasterOut; ++k) {
+      const int i = i0 + k * kRasterThreads + tid;
+      if (i >= npx) continue;
+      int dp = -1;
+      if (o[k] != kNoOwner) {
+        const int q = i / g.w, u = i - q * g.w, v = v0 + q;
+        const float mu = __fadd_rn(__fadd_rn(__fmul_rn(a[k], (float)u), __fmul_rn(b[k], (float)v)),
+                                   c[k]);
+        const float f = floorf(__fadd_rn(mu, 0.5f));
+        dp = f < (float)dmin ? dmin : (f > (float)dmax ? dmax : (int)f);
+      }
+      owner[i] = o[k];
+      dpl[i] = (int16_t)dp;
+    }
   }
 }
 
