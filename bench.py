@@ -324,10 +324,14 @@ def main():
     if args.mode == "serve":
         from paper_1802_07210_amd import serve
         cams, handles = serve.build_cameras()
-        batched = serve.run_sweep(seconds=args.serve_seconds, cams=cams, handles=handles)
-        plain = serve.run_sweep(seconds=args.serve_seconds, plain=True, cams=cams,
+        # the swept rates 200..2000 pairs/s, then rates beyond what one pair
+        # at a time can sustain, where continuous batching shows
+        rates = (200, 400, 800, 1200, 1600, 2000, 4000, 8000, 12000)
+        batched = serve.run_sweep(rates=rates, seconds=args.serve_seconds, cams=cams,
+                                  handles=handles)
+        plain = serve.run_sweep(rates=rates, seconds=args.serve_seconds, plain=True, cams=cams,
                                 handles=handles)
-        top = batched["levels"][-1]
+        top = [lv for lv in batched["levels"] if lv["rate"] == 2000][0]
         print(json.dumps({
             "metric": METRIC, "mode": "serve", "value": top["sustained_pairs_per_s"],
             "unit": "pairs/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
@@ -336,7 +340,7 @@ def main():
                                    "640x480 D128, 1242x375 D256, 1280x720 D192), Poisson "
                                    "arrivals swept over aggregate rates, seconds per level "
                                    f"{args.serve_seconds}", "cameras": 16, "pool_per_camera": 4},
-            "p50_ms_at_top_rate": top["p50_ms"], "p99_ms_at_top_rate": top["p99_ms"],
+            "p50_ms_at_2000": top["p50_ms"], "p99_ms_at_2000": top["p99_ms"],
             "batched": batched, "plain": plain}), flush=True)
         return
 
@@ -426,7 +430,7 @@ def main():
         # the full one): p50/p99 latency of the batched server and the plain one
         from paper_1802_07210_amd import serve
         cams, handles = serve.build_cameras()
-        rates = (200, 1000, 2000)
+        rates = (200, 2000, 8000)
         sb = serve.run_sweep(rates=rates, seconds=3.0, cams=cams, handles=handles)
         sp = serve.run_sweep(rates=rates, seconds=3.0, plain=True, cams=cams, handles=handles)
         out["serve"] = {"cameras": 16, "seconds_per_rate": 3.0,

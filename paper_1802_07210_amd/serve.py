@@ -12,6 +12,7 @@ completions over the time from the first submission to the last completion.
 from __future__ import annotations
 
 import math
+import sys
 import time
 from typing import Dict, List, Sequence
 
@@ -113,6 +114,8 @@ def run_sweep(rates: Sequence[float] = (200, 400, 800, 1200, 1600, 2000),
         nb = st1["batches"] - st0["batches"]
         lv["mean_batch"] = round((st1["batched_pairs"] - st0["batched_pairs"]) / max(1, nb), 2)
         levels.append(lv)
+        print(f"serve {'plain' if plain else 'batched'} rate {r}: {lv}", file=sys.stderr,
+              flush=True)
     st = server.stats()
     server.close()
     return {"mode": "plain" if plain else "batched", "max_batch": max_batch,
