@@ -161,6 +161,16 @@ def algorithmic_work(stage: str, w: int, h: int, st: dict):
     return 0, 0
 
 
+def workgroups(w: int, h: int, D: int, step: int = 5) -> dict:
+    """Workgroups each stage launches for one frame (default tile variants)."""
+    cd = lambda a, b: -(-a // b)
+    lw, lh = (w - 5) // step, (h - 5) // step
+    return {"descriptor": 2 * cd(w, 64) * cd(h, 4), "support": cd(lw * lh, 4),
+            "filter": cd(lw, 16) * cd(lh, 16), "rows": lh, "mesh": 2,
+            "raster": 2 * cd(h, max(1, min(4, 4096 // w))),
+            "dense": 2 * cd(h, 2) * cd(w, 256), "lrcheck": 2 * cd(w * h, 1024)}
+
+
 def roofline_of(stage: str, w: int, h: int, st: dict, ms: float, kernel: str) -> dict:
     """The binding roofline of one kernel: the resource whose floor (work over
     peak) is the larger; achieved = that work over the kernel's mean duration."""
@@ -396,8 +406,10 @@ def main():
     e.set_timing(False)
     stage_ms = {s: float(np.mean(v)) if v else float("nan") for s, v in acc.items()}
     kernel_ms = {s: stage_ms[s] for s in KERNEL_NAMES}
-    # share of chip time: the mesh kernel runs one workgroup (one CU) per view
-    chip_ms = {s: v * (2.0 / 256.0 if s == "mesh" else 1.0) for s, v in kernel_ms.items()}
+    # share of chip time: duration x the fraction of the 256 CUs the kernel's
+    # workgroups can occupy (launch geometry of each stage at this size)
+    wgs = workgroups(W, H, D)
+    chip_ms = {s: v * min(1.0, wgs[s] / 256.0) for s, v in kernel_ms.items()}
     dom = max(chip_ms, key=lambda k: chip_ms[k] if chip_ms[k] == chip_ms[k] else -1.0)
     st["lattice_rows"] = (H - 5) // 5
     roof = roofline_of(dom, W, H, st, kernel_ms[dom], KERNEL_NAMES[dom])

@@ -1189,6 +1189,8 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
 // ---------------------------------------------------------------------------
 // Final left/right consistency check (Section III-A: occlusions invalidated).
 // ---------------------------------------------------------------------------
+constexpr int kCheckPx = 4;  // pixels per thread (fewer, longer waves)
+
 __device__ __forceinline__ void check_body(const Frame& F, int lb) {
   const Geometry g = F.g;
   const int thr = F.p.lr_threshold;
@@ -1199,32 +1201,29 @@ __device__ __forceinline__ void check_body(const Frame& F, int lb) {
   int16_t* outR = F.outR;
   int16_t* chkL = F.chkL;
   int16_t* chkR = F.chkR;
-  const int px = (lb >> 1) * 256 + threadIdx.x;
-  if (px >= g.w * g.h) return;
-  const int v = px / g.w, u = px - v * g.w;
-  const size_t row = (size_t)v * g.w;
-  if ((lb & 1) == 0) {
-    const int d = rawL[px];
-    int r = -1;
-    if (d >= 0 && u - d >= 0) {
-      const int e = rawR[row + u - d];
-      if (e >= 0 && abs(e - d) <= thr) r = d;
-    }
-    if (med)
-      chkL[px] = (int16_t)r;
-    else
-      outL[px] = (int16_t)r;
-  } else {
-    const int d = rawR[px];
-    int r = -1;
-    if (d >= 0 && u + d < g.w) {
-      const int e = rawL[row + u + d];
-      if (e >= 0 && abs(e - d) <= thr) r = d;
-    }
-    if (med)
-      chkR[px] = (int16_t)r;
-    else
-      outR[px] = (int16_t)r;
+  const bool right = (lb & 1) != 0;
+  const int npx = g.w * g.h;
+  const int16_t* self = right ? rawR : rawL;
+  const int16_t* other = right ? rawL : rawR;
+  int16_t* dst = right ? (med ? chkR : outR) : (med ? chkL : outL);
+  const int px0 = (lb >> 1) * (256 * kCheckPx) + (int)threadIdx.x;
+  int d[kCheckPx], e[kCheckPx];
+#pragma unroll
+  for (int k = 0; k < kCheckPx; ++k) d[k] = self[min(px0 + 256 * k, npx - 1)];
+#pragma unroll
+  for (int k = 0; k < kCheckPx; ++k) {
+    const int px = min(px0 + 256 * k, npx - 1);
+    const int v = px / g.w, u = px - v * g.w;
+    const int x = right ? u + d[k] : u - d[k];  // partner column
+    const int ev = other[(size_t)v * g.w + min(max(x, 0), g.w - 1)];  // in bounds always
+    e[k] = (d[k] >= 0 && x >= 0 && x < g.w) ? ev : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < kCheckPx; ++k) {
+    const int px = px0 + 256 * k;
+    if (px >= npx) break;
+    const int r = (d[k] >= 0 && e[k] >= 0 && abs(e[k] - d[k]) <= thr) ? d[k] : -1;
+    dst[px] = (int16_t)r;
   }
 }
 
@@ -1377,7 +1376,7 @@ int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv)
     case kStageMesh: return 2;
     case kStageRaster: return 2 * cdiv(g.h, raster_band_rows(g.w));
     case kStageDense: return dense_blocks(g);
-    case kStageCheck: return 2 * cdiv((long long)g.w * g.h, 256);
+    case kStageCheck: return 2 * cdiv((long long)g.w * g.h, 256 * kCheckPx);
     case kStageMedian: return p.median ? 2 * cdiv(g.w, kMedW) * cdiv(g.h, kMedH) : 0;
     default: return 0;
   }
