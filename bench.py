@@ -143,8 +143,9 @@ def algorithmic_work(stage: str, w: int, h: int, st: dict):
     npx = w * h
     if stage == "descriptor":   # read 1 B image, write a 16 B descriptor; 2 views
         return 2 * npx * (1 + 16), 0
-    if stage == "support":      # descriptors of the lattice rows; 64 byte-|diff| per eval
-        return 2 * 16 * w * 5 * max(1, st.get("lattice_rows", 0)), 64 * st["support_evals"]
+    if stage == "support":      # descriptor rows v-2 and v+2 of each lattice row, 2 views;
+        # 64 byte-|diff| per 512-bit evaluation
+        return 2 * 2 * 16 * w * max(1, st.get("lattice_rows", 0)), 64 * st["support_evals"]
     if stage == "dense":        # own descriptor 16 B + prior 2 B read, raw 2 B written;
         return 2 * npx * (16 + 2 + 2), 16 * st["dense_evals"]       # 2 views
     if stage == "lrcheck":      # read 2 B + partner 2 B, write 2 B per pixel, 2 views
