@@ -167,7 +167,8 @@ def workgroups(w: int, h: int, D: int, step: int = 5) -> dict:
     cd = lambda a, b: -(-a // b)
     lw, lh = (w - 5) // step, (h - 5) // step
     return {"descriptor": 2 * cd(w, 64) * cd(h, 4), "support": cd(lw * lh, 4),
-            "filter": cd(lw, 16) * cd(lh, 16), "rows": lh, "mesh": 2,
+            "filter": (cd(lw, 8) * cd(lh, 8) if cd(lw, 8) * cd(lh, 8) <= 256
+                       else cd(lw, 16) * cd(lh, 16)), "rows": lh, "mesh": 2,
             "raster": 2 * cd(h, max(1, min(4, 4096 // w))),
             "dense": 2 * cd(h, 2) * cd(w, 256), "lrcheck": 2 * cd(w * h, 1024)}
 

@@ -450,8 +450,10 @@ __device__ __forceinline__ void support_body(const Frame& F, int lb) {
 
 // ---------------------------------------------------------------------------
 // Stage 3: support filtering (Section III-A, Fig. 1(e); Fig. 7A), three
-// simultaneous-update passes fused in one kernel over 16 x 16 lattice tiles
-// (1024 threads per tile, so each SIMD has four waves to hide LDS latency):
+// simultaneous-update passes fused in one kernel over 8 x 8 lattice tiles
+// (16 x 16 on lattices with more than 256 such tiles; 1024 threads per tile;
+// a position's consistency count is split over four lanes, so that the
+// longest per-thread chain is a quarter of the window):
 //  * consistency: a point survives iff at least incon_min_support other
 //    points within +-incon_window lattice steps have |d' - d| <=
 //    incon_threshold;
@@ -464,13 +466,18 @@ __device__ __forceinline__ void support_body(const Frame& F, int lb) {
 // grid masks that the rows stage fills. With past-only redundancy only the
 // consistency pass runs here.
 // ---------------------------------------------------------------------------
-constexpr int kFT = 16;
+constexpr int kFiltParts = 4;    // lanes sharing one position's consistency count
 
+// Tile side in lattice points: 8 while every tile can have a CU of its own,
+// else 16 (fewer halo positions per tile).
+__host__ __device__ __forceinline__ int filter_tile(const Geometry& g) {
+  return cdivd(max(g.lw, 1), 8) * cdivd(max(g.lh, 1), 8) <= 256 ? 8 : 16;
+}
 __host__ __device__ __forceinline__ int filter_tiles_x(const Geometry& g) {
-  return g.lw > 0 ? cdivd(g.lw, kFT) : 1;
+  return g.lw > 0 ? cdivd(g.lw, filter_tile(g)) : 1;
 }
 __host__ __device__ __forceinline__ int filter_tiles_y(const Geometry& g) {
-  return g.lh > 0 ? cdivd(g.lh, kFT) : 1;
+  return g.lh > 0 ? cdivd(g.lh, filter_tile(g)) : 1;
 }
 
 __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
@@ -478,12 +485,13 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
   const KParams p = F.p;
   int16_t* smem = reinterpret_cast<int16_t*>(dyn_smem);
   const int ri = p.incon_window, rr = p.redun_max_dist;
-  const int SR = kFT + 2 * (ri + rr), SI = kFT + 2 * rr;
+  const int ft = filter_tile(g);
+  const int SR = ft + 2 * (ri + rr), SI = ft + 2 * rr;
   int16_t* sraw = smem;            // SR x SR, origin (l0-ri-rr, k0-ri-rr)
   int16_t* sinc = sraw + SR * SR;  // SI x SI, origin (l0-rr, k0-rr)
-  int16_t* svert = sinc + SI * SI; // kFT x SI, origin (l0, k0-rr)
+  int16_t* svert = sinc + SI * SI; // ft x SI, origin (l0, k0-rr)
   const int ntx = filter_tiles_x(g), nblk = ntx * filter_tiles_y(g);
-  const int k0 = (lb % ntx) * kFT, l0 = (lb / ntx) * kFT;
+  const int k0 = (lb % ntx) * ft, l0 = (lb / ntx) * ft;
   const int tid = threadIdx.x;
   const int16_t* raw = F.dcan_raw;
   // clear the grid masks (grid-stride over the frame's blocks)
@@ -505,33 +513,42 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
       },
       [&](int i, int x) { sraw[i] = (int16_t)x; });
   __syncthreads();
-  for (int i = tid; i < SI * SI; i += 1024) {
-    const int y = i / SI, x = i - y * SI;
-    const int d = sraw[(y + ri) * SR + (x + ri)];
-    int res = -1;
-    if (d >= 0) {
+  // consistency count of each position: kFiltParts consecutive lanes take
+  // every kFiltParts-th window row and add their counts with shuffles (the
+  // loop bound is a multiple of 64, so whole wavefronts take part)
+  {
+    const int npos = SI * SI;
+    const int ntask = cdivd(npos * kFiltParts, 64) * 64;
+    for (int task = tid; task < ntask; task += 1024) {
+      const int i = min(task / kFiltParts, npos - 1), part = task % kFiltParts;
+      const int y = i / SI, x = i - y * SI;
+      const int d = sraw[(y + ri) * SR + (x + ri)];
       int count = 0;
-      for (int yy = y; yy <= y + 2 * ri; ++yy) {
-        const int16_t* row = sraw + yy * SR + x;
-        for (int xx = 0; xx <= 2 * ri; ++xx) {
-          const int e = row[xx];
-          count += (e >= 0 && abs(e - d) <= p.incon_threshold) ? 1 : 0;
+      if (d >= 0) {
+        for (int yy = y + part; yy <= y + 2 * ri; yy += kFiltParts) {
+          const int16_t* row = sraw + yy * SR + x;
+          for (int xx = 0; xx <= 2 * ri; ++xx) {
+            const int e = row[xx];
+            count += (e >= 0 && abs(e - d) <= p.incon_threshold) ? 1 : 0;
+          }
         }
       }
-      res = (count - 1 >= p.incon_min_support) ? d : -1;  // minus the point itself
+#pragma unroll
+      for (int off = 1; off < kFiltParts; off <<= 1) count += __shfl_xor(count, off, 64);
+      if (part == 0 && task / kFiltParts < npos)
+        sinc[i] = (int16_t)((d >= 0 && count - 1 >= p.incon_min_support) ? d : -1);  // minus itself
     }
-    sinc[i] = (int16_t)res;
   }
   __syncthreads();
   if (p.redundancy) {  // past-only redundancy runs in its own stage
-    if (tid < kFT * kFT) {
-      const int y = tid / kFT, x = tid - y * kFT;
+    if (tid < ft * ft) {
+      const int y = tid / ft, x = tid - y * ft;
       const int l = l0 + y, k = k0 + x;
       if (l < g.lh && k < g.lw) F.dcan_incon[(size_t)l * g.lw + k] = sinc[(y + rr) * SI + x + rr];
     }
     return;
   }
-  for (int i = tid; i < kFT * SI; i += 1024) {
+  for (int i = tid; i < ft * SI; i += 1024) {
     const int y = i / SI, x = i - y * SI;
     const int d = sinc[(y + rr) * SI + x];
     int res = d;
@@ -547,8 +564,8 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
     svert[i] = (int16_t)res;
   }
   __syncthreads();
-  if (tid < kFT * kFT) {
-    const int y = tid / kFT, x = tid - y * kFT;
+  if (tid < ft * ft) {
+    const int y = tid / ft, x = tid - y * ft;
     const int l = l0 + y, k = k0 + x;
     if (l < g.lh && k < g.lw) {
       const int d = svert[y * SI + x + rr];
@@ -1342,9 +1359,10 @@ ELAS_STAGE_KERNELS(k_median, median_body, 256)
 
 #undef ELAS_STAGE_KERNELS
 
-size_t filter_lds_bytes(const KParams& p) {
-  const int SR = kFT + 2 * (p.incon_window + p.redun_max_dist), SI = kFT + 2 * p.redun_max_dist;
-  return sizeof(int16_t) * (size_t)(SR * SR + SI * SI + kFT * SI);
+size_t filter_lds_bytes(const Geometry& g, const KParams& p) {
+  const int ft = filter_tile(g);
+  const int SR = ft + 2 * (p.incon_window + p.redun_max_dist), SI = ft + 2 * p.redun_max_dist;
+  return sizeof(int16_t) * (size_t)(SR * SR + SI * SI + ft * SI);
 }
 
 int stage_threads(int32_t stage) {
@@ -1384,7 +1402,7 @@ int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv)
 
 size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p) {
   switch (stage) {
-    case kStageFilter: return filter_lds_bytes(p);
+    case kStageFilter: return filter_lds_bytes(g, p);
     case kStageRows: return sizeof(int32_t) * (size_t)g.w;
     case kStageMesh: return kMeshLdsBytes;
     default: return 0;

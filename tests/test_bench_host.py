@@ -39,7 +39,7 @@ def test_binding_roofline_is_the_larger_floor():
 
 def test_workgroup_counts_of_the_bench_shape():
     wg = bench.workgroups(640, 480, 128)
-    assert wg["mesh"] == 2 and wg["filter"] == 8 * 6 and wg["rows"] == 95
+    assert wg["mesh"] == 2 and wg["filter"] == 16 * 12 and wg["rows"] == 95
     assert wg["dense"] == 2 * 240 * 3 and wg["raster"] == 2 * 120
 
 
