@@ -762,15 +762,20 @@ __device__ __forceinline__ void clip_edge(int k, int c, int* lo, int* hi) {
   }
 }
 
-constexpr int kRasterThreads = 256;
 constexpr int kRasterTile = 8192;   // LDS owner tile: band rows x width
-constexpr int kRasterScan = 8;      // triangles tested per thread and gather step
 constexpr int kRasterList = 4096;   // ranks of gathered triangles per pass
 constexpr int kBandRowsMax = 4;
 constexpr int kWaveSpan = 64 * (2 + 2 * kBandRowsMax);  // per-wave span table in LDS
-constexpr int kRasterOut = 8;       // output pixels per thread and step
 
+// Two workgroup sizes: 1024 threads spread a band's span expansion over 16
+// waves (single frames whose bands all fit on the CUs at once), 256 threads
+// pack more bands per CU (larger frames, batches).
+template <int kRasterThreads>
 __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
+  constexpr int kRasterScan = 2048 / kRasterThreads;  // triangles per thread and gather step
+  constexpr int kRasterOut = 2048 / kRasterThreads < 4 ? 4 : 2048 / kRasterThreads;
+  constexpr int kRasterWaves = kRasterThreads / 64;
+  static_assert(kRasterScan * kRasterThreads <= kRasterList, "a gather step must fit the list");
   __shared__ int32_t tile[kRasterTile];
   __shared__ int32_t rlist[kRasterList];
   __shared__ int32_t wspan[(kRasterThreads / 64) * kWaveSpan];
@@ -824,7 +829,7 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
     // rasterise the gathered triangles into the tile; consecutive entries go
     // to different waves
     for (int e0 = 0; e0 < cnt; e0 += kRasterThreads) {
-      const int e = e0 + (lane << 2) + wid;
+      const int e = e0 + lane * kRasterWaves + wid;
       int lo[kBandRowsMax], len[kBandRowsMax], tot = 0, rank = 0;
 #pragma unroll
       for (int q = 0; q < kBandRowsMax; ++q) {
@@ -1349,7 +1354,8 @@ ELAS_STAGE_KERNELS(k_descriptor16, stage1_body<16>, 256)
 ELAS_STAGE_KERNELS(k_support, support_body, 256)
 ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
 ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
-ELAS_STAGE_KERNELS(k_raster, raster_body, kRasterThreads)
+ELAS_STAGE_KERNELS(k_raster, raster_body<1024>, 1024)
+ELAS_STAGE_KERNELS(k_raster256, raster_body<256>, 256)
 ELAS_STAGE_KERNELS(k_dense1, dense_body<1>, 256)
 ELAS_STAGE_KERNELS(k_dense2, dense_body<2>, 256)
 ELAS_STAGE_KERNELS(k_dense4, dense_body<4>, 256)
@@ -1370,7 +1376,7 @@ int stage_threads(int32_t stage) {
     case kStageFilter: return 1024;
     case kStageRedun: return 1024;
     case kStageRows: return 64;
-    case kStageRaster: return kRasterThreads;
+    case kStageRaster: return 256;  // the batched launch; single frames choose in launch_stage
     default: return 256;
   }
 }
@@ -1414,7 +1420,9 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
   if (stage == kStageMesh) return launch_mesh_frame(f, s, start, stop);
   const int nb = stage_blocks(stage, f.g, f.p, variant);
   if (nb <= 0) return hipSuccess;
-  const dim3 grid(nb), block(stage_threads(stage));
+  // the wide raster workgroup when every band of the frame gets a CU
+  const bool wide_raster = stage == kStageRaster && nb <= 256;
+  const dim3 grid(nb), block(wide_raster ? 1024 : stage_threads(stage));
   const uint32_t lds = (uint32_t)stage_lds(stage, f.g, f.p);
   const bool timed = start || stop;
   auto go = [&](auto kernel) {
@@ -1436,7 +1444,12 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
     case kStageFilter: go(k_filter); break;
     case kStageRedun: go(k_redun); break;
     case kStageRows: go(k_rows); break;
-    case kStageRaster: go(k_raster); break;
+    case kStageRaster:
+      if (wide_raster)
+        go(k_raster);
+      else
+        go(k_raster256);
+      break;
     case kStageDense:
       if (variant == 0)
         go(k_dense1);
@@ -1477,7 +1490,7 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
       hipLaunchKernelGGL(k_rows_batch, grid, block, lds, s, frames, starts, nf);
       break;
     case kStageRaster:
-      hipLaunchKernelGGL(k_raster_batch, grid, block, 0, s, frames, starts, nf);
+      hipLaunchKernelGGL(k_raster256_batch, grid, block, 0, s, frames, starts, nf);
       break;
     case kStageDense:
       if (variant == 0)
