@@ -57,7 +57,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_SAD_TOPS = 256 * 64 * 2.4e9 * 4 / 1e12    # 157.3 T byte-|diff| per second
 
 STAGES = ["descriptor", "support", "filter", "rows", "mesh", "raster", "dense", "lrcheck"]
-KERNEL_NAMES = {"descriptor": "k_descriptor4", "support": "k_support", "filter": "k_filter",
+KERNEL_NAMES = {"descriptor": "k_descriptor8", "support": "k_support", "filter": "k_filter",
                 "rows": "k_rows", "mesh": "k_mesh", "raster": "k_raster", "dense": "k_dense2",
                 "lrcheck": "k_check"}
 
@@ -166,7 +166,7 @@ def workgroups(w: int, h: int, D: int, step: int = 5) -> dict:
     """Workgroups each stage launches for one frame (default tile variants)."""
     cd = lambda a, b: -(-a // b)
     lw, lh = (w - 5) // step, (h - 5) // step
-    return {"descriptor": 2 * cd(w, 64) * cd(h, 4), "support": cd(lw * lh, 4),
+    return {"descriptor": 2 * cd(w, 64) * cd(h, 8), "support": cd(lw * lh, 4),
             "filter": (cd(lw, 8) * cd(lh, 8) if cd(lw, 8) * cd(lh, 8) <= 256
                        else cd(lw, 16) * cd(lh, 16)), "rows": lh, "mesh": 2,
             "raster": 2 * cd(h, max(1, min(4, 4096 // w))),

@@ -421,7 +421,7 @@ int pool_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, size
 // the autotuner's choice, else the defaults.
 std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp, int32_t D) {
   auto it = h->tuned.find(std::make_tuple(w, hp, D));
-  return it != h->tuned.end() ? it->second : std::make_pair(0, 1);
+  return it != h->tuned.end() ? it->second : std::make_pair(1, 1);  // 8 rows, 2 per batch
 }
 
 std::pair<int, int> variants_for(const elas_handle* h, int32_t w, int32_t hp) {
