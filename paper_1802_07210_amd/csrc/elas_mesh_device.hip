@@ -385,6 +385,33 @@ __device__ void mesh_fail(MeshHeader* hdr, int view, int status) {
   }
 }
 
+// Tests edge i (end points a, b; apex p in the triangle) of triangle t for
+// round rr: the neighbour code e = 4 * o + j names the triangle o across the
+// edge and its apex index j. An edge whose other triangle was also flipped in
+// round rr - 1 (every triangle counts as flipped before round 1) is tested by
+// the one with the smaller index. An illegal edge claims both triangles with
+// the round-stamped inverted key (the smallest key wins) and is appended to
+// the round's candidates.
+template <typename I>
+__device__ __forceinline__ void test_edge(int t, uint32_t p, uint32_t a, uint32_t b, int i, int e,
+                                          int rr, const uint32_t* tk, const uint16_t* flipr,
+                                          typename ClaimT<I>::T* claim, I* cl, int* count,
+                                          int ncand, int* err) {
+  if (e < 0) return;
+  const int o = e >> 2, j = e & 3;
+  if (o < t && (int)flipr[o] == rr - 1) return;
+  if (!edge_illegal(p, a, b, tk[3 * o + j])) return;
+  const int key = t < o ? 4 * t + i : 4 * o + j;
+  const typename ClaimT<I>::T st = claim_stamp<I>(rr, key);
+  atomicMax(&claim[t], st);
+  atomicMax(&claim[o], st);
+  const int slot = atomicAdd(count, 1);
+  if (slot < ncand)
+    cl[slot] = (I)key;
+  else
+    *err = 2;
+}
+
 template <typename I>
 __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__ rows,
                          const int32_t* __restrict__ cnt_view, int c_first, int n, int tri_base,
@@ -577,66 +604,28 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   __syncthreads();
 
   // ---- 4. Lawson flips in synchronous rounds ------------------------------
-  for (int r = 1;; ++r) {
-    const int cur = r & 1, prev = cur ^ 1;
-    I* const lf_cur = cur ? lf1 : lf0;
-    const I* const lf_prev = cur ? lf0 : lf1;
-    I* const cl_cur = cur ? cl1 : cl0;
-    const I* const cl_prev = cur ? cl0 : cl1;
-    const int n_test = r == 1 ? NT : sh.nflip[prev];
-    const int n_old = r == 1 ? 0 : sh.ncand[prev];
-    // edges of the triangles flipped last round (every triangle in round 1);
-    // an edge between two such triangles is tested by the smaller one
-    for (int idx = tid; idx < n_test; idx += kMT) {
-      const int t = r == 1 ? idx : (int)lf_prev[idx];
-      const uint32_t kk[3] = {tk[3 * t], tk[3 * t + 1], tk[3 * t + 2]};
-      const int ee[3] = {tn[3 * t], tn[3 * t + 1], tn[3 * t + 2]};
+  // round 1 tests every edge; an edge between two tested triangles is tested
+  // by the one with the smaller index
+  for (int t = tid; t < NT; t += kMT) {
+    const uint32_t kk[3] = {tk[3 * t], tk[3 * t + 1], tk[3 * t + 2]};
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int e = ee[i];
-        if (e < 0) continue;
-        const int o = e >> 2, j = e & 3;
-        if (o < t && (int)flipr[o] == r - 1) continue;
-        if (edge_illegal(kk[i], kk[(i + 1) % 3], kk[(i + 2) % 3], tk[3 * o + j])) {
-          const int key = t < o ? 4 * t + i : 4 * o + j;
-          const C st = claim_stamp<I>(r, key);
-          atomicMax(&claim[t], st);
-          atomicMax(&claim[o], st);
-          const int slot = atomicAdd(&sh.ncand[cur], 1);
-          if (slot < ncand)
-            cl_cur[slot] = (I)key;
-          else
-            sh.err = 2;
-        }
-      }
-    }
-    // last round's candidates whose two triangles did not flip
-    for (int idx = tid; idx < n_old; idx += kMT) {
-      const int key = cl_prev[idx];
-      const int t = key >> 2, i = key & 3;
-      if ((int)flipr[t] == r - 1) continue;
-      const int o = (int)tn[3 * t + i] >> 2;
-      if ((int)flipr[o] == r - 1) continue;
-      const C st = claim_stamp<I>(r, key);
-      atomicMax(&claim[t], st);
-      atomicMax(&claim[o], st);
-      const int slot = atomicAdd(&sh.ncand[cur], 1);
-      if (slot < ncand)
-        cl_cur[slot] = (I)key;
-      else
-        sh.err = 2;
-    }
-    __syncthreads();
+    for (int i = 0; i < 3; ++i)
+      test_edge<I>(t, kk[i], kk[(i + 1) % 3], kk[(i + 2) % 3], i, (int)tn[3 * t + i], 1, tk,
+                   flipr, claim, cl1, &sh.ncand[1], ncand, &sh.err);
+  }
+  __syncthreads();
+  for (int r = 1;; ++r) {
+    const int cur = r & 1, nxt = cur ^ 1;
+    I* const lf_cur = cur ? lf1 : lf0;
+    I* const cl_cur = cur ? cl1 : cl0;
+    I* const cl_nxt = cur ? cl0 : cl1;
     const int nc = sh.ncand[cur];
     if (nc == 0) break;
     if (sh.err || r >= kMaxRounds) {
       mesh_fail<I>(hdr, view, sh.err ? sh.err : 1);
       return;
     }
-    if (tid == 0) {  // counters of the next round
-      sh.ncand[prev] = 0;
-      sh.nflip[prev] = 0;
-    }
+    if (tid == 0) sh.ncand[nxt] = 0;  // appended to only after the next barrier
     // winners flip: (p, a, b) + (q, b, a) -> (p, a, q) + (p, q, b)
     for (int idx = tid; idx < nc; idx += kMT) {
       const int key = cl_cur[idx];
@@ -673,36 +662,64 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       lf_cur[slot + 1] = (I)o;
     }
     __syncthreads();
-    // re-link: an unflipped neighbour is pointed back at the flipped
-    // triangle; across a flipped one the edge now lies in it or its partner
+    // every flipped triangle re-links its outer edges (an unflipped
+    // neighbour is pointed back at it; across a flipped one the edge now lies
+    // in that triangle or its partner) and at once tests them for round r+1;
+    // round r's candidates whose two triangles did not flip carry over
     const int nf = sh.nflip[cur];
+    if (tid == 0) sh.nflip[nxt] = 0;  // appended to only after the next barrier
     for (int idx = tid; idx < nf; idx += kMT) {
       const int x = lf_cur[idx];
       const int px = partner[x];
+      const uint32_t kk[3] = {tk[3 * x], tk[3 * x + 1], tk[3 * x + 2]};
+      int ne[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const int e = tn[3 * x + k];
-        if (e < 0) continue;
-        int z = e >> 2;
-        if (z == px) continue;
-        if ((int)flipr[z] != r) {
-          tn[3 * z + (e & 3)] = (I)(4 * x + k);
-          continue;
+        int e = tn[3 * x + k];
+        if (e >= 0) {
+          int z = e >> 2;
+          if (z != px) {
+            if ((int)flipr[z] != r) {
+              tn[3 * z + (e & 3)] = (I)(4 * x + k);
+            } else {
+              const uint32_t ea = kk[k == 2 ? 0 : k + 1];
+              const uint32_t eb = kk[k == 0 ? 2 : k - 1];
+              uint32_t z0 = tk[3 * z], z1 = tk[3 * z + 1], z2 = tk[3 * z + 2];
+              const bool has_a = z0 == ea || z1 == ea || z2 == ea;
+              const bool has_b = z0 == eb || z1 == eb || z2 == eb;
+              if (!(has_a && has_b)) {
+                z = partner[z];
+                z0 = tk[3 * z];
+                z1 = tk[3 * z + 1];
+                z2 = tk[3 * z + 2];
+              }
+              const int jj = (z0 != ea && z0 != eb) ? 0 : ((z1 != ea && z1 != eb) ? 1 : 2);
+              e = 4 * z + jj;
+              tn[3 * x + k] = (I)e;
+            }
+          }
         }
-        const uint32_t ea = tk[3 * x + (k == 2 ? 0 : k + 1)];
-        const uint32_t eb = tk[3 * x + (k == 0 ? 2 : k - 1)];
-        uint32_t z0 = tk[3 * z], z1 = tk[3 * z + 1], z2 = tk[3 * z + 2];
-        const bool has_a = z0 == ea || z1 == ea || z2 == ea;
-        const bool has_b = z0 == eb || z1 == eb || z2 == eb;
-        if (!(has_a && has_b)) {
-          z = partner[z];
-          z0 = tk[3 * z];
-          z1 = tk[3 * z + 1];
-          z2 = tk[3 * z + 2];
-        }
-        const int jj = (z0 != ea && z0 != eb) ? 0 : ((z1 != ea && z1 != eb) ? 1 : 2);
-        tn[3 * x + k] = (I)(4 * z + jj);
+        ne[k] = e;
       }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        test_edge<I>(x, kk[i], kk[(i + 1) % 3], kk[(i + 2) % 3], i, ne[i], r + 1, tk, flipr,
+                     claim, cl_nxt, &sh.ncand[nxt], ncand, &sh.err);
+    }
+    for (int idx = tid; idx < nc; idx += kMT) {
+      const int key = cl_cur[idx];
+      const int t = key >> 2, i = key & 3;
+      if ((int)flipr[t] == r) continue;
+      const int o = (int)tn[3 * t + i] >> 2;
+      if ((int)flipr[o] == r) continue;
+      const C st = claim_stamp<I>(r + 1, key);
+      atomicMax(&claim[t], st);
+      atomicMax(&claim[o], st);
+      const int slot = atomicAdd(&sh.ncand[nxt], 1);
+      if (slot < ncand)
+        cl_nxt[slot] = (I)key;
+      else
+        sh.err = 2;
     }
     __syncthreads();
   }
