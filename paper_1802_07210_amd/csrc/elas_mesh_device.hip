@@ -412,6 +412,83 @@ __device__ __forceinline__ void test_edge(int t, uint32_t p, uint32_t a, uint32_
     *err = 2;
 }
 
+// Re-links the three outer edges of triangle x, flipped in round r, and
+// tests them for round r + 1. Every entry that any case may need (the
+// neighbour across each edge, its flip round, keys and partner, and the
+// partner's keys) is loaded up front from indices kept in range, so the
+// chain is a few LDS round trips whatever the cases; the values are then
+// picked in registers. A neighbour that did not flip is written back at x;
+// only x's own thread writes x's entries in this phase.
+template <typename I>
+__device__ __forceinline__ void relink_test(int x, int r, int NT, const uint32_t* tk, I* tn,
+                                            const uint16_t* flipr, const I* partner,
+                                            typename ClaimT<I>::T* claim, I* cl, int* count,
+                                            int ncand, int* err) {
+  const int px = partner[x];
+  const uint32_t k0 = tk[3 * x], k1 = tk[3 * x + 1], k2 = tk[3 * x + 2];
+  int e[3], z[3], fz[3], pz[3];
+  uint32_t zk[3][3], qk[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    e[k] = tn[3 * x + k];
+    z[k] = e[k] < 0 ? x : e[k] >> 2;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    fz[k] = flipr[z[k]];
+    pz[k] = min(max((int)partner[z[k]], 0), NT - 1);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) zk[k][m] = tk[3 * z[k] + m];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) qk[k][m] = tk[3 * pz[k] + m];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint32_t p = k == 0 ? k0 : (k == 1 ? k1 : k2);
+    const uint32_t ea = k == 0 ? k1 : (k == 1 ? k2 : k0);
+    const uint32_t eb = k == 0 ? k2 : (k == 1 ? k0 : k1);
+    if (e[k] < 0) continue;
+    int ne = e[k];
+    uint32_t s0 = zk[k][0], s1 = zk[k][1], s2 = zk[k][2];
+    if (z[k] != px) {
+      if (fz[k] != r) {
+        tn[3 * z[k] + (e[k] & 3)] = (I)(4 * x + k);
+      } else {
+        const bool has_a = s0 == ea || s1 == ea || s2 == ea;
+        const bool has_b = s0 == eb || s1 == eb || s2 == eb;
+        int zz = z[k];
+        if (!(has_a && has_b)) {
+          zz = pz[k];
+          s0 = qk[k][0];
+          s1 = qk[k][1];
+          s2 = qk[k][2];
+        }
+        const int jj = (s0 != ea && s0 != eb) ? 0 : ((s1 != ea && s1 != eb) ? 1 : 2);
+        ne = 4 * zz + jj;
+        tn[3 * x + k] = (I)ne;
+      }
+    }
+    // the triangle across is z (unflipped, or x's partner) or z or its
+    // partner (both flipped in round r); s0..s2 hold its keys
+    const int o = ne >> 2, j = ne & 3;
+    const int fo = o == z[k] ? fz[k] : r;
+    if (o < x && fo == r) continue;
+    const uint32_t q = j == 0 ? s0 : (j == 1 ? s1 : s2);
+    if (!edge_illegal(p, ea, eb, q)) continue;
+    const int key = x < o ? 4 * x + k : ne;
+    const typename ClaimT<I>::T st = claim_stamp<I>(r + 1, key);
+    atomicMax(&claim[x], st);
+    atomicMax(&claim[o], st);
+    const int slot = atomicAdd(count, 1);
+    if (slot < ncand)
+      cl[slot] = (I)key;
+    else
+      *err = 2;
+  }
+}
+
 template <typename I>
 __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__ rows,
                          const int32_t* __restrict__ cnt_view, int c_first, int n, int tri_base,
@@ -626,21 +703,29 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       return;
     }
     if (tid == 0) sh.ncand[nxt] = 0;  // appended to only after the next barrier
-    // winners flip: (p, a, b) + (q, b, a) -> (p, a, q) + (p, q, b)
+    // winners flip: (p, a, b) + (q, b, a) -> (p, a, q) + (p, q, b). Both
+    // triangles' entries are loaded before the claims are compared, from
+    // indices kept in range, so one wait covers them; they are used only by
+    // the winner, which alone writes them in this phase.
     for (int idx = tid; idx < nc; idx += kMT) {
       const int key = cl_cur[idx];
       const int t = key >> 2, i = key & 3;
       const C st = claim_stamp<I>(r, key);
-      if (claim[t] != st) continue;
-      const int e = tn[3 * t + i];
-      const int o = e >> 2, j = e & 3;
-      if (claim[o] != st) continue;
-      const int i1 = i == 2 ? 0 : i + 1, i2 = i == 0 ? 2 : i - 1;
+      const C ct = claim[t];
+      const uint32_t t0 = tk[3 * t], t1 = tk[3 * t + 1], t2 = tk[3 * t + 2];
+      const I n0 = tn[3 * t], n1 = tn[3 * t + 1], n2 = tn[3 * t + 2];
+      const int e = i == 0 ? (int)n0 : (i == 1 ? (int)n1 : (int)n2);
+      const int o = e < 0 ? t : e >> 2, j = e & 3;
       const int j1 = j == 2 ? 0 : j + 1, j2 = j == 0 ? 2 : j - 1;
-      const uint32_t p = tk[3 * t + i], a = tk[3 * t + i1], b = tk[3 * t + i2];
+      const C co = claim[o];
       const uint32_t q = tk[3 * o + j];
-      const I t_bp = tn[3 * t + i1], t_pa = tn[3 * t + i2];
       const I o_aq = tn[3 * o + j1], o_qb = tn[3 * o + j2];
+      if (ct != st || co != st) continue;
+      const uint32_t p = i == 0 ? t0 : (i == 1 ? t1 : t2);
+      const uint32_t a = i == 0 ? t1 : (i == 1 ? t2 : t0);
+      const uint32_t b = i == 0 ? t2 : (i == 1 ? t0 : t1);
+      const I t_bp = i == 0 ? n1 : (i == 1 ? n2 : n0);
+      const I t_pa = i == 0 ? n2 : (i == 1 ? n0 : n1);
       tk[3 * t] = p;
       tk[3 * t + 1] = a;
       tk[3 * t + 2] = q;
@@ -662,56 +747,23 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       lf_cur[slot + 1] = (I)o;
     }
     __syncthreads();
-    // every flipped triangle re-links its outer edges (an unflipped
+    // Items [0, nf): a flipped triangle re-links its outer edges (an unflipped
     // neighbour is pointed back at it; across a flipped one the edge now lies
-    // in that triangle or its partner) and at once tests them for round r+1;
-    // round r's candidates whose two triangles did not flip carry over
+    // in that triangle or its partner) and at once tests them for round r+1.
+    // Items [nf, nf + nc): round r's candidates whose two triangles did not
+    // flip carry over. Both kinds run side by side on different threads.
     const int nf = sh.nflip[cur];
     if (tid == 0) sh.nflip[nxt] = 0;  // appended to only after the next barrier
-    for (int idx = tid; idx < nf; idx += kMT) {
-      const int x = lf_cur[idx];
-      const int px = partner[x];
-      const uint32_t kk[3] = {tk[3 * x], tk[3 * x + 1], tk[3 * x + 2]};
-      int ne[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        int e = tn[3 * x + k];
-        if (e >= 0) {
-          int z = e >> 2;
-          if (z != px) {
-            if ((int)flipr[z] != r) {
-              tn[3 * z + (e & 3)] = (I)(4 * x + k);
-            } else {
-              const uint32_t ea = kk[k == 2 ? 0 : k + 1];
-              const uint32_t eb = kk[k == 0 ? 2 : k - 1];
-              uint32_t z0 = tk[3 * z], z1 = tk[3 * z + 1], z2 = tk[3 * z + 2];
-              const bool has_a = z0 == ea || z1 == ea || z2 == ea;
-              const bool has_b = z0 == eb || z1 == eb || z2 == eb;
-              if (!(has_a && has_b)) {
-                z = partner[z];
-                z0 = tk[3 * z];
-                z1 = tk[3 * z + 1];
-                z2 = tk[3 * z + 2];
-              }
-              const int jj = (z0 != ea && z0 != eb) ? 0 : ((z1 != ea && z1 != eb) ? 1 : 2);
-              e = 4 * z + jj;
-              tn[3 * x + k] = (I)e;
-            }
-          }
-        }
-        ne[k] = e;
+    for (int idx = tid; idx < nf + nc; idx += kMT) {
+      if (idx < nf) {
+        relink_test<I>(lf_cur[idx], r, NT, tk, tn, flipr, partner, claim, cl_nxt,
+                       &sh.ncand[nxt], ncand, &sh.err);
+        continue;
       }
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        test_edge<I>(x, kk[i], kk[(i + 1) % 3], kk[(i + 2) % 3], i, ne[i], r + 1, tk, flipr,
-                     claim, cl_nxt, &sh.ncand[nxt], ncand, &sh.err);
-    }
-    for (int idx = tid; idx < nc; idx += kMT) {
-      const int key = cl_cur[idx];
+      const int key = cl_cur[idx - nf];
       const int t = key >> 2, i = key & 3;
-      if ((int)flipr[t] == r) continue;
       const int o = (int)tn[3 * t + i] >> 2;
-      if ((int)flipr[o] == r) continue;
+      if ((int)flipr[t] == r || (int)flipr[o] == r) continue;
       const C st = claim_stamp<I>(r + 1, key);
       atomicMax(&claim[t], st);
       atomicMax(&claim[o], st);
