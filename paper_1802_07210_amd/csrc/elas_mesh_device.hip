@@ -412,6 +412,13 @@ __device__ __forceinline__ void test_edge(int t, uint32_t p, uint32_t a, uint32_
     *err = 2;
 }
 
+// An empty asm that reads its operands: the loads that produce them are
+// issued before it and waited for together there, instead of one by one in
+// the branches that use them.
+__device__ __forceinline__ void pin(int v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void pin(uint32_t v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void pin(unsigned long long v) { asm volatile("" ::"v"(v)); }
+
 // Re-links the three outer edges of triangle x, flipped in round r, and
 // tests them for round r + 1. Every entry that any case may need (the
 // neighbour across each edge, its flip round, keys and partner, and the
@@ -646,15 +653,23 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   }
   __syncthreads();
   for (int e = tid; e < 3 * NT; e += kMT) {
-    // half-edge a -> b opposite vertex k; its twin runs b -> a
+    // half-edge a -> b opposite vertex k; its twin runs b -> a. The twin's
+    // triangle holds a half-edge leaving b (the twin) and one leaving a (the
+    // one after the twin, whose opposite vertex is b), so the smaller of the
+    // two buckets is searched: the corners' buckets are long.
     const int t = e / 3, k = e - 3 * t;
     const int a = tv[3 * t + (k == 2 ? 0 : k + 1)], b = tv[3 * t + (k == 0 ? 2 : k - 1)];
+    const int sa = vcnt[a], sa1 = vcnt[a + 1], sb = vcnt[b], sb1 = vcnt[b + 1];
+    const bool from_b = sb1 - sb <= sa1 - sa;
+    const int want = from_b ? a : b;
     int nb = -1;
-    for (int s = vcnt[b], s1 = vcnt[b + 1]; s < s1; ++s) {
+    for (int s = from_b ? sb : sa, s1 = from_b ? sb1 : sa1; s < s1; ++s) {
       const int e2 = hbuck[s];
       const int t2 = e2 / 3, k2 = e2 - 3 * t2;
-      if ((int)tv[3 * t2 + (k2 == 0 ? 2 : k2 - 1)] == a) {
-        nb = 4 * t2 + k2;
+      // from b: the end of b -> x; from a: the vertex before a in a -> x
+      const int probe = from_b ? (k2 == 0 ? 2 : k2 - 1) : k2;
+      if ((int)tv[3 * t2 + probe] == want) {
+        nb = 4 * t2 + (from_b ? k2 : (k2 == 0 ? 2 : k2 - 1));
         break;
       }
     }
@@ -720,6 +735,16 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       const C co = claim[o];
       const uint32_t q = tk[3 * o + j];
       const I o_aq = tn[3 * o + j1], o_qb = tn[3 * o + j2];
+      pin(t0);
+      pin(t1);
+      pin(t2);
+      pin((int)n0);
+      pin((int)n1);
+      pin((int)n2);
+      pin(q);
+      pin((int)o_aq);
+      pin((int)o_qb);
+      pin(co);
       if (ct != st || co != st) continue;
       const uint32_t p = i == 0 ? t0 : (i == 1 ? t1 : t2);
       const uint32_t a = i == 0 ? t1 : (i == 1 ? t2 : t0);
@@ -762,8 +787,10 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       }
       const int key = cl_cur[idx - nf];
       const int t = key >> 2, i = key & 3;
+      const int ft = flipr[t];
       const int o = (int)tn[3 * t + i] >> 2;
-      if ((int)flipr[t] == r || (int)flipr[o] == r) continue;
+      const int fo = flipr[o];
+      if ((ft == r) | (fo == r)) continue;
       const C st = claim_stamp<I>(r + 1, key);
       atomicMax(&claim[t], st);
       atomicMax(&claim[o], st);
