@@ -53,6 +53,7 @@ namespace {
 
 constexpr int kMT = 1024;          // threads per mesh workgroup
 constexpr int kMaxRounds = 32000;  // flip rounds before a view reports status 1
+constexpr int kPocketG = 8;        // lanes per side pocket point
 
 // ---- point keys and exact predicates --------------------------------------
 __device__ __forceinline__ int key_u(uint32_t k) { return (int)((k >> 8) & 0xFFFu); }
@@ -290,36 +291,64 @@ __device__ __forceinline__ void put_tri(I* tv, int NT, int k, int a, int b, int 
 }
 
 // One side pocket point: chain index k in 1..m of side s (0: the rows' first
-// points against the left border, 1: last points against the right border).
-template <typename I>
+// points against the left border, 1: last points against the right border),
+// evaluated by a group of G lanes (l: this lane's index in the group; the
+// group's lanes are consecutive and run this call together).
+template <typename I, int G>
 __device__ __forceinline__ void pocket_point(const uint32_t* pk, const uint32_t* ck,
                                              const int32_t* ci, I* tv, int NT, int s, int k, int m,
-                                             int n, int slot0, int* err) {
+                                             int n, int slot0, int l, int* err) {
   const int T = s == 0 ? 0 : 1, B = s == 0 ? n + 2 : n + 3;
   const uint32_t c = ck[k - 1];
-  // below c on the stack: the earlier point at the extreme angle from c
+  // below c on the stack: the earlier point at the extreme angle from c, the
+  // later one on ties. All earlier points (and the top corner, index 0 here)
+  // lie strictly above c's row, so the angle order is total and the choice
+  // is an argmax: each lane takes every G-th point, then the lanes combine.
   uint32_t q = pk[T];
-  int qi = T;
-  for (int x = 1; x < k; ++x) {
+  int qx = l == 0 ? 0 : -1;  // -1: none yet
+#pragma unroll 2
+  for (int x = 1 + l; x < k; x += G) {
     const uint32_t kx = ck[x - 1];
     const int o = orient_k(q, c, kx);
-    if (s == 0 ? o >= 0 : o <= 0) {
+    if (qx < 0 || (s == 0 ? o >= 0 : o <= 0)) {
       q = kx;
-      qi = ci[x - 1];
+      qx = x;
     }
   }
-  // the point that pops c: the first later point strictly across (q, c)
-  uint32_t p = pk[B];
-  int pi = B;
-  for (int y = k + 1; y <= m; ++y) {
-    const uint32_t ky = ck[y - 1];
-    const int o = orient_k(q, c, ky);
-    if (s == 0 ? o > 0 : o < 0) {
-      p = ky;
-      pi = ci[y - 1];
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) {
+    const uint32_t q2 = __shfl_xor(q, off, 64);
+    const int x2 = __shfl_xor(qx, off, 64);
+    const int o = orient_k(q, c, q2);
+    const bool take =
+        x2 >= 0 && (qx < 0 || (s == 0 ? o > 0 : o < 0) || (o == 0 && x2 > qx));
+    if (take) {
+      q = q2;
+      qx = x2;
+    }
+  }
+  // the point that pops c: the first later point strictly across (q, c),
+  // found G points at a time
+  const int gbase = (threadIdx.x & 63) - l;
+  const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+  int py = m + 1;  // none: the bottom corner
+  for (int base = k + 1; base <= m; base += G) {
+    const int y = base + l;
+    bool hit = false;
+    if (y <= m) {
+      const int o = orient_k(q, c, ck[y - 1]);
+      hit = s == 0 ? o > 0 : o < 0;
+    }
+    const unsigned long long gm = (__ballot(hit) >> gbase) & gmask;
+    if (gm) {
+      py = base + __ffsll((long long)gm) - 1;
       break;
     }
   }
+  if (l != 0) return;
+  const int qi = qx == 0 ? T : ci[qx - 1];
+  const int pi = py > m ? B : ci[py - 1];
+  const uint32_t p = py > m ? pk[B] : ck[py - 1];
   put_tri(tv, NT, slot0 + k - 1, qi, ci[k - 1], pi, q, c, p, err);
 }
 
@@ -614,8 +643,11 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   const int strip_tris = scan_array(stripOff, m + 2, sh.wsum);
 
   // ---- 2. initial triangulation: strips and both pockets concurrently ------
-  if (tid < kMT / 2) {
-    for (int s = tid; s <= m; s += kMT / 2) {
+  // one thread per strip, in whole waves; the rest split between the two
+  // pockets, kPocketG lanes per chain point
+  const int n_strip_thr = min(kMT / 2, (m + 1 + 63) & ~63);
+  if (tid < n_strip_thr) {
+    for (int s = tid; s <= m; s += n_strip_thr) {
       const int fa = s == 0 ? 0 : 2 + rowStart[rowNE[s - 1]];
       const int ca = s == 0 ? 2 : rowStart[rowNE[s - 1] + 1] - rowStart[rowNE[s - 1]];
       const int fb = s == m ? n + 2 : 2 + rowStart[rowNE[s]];
@@ -623,10 +655,14 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       zipper(pk, tv, NT, fa, ca, fb, cb, stripOff[s], &sh.err);
     }
   } else {
-    const int side = (tid - kMT / 2) / (kMT / 4), lt = (tid - kMT / 2) % (kMT / 4);
-    for (int k = 1 + lt; k <= m; k += kMT / 4)
-      pocket_point(pk, side == 0 ? chainK0 : chainK1, side == 0 ? chainI0 : chainI1, tv, NT,
-                   side, k, m, n, strip_tris + side * m, &sh.err);
+    const int per_side = (kMT - n_strip_thr) / 2;  // a multiple of 32
+    const int u = tid - n_strip_thr;
+    const int side = u / per_side, lt = u - side * per_side;
+    const int groups = per_side / kPocketG;
+    for (int k = 1 + lt / kPocketG; k <= m; k += groups)
+      pocket_point<I, kPocketG>(pk, side == 0 ? chainK0 : chainK1,
+                                side == 0 ? chainI0 : chainI1, tv, NT, side, k, m, n,
+                                strip_tris + side * m, lt % kPocketG, &sh.err);
   }
   if (tid == 0 && strip_tris + 2 * m != NT) sh.err = 2;
   __syncthreads();
