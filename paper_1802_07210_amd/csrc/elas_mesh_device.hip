@@ -448,81 +448,62 @@ __device__ __forceinline__ void pin(int v) { asm volatile("" ::"v"(v)); }
 __device__ __forceinline__ void pin(uint32_t v) { asm volatile("" ::"v"(v)); }
 __device__ __forceinline__ void pin(unsigned long long v) { asm volatile("" ::"v"(v)); }
 
-// Re-links the three outer edges of triangle x, flipped in round r, and
-// tests them for round r + 1. Every entry that any case may need (the
-// neighbour across each edge, its flip round, keys and partner, and the
-// partner's keys) is loaded up front from indices kept in range, so the
-// chain is a few LDS round trips whatever the cases; the values are then
-// picked in registers. A neighbour that did not flip is written back at x;
-// only x's own thread writes x's entries in this phase.
+// Re-links outer edge k of triangle x, flipped in round r, and tests it for
+// round r + 1 (one lane per edge: the three edges of x touch disjoint
+// entries). An unflipped neighbour is pointed back at x; across a flipped
+// one the edge now lies in that triangle or its partner. The entries any
+// case may need are loaded up front from indices kept in range.
 template <typename I>
-__device__ __forceinline__ void relink_test(int x, int r, int NT, const uint32_t* tk, I* tn,
-                                            const uint16_t* flipr, const I* partner,
+__device__ __forceinline__ void relink_edge(int x, int k, int r, int NT, const uint32_t* tk,
+                                            I* tn, const uint16_t* flipr, const I* partner,
                                             typename ClaimT<I>::T* claim, I* cl, int* count,
                                             int ncand, int* err) {
   const int px = partner[x];
   const uint32_t k0 = tk[3 * x], k1 = tk[3 * x + 1], k2 = tk[3 * x + 2];
-  int e[3], z[3], fz[3], pz[3];
-  uint32_t zk[3][3], qk[3][3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    e[k] = tn[3 * x + k];
-    z[k] = e[k] < 0 ? x : e[k] >> 2;
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    fz[k] = flipr[z[k]];
-    pz[k] = min(max((int)partner[z[k]], 0), NT - 1);
-#pragma unroll
-    for (int m = 0; m < 3; ++m) zk[k][m] = tk[3 * z[k] + m];
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-#pragma unroll
-    for (int m = 0; m < 3; ++m) qk[k][m] = tk[3 * pz[k] + m];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const uint32_t p = k == 0 ? k0 : (k == 1 ? k1 : k2);
-    const uint32_t ea = k == 0 ? k1 : (k == 1 ? k2 : k0);
-    const uint32_t eb = k == 0 ? k2 : (k == 1 ? k0 : k1);
-    if (e[k] < 0) continue;
-    int ne = e[k];
-    uint32_t s0 = zk[k][0], s1 = zk[k][1], s2 = zk[k][2];
-    if (z[k] != px) {
-      if (fz[k] != r) {
-        tn[3 * z[k] + (e[k] & 3)] = (I)(4 * x + k);
-      } else {
-        const bool has_a = s0 == ea || s1 == ea || s2 == ea;
-        const bool has_b = s0 == eb || s1 == eb || s2 == eb;
-        int zz = z[k];
-        if (!(has_a && has_b)) {
-          zz = pz[k];
-          s0 = qk[k][0];
-          s1 = qk[k][1];
-          s2 = qk[k][2];
-        }
-        const int jj = (s0 != ea && s0 != eb) ? 0 : ((s1 != ea && s1 != eb) ? 1 : 2);
-        ne = 4 * zz + jj;
-        tn[3 * x + k] = (I)ne;
+  int e = tn[3 * x + k];
+  if (e < 0) return;
+  const uint32_t p = k == 0 ? k0 : (k == 1 ? k1 : k2);
+  const uint32_t ea = k == 0 ? k1 : (k == 1 ? k2 : k0);
+  const uint32_t eb = k == 0 ? k2 : (k == 1 ? k0 : k1);
+  int z = e >> 2;
+  const int fz = flipr[z];
+  const int pz = min(max((int)partner[z], 0), NT - 1);
+  uint32_t z0 = tk[3 * z], z1 = tk[3 * z + 1], z2 = tk[3 * z + 2];
+  const uint32_t q0 = tk[3 * pz], q1 = tk[3 * pz + 1], q2 = tk[3 * pz + 2];
+  int fo = fz;
+  if (z != px) {
+    if (fz != r) {
+      tn[3 * z + (e & 3)] = (I)(4 * x + k);
+    } else {
+      const bool has_a = z0 == ea || z1 == ea || z2 == ea;
+      const bool has_b = z0 == eb || z1 == eb || z2 == eb;
+      if (!(has_a && has_b)) {
+        z = pz;
+        z0 = q0;
+        z1 = q1;
+        z2 = q2;
       }
+      const int jj = (z0 != ea && z0 != eb) ? 0 : ((z1 != ea && z1 != eb) ? 1 : 2);
+      e = 4 * z + jj;
+      tn[3 * x + k] = (I)e;
+      fo = r;
     }
-    // the triangle across is z (unflipped, or x's partner) or z or its
-    // partner (both flipped in round r); s0..s2 hold its keys
-    const int o = ne >> 2, j = ne & 3;
-    const int fo = o == z[k] ? fz[k] : r;
-    if (o < x && fo == r) continue;
-    const uint32_t q = j == 0 ? s0 : (j == 1 ? s1 : s2);
-    if (!edge_illegal(p, ea, eb, q)) continue;
-    const int key = x < o ? 4 * x + k : ne;
-    const typename ClaimT<I>::T st = claim_stamp<I>(r + 1, key);
-    atomicMax(&claim[x], st);
-    atomicMax(&claim[o], st);
-    const int slot = atomicAdd(count, 1);
-    if (slot < ncand)
-      cl[slot] = (I)key;
-    else
-      *err = 2;
   }
+  // the triangle across is o = e >> 2 with keys z0..z2; an edge between two
+  // triangles flipped in round r is tested by the one with the smaller index
+  const int o = e >> 2, j = e & 3;
+  if (o < x && fo == r) return;
+  const uint32_t q = j == 0 ? z0 : (j == 1 ? z1 : z2);
+  if (!edge_illegal(p, ea, eb, q)) return;
+  const int key = x < o ? 4 * x + k : e;
+  const typename ClaimT<I>::T st = claim_stamp<I>(r + 1, key);
+  atomicMax(&claim[x], st);
+  atomicMax(&claim[o], st);
+  const int slot = atomicAdd(count, 1);
+  if (slot < ncand)
+    cl[slot] = (I)key;
+  else
+    *err = 2;
 }
 
 template <typename I>
@@ -808,20 +789,20 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       lf_cur[slot + 1] = (I)o;
     }
     __syncthreads();
-    // Items [0, nf): a flipped triangle re-links its outer edges (an unflipped
-    // neighbour is pointed back at it; across a flipped one the edge now lies
-    // in that triangle or its partner) and at once tests them for round r+1.
-    // Items [nf, nf + nc): round r's candidates whose two triangles did not
-    // flip carry over. Both kinds run side by side on different threads.
+    // Items [0, 3 nf): edge idx % 3 of flipped triangle idx / 3 is re-linked
+    // and at once tested for round r + 1. Items [3 nf, 3 nf + nc): round r's
+    // candidates whose two triangles did not flip carry over. Both kinds run
+    // side by side on different threads.
     const int nf = sh.nflip[cur];
     if (tid == 0) sh.nflip[nxt] = 0;  // appended to only after the next barrier
-    for (int idx = tid; idx < nf + nc; idx += kMT) {
-      if (idx < nf) {
-        relink_test<I>(lf_cur[idx], r, NT, tk, tn, flipr, partner, claim, cl_nxt,
-                       &sh.ncand[nxt], ncand, &sh.err);
+    for (int idx = tid; idx < 3 * nf + nc; idx += kMT) {
+      if (idx < 3 * nf) {
+        const int item = idx / 3;
+        relink_edge<I>(lf_cur[item], idx - 3 * item, r, NT, tk, tn, flipr, partner, claim,
+                       cl_nxt, &sh.ncand[nxt], ncand, &sh.err);
         continue;
       }
-      const int key = cl_cur[idx - nf];
+      const int key = cl_cur[idx - 3 * nf];
       const int t = key >> 2, i = key & 3;
       const int ft = flipr[t];
       const int o = (int)tn[3 * t + i] >> 2;
