@@ -11,8 +11,9 @@
 //     order, so triangles carry keys and need no vertex ids.
 //  2. initial triangulation. Support points lie on lattice rows, so the
 //     region between two consecutive non-empty rows (the image's top and
-//     bottom edges act as extra rows) is a trapezoid, triangulated by a
-//     zipper over the two sorted rows (one thread per strip). The two side
+//     bottom edges act as extra rows) is a trapezoid, triangulated by the
+//     in-circle zipper over the two sorted rows, which for two horizontal
+//     rows is a merge of their edge u-sums (one lane per row edge). The two side
 //     pockets between the rows' end points and the image border are
 //     polygons monotone in v with one straight side. Their stack
 //     triangulation has a closed form that is evaluated in parallel: the
@@ -53,7 +54,7 @@ namespace {
 
 constexpr int kMT = 1024;          // threads per mesh workgroup
 constexpr int kMaxRounds = 32000;  // flip rounds before a view reports status 1
-constexpr int kPocketG = 8;        // lanes per side pocket point
+constexpr int kPocketG = 4;        // lanes per side pocket point
 
 // ---- point keys and exact predicates --------------------------------------
 __device__ __forceinline__ int key_u(uint32_t k) { return (int)((k >> 8) & 0xFFFu); }
@@ -164,6 +165,7 @@ struct MeshMem {
   // rows and side chains (sized by the lattice height only)
   int32_t* rowStart;     // lh + 1: first point of each lattice row, then n
   int32_t* rowNE;        // lh + 1: non-empty lattice rows in order
+  int32_t* rowRank;      // lh + 1: index of a non-empty lattice row among them
   int32_t* stripOff;     // lh + 2: first triangle of each strip
   uint32_t *chainK0, *chainK1;  // lh + 1: key of the first / last point of each non-empty row
   int32_t *chainI0, *chainI1;   // lh + 1: its rank
@@ -213,6 +215,7 @@ __host__ __device__ __forceinline__ size_t carve(char* base, int n, int lh, Mesh
   MeshMem<I> t{};
   t.rowStart = reinterpret_cast<int32_t*>(c.take(L * 4));
   t.rowNE = reinterpret_cast<int32_t*>(c.take(L * 4));
+  t.rowRank = reinterpret_cast<int32_t*>(c.take(L * 4));
   t.stripOff = reinterpret_cast<int32_t*>(c.take(L * 4));
   t.chainK0 = reinterpret_cast<uint32_t*>(c.take(L * 4));
   t.chainI0 = reinterpret_cast<int32_t*>(c.take(L * 4));
@@ -352,44 +355,99 @@ __device__ __forceinline__ void pocket_point(const uint32_t* pk, const uint32_t*
   put_tri(tv, NT, slot0 + k - 1, qi, ci[k - 1], pi, q, c, p, err);
 }
 
-// Zipper over one strip between the upper row (ranks fa.., ca points) and
-// the lower row (fb.., cb points), writing ca + cb - 2 triangles from slot k.
-template <typename I>
-__device__ __forceinline__ void zipper(const uint32_t* pk, I* tv, int NT, int fa, int ca, int fb,
-                                       int cb, int k, int* err) {
-  int i = 0, j = 0;
-  uint32_t A0 = pk[fa], A1 = ca > 1 ? pk[fa + 1] : 0u;
-  uint32_t B0 = pk[fb], B1 = cb > 1 ? pk[fb + 1] : 0u;
-  while (i + 1 < ca || j + 1 < cb) {
-    bool adv_i;
-    if (i + 1 >= ca)
-      adv_i = false;
-    else if (j + 1 >= cb)
-      adv_i = true;
+// Strip triangles. Within the band between two consecutive non-empty rows
+// (upper row A, lower row B, both sorted by u and each on one lattice row)
+// a zipper that takes the in-circle choice of the diagonal at every step is
+// a merge: for points on two horizontal lines, B[j+1] lies strictly inside
+// the circle through A[i], A[i+1], B[j] exactly when
+// u(B[j]) + u(B[j+1]) < u(A[i]) + u(A[i+1]). So the top edge i takes the
+// triangle (A[i], A[i+1], B[j]) with j the number of lower edge sums below
+// its sum, and the bottom edge j the triangle (A[i], B[j+1], B[j]) with i
+// the number of upper edge sums at or below its sum (ties: the upper edge
+// first); either sits at slot i + j of the band. Rows of band s: the upper
+// one is the top corners for s = 0, the lower one the bottom corners for
+// s = m.
+struct BandRow {
+  int first, count;  // rank of its first point, number of points
+};
+
+__device__ __forceinline__ BandRow band_upper(int s, const int32_t* rowStart,
+                                              const int32_t* rowNE) {
+  if (s == 0) return {0, 2};
+  const int l = rowNE[s - 1];
+  return {2 + rowStart[l], rowStart[l + 1] - rowStart[l]};
+}
+
+__device__ __forceinline__ BandRow band_lower(int s, int m, int n, const int32_t* rowStart,
+                                              const int32_t* rowNE) {
+  if (s == m) return {n + 2, 2};
+  const int l = rowNE[s];
+  return {2 + rowStart[l], rowStart[l + 1] - rowStart[l]};
+}
+
+// Number of edges of row r whose u-sum is below sum (or_equal: at or below).
+__device__ __forceinline__ int edges_below(const uint32_t* pk, BandRow r, int sum,
+                                           bool or_equal) {
+  int lo = 0, hi = r.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int t = key_u(pk[r.first + mid]) + key_u(pk[r.first + mid + 1]);
+    if (t < sum || (or_equal && t == sum))
+      lo = mid + 1;
     else
-      adv_i = !(incircle_k(A0, A1, B0, B1) > 0.0);
-    if (k >= NT) {
+      hi = mid;
+  }
+  return lo;
+}
+
+// The one or two band triangles of edge (ga, ga + 1). q = 0: the top
+// corners (top edge of band 0); q = 1: the bottom corners (bottom edge of
+// band m); q >= 2: the points of rank q and q + 1 if they share a row (the
+// top edge of the band below, the bottom edge of the band above).
+template <typename I>
+__device__ __forceinline__ void strip_edge(int q, const uint32_t* pk, const int32_t* rowStart,
+                                           const int32_t* rowNE, const int32_t* rowRank,
+                                           const int32_t* stripOff, const Geometry& g, int m,
+                                           int n, I* tv, int NT, int* err) {
+  int ga, idx, below, above;  // band below / above the edge, -1: none
+  if (q == 0) {
+    ga = 0, idx = 0, below = 0, above = -1;
+  } else if (q == 1) {
+    ga = n + 2, idx = 0, below = -1, above = m;
+  } else {
+    if (q + 1 > n + 1) return;
+    ga = q;
+    if (key_v(pk[q]) != key_v(pk[q + 1])) return;  // q ends its row
+    const int l = (key_v(pk[q]) - g.lv0) / g.step;
+    const int rho = rowRank[l];
+    idx = q - (2 + rowStart[l]);
+    below = rho + 1;
+    above = rho;
+  }
+  const int sum = key_u(pk[ga]) + key_u(pk[ga + 1]);
+  if (below >= 0) {
+    const BandRow B = band_lower(below, m, n, rowStart, rowNE);
+    const int j = edges_below(pk, B, sum, false);
+    const int k = stripOff[below] + idx + j;
+    if (k < 0 || k >= NT) {
       *err = 2;
-      return;
-    }
-    // the upper row lies above the lower one and both run left to right, so
-    // these vertex orders are counter-clockwise
-    if (adv_i) {
-      tv[3 * k] = (I)(fa + i);
-      tv[3 * k + 1] = (I)(fa + i + 1);
-      tv[3 * k + 2] = (I)(fb + j);
-      ++i;
-      A0 = A1;
-      A1 = i + 1 < ca ? pk[fa + i + 1] : 0u;
     } else {
-      tv[3 * k] = (I)(fa + i);
-      tv[3 * k + 1] = (I)(fb + j + 1);
-      tv[3 * k + 2] = (I)(fb + j);
-      ++j;
-      B0 = B1;
-      B1 = j + 1 < cb ? pk[fb + j + 1] : 0u;
+      tv[3 * k] = (I)ga;
+      tv[3 * k + 1] = (I)(ga + 1);
+      tv[3 * k + 2] = (I)(B.first + j);
     }
-    ++k;
+  }
+  if (above >= 0) {
+    const BandRow A = band_upper(above, rowStart, rowNE);
+    const int i = edges_below(pk, A, sum, true);
+    const int k = stripOff[above] + i + idx;
+    if (k < 0 || k >= NT) {
+      *err = 2;
+    } else {
+      tv[3 * k] = (I)(A.first + i);
+      tv[3 * k + 1] = (I)(ga + 1);
+      tv[3 * k + 2] = (I)ga;
+    }
   }
 }
 
@@ -518,6 +576,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   carve<I>(base, n, g.lh, M);
   int32_t* const rowStart = M.rowStart;
   int32_t* const rowNE = M.rowNE;
+  int32_t* const rowRank = M.rowRank;
   int32_t* const stripOff = M.stripOff;
   uint32_t* const chainK0 = M.chainK0;
   uint32_t* const chainK1 = M.chainK1;
@@ -592,7 +651,10 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
     const int f = (l < g.lh && rowStart[l + 1] > rowStart[l]) ? 1 : 0;
     int tot;
     const int e = scan_excl(f, &tot, sh.wsum);
-    if (f) rowNE[m + e] = l;
+    if (f) {
+      rowNE[m + e] = l;
+      rowRank[l] = m + e;
+    }
     m += tot;
   }
   if (tid < 4) {
@@ -624,22 +686,14 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   const int strip_tris = scan_array(stripOff, m + 2, sh.wsum);
 
   // ---- 2. initial triangulation: strips and both pockets concurrently ------
-  // one thread per strip, in whole waves; the rest split between the two
-  // pockets, kPocketG lanes per chain point
-  const int n_strip_thr = min(kMT / 2, (m + 1 + 63) & ~63);
-  if (tid < n_strip_thr) {
-    for (int s = tid; s <= m; s += n_strip_thr) {
-      const int fa = s == 0 ? 0 : 2 + rowStart[rowNE[s - 1]];
-      const int ca = s == 0 ? 2 : rowStart[rowNE[s - 1] + 1] - rowStart[rowNE[s - 1]];
-      const int fb = s == m ? n + 2 : 2 + rowStart[rowNE[s]];
-      const int cb = s == m ? 2 : rowStart[rowNE[s] + 1] - rowStart[rowNE[s]];
-      zipper(pk, tv, NT, fa, ca, fb, cb, stripOff[s], &sh.err);
-    }
-  } else {
-    const int per_side = (kMT - n_strip_thr) / 2;  // a multiple of 32
-    const int u = tid - n_strip_thr;
-    const int side = u / per_side, lt = u - side * per_side;
-    const int groups = per_side / kPocketG;
+  // every thread takes its band edges (one lane per row edge and per corner
+  // edge), then its share of the pockets (kPocketG lanes per chain point,
+  // half of the workgroup per side); the two write disjoint triangles
+  for (int q = tid; q < n + 2; q += kMT)
+    strip_edge(q, pk, rowStart, rowNE, rowRank, stripOff, g, m, n, tv, NT, &sh.err);
+  {
+    const int side = tid / (kMT / 2), lt = tid % (kMT / 2);
+    const int groups = kMT / 2 / kPocketG;
     for (int k = 1 + lt / kPocketG; k <= m; k += groups)
       pocket_point<I, kPocketG>(pk, side == 0 ? chainK0 : chainK1,
                                 side == 0 ? chainI0 : chainI1, tv, NT, side, k, m, n,
