@@ -55,6 +55,7 @@ namespace {
 constexpr int kMT = 1024;          // threads per mesh workgroup
 constexpr int kMaxRounds = 32000;  // flip rounds before a view reports status 1
 constexpr int kPocketG = 4;        // lanes per side pocket point
+constexpr int kTwinUnknown = -2;   // neighbour code of a half-edge not yet matched
 
 // ---- point keys and exact predicates --------------------------------------
 __device__ __forceinline__ int key_u(uint32_t k) { return (int)((k >> 8) & 0xFFFu); }
@@ -400,7 +401,10 @@ __device__ __forceinline__ int edges_below(const uint32_t* pk, BandRow r, int su
   return lo;
 }
 
-// The one or two band triangles of edge (ga, ga + 1). q = 0: the top
+// The one or two band triangles of edge (ga, ga + 1), with the twins known
+// from the construction: the row edge joins them, and each is joined to the
+// next triangle of its band across their diagonal (local vertex 0 of a top
+// edge triangle or 2 of a bottom edge one, against 1 of the next). q = 0: the top
 // corners (top edge of band 0); q = 1: the bottom corners (bottom edge of
 // band m); q >= 2: the points of rank q and q + 1 if they share a row (the
 // top edge of the band below, the bottom edge of the band above).
@@ -408,7 +412,7 @@ template <typename I>
 __device__ __forceinline__ void strip_edge(int q, const uint32_t* pk, const int32_t* rowStart,
                                            const int32_t* rowNE, const int32_t* rowRank,
                                            const int32_t* stripOff, const Geometry& g, int m,
-                                           int n, I* tv, int NT, int* err) {
+                                           int n, I* tv, I* tn, int NT, int* err) {
   int ga, idx, below, above;  // band below / above the edge, -1: none
   if (q == 0) {
     ga = 0, idx = 0, below = 0, above = -1;
@@ -425,29 +429,47 @@ __device__ __forceinline__ void strip_edge(int q, const uint32_t* pk, const int3
     above = rho;
   }
   const int sum = key_u(pk[ga]) + key_u(pk[ga + 1]);
+  int kb = -1, ka = -1;
   if (below >= 0) {
     const BandRow B = band_lower(below, m, n, rowStart, rowNE);
     const int j = edges_below(pk, B, sum, false);
     const int k = stripOff[below] + idx + j;
-    if (k < 0 || k >= NT) {
+    if (k < 0 || k + 1 > NT) {
       *err = 2;
     } else {
       tv[3 * k] = (I)ga;
       tv[3 * k + 1] = (I)(ga + 1);
       tv[3 * k + 2] = (I)(B.first + j);
+      kb = k;
+      // the next triangle of the band shares the diagonal (A[i+1], B[j])
+      if (k + 1 < stripOff[below + 1]) {
+        tn[3 * k] = (I)(4 * (k + 1) + 1);
+        tn[3 * (k + 1) + 1] = (I)(4 * k);
+      }
     }
   }
   if (above >= 0) {
     const BandRow A = band_upper(above, rowStart, rowNE);
     const int i = edges_below(pk, A, sum, true);
     const int k = stripOff[above] + i + idx;
-    if (k < 0 || k >= NT) {
+    if (k < 0 || k + 1 > NT) {
       *err = 2;
     } else {
       tv[3 * k] = (I)(A.first + i);
       tv[3 * k + 1] = (I)(ga + 1);
       tv[3 * k + 2] = (I)ga;
+      ka = k;
+      // the next triangle of the band shares the diagonal (A[i], B[j+1])
+      if (k + 1 < stripOff[above + 1]) {
+        tn[3 * k + 2] = (I)(4 * (k + 1) + 1);
+        tn[3 * (k + 1) + 1] = (I)(4 * k + 2);
+      }
     }
+  }
+  // a row edge joins its two band triangles
+  if (kb >= 0 && ka >= 0) {
+    tn[3 * kb + 2] = (I)(4 * ka);
+    tn[3 * ka] = (I)(4 * kb + 2);
   }
 }
 
@@ -602,6 +624,8 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   const int NP = M.NP, NT = M.NT, ncand = M.ncand;
 
   // ---- 1. points in rank order, corners ----------------------------------
+  // neighbours not known from the construction keep this mark until step 3
+  for (int e = tid; e < 3 * NT; e += kMT) tn[e] = (I)kTwinUnknown;
   for (int l = tid; l < g.lh; l += kMT) rowStart[l] = l < kMT ? c_first : cnt_view[l];
   if (tid == 0) rowStart[g.lh] = 0;
   if (tid < 4) sh.corner[tid] = ~0ull;
@@ -690,7 +714,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   // edge), then its share of the pockets (kPocketG lanes per chain point,
   // half of the workgroup per side); the two write disjoint triangles
   for (int q = tid; q < n + 2; q += kMT)
-    strip_edge(q, pk, rowStart, rowNE, rowRank, stripOff, g, m, n, tv, NT, &sh.err);
+    strip_edge(q, pk, rowStart, rowNE, rowRank, stripOff, g, m, n, tv, tn, NT, &sh.err);
   {
     const int side = tid / (kMT / 2), lt = tid % (kMT / 2);
     const int groups = kMT / 2 / kPocketG;
@@ -707,6 +731,9 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   }
 
   // ---- 3. adjacency -------------------------------------------------------
+  // every half-edge is bucketed by origin vertex; only those whose twin the
+  // bands did not set (the pockets' edges and each band's two side edges)
+  // are matched
   for (int v = tid; v <= NP; v += kMT) vcnt[v] = 0;
   __syncthreads();
   for (int e = tid; e < 3 * NT; e += kMT) {
@@ -724,12 +751,21 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   }
   __syncthreads();
   for (int e = tid; e < 3 * NT; e += kMT) {
+    if ((int)tn[e] != kTwinUnknown) continue;
     // half-edge a -> b opposite vertex k; its twin runs b -> a. The twin's
     // triangle holds a half-edge leaving b (the twin) and one leaving a (the
     // one after the twin, whose opposite vertex is b), so the smaller of the
     // two buckets is searched: the corners' buckets are long.
     const int t = e / 3, k = e - 3 * t;
     const int a = tv[3 * t + (k == 2 ? 0 : k + 1)], b = tv[3 * t + (k == 0 ? 2 : k - 1)];
+    // with any list point, the starting mesh joins two corners only along the
+    // image sides (bands and pockets each hold a list point otherwise): those
+    // are the border, whose search would run through two long buckets
+    if (n > 0 && (a < 2 || a >= n + 2) && (b < 2 || b >= n + 2)) {
+      tn[e] = (I)-1;
+      atomicAdd(&sh.border, 1);
+      continue;
+    }
     const int sa = vcnt[a], sa1 = vcnt[a + 1], sb = vcnt[b], sb1 = vcnt[b + 1];
     const bool from_b = sb1 - sb <= sa1 - sa;
     const int want = from_b ? a : b;
