@@ -303,7 +303,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
-    ap.add_argument("--streams", type=int, default=4,
+    ap.add_argument("--streams", type=int, default=3,
                     help="frames in flight: steps are issued round-robin on this many streams")
     ap.add_argument("--mode", choices=["frame", "serve", "calib"], default="frame",
                     help="frame: the 640x480 frame rate (default); serve: the camera-stream "

@@ -241,7 +241,7 @@ ELAS_API int elas_frame_bytes(elas_handle* h, int32_t w, int32_t h_px, int64_t* 
 typedef struct elas_server elas_server;
 typedef struct elas_server_config {
   int32_t max_batch;            /* pairs per launch, 1..1024 (32) */
-  int32_t max_inflight;         /* batches on the device at once, 1..16 (4) */
+  int32_t max_inflight;         /* batches on the device at once, 1..16 (3) */
   int64_t memory_budget;        /* device bytes of the pairs in flight (32 GiB) */
   int32_t plain;                /* 1: one pair at a time via elas_process (0) */
 } elas_server_config;

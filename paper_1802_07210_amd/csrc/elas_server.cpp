@@ -177,7 +177,7 @@ extern "C" {
 void elas_server_config_default(elas_server_config* c) {
   if (!c) return;
   c->max_batch = 32;
-  c->max_inflight = 4;
+  c->max_inflight = 3;
   c->memory_budget = (int64_t)32 << 30;
   c->plain = 0;
 }

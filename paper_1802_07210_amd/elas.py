@@ -333,7 +333,7 @@ class Server:
     """Continuous-batching server over one handle (the handle and every
     parameter handle of submitted pairs belong to the server until close)."""
 
-    def __init__(self, elas: "Elas", max_batch: int = 32, max_inflight: int = 4,
+    def __init__(self, elas: "Elas", max_batch: int = 32, max_inflight: int = 3,
                  memory_budget: int = 32 << 30, plain: bool = False):
         cfg = ServerConfig()
         lib().elas_server_config_default(C.byref(cfg))

@@ -95,7 +95,7 @@ def run_level(server, cams, handles, rate: float, seconds: float, seed: int) -> 
 
 def run_sweep(rates: Sequence[float] = (200, 400, 800, 1200, 1600, 2000),
               seconds: float = 10.0, cameras: int = 16, pool: int = 4, plain: bool = False,
-              max_batch: int = 32, max_inflight: int = 4, budget: int = 32 << 30,
+              max_batch: int = 32, max_inflight: int = 3, budget: int = 32 << 30,
               seed: int = 0, cams=None, handles=None) -> dict:
     from .elas import Elas, Server
     if cams is None:
