@@ -21,8 +21,10 @@
 //     extreme angle seen from it (the later one on ties); the point that pops
 //     it is the first later chain point strictly across that segment (none:
 //     the bottom corner). Each chain point gives one triangle.
-//  3. adjacency: half-edges bucketed by origin vertex, each matched with its
-//     reverse; a neighbour is stored as 4 * triangle + local vertex index.
+//  3. adjacency: a neighbour is stored as 4 * triangle + local vertex index.
+//     The bands set the neighbours their construction fixes (row edges and
+//     band diagonals); the other half-edges are matched with their reverse
+//     through buckets by origin vertex.
 //  4. Lawson flips in synchronous rounds until every edge is legal under the
 //     canonical rule (strictly outside the circumcircle, or exactly on it and
 //     the (v, u)-smallest of the four points is an endpoint of the edge).
