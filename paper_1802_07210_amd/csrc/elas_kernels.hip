@@ -779,6 +779,7 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   __shared__ int32_t tile[kRasterTile];
   __shared__ int32_t rlist[kRasterList];
   __shared__ int32_t wspan[(kRasterThreads / 64) * kWaveSpan];
+  __shared__ int32_t s_wtot[kRasterThreads / 64];  // span pixels per wave (1024 threads)
   __shared__ int s_cnt, s_done;
   const Geometry g = F.g;
   const int band_rows = F.raster_rows;
@@ -826,10 +827,15 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
       __syncthreads();
       if (done || cnt > kRasterList - kRasterScan * kRasterThreads) break;
     }
-    // rasterise the gathered triangles into the tile; consecutive entries go
-    // to different waves
+    // rasterise the gathered triangles into the tile. With 1024 threads,
+    // consecutive entries go to consecutive lanes, so only the first
+    // ceil(cnt / 64) waves work out spans, and every thread then takes an
+    // equal share of all span pixels; with 256 threads (several bands per
+    // CU), consecutive entries go to different waves and each wave expands
+    // its own spans
+    constexpr bool kShared = kRasterThreads == 1024;
     for (int e0 = 0; e0 < cnt; e0 += kRasterThreads) {
-      const int e = e0 + lane * kRasterWaves + wid;
+      const int e = kShared ? e0 + tid : e0 + lane * kRasterWaves + wid;
       int lo[kBandRowsMax], len[kBandRowsMax], tot = 0, rank = 0;
 #pragma unroll
       for (int q = 0; q < kBandRowsMax; ++q) {
@@ -860,16 +866,16 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
           tot += len[q];
         }
       }
-      // the wave's spans, lane by lane and row by row, form one pixel range;
-      // each lane takes a contiguous share of it, finds its first span with
-      // a binary search over the lanes' offsets and walks on from there
+      // the spans (of all waves, wave by wave, or of this wave), lane by lane
+      // and row by row, form one pixel range; each thread takes a contiguous
+      // share of it, finds its first span by a search over the waves' and
+      // the lanes' offsets and walks on from there
       int incl = tot;
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         const int y = __shfl_up(incl, off, 64);
         if (lane >= off) incl += y;
       }
-      const int P = __shfl(incl, 63, 64);
       int32_t* W = wspan + wid * kWaveSpan;  // [offsets 64][lo 64x4][len 64x4][rank 64]
       W[lane] = incl - tot;
 #pragma unroll
@@ -878,24 +884,40 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
         W[320 + 4 * lane + q] = len[q];
       }
       W[576 + lane] = rank;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int C = (P + 63) >> 6;
-      int i = lane * C;
-      const int iend = min(P, i + C);
+      int P, i;
+      if constexpr (kShared) {
+        if (lane == 63) s_wtot[wid] = incl;
+        __syncthreads();
+        P = 0;
+#pragma unroll
+        for (int w = 0; w < kRasterWaves; ++w) P += s_wtot[w];
+        i = tid * ((P + kRasterThreads - 1) / kRasterThreads);
+      } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        P = __shfl(incl, 63, 64);
+        i = lane * ((P + 63) >> 6);
+      }
+      const int iend = min(P, kShared ? i + (P + kRasterThreads - 1) / kRasterThreads
+                                      : i + ((P + 63) >> 6));
       if (i < iend) {
-        int a = 0, b = 63;  // last lane whose pixels start at or before i
+        int w = kShared ? 0 : wid, wbase = 0;  // the wave holding pixel i
+        if constexpr (kShared)
+          while (wbase + s_wtot[w] <= i) wbase += s_wtot[w++];
+        const int32_t* Wt = wspan + w * kWaveSpan;
+        const int li = i - wbase;
+        int a = 0, b = 63;  // last lane whose pixels start at or before li
         while (a < b) {
           const int mid = (a + b + 1) >> 1;
-          if (W[mid] <= i) a = mid; else b = mid - 1;
+          if (Wt[mid] <= li) a = mid; else b = mid - 1;
         }
-        int j = a, off = i - W[a], q = 0;
-        while (off >= W[320 + 4 * j + q]) {
-          off -= W[320 + 4 * j + q];
+        int j = a, off = li - Wt[a], q = 0;
+        while (off >= Wt[320 + 4 * j + q]) {
+          off -= Wt[320 + 4 * j + q];
           ++q;
         }
-        int L = W[320 + 4 * j + q], S = W[64 + 4 * j + q], R = W[576 + j];
+        int L = Wt[320 + 4 * j + q], S = Wt[64 + 4 * j + q], R = Wt[576 + j];
         for (;;) {
           atomicMin(&tile[q * g.w + S + off], R);
           if (++i >= iend) break;
@@ -904,16 +926,22 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
             do {
               if (++q == kBandRowsMax) {
                 q = 0;
-                ++j;
+                if (++j == 64) {
+                  j = 0;
+                  Wt += kWaveSpan;
+                }
               }
-              L = W[320 + 4 * j + q];
+              L = Wt[320 + 4 * j + q];
             } while (L == 0);
-            S = W[64 + 4 * j + q];
-            R = W[576 + j];
+            S = Wt[64 + 4 * j + q];
+            R = Wt[576 + j];
           }
         }
       }
-      __builtin_amdgcn_wave_barrier();
+      if constexpr (kShared)
+        __syncthreads();  // the span tables are written again by the next entries
+      else
+        __builtin_amdgcn_wave_barrier();
     }
     if (done || r0 >= nt) break;
   }
