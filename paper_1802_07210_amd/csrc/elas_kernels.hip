@@ -1092,8 +1092,10 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
 #pragma unroll
   for (int j = 0; j < kMaxD / 32; ++j) {
     if (j >= nw) break;
+    const uint32_t grid = p.full_search ? 0xFFFFFFFFu : cw[j];
+    if (grid == 0u) continue;  // nothing to mask (most words of a cell)
     const int wb = 32 * j;
-    uint32_t m = (p.full_search ? 0xFFFFFFFFu : cw[j]) & bits32_between(0, top - wb) &
+    uint32_t m = grid & bits32_between(0, top - wb) &
                  ~bits32_between(wlo - wb, whi - wb);
     n += __popc(m);
     while (m) {
