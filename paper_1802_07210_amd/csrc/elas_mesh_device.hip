@@ -191,6 +191,7 @@ struct MeshMem {
   int32_t* scnt;         // NP + 1 bucket starts by smallest vertex rank
   int32_t* scur;         // NP + 1 fill cursors
   I* slist;              // NT triangles grouped by smallest vertex
+  int32_t* smin;         // NT: rank of each triangle's smallest vertex
   int NP, NT, ncand;
 };
 
@@ -233,7 +234,7 @@ __host__ __device__ __forceinline__ size_t carve(char* base, int n, int lh, Mesh
   const size_t flip_bytes = a16(NT * sizeof(C)) + a16(NT * sizeof(I)) + a16(NT * 2) +
                             2 * a16(NT * sizeof(I)) + 2 * a16(ncand * sizeof(I));
   const size_t adj_bytes = a16(3 * NT * sizeof(I)) + 2 * a16((NP + 1) * 4);
-  const size_t fin_bytes = 2 * a16((NP + 1) * 4) + a16(NT * sizeof(I));
+  const size_t fin_bytes = 2 * a16((NP + 1) * 4) + a16(NT * sizeof(I)) + a16(NT * 4);
   size_t d_bytes = flip_bytes;
   if (adj_bytes > d_bytes) d_bytes = adj_bytes;
   if (fin_bytes > d_bytes) d_bytes = fin_bytes;
@@ -259,6 +260,7 @@ __host__ __device__ __forceinline__ size_t carve(char* base, int n, int lh, Mesh
     t.scnt = reinterpret_cast<int32_t*>(d.take((NP + 1) * 4));
     t.scur = reinterpret_cast<int32_t*>(d.take((NP + 1) * 4));
     t.slist = reinterpret_cast<I*>(d.take(NT * sizeof(I)));
+    t.smin = reinterpret_cast<int32_t*>(d.take(NT * 4));
   }
   t.NP = (int)NP;
   t.NT = (int)NT;
@@ -623,6 +625,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   int32_t* const scnt = M.scnt;
   int32_t* const scur = M.scur;
   I* const slist = M.slist;
+  int32_t* const smin = M.smin;
   const int NP = M.NP, NT = M.NT, ncand = M.ncand;
 
   // ---- 1. points in rank order, corners ----------------------------------
@@ -915,25 +918,24 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   // ---- 5. canonical order, planes, raster records -------------------------
   for (int v = tid; v <= NP; v += kMT) scnt[v] = 0;
   __syncthreads();
+  // the rank of each triangle's smallest vertex is searched once
   for (int t = tid; t < NT; t += kMT) {
     uint32_t s0 = tk[3 * t], s1 = tk[3 * t + 1], s2 = tk[3 * t + 2];
     sort3(s0, s1, s2);
-    atomicAdd(&scnt[rank_of(pk, NP, s0)], 1);
+    const int a = rank_of(pk, NP, s0);
+    smin[t] = a;
+    atomicAdd(&scnt[a], 1);
   }
   __syncthreads();
   scan_array(scnt, NP + 1, sh.wsum);
   for (int v = tid; v <= NP; v += kMT) scur[v] = scnt[v];
   __syncthreads();
-  for (int t = tid; t < NT; t += kMT) {
-    uint32_t s0 = tk[3 * t], s1 = tk[3 * t + 1], s2 = tk[3 * t + 2];
-    sort3(s0, s1, s2);
-    slist[atomicAdd(&scur[rank_of(pk, NP, s0)], 1)] = (I)t;
-  }
+  for (int t = tid; t < NT; t += kMT) slist[atomicAdd(&scur[smin[t]], 1)] = (I)t;
   __syncthreads();
   for (int t = tid; t < NT; t += kMT) {
     uint32_t s0 = tk[3 * t], s1 = tk[3 * t + 1], s2 = tk[3 * t + 2];
     sort3(s0, s1, s2);
-    const int a = rank_of(pk, NP, s0);
+    const int a = smin[t];
     // position: bucket start + triangles of the bucket with a smaller
     // (middle, largest) vertex pair
     int pos = scnt[a];
