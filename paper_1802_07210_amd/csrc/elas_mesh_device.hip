@@ -416,7 +416,8 @@ template <typename I>
 __device__ __forceinline__ void strip_edge(int q, const uint32_t* pk, const int32_t* rowStart,
                                            const int32_t* rowNE, const int32_t* rowRank,
                                            const int32_t* stripOff, const Geometry& g, int m,
-                                           int n, I* tv, I* tn, int NT, int* err) {
+                                           int n, I* tv, I* tn, int NT, int* err,
+                                           int* border) {
   int ga, idx, below, above;  // band below / above the edge, -1: none
   if (q == 0) {
     ga = 0, idx = 0, below = 0, above = -1;
@@ -470,10 +471,15 @@ __device__ __forceinline__ void strip_edge(int q, const uint32_t* pk, const int3
       }
     }
   }
-  // a row edge joins its two band triangles
+  // a row edge joins its two band triangles; the corner rows' edges are the
+  // image's top and bottom sides
   if (kb >= 0 && ka >= 0) {
     tn[3 * kb + 2] = (I)(4 * ka);
     tn[3 * ka] = (I)(4 * kb + 2);
+  } else if (kb >= 0 || ka >= 0) {
+    if (kb >= 0) tn[3 * kb + 2] = (I)-1;
+    if (ka >= 0) tn[3 * ka] = (I)-1;
+    atomicAdd(border, 1);
   }
 }
 
@@ -510,7 +516,10 @@ __device__ __forceinline__ void test_edge(int t, uint32_t p, uint32_t a, uint32_
                                           int rr, const uint32_t* tk, const uint16_t* flipr,
                                           typename ClaimT<I>::T* claim, I* cl, int* count,
                                           int ncand, int* err) {
-  if (e < 0) return;
+  if (e < 0) {
+    if (e == kTwinUnknown) *err = 2;  // a half-edge the adjacency step left unmatched
+    return;
+  }
   const int o = e >> 2, j = e & 3;
   if (o < t && (int)flipr[o] == rr - 1) return;
   if (!edge_illegal(p, a, b, tk[3 * o + j])) return;
@@ -719,7 +728,8 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   // edge), then its share of the pockets (kPocketG lanes per chain point,
   // half of the workgroup per side); the two write disjoint triangles
   for (int q = tid; q < n + 2; q += kMT)
-    strip_edge(q, pk, rowStart, rowNE, rowRank, stripOff, g, m, n, tv, tn, NT, &sh.err);
+    strip_edge(q, pk, rowStart, rowNE, rowRank, stripOff, g, m, n, tv, tn, NT, &sh.err,
+               &sh.border);
   {
     const int side = tid / (kMT / 2), lt = tid % (kMT / 2);
     const int groups = kMT / 2 / kPocketG;
@@ -736,9 +746,10 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   }
 
   // ---- 3. adjacency -------------------------------------------------------
-  // every half-edge is bucketed by origin vertex; only those whose twin the
-  // bands did not set (the pockets' edges and each band's two side edges)
-  // are matched
+  // every half-edge is bucketed by origin vertex. The bands set every twin
+  // but their two side edges, whose twins are pocket half-edges; so the
+  // pockets' half-edges (one contiguous range, all unmatched) are matched,
+  // each also linking the band side it finds
   for (int v = tid; v <= NP; v += kMT) vcnt[v] = 0;
   __syncthreads();
   for (int e = tid; e < 3 * NT; e += kMT) {
@@ -755,8 +766,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
     hbuck[atomicAdd(&vcur[a], 1)] = (I)e;
   }
   __syncthreads();
-  for (int e = tid; e < 3 * NT; e += kMT) {
-    if ((int)tn[e] != kTwinUnknown) continue;
+  for (int e = 3 * strip_tris + tid; e < 3 * NT; e += kMT) {
     // half-edge a -> b opposite vertex k; its twin runs b -> a. The twin's
     // triangle holds a half-edge leaving b (the twin) and one leaving a (the
     // one after the twin, whose opposite vertex is b), so the smaller of the
@@ -786,7 +796,10 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       }
     }
     tn[e] = (I)nb;
-    if (nb < 0) atomicAdd(&sh.border, 1);
+    if (nb < 0)
+      atomicAdd(&sh.border, 1);
+    else if ((nb >> 2) < strip_tris)  // a band side: its only twin is this one
+      tn[3 * (nb >> 2) + (nb & 3)] = (I)(4 * t + k);
   }
   __syncthreads();
   if (sh.border != 4) {  // only the four image sides lack a twin
@@ -824,11 +837,11 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
     I* const cl_cur = cur ? cl1 : cl0;
     I* const cl_nxt = cur ? cl0 : cl1;
     const int nc = sh.ncand[cur];
-    if (nc == 0) break;
-    if (sh.err || r >= kMaxRounds) {
+    if (sh.err || (nc > 0 && r >= kMaxRounds)) {
       mesh_fail<I>(hdr, view, sh.err ? sh.err : 1);
       return;
     }
+    if (nc == 0) break;
     if (tid == 0) sh.ncand[nxt] = 0;  // appended to only after the next barrier
     // winners flip: (p, a, b) + (q, b, a) -> (p, a, q) + (p, q, b). Both
     // triangles' entries are loaded before the claims are compared, from
