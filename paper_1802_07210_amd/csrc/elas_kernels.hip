@@ -1125,6 +1125,15 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
   return best != 0xFFFFFFFFu ? p.dmin + (int)(best & 0xFFu) : -1;
 }
 
+// Row of staged element i when each of the block's rows holds nc elements:
+// i / nc for i < kDenseRows * nc, by comparisons instead of a division.
+__device__ __forceinline__ int dense_row_of(int i, int nc) {
+  int r = 0;
+#pragma unroll
+  for (int rr = 1; rr < kDenseRows; ++rr) r += i >= rr * nc ? 1 : 0;
+  return r;
+}
+
 // One workgroup: kDenseRows rows x kDenseSeg columns of one view, a thread
 // per column and row. Every global load (the other view's reachable
 // descriptors, staged in LDS; the own descriptor, prior and grid-region mask
@@ -1168,7 +1177,7 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
 #pragma unroll
   for (int k = 0; k < kDenseRows * 2; ++k) {
     const int i = min((int)threadIdx.x + 256 * k, nst - 1);
-    const int r = i / nc, c = c0 + (i - r * nc);
+    const int r = dense_row_of(i, nc), c = c0 + (i - r * nc);
     sv[k] = DD::load(other_desc, (size_t)(v0 + r) * g.w + c);
   }
   const int32_t lv = lut[min((int)threadIdx.x, p.D - 1)];
@@ -1190,7 +1199,7 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
 #pragma unroll
   for (int k = 0; k < kDenseRows * 2; ++k) {
     const int i = (int)threadIdx.x + 256 * k;
-    const int r = i / nc, c = c0 + (i - r * nc);
+    const int r = dense_row_of(i, nc), c = c0 + (i - r * nc);
     if (i < nst) st[r * kDenseStage + (c - base)] = sv[k];
   }
   if ((int)threadIdx.x < p.D) s_lut[threadIdx.x] = lv;
