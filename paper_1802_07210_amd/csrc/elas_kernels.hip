@@ -977,7 +977,10 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
       if (i >= npx) continue;
       int dp = -1;
       if (o[k] != kNoOwner) {
-        const int q = i / g.w, u = i - q * g.w, v = v0 + q;
+        int q = 0;  // band row: i / g.w for i < rows * g.w, by comparisons
+#pragma unroll
+        for (int rr = 1; rr < kBandRowsMax; ++rr) q += i >= rr * g.w ? 1 : 0;
+        const int u = i - q * g.w, v = v0 + q;
         const float mu = __fadd_rn(__fadd_rn(__fmul_rn(a[k], (float)u), __fmul_rn(b[k], (float)v)),
                                    c[k]);
         const float f = floorf(__fadd_rn(mu, 0.5f));
