@@ -322,7 +322,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the ELAS path runs on a single MI355X "
-              "(frames are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(frames are independent, so more GPUs would each take whole frames)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
