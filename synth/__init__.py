@@ -212,3 +212,33 @@ def batch_shapes(n: int, seed: int = 0):
     r = rng.uniform(n)
     names = list(SHAPES)
     return [names[int(np.floor(x * len(names)))] for x in r]
+
+
+def sparse_layout_pair(width: int, height: int, kind: str, d0: int, seed: int = 0):
+    """Flat pair (R(u, v) = L(u + d0, v)) with noise texture only where a
+    support lattice of step 10 should find points: 'vline' one point per row,
+    all on one column; 'two' two such columns; 'diag' one point per row on a
+    staircase; 'spot' a single point; 'hline' every point in one row."""
+    rng = SplitMix64(seed)
+    left = np.full((height, width), 90, np.uint8)
+
+    def tex(v0, v1, u0, u1):
+        left[v0:v1, u0:u1] = rng.bytes_((v1 - v0) * (u1 - u0)).reshape(v1 - v0, u1 - u0)
+
+    if kind == "vline":
+        tex(8, height - 8, 48, 53)
+    elif kind == "two":
+        tex(8, height - 8, 38, 43)
+        tex(18, height - 18, 78, 83)
+    elif kind == "diag":
+        for i, v in enumerate(range(10, height - 10, 10)):
+            tex(v - 2, v + 3, 28 + 10 * (i % 6), 33 + 10 * (i % 6))
+    elif kind == "spot":
+        tex(38, 43, 58, 63)
+    elif kind == "hline":
+        tex(38, 43, d0 + 10, width - 10)
+    else:
+        raise ValueError(kind)
+    right = np.full_like(left, 90)
+    right[:, :width - d0] = left[:, d0:]
+    return left, right

@@ -151,6 +151,37 @@ def test_batches_on_two_streams_concurrently(E):
     check(p2, [(a.cpu().numpy(), b.cpu().numpy()) for a, b in o2])
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_sparse_support_layouts(E, graph):
+    # degenerate support layouts (empty bands, a collinear chain, one point,
+    # one row) next to an ordinary pair in one batched call, through the
+    # batched device mesh; each pair's maps equal the oracle's
+    dev = torch.device("cuda:0")
+    sparse = dict(disp_max=31, redun_max_dist=0, incon_min_support=0, candidate_stepsize=10)
+    plain = dict(disp_max=63)
+    hs, hp = E.Elas(**sparse), E.Elas(**plain)
+    cases = [(synth.sparse_layout_pair(128, 96, k, 9, seed=3), sparse, hs)
+             for k in ("vline", "two", "diag", "spot", "hline")]
+    p = synth.make_pair(synth.SceneConfig(160, 96, 64, 4, 0.05, 4.0, 59.0, 2.0, 0.1, seed=21))
+    cases.append(((p.left, p.right), plain, hp))
+    hp.set_batch_flags(graph=graph, autotune=False)
+    items, outs = [], []
+    for (left, right), _, h in cases:
+        L = torch.from_numpy(left).to(dev)
+        R = torch.from_numpy(right).to(dev)
+        oL = torch.full(left.shape, -7, dtype=torch.int16, device=dev)
+        oR = torch.full(left.shape, -7, dtype=torch.int16, device=dev)
+        items.append((L, R, oL, oR, h))
+        outs.append((oL, oR))
+    for _ in range(2):
+        hp.process_batch(items)
+    torch.cuda.synchronize()
+    for ((left, right), kw, _), (oL, oR) in zip(cases, outs):
+        t = ref.process(ref.params(**kw), left, right)
+        assert np.array_equal(oL.cpu().numpy(), t.outL), kw
+        assert np.array_equal(oR.cpu().numpy(), t.outR), kw
+
+
 def test_batch_argument_errors(E):
     e = E.Elas(disp_max=63)
     with pytest.raises(E.ElasError):

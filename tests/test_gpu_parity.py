@@ -255,41 +255,12 @@ def test_dense_support_sets_exercise_the_device_mesh(E, seed):
     assert run_and_compare(E, pair.left, pair.right, **kw) == []
 
 
-def sparse_layout_pair(w, h, kind, d0, seed):
-    """Flat pair (shift d0) with texture only where a lattice of step 10 should
-    get support points: 'vline' one point per row, all on one column (every
-    band between rows is empty and the chain is collinear), 'diag' one point
-    per row on a staircase, 'two' two columns, 'spot' a single point, 'hline'
-    every point in one row."""
-    rng = np.random.default_rng(seed)
-    L = np.full((h, w), 90, np.uint8)
-
-    def tex(v0, v1, u0, u1):
-        L[v0:v1, u0:u1] = rng.integers(0, 256, (v1 - v0, u1 - u0))
-
-    if kind == "vline":
-        tex(8, h - 8, 48, 53)
-    elif kind == "two":
-        tex(8, h - 8, 38, 43)
-        tex(18, h - 18, 78, 83)
-    elif kind == "diag":
-        for i, v in enumerate(range(10, h - 10, 10)):
-            tex(v - 2, v + 3, 28 + 10 * (i % 6), 33 + 10 * (i % 6))
-    elif kind == "spot":
-        tex(38, 43, 58, 63)
-    else:  # hline
-        tex(38, 43, d0 + 10, w - 10)
-    R = np.full_like(L, 90)
-    R[:, :w - d0] = L[:, d0:]
-    return L, R
-
-
 @pytest.mark.parametrize("mesh_on_host", [0, 1])
 @pytest.mark.parametrize("kind", ["vline", "two", "diag", "spot", "hline"])
 def test_sparse_support_layouts(E, kind, mesh_on_host):
     # few support points in degenerate layouts: single-point rows (empty
     # bands), a collinear chain, one point, one row
-    L, R = sparse_layout_pair(128, 96, kind, 9, seed=3)
+    L, R = synth.sparse_layout_pair(128, 96, kind, 9, seed=3)
     kw = dict(disp_max=31, redun_max_dist=0, incon_min_support=0, candidate_stepsize=10,
               mesh_on_host=mesh_on_host)
     t = ref.process(oracle_params(kw), L, R)
