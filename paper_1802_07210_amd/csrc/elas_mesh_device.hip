@@ -504,36 +504,6 @@ __device__ void mesh_fail(MeshHeader* hdr, int view, int status) {
   }
 }
 
-// Tests edge i (end points a, b; apex p in the triangle) of triangle t for
-// round rr: the neighbour code e = 4 * o + j names the triangle o across the
-// edge and its apex index j. An edge whose other triangle was also flipped in
-// round rr - 1 (every triangle counts as flipped before round 1) is tested by
-// the one with the smaller index. An illegal edge claims both triangles with
-// the round-stamped inverted key (the smallest key wins) and is appended to
-// the round's candidates.
-template <typename I>
-__device__ __forceinline__ void test_edge(int t, uint32_t p, uint32_t a, uint32_t b, int i, int e,
-                                          int rr, const uint32_t* tk, const uint16_t* flipr,
-                                          typename ClaimT<I>::T* claim, I* cl, int* count,
-                                          int ncand, int* err) {
-  if (e < 0) {
-    if (e == kTwinUnknown) *err = 2;  // a half-edge the adjacency step left unmatched
-    return;
-  }
-  const int o = e >> 2, j = e & 3;
-  if (o < t && (int)flipr[o] == rr - 1) return;
-  if (!edge_illegal(p, a, b, tk[3 * o + j])) return;
-  const int key = t < o ? 4 * t + i : 4 * o + j;
-  const typename ClaimT<I>::T st = claim_stamp<I>(rr, key);
-  atomicMax(&claim[t], st);
-  atomicMax(&claim[o], st);
-  const int slot = atomicAdd(count, 1);
-  if (slot < ncand)
-    cl[slot] = (I)key;
-  else
-    *err = 2;
-}
-
 // An empty asm that reads its operands: the loads that produce them are
 // issued before it and waited for together there, instead of one by one in
 // the branches that use them.
@@ -821,14 +791,34 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   __syncthreads();
 
   // ---- 4. Lawson flips in synchronous rounds ------------------------------
-  // round 1 tests every edge; an edge between two tested triangles is tested
-  // by the one with the smaller index
+  // round 1 tests every edge, from the triangle with the smaller index; the
+  // three apexes across are loaded together
   for (int t = tid; t < NT; t += kMT) {
     const uint32_t kk[3] = {tk[3 * t], tk[3 * t + 1], tk[3 * t + 2]};
+    int e[3];
+    uint32_t q[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-      test_edge<I>(t, kk[i], kk[(i + 1) % 3], kk[(i + 2) % 3], i, (int)tn[3 * t + i], 1, tk,
-                   flipr, claim, cl1, &sh.ncand[1], ncand, &sh.err);
+    for (int i = 0; i < 3; ++i) e[i] = tn[3 * t + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) q[i] = tk[e[i] >= 0 ? 3 * (e[i] >> 2) + (e[i] & 3) : 3 * t];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (e[i] < 0) {
+        if (e[i] == kTwinUnknown) sh.err = 2;  // left unmatched by the adjacency step
+        continue;
+      }
+      const int o = e[i] >> 2;
+      if (o < t || !edge_illegal(kk[i], kk[(i + 1) % 3], kk[(i + 2) % 3], q[i])) continue;
+      const int key = 4 * t + i;
+      const C st = claim_stamp<I>(1, key);
+      atomicMax(&claim[t], st);
+      atomicMax(&claim[o], st);
+      const int slot = atomicAdd(&sh.ncand[1], 1);
+      if (slot < ncand)
+        cl1[slot] = (I)key;
+      else
+        sh.err = 2;
+    }
   }
   __syncthreads();
   for (int r = 1;; ++r) {
