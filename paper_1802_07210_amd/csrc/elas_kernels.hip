@@ -665,6 +665,16 @@ __device__ __forceinline__ void redun_body(const Frame& F, int lb) {
 //    list point are OR-ed into its region's mask, per view;
 //  * the row's support-search evaluation count.
 // ---------------------------------------------------------------------------
+// Sets the grid bits d - 1 .. d + 1 (within the disparity range) of a cell:
+// one atomic OR per 32-bit word they touch (one, or two across a word edge).
+__device__ __forceinline__ void grid_mark(uint32_t* cell, int d, const KParams& p) {
+  const int lo = max(d - 1, p.dmin) - p.dmin, hi = min(d + 1, p.dmax) - p.dmin;
+  const int w0 = lo >> 5, w1 = hi >> 5;
+  const uint32_t top0 = w1 == w0 ? hi & 31 : 31;
+  atomicOr(&cell[w0], (top0 == 31 ? 0xFFFFFFFFu : ((2u << top0) - 1u)) & ~((1u << (lo & 31)) - 1u));
+  if (w1 != w0) atomicOr(&cell[w1], (2u << (hi & 31)) - 1u);
+}
+
 __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
   const Geometry g = F.g;
   const KParams p = F.p;
@@ -705,9 +715,7 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
       const int pos = nL + __popcll(m & below);
       hrowL[(size_t)l * g.lw + pos] = u | (d << 16);
       atomicMax(&slot[u - d], d);
-      uint32_t* cell = gridL + (grow + u / p.grid_size) * g.gwords;
-      for (int dd = max(d - 1, p.dmin); dd <= min(d + 1, p.dmax); ++dd)
-        atomicOr(&cell[(dd - p.dmin) >> 5], 1u << ((dd - p.dmin) & 31));
+      grid_mark(gridL + (grow + u / p.grid_size) * g.gwords, d, p);
     }
     nL += __popcll(m);
   }
@@ -720,9 +728,7 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
     if (d >= 0) {
       const int pos = nR + __popcll(m & ((1ull << lane) - 1ull));
       hrowR[(size_t)l * g.lw + pos] = x | (d << 16);
-      uint32_t* cell = gridR + (grow + x / p.grid_size) * g.gwords;
-      for (int dd = max(d - 1, p.dmin); dd <= min(d + 1, p.dmax); ++dd)
-        atomicOr(&cell[(dd - p.dmin) >> 5], 1u << ((dd - p.dmin) & 31));
+      grid_mark(gridR + (grow + x / p.grid_size) * g.gwords, d, p);
     }
     nR += __popcll(m);
   }
