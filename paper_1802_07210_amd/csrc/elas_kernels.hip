@@ -49,6 +49,21 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
   return x;
 }
 
+// Minimum over a full wavefront (all 64 lanes active) without LDS: DPP
+// exchanges within each 16-lane row (quad permutes 1032 and 2301, the
+// half-row and the row mirror), then the four rows' results read as scalars.
+__device__ __forceinline__ uint32_t wave_min_full(uint32_t x) {
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x141, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x140, 0xF, 0xF, false));
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
+  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
+  const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+  return min(min(r0, r1), min(r2, r3));
+}
+
 __device__ __forceinline__ int wave_sum(int x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -385,7 +400,7 @@ __device__ __forceinline__ bool support_search(const typename S::T& self, const 
       best = min(best, (c << 8) | (uint32_t)(d - p.dmin));
     }
   }
-  best = wave_min(best);
+  best = wave_min_full(best);  // the search's control flow is wavefront-uniform
   const int d1 = p.dmin + (int)(best & 0xFFu);
   const uint32_t m1 = best >> 8;
   uint32_t m2 = 0xFFFFFFFFu;
@@ -394,7 +409,7 @@ __device__ __forceinline__ bool support_search(const typename S::T& self, const 
     const int d = p.dmin + lane + 64 * j;
     if (d != d1) m2 = min(m2, cost[j]);
   }
-  m2 = wave_min(m2);
+  m2 = wave_min_full(m2);
   *d_best = d1;
   return support_accept(p, m1, m2);
 }
