@@ -21,6 +21,7 @@
 #include <hip/hip_ext.h>
 
 #include "elas_internal.h"
+#include "elas_wave.h"
 
 namespace elas {
 namespace {
@@ -41,33 +42,6 @@ __device__ __forceinline__ uint32_t sad16(const uint4 a, const uint4 b) {
 // Texture: distance of a descriptor from the flat descriptor (all bytes 128).
 __device__ __forceinline__ uint32_t texture16(const uint4 a) {
   return sad16(a, make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u));
-}
-
-__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, off, 64));
-  return x;
-}
-
-// Minimum over a full wavefront (all 64 lanes active) without LDS: DPP
-// exchanges within each 16-lane row (quad permutes 1032 and 2301, the
-// half-row and the row mirror), then the four rows' results read as scalars.
-__device__ __forceinline__ uint32_t wave_min_full(uint32_t x) {
-  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false));
-  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false));
-  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x141, 0xF, 0xF, false));
-  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x140, 0xF, 0xF, false));
-  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
-  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
-  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
-  const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
-  return min(min(r0, r1), min(r2, r3));
-}
-
-__device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
@@ -400,7 +374,7 @@ __device__ __forceinline__ bool support_search(const typename S::T& self, const 
       best = min(best, (c << 8) | (uint32_t)(d - p.dmin));
     }
   }
-  best = wave_min_full(best);  // the search's control flow is wavefront-uniform
+  best = wave_min_u32(best);  // the search's control flow is wavefront-uniform
   const int d1 = p.dmin + (int)(best & 0xFFu);
   const uint32_t m1 = best >> 8;
   uint32_t m2 = 0xFFFFFFFFu;
@@ -409,7 +383,7 @@ __device__ __forceinline__ bool support_search(const typename S::T& self, const 
     const int d = p.dmin + lane + 64 * j;
     if (d != d1) m2 = min(m2, cost[j]);
   }
-  m2 = wave_min_full(m2);
+  m2 = wave_min_u32(m2);
   *d_best = d1;
   return support_accept(p, m1, m2);
 }
@@ -548,8 +522,9 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
           }
         }
       }
-#pragma unroll
-      for (int off = 1; off < kFiltParts; off <<= 1) count += __shfl_xor(count, off, 64);
+      static_assert(kFiltParts == 4, "the parts of a count are the lanes of a quad");
+      count += quad_xor1(count);
+      count += quad_xor2(count);
       if (part == 0 && task / kFiltParts < npos)
         sinc[i] = (int16_t)((d >= 0 && count - 1 >= p.incon_min_support) ? d : -1);  // minus itself
     }
@@ -713,7 +688,7 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
     const int n = l * g.lw;
     int c = 0;
     for (int i = lane; i < n; i += 64) c += fin[i] >= 0 ? 1 : 0;
-    base = wave_sum(c);
+    base = wave_sum_i32(c);
   }
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int k0 = 0; k0 < g.lw; k0 += 64) {
@@ -747,7 +722,7 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
     }
     nR += __popcll(m);
   }
-  ev = wave_sum(ev);
+  ev = wave_sum_i32(ev);
   if (lane == 0) {
     F.cnt[l] = nL;
     F.cnt[g.lh + l] = nR;
@@ -891,12 +866,7 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
       // and row by row, form one pixel range; each thread takes a contiguous
       // share of it, finds its first span by a search over the waves' and
       // the lanes' offsets and walks on from there
-      int incl = tot;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
-      }
+      const int incl = wave_scan_incl(tot);
       int32_t* W = wspan + wid * kWaveSpan;  // [offsets 64][lo 64x4][len 64x4][rank 64]
       W[lane] = incl - tot;
 #pragma unroll
@@ -917,7 +887,7 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        P = __shfl(incl, 63, 64);
+        P = __builtin_amdgcn_readlane(incl, 63);
         i = lane * ((P + 63) >> 6);
       }
       const int iend = min(P, kShared ? i + (P + kRasterThreads - 1) / kRasterThreads
@@ -1265,7 +1235,7 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
                                 reinterpret_cast<uint64_t*>(s_stage), &cnt);
   else
     dense_rows<KB, GradDense>(F, g, p, right, v0, u0, s_lut, s_stage, &cnt);
-  cnt = wave_sum(cnt);
+  cnt = wave_sum_i32(cnt);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) F.dense_counts[lb] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];

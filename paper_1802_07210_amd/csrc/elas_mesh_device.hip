@@ -50,6 +50,7 @@
 #include <hip/hip_ext.h>
 
 #include "elas_internal.h"
+#include "elas_wave.h"
 
 namespace elas {
 namespace {
@@ -104,12 +105,7 @@ __device__ __forceinline__ void sort3(uint32_t& a, uint32_t& b, uint32_t& c) {
 // Exclusive scan over the workgroup; *total receives the sum.
 __device__ int scan_excl(int x, int* total, int* wsum) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int incl = x;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += y;
-  }
+  const int incl = wave_scan_incl(x);
   if (lane == 63) wsum[wid] = incl;
   __syncthreads();
   int before = 0, all = 0;
@@ -323,10 +319,11 @@ __device__ __forceinline__ void pocket_point(const uint32_t* pk, const uint32_t*
       qx = x;
     }
   }
+  static_assert(G == 4, "a pocket point's lanes are the lanes of a quad");
 #pragma unroll
-  for (int off = G / 2; off >= 1; off >>= 1) {
-    const uint32_t q2 = __shfl_xor(q, off, 64);
-    const int x2 = __shfl_xor(qx, off, 64);
+  for (int off = 2; off >= 1; off >>= 1) {
+    const uint32_t q2 = (uint32_t)(off == 2 ? quad_xor2((int)q) : quad_xor1((int)q));
+    const int x2 = off == 2 ? quad_xor2(qx) : quad_xor1(qx);
     const int o = orient_k(q, c, q2);
     const bool take =
         x2 >= 0 && (qx < 0 || (s == 0 ? o > 0 : o < 0) || (o == 0 && x2 > qx));
@@ -644,11 +641,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      unsigned long long b = best[c];
-      for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(b, off, 64);
-        b = o < b ? o : b;
-      }
+      const unsigned long long b = wave_min_u64(best[c]);
       if ((tid & 63) == 0) atomicMin(&sh.corner[c], b);
     }
   }
@@ -1009,12 +1002,9 @@ __device__ __forceinline__ void mesh_body(const Frame& F, int view) {
     ev += cnt[2 * g.lh + l];
   }
   const int lane = tid & 63, wid = tid >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    x += __shfl_xor(x, off, 64);
-    xl += __shfl_xor(xl, off, 64);
-    ev += __shfl_xor(ev, off, 64);
-  }
+  x = wave_sum_i32(x);
+  xl = wave_sum_i32(xl);
+  ev = wave_sum_i32(ev);
   if (lane == 0) {
     part[0][wid] = x;
     part[1][wid] = xl;
