@@ -6,7 +6,9 @@ support lists, device mesh, prior raster, dense matching of both views, final
 left/right check) on one resident 640x480 pair with disparities 0..127
 (seeded synthetic piecewise-planar scene). Consecutive steps are issued
 round-robin on --streams HIP streams, so up to that many frames are in flight
-(each stream has its own buffers in the library). Prints one JSON line.
+(each stream has its own buffers in the library); the process asks HIP for
+--hw-queues hardware queues so that the streams do not share one. Prints one
+JSON line.
 
 value           frames/s over the timed steps (inputs already in HBM)
 fps_one_stream  the same steps issued on a single stream (one frame at a time)
@@ -303,8 +305,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
-    ap.add_argument("--streams", type=int, default=3,
+    ap.add_argument("--streams", type=int, default=4,
                     help="frames in flight: steps are issued round-robin on this many streams")
+    ap.add_argument("--hw-queues", type=int, default=8,
+                    help="hardware queues of this process (GPU_MAX_HW_QUEUES, read when HIP "
+                         "starts); 0 keeps the environment's value")
     ap.add_argument("--mode", choices=["frame", "serve", "calib"], default="frame",
                     help="frame: the 640x480 frame rate (default); serve: the camera-stream "
                          "serving sweep (batched and plain servers); calib: a plain copy "
@@ -326,6 +331,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.hw_queues > 0:
+        # HIP maps streams onto this many hardware queues; four frame streams
+        # need more than HIP's default of four to run side by side
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     import torch
     import synth
     from paper_1802_07210_amd import Elas
@@ -427,6 +436,7 @@ def main():
                                f"piecewise-planar scene ({cfg.planes} planes)",
                    "width": W, "height": H, "disp_range": D, "pairs_per_step": 1,
                    "seed": args.seed, "frames_in_flight": K,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")) or None,
                    "mesh": "host" if args.mesh_on_host else "device"},
         "evals_per_frame": evals,
         "evals_per_s_algorithmic": round(evals * fps, 1),
