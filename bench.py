@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the ELAS hot path on one MI355X.
 
-One step = one elas_process call (descriptor, support matching and filtering,
-support lists, device mesh, prior raster, dense matching of both views, final
-left/right check) on one resident 640x480 pair with disparities 0..127
-(seeded synthetic piecewise-planar scene). Consecutive steps are issued
-round-robin on --streams HIP streams, so up to that many frames are in flight
-(each stream has its own buffers in the library); the process asks HIP for
---hw-queues hardware queues so that the streams do not share one. Prints one
-JSON line.
+One step = one elas_process_batch call over --batch resident 640x480 pairs
+with disparities 0..127 (seeded synthetic piecewise-planar scenes, pair i from
+seed + i): every stage of the path (descriptor, support matching and
+filtering, support lists, device mesh, prior raster, dense matching of both
+views, final left/right check) runs once for all pairs of the step, one
+launch per stage, from a captured graph. Consecutive steps are issued
+round-robin on --streams HIP streams, so up to streams x batch frames are in
+flight (each stream has its own buffers in the library); the process asks HIP
+for --hw-queues hardware queues. With --batch 1 a step is one elas_process
+call on one pair. Prints one JSON line.
 
 value           frames/s over the timed steps (inputs already in HBM)
-fps_one_stream  the same steps issued on a single stream (one frame at a time)
-roofline        the kernel with the largest share of chip time (duration x the
-                fraction of the 256 CUs it occupies; the mesh kernel holds one
-                CU per view), its algorithmic work per launch over its mean
-                duration (HIP events on the stream the library launches on),
-                against the MI355X peak
+fps_plain_calls one elas_process call per pair (pair seed), round-robin on the
+                same streams
+fps_one_stream  the same plain calls on a single stream (one frame at a time)
+roofline        the kernel with the largest share of chip time in a step
+                (duration x the fraction of the 256 CUs it occupies; the mesh
+                kernel holds one CU per view and pair), its algorithmic work
+                per launch over its mean duration (HIP events on the stream the
+                library launches on), against the MI355X peak
 batch           96 pairs of mixed resolutions and disparity ranges (seeded
                 synthetic, pair i from seed i), one batched call each repetition,
                 against 96 sequential plain calls
@@ -139,15 +143,17 @@ def variant_fps(torch, Elas, L, R, D, steps: int, streams):
     return res
 
 
-def algorithmic_work(stage: str, w: int, h: int, st: dict):
-    """(HBM bytes, byte-|diff| ops) one launch of a stage's kernel must move
-    and compute, counted from the algorithm (not from the counters)."""
-    npx = w * h
+def algorithmic_work(stage: str, w: int, h: int, st: dict, pairs: int = 1):
+    """(HBM bytes, byte-|diff| ops) one launch of a stage's kernel over `pairs`
+    pairs of w x h must move and compute, counted from the algorithm (not
+    from the counters); st: the pairs' statistics summed, lattice sizes per
+    pair."""
+    npx = w * h * pairs
     if stage == "descriptor":   # read 1 B image, write a 16 B descriptor; 2 views
         return 2 * npx * (1 + 16), 0
     if stage == "support":      # descriptor rows v-2 and v+2 of each lattice row, 2 views;
         # 64 byte-|diff| per 512-bit evaluation
-        return 2 * 2 * 16 * w * max(1, st.get("lattice_rows", 0)), 64 * st["support_evals"]
+        return 2 * 2 * 16 * w * max(1, st.get("lattice_rows", 0)) * pairs, 64 * st["support_evals"]
     if stage == "dense":        # own descriptor 16 B + prior 2 B read, raw 2 B written;
         return 2 * npx * (16 + 2 + 2), 16 * st["dense_evals"]       # 2 views
     if stage == "lrcheck":      # read 2 B + partner 2 B, write 2 B per pixel, 2 views
@@ -155,9 +161,9 @@ def algorithmic_work(stage: str, w: int, h: int, st: dict):
     if stage == "raster":       # a 4 B owner and a 2 B prior per pixel, 2 views
         return 2 * npx * 6, 0
     if stage == "filter":       # lattice read + three lattice writes
-        return 8 * max(1, st.get("lattice", 0)), 0
+        return 8 * max(1, st.get("lattice", 0)) * pairs, 0
     if stage == "rows":         # final lattice + evaluation counts read, lists written
-        return 6 * max(1, st.get("lattice", 0)), 0
+        return 6 * max(1, st.get("lattice", 0)) * pairs, 0
     if stage == "mesh":         # support points in, raster records out (24 B per triangle)
         n = st["n_support_left"] + st["n_support_right"]
         return 12 * n + 24 * (st["n_tri_left"] + st["n_tri_right"]), 0
@@ -175,10 +181,12 @@ def workgroups(w: int, h: int, D: int, step: int = 5) -> dict:
             "dense": 2 * cd(h, 2) * cd(w, 256), "lrcheck": 2 * cd(w * h, 1024)}
 
 
-def roofline_of(stage: str, w: int, h: int, st: dict, ms: float, kernel: str) -> dict:
+def roofline_of(stage: str, w: int, h: int, st: dict, ms: float, kernel: str,
+                pairs: int = 1) -> dict:
     """The binding roofline of one kernel: the resource whose floor (work over
-    peak) is the larger; achieved = that work over the kernel's mean duration."""
-    nbytes, ops = algorithmic_work(stage, w, h, st)
+    peak) is the larger; achieved = that work over the kernel's mean duration.
+    st holds the statistics summed over the `pairs` pairs of one launch."""
+    nbytes, ops = algorithmic_work(stage, w, h, st, pairs)
     dur_s = ms / 1e3
     t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
     t_alu = ops / (PEAK_SAD_TOPS * 1e12)
@@ -305,11 +313,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
-    ap.add_argument("--streams", type=int, default=4,
-                    help="frames in flight: steps are issued round-robin on this many streams")
-    ap.add_argument("--hw-queues", type=int, default=8,
+    ap.add_argument("--streams", type=int, default=3,
+                    help="steps are issued round-robin on this many streams")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="pairs per step (one batched call); 1: one plain call per step")
+    ap.add_argument("--hw-queues", type=int, default=4,
                     help="hardware queues of this process (GPU_MAX_HW_QUEUES, read when HIP "
-                         "starts); 0 keeps the environment's value")
+                         "starts; 4 is HIP's default); 0 keeps the environment's value")
     ap.add_argument("--mode", choices=["frame", "serve", "calib"], default="frame",
                     help="frame: the 640x480 frame rate (default); serve: the camera-stream "
                          "serving sweep (batched and plain servers); calib: a plain copy "
@@ -332,8 +342,7 @@ def main():
         sys.exit(2)
 
     if args.hw_queues > 0:
-        # HIP maps streams onto this many hardware queues; four frame streams
-        # need more than HIP's default of four to run side by side
+        # HIP maps the process's streams onto this many hardware queues
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     import torch
     import synth
@@ -370,46 +379,70 @@ def main():
     pair = synth.make_pair(cfg)
     W, H, D = cfg.width, cfg.height, cfg.disp_range
     dev = torch.device("cuda:0")
-    L = torch.from_numpy(pair.left).to(dev)
-    R = torch.from_numpy(pair.right).to(dev)
+    B = max(1, args.batch)
+    imgs = [(torch.from_numpy(pair.left).to(dev), torch.from_numpy(pair.right).to(dev))]
+    for i in range(1, B):
+        p = synth.make_pair(synth.SHAPES[args.workload].with_seed(args.seed + i))
+        imgs.append((torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev)))
+    L, R = imgs[0]
     K = max(1, args.streams)
     streams = [torch.cuda.Stream(device=dev) for _ in range(K)]  # default priority
-    outs = [(torch.empty((H, W), dtype=torch.int16, device=dev),
-             torch.empty((H, W), dtype=torch.int16, device=dev)) for _ in range(K)]
+    outs = [[(torch.empty((H, W), dtype=torch.int16, device=dev),
+              torch.empty((H, W), dtype=torch.int16, device=dev)) for _ in range(B)]
+            for _ in range(K)]
+    items = [[(imgs[i][0], imgs[i][1], outs[k][i][0], outs[k][i][1]) for i in range(B)]
+             for k in range(K)]
     e = Elas(disp_max=D - 1, mesh_on_host=int(args.mesh_on_host))
+    e.set_batch_flags(graph=True, autotune=False)  # default tile variants
     stream = streams[0]
 
     def run(nsteps, nstreams):
         for i in range(nsteps):
             k = i % nstreams
-            e.process(L, R, outs[k][0], outs[k][1], stream=streams[k])
+            if B > 1:
+                e.process_batch(items[k], stream=streams[k])
+            else:
+                e.process(L, R, outs[k][0][0], outs[k][0][1], stream=streams[k])
 
-    torch.cuda.synchronize()
-    run(max(args.warmup, K), K)          # allocates every stream's buffers
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(args.steps, K)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
-    fps = args.steps / dt
-    run(args.warmup, 1)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    run(args.steps, 1)
-    torch.cuda.synchronize()
-    fps_one = args.steps / (time.perf_counter() - t2)
-    st = e.stats()
-    st["lattice"] = ((W - 5) // 5) * ((H - 5) // 5)
-    evals = st["support_evals"] + st["dense_evals"]
+    def run_plain(nsteps, nstreams):
+        for i in range(nsteps):
+            k = i % nstreams
+            e.process(L, R, outs[k][0][0], outs[k][0][1], stream=streams[k])
+
+    def rate(fn, nsteps, nstreams, warm):
+        fn(max(warm, nstreams), nstreams)   # allocates every stream's buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(nsteps, nstreams)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    dt = rate(run, args.steps, K, args.warmup)
+    fps = args.steps * B / dt
+    plain_steps = args.steps * B
+    fps_plain = plain_steps / rate(run_plain, plain_steps, K, args.warmup)
+    fps_one = plain_steps / rate(run_plain, plain_steps, 1, args.warmup)
+    # statistics of the pairs of a step (plain calls), summed over the pairs
+    st = {}
+    for (Li, Ri) in imgs:
+        e.process(Li, Ri, outs[0][0][0], outs[0][0][1], stream=stream)
+        for k2, v2 in e.stats().items():
+            st[k2] = st.get(k2, 0) + v2
+    st["lattice"] = ((W - 5) // 5) * ((H - 5) // 5)   # per pair
+    st["lattice_rows"] = (H - 5) // 5
+    evals = (st["support_evals"] + st["dense_evals"]) / B
     nominal = 2 * W * H * D
 
-    # per-stage device times: HIP events recorded by the library on `stream`
+    # per-stage device times of one step: HIP events (hipExtLaunchKernel)
+    # recorded by the library on `stream` around each launch
     e.set_timing(True)
     acc = {s: [] for s in STAGES}
     host = {"host_wait_ms": [], "host_mesh_ms": [], "device_span_ms": []}
     for _ in range(args.profile_steps):
-        e.process(L, R, outs[0][0], outs[0][1], stream=stream)
+        if B > 1:
+            e.process_batch(items[0], stream=stream)
+        else:
+            e.process(L, R, outs[0][0][0], outs[0][0][1], stream=stream)
         tm = e.timing()
         for s in STAGES:
             acc[s].append(tm[s + "_ms"])
@@ -418,30 +451,34 @@ def main():
     e.set_timing(False)
     stage_ms = {s: float(np.mean(v)) if v else float("nan") for s, v in acc.items()}
     kernel_ms = {s: stage_ms[s] for s in KERNEL_NAMES}
+    names = dict(KERNEL_NAMES)
+    if B > 1:  # the batched kernels (the raster's 256-thread workgroup)
+        names = {s: ("k_raster256" if s == "raster" else n) + "_batch" for s, n in names.items()}
     # share of chip time: duration x the fraction of the 256 CUs the kernel's
     # workgroups can occupy (launch geometry of each stage at this size)
     wgs = workgroups(W, H, D)
-    chip_ms = {s: v * min(1.0, wgs[s] / 256.0) for s, v in kernel_ms.items()}
+    chip_ms = {s: v * min(1.0, B * wgs[s] / 256.0) for s, v in kernel_ms.items()}
     dom = max(chip_ms, key=lambda k: chip_ms[k] if chip_ms[k] == chip_ms[k] else -1.0)
-    st["lattice_rows"] = (H - 5) // 5
-    roof = roofline_of(dom, W, H, st, kernel_ms[dom], KERNEL_NAMES[dom])
+    roof = roofline_of(dom, W, H, st, kernel_ms[dom], names[dom], pairs=B)
 
     out = {
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
-        "fps_one_stream": round(fps_one, 2),
+        "fps_plain_calls": round(fps_plain, 2), "fps_one_stream": round(fps_one, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"{W}x{H} D={D}, one stereo pair per step, seeded synthetic "
-                               f"piecewise-planar scene ({cfg.planes} planes)",
-                   "width": W, "height": H, "disp_range": D, "pairs_per_step": 1,
-                   "seed": args.seed, "frames_in_flight": K,
+        "config": {"workload": f"{W}x{H} D={D}, {B} stereo pair(s) per step (one batched call), "
+                               f"seeded synthetic piecewise-planar scenes ({cfg.planes} planes), "
+                               f"pair i from seed + i",
+                   "width": W, "height": H, "disp_range": D, "pairs_per_step": B,
+                   "seed": args.seed, "streams": K, "frames_in_flight": K * B,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")) or None,
                    "mesh": "host" if args.mesh_on_host else "device"},
         "evals_per_frame": evals,
         "evals_per_s_algorithmic": round(evals * fps, 1),
         "evals_per_s_nominal": round(nominal * fps, 1),
-        "support_points": [st["n_support_left"], st["n_support_right"]],
+        "support_points_per_pair": [round(st["n_support_left"] / B, 1),
+                                    round(st["n_support_right"] / B, 1)],
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "host_ms": {k: round(float(np.mean(v)), 5) if v else None for k, v in host.items()},
         "roofline": roof,

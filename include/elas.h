@@ -278,7 +278,11 @@ ELAS_API int elas_get_stats(elas_handle* h, elas_stats* out);
 ELAS_API int elas_set_timing(elas_handle* h, int32_t enable);
 
 /* Stage times of the last call made with timing on (synchronises with its
- * stream). ELAS_ERR_ARG if no such call has completed. */
+ * stream). ELAS_ERR_ARG if no such call has completed. After an
+ * elas_process_batch call each figure is the summed duration of that stage's
+ * launches for the whole batch (a timed batch is launched directly, not from
+ * a graph), device_span_ms runs from the first launch's start to the last
+ * one's end, and the host fields are 0. */
 ELAS_API int elas_get_timing(elas_handle* h, elas_timing* out);
 
 /* Describes the last failure on h (or of elas_create when h is NULL). The

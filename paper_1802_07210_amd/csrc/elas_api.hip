@@ -170,6 +170,10 @@ struct elas_handle {
   bool have_timing = false;
   hipEvent_t kev[kTimed][2] = {};
   bool kev_used[kTimed] = {};
+  // the last timed batch: start/stop events of each launch and its stage
+  bool have_batch_timing = false;
+  std::vector<hipEvent_t> bev;
+  std::vector<int32_t> bev_stage;
   // batches: per-stream frame tables and graphs, per-(size, stream) buffer
   // pools, tile variants chosen by the autotuner per (w, h, D)
   int32_t batch_flags = ELAS_BATCH_GRAPH | ELAS_BATCH_AUTOTUNE;
@@ -755,6 +759,7 @@ int elas_destroy(elas_handle* h) {
   for (auto& pr : h->kev)
     for (hipEvent_t& e : pr)
       if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->bev) (void)hipEventDestroy(e);
   delete h->worker;
   mesh_scratch_destroy(h->meshL);
   mesh_scratch_destroy(h->meshR);
@@ -787,6 +792,7 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   if (rc != ELAS_OK) return rc;
   h->have_result = false;
   h->have_timing = false;
+  h->have_batch_timing = false;
   h->last = b;
   h->last_stream = stream;
   h->last_on_host = on_host;
@@ -897,11 +903,15 @@ void plan_batch(const std::vector<Frame>& frames, const std::vector<std::pair<in
   }
 }
 
-hipError_t enqueue_batch(const std::vector<LaunchRec>& recs, uint8_t* dev, hipStream_t s) {
-  for (const LaunchRec& r : recs) {
+// ev: null, or a start and a stop event per launch (hipExtLaunchKernel).
+hipError_t enqueue_batch(const std::vector<LaunchRec>& recs, uint8_t* dev, hipStream_t s,
+                         const hipEvent_t* ev = nullptr) {
+  for (size_t i = 0; i < recs.size(); ++i) {
+    const LaunchRec& r = recs[i];
     const hipError_t e = launch_stage_batch(
         r.stage, reinterpret_cast<const Frame*>(dev + r.table_off),
-        reinterpret_cast<const int32_t*>(dev + r.starts_off), r.nf, r.total, r.lds, r.variant, s);
+        reinterpret_cast<const int32_t*>(dev + r.starts_off), r.nf, r.total, r.lds, r.variant, s,
+        ev ? ev[2 * i] : nullptr, ev ? ev[2 * i + 1] : nullptr);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1047,7 +1057,23 @@ int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStr
   HIP_TRY(hipEventRecord(c->done[k], stream));
   c->pending[k] = true;
   uint8_t* dev = static_cast<uint8_t*>(c->dev);
-  if (h->batch_flags & ELAS_BATCH_GRAPH) {
+  h->have_batch_timing = false;
+  if (h->timing) {
+    // timed: launched directly (not from a graph), each launch with its own
+    // events; stages without workgroups launch nothing and are left out
+    std::vector<LaunchRec> run;
+    for (const LaunchRec& r : recs)
+      if (r.total > 0 || r.stage == kStageMesh) run.push_back(r);
+    while (h->bev.size() < 2 * run.size()) {
+      hipEvent_t e = nullptr;
+      HIP_TRY(hipEventCreate(&e));
+      h->bev.push_back(e);
+    }
+    h->bev_stage.clear();
+    for (const LaunchRec& r : run) h->bev_stage.push_back(r.stage);
+    HIP_TRY(enqueue_batch(run, dev, stream, h->bev.data()));
+    h->have_batch_timing = !run.empty();
+  } else if (h->batch_flags & ELAS_BATCH_GRAPH) {
     std::vector<int64_t> sig;
     sig.push_back((int64_t)(uintptr_t)dev);
     for (const LaunchRec& r : recs) {
@@ -1124,6 +1150,29 @@ int elas_set_timing(elas_handle* h, int32_t enable) {
 
 int elas_get_timing(elas_handle* h, elas_timing* out) {
   if (!h || !out) return fail(h, ELAS_ERR_ARG, "null argument");
+  if (h->have_batch_timing) {  // the last timed call was a batch: launch times per stage
+    const size_t nl = h->bev_stage.size();
+    HIP_TRY(hipEventSynchronize(h->bev[2 * nl - 1]));
+    float st[kStageCount] = {};
+    for (size_t i = 0; i < nl; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->bev[2 * i], h->bev[2 * i + 1]));
+      st[h->bev_stage[i]] += ms;
+    }
+    float span = 0.f;
+    HIP_TRY(hipEventElapsedTime(&span, h->bev[0], h->bev[2 * nl - 1]));
+    *out = elas_timing{};
+    out->descriptor_ms = st[kStageDescriptor];
+    out->support_ms = st[kStageSupport];
+    out->filter_ms = st[kStageFilter] + st[kStageRedun];
+    out->rows_ms = st[kStageRows];
+    out->mesh_ms = st[kStageMesh];
+    out->raster_ms = st[kStageRaster];
+    out->dense_ms = st[kStageDense];
+    out->lrcheck_ms = st[kStageCheck] + st[kStageMedian];
+    out->device_span_ms = span;
+    return ELAS_OK;
+  }
   if (!h->have_result || !h->have_timing)
     return fail(h, ELAS_ERR_ARG, "no completed call with timing enabled");
   int last = 0;

@@ -213,16 +213,18 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // One stage of nf frames in one launch: frames and starts (nf + 1 prefix of
 // the per-frame block counts) in device memory; lds: the largest per-frame
-// dynamic LDS.
+// dynamic LDS. Start/stop events as in launch_stage.
 hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
                               int32_t nf, int32_t total_blocks, size_t lds, int variant,
-                              hipStream_t s);
+                              hipStream_t s, hipEvent_t start = nullptr,
+                              hipEvent_t stop = nullptr);
 
 // The mesh stage (elas_mesh_device.hip): two workgroups per frame, for
 // frames with both sides at most kDeviceMeshMaxSide.
 hipError_t launch_mesh_frame(const Frame& f, hipStream_t s, hipEvent_t start = nullptr,
                              hipEvent_t stop = nullptr);
-hipError_t launch_mesh_batch(const Frame* frames, int32_t nf, hipStream_t s);
+hipError_t launch_mesh_batch(const Frame* frames, int32_t nf, hipStream_t s,
+                             hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Device mesh scratch per view (views that do not fit in LDS).
 size_t mesh_global_scratch_per_view(const Geometry& g);
 // Blocks of the dense launch (one candidate-count entry per block).

@@ -1500,48 +1500,42 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
 
 hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
                               int32_t nf, int32_t total_blocks, size_t lds, int variant,
-                              hipStream_t s) {
-  if (stage == kStageMesh) return launch_mesh_batch(frames, nf, s);
+                              hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  if (stage == kStageMesh) return launch_mesh_batch(frames, nf, s, start, stop);
   if (total_blocks <= 0 || nf <= 0) return hipSuccess;
   const dim3 grid(total_blocks), block(stage_threads(stage));
+  const uint32_t shm = (uint32_t)lds;
+  const bool timed = start || stop;
+  auto go = [&](auto kernel, uint32_t bytes) {
+    if (timed)
+      hipExtLaunchKernelGGL(kernel, grid, block, bytes, s, start, stop, 0u, frames, starts, nf);
+    else
+      hipLaunchKernelGGL(kernel, grid, block, bytes, s, frames, starts, nf);
+  };
   switch (stage) {
     case kStageDescriptor:
       if (variant == 1)
-        hipLaunchKernelGGL(k_descriptor8_batch, grid, block, 0, s, frames, starts, nf);
+        go(k_descriptor8_batch, 0u);
       else if (variant == 2)
-        hipLaunchKernelGGL(k_descriptor16_batch, grid, block, 0, s, frames, starts, nf);
+        go(k_descriptor16_batch, 0u);
       else
-        hipLaunchKernelGGL(k_descriptor4_batch, grid, block, 0, s, frames, starts, nf);
+        go(k_descriptor4_batch, 0u);
       break;
-    case kStageSupport:
-      hipLaunchKernelGGL(k_support_batch, grid, block, 0, s, frames, starts, nf);
-      break;
-    case kStageFilter:
-      hipLaunchKernelGGL(k_filter_batch, grid, block, lds, s, frames, starts, nf);
-      break;
-    case kStageRows:
-      hipLaunchKernelGGL(k_rows_batch, grid, block, lds, s, frames, starts, nf);
-      break;
-    case kStageRaster:
-      hipLaunchKernelGGL(k_raster256_batch, grid, block, 0, s, frames, starts, nf);
-      break;
+    case kStageSupport: go(k_support_batch, 0u); break;
+    case kStageFilter: go(k_filter_batch, shm); break;
+    case kStageRows: go(k_rows_batch, shm); break;
+    case kStageRaster: go(k_raster256_batch, 0u); break;
     case kStageDense:
       if (variant == 0)
-        hipLaunchKernelGGL(k_dense1_batch, grid, block, 0, s, frames, starts, nf);
+        go(k_dense1_batch, 0u);
       else if (variant == 2)
-        hipLaunchKernelGGL(k_dense4_batch, grid, block, 0, s, frames, starts, nf);
+        go(k_dense4_batch, 0u);
       else
-        hipLaunchKernelGGL(k_dense2_batch, grid, block, 0, s, frames, starts, nf);
+        go(k_dense2_batch, 0u);
       break;
-    case kStageCheck:
-      hipLaunchKernelGGL(k_check_batch, grid, block, 0, s, frames, starts, nf);
-      break;
-    case kStageRedun:
-      hipLaunchKernelGGL(k_redun_batch, grid, block, 0, s, frames, starts, nf);
-      break;
-    case kStageMedian:
-      hipLaunchKernelGGL(k_median_batch, grid, block, 0, s, frames, starts, nf);
-      break;
+    case kStageCheck: go(k_check_batch, 0u); break;
+    case kStageRedun: go(k_redun_batch, 0u); break;
+    case kStageMedian: go(k_median_batch, 0u); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

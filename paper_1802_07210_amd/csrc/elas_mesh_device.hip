@@ -1074,9 +1074,14 @@ hipError_t launch_mesh_frame(const Frame& f, hipStream_t s, hipEvent_t start, hi
   return hipGetLastError();
 }
 
-hipError_t launch_mesh_batch(const Frame* frames, int32_t nf, hipStream_t s) {
+hipError_t launch_mesh_batch(const Frame* frames, int32_t nf, hipStream_t s, hipEvent_t start,
+                             hipEvent_t stop) {
   if (nf <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mesh_batch, dim3(2 * nf), dim3(kMT), kMeshLdsBytes, s, frames, nf);
+  if (start || stop)
+    hipExtLaunchKernelGGL(k_mesh_batch, dim3(2 * nf), dim3(kMT), kMeshLdsBytes, s, start, stop,
+                          0u, frames, nf);
+  else
+    hipLaunchKernelGGL(k_mesh_batch, dim3(2 * nf), dim3(kMT), kMeshLdsBytes, s, frames, nf);
   return hipGetLastError();
 }
 

@@ -37,6 +37,20 @@ def test_binding_roofline_is_the_larger_floor():
     assert support["bound"] == "alu" and support["work_per_launch"] == 64 * 2_240_000
 
 
+def test_batched_launch_work_scales_with_the_pairs():
+    # statistics summed over 8 pairs, lattice sizes per pair
+    st = {"support_evals": 8 * 2_240_000, "dense_evals": 8 * 3_200_000, "n_support_left": 8 * 750,
+          "n_support_right": 8 * 750, "n_tri_left": 8 * 1502, "n_tri_right": 8 * 1502,
+          "lattice": 12065, "lattice_rows": 95}
+    dense = bench.roofline_of("dense", 640, 480, st, 0.09, "k_dense2_batch", pairs=8)
+    assert dense["work_per_launch"] == 8 * 2 * 640 * 480 * 20
+    assert dense["alu_view"]["work_per_launch"] == 16 * 8 * 3_200_000
+    sup_bytes, sup_ops = bench.algorithmic_work("support", 640, 480, st, pairs=8)
+    assert sup_bytes == 8 * 2 * 2 * 16 * 640 * 95 and sup_ops == 64 * 8 * 2_240_000
+    mesh_bytes, _ = bench.algorithmic_work("mesh", 640, 480, st, pairs=8)
+    assert mesh_bytes == 8 * (12 * 1500 + 24 * 3004)
+
+
 def test_workgroup_counts_of_the_bench_shape():
     wg = bench.workgroups(640, 480, 128)
     assert wg["mesh"] == 2 and wg["filter"] == 16 * 12 and wg["rows"] == 95

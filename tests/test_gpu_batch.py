@@ -86,6 +86,31 @@ def test_batch_graph_replay_with_new_inputs(E):
         check(pairs, got)
 
 
+def test_timed_batch_reports_stage_times_and_same_maps(E):
+    # with timing on, the batch is launched directly with events around each
+    # launch: the maps still equal the oracle's, every stage of the path has a
+    # positive time, and the stage times fit in the span
+    hs = {D: E.Elas(disp_max=D - 1) for D in {64, 32, 128, 256}}
+    base = hs[64]
+    base.set_timing(True)
+    pairs = make_mix(11)
+    got, _, _ = run_batch(E, pairs, True, False, handles=hs)
+    check(pairs, got)
+    t = base.timing()
+    stages = ["descriptor", "support", "filter", "rows", "mesh", "raster", "dense", "lrcheck"]
+    for s in stages:
+        assert t[s + "_ms"] > 0.0, s
+    assert sum(t[s + "_ms"] for s in stages) <= t["device_span_ms"] * 1.001 + 1e-3
+    assert t["host_wait_ms"] == 0.0 and t["host_mesh_ms"] == 0.0
+    # a plain call afterwards reports its own stages again
+    dev = torch.device("cuda:0")
+    p, D = pairs[0]
+    hs[D].set_timing(True)
+    hs[D].process(torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev))
+    t1 = hs[D].timing()
+    assert t1["dense_ms"] > 0.0 and t1["device_span_ms"] > 0.0
+
+
 def test_batch_equals_single_calls(E):
     dev = torch.device("cuda:0")
     pairs = make_mix(7)
