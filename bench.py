@@ -37,8 +37,8 @@ cpu_baseline    the CPU oracle (single-threaded C) on a bounded sample of the
 --mode calib runs a plain device copy of a known size (reads and writes
 COPY_BYTES per launch) so that rocprofv3's FETCH_SIZE / WRITE_SIZE counters
 can be scaled to bytes; profiles/ keeps the scaled per-launch traffic of the
-dominant kernel together with a hash of the kernel source it was taken on,
-and roofline.traffic reports it only while that source is unchanged.
+kernels that can be dominant, each with a hash of the kernel source it was
+taken on, and roofline.traffic reports it only while that source is unchanged.
 """
 from __future__ import annotations
 
@@ -70,7 +70,7 @@ KERNEL_NAMES = {"descriptor": "k_descriptor8", "support": "k_support", "filter":
 
 COPY_BYTES = 256 << 20
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1802_07210_amd", "csrc", "elas_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_640x480_D128.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 # Variants measured beside the headline configuration (parameter overrides).
 VARIANTS = {
@@ -91,11 +91,18 @@ def source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(kernel: str):
-    """Per-launch HBM bytes of `kernel` from the committed counter runs, or
-    None when they were taken on another version of the kernel source."""
+def traffic_file(kernel: str, workload: str) -> str:
+    """Counter summary of one kernel on one workload (e.g. 640x480_D128, or
+    640x480_D128_x8 for launches over 8 pairs)."""
+    return os.path.join(PROFILES, f"traffic_{kernel}_{workload}.json")
+
+
+def stored_traffic(kernel: str, workload: str = "640x480_D128"):
+    """Per-launch HBM bytes of `kernel` on `workload` from the committed
+    counter runs, or None when there are none or they were taken on another
+    version of the kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(kernel, workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -182,7 +189,7 @@ def workgroups(w: int, h: int, D: int, step: int = 5) -> dict:
 
 
 def roofline_of(stage: str, w: int, h: int, st: dict, ms: float, kernel: str,
-                pairs: int = 1) -> dict:
+                pairs: int = 1, workload: str = "640x480_D128") -> dict:
     """The binding roofline of one kernel: the resource whose floor (work over
     peak) is the larger; achieved = that work over the kernel's mean duration.
     st holds the statistics summed over the `pairs` pairs of one launch."""
@@ -197,7 +204,7 @@ def roofline_of(stage: str, w: int, h: int, st: dict, ms: float, kernel: str,
         achieved, peak, unit, bound, work, wunit = (nbytes / dur_s / 1e9, PEAK_HBM_GBS, "GB/s",
                                                     "hbm", nbytes, "bytes")
     roof = {"bound": bound, "achieved": round(achieved, 4), "peak": round(peak, 1),
-            "unit": unit, "frac": round(achieved / peak, 6), "traffic": stored_traffic(kernel),
+            "unit": unit, "frac": round(achieved / peak, 6), "traffic": stored_traffic(kernel, workload),
             "kernel": kernel, "kernel_ms": round(ms, 5), "work_per_launch": work,
             "work_unit": wunit}
     if bound == "hbm" and ops:
@@ -459,7 +466,8 @@ def main():
     wgs = workgroups(W, H, D)
     chip_ms = {s: v * min(1.0, B * wgs[s] / 256.0) for s, v in kernel_ms.items()}
     dom = max(chip_ms, key=lambda k: chip_ms[k] if chip_ms[k] == chip_ms[k] else -1.0)
-    roof = roofline_of(dom, W, H, st, kernel_ms[dom], names[dom], pairs=B)
+    wl = f"{W}x{H}_D{D}" + (f"_x{B}" if B > 1 else "")
+    roof = roofline_of(dom, W, H, st, kernel_ms[dom], names[dom], pairs=B, workload=wl)
 
     out = {
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,

@@ -58,15 +58,16 @@ def test_workgroup_counts_of_the_bench_shape():
 
 
 def test_stored_traffic_requires_the_same_kernel_source(tmp_path, monkeypatch):
-    f = tmp_path / "t.json"
-    f.write_text(json.dumps({"kernel": "k_dense2", "bytes_per_launch": 123,
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    f = tmp_path / "traffic_k_dense2_batch_640x480_D128_x8.json"
+    f.write_text(json.dumps({"kernel": "k_dense2_batch", "bytes_per_launch": 123,
                              "source_sha256_16": bench.source_hash()}))
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.stored_traffic("k_dense2") == 123
-    assert bench.stored_traffic("k_raster") is None
-    f.write_text(json.dumps({"kernel": "k_dense2", "bytes_per_launch": 123,
+    assert bench.stored_traffic("k_dense2_batch", "640x480_D128_x8") == 123
+    assert bench.stored_traffic("k_dense2_batch", "640x480_D128") is None  # other workload
+    assert bench.stored_traffic("k_raster", "640x480_D128_x8") is None
+    f.write_text(json.dumps({"kernel": "k_dense2_batch", "bytes_per_launch": 123,
                              "source_sha256_16": "0" * 16}))
-    assert bench.stored_traffic("k_dense2") is None
+    assert bench.stored_traffic("k_dense2_batch", "640x480_D128_x8") is None
 
 
 def _counter_csv(path, rows):
