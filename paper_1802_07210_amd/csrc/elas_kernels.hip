@@ -353,33 +353,40 @@ struct CensusSrc {
   }
 };
 
-// Full search of one point over d = dmin..dhi (at least two values); the
-// partner column is u + dir*d. Returns whether the ambiguity test accepts and
-// the best disparity (smallest cost, smallest d on ties). Control flow is
-// wavefront-uniform.
-template <class S>
-__device__ __forceinline__ bool support_search(const typename S::T& self, const S& other,
-                                               int u, int dir, int dhi, const KParams& p,
-                                               int lane, int* d_best) {
-  uint32_t cost[kMaxD / 64];
-  uint32_t best = 0xFFFFFFFFu;
-  const int nj = (dhi - p.dmin + 64) >> 6;
+// One search of a point: the candidate columns u + dir*d, d = dmin + lane +
+// 64 j for j < NJ (NJ 64-wide batches cover the disparity range). Lanes past
+// dhi load column dhi instead (in the image like every searched column) and
+// are masked out, so every load of a search is issued before the first wait.
+template <int NJ, class S>
+__device__ __forceinline__ void search_loads(const S& other, int u, int dir, int dhi,
+                                             const KParams& p, int lane,
+                                             typename S::T (&o)[NJ]) {
 #pragma unroll
-  for (int j = 0; j < kMaxD / 64; ++j) {
-    cost[j] = 0xFFFFFFFFu;
+  for (int j = 0; j < NJ; ++j) o[j] = other.load(u + dir * min(p.dmin + lane + 64 * j, dhi));
+}
+
+// Argmin over d = dmin..dhi (at least two values; smallest cost, smallest d
+// on ties) and the ambiguity test; returns whether it accepts. Control flow
+// is wavefront-uniform.
+template <int NJ, class S>
+__device__ __forceinline__ bool search_decide(const typename S::T& self,
+                                              const typename S::T (&o)[NJ], int dhi,
+                                              const KParams& p, int lane, int* d_best) {
+  uint32_t cost[NJ];
+  uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
     const int d = p.dmin + lane + 64 * j;
-    if (j < nj && d <= dhi) {
-      const uint32_t c = S::cost(self, other.load(u + dir * d));
-      cost[j] = c;
-      best = min(best, (c << 8) | (uint32_t)(d - p.dmin));
-    }
+    const uint32_t c = S::cost(self, o[j]);
+    cost[j] = d <= dhi ? c : 0xFFFFFFFFu;
+    if (d <= dhi) best = min(best, (c << 8) | (uint32_t)(d - p.dmin));
   }
-  best = wave_min_u32(best);  // the search's control flow is wavefront-uniform
+  best = wave_min_u32(best);
   const int d1 = p.dmin + (int)(best & 0xFFu);
   const uint32_t m1 = best >> 8;
   uint32_t m2 = 0xFFFFFFFFu;
 #pragma unroll
-  for (int j = 0; j < kMaxD / 64; ++j) {
+  for (int j = 0; j < NJ; ++j) {
     const int d = p.dmin + lane + 64 * j;
     if (d != d1) m2 = min(m2, cost[j]);
   }
@@ -388,26 +395,45 @@ __device__ __forceinline__ bool support_search(const typename S::T& self, const 
   return support_accept(p, m1, m2);
 }
 
-// One lattice point with descriptor sources sL (left view) and sR (right).
-template <class S>
+// One lattice point with descriptor sources sL (left view) and sR (right):
+// forward search, then the reverse search from the matched right column.
+// The point's own descriptor is loaded together with its candidates, and
+// the texture test waits only for it.
+template <int NJ, class S>
 __device__ __forceinline__ int support_point(const S& sL, const S& sR, int u, int w,
                                              const KParams& p, int lane, int* ev) {
-  const typename S::T ls = sL.load(u);
-  if ((int)S::texture(ls) < p.support_texture) return -1;
   const int dhi = min(p.dmax, u - 4);
   if (dhi - p.dmin + 1 < 2) return -1;
+  const typename S::T ls = sL.load(u);
+  typename S::T o[NJ];
+  search_loads<NJ>(sR, u, -1, dhi, p, lane, o);
+  if ((int)S::texture(ls) < p.support_texture) return -1;
   *ev += dhi - p.dmin + 1;
   int d1;
-  if (!support_search(ls, sR, u, -1, dhi, p, lane, &d1)) return -1;
+  if (!search_decide<NJ, S>(ls, o, dhi, p, lane, &d1)) return -1;
   const int ur = u - d1;
-  const typename S::T rs = sR.load(ur);
   const int dhi2 = min(p.dmax, w - 5 - ur);
-  if ((int)S::texture(rs) < p.support_texture || dhi2 - p.dmin + 1 < 2) return -1;
+  if (dhi2 - p.dmin + 1 < 2) return -1;
+  const typename S::T rs = sR.load(ur);
+  search_loads<NJ>(sL, ur, +1, dhi2, p, lane, o);
+  if ((int)S::texture(rs) < p.support_texture) return -1;
   *ev += dhi2 - p.dmin + 1;
   int d2;
-  if (support_search(rs, sL, ur, +1, dhi2, p, lane, &d2) && abs(d2 - d1) <= p.lr_threshold)
+  if (search_decide<NJ, S>(rs, o, dhi2, p, lane, &d2) && abs(d2 - d1) <= p.lr_threshold)
     return d1;
   return -1;
+}
+
+// The batch count of the frame's disparity range, as a template argument.
+template <class S>
+__device__ __forceinline__ int support_point_d(const S& sL, const S& sR, int u, int w,
+                                               const KParams& p, int lane, int* ev) {
+  switch ((p.D + 63) >> 6) {
+    case 1: return support_point<1>(sL, sR, u, w, p, lane, ev);
+    case 2: return support_point<2>(sL, sR, u, w, p, lane, ev);
+    case 3: return support_point<3>(sL, sR, u, w, p, lane, ev);
+    default: return support_point<4>(sL, sR, u, w, p, lane, ev);
+  }
 }
 
 __device__ __forceinline__ void support_body(const Frame& F, int lb) {
@@ -420,16 +446,18 @@ __device__ __forceinline__ void support_body(const Frame& F, int lb) {
   const int u = g.lu0 + k * g.step, v = g.lv0 + l * g.step;
   int result, ev = 0;
   if (p.descriptor == 0) {
-    result = support_point(GradSrc{F.descL, g.w, v}, GradSrc{F.descR, g.w, v}, u, g.w, p, lane,
-                           &ev);
+    result = support_point_d(GradSrc{F.descL, g.w, v}, GradSrc{F.descR, g.w, v}, u, g.w, p,
+                             lane, &ev);
   } else {
     const size_t row = (size_t)l * g.w * p.cs_q;
     const uint4* cL = F.csupL;
     const uint4* cR = F.csupR;
     if (p.cs_q == 1)
-      result = support_point(CensusSrc<1>{cL + row}, CensusSrc<1>{cR + row}, u, g.w, p, lane, &ev);
+      result = support_point_d(CensusSrc<1>{cL + row}, CensusSrc<1>{cR + row}, u, g.w, p,
+                               lane, &ev);
     else
-      result = support_point(CensusSrc<2>{cL + row}, CensusSrc<2>{cR + row}, u, g.w, p, lane, &ev);
+      result = support_point_d(CensusSrc<2>{cL + row}, CensusSrc<2>{cR + row}, u, g.w, p,
+                               lane, &ev);
   }
   if (lane == 0) {
     F.dcan_raw[pt] = (int16_t)result;
