@@ -227,6 +227,9 @@ Geometry make_geometry(const elas_params& p, int32_t w, int32_t h) {
   g.gh = (h + p.grid_size - 1) / p.grid_size;
   const int32_t D = p.disp_max - p.disp_min + 1;
   g.gwords = 2 * ((D + 63) / 64);
+  // 8 x 8 filter tiles while every tile of the frame can have a CU of its
+  // own, else 16 x 16 (fewer halo positions per tile)
+  g.ftile = ((g.lw + 7) / 8) * ((g.lh + 7) / 8) <= 256 ? 8 : 16;
   return g;
 }
 
@@ -415,6 +418,9 @@ int pool_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, size
     Buffers* b = nullptr;
     const int rc = alloc_buffers(h, w, hp, &b);
     if (rc != ELAS_OK) return rc;
+    // a batch has workgroups enough to fill the chip: the larger filter
+    // tiles, which compute fewer halo positions per lattice point
+    b->g.ftile = 16;
     v.push_back(b);
   }
   *out = v[slot];

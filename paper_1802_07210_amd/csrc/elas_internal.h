@@ -24,6 +24,7 @@ struct Geometry {
   int32_t step;       // lattice step in pixels
   int32_t gw, gh;     // grid-vector regions
   int32_t gwords;     // 32-bit words per region mask (even: 64-bit aligned masks)
+  int32_t ftile;      // support-filter tile side in lattice points (8 or 16)
 };
 
 // Parameters as the kernels consume them (passed by value).

@@ -468,7 +468,8 @@ __device__ __forceinline__ void support_body(const Frame& F, int lb) {
 // ---------------------------------------------------------------------------
 // Stage 3: support filtering (Section III-A, Fig. 1(e); Fig. 7A), three
 // simultaneous-update passes fused in one kernel over 8 x 8 lattice tiles
-// (16 x 16 on lattices with more than 256 such tiles; 1024 threads per tile;
+// (16 x 16 in batches and on lattices with more than 256 such tiles; 1024
+// threads per tile;
 // a position's consistency count is split over four lanes, so that the
 // longest per-thread chain is a quarter of the window):
 //  * consistency: a point survives iff at least incon_min_support other
@@ -485,11 +486,9 @@ __device__ __forceinline__ void support_body(const Frame& F, int lb) {
 // ---------------------------------------------------------------------------
 constexpr int kFiltParts = 4;    // lanes sharing one position's consistency count
 
-// Tile side in lattice points: 8 while every tile can have a CU of its own,
-// else 16 (fewer halo positions per tile).
-__host__ __device__ __forceinline__ int filter_tile(const Geometry& g) {
-  return cdivd(max(g.lw, 1), 8) * cdivd(max(g.lh, 1), 8) <= 256 ? 8 : 16;
-}
+// Tile side in lattice points (chosen with the frame's buffers: 8 for a
+// single frame whose tiles can each have a CU, else 16).
+__host__ __device__ __forceinline__ int filter_tile(const Geometry& g) { return g.ftile; }
 __host__ __device__ __forceinline__ int filter_tiles_x(const Geometry& g) {
   return g.lw > 0 ? cdivd(g.lw, filter_tile(g)) : 1;
 }
