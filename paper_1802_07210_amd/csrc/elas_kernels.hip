@@ -785,8 +785,6 @@ __device__ __forceinline__ void clip_edge(int k, int c, int* lo, int* hi) {
   }
 }
 
-constexpr int kRasterTile = 8192;   // LDS owner tile: band rows x width
-constexpr int kRasterList = 4096;   // ranks of gathered triangles per pass
 constexpr int kBandRowsMax = 4;
 constexpr int kWaveSpan = 64 * (2 + 2 * kBandRowsMax);  // per-wave span table in LDS
 
@@ -798,8 +796,11 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   constexpr int kRasterScan = 2048 / kRasterThreads;  // triangles per thread and gather step
   constexpr int kRasterOut = 2048 / kRasterThreads < 4 ? 4 : 2048 / kRasterThreads;
   constexpr int kRasterWaves = kRasterThreads / 64;
+  // ranks of gathered triangles per pass: the 256-thread variant keeps its
+  // LDS small, so that more bands share a CU
+  constexpr int kRasterList = kRasterThreads == 1024 ? 4096 : 2560;
   static_assert(kRasterScan * kRasterThreads <= kRasterList, "a gather step must fit the list");
-  __shared__ int32_t tile[kRasterTile];
+  int32_t* const tile = reinterpret_cast<int32_t*>(dyn_smem);  // band rows x width
   __shared__ int32_t rlist[kRasterList];
   __shared__ int32_t wspan[(kRasterThreads / 64) * kWaveSpan];
   __shared__ int32_t s_wtot[kRasterThreads / 64];  // span pixels per wave (1024 threads)
@@ -1470,6 +1471,7 @@ size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p) {
   switch (stage) {
     case kStageFilter: return filter_lds_bytes(g, p);
     case kStageRows: return sizeof(int32_t) * (size_t)g.w;
+    case kStageRaster: return sizeof(int32_t) * (size_t)raster_band_rows(g.w) * g.w;
     case kStageMesh: return kMeshLdsBytes;
     default: return 0;
   }
@@ -1551,7 +1553,7 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
     case kStageSupport: go(k_support_batch, 0u); break;
     case kStageFilter: go(k_filter_batch, shm); break;
     case kStageRows: go(k_rows_batch, shm); break;
-    case kStageRaster: go(k_raster256_batch, 0u); break;
+    case kStageRaster: go(k_raster256_batch, shm); break;
     case kStageDense:
       if (variant == 0)
         go(k_dense1_batch, 0u);
