@@ -429,9 +429,14 @@ int pool_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, size
 
 // Tile variants (descriptor, dense) for a frame size and disparity count:
 // the autotuner's choice, else the defaults.
-std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp, int32_t D) {
+std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp, int32_t D,
+                                    bool batched = false) {
   auto it = h->tuned.find(std::make_tuple(w, hp, D));
-  return it != h->tuned.end() ? it->second : std::make_pair(1, 1);  // 8 rows, 2 per batch
+  if (it != h->tuned.end()) return it->second;
+  // untuned: 8 descriptor rows per block (16 in batches, whose many blocks
+  // fill the chip anyway and gain from the smaller halo share), 2 dense
+  // candidates per step
+  return std::make_pair(batched ? 2 : 1, 1);
 }
 
 std::pair<int, int> variants_for(const elas_handle* h, int32_t w, int32_t hp) {
@@ -1027,7 +1032,7 @@ int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStr
     if (rc != ELAS_OK) return fail(h, rc, elas_last_error(ph));
     frames.push_back(make_frame(ph, b, q.left, q.right, q.stride, q.disp_left, q.disp_right,
                                 false));
-    var.push_back(variants_lookup(h, q.w, q.h, ph->kp.D));
+    var.push_back(variants_lookup(h, q.w, q.h, ph->kp.D, true));
   }
   BatchCtx* c = nullptr;
   int rc = batch_ctx(h, stream, &c);
