@@ -459,9 +459,9 @@ def main():
     stage_ms = {s: float(np.mean(v)) if v else float("nan") for s, v in acc.items()}
     kernel_ms = {s: stage_ms[s] for s in KERNEL_NAMES}
     names = dict(KERNEL_NAMES)
-    if B > 1:  # the batched kernels (16 descriptor rows, the raster's 256-thread workgroup)
-        names = {s: {"raster": "k_raster256", "descriptor": "k_descriptor16"}.get(s, n) + "_batch"
-                 for s, n in names.items()}
+    if B > 1:  # the batched kernels (their untuned tile variants; the raster's 256 threads)
+        names = {s: {"raster": "k_raster256", "descriptor": "k_descriptor16",
+                     "dense": "k_dense1"}.get(s, n) + "_batch" for s, n in names.items()}
     # share of chip time: duration x the fraction of the 256 CUs the kernel's
     # workgroups can occupy (launch geometry of each stage at this size)
     wgs = workgroups(W, H, D)

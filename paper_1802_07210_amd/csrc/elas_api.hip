@@ -433,10 +433,10 @@ std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp,
                                     bool batched = false) {
   auto it = h->tuned.find(std::make_tuple(w, hp, D));
   if (it != h->tuned.end()) return it->second;
-  // untuned: 8 descriptor rows per block (16 in batches, whose many blocks
-  // fill the chip anyway and gain from the smaller halo share), 2 dense
-  // candidates per step
-  return std::make_pair(batched ? 2 : 1, 1);
+  // untuned: 8 descriptor rows per block and 2 dense candidates per step; in
+  // batches, whose many blocks fill the chip anyway, 16 rows (a smaller halo
+  // share) and 1 candidate per step (fewer registers), measured faster there
+  return std::make_pair(batched ? 2 : 1, batched ? 0 : 1);
 }
 
 std::pair<int, int> variants_for(const elas_handle* h, int32_t w, int32_t hp) {
