@@ -435,7 +435,7 @@ std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp,
   if (it != h->tuned.end()) return it->second;
   // untuned: 8 descriptor rows per block and 2 dense candidates per step; in
   // batches, whose many blocks fill the chip anyway, 16 rows (a smaller halo
-  // share) and 1 candidate per step (fewer registers), measured faster there
+  // share) and 1 candidate per step, both measured faster there
   return std::make_pair(batched ? 2 : 1, batched ? 0 : 1);
 }
 
