@@ -188,6 +188,23 @@ def workgroups(w: int, h: int, D: int, step: int = 5) -> dict:
             "dense": 2 * cd(h, 2) * cd(w, 256), "lrcheck": 2 * cd(w * h, 1024)}
 
 
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second (4 cycles each)
+
+
+def stored_valu(kernel: str, workload: str = "640x480_D128"):
+    """VALU instructions per launch of `kernel` on `workload` from the
+    committed SQ counter run, or None (none, or another kernel source)."""
+    try:
+        with open(os.path.join(PROFILES, f"valu_{workload}.json")) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256_16") != source_hash():
+        return None
+    rec = t.get("kernels", {}).get(kernel)
+    return rec.get("sq_insts_valu") if rec else None
+
+
 def roofline_of(stage: str, w: int, h: int, st: dict, ms: float, kernel: str,
                 pairs: int = 1, workload: str = "640x480_D128") -> dict:
     """The binding roofline of one kernel: the resource whose floor (work over
@@ -207,6 +224,11 @@ def roofline_of(stage: str, w: int, h: int, st: dict, ms: float, kernel: str,
             "unit": unit, "frac": round(achieved / peak, 6), "traffic": stored_traffic(kernel, workload),
             "kernel": kernel, "kernel_ms": round(ms, 5), "work_per_launch": work,
             "work_unit": wunit}
+    valu = stored_valu(kernel, workload)
+    if valu:  # the share of the chip's VALU instruction issue this launch used
+        roof["valu_issue"] = {"insts_per_launch": round(valu), "achieved": round(valu / dur_s / 1e9, 2),
+                              "peak": round(VALU_ISSUE_PEAK / 1e9, 1), "unit": "G wave64 instr/s",
+                              "frac": round(valu / dur_s / VALU_ISSUE_PEAK, 4)}
     if bound == "hbm" and ops:
         roof["alu_view"] = {"achieved": round(ops / dur_s / 1e12, 4), "peak": round(PEAK_SAD_TOPS, 1),
                             "unit": "Tops/s", "frac": round(ops / dur_s / 1e12 / PEAK_SAD_TOPS, 6),

@@ -13,12 +13,22 @@ Two commands, each reading the CSV output of rocprofv3 runs
            counter units to bytes. Writes a JSON record (bytes per launch and a
            hash of the kernel source the counters were taken on) and a
            markdown summary.
+  valu     instruction counts per launch and per wavefront of every kernel of
+           one counter run (``--pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU
+           SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_WAVE_CYCLES SQ_WAIT_INST_ANY``):
+           a JSON record per kernel (with the kernel-source hash) and a
+           markdown table. With a kernel's duration they give its share of
+           the chip's VALU issue rate (a wave64 instruction holds a 16-lane
+           SIMD for 4 cycles: 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G
+           wavefront instructions per second).
 
 Usage:
   python -m paper_1802_07210_amd.profiling stats DIR OUT.md --cmd "..."
   python -m paper_1802_07210_amd.profiling traffic --kernel NAME \\
       --fetch DIR --write DIR --calib-fetch DIR --calib-write DIR \\
       --copy-bytes N --json OUT.json --md OUT.md --cmd "..."
+  python -m paper_1802_07210_amd.profiling valu DIR --workload W \
+      --json OUT.json --md OUT.md --cmd "..."
 """
 from __future__ import annotations
 
@@ -157,6 +167,56 @@ def cmd_traffic(args):
     print(json.dumps(rec))
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+               "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY")
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4   # wavefront instructions per second
+
+
+def valu_record(dirpath: str) -> dict:
+    """Per kernel: the mean of each SQ counter per dispatch (device totals)."""
+    means = {c: counter_means(dirpath, c) for c in SQ_COUNTERS}
+    out = {}
+    for k in means["SQ_WAVES"]:
+        if not all(k in means[c] for c in SQ_COUNTERS):
+            continue
+        rec = {c.lower(): means[c][k][0] for c in SQ_COUNTERS}
+        rec["dispatches"] = means["SQ_WAVES"][k][1]
+        out[k] = rec
+    return out
+
+
+def cmd_valu(args):
+    rec = valu_record(args.dir)
+    with open(KERNEL_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(args.json, "w") as f:
+        json.dump({"workload": args.workload, "valu_issue_peak_per_s": VALU_ISSUE_PEAK,
+                   "kernels": rec, "source_sha256_16": sha}, f, indent=1)
+        f.write("\n")
+    lines = [f"# Instruction counts per launch: {args.workload}", "",
+             "Command (from the repository root on the GPU host):", "",
+             "```", args.cmd, "```", "",
+             "SQ counters are device totals per dispatch, averaged over the kernel's",
+             "dispatches. A wave64 VALU instruction holds a 16-lane SIMD for 4 cycles,",
+             f"so the chip issues at most {VALU_ISSUE_PEAK / 1e9:.1f} G wavefront VALU "
+             "instructions per second;",
+             "a kernel's VALU instructions per launch over that rate is the floor of its",
+             "duration from instruction issue alone.", "",
+             "| kernel | waves | VALU / wave | SALU / wave | LDS / wave | VMEM rd / wave | "
+             "VALU per launch | VALU issue floor (us) |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(rec, key=lambda k: -rec[k]["sq_insts_valu"]):
+        r = rec[k]
+        w = max(r["sq_waves"], 1.0)
+        lines.append(f"| {k} | {r['sq_waves']:.0f} | {r['sq_insts_valu'] / w:.1f} | "
+                     f"{r['sq_insts_salu'] / w:.1f} | {r['sq_insts_lds'] / w:.1f} | "
+                     f"{r['sq_insts_vmem_rd'] / w:.1f} | {r['sq_insts_valu']:,.0f} | "
+                     f"{r['sq_insts_valu'] / VALU_ISSUE_PEAK * 1e6:.2f} |")
+    lines += ["", f"Kernel source sha256 (first 16 hex): {sha}"]
+    with open(args.md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -178,6 +238,13 @@ def main(argv=None):
     b.add_argument("--md", required=True)
     b.add_argument("--cmd", required=True)
     b.set_defaults(fn=cmd_traffic)
+    c = sub.add_parser("valu")
+    c.add_argument("dir")
+    c.add_argument("--workload", default="")
+    c.add_argument("--json", required=True)
+    c.add_argument("--md", required=True)
+    c.add_argument("--cmd", required=True)
+    c.set_defaults(fn=cmd_valu)
     args = ap.parse_args(argv)
     args.fn(args)
 

@@ -70,6 +70,26 @@ def test_stored_traffic_requires_the_same_kernel_source(tmp_path, monkeypatch):
     assert bench.stored_traffic("k_dense2_batch", "640x480_D128_x8") is None
 
 
+def test_stored_valu_issue_requires_the_same_kernel_source(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    f = tmp_path / "valu_640x480_D128_x8.json"
+    rec = {"kernels": {"k_support_batch": {"sq_insts_valu": 24_000_000.0}},
+           "source_sha256_16": bench.source_hash()}
+    f.write_text(json.dumps(rec))
+    assert bench.stored_valu("k_support_batch", "640x480_D128_x8") == 24_000_000.0
+    assert bench.stored_valu("k_dense1_batch", "640x480_D128_x8") is None
+    st = {"support_evals": 2_240_000, "dense_evals": 3_200_000, "n_support_left": 750,
+          "n_support_right": 750, "n_tri_left": 1502, "n_tri_right": 1502,
+          "lattice": 12065, "lattice_rows": 95}
+    roof = bench.roofline_of("support", 640, 480, st, 0.05, "k_support_batch", pairs=8,
+                             workload="640x480_D128_x8")
+    # 24 M wavefront instructions in 50 us against 614.4 G per second
+    assert abs(roof["valu_issue"]["frac"] - 24e6 / 50e-6 / 614.4e9) < 1e-4
+    rec["source_sha256_16"] = "0" * 16
+    f.write_text(json.dumps(rec))
+    assert bench.stored_valu("k_support_batch", "640x480_D128_x8") is None
+
+
 def _counter_csv(path, rows):
     with open(path, "w", newline="") as fh:
         w = csv.writer(fh)
