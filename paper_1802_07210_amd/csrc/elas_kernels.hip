@@ -286,15 +286,6 @@ struct Desc64 {
   uint4 q[4];
 };
 
-__device__ __forceinline__ Desc64 load_support(const uint8_t* desc, int w, int u, int v) {
-  Desc64 r;
-  r.q[0] = ld16(desc + ((size_t)(v - 2) * w + (u - 2)) * 16);
-  r.q[1] = ld16(desc + ((size_t)(v - 2) * w + (u + 2)) * 16);
-  r.q[2] = ld16(desc + ((size_t)(v + 2) * w + (u - 2)) * 16);
-  r.q[3] = ld16(desc + ((size_t)(v + 2) * w + (u + 2)) * 16);
-  return r;
-}
-
 __device__ __forceinline__ uint32_t sad64(const Desc64& a, const Desc64& b) {
   return sad16(a.q[0], b.q[0]) + sad16(a.q[1], b.q[1]) + sad16(a.q[2], b.q[2]) +
          sad16(a.q[3], b.q[3]);
@@ -311,11 +302,24 @@ __device__ __forceinline__ bool support_accept(const KParams& p, uint32_t m1, ui
 
 // Descriptor sources of the support search: load(x) = descriptor of column x
 // on the point's row; cost(a, b); texture(a).
+// The point's two descriptor rows are wavefront-uniform base pointers and a
+// column is a 32-bit byte offset (x - 2 >= 0 for every searched column), so
+// each load takes a scalar base, one vector offset and an immediate.
 struct GradSrc {
   typedef Desc64 T;
-  const uint8_t* desc;
-  int w, v;
-  __device__ __forceinline__ T load(int x) const { return load_support(desc, w, x, v); }
+  const uint8_t* ra;  // row v - 2
+  const uint8_t* rb;  // row v + 2
+  __device__ GradSrc(const uint8_t* desc, int w, int v)
+      : ra(desc + (size_t)(v - 2) * w * 16), rb(desc + (size_t)(v + 2) * w * 16) {}
+  __device__ __forceinline__ T load(int x) const {
+    const uint32_t o = (uint32_t)(x - 2) * 16u;  // columns x - 2 and x + 2: o and o + 64
+    Desc64 r;
+    r.q[0] = ld16(ra + o);
+    r.q[1] = ld16(ra + o + 64u);
+    r.q[2] = ld16(rb + o);
+    r.q[3] = ld16(rb + o + 64u);
+    return r;
+  }
   __device__ __forceinline__ static uint32_t cost(const T& a, const T& b) { return sad64(a, b); }
   __device__ __forceinline__ static uint32_t texture(const T& a) { return texture64(a); }
 };
@@ -334,9 +338,10 @@ struct CensusSrc {
   };
   const uint4* row;  // the lattice row's census, NQ words per column
   __device__ __forceinline__ T load(int x) const {
+    const uint32_t o = (uint32_t)x * NQ;  // a 32-bit offset from the uniform row
     T r;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) r.q[i] = row[(size_t)x * NQ + i];
+    for (int i = 0; i < NQ; ++i) r.q[i] = row[o + i];
     return r;
   }
   __device__ __forceinline__ static uint32_t cost(const T& a, const T& b) {
