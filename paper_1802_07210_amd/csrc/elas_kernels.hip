@@ -1058,6 +1058,12 @@ constexpr int kDenseSeg = 256;
 constexpr int kDenseRows = 2;
 constexpr int kWinBatch = 5;  // the whole plane window at the default sradius (2)
 constexpr int kDenseStage = kDenseSeg + kMaxD - 1;
+// Prior table in LDS, mirrored about its centre so that a candidate's entry
+// is one add away: s_lut[kLutC + k] = s_lut[kLutC - k] = lut[k] (the prior of
+// |d - dp| = k < D), then kMaxD zeros (pixels without a plane).
+constexpr int kLutC = kMaxD - 1;
+constexpr int kLutZero = 2 * kLutC + 1;
+constexpr int kLutSize = kLutZero + kMaxD;
 
 __host__ __device__ __forceinline__ int dense_segments(const Geometry& g) {
   return cdivd(g.w, kDenseSeg);
@@ -1073,7 +1079,7 @@ __device__ __forceinline__ uint32_t bits32_between(int a, int b) {
 
 // Argmin over the candidates of one pixel (descriptors defined there); st
 // holds the other view's descriptors of columns base .. base + n - 1; s_lut
-// has a zero entry at kMaxD for pixels without a plane. The plane window is
+// is the mirrored prior table (kLutC, kLutZero). The plane window is
 // evaluated as a range, the grid bits outside it (every admissible d with
 // full_search) from 32-bit mask words, KB at a time; a batch's unused slots
 // repeat its first candidate, so every slot is evaluated without branches
@@ -1093,7 +1099,9 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
   }
   const int slot0 = (right ? u + p.dmin : u - p.dmin) - base;
   const int dir = right ? 1 : -1;
-  const int lut_off = p.dmin - dp;  // |dd + lut_off| = |d - dp|
+  // entry of candidate dd (d = dmin + dd): kLutC + d - dp with a plane, else
+  // the zero block; dp lies in [dmin, dmax], so the index stays in the table
+  const int lidx = dp >= 0 ? kLutC + p.dmin - dp : kLutZero;
   uint32_t best = 0xFFFFFFFFu;
   int n = max(0, whi - wlo + 1);
   // the window, kWinBatch candidates at a time (the last batch repeats whi),
@@ -1107,7 +1115,7 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
 #pragma unroll
     for (int t = 0; t < kWinBatch; ++t) {
       o[t] = st[slot0 + dir * dd[t]];
-      lv[t] = s_lut[abs(dd[t] + lut_off)];  // a window exists only with a plane
+      lv[t] = s_lut[dd[t] + lidx];  // a window exists only with a plane
     }
 #pragma unroll
     for (int t = 0; t < kWinBatch; ++t) {
@@ -1139,7 +1147,7 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
 #pragma unroll
       for (int t = 0; t < KB; ++t) {
         o[t] = st[slot0 + dir * dd[t]];
-        lv[t] = s_lut[dp >= 0 ? abs(dd[t] + lut_off) : kMaxD];
+        lv[t] = s_lut[dd[t] + lidx];
       }
 #pragma unroll
       for (int t = 0; t < KB; ++t) {
@@ -1207,7 +1215,13 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
     const int r = dense_row_of(i, nc), c = c0 + (i - r * nc);
     sv[k] = DD::load(other_desc, (size_t)(v0 + r) * g.w + c);
   }
-  const int32_t lv = lut[min((int)threadIdx.x, p.D - 1)];
+  int32_t lv[3];  // the mirrored table's entries tid, tid + 256, tid + 512
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = (int)threadIdx.x + 256 * q;
+    const int32_t x = lut[min(abs(i - kLutC), p.D - 1)];
+    lv[q] = i <= 2 * kLutC ? x : 0;
+  }
   const int uc = min(u, g.w - 1);
   const int gwp = g.gwords >> 1;  // 64-bit words of a region mask
   int dpv[kDenseRows];
@@ -1229,8 +1243,11 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
     const int r = dense_row_of(i, nc), c = c0 + (i - r * nc);
     if (i < nst) st[r * kDenseStage + (c - base)] = sv[k];
   }
-  if ((int)threadIdx.x < p.D) s_lut[threadIdx.x] = lv;
-  if (threadIdx.x == 0) s_lut[kMaxD] = 0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = (int)threadIdx.x + 256 * q;
+    if (i < kLutSize) s_lut[i] = lv[q];
+  }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kDenseRows; ++r) {
@@ -1253,7 +1270,7 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
 
 template <int KB>
 __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
-  __shared__ int32_t s_lut[kMaxD + 1];  // entry kMaxD: 0, the prior of pixels without a plane
+  __shared__ int32_t s_lut[kLutSize];  // mirrored prior table, then zeros
   __shared__ int s_cnt[4];
   __shared__ uint4 s_stage[kDenseRows * kDenseStage];
   const Geometry g = F.g;
