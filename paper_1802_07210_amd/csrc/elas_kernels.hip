@@ -1084,8 +1084,8 @@ __device__ __forceinline__ uint32_t bits32_between(int a, int b) {
 // full_search) from 32-bit mask words, KB at a time; a batch's unused slots
 // repeat its first candidate, so every slot is evaluated without branches
 // (a repeat cannot change the argmin) and the count comes from popcounts.
-template <int KB, class DD>
-__device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, bool right, int u,
+template <int KB, class DD, bool right>
+__device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, int u,
                                            int dp, const uint32_t (&cw)[kMaxD / 32],
                                            const typename DD::T s, const typename DD::T* st,
                                            int base, const int32_t* s_lut, int* cnt) {
@@ -1174,9 +1174,11 @@ __device__ __forceinline__ int dense_row_of(int i, int nc) {
 // descriptors, staged in LDS; the own descriptor, prior and grid-region mask
 // of each pixel) is issued before the one barrier, so a wave waits on memory
 // once.
-template <int KB, class DD>
+// The view is a template argument: the search direction is then a constant
+// in every candidate's address.
+template <int KB, class DD, bool right>
 __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, const KParams& p,
-                                           bool right, int v0, int u0, int32_t* s_lut,
+                                           int v0, int u0, int32_t* s_lut,
                                            typename DD::T* st, int* cnt) {
   const int32_t* lut = F.lut;
   // fields copied to locals first, so that no pointer is selected by
@@ -1261,7 +1263,7 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
         cw[2 * j] = has_list ? cw2[r][j].x : 0u;
         cw[2 * j + 1] = has_list ? cw2[r][j].y : 0u;
       }
-      res = dense_pixel<KB, DD>(g, p, right, u, dpv[r], cw, s[r], st + r * kDenseStage, base,
+      res = dense_pixel<KB, DD, right>(g, p, u, dpv[r], cw, s[r], st + r * kDenseStage, base,
                                 s_lut, cnt);
     }
     raw[(size_t)v * g.w + u] = (int16_t)res;
@@ -1280,11 +1282,18 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
   const int rs = lb >> 1, band = rs / nseg, u0 = (rs - band * nseg) * kDenseSeg;
   const int v0 = band * kDenseRows;
   int cnt = 0;
-  if (p.descriptor)
-    dense_rows<KB, CensusDense>(F, g, p, right, v0, u0, s_lut,
-                                reinterpret_cast<uint64_t*>(s_stage), &cnt);
-  else
-    dense_rows<KB, GradDense>(F, g, p, right, v0, u0, s_lut, s_stage, &cnt);
+  uint64_t* const s_stage64 = reinterpret_cast<uint64_t*>(s_stage);
+  if (p.descriptor) {
+    if (right)
+      dense_rows<KB, CensusDense, true>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
+    else
+      dense_rows<KB, CensusDense, false>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
+  } else {
+    if (right)
+      dense_rows<KB, GradDense, true>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
+    else
+      dense_rows<KB, GradDense, false>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
+  }
   cnt = wave_sum_i32(cnt);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
