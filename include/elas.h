@@ -20,7 +20,16 @@
  *
  * Error behaviour: every entry point returns ELAS_OK (0) or a negative
  * ELAS_ERR_* code; no C++ exception crosses this interface. After a failure
- * elas_last_error() describes it.
+ * elas_last_error() describes it. Work that fails on the device after a
+ * call has returned (the device mesh exhausting its flip rounds or failing a
+ * consistency check; its frame is then matched without plane priors, so its
+ * maps differ from the reference pipeline) is reported as ELAS_ERR_INTERNAL:
+ * the failing kernel sets a pinned report word of the calling handle, and the
+ * first later call on that handle (elas_process, elas_process_batch,
+ * elas_get_stats) returns the error, once, without
+ * doing its own work. elas_get_stats synchronises first, so it always
+ * reports a failure of the last call. A server fails the tickets of the
+ * affected pairs instead.
  *
  * Threading: a handle is not thread-safe. Calls on one handle must be
  * ordered (one host thread, and either one stream or streams the caller
@@ -137,8 +146,10 @@ typedef struct elas_timing {
 /* Fills *p with the default parameters. */
 ELAS_API void elas_params_default(elas_params* p);
 
-/* Validates *p and creates a handle. Computes the prior table; makes no HIP
- * call (device memory is allocated by the first elas_process per image size).
+/* Validates *p and creates a handle (Section III-A: the matching parameters;
+ * the prior table of the plane prior). Computes the prior table and, when a
+ * device is present, allocates the handle's pinned failure report word;
+ * device memory is allocated by the first elas_process per image size.
  * Returns ELAS_ERR_ARG for invalid values (null pointers, D outside 1..256,
  * negative windows or thresholds, step or grid size < 1, non-positive or
  * non-finite beta/gamma/sigma) and ELAS_ERR_UNSUPPORTED when the prior
@@ -146,8 +157,8 @@ ELAS_API void elas_params_default(elas_params* p);
  * filter window exceeds 16 lattice steps (incon_window_size, redun_max_dist). */
 ELAS_API int elas_create(const elas_params* p, elas_handle** out);
 
-/* Frees the handle and everything it owns. Waits for its pending work.
- * NULL is accepted. */
+/* Frees the handle and everything it owns (the per-size buffers of the
+ * path of Section III-A). Waits for its pending work. NULL is accepted. */
 ELAS_API int elas_destroy(elas_handle* h);
 
 /* Computes both disparity maps of one pair.
@@ -195,7 +206,9 @@ enum elas_batch_flags {
 };
 ELAS_API int elas_set_batch_flags(elas_handle* h, int32_t flags);
 
-/* Computes n pairs of possibly different sizes and disparity ranges with one
+/* Several frames in flight at once, as the paper's dual system keeps two
+ * frames in its pipeline (Section VII-D), taken further: computes n pairs of
+ * possibly different sizes and disparity ranges with one
  * launch per stage (and tile variant) for the whole batch: every stage's
  * kernel covers the workgroups of all frames, a workgroup finds its frame in
  * a device table (uploaded by the call from pinned memory), and the two mesh
@@ -256,10 +269,19 @@ ELAS_API void elas_server_config_default(elas_server_config* c);
 /* ELAS_ERR_ARG for out-of-range settings, ELAS_ERR_HIP if streams fail. */
 ELAS_API int elas_server_create(elas_handle* h, const elas_server_config* cfg,
                                 elas_server** out);
-/* ELAS_ERR_ARG for a bad pair or one larger than the whole budget. */
+/* ELAS_ERR_ARG for a bad pair or one larger than the whole budget. The
+ * pair's images must be complete when it is submitted (the caller has
+ * synchronised with whatever wrote them); otherwise use elas_server_submit_on. */
 ELAS_API int elas_server_submit(elas_server* s, const elas_pair* pair, int64_t* ticket);
+/* As elas_server_submit, ordered after the work already enqueued on
+ * `producer` (the stream that wrote the images or last used the outputs): an
+ * event recorded there at submission is waited for on the device before the
+ * pair's batch runs. producer = NULL is the null stream. */
+ELAS_API int elas_server_submit_on(elas_server* s, const elas_pair* pair, hipStream_t producer,
+                                   int64_t* ticket);
 /* Blocks until the ticket completes; *latency_ms (optional) receives its
- * latency. Returns the pair's status (a ticket is reported once). */
+ * latency. Returns the pair's status (a ticket is reported once):
+ * ELAS_ERR_INTERNAL if its device mesh failed (see the top of this header). */
 ELAS_API int elas_server_wait(elas_server* s, int64_t ticket, double* latency_ms);
 /* Non-blocking: *done = 1 and the status and latency once complete. */
 ELAS_API int elas_server_poll(elas_server* s, int64_t ticket, int32_t* done,
@@ -272,6 +294,13 @@ ELAS_API int elas_server_destroy(elas_server* s);
 /* Copies the counters of the last elas_process call (synchronises with its
  * stream first). */
 ELAS_API int elas_get_stats(elas_handle* h, elas_stats* out);
+
+/* Test hook: caps the flip rounds of the device mesh (1..32000; the default
+ * 32000 never binds, a frame needs a few tens). A view that is not legal
+ * within the cap gives up, its frame is matched without plane priors, and the
+ * failure is reported as described at the top of this header. Lets tests
+ * force the failure path while every kernel still exits normally. */
+ELAS_API int elas_set_mesh_round_limit(elas_handle* h, int32_t rounds);
 
 /* Turns per-stage event timing on (1) or off (0) for later calls. Timing
  * adds one event record per stage boundary to the stream. */
@@ -334,6 +363,17 @@ enum elas_intermediate {
 };
 ELAS_API int elas_get_intermediate(elas_handle* h, int32_t which, void* dst_host,
                                    int64_t bytes, int64_t* needed);
+
+/* As elas_get_intermediate, for pair `pair` (0-based) of the last
+ * elas_process_batch call made on h: the stages computed by the batched
+ * kernels, for stage-by-stage verification of a batch. A pair meshed on the
+ * host was computed by elas_process on its parameter handle, and reads come
+ * from that handle's last call. Valid until the next call that uses the
+ * pair's buffers (a later batch on the same stream, or a call on its
+ * parameter handle); synchronises with the batch's stream. ELAS_ERR_ARG for a
+ * pair outside the last batch. */
+ELAS_API int elas_get_batch_intermediate(elas_handle* h, int32_t pair, int32_t which,
+                                         void* dst_host, int64_t bytes, int64_t* needed);
 
 /* The mesh step on its own, on the host (Section III-A: Delaunay
  * triangulation of the support points and one slanted plane per triangle;

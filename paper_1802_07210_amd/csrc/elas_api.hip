@@ -181,6 +181,21 @@ struct elas_handle {
   std::map<std::tuple<int32_t, int32_t, hipStream_t>, std::vector<Buffers*>> pool;
   std::map<std::tuple<int32_t, int32_t, int32_t>, std::pair<int, int>> tuned;
   hipStream_t tune_stream = nullptr;
+  // device-mesh failure report: a pinned, device-mapped word that the mesh
+  // kernel of a failing frame sets to its status; the next call on the
+  // handle (or elas_get_stats) turns it into ELAS_ERR_INTERNAL
+  int32_t* fail_host = nullptr;
+  int32_t* fail_dev = nullptr;
+  // the pairs of the last elas_process_batch call, for stage-by-stage reads:
+  // the pair's parameter handle and buffers (host-mesh pairs: that handle's
+  // last call), its stream, and whether it was meshed on the host
+  struct BatchPair {
+    elas_handle* ph;
+    Buffers* b;
+    hipStream_t stream;
+    bool on_host;
+  };
+  std::vector<BatchPair> last_batch;
 };
 
 namespace {
@@ -202,6 +217,40 @@ int fail_hip(elas_handle* h, const char* what, hipError_t e) {
     hipError_t e_ = (expr);                              \
     if (e_ != hipSuccess) return fail_hip(h, #expr, e_); \
   } while (0)
+
+// The handle's failure report word (allocated once, when a device exists).
+int ensure_fail_word(elas_handle* h) {
+  if (h->fail_host) return ELAS_OK;
+  void* p = nullptr;
+  hipError_t e = hipHostMalloc(&p, 64, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess)
+    return fail(h, ELAS_ERR_OOM, std::string("hipHostMalloc of the report word: ") +
+                                     hipGetErrorString(e));
+  void* d = nullptr;
+  e = hipHostGetDevicePointer(&d, p, 0);
+  if (e != hipSuccess) {
+    (void)hipHostFree(p);
+    return fail_hip(h, "hipHostGetDevicePointer of the report word", e);
+  }
+  h->fail_host = static_cast<int32_t*>(p);
+  h->fail_dev = static_cast<int32_t*>(d);
+  __atomic_store_n(h->fail_host, 0, __ATOMIC_RELAXED);
+  return ELAS_OK;
+}
+
+// Reports (once) a device-mesh failure of an earlier frame on this handle
+// whose kernel has finished: ELAS_ERR_INTERNAL, else ELAS_OK.
+int take_mesh_failure(elas_handle* h) {
+  if (!h->fail_host) return ELAS_OK;
+  const int32_t st = __atomic_load_n(h->fail_host, __ATOMIC_ACQUIRE);
+  if (st == 0) return ELAS_OK;
+  __atomic_store_n(h->fail_host, 0, __ATOMIC_RELAXED);
+  return fail(h, ELAS_ERR_INTERNAL,
+              std::string("the device mesh of an earlier frame on this handle failed (status ") +
+                  std::to_string(st) +
+                  (st == 1 ? ", flip rounds exhausted" : ", consistency check") +
+                  "); that frame's maps were computed without plane priors");
+}
 
 void free_buffers(Buffers* b) {
   if (!b) return;
@@ -309,65 +358,59 @@ BufLayout buffer_layout(const elas_params& p, int32_t w, int32_t hp) {
   return L;
 }
 
+// Points every device array of b at its offset in a block laid out as Lo.
+void carve_buffers(const BufLayout& Lo, const elas_params& p, uint8_t* base, Buffers* b) {
+  b->g = Lo.g;
+  b->ntmax = Lo.ntmax;
+  auto at = [&](size_t o) { return static_cast<void*>(base + o); };
+  b->descL = static_cast<uint8_t*>(at(Lo.descL));
+  b->descR = static_cast<uint8_t*>(at(Lo.descR));
+  b->desc_bytes = Lo.desc_bytes;
+  b->csup_bytes = Lo.csup_bytes;
+  b->csupL = Lo.csup_bytes ? static_cast<uint4*>(at(Lo.csL)) : nullptr;
+  b->csupR = Lo.csup_bytes ? static_cast<uint4*>(at(Lo.csR)) : nullptr;
+  b->chkL = p.median_window > 1 ? static_cast<int16_t*>(at(Lo.chL)) : nullptr;
+  b->chkR = p.median_window > 1 ? static_cast<int16_t*>(at(Lo.chR)) : nullptr;
+  b->dcan_raw = static_cast<int16_t*>(at(Lo.raw0));
+  b->dcan_incon = static_cast<int16_t*>(at(Lo.inc));
+  b->dcan_vert = static_cast<int16_t*>(at(Lo.vert));
+  b->dcan_final = static_cast<int16_t*>(at(Lo.fin));
+  b->evals = static_cast<int32_t*>(at(Lo.evals));
+  b->gridL = static_cast<uint32_t*>(at(Lo.gL));
+  b->gridR = static_cast<uint32_t*>(at(Lo.gR));
+  b->ownerL = static_cast<int32_t*>(at(Lo.oL));
+  b->ownerR = static_cast<int32_t*>(at(Lo.oR));
+  b->dplaneL = static_cast<int16_t*>(at(Lo.dpL));
+  b->dplaneR = static_cast<int16_t*>(at(Lo.dpR));
+  b->rawL = static_cast<int16_t*>(at(Lo.rL));
+  b->rawR = static_cast<int16_t*>(at(Lo.rR));
+  b->lut = static_cast<int32_t*>(at(Lo.lut));
+  b->dense_counts = static_cast<int32_t*>(at(Lo.cnt));
+  b->rowsL = static_cast<int32_t*>(at(Lo.rowsL));
+  b->rowsR = static_cast<int32_t*>(at(Lo.rowsR));
+  b->cnt = static_cast<int32_t*>(at(Lo.rc));
+  b->hdr = static_cast<MeshHeader*>(at(Lo.hdr));
+  b->ptsL = static_cast<int32_t*>(at(Lo.pL));
+  b->ptsR = static_cast<int32_t*>(at(Lo.pR));
+  b->recsL = static_cast<int32_t*>(at(Lo.recL));
+  b->recsR = static_cast<int32_t*>(at(Lo.recR));
+  b->planesL = static_cast<float*>(at(Lo.plL));
+  b->planesR = static_cast<float*>(at(Lo.plR));
+  b->tris = static_cast<RasterTri*>(at(Lo.tris));
+  b->mesh_scratch = static_cast<char*>(at(Lo.ms));
+}
+
 int alloc_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
   Buffers* b = new Buffers();
   const BufLayout Lo = buffer_layout(h->params, w, hp);
-  b->g = Lo.g;
-  const Geometry& g = b->g;
   const size_t nlat = Lo.nlat, nrows = Lo.nrows;
-  b->ntmax = Lo.ntmax;
-  const size_t off = Lo.total;
-  const size_t o_descL = Lo.descL, o_descR = Lo.descR, o_raw0 = Lo.raw0, o_inc = Lo.inc,
-               o_vert = Lo.vert, o_fin = Lo.fin, o_evals = Lo.evals, o_gL = Lo.gL, o_gR = Lo.gR,
-               o_oL = Lo.oL, o_oR = Lo.oR, o_dpL = Lo.dpL, o_dpR = Lo.dpR, o_rL = Lo.rL,
-               o_rR = Lo.rR, o_lut = Lo.lut, o_cnt = Lo.cnt, o_rowsL = Lo.rowsL,
-               o_rowsR = Lo.rowsR, o_rc = Lo.rc, o_hdr = Lo.hdr, o_pL = Lo.pL, o_pR = Lo.pR,
-               o_recL = Lo.recL, o_recR = Lo.recR, o_plL = Lo.plL, o_plR = Lo.plR,
-               o_tris = Lo.tris, o_ms = Lo.ms;
-  (void)g;
-  hipError_t e = hipMalloc(&b->dev_block, off);
+  hipError_t e = hipMalloc(&b->dev_block, Lo.total);
   if (e != hipSuccess) {
     delete b;
     return fail(h, ELAS_ERR_OOM,
                 std::string("hipMalloc of device buffers: ") + hipGetErrorString(e));
   }
-  uint8_t* base = static_cast<uint8_t*>(b->dev_block);
-  auto at = [&](size_t o) { return static_cast<void*>(base + o); };
-  b->descL = static_cast<uint8_t*>(at(o_descL));
-  b->descR = static_cast<uint8_t*>(at(o_descR));
-  b->desc_bytes = Lo.desc_bytes;
-  b->csup_bytes = Lo.csup_bytes;
-  b->csupL = Lo.csup_bytes ? static_cast<uint4*>(at(Lo.csL)) : nullptr;
-  b->csupR = Lo.csup_bytes ? static_cast<uint4*>(at(Lo.csR)) : nullptr;
-  b->chkL = h->params.median_window > 1 ? static_cast<int16_t*>(at(Lo.chL)) : nullptr;
-  b->chkR = h->params.median_window > 1 ? static_cast<int16_t*>(at(Lo.chR)) : nullptr;
-  b->dcan_raw = static_cast<int16_t*>(at(o_raw0));
-  b->dcan_incon = static_cast<int16_t*>(at(o_inc));
-  b->dcan_vert = static_cast<int16_t*>(at(o_vert));
-  b->dcan_final = static_cast<int16_t*>(at(o_fin));
-  b->evals = static_cast<int32_t*>(at(o_evals));
-  b->gridL = static_cast<uint32_t*>(at(o_gL));
-  b->gridR = static_cast<uint32_t*>(at(o_gR));
-  b->ownerL = static_cast<int32_t*>(at(o_oL));
-  b->ownerR = static_cast<int32_t*>(at(o_oR));
-  b->dplaneL = static_cast<int16_t*>(at(o_dpL));
-  b->dplaneR = static_cast<int16_t*>(at(o_dpR));
-  b->rawL = static_cast<int16_t*>(at(o_rL));
-  b->rawR = static_cast<int16_t*>(at(o_rR));
-  b->lut = static_cast<int32_t*>(at(o_lut));
-  b->dense_counts = static_cast<int32_t*>(at(o_cnt));
-  b->rowsL = static_cast<int32_t*>(at(o_rowsL));
-  b->rowsR = static_cast<int32_t*>(at(o_rowsR));
-  b->cnt = static_cast<int32_t*>(at(o_rc));
-  b->hdr = static_cast<MeshHeader*>(at(o_hdr));
-  b->ptsL = static_cast<int32_t*>(at(o_pL));
-  b->ptsR = static_cast<int32_t*>(at(o_pR));
-  b->recsL = static_cast<int32_t*>(at(o_recL));
-  b->recsR = static_cast<int32_t*>(at(o_recR));
-  b->planesL = static_cast<float*>(at(o_plL));
-  b->planesR = static_cast<float*>(at(o_plR));
-  b->tris = static_cast<RasterTri*>(at(o_tris));
-  b->mesh_scratch = static_cast<char*>(at(o_ms));
+  carve_buffers(Lo, h->params, static_cast<uint8_t*>(b->dev_block), b);
   // host-mapped per-row lists for the host mesh mode
   const size_t hcount = 3 * nrows + 2 * nlat;
   e = hipHostMalloc(&b->host_block, hcount * sizeof(int32_t), hipHostMallocMapped);
@@ -492,6 +535,7 @@ Frame make_frame(const elas_handle* h, const Buffers* b, const uint8_t* left,
   f.dense_counts = b->dense_counts;
   f.outL = outL;
   f.outR = outR;
+  f.mfail = h->fail_dev;
   return f;
 }
 
@@ -741,6 +785,18 @@ int elas_create(const elas_params* p, elas_handle** out) {
   k.redundancy = p->redundancy;
   k.subsample = p->support_subsample;
   k.median = p->median_window > 1 ? p->median_window : 0;
+  k.mesh_max_rounds = kMeshMaxRounds;
+  // the failure report word, when a device is present (no device: no call
+  // on this handle can reach a kernel anyway)
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+    const int rc = ensure_fail_word(h);
+    if (rc != ELAS_OK) {
+      g_create_error = h->err;
+      delete h;
+      return rc;
+    }
+  }
   h->meshL = mesh_scratch_create();
   h->meshR = mesh_scratch_create();
   *out = h;
@@ -772,6 +828,7 @@ int elas_destroy(elas_handle* h) {
       if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->bev) (void)hipEventDestroy(e);
   delete h->worker;
+  if (h->fail_host) (void)hipHostFree(h->fail_host);
   mesh_scratch_destroy(h->meshL);
   mesh_scratch_destroy(h->meshR);
   delete h;
@@ -785,12 +842,25 @@ const char* elas_last_error(const elas_handle* h) {
 int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int32_t w,
                  int32_t hp, int32_t stride, hipStream_t stream, int16_t* disp_left,
                  int16_t* disp_right) {
+  return elas::process_one(h, left, right, w, hp, stride, stream, disp_left, disp_right,
+                           nullptr);
+}
+
+}  // extern "C"
+
+int elas::process_one(elas_handle* h, const uint8_t* left, const uint8_t* right, int32_t w,
+                      int32_t hp, int32_t stride, hipStream_t stream, int16_t* disp_left,
+                      int16_t* disp_right, int32_t* report) {
   if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
   if (!left || !right || !disp_left || !disp_right)
     return fail(h, ELAS_ERR_ARG, "null image or output pointer");
   if (w < 9 || hp < 9 || w > 8192 || hp > 8192)
     return fail(h, ELAS_ERR_ARG, "image size must be 9..8192 in each dimension");
   if (stride < w) return fail(h, ELAS_ERR_ARG, "stride must be >= width");
+  int rc0 = take_mesh_failure(h);
+  if (rc0 != ELAS_OK) return rc0;
+  rc0 = ensure_fail_word(h);
+  if (rc0 != ELAS_OK) return rc0;
   const bool on_host =
       h->params.mesh_on_host != 0 || w > kDeviceMeshMaxSide || hp > kDeviceMeshMaxSide;
   if (on_host && !h->ev_lists) {
@@ -814,7 +884,8 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
       for (hipEvent_t& e : pr) HIP_TRY(hipEventCreate(&e));
   for (bool& u : h->kev_used) u = false;
 
-  const Frame F = make_frame(h, b, left, right, stride, disp_left, disp_right, on_host);
+  Frame F = make_frame(h, b, left, right, stride, disp_left, disp_right, on_host);
+  if (report) F.mfail = report;
   const std::pair<int, int> var = variants_for(h, w, hp);
   // one stage; while timing, kernel k records its start/stop events
   auto run = [&](int k, int32_t stage, int variant) -> hipError_t {
@@ -846,8 +917,6 @@ int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right, int3
   h->have_result = true;
   return ELAS_OK;
 }
-
-}  // extern "C"
 
 namespace {
 
@@ -996,6 +1065,13 @@ int elas_set_batch_flags(elas_handle* h, int32_t flags) {
 }
 
 int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStream_t stream) {
+  return elas::process_batch(h, n, pairs, stream, nullptr);
+}
+
+}  // extern "C"
+
+int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStream_t stream,
+                        int32_t* const* reports) {
   if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
   if (n < 0 || (n > 0 && !pairs)) return fail(h, ELAS_ERR_ARG, "bad pair array");
   for (int32_t i = 0; i < n; ++i) {
@@ -1005,16 +1081,22 @@ int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStr
     if (q.w < 9 || q.h < 9 || q.w > 8192 || q.h > 8192 || q.stride < q.w)
       return fail(h, ELAS_ERR_ARG, "bad size or stride in pair " + std::to_string(i));
   }
+  int rc0 = take_mesh_failure(h);
+  if (rc0 != ELAS_OK) return rc0;
+  rc0 = ensure_fail_word(h);
+  if (rc0 != ELAS_OK) return rc0;
   // pairs the device mesh cannot take go through single calls (host mesh)
+  h->last_batch.assign(n, elas_handle::BatchPair{nullptr, nullptr, stream, false});
   std::vector<int32_t> dev_idx;
   for (int32_t i = 0; i < n; ++i) {
     const elas_pair& q = pairs[i];
     elas_handle* ph = q.params ? q.params : h;
     if (ph->params.mesh_on_host || q.w > kDeviceMeshMaxSide || q.h > kDeviceMeshMaxSide) {
-      const int rc = elas_process(ph, q.left, q.right, q.w, q.h, q.stride, stream, q.disp_left,
-                                  q.disp_right);
+      const int rc = process_one(ph, q.left, q.right, q.w, q.h, q.stride, stream, q.disp_left,
+                                 q.disp_right, reports ? reports[i] : h->fail_dev);
       if (rc != ELAS_OK) return fail(h, rc, std::string("pair ") + std::to_string(i) + ": " +
                                                 elas_last_error(ph));
+      h->last_batch[i] = elas_handle::BatchPair{ph, ph->last, stream, ph->last_on_host};
     } else {
       dev_idx.push_back(i);
     }
@@ -1032,6 +1114,9 @@ int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStr
     if (rc != ELAS_OK) return fail(h, rc, elas_last_error(ph));
     frames.push_back(make_frame(ph, b, q.left, q.right, q.stride, q.disp_left, q.disp_right,
                                 false));
+    // a failing device mesh reports on the calling handle (or the pair's word)
+    frames.back().mfail = reports ? reports[i] : h->fail_dev;
+    h->last_batch[i] = elas_handle::BatchPair{ph, b, stream, false};
     var.push_back(variants_lookup(h, q.w, q.h, ph->kp.D, true));
   }
   BatchCtx* c = nullptr;
@@ -1130,6 +1215,8 @@ int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStr
   return ELAS_OK;
 }
 
+extern "C" {
+
 int elas_frame_bytes(elas_handle* h, int32_t w, int32_t hp, int64_t* bytes) {
   if (!h || !bytes) return fail(h, ELAS_ERR_ARG, "null argument");
   if (w < 9 || hp < 9 || w > 8192 || hp > 8192)
@@ -1152,6 +1239,13 @@ int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t hp, int32_t* desc
 }  // extern "C"
 
 extern "C" {
+
+int elas_set_mesh_round_limit(elas_handle* h, int32_t rounds) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  if (rounds < 1) return fail(h, ELAS_ERR_ARG, "round limit must be >= 1");
+  h->kp.mesh_max_rounds = std::min(rounds, kMeshMaxRounds);
+  return ELAS_OK;
+}
 
 int elas_set_timing(elas_handle* h, int32_t enable) {
   if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
@@ -1221,8 +1315,12 @@ int elas_get_stats(elas_handle* h, elas_stats* out) {
                     hipMemcpyDeviceToHost));
   int64_t cnt = 0;
   for (int32_t c : counts) cnt += c;
+  rc = take_mesh_failure(h);
   if (hd.status[0] || hd.status[1])
-    return fail(h, ELAS_ERR_INTERNAL, "device mesh did not converge");
+    return fail(h, ELAS_ERR_INTERNAL,
+                std::string("the device mesh of the last frame failed (status ") +
+                    std::to_string(std::max(hd.status[0], hd.status[1])) + ")");
+  if (rc != ELAS_OK) return rc;
   out->support_evals = hd.support_evals;
   out->dense_evals = cnt;
   out->n_support_left = hd.n[0];
@@ -1233,42 +1331,49 @@ int elas_get_stats(elas_handle* h, elas_stats* out) {
   return ELAS_OK;
 }
 
-int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t bytes,
-                          int64_t* needed) {
-  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
-  if (!h->have_result) return fail(h, ELAS_ERR_ARG, "no completed call");
-  Buffers* b = h->last;
+}  // extern "C"
+
+namespace {
+
+// One intermediate of a frame computed with ph's parameters in buffers b on
+// `stream` (errors are reported on h). For a host-meshed frame the lists,
+// triangles and planes are ph's host copies of its last call.
+int read_intermediate(elas_handle* h, elas_handle* ph, Buffers* b, hipStream_t stream,
+                      bool hm, int32_t which, void* dst, int64_t bytes, int64_t* needed) {
   const Geometry& g = b->g;
   MeshHeader hd;
-  int rc = last_header(h, &hd);
-  if (rc != ELAS_OK) return rc;
-  const bool hm = h->last_on_host;
+  if (hm) {
+    hd = ph->hhdr;
+  } else {
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMemcpy(&hd, b->hdr, sizeof(MeshHeader), hipMemcpyDeviceToHost));
+  }
   const int64_t npx = (int64_t)g.w * g.h, nlat = (int64_t)g.lw * g.lh;
   const void* dsrc = nullptr;
   const void* hsrc = nullptr;
   int64_t size = 0;
   switch (which) {
     case ELAS_I_DESC_LEFT:
-      if (h->params.descriptor) return fail(h, ELAS_ERR_ARG, "census mode has no gradient descriptors");
+      if (ph->params.descriptor) return fail(h, ELAS_ERR_ARG, "census mode has no gradient descriptors");
       dsrc = b->descL; size = npx * 16; break;
     case ELAS_I_DESC_RIGHT:
-      if (h->params.descriptor) return fail(h, ELAS_ERR_ARG, "census mode has no gradient descriptors");
+      if (ph->params.descriptor) return fail(h, ELAS_ERR_ARG, "census mode has no gradient descriptors");
       dsrc = b->descR; size = npx * 16; break;
     case ELAS_I_CENSUS_DENSE_LEFT:
     case ELAS_I_CENSUS_DENSE_RIGHT:
-      if (!h->params.descriptor) return fail(h, ELAS_ERR_ARG, "not in census mode");
+      if (!ph->params.descriptor) return fail(h, ELAS_ERR_ARG, "not in census mode");
       dsrc = which == ELAS_I_CENSUS_DENSE_LEFT ? b->descL : b->descR;
       size = npx * 8;
       break;
     case ELAS_I_CENSUS_SUPPORT_LEFT:
     case ELAS_I_CENSUS_SUPPORT_RIGHT:
-      if (!h->params.descriptor) return fail(h, ELAS_ERR_ARG, "not in census mode");
+      if (!ph->params.descriptor) return fail(h, ELAS_ERR_ARG, "not in census mode");
       dsrc = which == ELAS_I_CENSUS_SUPPORT_LEFT ? (const void*)b->csupL : (const void*)b->csupR;
       size = (int64_t)b->csup_bytes;
       break;
     case ELAS_I_CHECKED_LEFT:
     case ELAS_I_CHECKED_RIGHT:
-      if (h->params.median_window <= 1) return fail(h, ELAS_ERR_ARG, "no median filter set");
+      if (ph->params.median_window <= 1) return fail(h, ELAS_ERR_ARG, "no median filter set");
       dsrc = which == ELAS_I_CHECKED_LEFT ? b->chkL : b->chkR;
       size = npx * 2;
       break;
@@ -1278,28 +1383,28 @@ int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t byte
     case ELAS_I_DCAN_FINAL: dsrc = b->dcan_final; size = nlat * 2; break;
     case ELAS_I_SUPPORT_LEFT:
       size = (int64_t)hd.n[0] * 12;
-      if (hm) hsrc = h->ptsL.data(); else dsrc = b->ptsL;
+      if (hm) hsrc = ph->ptsL.data(); else dsrc = b->ptsL;
       break;
     case ELAS_I_SUPPORT_RIGHT:
       size = (int64_t)hd.n[1] * 12;
-      if (hm) hsrc = h->ptsR.data(); else dsrc = b->ptsR;
+      if (hm) hsrc = ph->ptsR.data(); else dsrc = b->ptsR;
       break;
     case ELAS_I_CORNERS: hsrc = hd.corners; size = 32; break;
     case ELAS_I_TRI_LEFT:
       size = (int64_t)hd.ntri[0] * 36;
-      if (hm) hsrc = h->recsL.data(); else dsrc = b->recsL;
+      if (hm) hsrc = ph->recsL.data(); else dsrc = b->recsL;
       break;
     case ELAS_I_TRI_RIGHT:
       size = (int64_t)hd.ntri[1] * 36;
-      if (hm) hsrc = h->recsR.data(); else dsrc = b->recsR;
+      if (hm) hsrc = ph->recsR.data(); else dsrc = b->recsR;
       break;
     case ELAS_I_PLANE_LEFT:
       size = (int64_t)hd.ntri[0] * 12;
-      if (hm) hsrc = h->planesL.data(); else dsrc = b->planesL;
+      if (hm) hsrc = ph->planesL.data(); else dsrc = b->planesL;
       break;
     case ELAS_I_PLANE_RIGHT:
       size = (int64_t)hd.ntri[1] * 12;
-      if (hm) hsrc = h->planesR.data(); else dsrc = b->planesR;
+      if (hm) hsrc = ph->planesR.data(); else dsrc = b->planesR;
       break;
     case ELAS_I_OWNER_LEFT: dsrc = b->ownerL; size = npx * 4; break;
     case ELAS_I_OWNER_RIGHT: dsrc = b->ownerR; size = npx * 4; break;
@@ -1309,7 +1414,7 @@ int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t byte
     case ELAS_I_GRID_RIGHT: dsrc = b->gridR; size = (int64_t)g.gw * g.gh * g.gwords * 4; break;
     case ELAS_I_RAW_LEFT: dsrc = b->rawL; size = npx * 2; break;
     case ELAS_I_RAW_RIGHT: dsrc = b->rawR; size = npx * 2; break;
-    case ELAS_I_LUT: hsrc = h->lut.data(); size = (int64_t)h->lut.size() * 4; break;
+    case ELAS_I_LUT: hsrc = ph->lut.data(); size = (int64_t)ph->lut.size() * 4; break;
     default: return fail(h, ELAS_ERR_ARG, "unknown intermediate");
   }
   if (needed) *needed = size;
@@ -1320,10 +1425,33 @@ int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t byte
     std::memcpy(dst, hsrc, (size_t)size);
     return ELAS_OK;
   }
-  HIP_TRY(hipStreamSynchronize(h->last_stream));
+  HIP_TRY(hipStreamSynchronize(stream));
   HIP_TRY(hipMemcpy(dst, dsrc, (size_t)size, hipMemcpyDeviceToHost));
   return ELAS_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int elas_get_intermediate(elas_handle* h, int32_t which, void* dst, int64_t bytes,
+                          int64_t* needed) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  if (!h->have_result) return fail(h, ELAS_ERR_ARG, "no completed call");
+  return read_intermediate(h, h, h->last, h->last_stream, h->last_on_host, which, dst, bytes,
+                           needed);
+}
+
+int elas_get_batch_intermediate(elas_handle* h, int32_t pair, int32_t which, void* dst,
+                                int64_t bytes, int64_t* needed) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  if (pair < 0 || pair >= (int32_t)h->last_batch.size())
+    return fail(h, ELAS_ERR_ARG, "no such pair in the last batch");
+  const elas_handle::BatchPair& q = h->last_batch[pair];
+  if (!q.b) return fail(h, ELAS_ERR_ARG, "the pair did not complete");
+  return read_intermediate(h, q.ph, q.b, q.stream, q.on_host, which, dst, bytes, needed);
+}
+
 
 int elas_triangulate(const int32_t* pts, int32_t n, const int32_t* corners, int32_t w,
                      int32_t h, int32_t* recs_out, float* planes_out) {

@@ -15,6 +15,9 @@ constexpr int kMeshLdsBytes = 160 * 1024 - 2048;  // dynamic LDS of one mesh wor
 // packs a point into a 32-bit key with 12-bit coordinates, and its fp64
 // in-circle test is exact only for coordinates below 2^12.
 constexpr int kDeviceMeshMaxSide = 4096;
+// Flip rounds a device mesh view may take before it reports failure; far
+// above what any frame needs (17 at 640x480), so it only binds when lowered.
+constexpr int kMeshMaxRounds = 32000;
 
 // Image, lattice and grid geometry of one (w, h) for one parameter set.
 struct Geometry {
@@ -45,6 +48,8 @@ struct KParams {
   int32_t redundancy;   // 0: two-sided; 1: past-only
   int32_t subsample;    // keep every k-th support point
   int32_t median;       // 0: no median; 3 or 5: median window
+  int32_t mesh_max_rounds;  // flip rounds before the device mesh gives up (a test
+                            // hook lowers it; the default never binds)
 };
 
 // One triangle as the raster and dense kernels read it: integer vertices in
@@ -128,6 +133,8 @@ struct Frame {
   int16_t* outR;
   int16_t* chkL;         // median mode: checked maps before the median
   int16_t* chkR;
+  int32_t* mfail;        // pinned host word the device mesh sets (to its nonzero
+                         // status) when a view fails; null: the header only
 };
 
 // Pointers read from the frame table are rebuilt as offsets from the table's
@@ -177,6 +184,7 @@ __device__ __forceinline__ Frame global_frame(const Frame& t, const char* base) 
   F.outR = rebase(base, F.outR);
   F.chkL = rebase(base, F.chkL);
   F.chkR = rebase(base, F.chkR);
+  F.mfail = rebase(base, F.mfail);
   return F;
 }
 
@@ -231,4 +239,18 @@ size_t mesh_global_scratch_per_view(const Geometry& g);
 // Blocks of the dense launch (one candidate-count entry per block).
 int32_t dense_blocks(const Geometry& g);
 
+}  // namespace elas
+
+// ---- entry points behind the C-ABI (elas_api.hip), for the server ---------
+// elas_process / elas_process_batch with the device mesh's failure report
+// going to the given pinned, device-mapped words (one per pair) instead of
+// the handle's.
+struct elas_handle;
+struct elas_pair;
+namespace elas {
+int process_one(elas_handle* h, const uint8_t* left, const uint8_t* right, int32_t w,
+                int32_t hp, int32_t stride, hipStream_t stream, int16_t* disp_left,
+                int16_t* disp_right, int32_t* report);
+int process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStream_t stream,
+                  int32_t* const* reports);
 }  // namespace elas

@@ -56,7 +56,6 @@ namespace elas {
 namespace {
 
 constexpr int kMT = 1024;          // threads per mesh workgroup
-constexpr int kMaxRounds = 32000;  // flip rounds before a view reports status 1
 constexpr int kPocketG = 4;        // lanes per side pocket point
 constexpr int kTwinUnknown = -2;   // neighbour code of a half-edge not yet matched
 
@@ -493,11 +492,15 @@ __device__ __forceinline__ int rank_of(const uint32_t* pk, int np, uint32_t s) {
   return lo;
 }
 
+// A view that fails leaves no triangles, so raster and dense run without a
+// plane prior; the failure is recorded in the header and, when the frame has
+// one, in its pinned host report word, which the host turns into an error.
 template <typename I>
-__device__ void mesh_fail(MeshHeader* hdr, int view, int status) {
+__device__ void mesh_fail(MeshHeader* hdr, int32_t* mfail, int view, int status) {
   if (threadIdx.x == 0) {
     hdr->status[view] = status;
     hdr->ntri[view] = 0;
+    if (mfail) __hip_atomic_store(mfail, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -569,9 +572,9 @@ __device__ __forceinline__ void relink_edge(int x, int k, int r, int NT, const u
 template <typename I>
 __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__ rows,
                          const int32_t* __restrict__ cnt_view, int c_first, int n, int tri_base,
-                         const Geometry& g, int dmin, MeshHeader* hdr, int view,
-                         int32_t* out_pts, int32_t* out_recs, float* out_planes,
-                         RasterTri* out_tris, MeshShared& sh) {
+                         const Geometry& g, int dmin, MeshHeader* hdr, int32_t* mfail,
+                         int max_rounds, int view, int32_t* out_pts, int32_t* out_recs,
+                         float* out_planes, RasterTri* out_tris, MeshShared& sh) {
   typedef typename ClaimT<I>::T C;
   const int tid = threadIdx.x;
   MeshMem<I> M;
@@ -704,7 +707,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   if (tid == 0 && strip_tris + 2 * m != NT) sh.err = 2;
   __syncthreads();
   if (sh.err) {
-    mesh_fail<I>(hdr, view, 2);
+    mesh_fail<I>(hdr, mfail, view, 2);
     return;
   }
 
@@ -766,7 +769,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
   }
   __syncthreads();
   if (sh.border != 4) {  // only the four image sides lack a twin
-    mesh_fail<I>(hdr, view, 2);
+    mesh_fail<I>(hdr, mfail, view, 2);
     return;
   }
   // vertex keys (over the buckets, which are no longer needed)
@@ -820,8 +823,8 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
     I* const cl_cur = cur ? cl1 : cl0;
     I* const cl_nxt = cur ? cl0 : cl1;
     const int nc = sh.ncand[cur];
-    if (sh.err || (nc > 0 && r >= kMaxRounds)) {
-      mesh_fail<I>(hdr, view, sh.err ? sh.err : 1);
+    if (sh.err || (nc > 0 && r >= max_rounds)) {
+      mesh_fail<I>(hdr, mfail, view, sh.err ? sh.err : 1);
       return;
     }
     if (nc == 0) break;
@@ -1038,14 +1041,16 @@ __device__ __forceinline__ void mesh_body(const Frame& F, int view) {
   int32_t* recs = view ? F.recsR : F.recsL;
   float* planes = view ? F.planesR : F.planesL;
   const int dmin = F.p.dmin;
+  int32_t* const mfail = F.mfail;
+  const int max_rounds = min(F.p.mesh_max_rounds, kMeshMaxRounds);
   MeshMem<int16_t> probe;
   if (2 * n + 2 < 8192 && carve<int16_t>(nullptr, n, g.lh, probe) <= (size_t)kMeshLdsBytes)
-    mesh_run<int16_t>(smem, rows, cnt + view * g.lh, c_first, n, tri_base, g, dmin, hdr, view,
-                      pts, recs, planes, F.tris, sh);
+    mesh_run<int16_t>(smem, rows, cnt + view * g.lh, c_first, n, tri_base, g, dmin, hdr, mfail,
+                      max_rounds, view, pts, recs, planes, F.tris, sh);
   else
     mesh_run<int32_t>(F.mesh_scratch + view * F.mesh_scratch_per_view, rows,
-                      cnt + view * g.lh, c_first, n, tri_base, g, dmin, hdr, view, pts, recs,
-                      planes, F.tris, sh);
+                      cnt + view * g.lh, c_first, n, tri_base, g, dmin, hdr, mfail, max_rounds,
+                      view, pts, recs, planes, F.tris, sh);
 }
 
 __global__ __launch_bounds__(kMT) void k_mesh(Frame F) { mesh_body(F, blockIdx.x); }

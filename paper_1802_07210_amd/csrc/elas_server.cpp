@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "elas.h"
+#include "elas_internal.h"
 
 namespace {
 
@@ -35,6 +36,7 @@ struct Request {
   int64_t ticket;
   elas_pair pair;
   int64_t bytes;
+  hipEvent_t ready;  // recorded on the producer's stream at submission, or null
 };
 
 struct Result {
@@ -49,6 +51,11 @@ struct Slot {
   bool busy = false;
   std::vector<int64_t> tickets;
   int64_t bytes = 0;
+  // one pinned, device-mapped failure report word per pair of the batch: the
+  // device mesh of a failing pair sets its word (cleared before each launch)
+  int32_t* report_host = nullptr;
+  int32_t* report_dev = nullptr;
+  std::vector<int32_t*> report_ptrs;
 };
 
 }  // namespace
@@ -65,6 +72,7 @@ struct elas_server {
   std::map<std::tuple<elas_handle*, int32_t, int32_t>, int64_t> footprint;
   int64_t next_ticket = 1;
   int64_t in_flight = 0;
+  std::vector<hipEvent_t> free_events;  // ready events not in use
   elas_server_stats stats{};
   bool stop = false;
   std::string err;
@@ -86,11 +94,21 @@ int server_fail(elas_server* s, int code, const std::string& msg) {
 }
 
 void finish(elas_server* S, Slot& sl, State st, int code, Clock::time_point now) {
-  for (int64_t t : sl.tickets) {
-    auto it = S->results.find(t);
+  for (size_t i = 0; i < sl.tickets.size(); ++i) {
+    auto it = S->results.find(sl.tickets[i]);
     if (it == S->results.end()) continue;
-    it->second.state = st;
-    it->second.code = code;
+    // a pair whose device mesh failed was matched without plane priors
+    const int32_t rep =
+        st == State::Done ? __atomic_load_n(&sl.report_host[i], __ATOMIC_ACQUIRE) : 0;
+    if (rep != 0) {
+      S->err = "the device mesh of ticket " + std::to_string(sl.tickets[i]) +
+               " failed (status " + std::to_string(rep) + ")";
+      it->second.state = State::Failed;
+      it->second.code = ELAS_ERR_INTERNAL;
+    } else {
+      it->second.state = st;
+      it->second.code = code;
+    }
     it->second.finished = now;
   }
   S->stats.completed += (int64_t)sl.tickets.size();
@@ -126,15 +144,19 @@ void worker_loop(elas_server* S) {
       const int maxb = S->cfg.plain ? 1 : S->cfg.max_batch;
       std::vector<elas_pair> pairs;
       std::vector<int64_t> tickets;
+      std::vector<hipEvent_t> ready;
       int64_t bytes = 0;
       while (!S->queue.empty() && (int)pairs.size() < maxb &&
              S->in_flight + bytes + S->queue.front().bytes <= S->cfg.memory_budget) {
         pairs.push_back(S->queue.front().pair);
         tickets.push_back(S->queue.front().ticket);
+        ready.push_back(S->queue.front().ready);
         bytes += S->queue.front().bytes;
         S->queue.pop_front();
       }
       if (pairs.empty()) break;  // the oldest request waits for memory
+      for (size_t i = 0; i < pairs.size(); ++i)
+        __atomic_store_n(&sl.report_host[i], 0, __ATOMIC_RELAXED);
       sl.busy = true;
       sl.tickets = tickets;
       sl.bytes = bytes;
@@ -143,18 +165,34 @@ void worker_loop(elas_server* S) {
       S->stats.batches += 1;
       S->stats.batched_pairs += (int64_t)pairs.size();
       lk.unlock();
-      int rc;
-      if (S->cfg.plain) {
+      // the batch waits for the streams that produced its inputs
+      hipError_t we = hipSuccess;
+      for (hipEvent_t ev : ready)
+        if (ev && we == hipSuccess) we = hipStreamWaitEvent(sl.stream, ev, 0);
+      int rc = we == hipSuccess ? ELAS_OK : ELAS_ERR_HIP;
+      if (rc != ELAS_OK) {
+      } else if (S->cfg.plain) {
         const elas_pair& q = pairs[0];
-        rc = elas_process(q.params ? q.params : S->h, q.left, q.right, q.w, q.h, q.stride,
-                          sl.stream, q.disp_left, q.disp_right);
+        rc = elas::process_one(q.params ? q.params : S->h, q.left, q.right, q.w, q.h, q.stride,
+                               sl.stream, q.disp_left, q.disp_right, sl.report_ptrs[0]);
       } else {
-        rc = elas_process_batch(S->h, (int32_t)pairs.size(), pairs.data(), sl.stream);
+        rc = elas::process_batch(S->h, (int32_t)pairs.size(), pairs.data(), sl.stream,
+                                 sl.report_ptrs.data());
       }
       const hipError_t re = rc == ELAS_OK ? hipEventRecord(sl.done, sl.stream) : hipSuccess;
       lk.lock();
+      // the waits are enqueued: the events can be recorded again
+      for (hipEvent_t ev : ready)
+        if (ev) S->free_events.push_back(ev);
+      if (we != hipSuccess) {
+        S->err = std::string("hipStreamWaitEvent: ") + hipGetErrorString(we);
+        finish(S, sl, State::Failed, ELAS_ERR_HIP, Clock::now());
+        S->done.notify_all();
+        continue;
+      }
       if (rc != ELAS_OK || re != hipSuccess) {
-        S->err = rc != ELAS_OK ? std::string(elas_last_error(S->h))
+        elas_handle* eh = S->cfg.plain && pairs[0].params ? pairs[0].params : S->h;
+        S->err = rc != ELAS_OK ? std::string(elas_last_error(eh))
                                : std::string("hipEventRecord: ") + hipGetErrorString(re);
         finish(S, sl, State::Failed, rc != ELAS_OK ? rc : ELAS_ERR_HIP, Clock::now());
         S->done.notify_all();
@@ -193,16 +231,31 @@ int elas_server_create(elas_handle* h, const elas_server_config* cfg, elas_serve
   S->h = h;
   S->cfg = *cfg;
   S->slots.resize(cfg->plain ? 1 : cfg->max_inflight);
+  const int nrep = cfg->plain ? 1 : cfg->max_batch;
   for (Slot& sl : S->slots) {
     hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    void* rh = nullptr;
+    if (e == hipSuccess)
+      e = hipHostMalloc(&rh, sizeof(int32_t) * nrep, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+      sl.report_host = static_cast<int32_t*>(rh);
+      void* rd = nullptr;
+      e = hipHostGetDevicePointer(&rd, rh, 0);
+      sl.report_dev = static_cast<int32_t*>(rd);
+    }
     if (e != hipSuccess) {
       for (Slot& x : S->slots) {
         if (x.done) (void)hipEventDestroy(x.done);
         if (x.stream) (void)hipStreamDestroy(x.stream);
+        if (x.report_host) (void)hipHostFree(x.report_host);
       }
       delete S;
       return server_fail(nullptr, ELAS_ERR_HIP, std::string("stream setup: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < nrep; ++i) {
+      sl.report_host[i] = 0;
+      sl.report_ptrs.push_back(sl.report_dev + i);
     }
   }
   S->worker = std::thread(worker_loop, S);
@@ -210,7 +263,14 @@ int elas_server_create(elas_handle* h, const elas_server_config* cfg, elas_serve
   return ELAS_OK;
 }
 
-int elas_server_submit(elas_server* s, const elas_pair* pair, int64_t* ticket) {
+}  // extern "C"
+
+namespace {
+
+// ordered: the pair waits on the device for the work enqueued on `producer`
+// (the null stream when producer is null) at submission
+int submit_pair(elas_server* s, const elas_pair* pair, bool ordered, hipStream_t producer,
+                int64_t* ticket) {
   if (!s || !pair || !ticket) return server_fail(s, ELAS_ERR_ARG, "null argument");
   if (!pair->left || !pair->right || !pair->disp_left || !pair->disp_right || pair->w < 9 ||
       pair->h < 9 || pair->w > 8192 || pair->h > 8192 || pair->stride < pair->w)
@@ -237,15 +297,47 @@ int elas_server_submit(elas_server* s, const elas_pair* pair, int64_t* ticket) {
     s->err = "server is shutting down";
     return ELAS_ERR_ARG;
   }
+  hipEvent_t ready = nullptr;
+  if (ordered) {  // order the pair after the work already on the producer's stream
+    if (!s->free_events.empty()) {
+      ready = s->free_events.back();
+      s->free_events.pop_back();
+    } else {
+      const hipError_t e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        s->err = std::string("hipEventCreate: ") + hipGetErrorString(e);
+        return ELAS_ERR_HIP;
+      }
+    }
+    const hipError_t e = hipEventRecord(ready, producer);
+    if (e != hipSuccess) {
+      s->free_events.push_back(ready);
+      s->err = std::string("hipEventRecord on the producer stream: ") + hipGetErrorString(e);
+      return ELAS_ERR_HIP;
+    }
+  }
   const int64_t t = s->next_ticket++;
   Result r;
   r.submitted = Clock::now();
   s->results.emplace(t, r);
-  s->queue.push_back(Request{t, *pair, bytes});
+  s->queue.push_back(Request{t, *pair, bytes, ready});
   s->stats.submitted += 1;
   *ticket = t;
   s->work.notify_one();
   return ELAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int elas_server_submit(elas_server* s, const elas_pair* pair, int64_t* ticket) {
+  return submit_pair(s, pair, false, nullptr, ticket);
+}
+
+int elas_server_submit_on(elas_server* s, const elas_pair* pair, hipStream_t producer,
+                          int64_t* ticket) {
+  return submit_pair(s, pair, true, producer, ticket);
 }
 
 static int take_result(elas_server* s, std::unordered_map<int64_t, Result>::iterator it,
@@ -316,7 +408,9 @@ int elas_server_destroy(elas_server* s) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.report_host) (void)hipHostFree(sl.report_host);
   }
+  for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
   delete s;
   return ELAS_OK;
 }

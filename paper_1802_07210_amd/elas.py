@@ -24,7 +24,9 @@ EXPORTS = ("elas_params_default", "elas_create", "elas_destroy", "elas_process",
            "elas_set_timing", "elas_get_timing", "elas_set_batch_flags", "elas_process_batch",
            "elas_get_tuned_variants", "elas_frame_bytes", "elas_server_config_default",
            "elas_server_create", "elas_server_submit", "elas_server_wait", "elas_server_poll",
-           "elas_server_get_stats", "elas_server_last_error", "elas_server_destroy")
+           "elas_server_get_stats", "elas_server_last_error", "elas_server_destroy",
+           "elas_server_submit_on", "elas_set_mesh_round_limit",
+           "elas_get_batch_intermediate")
 
 BATCH_GRAPH = 1
 BATCH_AUTOTUNE = 2
@@ -140,6 +142,11 @@ def lib() -> C.CDLL:
         L.elas_server_config_default.restype = None
         L.elas_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
         L.elas_server_submit.argtypes = [vp, C.POINTER(ElasPair), C.POINTER(C.c_int64)]
+        L.elas_server_submit_on.argtypes = [vp, C.POINTER(ElasPair), vp,
+                                            C.POINTER(C.c_int64)]
+        L.elas_set_mesh_round_limit.argtypes = [vp, C.c_int32]
+        L.elas_get_batch_intermediate.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int64,
+                                                  C.POINTER(C.c_int64)]
         L.elas_server_wait.argtypes = [vp, C.c_int64, C.POINTER(C.c_double)]
         L.elas_server_poll.argtypes = [vp, C.c_int64, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_double)]
@@ -295,6 +302,11 @@ class Elas:
         _check(lib().elas_get_stats(self._h, C.byref(st)), self._h)
         return {k: getattr(st, k) for k, _ in ElasStats._fields_}
 
+    def set_mesh_round_limit(self, rounds: int):
+        """Test hook: caps the device mesh's flip rounds (a frame that needs
+        more fails, reported as ELAS_ERR_INTERNAL by the next call)."""
+        _check(lib().elas_set_mesh_round_limit(self._h, int(rounds)), self._h)
+
     def set_timing(self, enable: bool):
         _check(lib().elas_set_timing(self._h, int(bool(enable))), self._h)
 
@@ -310,6 +322,19 @@ class Elas:
         nbytes = int(need.value)
         buf = np.zeros(max(nbytes, 1), np.uint8)
         _check(lib().elas_get_intermediate(self._h, which, _np_ptr(buf), nbytes, None), self._h)
+        return buf[:nbytes].view(dtype).copy()
+
+    def batch_intermediate(self, pair: int, name: str) -> np.ndarray:
+        """Stage `name` of pair `pair` of this handle's last batched call."""
+        which, dtype = INTERMEDIATES[name]
+        need = C.c_int64(0)
+        L = lib()
+        _check(L.elas_get_batch_intermediate(self._h, pair, which, None, 0, C.byref(need)),
+               self._h)
+        nbytes = int(need.value)
+        buf = np.zeros(max(nbytes, 1), np.uint8)
+        _check(L.elas_get_batch_intermediate(self._h, pair, which, _np_ptr(buf), nbytes, None),
+               self._h)
         return buf[:nbytes].view(dtype).copy()
 
 
@@ -353,10 +378,18 @@ class Server:
             raise ElasError(f"{ERRORS.get(rc, rc)}: {msg.decode() if msg else ''}")
         return rc
 
-    def submit(self, left, right, out_left, out_right, params: "Elas" = None) -> int:
+    def submit(self, left, right, out_left, out_right, params: "Elas" = None,
+               stream=None) -> int:
+        """Queues a pair; it runs after the work already on `stream` (default:
+        torch's current stream, which wrote the tensors)."""
+        import torch
         pr = _pair_of(left, right, out_left, out_right, params)
+        if stream is None:
+            stream = torch.cuda.current_stream(left.device)
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         t = C.c_int64()
-        self._check(lib().elas_server_submit(self._s, C.byref(pr), C.byref(t)))
+        self._check(lib().elas_server_submit_on(self._s, C.byref(pr), C.c_void_p(s),
+                                                C.byref(t)))
         self._keep[t.value] = (left, right, out_left, out_right)
         return t.value
 

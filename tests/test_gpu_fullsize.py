@@ -1,0 +1,192 @@
+"""Parity at full size, in the configurations that are timed and served:
+
+* all 96 pairs of the mixed-resolution batch (320x240 D=64, 640x480 D=128,
+  1242x375 D=256, 1280x720 D=192; pair i from seed i, its shape drawn by a
+  SplitMix64 stream seeded 0) in ONE batched call with graph capture and
+  autotuning on, then again with the tuned tile variants from the captured
+  graph; every map of every pair equals the oracle's;
+* the benchmark's timed step exactly (8 pairs 640x480 D=128, seeds 0..7, one
+  batched call with the default batch tile variants on a non-default
+  stream), compared stage by stage: descriptors, the four lattice stages,
+  lists, corners, triangles, planes, owners, prior maps, grid vectors, raw
+  and final maps;
+* a server fed by 16 cameras of the four full shapes (camera j at shape
+  j mod 4), pairs arriving while others run; every result equals the
+  oracle's.
+
+The oracle runs on a thread pool (the C oracle keeps no global state and
+ctypes releases the interpreter lock during each call)."""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+WORKERS = 12
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_07210_amd as pkg
+    return pkg
+
+
+def pmap(f, xs):
+    with ThreadPoolExecutor(WORKERS) as ex:
+        return list(ex.map(f, xs))
+
+
+def oracle_maps(item):
+    pair, D = item
+    t = ref.process(ref.params(disp_max=D - 1), pair.left, pair.right)
+    return t.outL, t.outR
+
+
+def test_batch_96_mixed_pairs_one_call(E):
+    names = synth.batch_shapes(96, 0)
+    cfgs = [synth.SHAPES[nm].with_seed(i) for i, nm in enumerate(names)]
+    pairs = pmap(synth.make_pair, cfgs)
+    print(f"96-pair batch: {dict((n, names.count(n)) for n in sorted(set(names)))}", flush=True)
+    dev = torch.device("cuda:0")
+    hs = {D: E.Elas(disp_max=D - 1) for D in sorted({c.disp_range for c in cfgs})}
+    base = hs[128]
+    base.set_batch_flags(graph=True, autotune=True)
+    items, outs = [], []
+    for p, c in zip(pairs, cfgs):
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        oL = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        oR = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        items.append((L, R, oL, oR, hs[c.disp_range]))
+        outs.append((oL, oR))
+    torch.cuda.synchronize()
+    expected = pmap(oracle_maps, [(p, c.disp_range) for p, c in zip(pairs, cfgs)])
+    # first call: default variants, then the autotuner's pass (same results);
+    # second call: the tuned variants, captured into a new graph
+    for rep in range(2):
+        for oL, oR in outs:
+            oL.fill_(-7)
+            oR.fill_(-7)
+        torch.cuda.synchronize()
+        base.process_batch(items)
+        torch.cuda.synchronize()
+        bad = []
+        for i, ((oL, oR), (eL, eR)) in enumerate(zip(outs, expected)):
+            nL = int((oL.cpu().numpy() != eL).sum())
+            nR = int((oR.cpu().numpy() != eR).sum())
+            if nL or nR:
+                bad.append((i, names[i], nL, nR))
+        assert bad == [], f"call {rep}: pairs differing from the oracle {bad}"
+        print(f"96-pair batch call {rep}: 0 mismatches", flush=True)
+    for nm in sorted(set(names)):
+        c = synth.SHAPES[nm]
+        if c.disp_range == 128:
+            rows, kb = base.tuned_variants(c.width, c.height)
+            assert rows in (4, 8, 16) and kb in (1, 2, 4)
+
+
+def stage_mismatches(get, t):
+    """(stage, mismatching elements) for every stage of one pair that differs
+    from the oracle trace t; get(name) reads the GPU's stage."""
+    h, w = t.outL.shape
+    lh, lw = t.dcan_raw.shape
+    bad = []
+
+    def chk(name, got, exp):
+        got, exp = np.asarray(got), np.asarray(exp)
+        if got.shape != exp.shape:
+            bad.append((name, f"shape {got.shape} vs {exp.shape}"))
+            return
+        n = int(np.count_nonzero(got != exp))
+        if n:
+            bad.append((name, n))
+
+    chk("desc_left", get("desc_left").reshape(h, w, 16), t.descL)
+    chk("desc_right", get("desc_right").reshape(h, w, 16), t.descR)
+    for nm, arr in (("dcan_raw", t.dcan_raw), ("dcan_incon", t.dcan_incon),
+                    ("dcan_vert", t.dcan_vert), ("dcan_final", t.dcan_final)):
+        chk(nm, get(nm).reshape(lh, lw), arr)
+    chk("support_left", get("support_left").reshape(-1, 3), t.ptsL)
+    chk("support_right", get("support_right").reshape(-1, 3), t.ptsR)
+    chk("corners", get("corners"), np.concatenate([t.cornersL, t.cornersR]))
+    chk("tri_left", get("tri_left").reshape(-1, 9), t.recL)
+    chk("tri_right", get("tri_right").reshape(-1, 9), t.recR)
+    chk("plane_left", get("plane_left").reshape(-1, 3).view(np.uint32), t.planeL.view(np.uint32))
+    chk("plane_right", get("plane_right").reshape(-1, 3).view(np.uint32),
+        t.planeR.view(np.uint32))
+    for side, own in (("left", t.ownerL), ("right", t.ownerR)):
+        got = get(f"owner_{side}").reshape(h, w)
+        chk(f"owner_{side}", np.where(got == 0x7FFFFFFF, -1, got), own)
+    chk("dplane_left", get("dplane_left").reshape(h, w), t.dplaneL)
+    chk("dplane_right", get("dplane_right").reshape(h, w), t.dplaneR)
+    chk("grid_left", get("grid_left").reshape(t.gridL.shape), t.gridL)
+    chk("grid_right", get("grid_right").reshape(t.gridR.shape), t.gridR)
+    chk("raw_left", get("raw_left").reshape(h, w), t.rawL)
+    chk("raw_right", get("raw_right").reshape(h, w), t.rawR)
+    chk("lut", get("lut"), t.lut)
+    return bad
+
+
+def test_bench_step_stage_by_stage(E):
+    cfgs = [synth.VGA.with_seed(i) for i in range(8)]
+    pairs = pmap(synth.make_pair, cfgs)
+    dev = torch.device("cuda:0")
+    e = E.Elas(disp_max=127)
+    e.set_batch_flags(graph=True, autotune=False)   # the bench's default batch variants
+    stream = torch.cuda.Stream(device=dev)
+    items, outs = [], []
+    for p in pairs:
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        oL = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        oR = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        items.append((L, R, oL, oR))
+        outs.append((oL, oR))
+    torch.cuda.synchronize()
+    traces = pmap(lambda p: ref.process(ref.params(disp_max=127), p.left, p.right), pairs)
+    for rep in range(2):   # the first call captures the graph, the second replays it
+        e.process_batch(items, stream=stream)
+        stream.synchronize()
+        for i, (t, (oL, oR)) in enumerate(zip(traces, outs)):
+            bad = stage_mismatches(lambda nm, i=i: e.batch_intermediate(i, nm), t)
+            assert bad == [], f"call {rep}, pair {i}: {bad}"
+            assert np.array_equal(oL.cpu().numpy(), t.outL), (rep, i)
+            assert np.array_equal(oR.cpu().numpy(), t.outR), (rep, i)
+            assert (t.outL >= 0).mean() > 0.4
+        print(f"bench step call {rep}: 8 pairs, every stage equal", flush=True)
+
+
+def test_server_full_shapes_16_cameras(E):
+    names = list(synth.SHAPES)
+    dev = torch.device("cuda:0")
+    cams = [(j, synth.SHAPES[names[j % 4]].with_seed(1000 * j)) for j in range(16)]
+    cams += [(j, synth.SHAPES[names[j % 4]].with_seed(1000 * j + 1)) for j in range(16)]
+    pairs = pmap(lambda jc: synth.make_pair(jc[1]), cams)
+    hs = {c.disp_range: E.Elas(disp_max=c.disp_range - 1) for _, c in cams}
+    srv = E.Server(E.Elas(disp_max=127), max_batch=8, max_inflight=3)
+    reqs = []
+    for (j, c), p in zip(cams, pairs):
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        oL = torch.full(p.left.shape, -9, dtype=torch.int16, device=dev)
+        oR = torch.full(p.left.shape, -9, dtype=torch.int16, device=dev)
+        reqs.append((p, c.disp_range, oL, oR, srv.submit(L, R, oL, oR, hs[c.disp_range])))
+    lat = [srv.wait(t) for *_, t in reqs]
+    assert all(x >= 0 for x in lat)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["batched_pairs"] == len(reqs)
+    srv.close()
+    expected = pmap(oracle_maps, [(p, D) for p, D, *_ in reqs])
+    for k, ((p, D, oL, oR, _), (eL, eR)) in enumerate(zip(reqs, expected)):
+        assert np.array_equal(oL.cpu().numpy(), eL), (k, p.left.shape)
+        assert np.array_equal(oR.cpu().numpy(), eR), (k, p.left.shape)
+    print(f"server: {len(reqs)} full-size pairs in {st['batches']} batches, 0 mismatches",
+          flush=True)
