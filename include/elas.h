@@ -26,7 +26,7 @@
  * maps differ from the reference pipeline) is reported as ELAS_ERR_INTERNAL:
  * the failing kernel sets a pinned report word of the calling handle, and the
  * first later call on that handle (elas_process, elas_process_batch,
- * elas_get_stats) returns the error, once, without
+ * elas_process_noalloc, elas_get_stats) returns the error, once, without
  * doing its own work. elas_get_stats synchronises first, so it always
  * reports a failure of the last call. A server fails the tickets of the
  * affected pairs instead.
@@ -183,6 +183,27 @@ ELAS_API int elas_destroy(elas_handle* h);
 ELAS_API int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* right,
                           int32_t w, int32_t h_px, int32_t stride, hipStream_t stream,
                           int16_t* disp_left, int16_t* disp_right);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): elas_process without any
+ * allocation. Same arguments, results and stream ordering as elas_process
+ * (bit-identical maps). Every device buffer of the frame lives in one
+ * library-owned device array of 160 MiB per GPU (held until the process
+ * ends), so the frame's footprint, elas_frame_bytes, must be at most
+ * 167772160 bytes (every workload shape fits: 1280x720 at D = 192 needs
+ * about 62 MiB): ELAS_ERR_ARG otherwise. The call makes no hipMalloc, hipFree
+ * or other allocating call, no memset and no copy: the prior table is
+ * written by a kernel from its argument, so the call enqueues kernels only.
+ * The stream must belong to the current device (ELAS_ERR_ARG otherwise).
+ * Device mesh only: ELAS_ERR_UNSUPPORTED with mesh_on_host or a side above
+ * 4096, or for a handle created without a device. All calls on one GPU share
+ * that GPU's array, which keeps the last call's contents (elas_get_stats and
+ * elas_get_intermediate read them): calls that overlap on one GPU (other
+ * streams, other handles, other host threads) race; order them. Timing is
+ * not recorded. */
+ELAS_API int elas_process_noalloc(elas_handle* h, const uint8_t* left, const uint8_t* right,
+                                  int32_t w, int32_t h_px, int32_t stride, hipStream_t stream,
+                                  int16_t* disp_left, int16_t* disp_right);
 
 /* One stereo pair of a batch (all pointers device memory, caller-owned). */
 typedef struct elas_pair {

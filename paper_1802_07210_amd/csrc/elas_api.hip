@@ -196,6 +196,9 @@ struct elas_handle {
     bool on_host;
   };
   std::vector<BatchPair> last_batch;
+  // the buffers of the last elas_process_noalloc call (pointers into the
+  // device's scratch array; nothing is owned)
+  Buffers noalloc_view;
 };
 
 namespace {
@@ -917,6 +920,106 @@ int elas::process_one(elas_handle* h, const uint8_t* left, const uint8_t* right,
   h->have_result = true;
   return ELAS_OK;
 }
+
+// ---- the entry point that allocates nothing ---------------------------------
+// Every device buffer of one frame lives in this file-scope array, one copy
+// per GPU, held until the process ends. In host code its name is only a
+// stand-in: host code uses the address hipGetSymbolAddress returns for the
+// current device, looked up once per device.
+constexpr size_t kNoAllocBytes = (size_t)160 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on device dev (the current device).
+int scratch_for_device(elas_handle* h, int dev, uint8_t** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(h, ELAS_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(h, "hipGetSymbolAddress of the scratch array", e);
+    if (!p) return fail(h, ELAS_ERR_HIP, "hipGetSymbolAddress returned no address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<uint8_t*>(g_scratch_ptr[dev]);
+  return ELAS_OK;
+}
+
+// The prior table, written into device memory from a kernel argument (no
+// copy node, so a captured call stays a chain of kernels).
+struct LutArg {
+  int32_t v[kMaxD];
+};
+
+__global__ __launch_bounds__(kMaxD) void k_write_lut(LutArg a, int32_t* dst, int n) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = a.v[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+int elas_process_noalloc(elas_handle* h, const uint8_t* left, const uint8_t* right, int32_t w,
+                         int32_t hp, int32_t stride, hipStream_t stream, int16_t* disp_left,
+                         int16_t* disp_right) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  if (!left || !right || !disp_left || !disp_right)
+    return fail(h, ELAS_ERR_ARG, "null image or output pointer");
+  if (w < 9 || hp < 9 || w > 8192 || hp > 8192)
+    return fail(h, ELAS_ERR_ARG, "image size must be 9..8192 in each dimension");
+  if (stride < w) return fail(h, ELAS_ERR_ARG, "stride must be >= width");
+  if (h->params.mesh_on_host || w > kDeviceMeshMaxSide || hp > kDeviceMeshMaxSide)
+    return fail(h, ELAS_ERR_UNSUPPORTED,
+                "the no-allocation path meshes on the device only (no mesh_on_host, sides "
+                "up to 4096)");
+  if (!h->fail_host) return fail(h, ELAS_ERR_UNSUPPORTED, "handle created without a device");
+  const BufLayout Lo = buffer_layout(h->params, w, hp);
+  if (Lo.total > kNoAllocBytes)
+    return fail(h, ELAS_ERR_ARG,
+                "frame needs " + std::to_string(Lo.total) + " bytes of scratch, the limit is " +
+                    std::to_string(kNoAllocBytes));
+  int rc = take_mesh_failure(h);
+  if (rc != ELAS_OK) return rc;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (stream) {
+    hipDevice_t sdev = 0;
+    HIP_TRY(hipStreamGetDevice(stream, &sdev));
+    if (sdev != dev) return fail(h, ELAS_ERR_ARG, "the stream belongs to another device");
+  }
+  uint8_t* base = nullptr;
+  rc = scratch_for_device(h, dev, &base);
+  if (rc != ELAS_OK) return rc;
+  Buffers& b = h->noalloc_view;
+  b = Buffers{};
+  carve_buffers(Lo, h->params, base, &b);
+  h->have_result = false;
+  h->have_timing = false;
+  h->have_batch_timing = false;
+  LutArg la{};
+  for (int32_t i = 0; i < h->kp.D; ++i) la.v[i] = h->lut[i];
+  hipLaunchKernelGGL(k_write_lut, dim3(1), dim3(kMaxD), 0, stream, la, b.lut, h->kp.D);
+  HIP_TRY(hipGetLastError());
+  const Frame F = make_frame(h, &b, left, right, stride, disp_left, disp_right, false);
+  const std::pair<int, int> var = variants_for(h, w, hp);
+  for (int32_t st = 0; st < kStageCount; ++st) {
+    const int v = st == kStageDescriptor ? var.first : (st == kStageDense ? var.second : 0);
+    HIP_TRY(launch_stage(st, F, v, stream));
+  }
+  h->last = &b;
+  h->last_stream = stream;
+  h->last_on_host = false;
+  h->have_result = true;
+  return ELAS_OK;
+}
+
+}  // extern "C"
 
 namespace {
 

@@ -26,7 +26,7 @@ EXPORTS = ("elas_params_default", "elas_create", "elas_destroy", "elas_process",
            "elas_server_create", "elas_server_submit", "elas_server_wait", "elas_server_poll",
            "elas_server_get_stats", "elas_server_last_error", "elas_server_destroy",
            "elas_server_submit_on", "elas_set_mesh_round_limit",
-           "elas_get_batch_intermediate")
+           "elas_get_batch_intermediate", "elas_process_noalloc")
 
 BATCH_GRAPH = 1
 BATCH_AUTOTUNE = 2
@@ -126,6 +126,8 @@ def lib() -> C.CDLL:
         L.elas_create.argtypes = [C.POINTER(ElasParams), C.POINTER(vp)]
         L.elas_destroy.argtypes = [vp]
         L.elas_process.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+        L.elas_process_noalloc.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp,
+                                           vp, vp]
         L.elas_get_stats.argtypes = [vp, C.POINTER(ElasStats)]
         L.elas_last_error.argtypes = [vp]
         L.elas_last_error.restype = C.c_char_p
