@@ -222,8 +222,8 @@ enum elas_batch_flags {
                                    once and replay it */
   ELAS_BATCH_AUTOTUNE = 2       /* on the first batch with a new (w, h, D), time the
                                    descriptor (4/8/16 rows per block) and dense (1/2/4
-                                   grid candidates per batch) variants on its frames and
-                                   keep the fastest; results are identical for all */
+                                   rows per block) variants on its frames and keep the
+                                   fastest; results are identical for all */
 };
 ELAS_API int elas_set_batch_flags(elas_handle* h, int32_t flags);
 
@@ -248,10 +248,17 @@ ELAS_API int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pair
                                 hipStream_t stream);
 
 /* Tile variants the autotuner chose for (w, h) at this handle's disparity
- * count: descriptor rows per block and dense grid candidates per batch.
+ * count: descriptor rows per block and dense rows per block.
  * ELAS_ERR_ARG if none has been chosen yet. */
 ELAS_API int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t h_px,
-                                     int32_t* desc_rows, int32_t* dense_batch);
+                                     int32_t* desc_rows, int32_t* dense_rows);
+
+/* Fixes the tile variants of (w, h) at this handle's disparity count, as the
+ * autotuner would (descriptor rows per block 4, 8 or 16; dense rows per
+ * block 1, 2 or 4); used by single and batched calls, and the autotuner then
+ * leaves that size alone. Results do not depend on the variants. */
+ELAS_API int elas_set_tile_variants(elas_handle* h, int32_t w, int32_t h_px, int32_t desc_rows,
+                                    int32_t dense_rows);
 
 /* Device bytes of the buffers one pair of size (w, h_px) needs with h's
  * parameters (descriptors, lattice, grid, mesh, maps); what a server admits

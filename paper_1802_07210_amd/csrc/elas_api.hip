@@ -103,6 +103,7 @@ struct Buffers {
           *dcan_final = nullptr;
   int32_t* evals = nullptr;
   uint32_t *gridL = nullptr, *gridR = nullptr;
+  int32_t *grangeL = nullptr, *grangeR = nullptr;
   int32_t *ownerL = nullptr, *ownerR = nullptr;
   int16_t *dplaneL = nullptr, *dplaneR = nullptr, *rawL = nullptr, *rawR = nullptr;
   int32_t* lut = nullptr;
@@ -196,6 +197,7 @@ struct elas_handle {
     bool on_host;
   };
   std::vector<BatchPair> last_batch;
+  int last_dense_variant = 0;  // dense tile variant of the last single call
   // the buffers of the last elas_process_noalloc call (pointers into the
   // device's scratch array; nothing is owned)
   Buffers noalloc_view;
@@ -282,6 +284,7 @@ Geometry make_geometry(const elas_params& p, int32_t w, int32_t h) {
   // 8 x 8 filter tiles while every tile of the frame can have a CU of its
   // own, else 16 x 16 (fewer halo positions per tile)
   g.ftile = ((g.lw + 7) / 8) * ((g.lh + 7) / 8) <= 256 ? 8 : 16;
+  g.gdiv = (uint32_t)(((1ull << 31) + (uint64_t)p.grid_size - 1) / (uint64_t)p.grid_size);
   return g;
 }
 
@@ -290,7 +293,8 @@ struct BufLayout {
   Geometry g{};
   size_t nlat = 0, nrows = 0;
   int32_t ntmax = 0;
-  size_t descL, descR, csL, csR, raw0, inc, vert, fin, evals, gL, gR, oL, oR, dpL, dpR, rL, rR,
+  size_t descL, descR, csL, csR, raw0, inc, vert, fin, evals, gL, gR, grL, grR, oL, oR, dpL,
+      dpR, rL, rR,
       lut, cnt, rowsL, rowsR, rc, hdr, pL, pR, recL, recR, plL, plR, tris, ms, chL, chR;
   size_t desc_bytes = 0, csup_bytes = 0;
   size_t total = 0;
@@ -332,6 +336,8 @@ BufLayout buffer_layout(const elas_params& p, int32_t w, int32_t hp) {
   L.evals = take(nlat * 4);
   L.gL = take(ngrid * 4 + 8);
   L.gR = take(ngrid * 4 + 8);
+  L.grL = take((size_t)g.gw * g.gh * 8);
+  L.grR = take((size_t)g.gw * g.gh * 8);
   L.oL = take(npx * 4);
   L.oR = take(npx * 4);
   L.dpL = take(npx * 2);
@@ -339,7 +345,7 @@ BufLayout buffer_layout(const elas_params& p, int32_t w, int32_t hp) {
   L.rL = take(npx * 2);
   L.rR = take(npx * 2);
   L.lut = take(kMaxD * 4);
-  L.cnt = take((size_t)dense_blocks(g) * 4);
+  L.cnt = take((size_t)dense_blocks_max(g) * 4);
   L.rowsL = take(nlat * 4);
   L.rowsR = take(nlat * 4);
   L.rc = take(3 * nrows * 4);
@@ -381,6 +387,8 @@ void carve_buffers(const BufLayout& Lo, const elas_params& p, uint8_t* base, Buf
   b->evals = static_cast<int32_t*>(at(Lo.evals));
   b->gridL = static_cast<uint32_t*>(at(Lo.gL));
   b->gridR = static_cast<uint32_t*>(at(Lo.gR));
+  b->grangeL = static_cast<int32_t*>(at(Lo.grL));
+  b->grangeR = static_cast<int32_t*>(at(Lo.grR));
   b->ownerL = static_cast<int32_t*>(at(Lo.oL));
   b->ownerR = static_cast<int32_t*>(at(Lo.oR));
   b->dplaneL = static_cast<int16_t*>(at(Lo.dpL));
@@ -476,17 +484,24 @@ int pool_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, size
 // Tile variants (descriptor, dense) for a frame size and disparity count:
 // the autotuner's choice, else the defaults.
 std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp, int32_t D,
-                                    bool batched = false) {
+                                    bool batched = false, bool census = false) {
+  std::pair<int, int> v;
   auto it = h->tuned.find(std::make_tuple(w, hp, D));
-  if (it != h->tuned.end()) return it->second;
-  // untuned: 8 descriptor rows per block and 2 dense candidates per step; in
-  // batches, whose many blocks fill the chip anyway, 16 rows (a smaller halo
-  // share) and 1 candidate per step, both measured faster there
-  return std::make_pair(batched ? 2 : 1, batched ? 0 : 1);
+  if (it != h->tuned.end()) {
+    v = it->second;
+  } else {
+    // untuned: 8 descriptor rows per block and 2 dense rows per block; in
+    // batches, whose many blocks fill the chip anyway, 16 descriptor rows (a
+    // smaller halo share)
+    v = std::make_pair(batched ? 2 : 1, 1);
+  }
+  // the pipelined dense kernel takes Sobel frames only
+  if (v.second == kDensePipe && census) v.second = 1;
+  return v;
 }
 
 std::pair<int, int> variants_for(const elas_handle* h, int32_t w, int32_t hp) {
-  return variants_lookup(h, w, hp, h->kp.D);
+  return variants_lookup(h, w, hp, h->kp.D, false, h->kp.descriptor != 0);
 }
 
 Frame make_frame(const elas_handle* h, const Buffers* b, const uint8_t* left,
@@ -512,6 +527,8 @@ Frame make_frame(const elas_handle* h, const Buffers* b, const uint8_t* left,
   f.evals = b->evals;
   f.gridL = b->gridL;
   f.gridR = b->gridR;
+  f.grangeL = b->grangeL;
+  f.grangeR = b->grangeR;
   f.rowsL = host_lists ? b->hrowL_dev : b->rowsL;
   f.rowsR = host_lists ? b->hrowR_dev : b->rowsR;
   f.cnt = host_lists ? b->hcnt_dev : b->cnt;
@@ -890,6 +907,7 @@ int elas::process_one(elas_handle* h, const uint8_t* left, const uint8_t* right,
   Frame F = make_frame(h, b, left, right, stride, disp_left, disp_right, on_host);
   if (report) F.mfail = report;
   const std::pair<int, int> var = variants_for(h, w, hp);
+  h->last_dense_variant = var.second;
   // one stage; while timing, kernel k records its start/stop events
   auto run = [&](int k, int32_t stage, int variant) -> hipError_t {
     if (!timed) return launch_stage(stage, F, variant, stream);
@@ -1008,6 +1026,7 @@ int elas_process_noalloc(elas_handle* h, const uint8_t* left, const uint8_t* rig
   HIP_TRY(hipGetLastError());
   const Frame F = make_frame(h, &b, left, right, stride, disp_left, disp_right, false);
   const std::pair<int, int> var = variants_for(h, w, hp);
+  h->last_dense_variant = var.second;
   for (int32_t st = 0; st < kStageCount; ++st) {
     const int v = st == kStageDescriptor ? var.first : (st == kStageDense ? var.second : 0);
     HIP_TRY(launch_stage(st, F, v, stream));
@@ -1060,14 +1079,15 @@ void plan_batch(const std::vector<Frame>& frames, const std::vector<std::pair<in
   const size_t main_table = put(frames.data(), frames.size() * sizeof(Frame));
   for (int32_t st = 0; st < kStageCount; ++st) {
     const bool tiled = st == kStageDescriptor || st == kStageDense;
-    for (int v = 0; v < (tiled ? 3 : 1); ++v) {
+    const int nvar = st == kStageDescriptor ? kDescVariants : (st == kStageDense ? kDenseVariants : 1);
+    for (int v = 0; v < nvar; ++v) {
       std::vector<Frame> sub;
       std::vector<int32_t> starts(1, 0);
       size_t lds = 0;
       for (size_t i = 0; i < frames.size(); ++i) {
         const int fv = st == kStageDescriptor ? var[i].first : var[i].second;
         if (tiled && fv != v) continue;
-        const int dv = st == kStageDescriptor ? v : 0;
+        const int dv = tiled ? v : 0;
         sub.push_back(frames[i]);
         starts.push_back(starts.back() + stage_blocks(st, frames[i].g, frames[i].p, dv));
         lds = std::max(lds, stage_lds(st, frames[i].g, frames[i].p));
@@ -1119,12 +1139,15 @@ int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
   HIP_TRY(hipEventCreate(&e1));
   int choice[2] = {0, 1};
   const int32_t stages[2] = {kStageDescriptor, kStageDense};
+  bool census = false;
+  for (const Frame& f : frames) census |= f.p.descriptor != 0;
   for (int k = 0; k < 2; ++k) {
     float best_ms = 1e30f;
-    for (int v = 0; v < 3; ++v) {
+    const int nvar = k == 0 ? kDescVariants : (census ? kDenseVariants - 1 : kDenseVariants);  // no pipelined variant for census
+    for (int v = 0; v < nvar; ++v) {
       std::vector<int32_t> starts(1, 0);
       for (const Frame& f : frames)
-        starts.push_back(starts.back() + stage_blocks(stages[k], f.g, f.p, k == 0 ? v : 0));
+        starts.push_back(starts.back() + stage_blocks(stages[k], f.g, f.p, v));
       uint8_t* dev = static_cast<uint8_t*>(c->tune_dev);
       const size_t soff = align256(frames.size() * sizeof(Frame));
       HIP_TRY(hipMemcpy(dev, frames.data(), frames.size() * sizeof(Frame), hipMemcpyHostToDevice));
@@ -1220,7 +1243,7 @@ int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipSt
     // a failing device mesh reports on the calling handle (or the pair's word)
     frames.back().mfail = reports ? reports[i] : h->fail_dev;
     h->last_batch[i] = elas_handle::BatchPair{ph, b, stream, false};
-    var.push_back(variants_lookup(h, q.w, q.h, ph->kp.D, true));
+    var.push_back(variants_lookup(h, q.w, q.h, ph->kp.D, true, ph->kp.descriptor != 0));
   }
   BatchCtx* c = nullptr;
   int rc = batch_ctx(h, stream, &c);
@@ -1328,12 +1351,28 @@ int elas_frame_bytes(elas_handle* h, int32_t w, int32_t hp, int64_t* bytes) {
   return ELAS_OK;
 }
 
+int elas_set_tile_variants(elas_handle* h, int32_t w, int32_t hp, int32_t desc_rows,
+                           int32_t dense_rows) {
+  if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
+  static const int32_t drows[3] = {4, 8, 16}, nrows[4] = {1, 2, 4, 0};
+  int dv = -1, nv = -1;
+  for (int k = 0; k < 4; ++k) {
+    if (k < 3 && drows[k] == desc_rows) dv = k;
+    if (nrows[k] == dense_rows) nv = k;
+  }
+  if (dv < 0 || nv < 0 || w < 9 || hp < 9)
+    return fail(h, ELAS_ERR_ARG,
+                "descriptor rows must be 4, 8 or 16 and dense rows 1, 2, 4 or 0 (pipelined bands)");
+  h->tuned[std::make_tuple(w, hp, h->kp.D)] = std::make_pair(dv, nv);
+  return ELAS_OK;
+}
+
 int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t hp, int32_t* desc_rows,
                             int32_t* dense_batch) {
   if (!h || !desc_rows || !dense_batch) return fail(h, ELAS_ERR_ARG, "null argument");
   auto it = h->tuned.find(std::make_tuple(w, hp, h->kp.D));
   if (it == h->tuned.end()) return fail(h, ELAS_ERR_ARG, "no tuned variants for this size");
-  static const int32_t rows[3] = {4, 8, 16}, batch[3] = {1, 2, 4};
+  static const int32_t rows[3] = {4, 8, 16}, batch[4] = {1, 2, 4, 0};  // descriptor / dense rows
   *desc_rows = rows[it->second.first];
   *dense_batch = batch[it->second.second];
   return ELAS_OK;
@@ -1413,7 +1452,7 @@ int elas_get_stats(elas_handle* h, elas_stats* out) {
   int rc = last_header(h, &hd);
   if (rc != ELAS_OK) return rc;
   HIP_TRY(hipStreamSynchronize(h->last_stream));
-  std::vector<int32_t> counts(dense_blocks(h->last->g));
+  std::vector<int32_t> counts(dense_blocks(h->last->g, h->last_dense_variant));
   HIP_TRY(hipMemcpy(counts.data(), h->last->dense_counts, counts.size() * sizeof(int32_t),
                     hipMemcpyDeviceToHost));
   int64_t cnt = 0;

@@ -28,6 +28,8 @@ struct Geometry {
   int32_t gw, gh;     // grid-vector regions
   int32_t gwords;     // 32-bit words per region mask (even: 64-bit aligned masks)
   int32_t ftile;      // support-filter tile side in lattice points (8 or 16)
+  uint32_t gdiv;      // ceil(2^31 / grid_size): x / grid_size = umulhi(2x, gdiv)
+                      // exactly for 0 <= x < 2^31 / grid_size
 };
 
 // Parameters as the kernels consume them (passed by value).
@@ -108,6 +110,8 @@ struct Frame {
   int32_t* evals;
   uint32_t* gridL;
   uint32_t* gridR;
+  int32_t* grangeL;      // per grid region: smallest and largest set bit of its mask
+  int32_t* grangeR;      // (0x7FFF and -1 while empty), [gh][gw][2]
   int32_t* rowsL;        // per-row lists [lh][lw], packed u | d << 16
   int32_t* rowsR;
   int32_t* cnt;          // left counts, right counts, evaluation counts [3][lh]
@@ -160,6 +164,8 @@ __device__ __forceinline__ Frame global_frame(const Frame& t, const char* base) 
   F.evals = rebase(base, F.evals);
   F.gridL = rebase(base, F.gridL);
   F.gridR = rebase(base, F.gridR);
+  F.grangeL = rebase(base, F.grangeL);
+  F.grangeR = rebase(base, F.grangeR);
   F.rowsL = rebase(base, F.rowsL);
   F.rowsR = rebase(base, F.rowsR);
   F.cnt = rebase(base, F.cnt);
@@ -207,7 +213,9 @@ enum Stage : int32_t {
 
 // Tile variants the autotuner chooses between (identical results).
 constexpr int kDescVariants = 3;   // descriptor rows per block: 4, 8, 16
-constexpr int kDenseVariants = 3;  // dense grid candidates per batch: 1, 2, 4
+constexpr int kDenseVariants = 4;  // dense rows per workgroup: 1, 2, 4; 3: pipelined
+constexpr int kDensePipe = 3;      // bands of 2 rows, 4 per workgroup, next band's loads in
+                                   // flight (Sobel frames; census frames take 2 rows)
 
 // Workgroups one frame needs for a stage (descriptor variant dv).
 int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv);
@@ -236,8 +244,10 @@ hipError_t launch_mesh_batch(const Frame* frames, int32_t nf, hipStream_t s,
                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Device mesh scratch per view (views that do not fit in LDS).
 size_t mesh_global_scratch_per_view(const Geometry& g);
-// Blocks of the dense launch (one candidate-count entry per block).
-int32_t dense_blocks(const Geometry& g);
+// Blocks of the dense launch for a tile variant (one candidate-count entry
+// per block); the count array is sized for the largest, dense_blocks_max.
+int32_t dense_blocks(const Geometry& g, int variant);
+int32_t dense_blocks_max(const Geometry& g);
 
 }  // namespace elas
 

@@ -490,6 +490,7 @@ __device__ __forceinline__ void support_body(const Frame& F, int lb) {
 // consistency pass runs here.
 // ---------------------------------------------------------------------------
 constexpr int kFiltParts = 4;    // lanes sharing one position's consistency count
+constexpr int32_t kGridEmptyLo = 0x7FFF;  // smallest set bit of an empty region mask
 
 // Tile side in lattice points (chosen with the frame's buffers: 8 for a
 // single frame whose tiles can each have a CU, else 16).
@@ -515,7 +516,8 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
   const int k0 = (lb % ntx) * ft, l0 = (lb / ntx) * ft;
   const int tid = threadIdx.x;
   const int16_t* raw = F.dcan_raw;
-  // clear the grid masks (grid-stride over the frame's blocks)
+  // clear the grid masks and their bit ranges (grid-stride over the frame's
+  // blocks)
   {
     const int gcount = g.gw * g.gh * g.gwords;
     uint32_t* gridL = F.gridL;
@@ -523,6 +525,14 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
     for (int i = lb * 1024 + tid; i < gcount; i += nblk * 1024) {
       gridL[i] = 0u;
       gridR[i] = 0u;
+    }
+    const int rcount = 2 * g.gw * g.gh;
+    int32_t* grL = F.grangeL;
+    int32_t* grR = F.grangeR;
+    for (int i = lb * 1024 + tid; i < rcount; i += nblk * 1024) {
+      const int32_t init = (i & 1) ? -1 : kGridEmptyLo;
+      grL[i] = init;
+      grR[i] = init;
     }
   }
   stage_copy<2, 1024>(
@@ -689,12 +699,17 @@ __device__ __forceinline__ void redun_body(const Frame& F, int lb) {
 // ---------------------------------------------------------------------------
 // Sets the grid bits d - 1 .. d + 1 (within the disparity range) of a cell:
 // one atomic OR per 32-bit word they touch (one, or two across a word edge).
-__device__ __forceinline__ void grid_mark(uint32_t* cell, int d, const KParams& p) {
+// The cell's bit range (smallest and largest set bit) follows by one atomic
+// minimum and maximum.
+__device__ __forceinline__ void grid_mark(uint32_t* cell, int32_t* range, int d,
+                                          const KParams& p) {
   const int lo = max(d - 1, p.dmin) - p.dmin, hi = min(d + 1, p.dmax) - p.dmin;
   const int w0 = lo >> 5, w1 = hi >> 5;
   const uint32_t top0 = w1 == w0 ? hi & 31 : 31;
   atomicOr(&cell[w0], (top0 == 31 ? 0xFFFFFFFFu : ((2u << top0) - 1u)) & ~((1u << (lo & 31)) - 1u));
   if (w1 != w0) atomicOr(&cell[w1], (2u << (hi & 31)) - 1u);
+  atomicMin(&range[0], lo);
+  atomicMax(&range[1], hi);
 }
 
 __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
@@ -737,7 +752,8 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
       const int pos = nL + __popcll(m & below);
       hrowL[(size_t)l * g.lw + pos] = u | (d << 16);
       atomicMax(&slot[u - d], d);
-      grid_mark(gridL + (grow + u / p.grid_size) * g.gwords, d, p);
+      const int cell = grow + u / p.grid_size;
+      grid_mark(gridL + cell * g.gwords, F.grangeL + 2 * cell, d, p);
     }
     nL += __popcll(m);
   }
@@ -750,7 +766,8 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
     if (d >= 0) {
       const int pos = nR + __popcll(m & ((1ull << lane) - 1ull));
       hrowR[(size_t)l * g.lw + pos] = x | (d << 16);
-      grid_mark(gridR + (grow + x / p.grid_size) * g.gwords, d, p);
+      const int cell = grow + x / p.grid_size;
+      grid_mark(gridR + cell * g.gwords, F.grangeR + 2 * cell, d, p);
     }
     nR += __popcll(m);
   }
@@ -1018,24 +1035,42 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
 
 // ---------------------------------------------------------------------------
 // Dense matching (Section III-A, Fig. 1(h)). One thread per pixel; a block is
-// a 256-pixel row segment of one view (views interleaved), with the other
-// view's reachable descriptors staged in LDS. The prior disparity comes from
-// the raster (the owning plane's rounded mean, -1 without a plane).
-// Candidates: the plane window, the
-// grid region's one-hot mask (or every d with full_search), restricted to
-// partners with a defined descriptor. Energy: descriptor SAD (or census
-// Hamming distance) plus the prior table at |d - d_plane|. Argmin by packed
-// key.
+// a 256-pixel row segment of R rows of one view (R = 1, 2 or 4: the tile
+// variant), views interleaved, with the other view's reachable descriptors
+// staged in LDS. The prior disparity comes from the raster (the owning
+// plane's rounded mean, -1 without a plane). Candidates: the plane window
+// |d - d_plane| <= sradius and the grid region's one-hot mask (every d with
+// full_search), restricted to partners with a defined descriptor. Energy:
+// descriptor SAD (or census Hamming distance) plus the prior table at
+// |d - d_plane|. Argmin by packed key (energy << 8 | d - dmin).
+//
+// Two facts keep a pixel's work short:
+//  * window fast path: with sradius 2 and the whole window admissible for
+//    every pixel of a wavefront, the five candidates of a pixel sit at fixed
+//    offsets from one LDS address and their priors are the constants
+//    prior[2], prior[1], prior[0], prior[1], prior[2];
+//  * grid bits inside the window add nothing. The rows stage records each
+//    region's smallest and largest set bit; a pixel whose admissible grid
+//    bits all lie in its window never reads the mask words (the common case
+//    on a smooth surface). The others walk the mask words for the bits
+//    outside the window.
+// A pixel's evaluation count is |window| + |grid bits outside it|.
 // ---------------------------------------------------------------------------
 // Dense descriptors: 16-byte gradient descriptors compared by SAD, or 64-bit
 // census descriptors (Section VI-A) compared by Hamming distance; texture is
-// the distance from the flat descriptor or the number of set bits.
+// the distance from the flat descriptor or the number of set bits. cost(a,
+// b, acc) = acc + distance.
 struct GradDense {
   typedef uint4 T;
   __device__ __forceinline__ static T load(const uint8_t* base, size_t px) {
     return ld16(base + px * 16);
   }
-  __device__ __forceinline__ static uint32_t cost(const T a, const T b) { return sad16(a, b); }
+  __device__ __forceinline__ static uint32_t cost(const T a, const T b, uint32_t acc) {
+    uint32_t s = __builtin_amdgcn_sad_u8(a.x, b.x, acc);
+    s = __builtin_amdgcn_sad_u8(a.y, b.y, s);
+    s = __builtin_amdgcn_sad_u8(a.z, b.z, s);
+    return __builtin_amdgcn_sad_u8(a.w, b.w, s);
+  }
   __device__ __forceinline__ static uint32_t texture(const T a) { return texture16(a); }
 };
 
@@ -1044,23 +1079,25 @@ struct CensusDense {
   __device__ __forceinline__ static T load(const uint8_t* base, size_t px) {
     return reinterpret_cast<const uint64_t*>(base)[px];
   }
-  __device__ __forceinline__ static uint32_t cost(const T a, const T b) {
-    return (uint32_t)__popcll(a ^ b);
+  __device__ __forceinline__ static uint32_t cost(const T a, const T b, uint32_t acc) {
+    return (uint32_t)__popcll(a ^ b) + acc;
   }
   __device__ __forceinline__ static uint32_t texture(const T a) { return (uint32_t)__popcll(a); }
 };
 
-// A workgroup matches kDenseSeg consecutive pixels of kDenseRows rows of one
-// view. The other view's descriptors of every column the segment can reach
+// A workgroup matches kDenseSeg consecutive pixels of R rows of one view.
+// The other view's descriptors of every column the segment can reach
 // (kDenseSeg + D - 1 per row) are staged in LDS once with coalesced loads, so
 // each candidate costs an LDS read instead of a global gather.
 constexpr int kDenseSeg = 256;
-constexpr int kDenseRows = 2;
-constexpr int kWinBatch = 5;  // the whole plane window at the default sradius (2)
+constexpr int kDenseRowsOf[kDenseVariants] = {1, 2, 4, 2};  // 3: pipelined bands of 2 rows
+constexpr int kWinBatch = 5;   // window candidates per step of the general window loop
+constexpr int kGridBatch = 2;  // grid candidates per step of the mask walk
 constexpr int kDenseStage = kDenseSeg + kMaxD - 1;
-// Prior table in LDS, mirrored about its centre so that a candidate's entry
-// is one add away: s_lut[kLutC + k] = s_lut[kLutC - k] = lut[k] (the prior of
-// |d - dp| = k < D), then kMaxD zeros (pixels without a plane).
+// Prior table in LDS for the general paths, mirrored about its centre so
+// that a candidate's entry is one add away: s_lut[kLutC + k] = s_lut[kLutC -
+// k] = lut[k] (the prior of |d - dp| = k < D), then kMaxD zeros (pixels
+// without a plane).
 constexpr int kLutC = kMaxD - 1;
 constexpr int kLutZero = 2 * kLutC + 1;
 constexpr int kLutSize = kLutZero + kMaxD;
@@ -1077,82 +1114,146 @@ __device__ __forceinline__ uint32_t bits32_between(int a, int b) {
   return hi & ~((1u << a) - 1u);
 }
 
+// x / grid_size for 0 <= x < 2^31 / grid_size.
+__device__ __forceinline__ int grid_div(int x, const Geometry& g) {
+  return (int)__umulhi(2u * (uint32_t)x, g.gdiv);
+}
+
+// The priors of the window fast path, energy bias included: prior[0..2].
+struct WinPrior {
+  uint32_t p0, p1, p2;
+};
+
 // Argmin over the candidates of one pixel (descriptors defined there); st
 // holds the other view's descriptors of columns base .. base + n - 1; s_lut
-// is the mirrored prior table (kLutC, kLutZero). The plane window is
-// evaluated as a range, the grid bits outside it (every admissible d with
-// full_search) from 32-bit mask words, KB at a time; a batch's unused slots
-// repeat its first candidate, so every slot is evaluated without branches
-// (a repeat cannot change the argmin) and the count comes from popcounts.
-template <int KB, class DD, bool right>
-__device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, int u,
-                                           int dp, const uint32_t (&cw)[kMaxD / 32],
-                                           const typename DD::T s, const typename DD::T* st,
-                                           int base, const int32_t* s_lut, int* cnt) {
+// is the mirrored prior table (kLutC, kLutZero); gmin / gmax the pixel's
+// grid region's bit range and cellw its mask words (global memory).
+template <class DD, bool right>
+__device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, int u, int dp,
+                                           int gmin, int gmax, const uint32_t* cellw,
+                                           bool has_list, const typename DD::T s,
+                                           const typename DD::T* st, int base,
+                                           const int32_t* s_lut, const WinPrior& wp, int* cnt) {
   const int lim = (right ? (g.w - 3 - u) : (u - 2)) - p.dmin;  // largest admissible d-dmin
   if ((int)DD::texture(s) < p.match_texture || lim < 0) return -1;
   const int top = min(lim, p.D - 1);
-  int wlo = 1, whi = 0;  // plane window in d - dmin units, clipped to [0, top]
+  const int c = dp - p.dmin;  // the plane disparity in d - dmin units (dp in [dmin, dmax])
+  int wlo = 1, whi = 0;       // plane window clipped to [0, top]; empty without a plane
   if (dp >= 0) {
-    wlo = max(dp - p.sradius, p.dmin) - p.dmin;
-    whi = min(min(dp + p.sradius, p.dmax) - p.dmin, top);
+    wlo = max(c - p.sradius, 0);
+    whi = min(c + p.sradius, top);
   }
   const int slot0 = (right ? u + p.dmin : u - p.dmin) - base;
   const int dir = right ? 1 : -1;
-  // entry of candidate dd (d = dmin + dd): kLutC + d - dp with a plane, else
-  // the zero block; dp lies in [dmin, dmax], so the index stays in the table
-  const int lidx = dp >= 0 ? kLutC + p.dmin - dp : kLutZero;
   uint32_t best = 0xFFFFFFFFu;
   int n = max(0, whi - wlo + 1);
-  // the window, kWinBatch candidates at a time (the last batch repeats whi),
-  // every LDS read of a batch issued before its arithmetic
-  for (int b = wlo; b <= whi; b += kWinBatch) {
-    int dd[kWinBatch];
-    typename DD::T o[kWinBatch];
-    int lv[kWinBatch];
+  const bool full = dp >= 0 && p.sradius == 2 && c >= 2 && c + 2 <= top;
+  if (__all(full)) {
+    // slots c-2 .. c+2 from one address; priors are constants
+    const typename DD::T* q = st + (slot0 + dir * (c - 2));
+    typename DD::T o[5];
 #pragma unroll
-    for (int t = 0; t < kWinBatch; ++t) dd[t] = min(b + t, whi);
+    for (int t = 0; t < 5; ++t) o[t] = q[dir * t];
+    const uint32_t pr[5] = {wp.p2, wp.p1, wp.p0, wp.p1, wp.p2};
 #pragma unroll
-    for (int t = 0; t < kWinBatch; ++t) {
-      o[t] = st[slot0 + dir * dd[t]];
-      lv[t] = s_lut[dd[t] + lidx];  // a window exists only with a plane
-    }
+    for (int t = 0; t < 5; ++t)
+      best = min(best, (DD::cost(s, o[t], pr[t]) << 8) | (uint32_t)(c - 2 + t));
+  } else if (dp >= 0) {
+    // entry of candidate dd (d = dmin + dd): kLutC + dd - c, inside the table
+    const int lidx = kLutC - c;
+    // kWinBatch candidates at a time (the last batch repeats whi), every LDS
+    // read of a batch issued before its arithmetic
+    for (int b = wlo; b <= whi; b += kWinBatch) {
+      int dd[kWinBatch];
+      typename DD::T o[kWinBatch];
+      int lv[kWinBatch];
 #pragma unroll
-    for (int t = 0; t < kWinBatch; ++t) {
-      const int E = (int)DD::cost(s, o[t]) + lv[t];
-      best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd[t]);
-    }
-  }
-  const int nw = (top >> 5) + 1;  // 32-bit words in play
+      for (int t = 0; t < kWinBatch; ++t) dd[t] = min(b + t, whi);
 #pragma unroll
-  for (int j = 0; j < kMaxD / 32; ++j) {
-    if (j >= nw) break;
-    const uint32_t grid = p.full_search ? 0xFFFFFFFFu : cw[j];
-    if (grid == 0u) continue;  // nothing to mask (most words of a cell)
-    const int wb = 32 * j;
-    uint32_t m = grid & bits32_between(0, top - wb) &
-                 ~bits32_between(wlo - wb, whi - wb);
-    n += __popc(m);
-    while (m) {
-      int dd[KB];
-      dd[0] = wb + __builtin_ctz(m);
-      m &= m - 1u;
-#pragma unroll
-      for (int t = 1; t < KB; ++t) {
-        dd[t] = m ? wb + __builtin_ctz(m) : dd[0];
-        m &= m - 1u;
-      }
-      typename DD::T o[KB];
-      int lv[KB];
-#pragma unroll
-      for (int t = 0; t < KB; ++t) {
+      for (int t = 0; t < kWinBatch; ++t) {
         o[t] = st[slot0 + dir * dd[t]];
         lv[t] = s_lut[dd[t] + lidx];
       }
 #pragma unroll
-      for (int t = 0; t < KB; ++t) {
-        const int E = (int)DD::cost(s, o[t]) + lv[t];
-        best = min(best, ((uint32_t)(E + p.lut_bias) << 8) | (uint32_t)dd[t]);
+      for (int t = 0; t < kWinBatch; ++t) {
+        const uint32_t E = DD::cost(s, o[t], (uint32_t)(lv[t] + p.lut_bias));
+        best = min(best, (E << 8) | (uint32_t)dd[t]);
+      }
+    }
+  }
+  // grid bits outside the window (every admissible d with full_search)
+  const int ghi = min(gmax, top);  // the region's largest admissible bit
+  const bool inside = dp >= 0 && gmin >= wlo && ghi <= whi;
+  const int lidx = dp >= 0 ? kLutC - c : kLutZero;
+  if (!p.full_search && has_list && !inside && gmin <= ghi && ghi - gmin < 64) {
+    // the region's admissible bits in one 64-bit word, bit 0 = gmin (the
+    // usual case: a region's support disparities lie close together)
+    const int j0 = gmin >> 5, sh = gmin & 31, jl = g.gwords - 1;
+    const uint32_t w0 = cellw[j0], w1 = cellw[min(j0 + 1, jl)], w2 = cellw[min(j0 + 2, jl)];
+    uint64_t m = ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, sh) << 32) |
+                 __builtin_amdgcn_alignbit(w1, w0, sh);
+    const int span = ghi - gmin;  // bits 0 .. span are admissible
+    m &= span == 63 ? ~0ull : ((2ull << span) - 1ull);
+    const int a = max(wlo - gmin, 0), b = min(whi - gmin, 63);  // the window's bits
+    if (a <= b) m &= ~((b == 63 ? ~0ull : ((2ull << b) - 1ull)) & ~((1ull << a) - 1ull));
+    n += __popcll(m);
+    while (m) {
+      int dd[kGridBatch];
+      dd[0] = gmin + __builtin_ctzll(m);
+      m &= m - 1ull;
+#pragma unroll
+      for (int t = 1; t < kGridBatch; ++t) {
+        dd[t] = m ? gmin + __builtin_ctzll(m) : dd[0];
+        m &= m - 1ull;
+      }
+      typename DD::T o[kGridBatch];
+      int lv[kGridBatch];
+#pragma unroll
+      for (int t = 0; t < kGridBatch; ++t) {
+        o[t] = st[slot0 + dir * dd[t]];
+        lv[t] = s_lut[dd[t] + lidx];
+      }
+#pragma unroll
+      for (int t = 0; t < kGridBatch; ++t) {
+        const uint32_t E = DD::cost(s, o[t], (uint32_t)(lv[t] + p.lut_bias));
+        best = min(best, (E << 8) | (uint32_t)dd[t]);
+      }
+    }
+  } else if (p.full_search || (has_list && gmax >= 0 && !inside && gmin <= ghi)) {
+    const int nw = (top >> 5) + 1;  // 32-bit words in play
+    // every word in play is loaded at once (one memory round trip)
+    uint32_t words[kMaxD / 32];
+#pragma unroll
+    for (int j = 0; j < kMaxD / 32; ++j) words[j] = cellw[min(j, nw - 1)];
+#pragma unroll
+    for (int j = 0; j < kMaxD / 32; ++j) {
+      if (j >= nw) break;
+      const uint32_t grid = p.full_search ? 0xFFFFFFFFu : words[j];
+      if (grid == 0u) continue;
+      const int wb = 32 * j;
+      uint32_t m = grid & bits32_between(0, top - wb) & ~bits32_between(wlo - wb, whi - wb);
+      n += __popc(m);
+      while (m) {
+        int dd[kGridBatch];
+        dd[0] = wb + __builtin_ctz(m);
+        m &= m - 1u;
+#pragma unroll
+        for (int t = 1; t < kGridBatch; ++t) {
+          dd[t] = m ? wb + __builtin_ctz(m) : dd[0];
+          m &= m - 1u;
+        }
+        typename DD::T o[kGridBatch];
+        int lv[kGridBatch];
+#pragma unroll
+        for (int t = 0; t < kGridBatch; ++t) {
+          o[t] = st[slot0 + dir * dd[t]];
+          lv[t] = s_lut[dd[t] + lidx];
+        }
+#pragma unroll
+        for (int t = 0; t < kGridBatch; ++t) {
+          const uint32_t E = DD::cost(s, o[t], (uint32_t)(lv[t] + p.lut_bias));
+          best = min(best, (E << 8) | (uint32_t)dd[t]);
+        }
       }
     }
   }
@@ -1160,23 +1261,24 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
   return best != 0xFFFFFFFFu ? p.dmin + (int)(best & 0xFFu) : -1;
 }
 
-// Row of staged element i when each of the block's rows holds nc elements:
-// i / nc for i < kDenseRows * nc, by comparisons instead of a division.
+// Row of staged element i when each of the block's R rows holds nc elements:
+// i / nc for i < R * nc, by comparisons instead of a division.
+template <int R>
 __device__ __forceinline__ int dense_row_of(int i, int nc) {
   int r = 0;
 #pragma unroll
-  for (int rr = 1; rr < kDenseRows; ++rr) r += i >= rr * nc ? 1 : 0;
+  for (int rr = 1; rr < R; ++rr) r += i >= rr * nc ? 1 : 0;
   return r;
 }
 
-// One workgroup: kDenseRows rows x kDenseSeg columns of one view, a thread
-// per column and row. Every global load (the other view's reachable
-// descriptors, staged in LDS; the own descriptor, prior and grid-region mask
-// of each pixel) is issued before the one barrier, so a wave waits on memory
-// once.
-// The view is a template argument: the search direction is then a constant
-// in every candidate's address.
-template <int KB, class DD, bool right>
+// One workgroup: R rows x kDenseSeg columns of one view, a thread per column
+// and row. Every global load (the other view's reachable descriptors, staged
+// in LDS; the own descriptor, prior and grid-region bit range of each pixel)
+// is issued before the one barrier, so a wave waits on memory once; only the
+// pixels whose grid bits reach outside their window read mask words after
+// it. The view is a template argument: the search direction is then a
+// constant in every candidate's address.
+template <class DD, bool right, int R>
 __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, const KParams& p,
                                            int v0, int u0, int32_t* s_lut,
                                            typename DD::T* st, int* cnt) {
@@ -1189,12 +1291,15 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
   const int16_t* dplR = F.dplaneR;
   const uint32_t* gridL = F.gridL;
   const uint32_t* gridR = F.gridR;
+  const int32_t* grL = F.grangeL;
+  const int32_t* grR = F.grangeR;
   int16_t* rawL = F.rawL;
   int16_t* rawR = F.rawR;
   const uint8_t* self_desc = right ? descR : descL;
   const uint8_t* other_desc = right ? descL : descR;
   const int16_t* dplane = right ? dplR : dplL;
   const uint32_t* grid = right ? gridR : gridL;
+  const int32_t* grange = right ? grR : grL;
   int16_t* raw = right ? rawR : rawL;
   const bool has_list = F.hdr->n[0] > 0;
   // other-view columns a pixel of this segment can reach
@@ -1207,14 +1312,14 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
   // or not its value is used (a conditional load would make the compiler
   // wait for it at the branch join): the reachable other-view columns of the
   // block's rows (at most kDenseStage per row: two per thread and row), the
-  // prior table, then each pixel's prior, descriptor and region mask
-  const int nc = c1 - c0 + 1, rows = min(kDenseRows, g.h - v0);
+  // prior table, then each pixel's prior, descriptor and region bit range
+  const int nc = c1 - c0 + 1, rows = min(R, g.h - v0);
   const int nst = nc * rows;
-  typename DD::T sv[kDenseRows * 2];
+  typename DD::T sv[R * 2];
 #pragma unroll
-  for (int k = 0; k < kDenseRows * 2; ++k) {
+  for (int k = 0; k < R * 2; ++k) {
     const int i = min((int)threadIdx.x + 256 * k, nst - 1);
-    const int r = dense_row_of(i, nc), c = c0 + (i - r * nc);
+    const int r = dense_row_of<R>(i, nc), c = c0 + (i - r * nc);
     sv[k] = DD::load(other_desc, (size_t)(v0 + r) * g.w + c);
   }
   int32_t lv[3];  // the mirrored table's entries tid, tid + 256, tid + 512
@@ -1224,25 +1329,27 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
     const int32_t x = lut[min(abs(i - kLutC), p.D - 1)];
     lv[q] = i <= 2 * kLutC ? x : 0;
   }
+  WinPrior wp;
+  wp.p0 = (uint32_t)(lut[0] + p.lut_bias);
+  wp.p1 = (uint32_t)(lut[min(1, p.D - 1)] + p.lut_bias);
+  wp.p2 = (uint32_t)(lut[min(2, p.D - 1)] + p.lut_bias);
   const int uc = min(u, g.w - 1);
-  const int gwp = g.gwords >> 1;  // 64-bit words of a region mask
-  int dpv[kDenseRows];
-  typename DD::T s[kDenseRows];
-  uint2 cw2[kDenseRows][kMaxD / 64];
+  const int cu = grid_div(uc, g);
+  int dpv[R], cell[R];
+  typename DD::T s[R];
+  int2 rng[R];
 #pragma unroll
-  for (int r = 0; r < kDenseRows; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int vc = min(v0 + r, g.h - 1);
     dpv[r] = dplane[(size_t)vc * g.w + uc];
     s[r] = DD::load(self_desc, (size_t)vc * g.w + uc);
-    const uint2* cell = reinterpret_cast<const uint2*>(
-        grid + ((size_t)(vc / p.grid_size) * g.gw + uc / p.grid_size) * g.gwords);
-#pragma unroll
-    for (int j = 0; j < kMaxD / 64; ++j) cw2[r][j] = cell[min(j, gwp - 1)];
+    cell[r] = grid_div(vc, g) * g.gw + cu;
+    rng[r] = reinterpret_cast<const int2*>(grange)[cell[r]];
   }
 #pragma unroll
-  for (int k = 0; k < kDenseRows * 2; ++k) {
+  for (int k = 0; k < R * 2; ++k) {
     const int i = (int)threadIdx.x + 256 * k;
-    const int r = dense_row_of(i, nc), c = c0 + (i - r * nc);
+    const int r = dense_row_of<R>(i, nc), c = c0 + (i - r * nc);
     if (i < nst) st[r * kDenseStage + (c - base)] = sv[k];
   }
 #pragma unroll
@@ -1252,48 +1359,193 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kDenseRows; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int v = v0 + r;
     if (!in_u || v >= g.h) continue;
     int res = -1;
-    if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
-      uint32_t cw[kMaxD / 32];
-#pragma unroll
-      for (int j = 0; j < kMaxD / 64; ++j) {
-        cw[2 * j] = has_list ? cw2[r][j].x : 0u;
-        cw[2 * j + 1] = has_list ? cw2[r][j].y : 0u;
-      }
-      res = dense_pixel<KB, DD, right>(g, p, u, dpv[r], cw, s[r], st + r * kDenseStage, base,
-                                s_lut, cnt);
-    }
+    if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3)
+      res = dense_pixel<DD, right>(g, p, u, dpv[r], rng[r].x, rng[r].y,
+                                   grid + (size_t)cell[r] * g.gwords, has_list, s[r],
+                                   st + r * kDenseStage, base, s_lut, wp, cnt);
     raw[(size_t)v * g.w + u] = (int16_t)res;
   }
 }
 
-template <int KB>
+template <int R>
 __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
   __shared__ int32_t s_lut[kLutSize];  // mirrored prior table, then zeros
   __shared__ int s_cnt[4];
-  __shared__ uint4 s_stage[kDenseRows * kDenseStage];
+  __shared__ uint4 s_stage[R * kDenseStage];
   const Geometry g = F.g;
   const KParams p = F.p;
   const bool right = (lb & 1) != 0;
   const int nseg = dense_segments(g);
   const int rs = lb >> 1, band = rs / nseg, u0 = (rs - band * nseg) * kDenseSeg;
-  const int v0 = band * kDenseRows;
+  const int v0 = band * R;
   int cnt = 0;
   uint64_t* const s_stage64 = reinterpret_cast<uint64_t*>(s_stage);
   if (p.descriptor) {
     if (right)
-      dense_rows<KB, CensusDense, true>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
+      dense_rows<CensusDense, true, R>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
     else
-      dense_rows<KB, CensusDense, false>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
+      dense_rows<CensusDense, false, R>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
   } else {
     if (right)
-      dense_rows<KB, GradDense, true>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
+      dense_rows<GradDense, true, R>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
     else
-      dense_rows<KB, GradDense, false>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
+      dense_rows<GradDense, false, R>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
   }
+  cnt = wave_sum_i32(cnt);
+  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) F.dense_counts[lb] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined dense matching (Sobel descriptors): a workgroup takes kPipeBands
+// consecutive bands of kPipeRows rows of one 256-column segment of one view.
+// While it matches one band, the loads of the next (the other view's
+// reachable descriptors for the staging buffer, and each pixel's own
+// descriptor, prior and region bit range) are in flight; two LDS buffers
+// alternate. The workgroup's setup (frame lookup, prior table) is paid once
+// for all its bands. A band's work and results are those of the 2-row dense
+// kernel.
+// ---------------------------------------------------------------------------
+constexpr int kPipeRows = 2;
+constexpr int kPipeBands = 4;
+
+__host__ __device__ __forceinline__ int pipe_groups(const Geometry& g) {
+  return cdivd(cdivd(g.h, kPipeRows), kPipeBands);
+}
+
+// A band's loads: staging (two per thread and row, in-bounds addresses) and
+// each pixel's own values.
+struct PipeLoads {
+  uint4 sv[2 * kPipeRows];
+  uint4 s[kPipeRows];
+  int dpv[kPipeRows];
+  int cell[kPipeRows];
+  int2 rng[kPipeRows];
+};
+
+template <bool right>
+__device__ __forceinline__ void pipe_issue(const Frame& F, const Geometry& g, const KParams& p,
+                                           int v0, int u0, PipeLoads& L) {
+  const uint8_t* other = right ? F.descL : F.descR;
+  const uint8_t* self_desc = right ? F.descR : F.descL;
+  const int16_t* dplane = right ? F.dplaneR : F.dplaneL;
+  const int32_t* grange = right ? F.grangeR : F.grangeL;
+  const int base = right ? u0 + p.dmin : u0 - p.dmax;
+  const int c0 = max(0, base), c1 = min(g.w - 1, base + kDenseSeg + p.D - 2);
+  const int nc = c1 - c0 + 1, nst = nc * min(kPipeRows, g.h - v0);
+#pragma unroll
+  for (int k = 0; k < 2 * kPipeRows; ++k) {
+    const int i = min((int)threadIdx.x + 256 * k, nst - 1);
+    const int r = dense_row_of<kPipeRows>(i, nc), c = c0 + (i - r * nc);
+    L.sv[k] = ld16(other + ((size_t)(v0 + r) * g.w + c) * 16);
+  }
+  const int uc = min(u0 + (int)threadIdx.x, g.w - 1);
+  const int cu = grid_div(uc, g);
+#pragma unroll
+  for (int r = 0; r < kPipeRows; ++r) {
+    const int vc = min(v0 + r, g.h - 1);
+    L.dpv[r] = dplane[(size_t)vc * g.w + uc];
+    L.s[r] = ld16(self_desc + ((size_t)vc * g.w + uc) * 16);
+    L.cell[r] = grid_div(vc, g) * g.gw + cu;
+    L.rng[r] = reinterpret_cast<const int2*>(grange)[L.cell[r]];
+  }
+}
+
+template <bool right>
+__device__ __forceinline__ void pipe_store(const Geometry& g, const KParams& p, int v0, int u0,
+                                           const PipeLoads& L, uint4* st) {
+  const int base = right ? u0 + p.dmin : u0 - p.dmax;
+  const int c0 = max(0, base), c1 = min(g.w - 1, base + kDenseSeg + p.D - 2);
+  const int nc = c1 - c0 + 1, nst = nc * min(kPipeRows, g.h - v0);
+#pragma unroll
+  for (int k = 0; k < 2 * kPipeRows; ++k) {
+    const int i = (int)threadIdx.x + 256 * k;
+    const int r = dense_row_of<kPipeRows>(i, nc), c = c0 + (i - r * nc);
+    if (i < nst) st[r * kDenseStage + (c - base)] = L.sv[k];
+  }
+}
+
+template <bool right>
+__device__ __forceinline__ void pipe_match(const Frame& F, const Geometry& g, const KParams& p,
+                                           int v0, int u0, const PipeLoads& L,
+                                           const uint4* st, const int32_t* s_lut,
+                                           bool has_list, const WinPrior& wp, int* cnt) {
+  const uint32_t* grid = right ? F.gridR : F.gridL;
+  int16_t* raw = right ? F.rawR : F.rawL;
+  const int base = right ? u0 + p.dmin : u0 - p.dmax;
+  const int u = u0 + (int)threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < kPipeRows; ++r) {
+    const int v = v0 + r;
+    if (u >= g.w || v >= g.h) continue;
+    int res = -1;
+    if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3)
+      res = dense_pixel<GradDense, right>(g, p, u, L.dpv[r], L.rng[r].x, L.rng[r].y,
+                                          grid + (size_t)L.cell[r] * g.gwords, has_list, L.s[r],
+                                          st + r * kDenseStage, base, s_lut, wp, cnt);
+    raw[(size_t)v * g.w + u] = (int16_t)res;
+  }
+}
+
+template <bool right>
+__device__ __forceinline__ void pipe_view(const Frame& F, int grp, int u0, int32_t* s_lut,
+                                          uint4* stage, int* cnt) {
+  const Geometry g = F.g;
+  const KParams p = F.p;
+  const int nbands = cdivd(g.h, kPipeRows);
+  const int b0 = grp * kPipeBands, nb = min(kPipeBands, nbands - b0);
+  const bool has_list = F.hdr->n[0] > 0;
+  const int32_t* lut = F.lut;
+  WinPrior wp;
+  wp.p0 = (uint32_t)(lut[0] + p.lut_bias);
+  wp.p1 = (uint32_t)(lut[min(1, p.D - 1)] + p.lut_bias);
+  wp.p2 = (uint32_t)(lut[min(2, p.D - 1)] + p.lut_bias);
+  int32_t lv[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = (int)threadIdx.x + 256 * q;
+    const int32_t x = lut[min(abs(i - kLutC), p.D - 1)];
+    lv[q] = i <= 2 * kLutC ? x : 0;
+  }
+  PipeLoads L[2];
+  pipe_issue<right>(F, g, p, b0 * kPipeRows, u0, L[0]);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = (int)threadIdx.x + 256 * q;
+    if (i < kLutSize) s_lut[i] = lv[q];
+  }
+  // bands k = 0 .. nb-1, unrolled so that each band's loads keep registers
+  // of their own; band k + 1 is issued before band k is matched
+#pragma unroll
+  for (int k = 0; k < kPipeBands; ++k) {
+    if (k >= nb) break;
+    const int v0 = (b0 + k) * kPipeRows;
+    uint4* st = stage + (k & 1) * (kPipeRows * kDenseStage);
+    pipe_store<right>(g, p, v0, u0, L[k & 1], st);
+    if (k + 1 < nb) pipe_issue<right>(F, g, p, v0 + kPipeRows, u0, L[(k + 1) & 1]);
+    __syncthreads();
+    pipe_match<right>(F, g, p, v0, u0, L[k & 1], st, s_lut, has_list, wp, cnt);
+  }
+}
+
+__device__ __forceinline__ void dense_pipe_body(const Frame& F, int lb) {
+  __shared__ int32_t s_lut[kLutSize];
+  __shared__ int s_cnt[4];
+  __shared__ uint4 s_stage[2 * kPipeRows * kDenseStage];
+  const Geometry g = F.g;
+  const bool right = (lb & 1) != 0;
+  const int nseg = dense_segments(g);
+  const int rs = lb >> 1, grp = rs / nseg, u0 = (rs - grp * nseg) * kDenseSeg;
+  int cnt = 0;
+  if (right)
+    pipe_view<true>(F, grp, u0, s_lut, s_stage, &cnt);
+  else
+    pipe_view<false>(F, grp, u0, s_lut, s_stage, &cnt);
   cnt = wave_sum_i32(cnt);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
@@ -1448,9 +1700,10 @@ ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
 ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
 ELAS_STAGE_KERNELS(k_raster, raster_body<1024>, 1024)
 ELAS_STAGE_KERNELS(k_raster256, raster_body<256>, 256)
-ELAS_STAGE_KERNELS(k_dense1, dense_body<1>, 256)
-ELAS_STAGE_KERNELS(k_dense2, dense_body<2>, 256)
-ELAS_STAGE_KERNELS(k_dense4, dense_body<4>, 256)
+ELAS_STAGE_KERNELS(k_dense_r1, dense_body<1>, 256)
+ELAS_STAGE_KERNELS(k_dense_r2, dense_body<2>, 256)
+ELAS_STAGE_KERNELS(k_dense_r4, dense_body<4>, 256)
+ELAS_STAGE_KERNELS(k_dense_pipe, dense_pipe_body, 256)
 ELAS_STAGE_KERNELS(k_check, check_body, 256)
 ELAS_STAGE_KERNELS(k_redun, redun_body, 1024)
 ELAS_STAGE_KERNELS(k_median, median_body, 256)
@@ -1477,9 +1730,13 @@ int stage_threads(int32_t stage) {
 
 int32_t raster_band_rows(int32_t w) { return std::max(1, std::min(kBandRowsMax, 4096 / w)); }
 
-int32_t dense_blocks(const Geometry& g) {
-  return 2 * cdiv(g.h, kDenseRows) * dense_segments(g);
+int32_t dense_blocks(const Geometry& g, int variant) {
+  if (variant == kDensePipe) return 2 * pipe_groups(g) * dense_segments(g);
+  return 2 * cdiv(g.h, kDenseRowsOf[std::min(std::max(variant, 0), kDenseVariants - 1)]) *
+         dense_segments(g);
 }
+
+int32_t dense_blocks_max(const Geometry& g) { return dense_blocks(g, 0); }
 
 int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv) {
   switch (stage) {
@@ -1491,7 +1748,7 @@ int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv)
     case kStageRows: return g.lh;
     case kStageMesh: return 2;
     case kStageRaster: return 2 * cdiv(g.h, raster_band_rows(g.w));
-    case kStageDense: return dense_blocks(g);
+    case kStageDense: return dense_blocks(g, dv);
     case kStageCheck: return 2 * cdiv((long long)g.w * g.h, 256 * kCheckPx);
     case kStageMedian: return p.median ? 2 * cdiv(g.w, kMedW) * cdiv(g.h, kMedH) : 0;
     default: return 0;
@@ -1543,13 +1800,15 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
       else
         go(k_raster256);
       break;
-    case kStageDense:
+    case kStageDense:  // census frames take the 2-row kernel for the pipelined variant
       if (variant == 0)
-        go(k_dense1);
+        go(k_dense_r1);
       else if (variant == 2)
-        go(k_dense4);
+        go(k_dense_r4);
+      else if (variant == kDensePipe && f.p.descriptor == 0)
+        go(k_dense_pipe);
       else
-        go(k_dense2);
+        go(k_dense_r2);
       break;
     case kStageCheck: go(k_check); break;
     case kStageMedian: go(k_median); break;
@@ -1587,11 +1846,13 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
     case kStageRaster: go(k_raster256_batch, shm); break;
     case kStageDense:
       if (variant == 0)
-        go(k_dense1_batch, 0u);
+        go(k_dense_r1_batch, 0u);
       else if (variant == 2)
-        go(k_dense4_batch, 0u);
+        go(k_dense_r4_batch, 0u);
+      else if (variant == kDensePipe)
+        go(k_dense_pipe_batch, 0u);
       else
-        go(k_dense2_batch, 0u);
+        go(k_dense_r2_batch, 0u);
       break;
     case kStageCheck: go(k_check_batch, 0u); break;
     case kStageRedun: go(k_redun_batch, 0u); break;

@@ -26,7 +26,7 @@ EXPORTS = ("elas_params_default", "elas_create", "elas_destroy", "elas_process",
            "elas_server_create", "elas_server_submit", "elas_server_wait", "elas_server_poll",
            "elas_server_get_stats", "elas_server_last_error", "elas_server_destroy",
            "elas_server_submit_on", "elas_set_mesh_round_limit",
-           "elas_get_batch_intermediate", "elas_process_noalloc")
+           "elas_get_batch_intermediate", "elas_process_noalloc", "elas_set_tile_variants")
 
 BATCH_GRAPH = 1
 BATCH_AUTOTUNE = 2
@@ -139,6 +139,7 @@ def lib() -> C.CDLL:
         L.elas_process_batch.argtypes = [vp, C.c_int32, C.POINTER(ElasPair), vp]
         L.elas_get_tuned_variants.argtypes = [vp, C.c_int32, C.c_int32,
                                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.elas_set_tile_variants.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.elas_frame_bytes.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
         L.elas_server_config_default.argtypes = [C.POINTER(ServerConfig)]
         L.elas_server_config_default.restype = None
@@ -293,6 +294,9 @@ class Elas:
         b = C.c_int64()
         _check(lib().elas_frame_bytes(self._h, w, h, C.byref(b)), self._h)
         return b.value
+
+    def set_tile_variants(self, w: int, h: int, desc_rows: int, dense_rows: int):
+        _check(lib().elas_set_tile_variants(self._h, w, h, desc_rows, dense_rows), self._h)
 
     def tuned_variants(self, w: int, h: int):
         r, b = C.c_int32(), C.c_int32()
