@@ -495,8 +495,7 @@ std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp,
     // smaller halo share)
     v = std::make_pair(batched ? 2 : 1, 1);
   }
-  // the pipelined dense kernel takes Sobel frames only
-  if (v.second == kDensePipe && census) v.second = 1;
+  (void)census;
   return v;
 }
 
@@ -1139,11 +1138,9 @@ int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
   HIP_TRY(hipEventCreate(&e1));
   int choice[2] = {0, 1};
   const int32_t stages[2] = {kStageDescriptor, kStageDense};
-  bool census = false;
-  for (const Frame& f : frames) census |= f.p.descriptor != 0;
   for (int k = 0; k < 2; ++k) {
     float best_ms = 1e30f;
-    const int nvar = k == 0 ? kDescVariants : (census ? kDenseVariants - 1 : kDenseVariants);  // no pipelined variant for census
+    const int nvar = k == 0 ? kDescVariants : kDenseVariants;
     for (int v = 0; v < nvar; ++v) {
       std::vector<int32_t> starts(1, 0);
       for (const Frame& f : frames)
@@ -1354,15 +1351,14 @@ int elas_frame_bytes(elas_handle* h, int32_t w, int32_t hp, int64_t* bytes) {
 int elas_set_tile_variants(elas_handle* h, int32_t w, int32_t hp, int32_t desc_rows,
                            int32_t dense_rows) {
   if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
-  static const int32_t drows[3] = {4, 8, 16}, nrows[4] = {1, 2, 4, 0};
+  static const int32_t drows[3] = {4, 8, 16}, nrows[3] = {1, 2, 4};
   int dv = -1, nv = -1;
-  for (int k = 0; k < 4; ++k) {
-    if (k < 3 && drows[k] == desc_rows) dv = k;
+  for (int k = 0; k < 3; ++k) {
+    if (drows[k] == desc_rows) dv = k;
     if (nrows[k] == dense_rows) nv = k;
   }
   if (dv < 0 || nv < 0 || w < 9 || hp < 9)
-    return fail(h, ELAS_ERR_ARG,
-                "descriptor rows must be 4, 8 or 16 and dense rows 1, 2, 4 or 0 (pipelined bands)");
+    return fail(h, ELAS_ERR_ARG, "descriptor rows must be 4, 8 or 16 and dense rows 1, 2 or 4");
   h->tuned[std::make_tuple(w, hp, h->kp.D)] = std::make_pair(dv, nv);
   return ELAS_OK;
 }
@@ -1372,7 +1368,7 @@ int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t hp, int32_t* desc
   if (!h || !desc_rows || !dense_batch) return fail(h, ELAS_ERR_ARG, "null argument");
   auto it = h->tuned.find(std::make_tuple(w, hp, h->kp.D));
   if (it == h->tuned.end()) return fail(h, ELAS_ERR_ARG, "no tuned variants for this size");
-  static const int32_t rows[3] = {4, 8, 16}, batch[4] = {1, 2, 4, 0};  // descriptor / dense rows
+  static const int32_t rows[3] = {4, 8, 16}, batch[3] = {1, 2, 4};  // descriptor / dense rows
   *desc_rows = rows[it->second.first];
   *dense_batch = batch[it->second.second];
   return ELAS_OK;

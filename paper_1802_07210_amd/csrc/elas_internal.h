@@ -213,9 +213,7 @@ enum Stage : int32_t {
 
 // Tile variants the autotuner chooses between (identical results).
 constexpr int kDescVariants = 3;   // descriptor rows per block: 4, 8, 16
-constexpr int kDenseVariants = 4;  // dense rows per workgroup: 1, 2, 4; 3: pipelined
-constexpr int kDensePipe = 3;      // bands of 2 rows, 4 per workgroup, next band's loads in
-                                   // flight (Sobel frames; census frames take 2 rows)
+constexpr int kDenseVariants = 3;  // dense rows per workgroup: 1, 2, 4
 
 // Workgroups one frame needs for a stage (descriptor variant dv).
 int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv);

@@ -1062,8 +1062,13 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
 // b, acc) = acc + distance.
 struct GradDense {
   typedef uint4 T;
+  static constexpr uint32_t kBytes = 16;
   __device__ __forceinline__ static T load(const uint8_t* base, size_t px) {
     return ld16(base + px * 16);
+  }
+  // column c of a row whose first descriptor is at row (a wavefront-uniform base)
+  __device__ __forceinline__ static T load_col(const uint8_t* row, uint32_t c) {
+    return ld16(row + c * 16u);
   }
   __device__ __forceinline__ static uint32_t cost(const T a, const T b, uint32_t acc) {
     uint32_t s = __builtin_amdgcn_sad_u8(a.x, b.x, acc);
@@ -1076,8 +1081,12 @@ struct GradDense {
 
 struct CensusDense {
   typedef uint64_t T;
+  static constexpr uint32_t kBytes = 8;
   __device__ __forceinline__ static T load(const uint8_t* base, size_t px) {
     return reinterpret_cast<const uint64_t*>(base)[px];
+  }
+  __device__ __forceinline__ static T load_col(const uint8_t* row, uint32_t c) {
+    return *reinterpret_cast<const uint64_t*>(row + c * 8u);
   }
   __device__ __forceinline__ static uint32_t cost(const T a, const T b, uint32_t acc) {
     return (uint32_t)__popcll(a ^ b) + acc;
@@ -1090,7 +1099,7 @@ struct CensusDense {
 // (kDenseSeg + D - 1 per row) are staged in LDS once with coalesced loads, so
 // each candidate costs an LDS read instead of a global gather.
 constexpr int kDenseSeg = 256;
-constexpr int kDenseRowsOf[kDenseVariants] = {1, 2, 4, 2};  // 3: pipelined bands of 2 rows
+constexpr int kDenseRowsOf[kDenseVariants] = {1, 2, 4};
 constexpr int kWinBatch = 5;   // window candidates per step of the general window loop
 constexpr int kGridBatch = 2;  // grid candidates per step of the mask walk
 constexpr int kDenseStage = kDenseSeg + kMaxD - 1;
@@ -1311,16 +1320,16 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
   // issue every global load first, each from an in-bounds address whether
   // or not its value is used (a conditional load would make the compiler
   // wait for it at the branch join): the reachable other-view columns of the
-  // block's rows (at most kDenseStage per row: two per thread and row), the
+  // block's rows (at most kDenseStage per row: two per thread and row, from
+  // the row's uniform base; rows past the frame repeat its last row), the
   // prior table, then each pixel's prior, descriptor and region bit range
-  const int nc = c1 - c0 + 1, rows = min(R, g.h - v0);
-  const int nst = nc * rows;
   typename DD::T sv[R * 2];
 #pragma unroll
-  for (int k = 0; k < R * 2; ++k) {
-    const int i = min((int)threadIdx.x + 256 * k, nst - 1);
-    const int r = dense_row_of<R>(i, nc), c = c0 + (i - r * nc);
-    sv[k] = DD::load(other_desc, (size_t)(v0 + r) * g.w + c);
+  for (int r = 0; r < R; ++r) {
+    const uint8_t* row = other_desc + (size_t)min(v0 + r, g.h - 1) * g.w * DD::kBytes;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      sv[2 * r + k] = DD::load_col(row, (uint32_t)min(c0 + (int)threadIdx.x + 256 * k, c1));
   }
   int32_t lv[3];  // the mirrored table's entries tid, tid + 256, tid + 512
 #pragma unroll
@@ -1341,17 +1350,20 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int vc = min(v0 + r, g.h - 1);
-    dpv[r] = dplane[(size_t)vc * g.w + uc];
-    s[r] = DD::load(self_desc, (size_t)vc * g.w + uc);
-    cell[r] = grid_div(vc, g) * g.gw + cu;
-    rng[r] = reinterpret_cast<const int2*>(grange)[cell[r]];
+    dpv[r] = (dplane + (size_t)vc * g.w)[(uint32_t)uc];
+    s[r] = DD::load_col(self_desc + (size_t)vc * g.w * DD::kBytes, (uint32_t)uc);
+    const int crow = grid_div(vc, g) * g.gw;  // wavefront-uniform
+    cell[r] = crow + cu;
+    rng[r] = (reinterpret_cast<const int2*>(grange) + crow)[(uint32_t)cu];
   }
+  // columns past c1 go to a spare slot after the rows (no branch)
 #pragma unroll
-  for (int k = 0; k < R * 2; ++k) {
-    const int i = (int)threadIdx.x + 256 * k;
-    const int r = dense_row_of<R>(i, nc), c = c0 + (i - r * nc);
-    if (i < nst) st[r * kDenseStage + (c - base)] = sv[k];
-  }
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int c = c0 + (int)threadIdx.x + 256 * k;
+      st[c <= c1 ? r * kDenseStage + (c - base) : R * kDenseStage] = sv[2 * r + k];
+    }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int i = (int)threadIdx.x + 256 * q;
@@ -1375,7 +1387,7 @@ template <int R>
 __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
   __shared__ int32_t s_lut[kLutSize];  // mirrored prior table, then zeros
   __shared__ int s_cnt[4];
-  __shared__ uint4 s_stage[R * kDenseStage];
+  __shared__ uint4 s_stage[R * kDenseStage + 1];  // + a spare slot for unused lanes
   const Geometry g = F.g;
   const KParams p = F.p;
   const bool right = (lb & 1) != 0;
@@ -1395,157 +1407,6 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
     else
       dense_rows<GradDense, false, R>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
   }
-  cnt = wave_sum_i32(cnt);
-  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) F.dense_counts[lb] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-}
-
-// ---------------------------------------------------------------------------
-// Pipelined dense matching (Sobel descriptors): a workgroup takes kPipeBands
-// consecutive bands of kPipeRows rows of one 256-column segment of one view.
-// While it matches one band, the loads of the next (the other view's
-// reachable descriptors for the staging buffer, and each pixel's own
-// descriptor, prior and region bit range) are in flight; two LDS buffers
-// alternate. The workgroup's setup (frame lookup, prior table) is paid once
-// for all its bands. A band's work and results are those of the 2-row dense
-// kernel.
-// ---------------------------------------------------------------------------
-constexpr int kPipeRows = 2;
-constexpr int kPipeBands = 4;
-
-__host__ __device__ __forceinline__ int pipe_groups(const Geometry& g) {
-  return cdivd(cdivd(g.h, kPipeRows), kPipeBands);
-}
-
-// A band's loads: staging (two per thread and row, in-bounds addresses) and
-// each pixel's own values.
-struct PipeLoads {
-  uint4 sv[2 * kPipeRows];
-  uint4 s[kPipeRows];
-  int dpv[kPipeRows];
-  int cell[kPipeRows];
-  int2 rng[kPipeRows];
-};
-
-template <bool right>
-__device__ __forceinline__ void pipe_issue(const Frame& F, const Geometry& g, const KParams& p,
-                                           int v0, int u0, PipeLoads& L) {
-  const uint8_t* other = right ? F.descL : F.descR;
-  const uint8_t* self_desc = right ? F.descR : F.descL;
-  const int16_t* dplane = right ? F.dplaneR : F.dplaneL;
-  const int32_t* grange = right ? F.grangeR : F.grangeL;
-  const int base = right ? u0 + p.dmin : u0 - p.dmax;
-  const int c0 = max(0, base), c1 = min(g.w - 1, base + kDenseSeg + p.D - 2);
-  const int nc = c1 - c0 + 1, nst = nc * min(kPipeRows, g.h - v0);
-#pragma unroll
-  for (int k = 0; k < 2 * kPipeRows; ++k) {
-    const int i = min((int)threadIdx.x + 256 * k, nst - 1);
-    const int r = dense_row_of<kPipeRows>(i, nc), c = c0 + (i - r * nc);
-    L.sv[k] = ld16(other + ((size_t)(v0 + r) * g.w + c) * 16);
-  }
-  const int uc = min(u0 + (int)threadIdx.x, g.w - 1);
-  const int cu = grid_div(uc, g);
-#pragma unroll
-  for (int r = 0; r < kPipeRows; ++r) {
-    const int vc = min(v0 + r, g.h - 1);
-    L.dpv[r] = dplane[(size_t)vc * g.w + uc];
-    L.s[r] = ld16(self_desc + ((size_t)vc * g.w + uc) * 16);
-    L.cell[r] = grid_div(vc, g) * g.gw + cu;
-    L.rng[r] = reinterpret_cast<const int2*>(grange)[L.cell[r]];
-  }
-}
-
-template <bool right>
-__device__ __forceinline__ void pipe_store(const Geometry& g, const KParams& p, int v0, int u0,
-                                           const PipeLoads& L, uint4* st) {
-  const int base = right ? u0 + p.dmin : u0 - p.dmax;
-  const int c0 = max(0, base), c1 = min(g.w - 1, base + kDenseSeg + p.D - 2);
-  const int nc = c1 - c0 + 1, nst = nc * min(kPipeRows, g.h - v0);
-#pragma unroll
-  for (int k = 0; k < 2 * kPipeRows; ++k) {
-    const int i = (int)threadIdx.x + 256 * k;
-    const int r = dense_row_of<kPipeRows>(i, nc), c = c0 + (i - r * nc);
-    if (i < nst) st[r * kDenseStage + (c - base)] = L.sv[k];
-  }
-}
-
-template <bool right>
-__device__ __forceinline__ void pipe_match(const Frame& F, const Geometry& g, const KParams& p,
-                                           int v0, int u0, const PipeLoads& L,
-                                           const uint4* st, const int32_t* s_lut,
-                                           bool has_list, const WinPrior& wp, int* cnt) {
-  const uint32_t* grid = right ? F.gridR : F.gridL;
-  int16_t* raw = right ? F.rawR : F.rawL;
-  const int base = right ? u0 + p.dmin : u0 - p.dmax;
-  const int u = u0 + (int)threadIdx.x;
-#pragma unroll
-  for (int r = 0; r < kPipeRows; ++r) {
-    const int v = v0 + r;
-    if (u >= g.w || v >= g.h) continue;
-    int res = -1;
-    if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3)
-      res = dense_pixel<GradDense, right>(g, p, u, L.dpv[r], L.rng[r].x, L.rng[r].y,
-                                          grid + (size_t)L.cell[r] * g.gwords, has_list, L.s[r],
-                                          st + r * kDenseStage, base, s_lut, wp, cnt);
-    raw[(size_t)v * g.w + u] = (int16_t)res;
-  }
-}
-
-template <bool right>
-__device__ __forceinline__ void pipe_view(const Frame& F, int grp, int u0, int32_t* s_lut,
-                                          uint4* stage, int* cnt) {
-  const Geometry g = F.g;
-  const KParams p = F.p;
-  const int nbands = cdivd(g.h, kPipeRows);
-  const int b0 = grp * kPipeBands, nb = min(kPipeBands, nbands - b0);
-  const bool has_list = F.hdr->n[0] > 0;
-  const int32_t* lut = F.lut;
-  WinPrior wp;
-  wp.p0 = (uint32_t)(lut[0] + p.lut_bias);
-  wp.p1 = (uint32_t)(lut[min(1, p.D - 1)] + p.lut_bias);
-  wp.p2 = (uint32_t)(lut[min(2, p.D - 1)] + p.lut_bias);
-  int32_t lv[3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int i = (int)threadIdx.x + 256 * q;
-    const int32_t x = lut[min(abs(i - kLutC), p.D - 1)];
-    lv[q] = i <= 2 * kLutC ? x : 0;
-  }
-  PipeLoads L[2];
-  pipe_issue<right>(F, g, p, b0 * kPipeRows, u0, L[0]);
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int i = (int)threadIdx.x + 256 * q;
-    if (i < kLutSize) s_lut[i] = lv[q];
-  }
-  // bands k = 0 .. nb-1, unrolled so that each band's loads keep registers
-  // of their own; band k + 1 is issued before band k is matched
-#pragma unroll
-  for (int k = 0; k < kPipeBands; ++k) {
-    if (k >= nb) break;
-    const int v0 = (b0 + k) * kPipeRows;
-    uint4* st = stage + (k & 1) * (kPipeRows * kDenseStage);
-    pipe_store<right>(g, p, v0, u0, L[k & 1], st);
-    if (k + 1 < nb) pipe_issue<right>(F, g, p, v0 + kPipeRows, u0, L[(k + 1) & 1]);
-    __syncthreads();
-    pipe_match<right>(F, g, p, v0, u0, L[k & 1], st, s_lut, has_list, wp, cnt);
-  }
-}
-
-__device__ __forceinline__ void dense_pipe_body(const Frame& F, int lb) {
-  __shared__ int32_t s_lut[kLutSize];
-  __shared__ int s_cnt[4];
-  __shared__ uint4 s_stage[2 * kPipeRows * kDenseStage];
-  const Geometry g = F.g;
-  const bool right = (lb & 1) != 0;
-  const int nseg = dense_segments(g);
-  const int rs = lb >> 1, grp = rs / nseg, u0 = (rs - grp * nseg) * kDenseSeg;
-  int cnt = 0;
-  if (right)
-    pipe_view<true>(F, grp, u0, s_lut, s_stage, &cnt);
-  else
-    pipe_view<false>(F, grp, u0, s_lut, s_stage, &cnt);
   cnt = wave_sum_i32(cnt);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
@@ -1703,7 +1564,6 @@ ELAS_STAGE_KERNELS(k_raster256, raster_body<256>, 256)
 ELAS_STAGE_KERNELS(k_dense_r1, dense_body<1>, 256)
 ELAS_STAGE_KERNELS(k_dense_r2, dense_body<2>, 256)
 ELAS_STAGE_KERNELS(k_dense_r4, dense_body<4>, 256)
-ELAS_STAGE_KERNELS(k_dense_pipe, dense_pipe_body, 256)
 ELAS_STAGE_KERNELS(k_check, check_body, 256)
 ELAS_STAGE_KERNELS(k_redun, redun_body, 1024)
 ELAS_STAGE_KERNELS(k_median, median_body, 256)
@@ -1731,7 +1591,6 @@ int stage_threads(int32_t stage) {
 int32_t raster_band_rows(int32_t w) { return std::max(1, std::min(kBandRowsMax, 4096 / w)); }
 
 int32_t dense_blocks(const Geometry& g, int variant) {
-  if (variant == kDensePipe) return 2 * pipe_groups(g) * dense_segments(g);
   return 2 * cdiv(g.h, kDenseRowsOf[std::min(std::max(variant, 0), kDenseVariants - 1)]) *
          dense_segments(g);
 }
@@ -1800,13 +1659,11 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
       else
         go(k_raster256);
       break;
-    case kStageDense:  // census frames take the 2-row kernel for the pipelined variant
+    case kStageDense:
       if (variant == 0)
         go(k_dense_r1);
       else if (variant == 2)
         go(k_dense_r4);
-      else if (variant == kDensePipe && f.p.descriptor == 0)
-        go(k_dense_pipe);
       else
         go(k_dense_r2);
       break;
@@ -1849,8 +1706,6 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
         go(k_dense_r1_batch, 0u);
       else if (variant == 2)
         go(k_dense_r4_batch, 0u);
-      else if (variant == kDensePipe)
-        go(k_dense_pipe_batch, 0u);
       else
         go(k_dense_r2_batch, 0u);
       break;

@@ -72,7 +72,7 @@ def test_batch_mixed_sizes_bit_exact(E, graph, autotune):
             if D == 64:
                 h, w = p.left.shape
                 rows, batch = base.tuned_variants(w, h)
-                assert rows in (4, 8, 16) and batch in (0, 1, 2, 4)  # dense rows (0: persistent)
+                assert rows in (4, 8, 16) and batch in (1, 2, 4)  # dense rows per block
 
 
 def test_batch_graph_replay_with_new_inputs(E):

@@ -90,7 +90,7 @@ def test_batch_96_mixed_pairs_one_call(E):
         c = synth.SHAPES[nm]
         if c.disp_range == 128:
             rows, kb = base.tuned_variants(c.width, c.height)
-            assert rows in (4, 8, 16) and kb in (0, 1, 2, 4)  # dense rows (0: persistent)
+            assert rows in (4, 8, 16) and kb in (1, 2, 4)  # dense rows per block
 
 
 def stage_mismatches(get, t):
