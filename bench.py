@@ -24,15 +24,17 @@ roofline        the kernel with the largest share of chip time in a step
 batch           96 pairs of mixed resolutions and disparity ranges (seeded
                 synthetic, pair i from seed i), one batched call each repetition,
                 against 96 sequential plain calls
-serve           16 camera streams with Poisson arrivals at three aggregate
-                rates: p50/p99 latency and sustained pairs/s of the batching
-                server and of the one-pair-at-a-time server
+serve           16 camera streams with Poisson arrivals at the six swept
+                aggregate rates 200..2000 pairs/s and one beyond them: p50/p99
+                latency and sustained pairs/s of the batching server and of the
+                one-pair-at-a-time server
 variants        frames/s of the same pair under the embedded variant and the
                 optional steps (census descriptors, eq. 3, past-only redundancy,
                 support down-sampling, median filter), each bit-exact to the
                 oracle in the test-suite
 cpu_baseline    the CPU oracle (single-threaded C) on a bounded sample of the
-                same workload, on this host
+                same workload, on this host; per stage, the median of 5 runs at
+                320x240, 640x480 and 1242x375; the CPU model and core count
 
 --mode calib runs a plain device copy of a known size (reads and writes
 COPY_BYTES per launch) so that rocprofv3's FETCH_SIZE / WRITE_SIZE counters
@@ -64,7 +66,7 @@ PEAK_SAD_TOPS = 256 * 64 * 2.4e9 * 4 / 1e12    # 157.3 T byte-|diff| per second
 
 STAGES = ["descriptor", "support", "filter", "rows", "mesh", "raster", "dense", "lrcheck"]
 KERNEL_NAMES = {"descriptor": "k_descriptor8", "support": "k_support", "filter": "k_filter",
-                "rows": "k_rows", "mesh": "k_mesh", "raster": "k_raster", "dense": "k_dense2",
+                "rows": "k_rows", "mesh": "k_mesh", "raster": "k_raster", "dense": "k_dense_r2",
                 "lrcheck": "k_check"}
 
 
@@ -246,7 +248,15 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+ORACLE_STAGES = ("descriptor", "support_match_filter_lists", "triangulate_plane_raster", "grid",
+                 "dense", "lrcheck")
+
+
 def cpu_baseline(left, right, disp_max, budget_s=12.0, max_frames=200):
+    """The oracle on this host: frames/s of the bench pair over a bounded
+    sample (one thread), and per stage the median of 5 runs (monotonic clock)
+    at the three single-frame workload shapes."""
+    import synth
     from oracle import ref   # the CPU oracle, timed as a reported baseline
     p = ref.params(disp_max=disp_max)
     ref.process(p, left[:64, :64].copy(), right[:64, :64].copy())  # load + warm
@@ -258,9 +268,25 @@ def cpu_baseline(left, right, disp_max, budget_s=12.0, max_frames=200):
             break
     dt = time.perf_counter() - t0
     h, w = left.shape
+    per_config = {}
+    for name in ("320x240", "640x480", "1242x375"):
+        cfg = synth.SHAPES[name]
+        pr = synth.make_pair(cfg)
+        pc = ref.params(disp_max=cfg.disp_range - 1)
+        runs = [ref.process(pc, pr.left, pr.right).stage_ms for _ in range(5)]
+        med = [float(np.median([r[k] for r in runs])) for k in range(len(ORACLE_STAGES))]
+        per_config[f"{name} D={cfg.disp_range}"] = {
+            "stage_ms_median_of_5": {k: round(v, 3) for k, v in zip(ORACLE_STAGES, med)},
+            "frame_ms": round(sum(med), 3), "fps": round(1000.0 / sum(med), 3)}
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
     return {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} full {w}x{h} D={disp_max + 1} frames of the bench pair, "
-                      f"{dt:.1f} s, single-threaded C oracle (-O2), {cpu_model()}"}
+                      f"{dt:.1f} s, single-threaded C oracle (-O2), {cpu_model()}",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "usable_cores": usable,
+            "per_config": per_config}
 
 
 def batch_c4(torch, Elas, reps=5, n=96):
@@ -462,6 +488,26 @@ def main():
     evals = (st["support_evals"] + st["dense_evals"]) / B
     nominal = 2 * W * H * D
 
+    # single-frame latency (the plain path, one frame at a time on one stream):
+    # host wall time from the call to the end of its work, and the device span
+    # from the first kernel's start to the last one's end (HIP events)
+    lat_wall, lat_dev = [], []
+    for i in range(60):
+        torch.cuda.synchronize()
+        e.set_timing(i >= 30)
+        t0 = time.perf_counter()
+        e.process(L, R, outs[0][0][0], outs[0][0][1], stream=stream)
+        stream.synchronize()
+        if i >= 30:
+            lat_wall.append((time.perf_counter() - t0) * 1e3)
+            lat_dev.append(e.timing()["device_span_ms"])
+        else:
+            lat_wall.append((time.perf_counter() - t0) * 1e3)
+    e.set_timing(False)
+    single = {"wall_ms_median": round(float(np.median(lat_wall[:30])), 4),
+              "device_span_ms_median": round(float(np.median(lat_dev)), 4),
+              "fps_one_stream": None}
+
     # per-stage device times of one step: HIP events (hipExtLaunchKernel)
     # recorded by the library on `stream` around each launch
     e.set_timing(True)
@@ -482,8 +528,8 @@ def main():
     kernel_ms = {s: stage_ms[s] for s in KERNEL_NAMES}
     names = dict(KERNEL_NAMES)
     if B > 1:  # the batched kernels (their untuned tile variants; the raster's 256 threads)
-        names = {s: {"raster": "k_raster256", "descriptor": "k_descriptor16",
-                     "dense": "k_dense1"}.get(s, n) + "_batch" for s, n in names.items()}
+        names = {s: {"raster": "k_raster256", "descriptor": "k_descriptor16"}.get(s, n) + "_batch"
+                 for s, n in names.items()}
     # share of chip time: duration x the fraction of the 256 CUs the kernel's
     # workgroups can occupy (launch geometry of each stage at this size)
     wgs = workgroups(W, H, D)
@@ -496,6 +542,7 @@ def main():
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
         "fps_plain_calls": round(fps_plain, 2), "fps_one_stream": round(fps_one, 2),
+        "single_frame": dict(single, fps_one_stream=round(fps_one, 2)),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"{W}x{H} D={D}, {B} stereo pair(s) per step (one batched call), "
@@ -519,20 +566,24 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_c4(torch, Elas)
     if not args.no_serve:
-        # a short serving sweep (three arrival rates, 3 s each; --mode serve runs
-        # the full one): p50/p99 latency of the batched server and the plain one
+        # the serving sweep over the six swept rates 200..2000 pairs/s (2 s each;
+        # --mode serve runs longer levels) and one rate beyond them, where one
+        # pair at a time no longer keeps up: p50/p99 latency of the batched
+        # server and of the plain one
         from paper_1802_07210_amd import serve
         cams, handles = serve.build_cameras()
-        rates = (200, 2000, 8000)
-        sb = serve.run_sweep(rates=rates, seconds=3.0, cams=cams, handles=handles)
-        sp = serve.run_sweep(rates=rates, seconds=3.0, plain=True, cams=cams, handles=handles)
-        out["serve"] = {"cameras": 16, "seconds_per_rate": 3.0,
+        rates = (200, 400, 800, 1200, 1600, 2000, 12000)
+        sb = serve.run_sweep(rates=rates, seconds=2.0, cams=cams, handles=handles)
+        sp = serve.run_sweep(rates=rates, seconds=2.0, plain=True, cams=cams, handles=handles)
+        out["serve"] = {"cameras": 16, "seconds_per_rate": 2.0,
+                        "memory_budget": sb["memory_budget"],
                         "batched": [{k: lv[k] for k in ("rate", "sustained_pairs_per_s", "p50_ms",
                                                         "p99_ms", "mean_batch")}
                                     for lv in sb["levels"]],
                         "plain": [{k: lv[k] for k in ("rate", "sustained_pairs_per_s", "p50_ms",
                                                       "p99_ms")} for lv in sp["levels"]],
-                        "peak_bytes_in_flight": sb["peak_bytes_in_flight"]}
+                        "peak_bytes_in_flight": sb["peak_bytes_in_flight"],
+                        "peak_resident_bytes": sb["peak_resident_bytes"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair.left, pair.right, D - 1)
     print(json.dumps(out), flush=True)

@@ -265,13 +265,19 @@ ELAS_API int elas_set_tile_variants(elas_handle* h, int32_t w, int32_t h_px, int
  * against its memory budget. No HIP call. */
 ELAS_API int elas_frame_bytes(elas_handle* h, int32_t w, int32_t h_px, int64_t* bytes);
 
+/* Device bytes the handle holds now: the buffer sets of every (size, stream)
+ * of single and batched calls, and the batch tables. No HIP call. */
+ELAS_API int elas_device_bytes(elas_handle* h, int64_t* bytes);
+
 /* ---- serving: continuous batching of pairs from many cameras ----------
  * A server owns a worker thread and max_inflight streams. elas_server_submit
  * queues a pair (device images and outputs, caller-owned until the ticket
  * completes) and returns a ticket at once. Whenever a stream is free and
  * pairs wait, the worker launches the longest-waiting ones (up to max_batch,
- * and only while the footprint of all pairs in flight stays within
- * memory_budget) as one elas_process_batch call; pairs that arrive while
+ * and only while the buffer sets they need fit memory_budget: a stream keeps
+ * one set of elas_frame_bytes per pair of a size in its largest batch; when
+ * the oldest pair does not fit, idle streams' sets are freed first) as one
+ * elas_process_batch call; pairs that arrive while
  * others run are admitted as streams and memory free up, and overlap on the
  * device with the batches already running. With plain = 1 the server runs
  * one pair at a time through elas_process (the unbatched baseline). Results
@@ -283,15 +289,18 @@ typedef struct elas_server elas_server;
 typedef struct elas_server_config {
   int32_t max_batch;            /* pairs per launch, 1..1024 (32) */
   int32_t max_inflight;         /* batches on the device at once, 1..16 (3) */
-  int64_t memory_budget;        /* device bytes of the pairs in flight (32 GiB) */
+  int64_t memory_budget;        /* device bytes the server's pairs may keep resident:
+                                   buffer sets per (stream, size), (32 GiB) */
   int32_t plain;                /* 1: one pair at a time via elas_process (0) */
 } elas_server_config;
 typedef struct elas_server_stats {
   int64_t submitted, completed;
   int64_t batches, batched_pairs;  /* launches and the pairs they carried */
-  int64_t peak_bytes_in_flight;
+  int64_t peak_bytes_in_flight;    /* footprint of the pairs on the device at once */
   int64_t queued;                  /* waiting now */
   int64_t bytes_in_flight;         /* admitted now */
+  int64_t resident_bytes;          /* buffer sets held for the server's pairs now */
+  int64_t peak_resident_bytes;     /* and at most; never above memory_budget */
 } elas_server_stats;
 ELAS_API void elas_server_config_default(elas_server_config* c);
 /* ELAS_ERR_ARG for out-of-range settings, ELAS_ERR_HIP if streams fail. */

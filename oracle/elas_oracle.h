@@ -192,7 +192,8 @@ typedef struct orc_trace {
   int16_t* rawL; int16_t* rawR;               /* h*w */
   int16_t* outL; int16_t* outR;               /* h*w */
   int64_t support_evals, dense_evals;
-  double stage_ms[6]; /* descriptor, support+filter, triangulate, raster+grid, dense, lrcheck */
+  double stage_ms[6]; /* descriptor, support+filter+lists, triangulate+planes+raster, grid,
+                         dense, lrcheck (+median) */
   int32_t swords, dwords;                     /* census words per pixel (census mode) */
   uint32_t* csupL; uint32_t* csupR;           /* h*w*swords, support census */
   uint32_t* cdenL; uint32_t* cdenR;           /* h*w*dwords, dense census */

@@ -93,6 +93,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Device and pinned host memory for one image size.
 struct Buffers {
   Geometry g{};
+  size_t bytes = 0;              // device bytes of dev_block
   int32_t ntmax = 0;             // triangle capacity per view (2 * lattice + 2)
   void* dev_block = nullptr;     // every device array, carved below
   uint8_t *descL = nullptr, *descR = nullptr;
@@ -422,6 +423,7 @@ int alloc_buffers(elas_handle* h, int32_t w, int32_t hp, Buffers** out) {
                 std::string("hipMalloc of device buffers: ") + hipGetErrorString(e));
   }
   carve_buffers(Lo, h->params, static_cast<uint8_t*>(b->dev_block), b);
+  b->bytes = Lo.total;
   // host-mapped per-row lists for the host mesh mode
   const size_t hcount = 3 * nrows + 2 * nlat;
   e = hipHostMalloc(&b->host_block, hcount * sizeof(int32_t), hipHostMallocMapped);
@@ -1338,7 +1340,53 @@ int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipSt
   return ELAS_OK;
 }
 
+int64_t elas::release_stream_buffers(elas_handle* h, hipStream_t stream) {
+  (void)hipStreamSynchronize(stream);
+  int64_t freed = 0;
+  bool last_freed = false;
+  auto drop = [&](Buffers* b) {
+    freed += (int64_t)b->bytes;
+    if (b == h->last) last_freed = true;
+    for (auto& q : h->last_batch)
+      if (q.b == b) q.b = nullptr;
+    free_buffers(b);
+  };
+  for (auto it = h->cache.begin(); it != h->cache.end();) {
+    if (std::get<2>(it->first) == stream) {
+      drop(it->second);
+      it = h->cache.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  for (auto it = h->pool.begin(); it != h->pool.end();) {
+    if (std::get<2>(it->first) == stream) {
+      for (Buffers* b : it->second) drop(b);
+      it = h->pool.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  if (last_freed) {
+    h->last = nullptr;
+    h->have_result = false;
+    h->have_timing = false;
+  }
+  return freed;
+}
+
 extern "C" {
+
+int elas_device_bytes(elas_handle* h, int64_t* bytes) {
+  if (!h || !bytes) return fail(h, ELAS_ERR_ARG, "null argument");
+  int64_t n = 0;
+  for (auto& kv : h->cache) n += (int64_t)kv.second->bytes;
+  for (auto& kv : h->pool)
+    for (Buffers* b : kv.second) n += (int64_t)b->bytes;
+  for (auto& kv : h->batch) n += (int64_t)(kv.second->dev_cap + kv.second->tune_cap);
+  *bytes = n;
+  return ELAS_OK;
+}
 
 int elas_frame_bytes(elas_handle* h, int32_t w, int32_t hp, int64_t* bytes) {
   if (!h || !bytes) return fail(h, ELAS_ERR_ARG, "null argument");
@@ -1586,7 +1634,11 @@ int elas_get_batch_intermediate(elas_handle* h, int32_t pair, int32_t which, voi
   if (pair < 0 || pair >= (int32_t)h->last_batch.size())
     return fail(h, ELAS_ERR_ARG, "no such pair in the last batch");
   const elas_handle::BatchPair& q = h->last_batch[pair];
-  if (!q.b) return fail(h, ELAS_ERR_ARG, "the pair did not complete");
+  // the buffers must still be the parameter handle's (not released since)
+  bool held = q.b && q.b == q.ph->last && q.on_host;
+  for (auto& kv : q.ph->pool)
+    for (Buffers* b : kv.second) held |= b == q.b;
+  if (!held) return fail(h, ELAS_ERR_ARG, "the pair's buffers are no longer held");
   return read_intermediate(h, q.ph, q.b, q.stream, q.on_host, which, dst, bytes, needed);
 }
 

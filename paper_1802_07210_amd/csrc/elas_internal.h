@@ -261,4 +261,7 @@ int process_one(elas_handle* h, const uint8_t* left, const uint8_t* right, int32
                 int16_t* disp_right, int32_t* report);
 int process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipStream_t stream,
                   int32_t* const* reports);
+// Frees the device buffers h keeps for calls on `stream` (single calls and
+// batch pools, every size) after the stream has finished; returns their bytes.
+int64_t release_stream_buffers(elas_handle* h, hipStream_t stream);
 }  // namespace elas

@@ -9,9 +9,10 @@
 // admit, and launches them as one elas_process_batch call. Requests that
 // arrive while others run are therefore admitted as soon as a stream and
 // memory free up, and their work overlaps the batches already on the device.
-// The memory budget bounds the device footprint (elas_frame_bytes) of the
-// requests in flight; the buffers themselves stay resident in the handles'
-// per-(size, stream) pools between batches. Latency is measured on the host
+// The memory budget bounds the device memory the server's pairs keep
+// resident: the buffer sets (elas_frame_bytes each) that the handles hold per
+// (stream, size) between batches. New sets are admitted against it, and the
+// sets of idle streams are released when the oldest request needs room. Latency is measured on the host
 // from submission to the worker seeing the batch's completion event.
 #include <chrono>
 #include <condition_variable>
@@ -70,6 +71,10 @@ struct elas_server {
   std::vector<Slot> slots;
   std::unordered_map<int64_t, Result> results;
   std::map<std::tuple<elas_handle*, int32_t, int32_t>, int64_t> footprint;
+  // buffer sets the library keeps for this server's pairs, per (slot, pair
+  // parameter handle, w, h), and their device bytes
+  std::map<std::tuple<int, elas_handle*, int32_t, int32_t>, int> sets;
+  int64_t resident = 0;
   int64_t next_ticket = 1;
   int64_t in_flight = 0;
   std::vector<hipEvent_t> free_events;  // ready events not in use
@@ -118,6 +123,32 @@ void finish(elas_server* S, Slot& sl, State st, int code, Clock::time_point now)
   sl.busy = false;
 }
 
+// Releases the buffer sets of every idle slot (their streams have finished);
+// returns whether anything was released.
+bool release_idle(elas_server* S) {
+  bool any = false;
+  for (size_t j = 0; j < S->slots.size(); ++j) {
+    if (S->slots[j].busy) continue;
+    std::map<elas_handle*, int64_t> held;  // per handle: bytes of its sets on this slot
+    for (auto it = S->sets.begin(); it != S->sets.end();) {
+      if (std::get<0>(it->first) != (int)j) {
+        ++it;
+        continue;
+      }
+      elas_handle* ph = std::get<1>(it->first);
+      const auto kind = std::make_tuple(ph, std::get<2>(it->first), std::get<3>(it->first));
+      held[ph] += S->footprint[kind] * it->second;
+      it = S->sets.erase(it);
+    }
+    for (auto& kv : held) {
+      (void)elas::release_stream_buffers(kv.first, S->slots[j].stream);
+      S->resident -= kv.second;
+      any = true;
+    }
+  }
+  return any;
+}
+
 void worker_loop(elas_server* S) {
   std::unique_lock<std::mutex> lk(S->m);
   for (;;) {
@@ -138,23 +169,53 @@ void worker_loop(elas_server* S) {
       }
     }
     if (any_done) S->done.notify_all();
-    // launches: oldest requests first, while a stream is free and they fit
-    for (Slot& sl : S->slots) {
+    // launches: oldest requests first, while a stream is free and the buffer
+    // sets they need fit the budget. A batch with k pairs of one kind (pair
+    // parameters and size) on a slot needs k buffer sets of that kind there;
+    // sets the slot already holds are reused, new ones count against the
+    // budget. When the oldest request does not fit, the sets of idle slots
+    // are released once and it is tried again; otherwise it waits.
+    for (size_t si = 0; si < S->slots.size(); ++si) {
+      Slot& sl = S->slots[si];
       if (sl.busy || S->queue.empty()) continue;
       const int maxb = S->cfg.plain ? 1 : S->cfg.max_batch;
       std::vector<elas_pair> pairs;
       std::vector<int64_t> tickets;
       std::vector<hipEvent_t> ready;
-      int64_t bytes = 0;
-      while (!S->queue.empty() && (int)pairs.size() < maxb &&
-             S->in_flight + bytes + S->queue.front().bytes <= S->cfg.memory_budget) {
-        pairs.push_back(S->queue.front().pair);
-        tickets.push_back(S->queue.front().ticket);
-        ready.push_back(S->queue.front().ready);
-        bytes += S->queue.front().bytes;
+      std::map<std::tuple<elas_handle*, int32_t, int32_t>, int> kinds;
+      int64_t bytes = 0, grow = 0;
+      bool released = false;
+      while (!S->queue.empty() && (int)pairs.size() < maxb) {
+        const Request& q = S->queue.front();
+        elas_handle* ph = q.pair.params ? q.pair.params : S->h;
+        const auto kind = std::make_tuple(ph, q.pair.w, q.pair.h);
+        const int need = kinds.count(kind) ? kinds[kind] + 1 : 1;
+        const auto skey = std::make_tuple((int)si, ph, q.pair.w, q.pair.h);
+        const auto sit = S->sets.find(skey);
+        const int have = sit == S->sets.end() ? 0 : sit->second;
+        const int64_t extra = need > have ? q.bytes : 0;
+        if (S->resident + grow + extra > S->cfg.memory_budget) {
+          if (!pairs.empty() || released) break;
+          released = true;
+          if (release_idle(S)) continue;
+          break;
+        }
+        kinds[kind] = need;
+        grow += extra;
+        pairs.push_back(q.pair);
+        tickets.push_back(q.ticket);
+        ready.push_back(q.ready);
+        bytes += q.bytes;
         S->queue.pop_front();
       }
       if (pairs.empty()) break;  // the oldest request waits for memory
+      for (auto& kv : kinds) {
+        int& n = S->sets[std::make_tuple((int)si, std::get<0>(kv.first), std::get<1>(kv.first),
+                                         std::get<2>(kv.first))];
+        n = std::max(n, kv.second);
+      }
+      S->resident += grow;
+      S->stats.peak_resident_bytes = std::max(S->stats.peak_resident_bytes, S->resident);
       for (size_t i = 0; i < pairs.size(); ++i)
         __atomic_store_n(&sl.report_host[i], 0, __ATOMIC_RELAXED);
       sl.busy = true;
@@ -389,6 +450,7 @@ int elas_server_get_stats(elas_server* s, elas_server_stats* out) {
   *out = s->stats;
   out->queued = (int64_t)s->queue.size();
   out->bytes_in_flight = s->in_flight;
+  out->resident_bytes = s->resident;
   return ELAS_OK;
 }
 

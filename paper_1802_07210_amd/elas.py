@@ -26,7 +26,8 @@ EXPORTS = ("elas_params_default", "elas_create", "elas_destroy", "elas_process",
            "elas_server_create", "elas_server_submit", "elas_server_wait", "elas_server_poll",
            "elas_server_get_stats", "elas_server_last_error", "elas_server_destroy",
            "elas_server_submit_on", "elas_set_mesh_round_limit",
-           "elas_get_batch_intermediate", "elas_process_noalloc", "elas_set_tile_variants")
+           "elas_get_batch_intermediate", "elas_process_noalloc", "elas_set_tile_variants",
+           "elas_device_bytes")
 
 BATCH_GRAPH = 1
 BATCH_AUTOTUNE = 2
@@ -85,7 +86,8 @@ class ServerConfig(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
                 ("batched_pairs", C.c_int64), ("peak_bytes_in_flight", C.c_int64),
-                ("queued", C.c_int64), ("bytes_in_flight", C.c_int64)]
+                ("queued", C.c_int64), ("bytes_in_flight", C.c_int64),
+                ("resident_bytes", C.c_int64), ("peak_resident_bytes", C.c_int64)]
 
 
 # name -> (enum value, numpy dtype, trailing shape kind)
@@ -141,6 +143,7 @@ def lib() -> C.CDLL:
                                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.elas_set_tile_variants.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.elas_frame_bytes.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
+        L.elas_device_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
         L.elas_server_config_default.argtypes = [C.POINTER(ServerConfig)]
         L.elas_server_config_default.restype = None
         L.elas_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
@@ -297,6 +300,12 @@ class Elas:
 
     def set_tile_variants(self, w: int, h: int, desc_rows: int, dense_rows: int):
         _check(lib().elas_set_tile_variants(self._h, w, h, desc_rows, dense_rows), self._h)
+
+    def device_bytes(self) -> int:
+        """Device bytes the handle holds (buffer sets of every size and stream)."""
+        b = C.c_int64()
+        _check(lib().elas_device_bytes(self._h, C.byref(b)), self._h)
+        return b.value
 
     def tuned_variants(self, w: int, h: int):
         r, b = C.c_int32(), C.c_int32()

@@ -120,4 +120,5 @@ def run_sweep(rates: Sequence[float] = (200, 400, 800, 1200, 1600, 2000),
     server.close()
     return {"mode": "plain" if plain else "batched", "max_batch": max_batch,
             "max_inflight": max_inflight if not plain else 1, "memory_budget": budget,
-            "peak_bytes_in_flight": st["peak_bytes_in_flight"], "levels": levels}
+            "peak_bytes_in_flight": st["peak_bytes_in_flight"],
+            "peak_resident_bytes": st["peak_resident_bytes"], "levels": levels}

@@ -85,7 +85,9 @@ def test_server_admission_budget(E):
         srv.wait(t)
     st = srv.stats()
     assert st["peak_bytes_in_flight"] <= int(2.5 * one)
-    assert st["batches"] >= 2  # at most two 320x240 frames fit at once
+    assert st["peak_resident_bytes"] <= int(2.5 * one)
+    assert st["batches"] >= 2  # at most two 320x240 buffer sets fit at once
+    assert st["resident_bytes"] <= int(2.5 * one)
     oracle_check(reqs)
     with pytest.raises(E.ElasError):  # larger than the whole budget
         srv.submit(torch.zeros((1000, 1000), dtype=torch.uint8, device="cuda:0"),
@@ -93,6 +95,10 @@ def test_server_admission_budget(E):
                    torch.zeros((1000, 1000), dtype=torch.int16, device="cuda:0"),
                    torch.zeros((1000, 1000), dtype=torch.int16, device="cuda:0"), hs[64])
     srv.close()
+    # the handles (theirs again once the server is closed) hold what the
+    # server accounted for, plus small batch tables
+    held = sum(h.device_bytes() for h in hs.values()) + base.device_bytes()
+    assert held <= st["resident_bytes"] + (1 << 20)
 
 
 def test_server_plain_mode(E):
@@ -126,3 +132,40 @@ def test_server_poll_and_unknown_ticket(E):
     with pytest.raises(E.ElasError):
         srv.wait(t)  # a ticket is reported once
     srv.close()
+
+
+def test_server_budget_with_full_size_frames(E):
+    # the four full workload shapes under a budget of three 1280x720 buffer
+    # sets: new sets are admitted against the budget, idle streams' sets are
+    # released when the oldest pair needs room, and what the library holds
+    # never exceeds it; every result equals the oracle's
+    import synth as S
+    names = list(S.SHAPES)
+    hs = {S.SHAPES[n].disp_range: E.Elas(disp_max=S.SHAPES[n].disp_range - 1) for n in names}
+    base = E.Elas(disp_max=127)
+    big = hs[192].frame_bytes(1280, 720)
+    budget = 3 * big
+    srv = E.Server(base, max_batch=8, max_inflight=3, memory_budget=budget)
+    dev = torch.device("cuda:0")
+    reqs = []
+    for k in range(12):
+        cfg = S.SHAPES[names[k % 4]].with_seed(500 + k)
+        p = S.make_pair(cfg)
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        oL = torch.full(p.left.shape, -9, dtype=torch.int16, device=dev)
+        oR = torch.full(p.left.shape, -9, dtype=torch.int16, device=dev)
+        reqs.append((p, cfg.disp_range, L, R, oL, oR))
+    tickets = [srv.submit(L, R, oL, oR, hs[D]) for _, D, L, R, oL, oR in reqs]
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    assert st["completed"] == 12
+    assert st["peak_resident_bytes"] <= budget
+    srv.close()
+    held = sum(h.device_bytes() for h in hs.values()) + base.device_bytes()
+    assert held <= st["resident_bytes"] + (1 << 20) <= budget + (1 << 20)
+    for p, D, _, _, oL, oR in reqs:
+        t = ref.process(ref.params(disp_max=D - 1), p.left, p.right)
+        assert np.array_equal(oL.cpu().numpy(), t.outL)
+        assert np.array_equal(oR.cpu().numpy(), t.outR)
