@@ -13,7 +13,10 @@
 //     region between two consecutive non-empty rows (the image's top and
 //     bottom edges act as extra rows) is a trapezoid, triangulated by the
 //     in-circle zipper over the two sorted rows, which for two horizontal
-//     rows is a merge of their edge u-sums (one lane per row edge). The two side
+//     rows is a merge of their edge u-sums (one lane per row edge). On a tie
+//     (four co-circular points, e.g. every lattice rectangle) the lower edge's
+//     triangle comes first, which gives the diagonal from the (v, u)-smallest
+//     of the four: the canonical fan, so such cells need no flip. The two side
 //     pockets between the rows' end points and the image border are
 //     polygons monotone in v with one straight side. Their stack
 //     triangulation has a closed form that is evaluated in parallel: the
@@ -433,7 +436,7 @@ __device__ __forceinline__ void strip_edge(int q, const uint32_t* pk, const int3
   int kb = -1, ka = -1;
   if (below >= 0) {
     const BandRow B = band_lower(below, m, n, rowStart, rowNE);
-    const int j = edges_below(pk, B, sum, false);
+    const int j = edges_below(pk, B, sum, true);
     const int k = stripOff[below] + idx + j;
     if (k < 0 || k + 1 > NT) {
       *err = 2;
@@ -451,7 +454,7 @@ __device__ __forceinline__ void strip_edge(int q, const uint32_t* pk, const int3
   }
   if (above >= 0) {
     const BandRow A = band_upper(above, rowStart, rowNE);
-    const int i = edges_below(pk, A, sum, true);
+    const int i = edges_below(pk, A, sum, false);
     const int k = stripOff[above] + i + idx;
     if (k < 0 || k + 1 > NT) {
       *err = 2;

@@ -4,8 +4,10 @@ on the CPU from their definitions.
 
 * Band zipper = merge. Between two horizontal rows of points the zipper that
   picks each diagonal by the exact in-circle test emits the same triangles,
-  in the same order, as a merge of the two rows' edge u-sums (upper edge
-  first on ties). The device places each band triangle by that merge.
+  in the same order, as a merge of the two rows' edge u-sums (lower edge
+  first on ties: the four points are co-circular, and that gives the
+  diagonal from the (v, u)-smallest of them, the canonical fan). The device
+  places each band triangle by that merge.
 * Band twins. In that order, a row edge joins the triangle of the band below
   (local vertex 2) and of the band above (local vertex 0), and consecutive
   triangles of a band share their diagonal: local vertex 0 of a top-edge
@@ -29,8 +31,9 @@ def incircle(a, b, c, d):
 
 
 def zipper(A, B):
-    """Sequential band zipper: advance on the upper row unless the next lower
-    point lies strictly inside the circle of the current upper edge."""
+    """Sequential band zipper: advance on the upper row while the next lower
+    point lies strictly outside the circle of the current upper edge (on it:
+    the lower row advances, the canonical fan diagonal)."""
     out, i, j = [], 0, 0
     while i + 1 < len(A) or j + 1 < len(B):
         if i + 1 >= len(A):
@@ -38,7 +41,7 @@ def zipper(A, B):
         elif j + 1 >= len(B):
             upper = True
         else:
-            upper = not incircle(A[i], A[i + 1], B[j], B[j + 1]) > 0
+            upper = incircle(A[i], A[i + 1], B[j], B[j + 1]) < 0
         if upper:
             out.append(("top", i, j))
             i += 1
@@ -49,16 +52,16 @@ def zipper(A, B):
 
 
 def merge(A, B):
-    """The same band by ranks: upper edge i sits at slot i + #(lower sums
-    below its sum), lower edge j at j + #(upper sums at or below its sum)."""
+    """The same band by ranks: upper edge i sits at slot i + #(lower sums at
+    or below its sum), lower edge j at j + #(upper sums below its sum)."""
     S = [A[i][0] + A[i + 1][0] for i in range(len(A) - 1)]
     T = [B[j][0] + B[j + 1][0] for j in range(len(B) - 1)]
     slots = {}
     for i, s in enumerate(S):
-        j = sum(1 for t in T if t < s)
+        j = sum(1 for t in T if t <= s)
         slots[i + j] = ("top", i, j)
     for j, t in enumerate(T):
-        i = sum(1 for s in S if s <= t)
+        i = sum(1 for s in S if s < t)
         slots[i + j] = ("bot", i, j)
     assert sorted(slots) == list(range(len(A) + len(B) - 2))
     return [slots[k] for k in range(len(slots))]
@@ -86,11 +89,13 @@ def test_band_zipper_is_a_merge_of_edge_sums(seed):
     assert n > 3000
 
 
-def test_tied_sums_take_the_upper_edge_first():
-    # u-sums 0+4 = 4 above and 1+3 = 4 below: B[1] lies exactly on the circle
+def test_tied_sums_take_the_lower_edge_first():
+    # u-sums 0+4 = 4 above and 1+3 = 4 below: B[1] lies exactly on the circle.
+    # The lower edge first gives the diagonal A[0]-B[1], from the
+    # (v, u)-smallest point A[0]: the canonical fan of the co-circular cell
     A, B = [(0, 0), (4, 0)], [(1, 5), (3, 5)]
     assert incircle(A[0], A[1], B[0], B[1]) == 0
-    assert zipper(A, B) == merge(A, B) == [("top", 0, 0), ("bot", 1, 0)]
+    assert zipper(A, B) == merge(A, B) == [("bot", 0, 0), ("top", 0, 1)]
 
 
 def band_mesh(rows):
