@@ -482,7 +482,10 @@ def main():
     for (Li, Ri) in imgs:
         e.process(Li, Ri, outs[0][0][0], outs[0][0][1], stream=stream)
         for k2, v2 in e.stats().items():
-            st[k2] = st.get(k2, 0) + v2
+            if isinstance(v2, list):
+                st[k2] = [a + b for a, b in zip(st.get(k2, [0] * len(v2)), v2)]
+            else:
+                st[k2] = st.get(k2, 0) + v2
     st["lattice"] = ((W - 5) // 5) * ((H - 5) // 5)   # per pair
     st["lattice_rows"] = (H - 5) // 5
     evals = (st["support_evals"] + st["dense_evals"]) / B

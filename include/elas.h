@@ -119,6 +119,9 @@ typedef struct elas_stats {
   int32_t n_tri_left;          /* triangles of the left-view mesh */
   int32_t n_tri_right;
   double  host_mesh_ms;        /* host time spent triangulating (both views) */
+  int32_t mesh_rounds[2];      /* device mesh: synchronous flip rounds, left and right
+                                  view (0 when meshed on the host) */
+  int32_t mesh_flips[2];       /* device mesh: edge flips, left and right view */
 } elas_stats;
 
 /* Per-kernel device times of the most recent elas_process call (only while

@@ -1514,6 +1514,10 @@ int elas_get_stats(elas_handle* h, elas_stats* out) {
   out->n_tri_left = hd.ntri[0];
   out->n_tri_right = hd.ntri[1];
   out->host_mesh_ms = h->host_mesh_ms;
+  for (int k = 0; k < 2; ++k) {
+    out->mesh_rounds[k] = hd.rounds[k];
+    out->mesh_flips[k] = hd.flips[k];
+  }
   return ELAS_OK;
 }
 

@@ -72,6 +72,8 @@ struct MeshHeader {
   int64_t support_evals; // support-search evaluations of the frame
   int32_t status[2];     // 0; 1 if a view's flip rounds hit their limit; 2 if its
                          // initial triangulation failed a consistency check
+  int32_t rounds[2];     // device mesh: flip rounds of each view (0 on the host)
+  int32_t flips[2];      // device mesh: edge flips of each view
 };
 
 // ---- host mesh builder (elas_mesh.cpp) ----------------------------------

@@ -820,6 +820,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
     }
   }
   __syncthreads();
+  int nflips = 0;  // thread 0's count of the view's flips
   for (int r = 1;; ++r) {
     const int cur = r & 1, nxt = cur ^ 1;
     I* const lf_cur = cur ? lf1 : lf0;
@@ -830,7 +831,13 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
       mesh_fail<I>(hdr, mfail, view, sh.err ? sh.err : 1);
       return;
     }
-    if (nc == 0) break;
+    if (nc == 0) {
+      if (tid == 0) {
+        hdr->rounds[view] = r - 1;
+        hdr->flips[view] = nflips;
+      }
+      break;
+    }
     if (tid == 0) sh.ncand[nxt] = 0;  // appended to only after the next barrier
     // winners flip: (p, a, b) + (q, b, a) -> (p, a, q) + (p, q, b). Both
     // triangles' entries are loaded before the claims are compared, from
@@ -891,6 +898,7 @@ __device__ __forceinline__ void mesh_run(char* base, const int32_t* __restrict__
     // candidates whose two triangles did not flip carry over. Both kinds run
     // side by side on different threads.
     const int nf = sh.nflip[cur];
+    nflips += nf >> 1;
     if (tid == 0) sh.nflip[nxt] = 0;  // appended to only after the next barrier
     for (int idx = tid; idx < 3 * nf + nc; idx += kMT) {
       if (idx < 3 * nf) {
@@ -1032,6 +1040,8 @@ __device__ __forceinline__ void mesh_body(const Frame& F, int view) {
     hdr->n[view] = n;
     hdr->ntri[view] = n > 0 ? 2 * n + 2 : 0;
     hdr->status[view] = 0;
+    hdr->rounds[view] = 0;
+    hdr->flips[view] = 0;
     if (view == 0) hdr->support_evals = evals;
     if (n == 0) {
       for (int c = 0; c < 4; ++c) hdr->corners[4 * view + c] = -1;

@@ -57,6 +57,7 @@ class ElasStats(C.Structure):
         ("n_support_left", C.c_int32), ("n_support_right", C.c_int32),
         ("n_tri_left", C.c_int32), ("n_tri_right", C.c_int32),
         ("host_mesh_ms", C.c_double),
+        ("mesh_rounds", C.c_int32 * 2), ("mesh_flips", C.c_int32 * 2),
     ]
 
 
@@ -315,7 +316,10 @@ class Elas:
     def stats(self) -> dict:
         st = ElasStats()
         _check(lib().elas_get_stats(self._h, C.byref(st)), self._h)
-        return {k: getattr(st, k) for k, _ in ElasStats._fields_}
+        out = {k: getattr(st, k) for k, _ in ElasStats._fields_}
+        for k in ("mesh_rounds", "mesh_flips"):
+            out[k] = list(out[k])
+        return out
 
     def set_mesh_round_limit(self, rounds: int):
         """Test hook: caps the device mesh's flip rounds (a frame that needs
