@@ -106,6 +106,14 @@ typedef struct elas_params {
                                   (Section VIII): invalid pixels stay invalid, valid
                                   ones take the lower median of the valid values in
                                   the window clipped to the image (0) */
+  int32_t add_corners;         /* 1: the four image corners join each view's mesh,
+                                  each with the d of its nearest support point, so
+                                  every pixel has a plane prior (1); 0: the mesh of
+                                  the support points alone (Section III-A
+                                  triangulates the support points only): pixels
+                                  outside their convex hull get no plane prior and
+                                  take their candidates from the grid vectors
+                                  alone. 0 meshes on the host */
 } elas_params;
 
 typedef struct elas_handle elas_handle;
@@ -418,16 +426,19 @@ ELAS_API int elas_get_batch_intermediate(elas_handle* h, int32_t pair, int32_t w
 /* The mesh step on its own, on the host (Section III-A: Delaunay
  * triangulation of the support points and one slanted plane per triangle;
  * Section IV leaves this sequential step on the CPU). Makes no HIP call.
- *   pts      n support points as (u, v, d) int32 triples, distinct, each
- *            strictly inside the image (0 < u < w-1, 0 < v < h-1).
- *   corners  d of the image corners (0,0), (w-1,0), (0,h-1), (w-1,h-1).
+ *   pts      n support points as (u, v, d) int32 triples, distinct; with
+ *            corners each strictly inside the image (0 < u < w-1,
+ *            0 < v < h-1), without them anywhere in it.
+ *   corners  d of the image corners (0,0), (w-1,0), (0,h-1), (w-1,h-1); NULL:
+ *            the mesh of the points alone (add_corners = 0).
  *   recs_out capacity (2n+2)*9 int32: canonical triangles, layout of TRI_*.
  *   planes_out capacity (2n+2)*3 float: planes, layout of PLANE_*.
- * The mesh is the Delaunay triangulation of corners + points in which every
- * set of four or more co-circular points is split as a fan from its
- * (v, u)-smallest point. Returns the triangle count 2n+2, ELAS_ERR_ARG for
- * bad input (n < 1, null pointers, points outside, duplicates), or
- * ELAS_ERR_INTERNAL. */
+ * The mesh is the Delaunay triangulation of corners + points (or of the
+ * points alone) in which every set of four or more co-circular points is
+ * split as a fan from its (v, u)-smallest point. Returns the triangle count
+ * (2n+2 with corners; 2n-2-h without, h = points on the hull, 0 for fewer
+ * than three or collinear points), ELAS_ERR_ARG for bad input (n < 1, null
+ * pointers, points outside, duplicates), or ELAS_ERR_INTERNAL. */
 ELAS_API int elas_triangulate(const int32_t* pts, int32_t n, const int32_t* corners, int32_t w,
                               int32_t h, int32_t* recs_out, float* planes_out);
 

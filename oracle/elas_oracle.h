@@ -62,6 +62,10 @@ typedef struct orc_params {
   int32_t redundancy;          /* 0: two-sided (Fig. 7A); 1: past-only (Fig. 7B) */
   int32_t support_subsample;   /* keep every k-th support point (k >= 1) */
   int32_t median_window;       /* 0 or 1: off; 3 or 5: median post-filter */
+  int32_t add_corners;         /* 1: the four image corners join each view's mesh
+                                  (nearest point's d); 0: the mesh of the support
+                                  points alone, pixels outside their hull get no
+                                  plane prior */
 } orc_params;
 
 /* ---- stage 1: gradients and descriptors -------------------------------- */
@@ -106,6 +110,11 @@ void orc_support_lists(const orc_params* p, const int16_t* dcan, int32_t lw,
  * inside that rectangle. Writes at most 2n triangles as vertex-index triples
  * (positively oriented) and returns their count, or -1 on bad input. */
 int32_t orc_delaunay(const int32_t* pts, int32_t n, int32_t* tris);
+/* Delaunay triangulation (same canonical rule) of n distinct points alone, no
+ * corners: [ntri][3] vertex indices in positive orientation into tris
+ * (capacity 2n). Returns ntri (0 for n < 3 or collinear points), -1 for bad
+ * input (duplicates). */
+int32_t orc_delaunay_points(const int32_t* pts, int32_t n, int32_t* tris);
 /* Exact predicates, exposed for unit tests. */
 int64_t orc_orient(const int32_t* a, const int32_t* b, const int32_t* c);
 int64_t orc_incircle(const int32_t* a, const int32_t* b, const int32_t* c,

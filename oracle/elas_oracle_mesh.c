@@ -140,6 +140,126 @@ int32_t orc_delaunay(const int32_t* pts, int32_t n, int32_t* tris) {
 }
 
 /* ------------------------------------------------------------------------
+ * Delaunay triangulation of the points alone (no image corners), by gift
+ * wrapping: every hull edge and every edge of a Delaunay triangle is a
+ * Delaunay edge, and the triangle on the left of a Delaunay edge (a, b) has
+ * as apex the point left of it whose circle through a and b holds no other
+ * candidate (under the same perturbed in-circle test, the points are in
+ * general position, so that point is unique). Starting from one hull edge,
+ * each triangle's two new edges are wrapped in turn; each directed edge is
+ * taken once. Plain O(n^2): n scans of the points per triangle pair.
+ * Returns the triangle count (0 for fewer than three points or collinear
+ * ones), -1 for bad input.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int64_t* keys;  /* directed edge a * n + b, or -1 */
+  int64_t cap;
+} edge_set;
+
+static int edge_set_add(edge_set* s, int64_t key) { /* 1 if newly added */
+  uint64_t h = (uint64_t)key * 0x9E3779B97F4A7C15ull;
+  int64_t i = (int64_t)(h % (uint64_t)s->cap);
+  while (s->keys[i] >= 0) {
+    if (s->keys[i] == key) return 0;
+    i = (i + 1) % s->cap;
+  }
+  s->keys[i] = key;
+  return 1;
+}
+
+static int edge_set_has(const edge_set* s, int64_t key) {
+  uint64_t h = (uint64_t)key * 0x9E3779B97F4A7C15ull;
+  int64_t i = (int64_t)(h % (uint64_t)s->cap);
+  while (s->keys[i] >= 0) {
+    if (s->keys[i] == key) return 1;
+    i = (i + 1) % s->cap;
+  }
+  return 0;
+}
+
+int32_t orc_delaunay_points(const int32_t* pts, int32_t n, int32_t* tris) {
+  if (n < 0) return -1;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t j = i + 1; j < n; ++j)
+      if (pts[2 * i] == pts[2 * j] && pts[2 * i + 1] == pts[2 * j + 1]) return -1;
+  if (n < 3) return 0;
+  /* a: the (v, u)-smallest point; b: the next hull vertex, the point with
+   * every other point on its positive side or on the line beyond it */
+  int32_t a = 0;
+  for (int32_t i = 1; i < n; ++i)
+    if (lex_less(pts + 2 * i, pts + 2 * a)) a = i;
+  int32_t b = -1;
+  for (int32_t i = 0; i < n; ++i) {
+    if (i == a) continue;
+    if (b < 0) {
+      b = i;
+      continue;
+    }
+    int64_t o = orc_orient(pts + 2 * a, pts + 2 * b, pts + 2 * i);
+    if (o < 0) {
+      b = i;
+    } else if (o == 0) { /* collinear: the nearer point is the hull neighbour */
+      int64_t db = (int64_t)(pts[2 * b] - pts[2 * a]) * (pts[2 * b] - pts[2 * a]) +
+                   (int64_t)(pts[2 * b + 1] - pts[2 * a + 1]) * (pts[2 * b + 1] - pts[2 * a + 1]);
+      int64_t di = (int64_t)(pts[2 * i] - pts[2 * a]) * (pts[2 * i] - pts[2 * a]) +
+                   (int64_t)(pts[2 * i + 1] - pts[2 * a + 1]) * (pts[2 * i + 1] - pts[2 * a + 1]);
+      if (di < db) b = i;
+    }
+  }
+  int collinear = 1;
+  for (int32_t i = 0; i < n && collinear; ++i)
+    if (orc_orient(pts + 2 * a, pts + 2 * b, pts + 2 * i) != 0) collinear = 0;
+  if (collinear) return 0;
+  edge_set done = {NULL, 16 * (int64_t)n + 64};
+  done.keys = (int64_t*)malloc(sizeof(int64_t) * done.cap);
+  for (int64_t i = 0; i < done.cap; ++i) done.keys[i] = -1;
+  int32_t* stack = (int32_t*)malloc(sizeof(int32_t) * 2 * (6 * (size_t)n + 8));
+  int32_t top = 0, nt = 0, cap = 2 * n;
+  stack[top++] = a;
+  stack[top++] = b;
+  int32_t status = 0;
+  while (top > 0 && status == 0) {
+    const int32_t y = stack[--top], x = stack[--top];
+    if (edge_set_has(&done, (int64_t)x * n + y)) continue;
+    /* the apex: the left point whose circle through x, y holds no other */
+    int32_t c = -1;
+    for (int32_t i = 0; i < n; ++i) {
+      if (orc_orient(pts + 2 * x, pts + 2 * y, pts + 2 * i) <= 0) continue;
+      if (c < 0) {
+        c = i;
+        continue;
+      }
+      const int32_t t[3] = {x, y, c};
+      if (inside_perturbed(pts, t, i)) c = i;
+    }
+    if (c < 0) continue; /* a hull edge: nothing on its left */
+    if (nt >= cap) {
+      status = -1;
+      break;
+    }
+    tris[3 * nt] = x;
+    tris[3 * nt + 1] = y;
+    tris[3 * nt + 2] = c;
+    ++nt;
+    edge_set_add(&done, (int64_t)x * n + y);
+    edge_set_add(&done, (int64_t)y * n + c);
+    edge_set_add(&done, (int64_t)c * n + x);
+    /* the triangles across its two other edges */
+    if (!edge_set_has(&done, (int64_t)c * n + y)) {
+      stack[top++] = c;
+      stack[top++] = y;
+    }
+    if (!edge_set_has(&done, (int64_t)x * n + c)) {
+      stack[top++] = x;
+      stack[top++] = c;
+    }
+  }
+  free(done.keys);
+  free(stack);
+  return status == 0 ? nt : -1;
+}
+
+/* ------------------------------------------------------------------------
  * Canonical triangle records: vertices sorted by (v, u), triangles sorted by
  * their sorted vertex triples. The record order is the tie rule for pixels
  * on shared edges and vertices (the earlier record owns them).

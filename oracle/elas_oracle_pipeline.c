@@ -17,27 +17,29 @@ static double now_ms(void) {
   return ts.tv_sec * 1e3 + ts.tv_nsec * 1e-6;
 }
 
-/* Points for triangulation: the four image corners first, then the list. */
+/* Points for triangulation: the four image corners first, then the list
+ * (without add_corners: the list alone). */
 static int32_t build_mesh(const orc_params* p, const int32_t* list, int32_t n,
                           const int32_t* corners, int32_t w, int32_t h, int32_t** recs,
                           float** planes, int32_t** owner, int16_t* dplane) {
-  int32_t total = n + 4;
+  const int32_t nc = p->add_corners ? 4 : 0;
+  int32_t total = n + nc;
   int32_t* uvd = (int32_t*)malloc(sizeof(int32_t) * 3 * total);
   int32_t* uv = (int32_t*)malloc(sizeof(int32_t) * 2 * total);
   const int32_t cu[4] = {0, w - 1, 0, w - 1};
   const int32_t cv[4] = {0, 0, h - 1, h - 1};
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < nc; ++c) {
     uvd[3 * c] = cu[c];
     uvd[3 * c + 1] = cv[c];
     uvd[3 * c + 2] = corners[c];
   }
-  memcpy(uvd + 12, list, sizeof(int32_t) * 3 * n);
+  memcpy(uvd + 3 * nc, list, sizeof(int32_t) * 3 * n);
   for (int32_t i = 0; i < total; ++i) {
     uv[2 * i] = uvd[3 * i];
     uv[2 * i + 1] = uvd[3 * i + 1];
   }
   int32_t* tris = (int32_t*)malloc(sizeof(int32_t) * 3 * (2 * total + 8));
-  int32_t nt = orc_delaunay(uv, total, tris);
+  int32_t nt = nc ? orc_delaunay(uv, total, tris) : orc_delaunay_points(uv, total, tris);
   if (nt < 0) {
     free(uvd);
     free(uv);
@@ -65,7 +67,8 @@ int32_t orc_process(const orc_params* p, const uint8_t* left, const uint8_t* rig
       (p->ambiguity != 0 && p->ambiguity != 1) || (p->redundancy != 0 && p->redundancy != 1) ||
       p->support_subsample < 1 || p->support_subsample > 64 ||
       (p->median_window != 0 && p->median_window != 1 && p->median_window != 3 &&
-       p->median_window != 5))
+       p->median_window != 5) ||
+      (p->add_corners != 0 && p->add_corners != 1))
     return -1;
   if (p->descriptor == 1 &&
       (p->census_support_window < 3 || p->census_support_window > 13 ||
@@ -128,6 +131,8 @@ int32_t orc_process(const orc_params* p, const uint8_t* left, const uint8_t* rig
   t->ptsR = (int32_t*)malloc(nlc * 3 * sizeof(int32_t));
   orc_support_lists(p, t->dcan_final, t->lw, t->lh, w, h, t->ptsL, &t->nL, t->cornersL,
                     t->ptsR, &t->nR, t->cornersR);
+  if (!p->add_corners) /* no corners join the meshes */
+    for (int c = 0; c < 4; ++c) t->cornersL[c] = t->cornersR[c] = -1;
   double t2 = now_ms();
 
   t->lut = (int32_t*)malloc(sizeof(int32_t) * t->D);

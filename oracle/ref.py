@@ -23,7 +23,7 @@ DEFAULTS = dict(
     beta=0.02, gamma=3.0, sigma=1.0, sradius=2, match_texture=1,
     lr_threshold=2, full_search=0, descriptor=0, census_support_window=9,
     census_dense_window=5, ambiguity=0, redundancy=0, support_subsample=1,
-    median_window=0)
+    median_window=0, add_corners=1)
 
 
 class OrcParams(C.Structure):
@@ -39,7 +39,7 @@ class OrcParams(C.Structure):
         ("descriptor", C.c_int32), ("census_support_window", C.c_int32),
         ("census_dense_window", C.c_int32), ("ambiguity", C.c_int32),
         ("redundancy", C.c_int32), ("support_subsample", C.c_int32),
-        ("median_window", C.c_int32),
+        ("median_window", C.c_int32), ("add_corners", C.c_int32),
     ]
 
 
@@ -114,6 +114,8 @@ def lib():
                                         C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp]
         L.orc_delaunay.argtypes = [vp, C.c_int32, vp]
         L.orc_delaunay.restype = C.c_int32
+        L.orc_delaunay_points.argtypes = [vp, C.c_int32, vp]
+        L.orc_delaunay_points.restype = C.c_int32
         L.orc_orient.argtypes = [vp, vp, vp]
         L.orc_orient.restype = C.c_int64
         L.orc_incircle.argtypes = [vp, vp, vp, vp]
@@ -264,6 +266,18 @@ def delaunay(uv: np.ndarray) -> np.ndarray:
     nt = lib().orc_delaunay(_ptr(uv), n, _ptr(tris))
     if nt < 0:
         raise ValueError("orc_delaunay rejected its input")
+    return tris[:nt].copy()
+
+
+def delaunay_points(uv: np.ndarray) -> np.ndarray:
+    """uv: [n, 2] distinct points, no corners. Returns [ntri, 3] vertex
+    indices (empty for collinear points)."""
+    uv = np.ascontiguousarray(uv, np.int32).reshape(-1, 2)
+    n = uv.shape[0]
+    tris = np.zeros((max(1, 2 * n), 3), np.int32)
+    nt = lib().orc_delaunay_points(_ptr(uv), n, _ptr(tris))
+    if nt < 0:
+        raise ValueError("orc_delaunay_points rejected its input")
     return tris[:nt].copy()
 
 

@@ -574,6 +574,13 @@ int ensure_upload(elas_handle* h, Buffers* b, size_t bytes) {
 
 bool finite_positive(float x) { return std::isfinite(x) && x > 0.0f; }
 
+// Frames that the device mesh does not take: mesh_on_host, a side above the
+// device mesh limit, or a mesh of the support points alone (no corners).
+bool mesh_host_only(const elas_params& p, int32_t w, int32_t hp) {
+  return p.mesh_on_host != 0 || p.add_corners == 0 || w > kDeviceMeshMaxSide ||
+         hp > kDeviceMeshMaxSide;
+}
+
 // Each image corner takes the d of the nearest list point (squared
 // distance; the earlier point in list order on ties).
 void corner_disparities(const std::vector<int32_t>& pts, int32_t n, int32_t w, int32_t hp,
@@ -626,11 +633,16 @@ void gather_lists(elas_handle* h, Buffers* b, MeshHeader* hd) {
   *hd = MeshHeader{};
   hd->n[0] = nL;
   hd->n[1] = nR;
+  // with corners: 2n + 2 triangles; without: at most 2n - 5, known once built
   hd->ntri[0] = nL > 0 ? 2 * nL + 2 : 0;
   hd->ntri[1] = nR > 0 ? 2 * nR + 2 : 0;
   hd->support_evals = evals;
-  corner_disparities(h->ptsL, nL, g.w, g.h, hd->corners);
-  corner_disparities(h->ptsR, nR, g.w, g.h, hd->corners + 4);
+  if (h->params.add_corners) {
+    corner_disparities(h->ptsL, nL, g.w, g.h, hd->corners);
+    corner_disparities(h->ptsR, nR, g.w, g.h, hd->corners + 4);
+  } else {
+    for (int c = 0; c < 8; ++c) hd->corners[c] = -1;
+  }
 }
 
 // Host mesh mode, after k_rows: wait, gather, mesh both views, upload the
@@ -644,30 +656,45 @@ int host_mesh_step(elas_handle* h, Buffers* b, hipStream_t stream) {
   h->host_wait_ms = std::chrono::duration<double, std::milli>(t0 - tw0).count();
   MeshHeader hd;
   gather_lists(h, b, &hd);
-  const int32_t ntL = hd.ntri[0], ntR = hd.ntri[1];
+  // capacities: 2n + 2 triangles per view (exact with corners, a bound without)
+  const int32_t capL = hd.ntri[0], capR = hd.ntri[1];
   // the staging buffer of the previous call must have been consumed
   if (h->upload_pending) HIP_TRY(hipEventSynchronize(h->ev_upload));
   h->upload_pending = false;
-  const size_t tri_bytes = align_up((size_t)(ntL + ntR) * sizeof(RasterTri), 256);
+  const size_t tri_bytes = align_up((size_t)(capL + capR) * sizeof(RasterTri), 256);
   int rc = ensure_upload(h, b, tri_bytes + sizeof(MeshHeader));
   if (rc != ELAS_OK) return rc;
   RasterTri* tris = static_cast<RasterTri*>(b->up_host);
-  h->recsL.assign((size_t)ntL * 9, 0);
-  h->planesL.assign((size_t)ntL * 3, 0.f);
-  h->recsR.assign((size_t)ntR * 9, 0);
-  h->planesR.assign((size_t)ntR * 3, 0.f);
-  if (hd.n[0] > 0) {
-    int32_t gotR = -1;
-    h->worker->submit([&] {
-      gotR = build_mesh(h->meshR, h->ptsR.data(), hd.n[1], hd.corners + 4, g.w, g.h,
-                        tris + ntL, h->recsR.data(), h->planesR.data());
-    });
-    const int32_t gotL = build_mesh(h->meshL, h->ptsL.data(), hd.n[0], hd.corners, g.w, g.h,
-                                    tris, h->recsL.data(), h->planesL.data());
-    h->worker->wait();
-    if (gotL != ntL || gotR != ntR)
-      return fail(h, ELAS_ERR_INTERNAL, "host triangulation failed its consistency checks");
+  h->recsL.assign((size_t)capL * 9, 0);
+  h->planesL.assign((size_t)capL * 3, 0.f);
+  h->recsR.assign((size_t)capR * 9, 0);
+  h->planesR.assign((size_t)capR * 3, 0.f);
+  const bool corners = h->params.add_corners != 0;
+  auto mesh = [&](MeshScratch* s, const std::vector<int32_t>& pts, int32_t n, const int32_t* c,
+                  RasterTri* out, std::vector<int32_t>& recs, std::vector<float>& planes) {
+    if (n == 0) return 0;
+    return corners ? build_mesh(s, pts.data(), n, c, g.w, g.h, out, recs.data(), planes.data())
+                   : build_mesh_points(s, pts.data(), n, g.w, g.h, out, recs.data(),
+                                       planes.data());
+  };
+  int32_t gotR = -1;
+  h->worker->submit([&] {
+    gotR = mesh(h->meshR, h->ptsR, hd.n[1], hd.corners + 4, tris + capL, h->recsR, h->planesR);
+  });
+  const int32_t gotL = mesh(h->meshL, h->ptsL, hd.n[0], hd.corners, tris, h->recsL, h->planesL);
+  h->worker->wait();
+  if (gotL < 0 || gotR < 0 || (corners && (gotL != capL || gotR != capR)))
+    return fail(h, ELAS_ERR_INTERNAL, "host triangulation failed its consistency checks");
+  const int32_t ntL = gotL, ntR = gotR;
+  hd.ntri[0] = ntL;
+  hd.ntri[1] = ntR;
+  if (ntL < capL) {  // the right view's records follow the left's
+    std::memmove(tris + ntL, tris + capL, (size_t)ntR * sizeof(RasterTri));
+    h->recsL.resize((size_t)ntL * 9);
+    h->planesL.resize((size_t)ntL * 3);
   }
+  h->recsR.resize((size_t)ntR * 9);
+  h->planesR.resize((size_t)ntR * 3);
   uint8_t* hdr_host = static_cast<uint8_t*>(b->up_host) + tri_bytes;
   std::memcpy(hdr_host, &hd, sizeof(hd));
   h->hhdr = hd;
@@ -725,6 +752,7 @@ void elas_params_default(elas_params* p) {
   p->redundancy = 0;
   p->support_subsample = 1;
   p->median_window = 0;
+  p->add_corners = 1;
 }
 
 int elas_create(const elas_params* p, elas_handle** out) {
@@ -747,6 +775,8 @@ int elas_create(const elas_params* p, elas_handle** out) {
     return fail(nullptr, ELAS_ERR_ARG, "full_search must be 0 or 1");
   if (p->mesh_on_host != 0 && p->mesh_on_host != 1)
     return fail(nullptr, ELAS_ERR_ARG, "mesh_on_host must be 0 or 1");
+  if (p->add_corners != 0 && p->add_corners != 1)
+    return fail(nullptr, ELAS_ERR_ARG, "add_corners must be 0 or 1");
   if (p->incon_window_size > 16 || p->redun_max_dist > 16)
     return fail(nullptr, ELAS_ERR_UNSUPPORTED, "filter windows above 16 lattice steps");
   if ((p->descriptor != 0 && p->descriptor != 1) || (p->ambiguity != 0 && p->ambiguity != 1) ||
@@ -882,8 +912,7 @@ int elas::process_one(elas_handle* h, const uint8_t* left, const uint8_t* right,
   if (rc0 != ELAS_OK) return rc0;
   rc0 = ensure_fail_word(h);
   if (rc0 != ELAS_OK) return rc0;
-  const bool on_host =
-      h->params.mesh_on_host != 0 || w > kDeviceMeshMaxSide || hp > kDeviceMeshMaxSide;
+  const bool on_host = mesh_host_only(h->params, w, hp);
   if (on_host && !h->ev_lists) {
     HIP_TRY(hipEventCreateWithFlags(&h->ev_lists, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&h->ev_upload, hipEventDisableTiming));
@@ -993,10 +1022,10 @@ int elas_process_noalloc(elas_handle* h, const uint8_t* left, const uint8_t* rig
   if (w < 9 || hp < 9 || w > 8192 || hp > 8192)
     return fail(h, ELAS_ERR_ARG, "image size must be 9..8192 in each dimension");
   if (stride < w) return fail(h, ELAS_ERR_ARG, "stride must be >= width");
-  if (h->params.mesh_on_host || w > kDeviceMeshMaxSide || hp > kDeviceMeshMaxSide)
+  if (mesh_host_only(h->params, w, hp))
     return fail(h, ELAS_ERR_UNSUPPORTED,
-                "the no-allocation path meshes on the device only (no mesh_on_host, sides "
-                "up to 4096)");
+                "the no-allocation path meshes on the device only (no mesh_on_host, corners "
+                "added, sides up to 4096)");
   if (!h->fail_host) return fail(h, ELAS_ERR_UNSUPPORTED, "handle created without a device");
   const BufLayout Lo = buffer_layout(h->params, w, hp);
   if (Lo.total > kNoAllocBytes)
@@ -1216,7 +1245,7 @@ int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipSt
   for (int32_t i = 0; i < n; ++i) {
     const elas_pair& q = pairs[i];
     elas_handle* ph = q.params ? q.params : h;
-    if (ph->params.mesh_on_host || q.w > kDeviceMeshMaxSide || q.h > kDeviceMeshMaxSide) {
+    if (mesh_host_only(ph->params, q.w, q.h)) {
       const int rc = process_one(ph, q.left, q.right, q.w, q.h, q.stride, stream, q.disp_left,
                                  q.disp_right, reports ? reports[i] : h->fail_dev);
       if (rc != ELAS_OK) return fail(h, rc, std::string("pair ") + std::to_string(i) + ": " +
@@ -1649,18 +1678,22 @@ int elas_get_batch_intermediate(elas_handle* h, int32_t pair, int32_t which, voi
 
 int elas_triangulate(const int32_t* pts, int32_t n, const int32_t* corners, int32_t w,
                      int32_t h, int32_t* recs_out, float* planes_out) {
-  if (!pts || !corners || !recs_out || !planes_out || n < 1 || w < 3 || h < 3 || w > 8192 ||
-      h > 8192)
+  if (!pts || !recs_out || !planes_out || n < 1 || w < 3 || h < 3 || w > 8192 || h > 8192)
     return fail(nullptr, ELAS_ERR_ARG, "bad triangulation arguments");
-  for (int32_t i = 0; i < n; ++i)
-    if (pts[3 * i] <= 0 || pts[3 * i] >= w - 1 || pts[3 * i + 1] <= 0 ||
-        pts[3 * i + 1] >= h - 1)
-      return fail(nullptr, ELAS_ERR_ARG, "support point outside the image interior");
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t u = pts[3 * i], v = pts[3 * i + 1];
+    const bool ok = corners ? (u > 0 && u < w - 1 && v > 0 && v < h - 1)
+                            : (u >= 0 && u <= w - 1 && v >= 0 && v <= h - 1);
+    if (!ok) return fail(nullptr, ELAS_ERR_ARG, "support point outside the image (interior)");
+  }
   MeshScratch* s = mesh_scratch_create();
   std::vector<RasterTri> tris((size_t)2 * n + 2);
-  const int32_t nt = build_mesh(s, pts, n, corners, w, h, tris.data(), recs_out, planes_out);
+  const int32_t nt = corners
+                         ? build_mesh(s, pts, n, corners, w, h, tris.data(), recs_out, planes_out)
+                         : build_mesh_points(s, pts, n, w, h, tris.data(), recs_out, planes_out);
   mesh_scratch_destroy(s);
-  if (nt != 2 * n + 2) return fail(nullptr, ELAS_ERR_ARG, "triangulation rejected its input");
+  if (nt < 0 || (corners && nt != 2 * n + 2))
+    return fail(nullptr, ELAS_ERR_ARG, "triangulation rejected its input");
   return nt;
 }
 

@@ -89,6 +89,11 @@ void mesh_scratch_destroy(MeshScratch*);
 int32_t build_mesh(MeshScratch* s, const int32_t* pts, int32_t n, const int32_t* corners,
                    int32_t w, int32_t h, RasterTri* tri_out, int32_t* recs_out,
                    float* planes_out);
+// The canonical Delaunay mesh of the n points alone (no corners; points
+// anywhere in the image): at most 2n - 5 records in the same canonical order.
+// Returns the triangle count (0 for n < 3 or collinear points) or -1.
+int32_t build_mesh_points(MeshScratch* s, const int32_t* pts, int32_t n, int32_t w, int32_t h,
+                          RasterTri* tri_out, int32_t* recs_out, float* planes_out);
 
 // ---- one frame as the kernels see it -------------------------------------
 // Sizes, parameters and every device array of one stereo pair. Passed by

@@ -210,6 +210,11 @@ bool insert(MeshScratch& s, int32_t ip) {
 
 }  // namespace
 
+namespace {
+int32_t finish_mesh(MeshScratch& s, int32_t nv, RasterTri* tri_out, int32_t* recs_out,
+                    float* planes_out);
+}  // namespace
+
 int32_t build_mesh(MeshScratch* sp, const int32_t* list, int32_t n, const int32_t* corners,
                    int32_t w, int32_t h, RasterTri* tri_out, int32_t* recs_out,
                    float* planes_out) {
@@ -240,12 +245,20 @@ int32_t build_mesh(MeshScratch* sp, const int32_t* list, int32_t n, const int32_
     if (!insert(s, i)) return -1;
   const int32_t ntri = (int32_t)s.tris.size();
   if (ntri != 2 * total - 6) return -1;
+  return finish_mesh(s, total, tri_out, recs_out, planes_out);
+}
 
+namespace {
+
+// Canonical records, planes and raster records of the triangles in s.tris
+// over the nv vertices in s.pts / s.disp; returns the triangle count or -1.
+int32_t finish_mesh(MeshScratch& s, int32_t nv, RasterTri* tri_out, int32_t* recs_out,
+                    float* planes_out) {
+  const int32_t ntri = (int32_t)s.tris.size();
   // canonical records: vertices by (v, u), triangles by their vertex triples.
   // Rank every vertex in (v, u) order, then order triangles by their sorted
   // rank triples: a counting sort on the smallest rank, and an insertion sort
   // of the few triangles that share it.
-  const int32_t nv = total;
   s.rank.resize(nv);
   s.order.resize(nv);
   for (int32_t i = 0; i < nv; ++i) s.order[i] = i;
@@ -323,6 +336,194 @@ int32_t build_mesh(MeshScratch* sp, const int32_t* list, int32_t n, const int32_
     }
   }
   return ntri;
+}
+
+// The triangle across edge k of t, flipped when the edge is illegal under the
+// canonical rule; returns whether it flipped. t = (p, a, b) with p = v[k]
+// and o = (q, b, a) across (a, b) become (p, a, q) and (p, q, b).
+bool flip_if_illegal(MeshScratch& s, int32_t t, int k) {
+  auto& T = s.tris;
+  const int32_t o = T[t].nb[k];
+  if (o < 0) return false;
+  const int32_t p = T[t].v[k], a = T[t].v[(k + 1) % 3], b = T[t].v[(k + 2) % 3];
+  int j = 0;
+  while (T[o].nb[j] != t) ++j;
+  const int32_t q = T[o].v[j];
+  const Pt P = s.pts[p], A = s.pts[a], B = s.pts[b], Q = s.pts[q];
+  const int64_t ic = incircle(P, A, B, Q);
+  bool flip = ic > 0;
+  if (ic == 0) {
+    Pt m = P;
+    for (Pt x : {A, B, Q})
+      if (vu_less(x, m)) m = x;
+    flip = !((m.u == A.u && m.v == A.v) || (m.u == B.u && m.v == B.v));
+  }
+  if (!flip) return false;
+  const int32_t t_bp = T[t].nb[(k + 1) % 3];  // across (b, p)
+  const int32_t t_pa = T[t].nb[(k + 2) % 3];  // across (p, a)
+  const int32_t o_aq = T[o].nb[(j + 1) % 3];  // across (a, q)
+  const int32_t o_qb = T[o].nb[(j + 2) % 3];  // across (q, b)
+  T[t] = Tri{{p, a, q}, {o_aq, o, t_pa}};
+  T[o] = Tri{{p, q, b}, {o_qb, t_bp, t}};
+  replace_neighbour(T, o_aq, o, t);
+  replace_neighbour(T, t_bp, t, o);
+  return true;
+}
+
+}  // namespace
+
+// The mesh of the support points alone (no corners). A sweep in (v, u) order
+// joins each new point to every hull edge it sees (the new point is the
+// largest so far, so it lies outside the hull and sees a contiguous chain of
+// edges around the previous point); collinear points that start the sweep are
+// fanned from the first point off their line. Lawson flips under the
+// canonical rule then make every edge legal. Returns the triangle count
+// (2n - 2 - hull points; 0 for collinear or fewer than three points), or -1.
+int32_t build_mesh_points(MeshScratch* sp, const int32_t* list, int32_t n, int32_t w,
+                          int32_t h, RasterTri* tri_out, int32_t* recs_out,
+                          float* planes_out) {
+  MeshScratch& s = *sp;
+  s.pts.resize(n);
+  s.disp.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    s.pts[i] = Pt{list[3 * i], list[3 * i + 1]};
+    s.disp[i] = list[3 * i + 2];
+    if (list[3 * i] < 0 || list[3 * i] > w - 1 || list[3 * i + 1] < 0 || list[3 * i + 1] > h - 1)
+      return -1;
+  }
+  s.tris.clear();
+  if (n < 3) return 0;
+  std::vector<int32_t> ord(n);
+  for (int32_t i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return vu_less(s.pts[x], s.pts[y]); });
+  for (int32_t i = 1; i < n; ++i)
+    if (!vu_less(s.pts[ord[i - 1]], s.pts[ord[i]])) return -1;  // duplicate points
+  // the first point off the line of the first two
+  int32_t k = 2;
+  while (k < n && orient(s.pts[ord[0]], s.pts[ord[1]], s.pts[ord[k]]) == 0) ++k;
+  if (k == n) return 0;
+  auto& T = s.tris;
+  // the hull as a cycle nxt / prv in positive orientation; etri[x], eopp[x]:
+  // the triangle holding the hull edge x -> nxt[x] and the local index of
+  // the vertex opposite that edge
+  std::vector<int32_t> nxt(n, -1), prv(n, -1), etri(n, -1), eopp(n, -1);
+  const int32_t pk = ord[k];
+  const bool pos = orient(s.pts[ord[0]], s.pts[ord[1]], s.pts[pk]) > 0;
+  for (int32_t i = 0; i + 1 < k; ++i) {
+    const int32_t a = ord[i], b = ord[i + 1];
+    const int32_t t = (int32_t)T.size();
+    if (pos)
+      T.push_back(Tri{{a, b, pk}, {-1, -1, -1}});  // edge a->b opposite pk (index 2)
+    else
+      T.push_back(Tri{{b, a, pk}, {-1, -1, -1}});  // edge b->a opposite pk
+    if (i > 0) {  // shares (a, pk) with the previous triangle
+      const int32_t tp = t - 1;
+      if (pos) {  // t = (a, b, pk): edge (pk, a) opposite b (1); tp = (a', a, pk): edge (a, pk) opposite a' (0)
+        T[t].nb[1] = tp;
+        T[tp].nb[0] = t;
+      } else {    // t = (b, a, pk): edge (a, pk) opposite b (0); tp = (a, a', pk): edge (pk, a) opposite a' (1)
+        T[t].nb[0] = tp;
+        T[tp].nb[1] = t;
+      }
+    }
+  }
+  const int32_t t0 = 0, tl = (int32_t)T.size() - 1;
+  if (pos) {  // o0 -> o1 -> ... -> o(k-1) -> pk -> o0
+    for (int32_t i = 0; i + 1 < k; ++i) {
+      nxt[ord[i]] = ord[i + 1];
+      etri[ord[i]] = i;
+      eopp[ord[i]] = 2;
+    }
+    nxt[ord[k - 1]] = pk;
+    etri[ord[k - 1]] = tl;   // (o(k-2), o(k-1), pk): edge o(k-1) -> pk opposite o(k-2)
+    eopp[ord[k - 1]] = 0;
+    nxt[pk] = ord[0];
+    etri[pk] = t0;           // (o0, o1, pk): edge pk -> o0 opposite o1
+    eopp[pk] = 1;
+  } else {    // o(k-1) -> ... -> o1 -> o0 -> pk -> o(k-1)
+    for (int32_t i = k - 1; i > 0; --i) {
+      nxt[ord[i]] = ord[i - 1];
+      etri[ord[i]] = i - 1;
+      eopp[ord[i]] = 2;
+    }
+    nxt[ord[0]] = pk;
+    etri[ord[0]] = t0;       // (o1, o0, pk): edge o0 -> pk opposite o1
+    eopp[ord[0]] = 0;
+    nxt[pk] = ord[k - 1];
+    etri[pk] = tl;           // (o(k-1), o(k-2), pk): edge pk -> o(k-1) opposite o(k-2)
+    eopp[pk] = 1;
+  }
+  for (int32_t i = 0; i < n; ++i)
+    if (nxt[i] >= 0) prv[nxt[i]] = i;
+  // the remaining points in (v, u) order, each outside the hull so far
+  int32_t last = pk;
+  for (int32_t ii = k + 1; ii < n; ++ii) {
+    const int32_t p = ord[ii];
+    const Pt P = s.pts[p];
+    auto visible = [&](int32_t x) { return orient(s.pts[x], s.pts[nxt[x]], P) < 0; };
+    // The visible edges form one chain first -> ... -> end on the hull, and
+    // it holds an edge at `last`: the hull lies in the points (v, u)-smaller
+    // than `last`, a vertex with an angle below 180 degrees, and p lies
+    // beyond it in that order.
+    int32_t first = last, end = last;
+    if (visible(last)) end = nxt[last];
+    if (visible(prv[last])) first = prv[last];
+    if (first == end) return -1;
+    for (int32_t steps = 0; visible(prv[first]); first = prv[first])
+      if (++steps > n) return -1;
+    for (int32_t steps = 0; visible(end); end = nxt[end])
+      if (++steps > n) return -1;
+    // one triangle (y, x, p) per visible edge x -> y, chained along p
+    int32_t prev_t = -1, first_t = -1;
+    for (int32_t x = first; x != end; x = nxt[x]) {
+      const int32_t y = nxt[x];
+      const int32_t t = (int32_t)T.size();
+      T.push_back(Tri{{y, x, p}, {-1, -1, etri[x]}});  // edge (y, x) opposite p
+      T[etri[x]].nb[eopp[x]] = t;
+      if (prev_t >= 0) {  // (x, x_prev, p) and (y, x, p) share (x, p)
+        T[prev_t].nb[1] = t;  // in (x, x_prev, p) it is (p, x), opposite x_prev
+        T[t].nb[0] = prev_t;  // in (y, x, p) it is (x, p), opposite y
+      }
+      if (first_t < 0) first_t = t;
+      prev_t = t;
+    }
+    // hull: first -> p -> end; the chain's inner vertices leave it
+    for (int32_t x = nxt[first]; x != end;) {
+      const int32_t nx = nxt[x];
+      nxt[x] = prv[x] = -1;
+      x = nx;
+    }
+    nxt[first] = p;
+    prv[p] = first;
+    nxt[p] = end;
+    prv[end] = p;
+    etri[first] = first_t;   // (x1, first, p): edge first -> p opposite x1
+    eopp[first] = 0;
+    etri[p] = prev_t;        // (end, x_last, p): edge p -> end opposite x_last
+    eopp[p] = 1;
+    last = p;
+  }
+  // Lawson flips until every interior edge is legal
+  std::vector<std::pair<int32_t, int>> stack;
+  for (int32_t t = 0; t < (int32_t)T.size(); ++t)
+    for (int k2 = 0; k2 < 3; ++k2)
+      if (T[t].nb[k2] > t) stack.push_back({t, k2});
+  const int64_t limit = 64ll * (int64_t)T.size() * (int64_t)T.size() + 1024;
+  for (int64_t guard = 0; !stack.empty(); ++guard) {
+    if (guard > limit) return -1;
+    const auto [t, kk] = stack.back();
+    stack.pop_back();
+    const int32_t o = T[t].nb[kk];
+    if (!flip_if_illegal(s, t, kk)) continue;
+    for (int q = 0; q < 3; ++q) {
+      stack.push_back({t, q});
+      stack.push_back({o, q});
+    }
+  }
+  int32_t nhull = 0;
+  for (int32_t i = 0; i < n; ++i) nhull += nxt[i] >= 0 ? 1 : 0;
+  if ((int32_t)T.size() != 2 * n - 2 - nhull) return -1;
+  return finish_mesh(s, n, tri_out, recs_out, planes_out);
 }
 
 }  // namespace elas

@@ -47,7 +47,7 @@ class ElasParams(C.Structure):
         ("descriptor", C.c_int32), ("census_support_window", C.c_int32),
         ("census_dense_window", C.c_int32), ("ambiguity", C.c_int32),
         ("redundancy", C.c_int32), ("support_subsample", C.c_int32),
-        ("median_window", C.c_int32),
+        ("median_window", C.c_int32), ("add_corners", C.c_int32),
     ]
 
 
@@ -192,13 +192,18 @@ def _np_ptr(a: np.ndarray):
 
 
 def triangulate(pts: np.ndarray, corners, w: int, h: int) -> Tuple[np.ndarray, np.ndarray]:
-    """Host mesh step: canonical triangles [2n+2, 9] and planes [2n+2, 3]."""
+    """Host mesh step: canonical triangles [ntri, 9] and planes [ntri, 3];
+    ntri = 2n+2 with the four corners' d in `corners`, or, with corners None,
+    the mesh of the points alone."""
     pts = np.ascontiguousarray(pts, np.int32).reshape(-1, 3)
     n = len(pts)
-    corners = np.ascontiguousarray(corners, np.int32)
+    cptr = None
+    if corners is not None:
+        corners = np.ascontiguousarray(corners, np.int32)
+        cptr = _np_ptr(corners)
     recs = np.zeros((max(1, 2 * n + 2), 9), np.int32)
     planes = np.zeros((max(1, 2 * n + 2), 3), np.float32)
-    nt = _check(lib().elas_triangulate(_np_ptr(pts), n, _np_ptr(corners), w, h,
+    nt = _check(lib().elas_triangulate(_np_ptr(pts), n, cptr, w, h,
                                        _np_ptr(recs), _np_ptr(planes)))
     return recs[:nt], planes[:nt]
 

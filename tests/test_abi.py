@@ -50,6 +50,7 @@ def test_defaults_match_the_workload_parameters(E):
     assert (p.descriptor, p.ambiguity, p.redundancy) == (0, 0, 0)
     assert (p.census_support_window, p.census_dense_window) == (9, 5)
     assert p.support_subsample == 1 and p.median_window == 0
+    assert p.add_corners == 1
 
 
 def test_param_struct_mirrors_the_oracle_fields():
@@ -68,7 +69,7 @@ def test_param_struct_mirrors_the_oracle_fields():
     dict(descriptor=1, census_support_window=8), dict(descriptor=1, census_support_window=15),
     dict(descriptor=1, census_dense_window=1), dict(descriptor=1, census_dense_window=9),
     dict(support_subsample=0), dict(support_subsample=65), dict(median_window=2),
-    dict(median_window=7),
+    dict(median_window=7), dict(add_corners=2), dict(add_corners=-1),
 ])
 def test_create_rejects_bad_parameters(E, bad):
     with pytest.raises(E.ElasError, match="ELAS_ERR_ARG"):
@@ -86,9 +87,21 @@ def test_create_accepts_edge_parameters(E):
                dict(descriptor=1, census_support_window=13, census_dense_window=7),
                dict(descriptor=1, census_support_window=3, census_dense_window=3),
                dict(ambiguity=1, redundancy=1, support_subsample=64, median_window=5),
-               dict(median_window=1), dict(redundancy=1, redun_max_dist=16)):
+               dict(median_window=1), dict(redundancy=1, redun_max_dist=16),
+               dict(add_corners=0)):
         e = E.Elas(**kw)
         e.close()
+
+
+def test_noalloc_rejects_a_mesh_without_corners_before_any_hip_call(E):
+    # the points-alone mesh is built on the host, which the entry point that
+    # allocates nothing does not do
+    e = E.Elas(add_corners=0)
+    buf = C.c_void_p(0x1000)    # never dereferenced: validation fails first
+    assert E.elas.lib().elas_process_noalloc(e.handle, buf, buf, 64, 64, 64, None, buf,
+                                             buf) == -4
+    assert b"corners" in E.elas.lib().elas_last_error(e.handle)
+    e.close()
 
 
 def test_process_rejects_bad_arguments_before_any_hip_call(E):
@@ -151,3 +164,61 @@ def test_host_mesh_matches_oracle_on_dense_cocircular_lattices(E, seed):
     r2, p2 = E.triangulate(pts, corners, W, H)
     assert np.array_equal(r2, recs)
     assert np.array_equal(p2.view(np.uint32), planes.view(np.uint32))
+
+
+def _points_alone(rng, W, H, k, lattice):
+    if lattice:  # many co-circular cells and collinear hull runs
+        cand = [(u, v) for v in range(0, H, 5) for u in range(0, W, 5)]
+    else:
+        cand = [(u, v) for v in range(H) for u in range(W)]
+    sel = sorted(rng.choice(len(cand), size=k, replace=False))
+    return np.array([(cand[i][0], cand[i][1], int(rng.integers(0, 64))) for i in sel], np.int32)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_host_mesh_of_points_alone_matches_oracle(E, seed):
+    # no corners: the library's sweep + flips against the oracle's gift
+    # wrapping, lattice subsets (co-circular cells, hull runs touching the
+    # image border) and random points
+    rng = np.random.default_rng(100 + seed)
+    W, H = 101, 81
+    for lattice in (True, False):
+        k = int(rng.integers(3, 300 if lattice else 150))
+        pts = _points_alone(rng, W, H, k, lattice)
+        tris = ref.delaunay_points(pts[:, :2])
+        recs = ref.canonical(pts, tris)
+        planes = np.array([ref.plane(r) for r in recs], np.float32).reshape(-1, 3)
+        r2, p2 = E.triangulate(pts, None, W, H)
+        assert np.array_equal(r2, recs), (seed, lattice, k)
+        assert np.array_equal(p2.view(np.uint32), planes.view(np.uint32))
+
+
+def test_host_mesh_of_points_alone_degenerate(E):
+    # fewer than three points, collinear points: no triangles
+    for pts in ([[3, 3, 1]], [[3, 3, 1], [9, 4, 2]], [[0, 0, 1], [5, 5, 2], [10, 10, 3], [20, 20, 4]],
+                [[4, 7, 1], [9, 7, 1], [30, 7, 1]]):
+        r, p = E.triangulate(np.array(pts, np.int32), None, 40, 40)
+        assert len(r) == 0 and len(p) == 0
+    # a collinear run then one point off it: a fan of n - 2 triangles
+    pts = np.array([[u, 10, 5] for u in range(0, 40, 4)] + [[17, 30, 9]], np.int32)
+    r, _ = E.triangulate(pts, None, 40, 40)
+    assert len(r) == len(pts) - 2
+    assert np.array_equal(r, ref.canonical(pts, ref.delaunay_points(pts[:, :2])))
+    # points on the border are allowed without corners, not with them
+    E.triangulate(np.array([[0, 0, 1], [39, 0, 2], [0, 39, 3]], np.int32), None, 40, 40)
+    with pytest.raises(E.ElasError):
+        E.triangulate(np.array([[0, 0, 1], [39, 0, 2], [0, 39, 3]], np.int32), [1, 1, 1, 1], 40, 40)
+    with pytest.raises(E.ElasError):
+        E.triangulate(np.array([[5, 5, 1], [5, 5, 2], [9, 1, 3]], np.int32), None, 40, 40)
+
+
+@pytest.mark.parametrize("shape", list(synth.SHAPES))
+def test_host_mesh_of_points_alone_on_pipeline_lists(E, shape):
+    cfg = synth.SHAPES[shape]
+    pr = synth.make_pair(cfg.with_seed(5))
+    t = ref.process(ref.params(disp_max=cfg.disp_range - 1, add_corners=0), pr.left, pr.right)
+    assert list(t.cornersL) == [-1] * 4 and list(t.cornersR) == [-1] * 4
+    for pts, recs, planes in ((t.ptsL, t.recL, t.planeL), (t.ptsR, t.recR, t.planeR)):
+        r2, p2 = E.triangulate(pts, None, cfg.width, cfg.height)
+        assert np.array_equal(r2, recs)
+        assert np.array_equal(p2.view(np.uint32), planes.view(np.uint32))

@@ -215,3 +215,33 @@ def test_batch_argument_errors(E):
                           torch.zeros((4, 4), dtype=torch.int16, device="cuda:0"),
                           torch.zeros((4, 4), dtype=torch.int16, device="cuda:0"))])
     e.process_batch([])  # an empty batch is a no-op
+
+
+def test_batch_with_pairs_meshed_without_corners(E):
+    # pairs whose handle meshes the support points alone go through the host
+    # mesh path inside the batch, next to device-meshed pairs
+    dev = torch.device("cuda:0")
+    hc = E.Elas(disp_max=63)
+    hn = E.Elas(disp_max=63, add_corners=0)
+    hc.set_batch_flags(graph=True, autotune=False)
+    pairs = make_mix(30)[:4]
+    items, outs, want = [], [], []
+    for k, (p, D) in enumerate(pairs):
+        if D != 64:
+            continue
+        for h, ac in ((hc, 1), (hn, 0)):
+            L = torch.from_numpy(p.left).to(dev)
+            R = torch.from_numpy(p.right).to(dev)
+            oL = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+            oR = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+            items.append((L, R, oL, oR, h))
+            outs.append((oL, oR))
+            want.append((p, ac))
+    torch.cuda.synchronize()
+    for _ in range(2):
+        hc.process_batch(items)
+    torch.cuda.synchronize()
+    for (p, ac), (oL, oR) in zip(want, outs):
+        t = ref.process(ref.params(disp_max=63, add_corners=ac), p.left, p.right)
+        assert np.array_equal(oL.cpu().numpy(), t.outL), ac
+        assert np.array_equal(oR.cpu().numpy(), t.outR), ac

@@ -299,3 +299,42 @@ def test_concurrent_streams_each_frame_bit_exact(E):
         t = ref.process(ref.params(disp_max=63), p.left, p.right)
         assert np.array_equal(oL.cpu().numpy(), t.outL)
         assert np.array_equal(oR.cpu().numpy(), t.outR)
+
+
+# The mesh of the support points alone (add_corners = 0, Section III-A): it is
+# built on the host; pixels outside the hull have no plane prior.
+@pytest.mark.parametrize("shape", ["320x240", "640x480", "1242x375", "1280x720"])
+def test_workload_shapes_without_corners(E, shape):
+    cfg = synth.SHAPES[shape]
+    pair = synth.make_pair(cfg.with_seed(3))
+    kw = dict(disp_max=cfg.disp_range - 1, add_corners=0)
+    e, oL, oR = run_pair(E, pair.left, pair.right, **kw)
+    t = ref.process(oracle_params(kw), pair.left, pair.right)
+    assert (t.ownerL < 0).any() and list(t.cornersL) == [-1] * 4
+    assert compare(e, t, oL, oR) == []
+
+
+@pytest.mark.parametrize("kind", ["vline", "two", "diag", "spot", "hline"])
+def test_sparse_support_layouts_without_corners(E, kind):
+    # collinear support (vline, hline) and a single point give no triangles:
+    # no pixel has a plane prior, the grid vectors alone give candidates
+    L, R = synth.sparse_layout_pair(128, 96, kind, 9, seed=3)
+    kw = dict(disp_max=31, redun_max_dist=0, incon_min_support=0, candidate_stepsize=10,
+              add_corners=0)
+    t = ref.process(oracle_params(kw), L, R)
+    if kind in ("vline", "hline", "spot"):
+        assert len(t.recL) == 0
+    e, oL, oR = run_pair(E, L, R, **kw)
+    assert compare(e, t, oL, oR) == []
+
+
+@pytest.mark.parametrize("w,h,D,extra", SMALL[:9])
+def test_small_sizes_without_corners(E, w, h, D, extra):
+    dmin = extra.get("disp_min", 0)
+    cfg = synth.SceneConfig(w, h, max(D, 4), 3, 0.05, 1.0, max(2.0, D - 3.0), 2.0, 0.1,
+                            seed=w * 7 + h)
+    pair = synth.make_pair(cfg)
+    kw = dict(extra, add_corners=0)
+    kw["disp_max"] = dmin + D - 1
+    e, oL, oR = run_pair(E, pair.left, pair.right, **kw)
+    assert compare(e, ref.process(oracle_params(kw), pair.left, pair.right), oL, oR) == []

@@ -255,3 +255,123 @@ def test_plane_map_owner_is_first_containing_triangle(seed):
             mu = np.float32(np.float32(np.float32(a * np.float32(u)) + np.float32(b * np.float32(v))) + c)
             exp = int(np.floor(np.float32(mu + np.float32(0.5))))
             assert dp[v, u] == min(max(exp, 0), 63)
+
+
+# ---- the mesh of the support points alone (add_corners = 0) -----------------
+
+def hull_boundary(pts):
+    """Points on the convex hull boundary (vertices and collinear points on
+    its edges), and twice the hull's area: Andrew's monotone chain, then each
+    point tested against the hull's edges."""
+    P = sorted(set(map(tuple, pts)))
+    if len(P) < 3:
+        return set(P), 0
+
+    def chain(seq):
+        out = []
+        for p in seq:
+            while len(out) >= 2 and _orient(out[-2], out[-1], p) <= 0:
+                out.pop()
+            out.append(p)
+        return out
+
+    H = chain(P)[:-1] + chain(P[::-1])[:-1]
+    area2 = abs(sum(H[i][0] * H[(i + 1) % len(H)][1] - H[(i + 1) % len(H)][0] * H[i][1]
+                    for i in range(len(H))))
+    on = set()
+    for p in P:
+        for i in range(len(H)):
+            a, b = H[i], H[(i + 1) % len(H)]
+            if _orient(a, b, p) == 0 and min(a[0], b[0]) <= p[0] <= max(a[0], b[0]) \
+                    and min(a[1], b[1]) <= p[1] <= max(a[1], b[1]):
+                on.add(p)
+    return on, area2
+
+
+def check_valid_points(pts, tris):
+    for t in tris:
+        assert _orient(*[tuple(pts[q]) for q in t]) > 0
+    on, area2 = hull_boundary(pts)
+    assert sum(_orient(*[tuple(pts[q]) for q in t]) for t in tris) == area2  # tiles the hull
+    assert len(tris) == 2 * len(pts) - 2 - len(on)                           # Euler
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_points_alone_match_brute_force_on_lattice_subsets(seed):
+    rng = np.random.default_rng(300 + seed)
+    cand = [(u, v) for v in range(5, 41, 5) for u in range(5, 51, 5)]
+    k = int(rng.integers(4, 28))
+    sel = rng.choice(len(cand), size=k, replace=False)
+    pts = [cand[s] for s in sorted(sel)]
+    tris = ref.delaunay_points(np.array(pts))
+    if len(tris):
+        check_valid_points(pts, tris)
+    assert {tuple(sorted(t)) for t in tris.tolist()} == brute_force_delaunay(pts)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_points_alone_match_brute_force_on_random_points(seed):
+    rng = np.random.default_rng(400 + seed)
+    allp = {(int(u), int(v)) for u, v in zip(rng.integers(1, 60, 40), rng.integers(1, 45, 40))}
+    pts = sorted(allp, key=lambda p: (p[1], p[0]))[:28]
+    tris = ref.delaunay_points(np.array(pts))
+    check_valid_points(pts, tris)
+    assert {tuple(sorted(t)) for t in tris.tolist()} == brute_force_delaunay(pts)
+
+
+def test_points_alone_degenerate_sets():
+    assert len(ref.delaunay_points(np.zeros((0, 2), np.int32))) == 0
+    assert len(ref.delaunay_points(np.array([(3, 4), (9, 4)]))) == 0
+    assert len(ref.delaunay_points(np.array([(5, 5), (10, 5), (20, 5), (40, 5)]))) == 0
+    assert len(ref.delaunay_points(np.array([(5, 5), (10, 10), (15, 15)]))) == 0
+    # a row and one point below: a fan of triangles from that point
+    pts = [(5, 5), (10, 5), (15, 5), (20, 5), (12, 9)]
+    tris = ref.delaunay_points(np.array(pts))
+    assert {tuple(sorted(t)) for t in tris.tolist()} == {(0, 1, 4), (1, 2, 4), (2, 3, 4)}
+    with pytest.raises(ValueError):
+        ref.delaunay_points(np.array([(5, 5), (5, 5), (7, 8)]))
+
+
+@pytest.mark.parametrize("with_centre", [False, True])
+def test_points_alone_twelve_point_circle(with_centre):
+    c = (30, 30)
+    ring = [(c[0] + 5 * x, c[1] + 5 * y) for x, y in
+            [(3, 4), (4, 3), (5, 0), (4, -3), (3, -4), (0, -5), (-3, -4), (-4, -3), (-5, 0),
+             (-4, 3), (-3, 4), (0, 5)]]
+    pts = ring + ([c] if with_centre else [])
+    tris = ref.delaunay_points(np.array(pts))
+    check_valid_points(pts, tris)
+    assert {tuple(sorted(t)) for t in tris.tolist()} == brute_force_delaunay(pts)
+
+
+def test_pipeline_without_corners_has_priors_exactly_on_the_hull():
+    cfg = synth.QVGA.with_seed(2)
+    pr = synth.make_pair(cfg)
+    t1 = ref.process(ref.params(disp_max=63), pr.left, pr.right)
+    t0 = ref.process(ref.params(disp_max=63, add_corners=0), pr.left, pr.right)
+    # the stages before the mesh do not change; no corners are reported
+    assert np.array_equal(t0.ptsL, t1.ptsL) and np.array_equal(t0.gridL, t1.gridL)
+    assert np.all(t0.cornersL == -1) and np.all(t0.cornersR == -1)
+    for pts, rec, dpl in ((t0.ptsL, t0.recL, t0.dplaneL), (t0.ptsR, t0.recR, t0.dplaneR)):
+        on, _ = hull_boundary(pts[:, :2])
+        assert len(rec) == 2 * len(pts) - 2 - len(on)
+        # a pixel has a plane prior iff it lies in the hull of the points
+        H, W = dpl.shape
+        P = sorted(set(map(tuple, pts[:, :2].tolist())))
+
+        def half(seq):
+            out = []
+            for p in seq:
+                while len(out) >= 2 and _orient(out[-2], out[-1], p) <= 0:
+                    out.pop()
+                out.append(p)
+            return out
+
+        hull = half(P)[:-1] + half(P[::-1])[:-1]
+        vv, uu = np.mgrid[0:H, 0:W]
+        inside = np.ones((H, W), bool)
+        for i in range(len(hull)):
+            a, b = hull[i], hull[(i + 1) % len(hull)]
+            o = (b[0] - a[0]) * (vv - a[1]) - (b[1] - a[1]) * (uu - a[0])
+            inside &= o >= 0
+        assert np.array_equal(dpl >= 0, inside)
