@@ -154,7 +154,10 @@ typedef struct elas_timing {
   double host_mesh_ms;         /* host triangulation and record building */
 } elas_timing;
 
-/* Fills *p with the default parameters. */
+/* Fills *p with the default parameters: the matching parameters of the
+ * original algorithm (Section III-A) at the values given beside each field,
+ * the Sobel descriptor and eq. 1-2 ratio test of the plain path, and none of
+ * the Section VI changes. A NULL p is ignored. */
 ELAS_API void elas_params_default(elas_params* p);
 
 /* Validates *p and creates a handle (Section III-A: the matching parameters;
@@ -169,7 +172,9 @@ ELAS_API void elas_params_default(elas_params* p);
 ELAS_API int elas_create(const elas_params* p, elas_handle** out);
 
 /* Frees the handle and everything it owns (the per-size buffers of the
- * path of Section III-A). Waits for its pending work. NULL is accepted. */
+ * path of Section III-A). Waits for its pending work. NULL is accepted.
+ * Returns ELAS_OK; HIP errors while waiting or freeing are ignored and the
+ * handle is freed regardless. */
 ELAS_API int elas_destroy(elas_handle* h);
 
 /* Computes both disparity maps of one pair.
@@ -180,12 +185,16 @@ ELAS_API int elas_destroy(elas_handle* h);
  *   stream           HIP stream the work is ordered on (0 = null stream).
  *   disp_left/right  device pointers, int16, w*h_px elements, row stride w;
  *                    caller-owned.
+ * The path of Section III-A, Fig. 1: descriptors, support matching and its
+ * filters, the mesh and its plane prior, dense matching, the left/right
+ * check (with the Section VI options the parameters select).
  * Stream-ordered: outputs are valid once `stream` reaches the end of the
  * enqueued work; with the default device mesh the call only enqueues work.
  * With mesh_on_host the call blocks the calling thread until the support
  * stage has finished, triangulates on the host, then enqueues the rest (the
  * CPU/accelerator split of the paper, Section IV); frames wider or taller
- * than 4096 pixels are always triangulated this way. Inputs must stay valid
+ * than 4096 pixels, and every frame with add_corners = 0, are triangulated
+ * this way. Inputs must stay valid
  * until the stream passes the work. Device buffers are kept per (image size,
  * stream): they are allocated on the first call for that pair (which
  * synchronises the device) and reused by later calls on the same stream, so
@@ -206,8 +215,8 @@ ELAS_API int elas_process(elas_handle* h, const uint8_t* left, const uint8_t* ri
  * or other allocating call, no memset and no copy: the prior table is
  * written by a kernel from its argument, so the call enqueues kernels only.
  * The stream must belong to the current device (ELAS_ERR_ARG otherwise).
- * Device mesh only: ELAS_ERR_UNSUPPORTED with mesh_on_host or a side above
- * 4096, or for a handle created without a device. All calls on one GPU share
+ * Device mesh only: ELAS_ERR_UNSUPPORTED with mesh_on_host, add_corners = 0
+ * or a side above 4096, or for a handle created without a device. All calls on one GPU share
  * that GPU's array, which keeps the last call's contents (elas_get_stats and
  * elas_get_intermediate read them): calls that overlap on one GPU (other
  * streams, other handles, other host threads) race; order them. Timing is
@@ -227,7 +236,11 @@ typedef struct elas_pair {
                                    this handle's (e.g. another disparity range) */
 } elas_pair;
 
-/* Flags of elas_process_batch (elas_set_batch_flags; both set by default). */
+/* Flags of elas_process_batch (both set by default). The batch is the
+ * device's form of the paper's pipelining (Section V-B: many inputs in the
+ * accelerator at once); capture and tuning only change how it is launched.
+ * elas_set_batch_flags returns ELAS_ERR_ARG for a null handle or unknown
+ * bits. */
 enum elas_batch_flags {
   ELAS_BATCH_GRAPH = 1,         /* capture each batch shape's launches in a HIP graph
                                    once and replay it */
@@ -249,7 +262,7 @@ ELAS_API int elas_set_batch_flags(elas_handle* h, int32_t flags);
  * come from per-(size, stream) pools in the pair's parameter handle, so
  * batches on different streams run concurrently; a batch reuses them only
  * after the stream has passed the previous batch. Pairs the device mesh
- * cannot take (a side above 4096, or mesh_on_host) are processed by
+ * cannot take (a side above 4096, mesh_on_host, or add_corners = 0) are processed by
  * elas_process on the same stream first. Stream-ordered; the call returns
  * after enqueueing, except for the autotuning pass (synchronous, once per new
  * size). The handle is used by one host thread at a time.
@@ -259,29 +272,38 @@ ELAS_API int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pair
                                 hipStream_t stream);
 
 /* Tile variants the autotuner chose for (w, h) at this handle's disparity
- * count: descriptor rows per block and dense rows per block.
- * ELAS_ERR_ARG if none has been chosen yet. */
+ * count: descriptor rows per block and dense rows per block (the rows a
+ * workgroup stages in LDS, the device's counterpart of the line buffers of
+ * Section V-A). ELAS_ERR_ARG if none has been chosen yet. */
 ELAS_API int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t h_px,
                                      int32_t* desc_rows, int32_t* dense_rows);
 
 /* Fixes the tile variants of (w, h) at this handle's disparity count, as the
  * autotuner would (descriptor rows per block 4, 8 or 16; dense rows per
- * block 1, 2 or 4); used by single and batched calls, and the autotuner then
- * leaves that size alone. Results do not depend on the variants. */
+ * block 1, 2 or 4: the LDS row tiles of Section V-A's line buffers); used by
+ * single and batched calls, and the autotuner then leaves that size alone.
+ * Results do not depend on the variants. ELAS_ERR_ARG for other values or
+ * a side below 9. */
 ELAS_API int elas_set_tile_variants(elas_handle* h, int32_t w, int32_t h_px, int32_t desc_rows,
                                     int32_t dense_rows);
 
 /* Device bytes of the buffers one pair of size (w, h_px) needs with h's
- * parameters (descriptors, lattice, grid, mesh, maps); what a server admits
- * against its memory budget. No HIP call. */
+ * parameters (descriptors, lattice, grid, mesh, maps: every intermediate of
+ * Section III-A stays resident in HBM, where Section V-A streams through line
+ * buffers); what a server admits against its memory budget. No HIP call.
+ * ELAS_ERR_ARG for null pointers or sizes outside 9..8192. */
 ELAS_API int elas_frame_bytes(elas_handle* h, int32_t w, int32_t h_px, int64_t* bytes);
 
-/* Device bytes the handle holds now: the buffer sets of every (size, stream)
- * of single and batched calls, and the batch tables. No HIP call. */
+/* Device bytes the handle holds now (the Section V-A memory of every frame
+ * in flight): the buffer sets of every (size, stream) of single and batched
+ * calls, and the batch tables. No HIP call. ELAS_ERR_ARG for null pointers. */
 ELAS_API int elas_device_bytes(elas_handle* h, int64_t* bytes);
 
 /* ---- serving: continuous batching of pairs from many cameras ----------
- * A server owns a worker thread and max_inflight streams. elas_server_submit
+ * The paper's throughput setting (Section VII-D: frames streamed through
+ * the pipelined accelerators, two frames in flight in the dual system), for
+ * many cameras at once. A server owns a worker thread and max_inflight
+ * streams. elas_server_submit
  * queues a pair (device images and outputs, caller-owned until the ticket
  * completes) and returns a ticket at once. Whenever a stream is free and
  * pairs wait, the worker launches the longest-waiting ones (up to max_batch,
@@ -313,6 +335,7 @@ typedef struct elas_server_stats {
   int64_t resident_bytes;          /* buffer sets held for the server's pairs now */
   int64_t peak_resident_bytes;     /* and at most; never above memory_budget */
 } elas_server_stats;
+/* Fills *c with the defaults given beside each field. */
 ELAS_API void elas_server_config_default(elas_server_config* c);
 /* ELAS_ERR_ARG for out-of-range settings, ELAS_ERR_HIP if streams fail. */
 ELAS_API int elas_server_create(elas_handle* h, const elas_server_config* cfg,
@@ -334,40 +357,51 @@ ELAS_API int elas_server_wait(elas_server* s, int64_t ticket, double* latency_ms
 /* Non-blocking: *done = 1 and the status and latency once complete. */
 ELAS_API int elas_server_poll(elas_server* s, int64_t ticket, int32_t* done,
                               double* latency_ms);
+/* Counters since creation (ELAS_ERR_ARG for null pointers). */
 ELAS_API int elas_server_get_stats(elas_server* s, elas_server_stats* out);
+/* The server's last failure; owned by the server, valid until its next call. */
 ELAS_API const char* elas_server_last_error(const elas_server* s);
 /* Finishes every queued and running pair, then frees the server. */
 ELAS_API int elas_server_destroy(elas_server* s);
 
 /* Copies the counters of the last elas_process call (synchronises with its
- * stream first). */
+ * stream first): the work of Section III-A's stages (support and dense SAD
+ * evaluations, support points, triangles) that Section VII-B's per-frame
+ * times scale with. ELAS_ERR_ARG before any completed call; ELAS_ERR_INTERNAL
+ * if a device mesh failed since the last call. */
 ELAS_API int elas_get_stats(elas_handle* h, elas_stats* out);
 
-/* Test hook: caps the flip rounds of the device mesh (1..32000; the default
- * 32000 never binds, a frame needs a few tens). A view that is not legal
+/* Test hook: caps the flip rounds of the device mesh that builds Section
+ * III-A's Delaunay triangulation (1..32000, larger values clamp; the default
+ * 32000 never binds, a frame needs a few tens; ELAS_ERR_ARG below 1). A view that is not legal
  * within the cap gives up, its frame is matched without plane priors, and the
  * failure is reported as described at the top of this header. Lets tests
  * force the failure path while every kernel still exits normally. */
 ELAS_API int elas_set_mesh_round_limit(elas_handle* h, int32_t rounds);
 
-/* Turns per-stage event timing on (1) or off (0) for later calls. Timing
- * adds one event record per stage boundary to the stream. */
+/* Turns per-stage event timing on (1) or off (0) for later calls: the
+ * stage breakdown of a frame's time that Section VII-B reports per
+ * accelerator. Timing adds one event record per stage boundary to the
+ * stream. ELAS_ERR_ARG for a null handle. */
 ELAS_API int elas_set_timing(elas_handle* h, int32_t enable);
 
 /* Stage times of the last call made with timing on (synchronises with its
- * stream). ELAS_ERR_ARG if no such call has completed. After an
+ * stream), split by the stages of Section III-A as Section VII-B splits a
+ * frame's time. ELAS_ERR_ARG if no such call has completed. After an
  * elas_process_batch call each figure is the summed duration of that stage's
  * launches for the whole batch (a timed batch is launched directly, not from
  * a graph), device_span_ms runs from the first launch's start to the last
  * one's end, and the host fields are 0. */
 ELAS_API int elas_get_timing(elas_handle* h, elas_timing* out);
 
-/* Describes the last failure on h (or of elas_create when h is NULL). The
+/* Describes the last failure on h (or of elas_create when h is NULL): the
+ * library's error reporting, which no passage of the paper defines. The
  * string belongs to the library and stays valid until the next call. */
 ELAS_API const char* elas_last_error(const elas_handle* h);
 
 /* Intermediate results of the last elas_process call, for stage-by-stage
- * verification. Layouts (row-major; w, h image size; lw, lh lattice size;
+ * verification: one array per step of Section III-A (Fig. 1 (b)-(h)), and of
+ * the Section VI variants. Layouts (row-major; w, h image size; lw, lh lattice size;
  * gw, gh grid size; n list length; ntri triangle count):
  *   DESC_*     uint8   [h][w][16]   16-byte descriptor, all-zero if undefined
  *   DCAN_*     int16   [lh][lw]     support disparity per lattice point or -1
