@@ -273,8 +273,13 @@ __device__ __forceinline__ void stage1_body(const Frame& F, int lb) {
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2: support matching (Section III-A) with a reverse check. One
-// wavefront per lattice point; lane k evaluates d = dmin + k + 64 j.
+// Stage 2: support matching (Section III-A) with a reverse check. A
+// workgroup takes a run of up to 16 lattice points on one lattice row and
+// stages, once, every descriptor column its searches can reach (both views,
+// the rows the support descriptor samples) in LDS; each wavefront then takes
+// every fourth point of the run, lane k evaluating d = dmin + k + 64 j with
+// its candidates read from LDS and the point's own descriptor from scalar
+// loads (one address for the whole wavefront).
 // Ambiguity test: eq. 1-2 (m1 < t*m2 in FP32) or the shift-sum of eq. 3
 // (m1 <= m2/2 + m2/4 + m2/8 + m2/32 with truncating shifts). Descriptors:
 //  * gradient: the 512-bit support descriptor is the four 16-byte descriptors
@@ -291,38 +296,10 @@ __device__ __forceinline__ uint32_t sad64(const Desc64& a, const Desc64& b) {
          sad16(a.q[3], b.q[3]);
 }
 
-__device__ __forceinline__ uint32_t texture64(const Desc64& a) {
-  return texture16(a.q[0]) + texture16(a.q[1]) + texture16(a.q[2]) + texture16(a.q[3]);
-}
-
 __device__ __forceinline__ bool support_accept(const KParams& p, uint32_t m1, uint32_t m2) {
   if (p.ambiguity) return m1 <= (m2 >> 1) + (m2 >> 2) + (m2 >> 3) + (m2 >> 5);
   return (float)m1 < __fmul_rn(p.support_threshold, (float)m2);
 }
-
-// Descriptor sources of the support search: load(x) = descriptor of column x
-// on the point's row; cost(a, b); texture(a).
-// The point's two descriptor rows are wavefront-uniform base pointers and a
-// column is a 32-bit byte offset (x - 2 >= 0 for every searched column), so
-// each load takes a scalar base, one vector offset and an immediate.
-struct GradSrc {
-  typedef Desc64 T;
-  const uint8_t* ra;  // row v - 2
-  const uint8_t* rb;  // row v + 2
-  __device__ GradSrc(const uint8_t* desc, int w, int v)
-      : ra(desc + (size_t)(v - 2) * w * 16), rb(desc + (size_t)(v + 2) * w * 16) {}
-  __device__ __forceinline__ T load(int x) const {
-    const uint32_t o = (uint32_t)(x - 2) * 16u;  // columns x - 2 and x + 2: o and o + 64
-    Desc64 r;
-    r.q[0] = ld16(ra + o);
-    r.q[1] = ld16(ra + o + 64u);
-    r.q[2] = ld16(rb + o);
-    r.q[3] = ld16(rb + o + 64u);
-    return r;
-  }
-  __device__ __forceinline__ static uint32_t cost(const T& a, const T& b) { return sad64(a, b); }
-  __device__ __forceinline__ static uint32_t texture(const T& a) { return texture64(a); }
-};
 
 __device__ __forceinline__ uint32_t popc4(const uint4 a) {
   return __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
@@ -331,142 +308,317 @@ __device__ __forceinline__ uint4 xor4(const uint4 a, const uint4 b) {
   return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w);
 }
 
+// A census support descriptor: NQ 16-byte words; cost = Hamming distance.
 template <int NQ>
-struct CensusSrc {
-  struct T {
-    uint4 q[NQ];
-  };
-  const uint4* row;  // the lattice row's census, NQ words per column
-  __device__ __forceinline__ T load(int x) const {
-    const uint32_t o = (uint32_t)x * NQ;  // a 32-bit offset from the uniform row
-    T r;
+struct CensusDesc {
+  uint4 q[NQ];
+};
+template <int NQ>
+__device__ __forceinline__ uint32_t hamming(const CensusDesc<NQ>& a, const CensusDesc<NQ>& b) {
+  uint32_t c = 0;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) r.q[i] = row[o + i];
+  for (int i = 0; i < NQ; ++i) c += popc4(xor4(a.q[i], b.q[i]));
+  return c;
+}
+
+// LDS copies of a view's descriptor columns c0.. (one plane of 16 bytes per
+// column for each descriptor row or census word), the sources of the
+// searches: load(x) = the descriptor of column x on the point's row (the
+// gradient descriptor takes columns x - 2 and x + 2 of rows v - 2 and
+// v + 2); cost(a, b). texture(x, lane) splits the point's own texture over the
+// lanes of each 16-lane row: lane i takes 4 of its bytes, a row sum adds
+// them, so the wavefront pays one SAD instead of sixteen.
+__device__ __forceinline__ uint4 lds16(uint32_t off) {
+  return *reinterpret_cast<const uint4*>(dyn_smem + off);
+}
+__device__ __forceinline__ uint32_t lds4(uint32_t off) {
+  return *reinterpret_cast<const uint32_t*>(dyn_smem + off);
+}
+
+struct LdsGrad {
+  typedef Desc64 T;
+  __device__ __forceinline__ static uint32_t cost(const T& a, const T& b) { return sad64(a, b); }
+  uint32_t base;     // plane 0: row v - 2; plane 1 (base + pstride): row v + 2
+  uint32_t pstride;
+  int c0;
+  __device__ __forceinline__ T load(int x) const {
+    const uint32_t o = base + (uint32_t)(x - 2 - c0) * 16u;  // columns x - 2 and x + 2
+    Desc64 r;
+    r.q[0] = lds16(o);
+    r.q[1] = lds16(o + 64u);
+    r.q[2] = lds16(o + pstride);
+    r.q[3] = lds16(o + pstride + 64u);
     return r;
   }
-  __device__ __forceinline__ static uint32_t cost(const T& a, const T& b) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) c += popc4(xor4(a.q[i], b.q[i]));
-    return c;
-  }
-  __device__ __forceinline__ static uint32_t texture(const T& a) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) c += popc4(a.q[i]);
-    return c;
+  // lane i of a row: dword i & 3 of part (i >> 2) & 3 of the descriptor
+  __device__ __forceinline__ uint32_t texture(int x, int lane) const {
+    const int part = (lane >> 2) & 3;
+    const uint32_t o = base + (uint32_t)(x - 2 - c0) * 16u + (uint32_t)(part & 1) * 64u +
+                       (uint32_t)(part >> 1) * pstride + (uint32_t)(lane & 3) * 4u;
+    const uint32_t t = __builtin_amdgcn_sad_u8(lds4(o), 0x80808080u, 0u);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)row_sum_u32(t));
   }
 };
 
-// One search of a point: the candidate columns u + dir*d, d = dmin + lane +
-// 64 j for j < NJ (NJ 64-wide batches cover the disparity range). Lanes past
-// dhi load column dhi instead (in the image like every searched column) and
-// are masked out, so every load of a search is issued before the first wait.
-template <int NJ, class S>
-__device__ __forceinline__ void search_loads(const S& other, int u, int dir, int dhi,
-                                             const KParams& p, int lane,
-                                             typename S::T (&o)[NJ]) {
+template <int NQ>
+struct LdsCensus {
+  typedef CensusDesc<NQ> T;
+  __device__ __forceinline__ static uint32_t cost(const T& a, const T& b) { return hamming(a, b); }
+  uint32_t base;     // plane i (base + i * pstride): word i of each column
+  uint32_t pstride;
+  int c0;
+  __device__ __forceinline__ T load(int x) const {
+    const uint32_t o = base + (uint32_t)(x - c0) * 16u;
+    T r;
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) o[j] = other.load(u + dir * min(p.dmin + lane + 64 * j, dhi));
-}
+    for (int i = 0; i < NQ; ++i) r.q[i] = lds16(o + (uint32_t)i * pstride);
+    return r;
+  }
+  // lane i < 4 NQ of a row: the set bits of dword i & 3 of word i >> 2
+  __device__ __forceinline__ uint32_t texture(int x, int lane) const {
+    const int i = lane & 15, wd = min(i >> 2, NQ - 1);
+    const uint32_t o = base + (uint32_t)(x - c0) * 16u + (uint32_t)wd * pstride +
+                       (uint32_t)(i & 3) * 4u;
+    const uint32_t t = i < 4 * NQ ? (uint32_t)__popc(lds4(o)) : 0u;
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)row_sum_u32(t));
+  }
+};
 
-// Argmin over d = dmin..dhi (at least two values; smallest cost, smallest d
-// on ties) and the ambiguity test; returns whether it accepts. Control flow
-// is wavefront-uniform.
-template <int NJ, class S>
-__device__ __forceinline__ bool search_decide(const typename S::T& self,
-                                              const typename S::T (&o)[NJ], int dhi,
-                                              const KParams& p, int lane, int* d_best) {
-  uint32_t cost[NJ];
-  uint32_t best = 0xFFFFFFFFu;
+// The point's own descriptor in global memory, one address for the whole
+// wavefront: scalar loads into SGPRs, which each SAD takes as its scalar
+// operand (no LDS bandwidth and no VGPRs for it).
+struct GradSelf {
+  const uint8_t* ra;  // row v - 2
+  const uint8_t* rb;  // row v + 2
+  __device__ __forceinline__ Desc64 load(int x) const {
+    const uint32_t o = (uint32_t)(x - 2) * 16u;  // columns x - 2 and x + 2
+    Desc64 r;
+    r.q[0] = ld16(ra + o);
+    r.q[1] = ld16(ra + o + 64u);
+    r.q[2] = ld16(rb + o);
+    r.q[3] = ld16(rb + o + 64u);
+    return r;
+  }
+};
+
+template <int NQ>
+struct CensusSelf {
+  const uint4* row;  // the lattice row's census, NQ words per column
+  __device__ __forceinline__ CensusDesc<NQ> load(int x) const {
+    CensusDesc<NQ> r;
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int d = p.dmin + lane + 64 * j;
-    const uint32_t c = S::cost(self, o[j]);
-    cost[j] = d <= dhi ? c : 0xFFFFFFFFu;
-    if (d <= dhi) best = min(best, (c << 8) | (uint32_t)(d - p.dmin));
+    for (int i = 0; i < NQ; ++i) r.q[i] = row[(uint32_t)x * NQ + i];
+    return r;
+  }
+};
+
+// One search of a point with own descriptor `self`: the candidate columns
+// u + dir*d, d = dmin + lane + 64 j for j < NJ (NJ 64-wide batches cover the
+// disparity range), taken two batches at a time so that at most two
+// candidate descriptors per lane are live. Lanes past dhi load column dhi
+// instead (in the image like every searched column) and are masked out.
+// FULL: every lane of every batch is in range (dhi = dmin + 64 NJ - 1), so a
+// batch's columns are one lane-dependent base plus constants and its loads
+// take immediate offsets. Argmin over d = dmin..dhi (smallest cost, smallest
+// d on ties; at least two values) and the ambiguity test; returns whether it
+// accepts. Control flow is wavefront-uniform.
+template <int NJ, bool FULL, class C>
+__device__ __forceinline__ bool search(const typename C::T& self, const C& other, int u, int dir,
+                                       int dhi, const KParams& p, int lane, int* d_best) {
+  uint32_t key[NJ];
+  uint32_t best = 0xFFFFFFFFu;
+  const int xb = dir < 0 ? u - p.dmin - lane : u + p.dmin + lane;  // column of batch 0
+#pragma unroll
+  for (int j0 = 0; j0 < NJ; j0 += 2) {
+    typename C::T o[2];
+#pragma unroll
+    for (int jj = 0; jj < 2 && j0 + jj < NJ; ++jj) {
+      const int j = j0 + jj;
+      o[jj] = other.load(FULL ? xb + dir * 64 * j : u + dir * min(p.dmin + lane + 64 * j, dhi));
+    }
+#pragma unroll
+    for (int jj = 0; jj < 2 && j0 + jj < NJ; ++jj) {
+      const int j = j0 + jj, k = lane + 64 * j;  // k = d - dmin
+      const uint32_t c = C::cost(self, o[jj]);
+      key[j] = FULL || p.dmin + k <= dhi ? (c << 8) | (uint32_t)k : 0xFFFFFFFFu;
+      best = min(best, key[j]);
+    }
   }
   best = wave_min_u32(best);
   const int d1 = p.dmin + (int)(best & 0xFFu);
   const uint32_t m1 = best >> 8;
   uint32_t m2 = 0xFFFFFFFFu;
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int d = p.dmin + lane + 64 * j;
-    if (d != d1) m2 = min(m2, cost[j]);
-  }
-  m2 = wave_min_u32(m2);
+  for (int j = 0; j < NJ; ++j) m2 = min(m2, key[j] != best ? key[j] : 0xFFFFFFFFu);
+  m2 = wave_min_u32(m2) >> 8;
   *d_best = d1;
   return support_accept(p, m1, m2);
 }
 
-// One lattice point with descriptor sources sL (left view) and sR (right):
-// forward search, then the reverse search from the matched right column.
-// The point's own descriptor is loaded together with its candidates, and
-// the texture test waits only for it.
-template <int NJ, class S>
-__device__ __forceinline__ int support_point(const S& sL, const S& sR, int u, int w,
-                                             const KParams& p, int lane, int* ev) {
+// The search (full or general form) and the texture test. The search runs
+// whether or not the own descriptor is textured, so that its loads (scalar
+// and LDS) all issue at once instead of waiting behind the texture test's
+// branch; *d_best = -2 when the own descriptor is untextured (the search
+// does not count as evaluated and never accepts).
+template <int NJ, class G, class C>
+__device__ __forceinline__ bool support_search(const G& self_src, const C& self_lds, int xs,
+                                               const C& other, int u, int dir, int dhi,
+                                               const KParams& p, int lane, int* d_best) {
+  const typename C::T self = self_src.load(xs);
+  const bool textured = (int)self_lds.texture(xs, lane) >= p.support_texture;
+  const bool ok = dhi - p.dmin + 1 == 64 * NJ
+                      ? search<NJ, true>(self, other, u, dir, dhi, p, lane, d_best)
+                      : search<NJ, false>(self, other, u, dir, dhi, p, lane, d_best);
+  if (!textured) *d_best = -2;
+  return ok && textured;
+}
+
+// One lattice point: forward search, then the reverse search from the
+// matched right column. gL, gR: the views in global memory (the own
+// descriptors); cL, cR: the staged columns in LDS (candidates, texture).
+template <int NJ, class G, class C>
+__device__ __forceinline__ int support_point(const G& gL, const G& gR, const C& cL, const C& cR,
+                                             int u, int w, const KParams& p, int lane,
+                                             int* ev) {
   const int dhi = min(p.dmax, u - 4);
   if (dhi - p.dmin + 1 < 2) return -1;
-  const typename S::T ls = sL.load(u);
-  typename S::T o[NJ];
-  search_loads<NJ>(sR, u, -1, dhi, p, lane, o);
-  if ((int)S::texture(ls) < p.support_texture) return -1;
-  *ev += dhi - p.dmin + 1;
   int d1;
-  if (!search_decide<NJ, S>(ls, o, dhi, p, lane, &d1)) return -1;
+  const bool fwd = support_search<NJ>(gL, cL, u, cR, u, -1, dhi, p, lane, &d1);
+  if (d1 != -2) *ev += dhi - p.dmin + 1;  // textured: the search was evaluated
+  if (!fwd) return -1;
   const int ur = u - d1;
   const int dhi2 = min(p.dmax, w - 5 - ur);
   if (dhi2 - p.dmin + 1 < 2) return -1;
-  const typename S::T rs = sR.load(ur);
-  search_loads<NJ>(sL, ur, +1, dhi2, p, lane, o);
-  if ((int)S::texture(rs) < p.support_texture) return -1;
-  *ev += dhi2 - p.dmin + 1;
   int d2;
-  if (search_decide<NJ, S>(rs, o, dhi2, p, lane, &d2) && abs(d2 - d1) <= p.lr_threshold)
-    return d1;
-  return -1;
+  const bool rev = support_search<NJ>(gR, cR, ur, cL, ur, +1, dhi2, p, lane, &d2);
+  if (d2 != -2) *ev += dhi2 - p.dmin + 1;
+  return rev && abs(d2 - d1) <= p.lr_threshold ? d1 : -1;
 }
 
 // The batch count of the frame's disparity range, as a template argument.
-template <class S>
-__device__ __forceinline__ int support_point_d(const S& sL, const S& sR, int u, int w,
-                                               const KParams& p, int lane, int* ev) {
+template <class G, class C>
+__device__ __forceinline__ int support_point_d(const G& gL, const G& gR, const C& cL,
+                                               const C& cR, int u, int w, const KParams& p,
+                                               int lane, int* ev) {
   switch ((p.D + 63) >> 6) {
-    case 1: return support_point<1>(sL, sR, u, w, p, lane, ev);
-    case 2: return support_point<2>(sL, sR, u, w, p, lane, ev);
-    case 3: return support_point<3>(sL, sR, u, w, p, lane, ev);
-    default: return support_point<4>(sL, sR, u, w, p, lane, ev);
+    case 1: return support_point<1>(gL, gR, cL, cR, u, w, p, lane, ev);
+    case 2: return support_point<2>(gL, gR, cL, cR, u, w, p, lane, ev);
+    case 3: return support_point<3>(gL, gR, cL, cR, u, w, p, lane, ev);
+    default: return support_point<4>(gL, gR, cL, cR, u, w, p, lane, ev);
   }
+}
+
+// Columns a run of q lattice points (step apart) can reach, per view: right
+// view [max(u_first - dmax, 4), u_last - dmin], left view that range shifted
+// by up to D - 1 (reverse candidates), each widened by the two columns the
+// gradient descriptor samples on either side.
+__host__ __device__ __forceinline__ int support_cols_right(int q, int step, int D) {
+  return (q - 1) * step + D + 4;
+}
+__host__ __device__ __forceinline__ int support_cols_left(int q, int step, int D) {
+  return (q - 1) * step + 2 * D + 3;
+}
+constexpr int kSupportRunMax = 16;          // lattice points per workgroup
+constexpr int kSupportLdsMax = 64 * 1024;   // 32 bytes per staged column
+constexpr int kSupportStageCols = 512;      // columns per plane staged per round
+
+// Points per workgroup: 16, fewer when the staged columns would not fit.
+__host__ __device__ __forceinline__ int support_run(const Geometry& g, const KParams& p) {
+  int q = kSupportRunMax;
+  while (q > 1 && 32 * (support_cols_right(q, g.step, p.D) + support_cols_left(q, g.step, p.D)) >
+                      kSupportLdsMax)
+    --q;
+  return q;
 }
 
 __device__ __forceinline__ void support_body(const Frame& F, int lb) {
   const Geometry g = F.g;
   const KParams p = F.p;
-  const int lane = threadIdx.x & 63;
-  const int pt = __builtin_amdgcn_readfirstlane(lb * 4 + (threadIdx.x >> 6));
-  if (pt >= g.lw * g.lh) return;
-  const int l = pt / g.lw, k = pt - l * g.lw;
-  const int u = g.lu0 + k * g.step, v = g.lv0 + l * g.step;
-  int result, ev = 0;
-  if (p.descriptor == 0) {
-    result = support_point_d(GradSrc{F.descL, g.w, v}, GradSrc{F.descR, g.w, v}, u, g.w, p,
-                             lane, &ev);
-  } else {
-    const size_t row = (size_t)l * g.w * p.cs_q;
-    const uint4* cL = F.csupL;
-    const uint4* cR = F.csupR;
-    if (p.cs_q == 1)
-      result = support_point_d(CensusSrc<1>{cL + row}, CensusSrc<1>{cR + row}, u, g.w, p,
-                               lane, &ev);
+  const int q = support_run(g, p), runs = cdivd(g.lw, q);
+  const int l = lb / runs, k0 = (lb - l * runs) * q, k1 = min(g.lw, k0 + q);
+  const int v = g.lv0 + l * g.step;
+  const int uf = g.lu0 + k0 * g.step, ul = g.lu0 + (k1 - 1) * g.step;
+  // staged search columns (every searched column lies in them; clamped ends
+  // keep an empty search range in the image)
+  const int rlo = max(uf - p.dmax, 4), rhi = max(rlo, ul - p.dmin);
+  const int llo = min(uf, rlo + p.dmin), lhi = max(ul, min(ul - p.dmin + p.dmax, g.w - 5));
+  const int cR0 = rlo - 2, nR = rhi - rlo + 5, cL0 = llo - 2, nL = lhi - llo + 5;
+  const int planes = p.descriptor == 0 ? 2 : p.cs_q;  // 16-byte planes per view
+  // LDS: the right view's planes (nR columns each), then the left view's.
+  // Each plane is a run of columns at a fixed pitch from a uniform base;
+  // every thread issues its loads for all planes before its first store.
+  const int tid = threadIdx.x;
+  const uint8_t* pb[4];  // plane bases: right 0, right 1, left 0, left 1
+  uint32_t pd[4];        // LDS byte offsets of the planes
+  int pn[4];             // columns per plane
+  const uint32_t pitch = p.descriptor == 0 ? 16u : 16u * (uint32_t)p.cs_q;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bool right = k < 2;
+    const int pl = k & 1, c0 = right ? cR0 : cL0;
+    pn[k] = pl < planes ? (right ? nR : nL) : 0;
+    pd[k] = (uint32_t)(right ? pl * nR : planes * nR + pl * nL) * 16u;
+    if (p.descriptor == 0)
+      pb[k] = (right ? F.descR : F.descL) + ((size_t)(v - 2 + 4 * pl) * g.w + c0) * 16;
     else
-      result = support_point_d(CensusSrc<2>{cL + row}, CensusSrc<2>{cR + row}, u, g.w, p,
-                               lane, &ev);
+      pb[k] = reinterpret_cast<const uint8_t*>((right ? F.csupR : F.csupL) +
+                                               ((size_t)l * g.w + c0) * p.cs_q + pl);
   }
-  if (lane == 0) {
-    F.dcan_raw[pt] = (int16_t)result;
-    F.evals[pt] = ev;
+  const int nmax = max(nR, nL);
+  for (int c0 = 0; c0 < nmax; c0 += kSupportStageCols) {
+    uint4 t[4][kSupportStageCols / 256];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int s2 = 0; s2 < kSupportStageCols / 256; ++s2) {
+        const int c = min(c0 + s2 * 256 + tid, max(pn[k], 1) - 1);
+        t[k][s2] = ld16(pb[k] + (uint32_t)c * pitch);
+      }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int s2 = 0; s2 < kSupportStageCols / 256; ++s2) {
+        const int c = c0 + s2 * 256 + tid;
+        if (c < pn[k]) *reinterpret_cast<uint4*>(dyn_smem + pd[k] + (uint32_t)c * 16u) = t[k][s2];
+      }
+  }
+  __syncthreads();
+  // results go through LDS and out in one coalesced store per block: with no
+  // global store in the kernel before them, the loads of each point's own
+  // descriptor are known not to be clobbered and become scalar loads
+  __shared__ int32_t s_res[kSupportRunMax], s_ev[kSupportRunMax];
+  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t bR = 0, bL = (uint32_t)(planes * nR) * 16u;
+  for (int k = k0 + wv; k < k1; k += 4) {
+    const int u = g.lu0 + k * g.step;
+    int result, ev = 0;
+    if (p.descriptor == 0) {
+      const LdsGrad cR{bR, (uint32_t)nR * 16u, cR0}, cL{bL, (uint32_t)nL * 16u, cL0};
+      const size_t ra = (size_t)(v - 2) * g.w * 16, rb = (size_t)(v + 2) * g.w * 16;
+      result = support_point_d(GradSelf{F.descL + ra, F.descL + rb},
+                               GradSelf{F.descR + ra, F.descR + rb}, cL, cR, u, g.w, p, lane,
+                               &ev);
+    } else {
+      const size_t row = (size_t)l * g.w * p.cs_q;
+      if (p.cs_q == 1) {
+        const LdsCensus<1> cR{bR, (uint32_t)nR * 16u, cR0}, cL{bL, (uint32_t)nL * 16u, cL0};
+        result = support_point_d(CensusSelf<1>{F.csupL + row}, CensusSelf<1>{F.csupR + row}, cL,
+                                 cR, u, g.w, p, lane, &ev);
+      } else {
+        const LdsCensus<2> cR{bR, (uint32_t)nR * 16u, cR0}, cL{bL, (uint32_t)nL * 16u, cL0};
+        result = support_point_d(CensusSelf<2>{F.csupL + row}, CensusSelf<2>{F.csupR + row}, cL,
+                                 cR, u, g.w, p, lane, &ev);
+      }
+    }
+    if (lane == 0) {
+      s_res[k - k0] = result;
+      s_ev[k - k0] = ev;
+    }
+  }
+  __syncthreads();
+  if (tid < k1 - k0) {
+    F.dcan_raw[l * g.lw + k0 + tid] = (int16_t)s_res[tid];
+    F.evals[l * g.lw + k0 + tid] = s_ev[tid];
   }
 }
 
@@ -1601,7 +1753,7 @@ int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv)
   switch (stage) {
     case kStageDescriptor:
       return 2 * cdiv(g.w, kDescW) * cdiv(g.h, kDescRows[std::min(std::max(dv, 0), 2)]);
-    case kStageSupport: return cdiv((long long)g.lw * g.lh, 4);
+    case kStageSupport: return g.lw > 0 ? g.lh * cdiv(g.lw, support_run(g, p)) : 0;
     case kStageFilter: return filter_tiles_x(g) * filter_tiles_y(g);
     case kStageRedun: return p.redundancy ? 1 : 0;
     case kStageRows: return g.lh;
@@ -1620,6 +1772,10 @@ size_t stage_lds(int32_t stage, const Geometry& g, const KParams& p) {
     case kStageRows: return sizeof(int32_t) * (size_t)g.w;
     case kStageRaster: return sizeof(int32_t) * (size_t)raster_band_rows(g.w) * g.w;
     case kStageMesh: return kMeshLdsBytes;
+    case kStageSupport: {
+      const int q = support_run(g, p);
+      return 32 * (size_t)(support_cols_right(q, g.step, p.D) + support_cols_left(q, g.step, p.D));
+    }
     default: return 0;
   }
 }
@@ -1697,7 +1853,7 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
       else
         go(k_descriptor4_batch, 0u);
       break;
-    case kStageSupport: go(k_support_batch, 0u); break;
+    case kStageSupport: go(k_support_batch, shm); break;
     case kStageFilter: go(k_filter_batch, shm); break;
     case kStageRows: go(k_rows_batch, shm); break;
     case kStageRaster: go(k_raster256_batch, shm); break;

@@ -27,33 +27,51 @@ __device__ __forceinline__ int quad_xor2(int x) {
   return __builtin_amdgcn_update_dpp(x, x, kDppQuadXor2, 0xF, 0xF, false);
 }
 
+// DPP row broadcasts: lane 15 of each row to the next row, lane 31 to rows
+// 2 and 3.
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+// The value of lane ctl(i) for a control under which every lane has a valid
+// source (quad permutes, mirrors). The form (old 0, bound_ctrl) lets the
+// compiler fold the exchange into the DPP operand of the ALU op that uses it.
+template <int kCtl>
+__device__ __forceinline__ uint32_t dpp_full(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kCtl, 0xF, 0xF, true);
+}
+
 // Every lane of a row ends with the row's minimum / sum.
 __device__ __forceinline__ uint32_t row_min_u32(uint32_t x) {
-  x = min(x, (uint32_t)quad_xor1((int)x));
-  x = min(x, (uint32_t)quad_xor2((int)x));
-  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, kDppRowHalfMirror, 0xF, 0xF,
-                                                     false));
-  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, kDppRowMirror, 0xF, 0xF,
-                                                     false));
-  return x;
+  x = min(x, dpp_full<kDppQuadXor1>(x));
+  x = min(x, dpp_full<kDppQuadXor2>(x));
+  x = min(x, dpp_full<kDppRowHalfMirror>(x));
+  return min(x, dpp_full<kDppRowMirror>(x));
+}
+
+__device__ __forceinline__ uint32_t row_sum_u32(uint32_t x) {
+  x += dpp_full<kDppQuadXor1>(x);
+  x += dpp_full<kDppQuadXor2>(x);
+  x += dpp_full<kDppRowHalfMirror>(x);
+  return x + dpp_full<kDppRowMirror>(x);
+}
+
+// Row results to lane 63: row 1 takes row 0's and row 3 row 2's (lane 15 of
+// the row before), then rows 2 and 3 take row 1's (lane 31). Rows outside a
+// broadcast's row mask get the operation's identity.
+__device__ __forceinline__ uint32_t rows_min_to_lane63(uint32_t x) {
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, kDppRowBcast15, 0xA, 0xF, false));
+  return min(x, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, kDppRowBcast31, 0xC, 0xF, false));
 }
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-  x = row_min_u32(x);
-  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
-  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
-  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
-  const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
-  return min(min(r0, r1), min(r2, r3));
+  return (uint32_t)__builtin_amdgcn_readlane((int)rows_min_to_lane63(row_min_u32(x)), 63);
 }
 
 __device__ __forceinline__ int wave_sum_i32(int x) {
-  x += quad_xor1(x);
-  x += quad_xor2(x);
-  x += __builtin_amdgcn_update_dpp(x, x, kDppRowHalfMirror, 0xF, 0xF, false);
-  x += __builtin_amdgcn_update_dpp(x, x, kDppRowMirror, 0xF, 0xF, false);
-  return __builtin_amdgcn_readlane(x, 0) + __builtin_amdgcn_readlane(x, 16) +
-         __builtin_amdgcn_readlane(x, 32) + __builtin_amdgcn_readlane(x, 48);
+  uint32_t y = row_sum_u32((uint32_t)x);
+  y += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)y, kDppRowBcast15, 0xA, 0xF, false);
+  y += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)y, kDppRowBcast31, 0xC, 0xF, false);
+  return __builtin_amdgcn_readlane((int)y, 63);
 }
 
 // 64-bit minimum: both halves take the same exchange, then one comparison.
