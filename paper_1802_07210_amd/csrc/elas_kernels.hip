@@ -98,17 +98,41 @@ __device__ __forceinline__ uint32_t quantise(int g) {
 // ---------------------------------------------------------------------------
 // Stage 1: 3x3 Sobel gradients and the 16-byte descriptor (Section III-A,
 // Fig. 1(b); Section VI-A: a 16-byte subset of the window's gradients).
-// Block = 64 columns x TH rows (256 threads, TH/4 rows each). The image tile
-// with a 3-pixel halo is staged in LDS, the quantised gradients of the tile
-// with a 2-pixel halo are computed once into LDS, and each thread gathers its
-// 16 bytes and writes one 16-byte store (a wave writes 1 KiB contiguous).
+// Block = 128 columns x TH rows, 256 threads; a thread works on 4 adjacent
+// columns at a time, so that every LDS access moves a word or two instead of
+// a byte. The image tile with its halo is staged in LDS, the quantised
+// gradients of the tile with a 2-pixel halo are computed once into LDS (4
+// per thread step, from two words per image row), and each thread assembles
+// the descriptors of its 4 pixels from two words per gradient row with byte
+// permutes; they leave through an LDS buffer in 1 KiB contiguous stores.
 // Sample pattern (column, row offsets): du at (-2,0) (-1,0) (1,0) (2,0)
 // (-1,-2) (1,-2) (-1,2) (1,2); dv at (0,-2) (0,-1) (0,1) (0,2) (-2,-1) (2,-1)
 // (-2,1) (2,1). Descriptors are defined for 2 <= u <= w-3, 2 <= v <= h-3 and
 // all-zero elsewhere.
 // ---------------------------------------------------------------------------
-constexpr int kDescW = 64;
+constexpr int kDescW = 128;                  // columns per Sobel block
+constexpr int kDescGroups = kDescW / 4;      // 4-column groups per block row
+constexpr int kDescTW = kDescW / 4 + 2;      // tile words per row: image u0-4 .. u0+kDescW+3
+constexpr int kDescQW = kDescW / 4 + 2;      // gradient words per row: image u0-2 .. u0+kDescW+5
+constexpr int kCensusW = 64;                 // columns per census block
 constexpr int kDescRows[kDescVariants] = {4, 8, 16};
+
+__host__ __device__ __forceinline__ int desc_block_width(const KParams& p) {
+  return p.descriptor == 0 ? kDescW : kCensusW;
+}
+
+// Byte k (0..7) of the little-endian pair (lo, hi), k a compile-time constant.
+template <int K>
+__device__ __forceinline__ uint32_t byte_of(uint32_t lo, uint32_t hi) {
+  return K < 4 ? (lo >> (8 * K)) & 0xFFu : (hi >> (8 * (K - 4))) & 0xFFu;
+}
+
+// Selector of v_perm_b32(hi, lo, sel): result byte n = byte sel_n of the
+// pair, 0x0C = zero byte.
+__host__ __device__ constexpr uint32_t perm_sel(int b0, int b1, int b2, int b3) {
+  return (uint32_t)b0 | ((uint32_t)b1 << 8) | ((uint32_t)b2 << 16) | ((uint32_t)b3 << 24);
+}
+constexpr int kZ = 0x0C;  // v_perm: a zero byte
 
 template <int TH>
 __device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
@@ -118,61 +142,124 @@ __device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
   const uint8_t* img = view ? F.right : F.left;
   uint8_t* desc = view ? F.descR : F.descL;
   const int stride = F.stride;
-  __shared__ uint8_t tile[TH + 6][kDescW + 8];
-  __shared__ uint8_t qdu[TH + 4][kDescW + 4];
-  __shared__ uint8_t qdv[TH + 4][kDescW + 4];
+  // tile word j of row r: image columns u0-4+4j .. +3 of image row v0-3+r;
+  // gradient word j of row r: image columns u0-2+4j .. +3 of image row v0-2+r
+  __shared__ uint32_t tile[TH + 6][kDescTW];
+  __shared__ uint32_t qdu[TH + 4][kDescQW];
+  __shared__ uint32_t qdv[TH + 4][kDescQW];
   const int u0 = (tile_id % nbx) * kDescW, v0 = (tile_id / nbx) * TH;
   const int tid = threadIdx.x;
-  constexpr int kTile = (TH + 6) * (kDescW + 6);
+  // rows of 4-byte aligned words whole in the image load as words; the rest
+  // byte by byte (zero outside the image)
+  const bool words_ok = ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)stride) & 3u) == 0;
+  constexpr int kTile = (TH + 6) * kDescTW;
   stage_copy<(kTile + 255) / 256, 256>(
       kTile,
       [&](int i) -> uint32_t {
-        const int r = i / (kDescW + 6), c = i - r * (kDescW + 6);
-        const int y = v0 - 3 + r, x = u0 - 3 + c;
-        return (x >= 0 && x < g.w && y >= 0 && y < g.h) ? img[(size_t)y * stride + x] : 0u;
+        const int r = i / kDescTW, j = i - r * kDescTW;
+        const int y = v0 - 3 + r, x = u0 - 4 + 4 * j;
+        if (y < 0 || y >= g.h) return 0u;
+        const uint8_t* row = img + (size_t)y * stride;
+        if (words_ok && x >= 0 && x + 3 < g.w) return *reinterpret_cast<const uint32_t*>(row + x);
+        uint32_t wv = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (x + b >= 0 && x + b < g.w) wv |= (uint32_t)row[x + b] << (8 * b);
+        return wv;
       },
       [&](int i, uint32_t x) {
-        const int r = i / (kDescW + 6), c = i - r * (kDescW + 6);
-        tile[r][c] = (uint8_t)x;
+        const int r = i / kDescTW, j = i - r * kDescTW;
+        tile[r][j] = x;
       });
   __syncthreads();
-  for (int i = tid; i < (TH + 4) * (kDescW + 4); i += 256) {
-    const int r = i / (kDescW + 4), c = i - r * (kDescW + 4);
-    const int y = v0 - 2 + r, x = u0 - 2 + c;
-    int gx = 0, gy = 0;
-    if (x >= 1 && x <= g.w - 2 && y >= 1 && y <= g.h - 2) {
-      const int tr = r + 1, tc = c + 1;  // (x, y) in tile coordinates
-      const int a = tile[tr - 1][tc - 1], b = tile[tr - 1][tc], cc = tile[tr - 1][tc + 1];
-      const int l = tile[tr][tc - 1], rr = tile[tr][tc + 1];
-      const int d = tile[tr + 1][tc - 1], e = tile[tr + 1][tc], f = tile[tr + 1][tc + 1];
-      gx = (cc + 2 * rr + f) - (a + 2 * l + d);
-      gy = (d + 2 * e + f) - (a + 2 * b + cc);
+  // gradients: word j of gradient row r (image columns x0 .. x0+3, x0 =
+  // u0-2+4j, image row y = v0-2+r) from tile words j, j+1 of tile rows r,
+  // r+1, r+2 (image columns x0-1 .. x0+4 are bytes 1..6 of the pair)
+  for (int i = tid; i < (TH + 4) * kDescQW; i += 256) {
+    const int r = i / kDescQW, j = i - r * kDescQW;
+    const int y = v0 - 2 + r, x0 = u0 - 2 + 4 * j;
+    const uint32_t t0 = tile[r][j], t1 = tile[r][min(j + 1, kDescTW - 1)];
+    const uint32_t m0 = tile[r + 1][j], m1 = tile[r + 1][min(j + 1, kDescTW - 1)];
+    const uint32_t b0 = tile[r + 2][j], b1 = tile[r + 2][min(j + 1, kDescTW - 1)];
+    int colS[6], colD[6];  // per column x0-1+k: top + 2 mid + bottom, bottom - top
+#define ELAS_SOBEL_COL(K)                                                             \
+  {                                                                                   \
+    const int tt = (int)byte_of<K + 1>(t0, t1), mm = (int)byte_of<K + 1>(m0, m1),     \
+              bb = (int)byte_of<K + 1>(b0, b1);                                       \
+    colS[K] = tt + 2 * mm + bb;                                                       \
+    colD[K] = bb - tt;                                                                \
+  }
+    ELAS_SOBEL_COL(0) ELAS_SOBEL_COL(1) ELAS_SOBEL_COL(2) ELAS_SOBEL_COL(3)
+    ELAS_SOBEL_COL(4) ELAS_SOBEL_COL(5)
+#undef ELAS_SOBEL_COL
+    const bool yin = y >= 1 && y <= g.h - 2;
+    uint32_t wu = 0u, wv = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int x = x0 + k;
+      int gx = colS[k + 2] - colS[k];
+      int gy = colD[k] + 2 * colD[k + 1] + colD[k + 2];
+      if (!(yin && x >= 1 && x <= g.w - 2)) gx = gy = 0;
+      wu |= quantise(gx) << (8 * k);
+      wv |= quantise(gy) << (8 * k);
     }
-    qdu[r][c] = (uint8_t)quantise(gx);
-    qdv[r][c] = (uint8_t)quantise(gy);
+    qdu[r][j] = wu;
+    qdv[r][j] = wv;
   }
   __syncthreads();
-  const int tx = tid & 63;
-  const int u = u0 + tx;
-  if (u >= g.w) return;
-#pragma unroll
-  for (int ty = tid >> 6; ty < TH; ty += 4) {
-    const int v = v0 + ty;
-    if (v >= g.h) break;
-    uint4 out = make_uint4(0u, 0u, 0u, 0u);
-    if (u >= 2 && u <= g.w - 3 && v >= 2 && v <= g.h - 3) {
-      const int r = ty + 2, c = tx + 2;
-      out.x = qdu[r][c - 2] | (qdu[r][c - 1] << 8) | (qdu[r][c + 1] << 16) |
-              ((uint32_t)qdu[r][c + 2] << 24);
-      out.y = qdu[r - 2][c - 1] | (qdu[r - 2][c + 1] << 8) | (qdu[r + 2][c - 1] << 16) |
-              ((uint32_t)qdu[r + 2][c + 1] << 24);
-      out.z = qdv[r - 2][c] | (qdv[r - 1][c] << 8) | (qdv[r + 1][c] << 16) |
-              ((uint32_t)qdv[r + 2][c] << 24);
-      out.w = qdv[r - 1][c - 2] | (qdv[r - 1][c + 2] << 8) | (qdv[r + 1][c - 2] << 16) |
-              ((uint32_t)qdv[r + 1][c + 2] << 24);
+  // descriptors: pixels u = u0+4c .. u0+4c+3 of image row v = v0+ty take
+  // gradient words c, c+1 (image columns u-2 .. u+5 as bytes k = 0..7 for
+  // the first pixel, shifted by one per pixel) of gradient rows ty .. ty+4.
+  // Eight rows at a time; the 4 descriptors of a thread go through LDS so
+  // that each store instruction writes 1 KiB contiguous. A descriptor's slot
+  // in a row of the buffer is swizzled (pixel 4c+k at 4c + (k ^ (c/4 % 4)))
+  // so that neither the writes nor the reads conflict on LDS banks.
+  __shared__ uint4 obuf[8][kDescW];
+  const int c = tid & (kDescGroups - 1), orow = tid / kDescGroups;
+  const int ug = u0 + 4 * c;
+  for (int pass = 0; pass < TH; pass += 8) {
+    const int ty = pass + orow;
+    if (ty < TH) {
+      const int v = v0 + ty;
+      const int r = ty + 2;  // gradient row of image row v
+      const uint32_t a0 = qdu[r][c], a1 = qdu[r][c + 1];          // du, row v
+      const uint32_t n0 = qdu[r - 2][c], n1 = qdu[r - 2][c + 1];  // du, row v-2
+      const uint32_t s0 = qdu[r + 2][c], s1 = qdu[r + 2][c + 1];  // du, row v+2
+      const uint32_t e0 = qdv[r - 2][c], e1 = qdv[r - 2][c + 1];  // dv, row v-2
+      const uint32_t f0 = qdv[r - 1][c], f1 = qdv[r - 1][c + 1];  // dv, row v-1
+      const uint32_t h0 = qdv[r + 1][c], h1 = qdv[r + 1][c + 1];  // dv, row v+1
+      const uint32_t k0 = qdv[r + 2][c], k1 = qdv[r + 2][c + 1];  // dv, row v+2
+      const bool vin = v >= 2 && v <= g.h - 3;
+      const int sw = (c >> 2) & 3;
+#define ELAS_DESC_PIXEL(I)                                                                     \
+  {                                                                                            \
+    uint4 o;                                                                                   \
+    o.x = __builtin_amdgcn_perm(a1, a0, perm_sel(I, I + 1, I + 3, I + 4));                     \
+    o.y = __builtin_amdgcn_perm(n1, n0, perm_sel(I + 1, I + 3, kZ, kZ)) |                      \
+          __builtin_amdgcn_perm(s1, s0, perm_sel(kZ, kZ, I + 1, I + 3));                       \
+    o.z = __builtin_amdgcn_perm(e1, e0, perm_sel(I + 2, kZ, kZ, kZ)) |                         \
+          __builtin_amdgcn_perm(f1, f0, perm_sel(kZ, I + 2, kZ, kZ)) |                         \
+          __builtin_amdgcn_perm(h1, h0, perm_sel(kZ, kZ, I + 2, kZ)) |                         \
+          __builtin_amdgcn_perm(k1, k0, perm_sel(kZ, kZ, kZ, I + 2));                          \
+    o.w = __builtin_amdgcn_perm(f1, f0, perm_sel(I, I + 4, kZ, kZ)) |                          \
+          __builtin_amdgcn_perm(h1, h0, perm_sel(kZ, kZ, I, I + 4));                           \
+    const int u = ug + I;                                                                      \
+    if (!(vin && u >= 2 && u <= g.w - 3)) o = make_uint4(0u, 0u, 0u, 0u);                      \
+    obuf[orow][4 * c + (I ^ sw)] = o;                                                          \
+  }
+      ELAS_DESC_PIXEL(0) ELAS_DESC_PIXEL(1) ELAS_DESC_PIXEL(2) ELAS_DESC_PIXEL(3)
+#undef ELAS_DESC_PIXEL
     }
-    const size_t px = (size_t)v * g.w + u;
-    *reinterpret_cast<uint4*>(desc + px * 16) = out;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8 * kDescW / 256; ++i) {
+      const int q = tid + 256 * i, rr = q / kDescW, col = q & (kDescW - 1);
+      const int v = v0 + pass + rr, u = u0 + col;
+      if (pass + rr < TH && v < g.h && u < g.w)
+        *reinterpret_cast<uint4*>(desc + ((size_t)v * g.w + u) * 16) =
+            obuf[rr][(col & ~3) | ((col & 3) ^ ((col >> 4) & 3))];
+    }
+    __syncthreads();
   }
 }
 
@@ -202,15 +289,15 @@ template <int TH>
 __device__ __forceinline__ void census_body(const Frame& F, int lb) {
   const Geometry g = F.g;
   const KParams p = F.p;
-  const int nbx = cdivd(g.w, kDescW);
+  const int nbx = cdivd(g.w, kCensusW);
   const int view = lb & 1, tile_id = lb >> 1;
   const uint8_t* img = view ? F.right : F.left;
   uint64_t* dcen = reinterpret_cast<uint64_t*>(view ? F.descR : F.descL);
   uint4* scen = view ? F.csupR : F.csupL;
   const int stride = F.stride;
-  constexpr int H = kCensusHalo, TW = kDescW + 2 * H;
+  constexpr int H = kCensusHalo, TW = kCensusW + 2 * H;
   __shared__ uint8_t tile[TH + 2 * H][TW];
-  const int u0 = (tile_id % nbx) * kDescW, v0 = (tile_id / nbx) * TH;
+  const int u0 = (tile_id % nbx) * kCensusW, v0 = (tile_id / nbx) * TH;
   const int tid = threadIdx.x;
   constexpr int kTile = (TH + 2 * H) * TW;
   stage_copy<(kTile + 255) / 256, 256>(
@@ -1752,7 +1839,7 @@ int32_t dense_blocks_max(const Geometry& g) { return dense_blocks(g, 0); }
 int32_t stage_blocks(int32_t stage, const Geometry& g, const KParams& p, int dv) {
   switch (stage) {
     case kStageDescriptor:
-      return 2 * cdiv(g.w, kDescW) * cdiv(g.h, kDescRows[std::min(std::max(dv, 0), 2)]);
+      return 2 * cdiv(g.w, desc_block_width(p)) * cdiv(g.h, kDescRows[std::min(std::max(dv, 0), 2)]);
     case kStageSupport: return g.lw > 0 ? g.lh * cdiv(g.lw, support_run(g, p)) : 0;
     case kStageFilter: return filter_tiles_x(g) * filter_tiles_y(g);
     case kStageRedun: return p.redundancy ? 1 : 0;
