@@ -741,11 +741,14 @@ __host__ __device__ __forceinline__ int filter_tiles_y(const Geometry& g) {
   return g.lh > 0 ? cdivd(g.lh, filter_tile(g)) : 1;
 }
 
-__device__ __forceinline__ void filter_body(const Frame& F, int lb) {
+template <int RI, int RR>
+__device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
   const Geometry g = F.g;
   const KParams p = F.p;
   int16_t* smem = reinterpret_cast<int16_t*>(dyn_smem);
-  const int ri = p.incon_window, rr = p.redun_max_dist;
+  // window radii: compile-time when RI / RR > 0 (the loops then unroll and
+  // every LDS read of a window row issues at once)
+  const int ri = RI > 0 ? RI : p.incon_window, rr = RR > 0 ? RR : p.redun_max_dist;
   const int ft = filter_tile(g);
   const int SR = ft + 2 * (ri + rr), SI = ft + 2 * rr;
   int16_t* sraw = smem;            // SR x SR, origin (l0-ri-rr, k0-ri-rr)
@@ -795,11 +798,26 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
       const int d = sraw[(y + ri) * SR + (x + ri)];
       int count = 0;
       if (d >= 0) {
-        for (int yy = y + part; yy <= y + 2 * ri; yy += kFiltParts) {
-          const int16_t* row = sraw + yy * SR + x;
-          for (int xx = 0; xx <= 2 * ri; ++xx) {
-            const int e = row[xx];
-            count += (e >= 0 && abs(e - d) <= p.incon_threshold) ? 1 : 0;
+        if constexpr (RI > 0) {
+#pragma unroll
+          for (int q = 0; q < (2 * RI + kFiltParts) / kFiltParts; ++q) {
+            const int yy = y + part + q * kFiltParts;
+            if (yy > y + 2 * RI) break;
+            const int16_t* row = sraw + yy * SR + x;
+            int e[2 * RI + 1];
+#pragma unroll
+            for (int xx = 0; xx <= 2 * RI; ++xx) e[xx] = row[xx];
+#pragma unroll
+            for (int xx = 0; xx <= 2 * RI; ++xx)
+              count += (e[xx] >= 0 && abs(e[xx] - d) <= p.incon_threshold) ? 1 : 0;
+          }
+        } else {
+          for (int yy = y + part; yy <= y + 2 * ri; yy += kFiltParts) {
+            const int16_t* row = sraw + yy * SR + x;
+            for (int xx = 0; xx <= 2 * ri; ++xx) {
+              const int e = row[xx];
+              count += (e >= 0 && abs(e - d) <= p.incon_threshold) ? 1 : 0;
+            }
           }
         }
       }
@@ -825,10 +843,16 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
     int res = d;
     if (d >= 0) {
       bool before = false, after = false;
-      for (int j = 1; j <= rr; ++j) {
+      auto probe = [&](int j) {
         const int eb = sinc[(y + rr - j) * SI + x], ea = sinc[(y + rr + j) * SI + x];
         before |= eb >= 0 && abs(eb - d) <= p.redun_threshold;
         after |= ea >= 0 && abs(ea - d) <= p.redun_threshold;
+      };
+      if constexpr (RR > 0) {
+#pragma unroll
+        for (int j = 1; j <= RR; ++j) probe(j);
+      } else {
+        for (int j = 1; j <= rr; ++j) probe(j);
       }
       if (before && after) res = -1;
     }
@@ -843,10 +867,16 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
       int res = d;
       if (d >= 0) {
         bool before = false, after = false;
-        for (int j = 1; j <= rr; ++j) {
+        auto probe = [&](int j) {
           const int eb = svert[y * SI + x + rr - j], ea = svert[y * SI + x + rr + j];
           before |= eb >= 0 && abs(eb - d) <= p.redun_threshold;
           after |= ea >= 0 && abs(ea - d) <= p.redun_threshold;
+        };
+        if constexpr (RR > 0) {
+#pragma unroll
+          for (int j = 1; j <= RR; ++j) probe(j);
+        } else {
+          for (int j = 1; j <= rr; ++j) probe(j);
         }
         if (before && after) res = -1;
       }
@@ -856,6 +886,14 @@ __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
       F.dcan_final[idx] = (int16_t)res;
     }
   }
+}
+
+// The default windows (5 and 5 lattice steps) at compile time, else any.
+__device__ __forceinline__ void filter_body(const Frame& F, int lb) {
+  if (F.p.incon_window == 5 && F.p.redun_max_dist == 5)
+    filter_windows<5, 5>(F, lb);
+  else
+    filter_windows<0, 0>(F, lb);
 }
 
 // ---------------------------------------------------------------------------
