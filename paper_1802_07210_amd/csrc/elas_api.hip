@@ -285,6 +285,9 @@ Geometry make_geometry(const elas_params& p, int32_t w, int32_t h) {
   // 8 x 8 filter tiles while every tile of the frame can have a CU of its
   // own, else 16 x 16 (fewer halo positions per tile)
   g.ftile = ((g.lw + 7) / 8) * ((g.lh + 7) / 8) <= 256 ? 8 : 16;
+  // runs of 8 support points while runs of 16 would leave fewer than two
+  // workgroups per CU, else 16 (less staging per point)
+  g.srun = g.lh * ((g.lw + 15) / 16) < 512 ? 8 : 16;
   g.gdiv = (uint32_t)(((1ull << 31) + (uint64_t)p.grid_size - 1) / (uint64_t)p.grid_size);
   return g;
 }
@@ -475,8 +478,9 @@ int pool_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, size
     const int rc = alloc_buffers(h, w, hp, &b);
     if (rc != ELAS_OK) return rc;
     // a batch has workgroups enough to fill the chip: the larger filter
-    // tiles, which compute fewer halo positions per lattice point
+    // tiles and support runs, which compute and stage less halo per point
     b->g.ftile = 16;
+    b->g.srun = 16;
     v.push_back(b);
   }
   *out = v[slot];

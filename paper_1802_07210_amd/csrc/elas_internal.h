@@ -28,6 +28,8 @@ struct Geometry {
   int32_t gw, gh;     // grid-vector regions
   int32_t gwords;     // 32-bit words per region mask (even: 64-bit aligned masks)
   int32_t ftile;      // support-filter tile side in lattice points (8 or 16)
+  int32_t srun;       // lattice points per support workgroup (8 or 16; fewer when
+                      // the staged columns would not fit in LDS)
   uint32_t gdiv;      // ceil(2^31 / grid_size): x / grid_size = umulhi(2x, gdiv)
                       // exactly for 0 <= x < 2^31 / grid_size
 };

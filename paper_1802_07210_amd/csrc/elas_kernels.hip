@@ -605,13 +605,14 @@ __host__ __device__ __forceinline__ int support_cols_right(int q, int step, int 
 __host__ __device__ __forceinline__ int support_cols_left(int q, int step, int D) {
   return (q - 1) * step + 2 * D + 3;
 }
-constexpr int kSupportRunMax = 16;          // lattice points per workgroup
+constexpr int kSupportRunMax = 16;          // lattice points per workgroup, at most
 constexpr int kSupportLdsMax = 64 * 1024;   // 32 bytes per staged column
 constexpr int kSupportStageCols = 512;      // columns per plane staged per round
 
-// Points per workgroup: 16, fewer when the staged columns would not fit.
+// Points per workgroup: the geometry's run length, fewer when the staged
+// columns would not fit.
 __host__ __device__ __forceinline__ int support_run(const Geometry& g, const KParams& p) {
-  int q = kSupportRunMax;
+  int q = max(1, min(g.srun, kSupportRunMax));
   while (q > 1 && 32 * (support_cols_right(q, g.step, p.D) + support_cols_left(q, g.step, p.D)) >
                       kSupportLdsMax)
     --q;
