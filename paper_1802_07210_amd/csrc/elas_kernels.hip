@@ -1819,17 +1819,25 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
 }
 
 // ---- kernels: one frame, or a batch in one launch --------------------------
-#define ELAS_STAGE_KERNELS(NAME, BODY, THREADS)                                         \
-  __global__ __launch_bounds__(THREADS) void NAME(Frame F) {                            \
+// ATTR: extra kernel attributes (an occupancy target where measured faster).
+#define ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ATTR)                              \
+  __global__ __launch_bounds__(THREADS) ATTR void NAME(Frame F) {                       \
     BODY(F, xcd_remap(blockIdx.x, gridDim.x));                                          \
   }                                                                                     \
-  __global__ __launch_bounds__(THREADS) void NAME##_batch(                              \
+  __global__ __launch_bounds__(THREADS) ATTR void NAME##_batch(                         \
       const Frame* __restrict__ frames, const int32_t* __restrict__ starts, int nf) {   \
     const int b = xcd_remap(blockIdx.x, gridDim.x);                                     \
     const int f = frame_of(starts, nf, b);                                              \
     const Frame F = global_frame(frames[f], reinterpret_cast<const char*>(frames));     \
     BODY(F, b - starts[f]);                                                             \
   }
+#define ELAS_NO_ATTR
+#define ELAS_STAGE_KERNELS(NAME, BODY, THREADS) \
+  ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ELAS_NO_ATTR)
+// Eight wavefronts per SIMD: the register budget that lets the 1- and 2-row
+// dense tiles fill the SIMDs (their LDS allows it; the compiler would
+// otherwise take a few more VGPRs and stop at seven)
+#define ELAS_OCC8 __attribute__((amdgpu_waves_per_eu(8, 8)))
 
 ELAS_STAGE_KERNELS(k_descriptor4, stage1_body<4>, 256)
 ELAS_STAGE_KERNELS(k_descriptor8, stage1_body<8>, 256)
@@ -1839,14 +1847,17 @@ ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
 ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
 ELAS_STAGE_KERNELS(k_raster, raster_body<1024>, 1024)
 ELAS_STAGE_KERNELS(k_raster256, raster_body<256>, 256)
-ELAS_STAGE_KERNELS(k_dense_r1, dense_body<1>, 256)
-ELAS_STAGE_KERNELS(k_dense_r2, dense_body<2>, 256)
+ELAS_STAGE_KERNELS_ATTR(k_dense_r1, dense_body<1>, 256, ELAS_OCC8)
+ELAS_STAGE_KERNELS_ATTR(k_dense_r2, dense_body<2>, 256, ELAS_OCC8)
 ELAS_STAGE_KERNELS(k_dense_r4, dense_body<4>, 256)
 ELAS_STAGE_KERNELS(k_check, check_body, 256)
 ELAS_STAGE_KERNELS(k_redun, redun_body, 1024)
 ELAS_STAGE_KERNELS(k_median, median_body, 256)
 
 #undef ELAS_STAGE_KERNELS
+#undef ELAS_STAGE_KERNELS_ATTR
+#undef ELAS_NO_ATTR
+#undef ELAS_OCC8
 
 size_t filter_lds_bytes(const Geometry& g, const KParams& p) {
   const int ft = filter_tile(g);
