@@ -210,16 +210,18 @@ __device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
   // descriptors: pixels u = u0+4c .. u0+4c+3 of image row v = v0+ty take
   // gradient words c, c+1 (image columns u-2 .. u+5 as bytes k = 0..7 for
   // the first pixel, shifted by one per pixel) of gradient rows ty .. ty+4.
-  // Eight rows at a time; the 4 descriptors of a thread go through LDS so
-  // that each store instruction writes 1 KiB contiguous. A descriptor's slot
+  // Four rows at a time (a smaller buffer, more workgroups per CU); the 4
+  // descriptors of a thread go through LDS so that each store instruction
+  // writes 1 KiB contiguous. A descriptor's slot
   // in a row of the buffer is swizzled (pixel 4c+k at 4c + (k ^ (c/4 % 4)))
   // so that neither the writes nor the reads conflict on LDS banks.
-  __shared__ uint4 obuf[8][kDescW];
+  constexpr int kOutRows = 4;
+  __shared__ uint4 obuf[kOutRows][kDescW];
   const int c = tid & (kDescGroups - 1), orow = tid / kDescGroups;
   const int ug = u0 + 4 * c;
-  for (int pass = 0; pass < TH; pass += 8) {
+  for (int pass = 0; pass < TH; pass += kOutRows) {
     const int ty = pass + orow;
-    if (ty < TH) {
+    if (orow < kOutRows && ty < TH) {
       const int v = v0 + ty;
       const int r = ty + 2;  // gradient row of image row v
       const uint32_t a0 = qdu[r][c], a1 = qdu[r][c + 1];          // du, row v
@@ -252,7 +254,7 @@ __device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8 * kDescW / 256; ++i) {
+    for (int i = 0; i < kOutRows * kDescW / 256; ++i) {
       const int q = tid + 256 * i, rr = q / kDescW, col = q & (kDescW - 1);
       const int v = v0 + pass + rr, u = u0 + col;
       if (pass + rr < TH && v < g.h && u < g.w)
