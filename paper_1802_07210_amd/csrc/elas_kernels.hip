@@ -1095,12 +1095,15 @@ constexpr int kWaveSpan = 64 * (2 + 2 * kBandRowsMax);  // per-wave span table i
 // pack more bands per CU (larger frames, batches).
 template <int kRasterThreads>
 __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
-  constexpr int kRasterScan = 2048 / kRasterThreads;  // triangles per thread and gather step
+  // triangles per thread and gather step: 2048 per step with 1024 threads,
+  // 1024 with 256
+  constexpr int kRasterScan = kRasterThreads == 1024 ? 2 : 4;
   constexpr int kRasterOut = 2048 / kRasterThreads < 4 ? 4 : 2048 / kRasterThreads;
   constexpr int kRasterWaves = kRasterThreads / 64;
   // ranks of gathered triangles per pass: the 256-thread variant keeps its
-  // LDS small, so that more bands share a CU
-  constexpr int kRasterList = kRasterThreads == 1024 ? 4096 : 2560;
+  // LDS small, so that more bands share a CU (a band of a few rows overlaps
+  // tens of triangles; a pass ends when the list could overflow)
+  constexpr int kRasterList = kRasterThreads == 1024 ? 4096 : 1280;
   static_assert(kRasterScan * kRasterThreads <= kRasterList, "a gather step must fit the list");
   int32_t* const tile = reinterpret_cast<int32_t*>(dyn_smem);  // band rows x width
   __shared__ int32_t rlist[kRasterList];
