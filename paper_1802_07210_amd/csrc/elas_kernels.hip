@@ -799,6 +799,11 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
       const int i = min(task / kFiltParts, npos - 1), part = task % kFiltParts;
       const int y = i / SI, x = i - y * SI;
       const int d = sraw[(y + ri) * SR + (x + ri)];
+      // e counts iff e >= 0 and |e - d| <= threshold: for d >= 0 one unsigned
+      // range test, e in [max(0, d - t), d + t] (e = -1 falls outside)
+      const int t = min(p.incon_threshold, 1 << 12);  // disparities differ by < 2^9
+      const int lo = max(0, d - t);
+      const uint32_t span = (uint32_t)(d + t - lo);
       int count = 0;
       if (d >= 0) {
         if constexpr (RI > 0) {
@@ -811,16 +816,12 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
 #pragma unroll
             for (int xx = 0; xx <= 2 * RI; ++xx) e[xx] = row[xx];
 #pragma unroll
-            for (int xx = 0; xx <= 2 * RI; ++xx)
-              count += (e[xx] >= 0 && abs(e[xx] - d) <= p.incon_threshold) ? 1 : 0;
+            for (int xx = 0; xx <= 2 * RI; ++xx) count += (uint32_t)(e[xx] - lo) <= span ? 1 : 0;
           }
         } else {
           for (int yy = y + part; yy <= y + 2 * ri; yy += kFiltParts) {
             const int16_t* row = sraw + yy * SR + x;
-            for (int xx = 0; xx <= 2 * ri; ++xx) {
-              const int e = row[xx];
-              count += (e >= 0 && abs(e - d) <= p.incon_threshold) ? 1 : 0;
-            }
+            for (int xx = 0; xx <= 2 * ri; ++xx) count += (uint32_t)(row[xx] - lo) <= span ? 1 : 0;
           }
         }
       }
@@ -846,10 +847,13 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
     int res = d;
     if (d >= 0) {
       bool before = false, after = false;
+      // e >= 0 and |e - d| <= threshold as one unsigned range test (d >= 0)
+      const int t = min(p.redun_threshold, 1 << 12), lo = max(0, d - t);
+      const uint32_t span = (uint32_t)(d + t - lo);
       auto probe = [&](int j) {
         const int eb = sinc[(y + rr - j) * SI + x], ea = sinc[(y + rr + j) * SI + x];
-        before |= eb >= 0 && abs(eb - d) <= p.redun_threshold;
-        after |= ea >= 0 && abs(ea - d) <= p.redun_threshold;
+        before |= (uint32_t)(eb - lo) <= span;
+        after |= (uint32_t)(ea - lo) <= span;
       };
       if constexpr (RR > 0) {
 #pragma unroll
@@ -870,10 +874,12 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
       int res = d;
       if (d >= 0) {
         bool before = false, after = false;
+        const int t = min(p.redun_threshold, 1 << 12), lo = max(0, d - t);
+        const uint32_t span = (uint32_t)(d + t - lo);
         auto probe = [&](int j) {
           const int eb = svert[y * SI + x + rr - j], ea = svert[y * SI + x + rr + j];
-          before |= eb >= 0 && abs(eb - d) <= p.redun_threshold;
-          after |= ea >= 0 && abs(ea - d) <= p.redun_threshold;
+          before |= (uint32_t)(eb - lo) <= span;
+          after |= (uint32_t)(ea - lo) <= span;
         };
         if constexpr (RR > 0) {
 #pragma unroll
