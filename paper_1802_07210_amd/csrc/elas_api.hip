@@ -289,6 +289,7 @@ Geometry make_geometry(const elas_params& p, int32_t w, int32_t h) {
   // workgroups per CU, else 16 (less staging per point)
   g.srun = g.lh * ((g.lw + 15) / 16) < 512 ? 8 : 16;
   g.gdiv = (uint32_t)(((1ull << 31) + (uint64_t)p.grid_size - 1) / (uint64_t)p.grid_size);
+  g.rowmul = ((1ull << 40) + (uint64_t)w - 1) / (uint64_t)w;
   return g;
 }
 

@@ -30,6 +30,8 @@ struct Geometry {
   int32_t ftile;      // support-filter tile side in lattice points (8 or 16)
   int32_t srun;       // lattice points per support workgroup (8 or 16; fewer when
                       // the staged columns would not fit in LDS)
+  uint64_t rowmul;    // ceil(2^40 / w): row of pixel index px = (px * rowmul) >> 40,
+                      // exact for px < 2^27
   uint32_t gdiv;      // ceil(2^31 / grid_size): x / grid_size = umulhi(2x, gdiv)
                       // exactly for 0 <= x < 2^31 / grid_size
 };

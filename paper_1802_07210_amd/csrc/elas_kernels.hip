@@ -1723,23 +1723,30 @@ __device__ __forceinline__ void check_body(const Frame& F, int lb) {
   const int16_t* other = right ? rawL : rawR;
   int16_t* dst = right ? (med ? chkR : outR) : (med ? chkL : outL);
   const int px0 = (lb >> 1) * (256 * kCheckPx) + (int)threadIdx.x;
+  // row of a pixel index by a multiply: v = floor(px * m / 2^40), m =
+  // ceil(2^40 / w), exact for px < 2^27 and w < 2^13 (the error term stays
+  // below px * w / 2^40 < 1/2 of a step)
+  const uint64_t m = g.rowmul;
   int d[kCheckPx], e[kCheckPx];
 #pragma unroll
   for (int k = 0; k < kCheckPx; ++k) d[k] = self[min(px0 + 256 * k, npx - 1)];
 #pragma unroll
   for (int k = 0; k < kCheckPx; ++k) {
     const int px = min(px0 + 256 * k, npx - 1);
-    const int v = px / g.w, u = px - v * g.w;
+    const int v = (int)(((uint64_t)(uint32_t)px * m) >> 40), u = px - v * g.w;
     const int x = right ? u + d[k] : u - d[k];  // partner column
     const int ev = other[(size_t)v * g.w + min(max(x, 0), g.w - 1)];  // in bounds always
     e[k] = (d[k] >= 0 && x >= 0 && x < g.w) ? ev : -1;
   }
+  // e >= 0 and |e - d| <= threshold as one unsigned range test (for d >= 0)
+  const int t = min(thr, 1 << 12);
 #pragma unroll
   for (int k = 0; k < kCheckPx; ++k) {
     const int px = px0 + 256 * k;
     if (px >= npx) break;
-    const int r = (d[k] >= 0 && e[k] >= 0 && abs(e[k] - d[k]) <= thr) ? d[k] : -1;
-    dst[px] = (int16_t)r;
+    const int lo = max(0, d[k] - t);
+    const bool ok = d[k] >= 0 && (uint32_t)(e[k] - lo) <= (uint32_t)(d[k] + t - lo);
+    dst[px] = (int16_t)(ok ? d[k] : -1);
   }
 }
 
