@@ -1078,8 +1078,13 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
 // whole tile with coalesced stores, together with each pixel's prior
 // disparity (the owning plane's mean). Every pixel is written.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int floordiv_pos(int a, int b) {  // b > 0
-  return a >= 0 ? a / b : -((-a + b - 1) / b);
+// floor(a / b) for any int a and 0 < b <= 2^13, by a correctly rounded fp64
+// division (no integer division sequence): a non-integral quotient lies at
+// least 1/b >= 2^-13 from the nearest integer, and the rounding error of a
+// quotient below 2^31 is at most 2^-22, so rounding cannot carry it across
+// an integer.
+__device__ __forceinline__ int floordiv_pos(int a, int b) {
+  return (int)floor(__ddiv_rn((double)a, (double)b));
 }
 
 // Narrows [lo, hi] to the u with k*u + c >= 0.
