@@ -744,6 +744,10 @@ __host__ __device__ __forceinline__ int filter_tiles_y(const Geometry& g) {
   return g.lh > 0 ? cdivd(g.lh, filter_tile(g)) : 1;
 }
 
+// i / n for 2 <= n and 0 <= i < 2^32 / n by a multiply: m = ceil(2^32 / n)
+// (the error term i * (m n - 2^32) / 2^32 stays below i n / 2^32 < 1)
+__device__ __forceinline__ int div_small(int i, uint32_t m) { return (int)__umulhi((uint32_t)i, m); }
+
 template <int RI, int RR>
 __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
   const Geometry g = F.g;
@@ -757,6 +761,23 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
   int16_t* sraw = smem;            // SR x SR, origin (l0-ri-rr, k0-ri-rr)
   int16_t* sinc = sraw + SR * SR;  // SI x SI, origin (l0-rr, k0-rr)
   int16_t* svert = sinc + SI * SI; // ft x SI, origin (l0, k0-rr)
+  // positions to (row, column) by multiplies (8 <= SI <= SR <= 80); with
+  // compile-time windows the multipliers are constants for both tile sides
+  auto mul_of = [](int n) { return (uint32_t)(((1ull << 32) + n - 1) / n); };
+  uint32_t mSR, mSI;
+  if constexpr (RI > 0 && RR > 0) {
+    constexpr int kSR8 = 8 + 2 * (RI + RR), kSI8 = 8 + 2 * RR;
+    constexpr int kSR16 = 16 + 2 * (RI + RR), kSI16 = 16 + 2 * RR;
+    constexpr uint32_t mR8 = (uint32_t)(((1ull << 32) + kSR8 - 1) / kSR8);
+    constexpr uint32_t mR16 = (uint32_t)(((1ull << 32) + kSR16 - 1) / kSR16);
+    constexpr uint32_t mI8 = (uint32_t)(((1ull << 32) + kSI8 - 1) / kSI8);
+    constexpr uint32_t mI16 = (uint32_t)(((1ull << 32) + kSI16 - 1) / kSI16);
+    mSR = ft == 8 ? mR8 : (ft == 16 ? mR16 : mul_of(SR));
+    mSI = ft == 8 ? mI8 : (ft == 16 ? mI16 : mul_of(SI));
+  } else {
+    mSR = mul_of(SR);
+    mSI = mul_of(SI);
+  }
   const int ntx = filter_tiles_x(g), nblk = ntx * filter_tiles_y(g);
   const int k0 = (lb % ntx) * ft, l0 = (lb / ntx) * ft;
   const int tid = threadIdx.x;
@@ -783,7 +804,7 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
   stage_copy<2, 1024>(
       SR * SR,
       [&](int i) -> int {
-        const int y = i / SR, x = i - y * SR;
+        const int y = div_small(i, mSR), x = i - y * SR;
         const int l = l0 - ri - rr + y, k = k0 - ri - rr + x;
         return (l >= 0 && l < g.lh && k >= 0 && k < g.lw) ? (int)raw[(size_t)l * g.lw + k] : -1;
       },
@@ -797,7 +818,7 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
     const int ntask = cdivd(npos * kFiltParts, 64) * 64;
     for (int task = tid; task < ntask; task += 1024) {
       const int i = min(task / kFiltParts, npos - 1), part = task % kFiltParts;
-      const int y = i / SI, x = i - y * SI;
+      const int y = div_small(i, mSI), x = i - y * SI;
       const int d = sraw[(y + ri) * SR + (x + ri)];
       // e counts iff e >= 0 and |e - d| <= threshold: for d >= 0 one unsigned
       // range test, e in [max(0, d - t), d + t] (e = -1 falls outside)
@@ -842,7 +863,7 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
     return;
   }
   for (int i = tid; i < ft * SI; i += 1024) {
-    const int y = i / SI, x = i - y * SI;
+    const int y = div_small(i, mSI), x = i - y * SI;
     const int d = sinc[(y + rr) * SI + x];
     int res = d;
     if (d >= 0) {
