@@ -356,7 +356,7 @@ def batch_c4(torch, Elas, reps=5, n=96):
             "evals_per_s_algorithmic": round(evals * fps_batch / n, 1),
             "identical_to_sequential": bool(same),
             "graph": True, "autotune": True,
-            "tuned_desc_rows_dense_batch_at_D128": tuned}
+            "tuned_desc_rows_dense_rows_support_run_at_D128": tuned}
 
 
 def main():

@@ -245,9 +245,10 @@ enum elas_batch_flags {
   ELAS_BATCH_GRAPH = 1,         /* capture each batch shape's launches in a HIP graph
                                    once and replay it */
   ELAS_BATCH_AUTOTUNE = 2       /* on the first batch with a new (w, h, D), time the
-                                   descriptor (4/8/16 rows per block) and dense (1/2/4
-                                   rows per block) variants on its frames and keep the
-                                   fastest; results are identical for all */
+                                   descriptor (4/8/16 rows per block), dense (1/2/4
+                                   rows per block) and support (16/32 lattice points per
+                                   block) variants on its frames and keep the fastest;
+                                   results are identical for all */
 };
 ELAS_API int elas_set_batch_flags(elas_handle* h, int32_t flags);
 
@@ -272,20 +273,24 @@ ELAS_API int elas_process_batch(elas_handle* h, int32_t n, const elas_pair* pair
                                 hipStream_t stream);
 
 /* Tile variants the autotuner chose for (w, h) at this handle's disparity
- * count: descriptor rows per block and dense rows per block (the rows a
+ * count: descriptor rows per block, dense rows per block (the rows a
  * workgroup stages in LDS, the device's counterpart of the line buffers of
- * Section V-A). ELAS_ERR_ARG if none has been chosen yet. */
+ * Section V-A) and support run length (lattice points per support workgroup,
+ * whose reachable descriptor columns it stages in LDS: 16 or 32 when tuned).
+ * ELAS_ERR_ARG for null pointers or if none has been chosen yet. */
 ELAS_API int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t h_px,
-                                     int32_t* desc_rows, int32_t* dense_rows);
+                                     int32_t* desc_rows, int32_t* dense_rows,
+                                     int32_t* support_run);
 
 /* Fixes the tile variants of (w, h) at this handle's disparity count, as the
  * autotuner would (descriptor rows per block 4, 8 or 16; dense rows per
- * block 1, 2 or 4: the LDS row tiles of Section V-A's line buffers); used by
- * single and batched calls, and the autotuner then leaves that size alone.
- * Results do not depend on the variants. ELAS_ERR_ARG for other values or
- * a side below 9. */
+ * block 1, 2 or 4: the LDS row tiles of Section V-A's line buffers; support
+ * run length 8, 16 or 32 lattice points per workgroup); used by single and
+ * batched calls, and the autotuner then leaves that size alone. Results do
+ * not depend on the variants. ELAS_ERR_ARG for other values or a side below
+ * 9. */
 ELAS_API int elas_set_tile_variants(elas_handle* h, int32_t w, int32_t h_px, int32_t desc_rows,
-                                    int32_t dense_rows);
+                                    int32_t dense_rows, int32_t support_run);
 
 /* Device bytes of the buffers one pair of size (w, h_px) needs with h's
  * parameters (descriptors, lattice, grid, mesh, maps: every intermediate of

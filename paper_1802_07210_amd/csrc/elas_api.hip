@@ -182,6 +182,9 @@ struct elas_handle {
   std::map<hipStream_t, BatchCtx*> batch;
   std::map<std::tuple<int32_t, int32_t, hipStream_t>, std::vector<Buffers*>> pool;
   std::map<std::tuple<int32_t, int32_t, int32_t>, std::pair<int, int>> tuned;
+  // support run length (lattice points per workgroup) per (w, h, D), when
+  // tuned or set; otherwise the geometry's default
+  std::map<std::tuple<int32_t, int32_t, int32_t>, int32_t> tuned_srun;
   hipStream_t tune_stream = nullptr;
   // device-mesh failure report: a pinned, device-mapped word that the mesh
   // kernel of a failing frame sets to its status; the next call on the
@@ -480,8 +483,9 @@ int pool_buffers(elas_handle* h, int32_t w, int32_t hp, hipStream_t stream, size
     if (rc != ELAS_OK) return rc;
     // a batch has workgroups enough to fill the chip: the larger filter
     // tiles and support runs, which compute and stage less halo per point
+    // (runs of 32 measured faster up to D = 192, 16 at D = 256)
     b->g.ftile = 16;
-    b->g.srun = 16;
+    b->g.srun = h->kp.D <= 192 ? 32 : 16;
     v.push_back(b);
   }
   *out = v[slot];
@@ -508,6 +512,13 @@ std::pair<int, int> variants_lookup(const elas_handle* h, int32_t w, int32_t hp,
 
 std::pair<int, int> variants_for(const elas_handle* h, int32_t w, int32_t hp) {
   return variants_lookup(h, w, hp, h->kp.D, false, h->kp.descriptor != 0);
+}
+
+// The frame's support run length: tuned or set for its (w, h, D), else the
+// geometry's default.
+void apply_support_run(const elas_handle* h, Frame* f) {
+  auto it = h->tuned_srun.find(std::make_tuple(f->g.w, f->g.h, f->p.D));
+  if (it != h->tuned_srun.end()) f->g.srun = it->second;
 }
 
 Frame make_frame(const elas_handle* h, const Buffers* b, const uint8_t* left,
@@ -940,6 +951,7 @@ int elas::process_one(elas_handle* h, const uint8_t* left, const uint8_t* right,
   for (bool& u : h->kev_used) u = false;
 
   Frame F = make_frame(h, b, left, right, stride, disp_left, disp_right, on_host);
+  apply_support_run(h, &F);
   if (report) F.mfail = report;
   const std::pair<int, int> var = variants_for(h, w, hp);
   h->last_dense_variant = var.second;
@@ -1059,7 +1071,8 @@ int elas_process_noalloc(elas_handle* h, const uint8_t* left, const uint8_t* rig
   for (int32_t i = 0; i < h->kp.D; ++i) la.v[i] = h->lut[i];
   hipLaunchKernelGGL(k_write_lut, dim3(1), dim3(kMaxD), 0, stream, la, b.lut, h->kp.D);
   HIP_TRY(hipGetLastError());
-  const Frame F = make_frame(h, &b, left, right, stride, disp_left, disp_right, false);
+  Frame F = make_frame(h, &b, left, right, stride, disp_left, disp_right, false);
+  apply_support_run(h, &F);
   const std::pair<int, int> var = variants_for(h, w, hp);
   h->last_dense_variant = var.second;
   for (int32_t st = 0; st < kStageCount; ++st) {
@@ -1159,7 +1172,7 @@ hipError_t enqueue_batch(const std::vector<LaunchRec>& recs, uint8_t* dev, hipSt
 // (w, h, D) and keeps the fastest of each (the stages recompute identical
 // outputs, so the batch's results are unaffected).
 int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
-             hipStream_t stream, std::pair<int, int>* best) {
+             hipStream_t stream, std::pair<int, int>* best, int32_t* best_srun) {
   HIP_TRY(hipStreamSynchronize(stream));
   const size_t need = align256(frames.size() * sizeof(Frame)) + align256((frames.size() + 1) * 4);
   if (need > c->tune_cap) {
@@ -1172,27 +1185,34 @@ int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  int choice[2] = {0, 1};
-  const int32_t stages[2] = {kStageDescriptor, kStageDense};
-  for (int k = 0; k < 2; ++k) {
+  // descriptor rows (variant 0..2), dense rows (0..2), support run length
+  // (16 or 32 lattice points per workgroup, set in the frames' geometry)
+  int choice[3] = {0, 1, 0};
+  static const int32_t kRuns[2] = {16, 32};
+  const int32_t stages[3] = {kStageDescriptor, kStageDense, kStageSupport};
+  std::vector<Frame> fr(frames);
+  for (int k = 0; k < 3; ++k) {
     float best_ms = 1e30f;
-    const int nvar = k == 0 ? kDescVariants : kDenseVariants;
+    const int nvar = k == 0 ? kDescVariants : (k == 1 ? kDenseVariants : 2);
     for (int v = 0; v < nvar; ++v) {
+      if (k == 2)
+        for (Frame& f : fr) f.g.srun = kRuns[v];
+      const int lv = k == 2 ? 0 : v;  // the launch's tile variant
       std::vector<int32_t> starts(1, 0);
-      for (const Frame& f : frames)
-        starts.push_back(starts.back() + stage_blocks(stages[k], f.g, f.p, v));
+      for (const Frame& f : fr)
+        starts.push_back(starts.back() + stage_blocks(stages[k], f.g, f.p, lv));
       uint8_t* dev = static_cast<uint8_t*>(c->tune_dev);
-      const size_t soff = align256(frames.size() * sizeof(Frame));
-      HIP_TRY(hipMemcpy(dev, frames.data(), frames.size() * sizeof(Frame), hipMemcpyHostToDevice));
+      const size_t soff = align256(fr.size() * sizeof(Frame));
+      HIP_TRY(hipMemcpy(dev, fr.data(), fr.size() * sizeof(Frame), hipMemcpyHostToDevice));
       HIP_TRY(hipMemcpy(dev + soff, starts.data(), starts.size() * 4, hipMemcpyHostToDevice));
       size_t lds = 0;
-      for (const Frame& f : frames) lds = std::max(lds, stage_lds(stages[k], f.g, f.p));
+      for (const Frame& f : fr) lds = std::max(lds, stage_lds(stages[k], f.g, f.p));
       float ms_min = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
         HIP_TRY(hipEventRecord(e0, stream));
         HIP_TRY(launch_stage_batch(stages[k], reinterpret_cast<const Frame*>(dev),
                                    reinterpret_cast<const int32_t*>(dev + soff),
-                                   (int32_t)frames.size(), starts.back(), lds, v, stream));
+                                   (int32_t)fr.size(), starts.back(), lds, lv, stream));
         HIP_TRY(hipEventRecord(e1, stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -1208,6 +1228,7 @@ int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
   HIP_TRY(hipEventDestroy(e0));
   HIP_TRY(hipEventDestroy(e1));
   *best = std::make_pair(choice[0], choice[1]);
+  *best_srun = kRuns[choice[2]];
   return ELAS_OK;
 }
 
@@ -1273,6 +1294,7 @@ int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipSt
     if (rc != ELAS_OK) return fail(h, rc, elas_last_error(ph));
     frames.push_back(make_frame(ph, b, q.left, q.right, q.stride, q.disp_left, q.disp_right,
                                 false));
+    apply_support_run(h, &frames.back());
     // a failing device mesh reports on the calling handle (or the pair's word)
     frames.back().mfail = reports ? reports[i] : h->fail_dev;
     h->last_batch[i] = elas_handle::BatchPair{ph, b, stream, false};
@@ -1366,9 +1388,11 @@ int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipSt
     }
     for (auto& kv : groups) {
       std::pair<int, int> best;
-      rc = autotune(h, c, kv.second, stream, &best);
+      int32_t srun = 16;
+      rc = autotune(h, c, kv.second, stream, &best, &srun);
       if (rc != ELAS_OK) return rc;
       h->tuned[kv.first] = best;
+      h->tuned_srun[kv.first] = srun;
     }
   }
   return ELAS_OK;
@@ -1431,7 +1455,7 @@ int elas_frame_bytes(elas_handle* h, int32_t w, int32_t hp, int64_t* bytes) {
 }
 
 int elas_set_tile_variants(elas_handle* h, int32_t w, int32_t hp, int32_t desc_rows,
-                           int32_t dense_rows) {
+                           int32_t dense_rows, int32_t support_run) {
   if (!h) return fail(nullptr, ELAS_ERR_ARG, "null handle");
   static const int32_t drows[3] = {4, 8, 16}, nrows[3] = {1, 2, 4};
   int dv = -1, nv = -1;
@@ -1439,20 +1463,29 @@ int elas_set_tile_variants(elas_handle* h, int32_t w, int32_t hp, int32_t desc_r
     if (drows[k] == desc_rows) dv = k;
     if (nrows[k] == dense_rows) nv = k;
   }
-  if (dv < 0 || nv < 0 || w < 9 || hp < 9)
-    return fail(h, ELAS_ERR_ARG, "descriptor rows must be 4, 8 or 16 and dense rows 1, 2 or 4");
-  h->tuned[std::make_tuple(w, hp, h->kp.D)] = std::make_pair(dv, nv);
+  if (dv < 0 || nv < 0 || w < 9 || hp < 9 ||
+      (support_run != 8 && support_run != 16 && support_run != 32))
+    return fail(h, ELAS_ERR_ARG,
+                "descriptor rows must be 4, 8 or 16, dense rows 1, 2 or 4, support run 8, 16 "
+                "or 32");
+  const auto key = std::make_tuple(w, hp, h->kp.D);
+  h->tuned[key] = std::make_pair(dv, nv);
+  h->tuned_srun[key] = support_run;
   return ELAS_OK;
 }
 
 int elas_get_tuned_variants(elas_handle* h, int32_t w, int32_t hp, int32_t* desc_rows,
-                            int32_t* dense_batch) {
-  if (!h || !desc_rows || !dense_batch) return fail(h, ELAS_ERR_ARG, "null argument");
-  auto it = h->tuned.find(std::make_tuple(w, hp, h->kp.D));
+                            int32_t* dense_batch, int32_t* support_run) {
+  if (!h || !desc_rows || !dense_batch || !support_run)
+    return fail(h, ELAS_ERR_ARG, "null argument");
+  const auto key = std::make_tuple(w, hp, h->kp.D);
+  auto it = h->tuned.find(key);
   if (it == h->tuned.end()) return fail(h, ELAS_ERR_ARG, "no tuned variants for this size");
   static const int32_t rows[3] = {4, 8, 16}, batch[3] = {1, 2, 4};  // descriptor / dense rows
   *desc_rows = rows[it->second.first];
   *dense_batch = batch[it->second.second];
+  auto is = h->tuned_srun.find(key);
+  *support_run = is != h->tuned_srun.end() ? is->second : 16;
   return ELAS_OK;
 }
 

@@ -607,7 +607,7 @@ __host__ __device__ __forceinline__ int support_cols_right(int q, int step, int 
 __host__ __device__ __forceinline__ int support_cols_left(int q, int step, int D) {
   return (q - 1) * step + 2 * D + 3;
 }
-constexpr int kSupportRunMax = 16;          // lattice points per workgroup, at most
+constexpr int kSupportRunMax = 32;          // lattice points per workgroup, at most
 constexpr int kSupportLdsMax = 64 * 1024;   // 32 bytes per staged column
 constexpr int kSupportStageCols = 512;      // columns per plane staged per round
 

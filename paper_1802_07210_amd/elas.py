@@ -140,9 +140,10 @@ def lib() -> C.CDLL:
         L.elas_get_timing.argtypes = [vp, C.POINTER(ElasTiming)]
         L.elas_set_batch_flags.argtypes = [vp, C.c_int32]
         L.elas_process_batch.argtypes = [vp, C.c_int32, C.POINTER(ElasPair), vp]
-        L.elas_get_tuned_variants.argtypes = [vp, C.c_int32, C.c_int32,
+        L.elas_get_tuned_variants.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
-        L.elas_set_tile_variants.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.elas_set_tile_variants.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                             C.c_int32]
         L.elas_frame_bytes.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
         L.elas_device_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
         L.elas_server_config_default.argtypes = [C.POINTER(ServerConfig)]
@@ -304,8 +305,10 @@ class Elas:
         _check(lib().elas_frame_bytes(self._h, w, h, C.byref(b)), self._h)
         return b.value
 
-    def set_tile_variants(self, w: int, h: int, desc_rows: int, dense_rows: int):
-        _check(lib().elas_set_tile_variants(self._h, w, h, desc_rows, dense_rows), self._h)
+    def set_tile_variants(self, w: int, h: int, desc_rows: int, dense_rows: int,
+                          support_run: int = 16):
+        _check(lib().elas_set_tile_variants(self._h, w, h, desc_rows, dense_rows, support_run),
+               self._h)
 
     def device_bytes(self) -> int:
         """Device bytes the handle holds (buffer sets of every size and stream)."""
@@ -314,9 +317,11 @@ class Elas:
         return b.value
 
     def tuned_variants(self, w: int, h: int):
-        r, b = C.c_int32(), C.c_int32()
-        _check(lib().elas_get_tuned_variants(self._h, w, h, C.byref(r), C.byref(b)), self._h)
-        return r.value, b.value
+        """(descriptor rows, dense rows, support run) chosen for (w, h)."""
+        r, b, q = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().elas_get_tuned_variants(self._h, w, h, C.byref(r), C.byref(b), C.byref(q)),
+               self._h)
+        return r.value, b.value, q.value
 
     def stats(self) -> dict:
         st = ElasStats()

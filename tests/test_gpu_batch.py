@@ -71,8 +71,9 @@ def test_batch_mixed_sizes_bit_exact(E, graph, autotune):
         for p, D in pairs:
             if D == 64:
                 h, w = p.left.shape
-                rows, batch = base.tuned_variants(w, h)
+                rows, batch, run = base.tuned_variants(w, h)
                 assert rows in (4, 8, 16) and batch in (1, 2, 4)  # dense rows per block
+                assert run in (16, 32)  # support lattice points per block
 
 
 def test_batch_graph_replay_with_new_inputs(E):
@@ -245,3 +246,26 @@ def test_batch_with_pairs_meshed_without_corners(E):
         t = ref.process(ref.params(disp_max=63, add_corners=ac), p.left, p.right)
         assert np.array_equal(oL.cpu().numpy(), t.outL), ac
         assert np.array_equal(oR.cpu().numpy(), t.outR), ac
+
+
+@pytest.mark.parametrize("run", [8, 16, 32])
+def test_support_run_lengths_bit_exact(E, run):
+    # the support stage's lattice points per workgroup, fixed per size: single
+    # calls and a batch give the oracle's maps with each
+    dev = torch.device("cuda:0")
+    pairs = make_mix(40)
+    hs = {D: E.Elas(disp_max=D - 1) for D in {64, 32, 128, 256}}
+    for p, D in pairs:
+        h, w = p.left.shape
+        hs[D].set_tile_variants(w, h, 8, 2, run)
+        assert hs[D].tuned_variants(w, h) == (8, 2, run)
+    got, _, _ = run_batch(E, pairs, True, False, handles=hs)
+    check(pairs, got)
+    p, D = pairs[5]
+    L = torch.from_numpy(p.left).to(dev)
+    R = torch.from_numpy(p.right).to(dev)
+    sL, sR = hs[D].process(L, R)
+    torch.cuda.synchronize()
+    t = ref.process(ref.params(disp_max=D - 1), p.left, p.right)
+    assert np.array_equal(sL.cpu().numpy(), t.outL)
+    assert np.array_equal(sR.cpu().numpy(), t.outR)

@@ -89,8 +89,9 @@ def test_batch_96_mixed_pairs_one_call(E):
     for nm in sorted(set(names)):
         c = synth.SHAPES[nm]
         if c.disp_range == 128:
-            rows, kb = base.tuned_variants(c.width, c.height)
+            rows, kb, run = base.tuned_variants(c.width, c.height)
             assert rows in (4, 8, 16) and kb in (1, 2, 4)  # dense rows per block
+            assert run in (16, 32)  # support lattice points per block
 
 
 def stage_mismatches(get, t):
