@@ -183,7 +183,7 @@ def workgroups(w: int, h: int, D: int, step: int = 5) -> dict:
     """Workgroups each stage launches for one frame (default tile variants)."""
     cd = lambda a, b: -(-a // b)
     lw, lh = (w - 5) // step, (h - 5) // step
-    return {"descriptor": 2 * cd(w, 128) * cd(h, 8), "support": lh * cd(lw, 16),
+    return {"descriptor": 2 * cd(w, 128) * cd(h, 8), "support": lh * cd(lw, 32 if D <= 192 else 16),
             "filter": (cd(lw, 8) * cd(lh, 8) if cd(lw, 8) * cd(lh, 8) <= 256
                        else cd(lw, 16) * cd(lh, 16)), "rows": lh, "mesh": 2,
             "raster": 2 * cd(h, max(1, min(4, 4096 // w))),
