@@ -1093,6 +1093,7 @@ namespace {
 // One launch of a batch: a stage (and tile variant) over a table of frames.
 struct LaunchRec {
   int32_t stage, variant, nf, total;
+  int32_t bpf;  // blocks of every frame when uniform, else 0
   size_t table_off, starts_off, lds;
 };
 
@@ -1146,6 +1147,7 @@ void plan_batch(const std::vector<Frame>& frames, const std::vector<std::pair<in
       r.variant = v;
       r.nf = (int32_t)sub.size();
       r.total = starts.back();
+      r.bpf = uniform_blocks(starts.data(), r.nf);
       r.lds = lds;
       r.table_off = tiled ? put(sub.data(), sub.size() * sizeof(Frame)) : main_table;
       r.starts_off = put(starts.data(), starts.size() * sizeof(int32_t));
@@ -1161,7 +1163,8 @@ hipError_t enqueue_batch(const std::vector<LaunchRec>& recs, uint8_t* dev, hipSt
     const LaunchRec& r = recs[i];
     const hipError_t e = launch_stage_batch(
         r.stage, reinterpret_cast<const Frame*>(dev + r.table_off),
-        reinterpret_cast<const int32_t*>(dev + r.starts_off), r.nf, r.total, r.lds, r.variant, s,
+        reinterpret_cast<const int32_t*>(dev + r.starts_off), r.nf, r.total, r.bpf, r.lds,
+        r.variant, s,
         ev ? ev[2 * i] : nullptr, ev ? ev[2 * i + 1] : nullptr);
     if (e != hipSuccess) return e;
   }
@@ -1212,7 +1215,9 @@ int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
         HIP_TRY(hipEventRecord(e0, stream));
         HIP_TRY(launch_stage_batch(stages[k], reinterpret_cast<const Frame*>(dev),
                                    reinterpret_cast<const int32_t*>(dev + soff),
-                                   (int32_t)fr.size(), starts.back(), lds, lv, stream));
+                                   (int32_t)fr.size(), starts.back(),
+                                   uniform_blocks(starts.data(), (int32_t)fr.size()), lds, lv,
+                                   stream));
         HIP_TRY(hipEventRecord(e1, stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -1358,6 +1363,7 @@ int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipSt
       sig.push_back(r.variant);
       sig.push_back(r.nf);
       sig.push_back(r.total);
+      sig.push_back(r.bpf);
       sig.push_back((int64_t)r.lds);
       sig.push_back((int64_t)r.table_off);
       sig.push_back((int64_t)r.starts_off);

@@ -28,10 +28,10 @@ struct Geometry {
   int32_t gw, gh;     // grid-vector regions
   int32_t gwords;     // 32-bit words per region mask (even: 64-bit aligned masks)
   int32_t ftile;      // support-filter tile side in lattice points (8 or 16)
-  int32_t srun;       // lattice points per support workgroup (8 or 16; fewer when
-                      // the staged columns would not fit in LDS)
+  int32_t srun;       // lattice points per support workgroup (8, 16 or 32; fewer
+                      // when the staged columns would not fit in LDS)
   uint64_t rowmul;    // ceil(2^40 / w): row of pixel index px = (px * rowmul) >> 40,
-                      // exact for px < 2^27
+                      // exact while px * w < 2^40 (px < 2^27, w <= 8192)
   uint32_t gdiv;      // ceil(2^31 / grid_size): x / grid_size = umulhi(2x, gdiv)
                       // exactly for 0 <= x < 2^31 / grid_size
 };
@@ -240,10 +240,17 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
 // One stage of nf frames in one launch: frames and starts (nf + 1 prefix of
 // the per-frame block counts) in device memory; lds: the largest per-frame
 // dynamic LDS. Start/stop events as in launch_stage.
+// bpf: the workgroups of every frame when all nf frames have that many (a
+// block's frame is then one multiply away), else 0 (the frame is searched in
+// starts).
 hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
-                              int32_t nf, int32_t total_blocks, size_t lds, int variant,
-                              hipStream_t s, hipEvent_t start = nullptr,
+                              int32_t nf, int32_t total_blocks, int32_t bpf, size_t lds,
+                              int variant, hipStream_t s, hipEvent_t start = nullptr,
                               hipEvent_t stop = nullptr);
+
+// Blocks per frame of a prefix table starts[0..nf] when every frame has the
+// same number, else 0.
+int32_t uniform_blocks(const int32_t* starts, int32_t nf);
 
 // The mesh stage (elas_mesh_device.hip): two workgroups per frame, for
 // frames with both sides at most kDeviceMeshMaxSide.

@@ -1419,9 +1419,10 @@ constexpr int kWinBatch = 5;   // window candidates per step of the general wind
 constexpr int kGridBatch = 2;  // grid candidates per step of the mask walk
 constexpr int kDenseStage = kDenseSeg + kMaxD - 1;
 // Prior table in LDS for the general paths, mirrored about its centre so
-// that a candidate's entry is one add away: s_lut[kLutC + k] = s_lut[kLutC -
-// k] = lut[k] (the prior of |d - dp| = k < D), then kMaxD zeros (pixels
-// without a plane).
+// that a candidate's entry is one add away, with the energy offset lut_bias
+// already added: s_lut[kLutC + k] = s_lut[kLutC - k] = lut[k] + lut_bias (the
+// prior of |d - dp| = k < D), then kMaxD entries lut_bias (pixels without a
+// plane).
 constexpr int kLutC = kMaxD - 1;
 constexpr int kLutZero = 2 * kLutC + 1;
 constexpr int kLutSize = kLutZero + kMaxD;
@@ -1429,6 +1430,9 @@ constexpr int kLutSize = kLutZero + kMaxD;
 __host__ __device__ __forceinline__ int dense_segments(const Geometry& g) {
   return cdivd(g.w, kDenseSeg);
 }
+
+__device__ __forceinline__ int ctz_any(uint32_t m) { return __builtin_ctz(m); }
+__device__ __forceinline__ int ctz_any(uint64_t m) { return __builtin_ctzll(m); }
 
 __device__ __forceinline__ uint32_t bits32_between(int a, int b) {
   a = max(a, 0);
@@ -1500,7 +1504,7 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
       }
 #pragma unroll
       for (int t = 0; t < kWinBatch; ++t) {
-        const uint32_t E = DD::cost(s, o[t], (uint32_t)(lv[t] + p.lut_bias));
+        const uint32_t E = DD::cost(s, o[t], (uint32_t)lv[t]);
         best = min(best, (E << 8) | (uint32_t)dd[t]);
       }
     }
@@ -1521,28 +1525,38 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
     const int a = max(wlo - gmin, 0), b = min(whi - gmin, 63);  // the window's bits
     if (a <= b) m &= ~((b == 63 ? ~0ull : ((2ull << b) - 1ull)) & ~((1ull << a) - 1ull));
     n += __popcll(m);
-    while (m) {
-      int dd[kGridBatch];
-      dd[0] = gmin + __builtin_ctzll(m);
-      m &= m - 1ull;
+    // the bits come two at a time; when no lane of the wavefront that walks
+    // its bits has one past bit 31 (most of them: a region's support
+    // disparities lie close together), from a 32-bit mask, whose lowest bit
+    // costs one instruction instead of four
+    auto walk = [&](auto mask) {
+      while (mask) {
+        int dd[kGridBatch];
+        dd[0] = gmin + ctz_any(mask);
+        mask &= mask - 1u;
 #pragma unroll
-      for (int t = 1; t < kGridBatch; ++t) {
-        dd[t] = m ? gmin + __builtin_ctzll(m) : dd[0];
-        m &= m - 1ull;
-      }
-      typename DD::T o[kGridBatch];
-      int lv[kGridBatch];
+        for (int t = 1; t < kGridBatch; ++t) {
+          dd[t] = mask ? gmin + ctz_any(mask) : dd[0];
+          mask &= mask - 1u;
+        }
+        typename DD::T o[kGridBatch];
+        int lv[kGridBatch];
 #pragma unroll
-      for (int t = 0; t < kGridBatch; ++t) {
-        o[t] = st[slot0 + dir * dd[t]];
-        lv[t] = s_lut[dd[t] + lidx];
-      }
+        for (int t = 0; t < kGridBatch; ++t) {
+          o[t] = st[slot0 + dir * dd[t]];
+          lv[t] = s_lut[dd[t] + lidx];
+        }
 #pragma unroll
-      for (int t = 0; t < kGridBatch; ++t) {
-        const uint32_t E = DD::cost(s, o[t], (uint32_t)(lv[t] + p.lut_bias));
-        best = min(best, (E << 8) | (uint32_t)dd[t]);
+        for (int t = 0; t < kGridBatch; ++t) {
+          const uint32_t E = DD::cost(s, o[t], (uint32_t)lv[t]);
+          best = min(best, (E << 8) | (uint32_t)dd[t]);
+        }
       }
-    }
+    };
+    if (__all((uint32_t)(m >> 32) == 0u))
+      walk((uint32_t)m);
+    else
+      walk(m);
   } else if (p.full_search || (has_list && gmax >= 0 && !inside && gmin <= ghi)) {
     const int nw = (top >> 5) + 1;  // 32-bit words in play
     // every word in play is loaded at once (one memory round trip)
@@ -1575,7 +1589,7 @@ __device__ __forceinline__ int dense_pixel(const Geometry& g, const KParams& p, 
         }
 #pragma unroll
         for (int t = 0; t < kGridBatch; ++t) {
-          const uint32_t E = DD::cost(s, o[t], (uint32_t)(lv[t] + p.lut_bias));
+          const uint32_t E = DD::cost(s, o[t], (uint32_t)lv[t]);
           best = min(best, (E << 8) | (uint32_t)dd[t]);
         }
       }
@@ -1651,7 +1665,7 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
   for (int q = 0; q < 3; ++q) {
     const int i = (int)threadIdx.x + 256 * q;
     const int32_t x = lut[min(abs(i - kLutC), p.D - 1)];
-    lv[q] = i <= 2 * kLutC ? x : 0;
+    lv[q] = (i <= 2 * kLutC ? x : 0) + p.lut_bias;
   }
   WinPrior wp;
   wp.p0 = (uint32_t)(lut[0] + p.lut_bias);
@@ -1864,16 +1878,27 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
 
 // ---- kernels: one frame, or a batch in one launch --------------------------
 // ATTR: extra kernel attributes (an occupancy target where measured faster).
+// A batch launch finds a block's frame as floor(b / bpf) = umulhi(b, bmul)
+// when every frame has bpf blocks (bmul = ceil(2^32 / bpf), exact for
+// b * bpf < 2^32, which the launcher checks), else by binary search.
 #define ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ATTR)                              \
   __global__ __launch_bounds__(THREADS) ATTR void NAME(Frame F) {                       \
     BODY(F, xcd_remap(blockIdx.x, gridDim.x));                                          \
   }                                                                                     \
   __global__ __launch_bounds__(THREADS) ATTR void NAME##_batch(                         \
-      const Frame* __restrict__ frames, const int32_t* __restrict__ starts, int nf) {   \
+      const Frame* __restrict__ frames, const int32_t* __restrict__ starts, int nf,      \
+      int bpf, uint32_t bmul) {                                                          \
     const int b = xcd_remap(blockIdx.x, gridDim.x);                                     \
-    const int f = frame_of(starts, nf, b);                                              \
+    int f, lb;                                                                           \
+    if (bpf > 0) {                                                                       \
+      f = (int)__umulhi((uint32_t)b, bmul);                                              \
+      lb = b - f * bpf;                                                                  \
+    } else {                                                                             \
+      f = frame_of(starts, nf, b);                                                       \
+      lb = b - starts[f];                                                                \
+    }                                                                                    \
     const Frame F = global_frame(frames[f], reinterpret_cast<const char*>(frames));     \
-    BODY(F, b - starts[f]);                                                             \
+    BODY(F, lb);                                                                         \
   }
 #define ELAS_NO_ATTR
 #define ELAS_STAGE_KERNELS(NAME, BODY, THREADS) \
@@ -2011,19 +2036,34 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
   return hipGetLastError();
 }
 
+int32_t uniform_blocks(const int32_t* starts, int32_t nf) {
+  if (nf <= 0) return 0;
+  const int32_t d = starts[1] - starts[0];
+  for (int32_t i = 1; i < nf; ++i)
+    if (starts[i + 1] - starts[i] != d) return 0;
+  return d;
+}
+
 hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
-                              int32_t nf, int32_t total_blocks, size_t lds, int variant,
-                              hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+                              int32_t nf, int32_t total_blocks, int32_t bpf, size_t lds,
+                              int variant, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   if (stage == kStageMesh) return launch_mesh_batch(frames, nf, s, start, stop);
   if (total_blocks <= 0 || nf <= 0) return hipSuccess;
+  // the multiply path needs bpf >= 2 (bmul < 2^32), bpf * nf == total and
+  // b * bpf < 2^32 for every block b
+  if (bpf < 2 || (int64_t)bpf * nf != total_blocks ||
+      (uint64_t)total_blocks * (uint64_t)bpf >= (1ull << 32))
+    bpf = 0;
+  const uint32_t bmul = bpf ? (uint32_t)(((1ull << 32) + (uint64_t)bpf - 1) / (uint64_t)bpf) : 0u;
   const dim3 grid(total_blocks), block(stage_threads(stage));
   const uint32_t shm = (uint32_t)lds;
   const bool timed = start || stop;
   auto go = [&](auto kernel, uint32_t bytes) {
     if (timed)
-      hipExtLaunchKernelGGL(kernel, grid, block, bytes, s, start, stop, 0u, frames, starts, nf);
+      hipExtLaunchKernelGGL(kernel, grid, block, bytes, s, start, stop, 0u, frames, starts, nf,
+                            bpf, bmul);
     else
-      hipLaunchKernelGGL(kernel, grid, block, bytes, s, frames, starts, nf);
+      hipLaunchKernelGGL(kernel, grid, block, bytes, s, frames, starts, nf, bpf, bmul);
   };
   switch (stage) {
     case kStageDescriptor:

@@ -76,6 +76,26 @@ def test_batch_mixed_sizes_bit_exact(E, graph, autotune):
                 assert run in (16, 32)  # support lattice points per block
 
 
+def test_uniform_and_mixed_batches_alternate_on_one_handle(E):
+    # equal frames find a block's frame by a multiply, mixed ones by search;
+    # each batch shape keeps its own captured graph, replayed in turn
+    uni = []
+    for i in range(4):
+        cfg = synth.SceneConfig(320, 240, 64, 4, 0.05, 4.0, 59.0, 2.0, 0.1, seed=40 + i)
+        uni.append((synth.make_pair(cfg), 64))
+    mix = make_mix(seed_shift=20)
+    want = {}
+    for name, pairs in (("uni", uni), ("mix", mix)):
+        want[name] = [ref.process(ref.params(disp_max=D - 1), p.left, p.right) for p, D in pairs]
+    handles = {D: E.Elas(disp_max=D - 1) for D in {64, 32, 128, 256}}
+    for rep in range(2):
+        for name, pairs in (("uni", uni), ("mix", mix)):
+            got, _, _ = run_batch(E, pairs, True, False, handles=handles)
+            for (p, D), t, (oL, oR) in zip(pairs, want[name], got):
+                assert np.array_equal(oL, t.outL), (name, rep, p.left.shape, D)
+                assert np.array_equal(oR, t.outR), (name, rep, p.left.shape, D)
+
+
 def test_batch_graph_replay_with_new_inputs(E):
     # the same batch shape replays its captured graph; the frame table is
     # uploaded per call, so new images and outputs are picked up
