@@ -368,9 +368,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
-    ap.add_argument("--streams", type=int, default=3,
+    ap.add_argument("--streams", type=int, default=2,
                     help="steps are issued round-robin on this many streams")
-    ap.add_argument("--batch", type=int, default=8,
+    ap.add_argument("--batch", type=int, default=32,
                     help="pairs per step (one batched call); 1: one plain call per step")
     ap.add_argument("--hw-queues", type=int, default=4,
                     help="hardware queues of this process (GPU_MAX_HW_QUEUES, read when HIP "
