@@ -13,8 +13,8 @@ for --hw-queues hardware queues. With --batch 1 a step is one elas_process
 call on one pair. Prints one JSON line.
 
 value           frames/s over the timed steps (inputs already in HBM)
-fps_plain_calls one elas_process call per pair (pair seed), round-robin on the
-                same streams
+fps_plain_calls one elas_process call per pair (pair seed), round-robin on
+                --plain-streams streams
 fps_one_stream  the same plain calls on a single stream (one frame at a time)
 roofline        the kernel with the largest share of chip time in a step
                 (duration x the fraction of the 256 CUs it occupies; the mesh
@@ -31,7 +31,7 @@ serve           16 camera streams with Poisson arrivals at the six swept
 variants        frames/s of the same pair under the embedded variant and the
                 optional steps (census descriptors, eq. 3, past-only redundancy,
                 support down-sampling, median filter), each bit-exact to the
-                oracle in the test-suite
+                oracle in the test-suite (plain calls on --plain-streams streams)
 cpu_baseline    the CPU oracle (single-threaded C) on a bounded sample of the
                 same workload, on this host; per stage, the median of 5 runs at
                 320x240, 640x480 and 1242x375; the CPU model and core count
@@ -372,6 +372,9 @@ def main():
                     help="steps are issued round-robin on this many streams")
     ap.add_argument("--batch", type=int, default=32,
                     help="pairs per step (one batched call); 1: one plain call per step")
+    ap.add_argument("--plain-streams", type=int, default=3,
+                    help="streams of the plain-call and variant rates (one elas_process "
+                         "call per pair)")
     ap.add_argument("--hw-queues", type=int, default=4,
                     help="hardware queues of this process (GPU_MAX_HW_QUEUES, read when HIP "
                          "starts; 4 is HIP's default); 0 keeps the environment's value")
@@ -441,10 +444,12 @@ def main():
         imgs.append((torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev)))
     L, R = imgs[0]
     K = max(1, args.streams)
-    streams = [torch.cuda.Stream(device=dev) for _ in range(K)]  # default priority
+    KP = max(1, args.plain_streams)
+    NS = max(K, KP)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(NS)]  # default priority
     outs = [[(torch.empty((H, W), dtype=torch.int16, device=dev),
               torch.empty((H, W), dtype=torch.int16, device=dev)) for _ in range(B)]
-            for _ in range(K)]
+            for _ in range(NS)]
     items = [[(imgs[i][0], imgs[i][1], outs[k][i][0], outs[k][i][1]) for i in range(B)]
              for k in range(K)]
     e = Elas(disp_max=D - 1, mesh_on_host=int(args.mesh_on_host))
@@ -475,7 +480,7 @@ def main():
     dt = rate(run, args.steps, K, args.warmup)
     fps = args.steps * B / dt
     plain_steps = args.steps * B
-    fps_plain = plain_steps / rate(run_plain, plain_steps, K, args.warmup)
+    fps_plain = plain_steps / rate(run_plain, plain_steps, KP, args.warmup)
     fps_one = plain_steps / rate(run_plain, plain_steps, 1, args.warmup)
     # statistics of the pairs of a step (plain calls), summed over the pairs
     st = {}
@@ -553,6 +558,7 @@ def main():
                                f"pair i from seed + i",
                    "width": W, "height": H, "disp_range": D, "pairs_per_step": B,
                    "seed": args.seed, "streams": K, "frames_in_flight": K * B,
+                   "plain_call_streams": KP,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")) or None,
                    "mesh": "host" if args.mesh_on_host else "device"},
         "evals_per_frame": evals,
@@ -565,7 +571,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_variants:
-        out["variants"] = variant_fps(torch, Elas, L, R, D, min(args.steps, 200), streams)
+        out["variants"] = variant_fps(torch, Elas, L, R, D, min(args.steps, 200), streams[:KP])
     if not args.no_batch:
         out["batch"] = batch_c4(torch, Elas)
     if not args.no_serve:
