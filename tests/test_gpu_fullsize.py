@@ -5,7 +5,7 @@
   SplitMix64 stream seeded 0) in ONE batched call with graph capture and
   autotuning on, then again with the tuned tile variants from the captured
   graph; every map of every pair equals the oracle's;
-* the benchmark's timed step exactly (8 pairs 640x480 D=128, seeds 0..7, one
+* the benchmark's timed step exactly (32 pairs 640x480 D=128, seeds 0..31, one
   batched call with the default batch tile variants on a non-default
   stream), compared stage by stage: descriptors, the four lattice stages,
   lists, corners, triangles, planes, owners, prior maps, grid vectors, raw
@@ -137,7 +137,7 @@ def stage_mismatches(get, t):
 
 
 def test_bench_step_stage_by_stage(E):
-    cfgs = [synth.VGA.with_seed(i) for i in range(8)]
+    cfgs = [synth.VGA.with_seed(i) for i in range(32)]
     pairs = pmap(synth.make_pair, cfgs)
     dev = torch.device("cuda:0")
     e = E.Elas(disp_max=127)
@@ -162,7 +162,7 @@ def test_bench_step_stage_by_stage(E):
             assert np.array_equal(oL.cpu().numpy(), t.outL), (rep, i)
             assert np.array_equal(oR.cpu().numpy(), t.outR), (rep, i)
             assert (t.outL >= 0).mean() > 0.4
-        print(f"bench step call {rep}: 8 pairs, every stage equal", flush=True)
+        print(f"bench step call {rep}: {len(pairs)} pairs, every stage equal", flush=True)
 
 
 def test_server_full_shapes_16_cameras(E):
