@@ -10,6 +10,8 @@
   stream), compared stage by stage: descriptors, the four lattice stages,
   lists, corners, triangles, planes, owners, prior maps, grid vectors, raw
   and final maps;
+* uniform batches of four pairs at 1242x375 D=256 and 1280x720 D=192,
+  stage by stage;
 * a server fed by 16 cameras of the four full shapes (camera j at shape
   j mod 4), pairs arriving while others run; every result equals the
   oracle's.
@@ -163,6 +165,39 @@ def test_bench_step_stage_by_stage(E):
             assert np.array_equal(oR.cpu().numpy(), t.outR), (rep, i)
             assert (t.outL >= 0).mean() > 0.4
         print(f"bench step call {rep}: {len(pairs)} pairs, every stage equal", flush=True)
+
+
+@pytest.mark.parametrize("shape", ["1242x375", "1280x720"])
+def test_uniform_batches_of_the_larger_shapes(E, shape):
+    # four pairs of one shape: every frame of a launch has the same block
+    # count, so blocks find their frame by a multiply (the mixed batch above
+    # takes the search); the support runs are 16 points at D = 256 and 32 at
+    # D = 192
+    cfg = synth.SHAPES[shape]
+    D = cfg.disp_range
+    pairs = pmap(synth.make_pair, [cfg.with_seed(500 + i) for i in range(4)])
+    dev = torch.device("cuda:0")
+    e = E.Elas(disp_max=D - 1)
+    e.set_batch_flags(graph=True, autotune=False)
+    items, outs = [], []
+    for p in pairs:
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        oL = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        oR = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        items.append((L, R, oL, oR))
+        outs.append((oL, oR))
+    torch.cuda.synchronize()
+    traces = pmap(lambda p: ref.process(ref.params(disp_max=D - 1), p.left, p.right), pairs)
+    for rep in range(2):   # capture, then replay
+        e.process_batch(items)
+        torch.cuda.synchronize()
+        for i, (t, (oL, oR)) in enumerate(zip(traces, outs)):
+            bad = stage_mismatches(lambda nm, i=i: e.batch_intermediate(i, nm), t)
+            assert bad == [], f"{shape} call {rep}, pair {i}: {bad}"
+            assert np.array_equal(oL.cpu().numpy(), t.outL), (shape, rep, i)
+            assert np.array_equal(oR.cpu().numpy(), t.outR), (shape, rep, i)
+        print(f"{shape}: 4 pairs, call {rep}, every stage equal", flush=True)
 
 
 def test_server_full_shapes_16_cameras(E):
