@@ -145,6 +145,28 @@ def test_batch_equals_single_calls(E):
         assert np.array_equal(sR.cpu().numpy(), oR)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_of_one_pair(E, graph):
+    # one frame: its block count is the whole grid, and every block finds
+    # frame 0 by the multiply
+    for (w, h, D, seed) in [(320, 240, 64, 3), (97, 61, 64, 6), (256, 96, 256, 5)]:
+        cfg = synth.SceneConfig(w, h, D, 4, 0.05, 4.0, max(5.0, D - 5.0), 2.0, 0.1, seed=seed)
+        pairs = [(synth.make_pair(cfg), D)]
+        got, _, _ = run_batch(E, pairs, graph, False, reps=2)
+        check(pairs, got)
+
+
+def test_batch_of_many_equal_small_pairs(E):
+    # 48 frames of one shape in one call: the frame of a block by the
+    # multiply, across many frame boundaries
+    pairs = []
+    for i in range(48):
+        cfg = synth.SceneConfig(97, 61, 64, 4, 0.05, 4.0, 59.0, 2.0, 0.1, seed=200 + i)
+        pairs.append((synth.make_pair(cfg), 64))
+    got, _, _ = run_batch(E, pairs, True, False, reps=2)
+    check(pairs, got)
+
+
 def test_batch_with_host_mesh_pairs(E):
     # a pair wider than the device mesh limit goes through the host mesh path
     dev = torch.device("cuda:0")
