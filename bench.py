@@ -535,8 +535,10 @@ def main():
     stage_ms = {s: float(np.mean(v)) if v else float("nan") for s, v in acc.items()}
     kernel_ms = {s: stage_ms[s] for s in KERNEL_NAMES}
     names = dict(KERNEL_NAMES)
-    if B > 1:  # the batched kernels (their untuned tile variants; the raster's 256 threads)
-        names = {s: {"raster": "k_raster256", "descriptor": "k_descriptor16"}.get(s, n) + "_batch"
+    if B > 1:  # the batched kernels (their untuned tile variants; the raster's 256 threads;
+        # descriptors with non-temporal stores once a batch's reach 192 MiB)
+        desc = "k_descriptor16nt" if B * 32 * W * H >= (192 << 20) else "k_descriptor16"
+        names = {s: {"raster": "k_raster256", "descriptor": desc}.get(s, n) + "_batch"
                  for s, n in names.items()}
     # share of chip time: duration x the fraction of the 256 CUs the kernel's
     # workgroups can occupy (launch geometry of each stage at this size)

@@ -1093,7 +1093,8 @@ namespace {
 // One launch of a batch: a stage (and tile variant) over a table of frames.
 struct LaunchRec {
   int32_t stage, variant, nf, total;
-  int32_t bpf;  // blocks of every frame when uniform, else 0
+  int32_t bpf;   // blocks of every frame when uniform, else 0
+  bool desc_nt;  // descriptor stage: non-temporal stores
   size_t table_off, starts_off, lds;
 };
 
@@ -1114,11 +1115,25 @@ int batch_ctx(elas_handle* h, hipStream_t stream, BatchCtx** out) {
   return ELAS_OK;
 }
 
+// A batch whose Sobel descriptors (32 bytes per pixel for the two views)
+// reach this size writes them with non-temporal stores: beyond about three
+// quarters of the 256 MB last-level (Infinity) cache, the dirty lines that
+// ordinary stores leave are written back while the support and dense stages
+// read, and those stages run slower than with descriptors that went straight
+// to HBM (measured at 640x480 D=128: 24 and 32 pairs per call, and 1280x720
+// with 8, faster with non-temporal stores; 8 pairs at 640x480, 79 MB,
+// faster with ordinary ones; 16 pairs, 157 MB, even).
+constexpr uint64_t kDescNtBytes = 192ull << 20;
+
 // Frame tables and block prefixes of every launch, in one blob.
 void plan_batch(const std::vector<Frame>& frames, const std::vector<std::pair<int, int>>& var,
                 std::vector<LaunchRec>* recs, std::vector<uint8_t>* blob) {
   recs->clear();
   blob->clear();
+  uint64_t desc_bytes = 0;
+  for (const Frame& f : frames)
+    if (f.p.descriptor == 0) desc_bytes += 32ull * (uint64_t)f.g.w * (uint64_t)f.g.h;
+  const bool desc_nt = desc_bytes >= kDescNtBytes;
   auto put = [&](const void* p, size_t bytes) {
     const size_t off = blob->size();
     blob->resize(align256(off + bytes));
@@ -1148,6 +1163,7 @@ void plan_batch(const std::vector<Frame>& frames, const std::vector<std::pair<in
       r.nf = (int32_t)sub.size();
       r.total = starts.back();
       r.bpf = uniform_blocks(starts.data(), r.nf);
+      r.desc_nt = st == kStageDescriptor && desc_nt;
       r.lds = lds;
       r.table_off = tiled ? put(sub.data(), sub.size() * sizeof(Frame)) : main_table;
       r.starts_off = put(starts.data(), starts.size() * sizeof(int32_t));
@@ -1164,7 +1180,7 @@ hipError_t enqueue_batch(const std::vector<LaunchRec>& recs, uint8_t* dev, hipSt
     const hipError_t e = launch_stage_batch(
         r.stage, reinterpret_cast<const Frame*>(dev + r.table_off),
         reinterpret_cast<const int32_t*>(dev + r.starts_off), r.nf, r.total, r.bpf, r.lds,
-        r.variant, s,
+        r.variant, r.desc_nt, s,
         ev ? ev[2 * i] : nullptr, ev ? ev[2 * i + 1] : nullptr);
     if (e != hipSuccess) return e;
   }
@@ -1217,7 +1233,7 @@ int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
                                    reinterpret_cast<const int32_t*>(dev + soff),
                                    (int32_t)fr.size(), starts.back(),
                                    uniform_blocks(starts.data(), (int32_t)fr.size()), lds, lv,
-                                   stream));
+                                   false, stream));
         HIP_TRY(hipEventRecord(e1, stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -1364,6 +1380,7 @@ int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipSt
       sig.push_back(r.nf);
       sig.push_back(r.total);
       sig.push_back(r.bpf);
+      sig.push_back(r.desc_nt ? 1 : 0);
       sig.push_back((int64_t)r.lds);
       sig.push_back((int64_t)r.table_off);
       sig.push_back((int64_t)r.starts_off);

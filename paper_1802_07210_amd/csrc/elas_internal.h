@@ -243,10 +243,12 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
 // bpf: the workgroups of every frame when all nf frames have that many (a
 // block's frame is then one multiply away), else 0 (the frame is searched in
 // starts).
+// desc_nt: the descriptor stage writes the Sobel descriptors with
+// non-temporal stores (separate kernels).
 hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
                               int32_t nf, int32_t total_blocks, int32_t bpf, size_t lds,
-                              int variant, hipStream_t s, hipEvent_t start = nullptr,
-                              hipEvent_t stop = nullptr);
+                              int variant, bool desc_nt, hipStream_t s,
+                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 
 // Blocks per frame of a prefix table starts[0..nf] when every frame has the
 // same number, else 0.

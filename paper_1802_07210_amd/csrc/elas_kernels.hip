@@ -134,7 +134,10 @@ __host__ __device__ constexpr uint32_t perm_sel(int b0, int b1, int b2, int b3) 
 }
 constexpr int kZ = 0x0C;  // v_perm: a zero byte
 
-template <int TH>
+// NT: the descriptors leave with non-temporal stores (a template argument:
+// a runtime choice between two stores of the same value to the same address
+// is merged into one ordinary store by the compiler).
+template <int TH, bool NT>
 __device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
   const Geometry g = F.g;
   const int nbx = cdivd(g.w, kDescW);
@@ -257,9 +260,18 @@ __device__ __forceinline__ void descriptor_body(const Frame& F, int lb) {
     for (int i = 0; i < kOutRows * kDescW / 256; ++i) {
       const int q = tid + 256 * i, rr = q / kDescW, col = q & (kDescW - 1);
       const int v = v0 + pass + rr, u = u0 + col;
-      if (pass + rr < TH && v < g.h && u < g.w)
-        *reinterpret_cast<uint4*>(desc + ((size_t)v * g.w + u) * 16) =
-            obuf[rr][(col & ~3) | ((col & 3) ^ ((col >> 4) & 3))];
+      if (pass + rr < TH && v < g.h && u < g.w) {
+        const uint4 o = obuf[rr][(col & ~3) | ((col & 3) ^ ((col >> 4) & 3))];
+        uint4* dst = reinterpret_cast<uint4*>(desc + ((size_t)v * g.w + u) * 16);
+        if constexpr (NT) {  // straight to HBM, leaving no dirty lines in the caches
+          __builtin_nontemporal_store(o.x, &dst->x);
+          __builtin_nontemporal_store(o.y, &dst->y);
+          __builtin_nontemporal_store(o.z, &dst->z);
+          __builtin_nontemporal_store(o.w, &dst->w);
+        } else {
+          *dst = o;
+        }
+      }
     }
     __syncthreads();
   }
@@ -353,12 +365,16 @@ __device__ __forceinline__ void census_body(const Frame& F, int lb) {
   }
 }
 
-template <int TH>
+template <int TH, bool NT = false>
 __device__ __forceinline__ void stage1_body(const Frame& F, int lb) {
   if (F.p.descriptor)
     census_body<TH>(F, lb);
   else
-    descriptor_body<TH>(F, lb);
+    descriptor_body<TH, NT>(F, lb);
+}
+template <int TH>
+__device__ __forceinline__ void stage1_nt_body(const Frame& F, int lb) {
+  stage1_body<TH, true>(F, lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1911,6 +1927,9 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
 ELAS_STAGE_KERNELS(k_descriptor4, stage1_body<4>, 256)
 ELAS_STAGE_KERNELS(k_descriptor8, stage1_body<8>, 256)
 ELAS_STAGE_KERNELS(k_descriptor16, stage1_body<16>, 256)
+ELAS_STAGE_KERNELS(k_descriptor4nt, stage1_nt_body<4>, 256)
+ELAS_STAGE_KERNELS(k_descriptor8nt, stage1_nt_body<8>, 256)
+ELAS_STAGE_KERNELS(k_descriptor16nt, stage1_nt_body<16>, 256)
 ELAS_STAGE_KERNELS(k_support, support_body, 256)
 ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
 ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
@@ -2046,7 +2065,8 @@ int32_t uniform_blocks(const int32_t* starts, int32_t nf) {
 
 hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
                               int32_t nf, int32_t total_blocks, int32_t bpf, size_t lds,
-                              int variant, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+                              int variant, bool desc_nt, hipStream_t s, hipEvent_t start,
+                              hipEvent_t stop) {
   if (stage == kStageMesh) return launch_mesh_batch(frames, nf, s, start, stop);
   if (total_blocks <= 0 || nf <= 0) return hipSuccess;
   // the multiply path needs bpf >= 2 (bmul < 2^32), bpf * nf == total and
@@ -2068,11 +2088,11 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
   switch (stage) {
     case kStageDescriptor:
       if (variant == 1)
-        go(k_descriptor8_batch, 0u);
+        desc_nt ? go(k_descriptor8nt_batch, 0u) : go(k_descriptor8_batch, 0u);
       else if (variant == 2)
-        go(k_descriptor16_batch, 0u);
+        desc_nt ? go(k_descriptor16nt_batch, 0u) : go(k_descriptor16_batch, 0u);
       else
-        go(k_descriptor4_batch, 0u);
+        desc_nt ? go(k_descriptor4nt_batch, 0u) : go(k_descriptor4_batch, 0u);
       break;
     case kStageSupport: go(k_support_batch, shm); break;
     case kStageFilter: go(k_filter_batch, shm); break;
