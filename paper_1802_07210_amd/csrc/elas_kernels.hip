@@ -1358,7 +1358,9 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
         const float f = floorf(__fadd_rn(mu, 0.5f));
         dp = f < (float)dmin ? dmin : (f > (float)dmax ? dmax : (int)f);
       }
-      owner[i] = o[k];
+      // the owner map is read by no later stage: it goes straight to HBM
+      // (non-temporal), leaving the caches to the prior and the descriptors
+      __builtin_nontemporal_store(o[k], &owner[i]);
       dpl[i] = (int16_t)dp;
     }
   }
@@ -1763,10 +1765,14 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
 // ---------------------------------------------------------------------------
 constexpr int kCheckPx = 4;  // pixels per thread (fewer, longer waves)
 
-__device__ __forceinline__ void check_body(const Frame& F, int lb) {
+// MED: the checked maps go to the median stage's inputs (ordinary stores,
+// read back next); otherwise they are the outputs, which no later stage
+// reads, and leave with non-temporal stores.
+template <bool MED>
+__device__ __forceinline__ void check_rows(const Frame& F, int lb) {
   const Geometry g = F.g;
   const int thr = F.p.lr_threshold;
-  const bool med = F.p.median != 0;
+  constexpr bool med = MED;
   const int16_t* rawL = F.rawL;
   const int16_t* rawR = F.rawR;
   int16_t* outL = F.outL;
@@ -1802,8 +1808,22 @@ __device__ __forceinline__ void check_body(const Frame& F, int lb) {
     if (px >= npx) break;
     const int lo = max(0, d[k] - t);
     const bool ok = d[k] >= 0 && (uint32_t)(e[k] - lo) <= (uint32_t)(d[k] + t - lo);
-    dst[px] = (int16_t)(ok ? d[k] : -1);
+    const int16_t res = (int16_t)(ok ? d[k] : -1);
+    if constexpr (MED)
+      dst[px] = res;
+    else
+      __builtin_nontemporal_store(res, &dst[px]);
   }
+  // keeps the two instantiations' last stores apart (the compiler would
+  // otherwise sink them into one ordinary store)
+  if constexpr (!MED) asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ void check_body(const Frame& F, int lb) {
+  if (F.p.median)
+    check_rows<true>(F, lb);
+  else
+    check_rows<false>(F, lb);
 }
 
 // ---------------------------------------------------------------------------
