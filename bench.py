@@ -536,9 +536,10 @@ def main():
     kernel_ms = {s: stage_ms[s] for s in KERNEL_NAMES}
     names = dict(KERNEL_NAMES)
     if B > 1:  # the batched kernels (their untuned tile variants; the raster's 256 threads;
-        # descriptors with non-temporal stores once a batch's reach 192 MiB)
-        desc = "k_descriptor16nt" if B * 32 * W * H >= (192 << 20) else "k_descriptor16"
-        names = {s: {"raster": "k_raster256", "descriptor": desc}.get(s, n) + "_batch"
+        # descriptors by non-temporal stores and loads once a batch's reach 192 MiB)
+        nt = "nt" if B * 32 * W * H >= (192 << 20) else ""
+        names = {s: {"raster": "k_raster256", "descriptor": "k_descriptor16" + nt,
+                     "dense": "k_dense_r2" + nt}.get(s, n) + "_batch"
                  for s, n in names.items()}
     # share of chip time: duration x the fraction of the 256 CUs the kernel's
     # workgroups can occupy (launch geometry of each stage at this size)

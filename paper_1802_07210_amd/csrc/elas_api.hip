@@ -1094,7 +1094,7 @@ namespace {
 struct LaunchRec {
   int32_t stage, variant, nf, total;
   int32_t bpf;   // blocks of every frame when uniform, else 0
-  bool desc_nt;  // descriptor stage: non-temporal stores
+  bool desc_nt;  // descriptor and dense stages: descriptors by non-temporal stores and loads
   size_t table_off, starts_off, lds;
 };
 
@@ -1116,13 +1116,15 @@ int batch_ctx(elas_handle* h, hipStream_t stream, BatchCtx** out) {
 }
 
 // A batch whose Sobel descriptors (32 bytes per pixel for the two views)
-// reach this size writes them with non-temporal stores: beyond about three
-// quarters of the 256 MB last-level (Infinity) cache, the dirty lines that
-// ordinary stores leave are written back while the support and dense stages
-// read, and those stages run slower than with descriptors that went straight
-// to HBM (measured at 640x480 D=128: 24 and 32 pairs per call, and 1280x720
-// with 8, faster with non-temporal stores; 8 pairs at 640x480, 79 MB,
-// faster with ordinary ones; 16 pairs, 157 MB, even).
+// reach this size writes them with non-temporal stores, and the dense stage
+// (their last reader) reads them, and the prior map, with non-temporal
+// loads: beyond about three quarters of the 256 MB last-level (Infinity)
+// cache, the dirty lines that ordinary stores leave are written back while
+// the support and dense stages read, and lines the dense stage leaves cached
+// slow the next batch's non-temporal writes to the same (reused) buffers
+// (measured at 640x480 D=128: 24 and 32 pairs per call, and 1280x720 with
+// 8, faster both ways; 8 pairs at 640x480, 79 MB, faster with ordinary
+// stores and loads; 16 pairs, 157 MB, even).
 constexpr uint64_t kDescNtBytes = 192ull << 20;
 
 // Frame tables and block prefixes of every launch, in one blob.
@@ -1163,7 +1165,7 @@ void plan_batch(const std::vector<Frame>& frames, const std::vector<std::pair<in
       r.nf = (int32_t)sub.size();
       r.total = starts.back();
       r.bpf = uniform_blocks(starts.data(), r.nf);
-      r.desc_nt = st == kStageDescriptor && desc_nt;
+      r.desc_nt = (st == kStageDescriptor || st == kStageDense) && desc_nt;
       r.lds = lds;
       r.table_off = tiled ? put(sub.data(), sub.size() * sizeof(Frame)) : main_table;
       r.starts_off = put(starts.data(), starts.size() * sizeof(int32_t));

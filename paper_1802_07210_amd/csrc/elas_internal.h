@@ -244,7 +244,8 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
 // block's frame is then one multiply away), else 0 (the frame is searched in
 // starts).
 // desc_nt: the descriptor stage writes the Sobel descriptors with
-// non-temporal stores (separate kernels).
+// non-temporal stores and the dense stage reads them (and the prior map)
+// with non-temporal loads (separate kernels).
 hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t* starts,
                               int32_t nf, int32_t total_blocks, int32_t bpf, size_t lds,
                               int variant, bool desc_nt, hipStream_t s,

@@ -1399,9 +1399,17 @@ struct GradDense {
   __device__ __forceinline__ static T load(const uint8_t* base, size_t px) {
     return ld16(base + px * 16);
   }
-  // column c of a row whose first descriptor is at row (a wavefront-uniform base)
+  // column c of a row whose first descriptor is at row (a wavefront-uniform
+  // base); NT: a non-temporal load (the line is not kept in the caches)
+  template <bool NT = false>
   __device__ __forceinline__ static T load_col(const uint8_t* row, uint32_t c) {
-    return ld16(row + c * 16u);
+    if constexpr (NT) {
+      typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+      const v4u x = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(row + c * 16u));
+      return make_uint4(x.x, x.y, x.z, x.w);
+    } else {
+      return ld16(row + c * 16u);
+    }
   }
   __device__ __forceinline__ static uint32_t cost(const T a, const T b, uint32_t acc) {
     uint32_t s = __builtin_amdgcn_sad_u8(a.x, b.x, acc);
@@ -1418,8 +1426,13 @@ struct CensusDense {
   __device__ __forceinline__ static T load(const uint8_t* base, size_t px) {
     return reinterpret_cast<const uint64_t*>(base)[px];
   }
+  template <bool NT = false>
   __device__ __forceinline__ static T load_col(const uint8_t* row, uint32_t c) {
-    return *reinterpret_cast<const uint64_t*>(row + c * 8u);
+    const uint64_t* q = reinterpret_cast<const uint64_t*>(row + c * 8u);
+    if constexpr (NT)
+      return __builtin_nontemporal_load(q);
+    else
+      return *q;
   }
   __device__ __forceinline__ static uint32_t cost(const T a, const T b, uint32_t acc) {
     return (uint32_t)__popcll(a ^ b) + acc;
@@ -1634,7 +1647,7 @@ __device__ __forceinline__ int dense_row_of(int i, int nc) {
 // pixels whose grid bits reach outside their window read mask words after
 // it. The view is a template argument: the search direction is then a
 // constant in every candidate's address.
-template <class DD, bool right, int R>
+template <class DD, bool right, int R, bool NT>
 __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, const KParams& p,
                                            int v0, int u0, int32_t* s_lut,
                                            typename DD::T* st, int* cnt) {
@@ -1676,7 +1689,7 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
     const uint8_t* row = other_desc + (size_t)min(v0 + r, g.h - 1) * g.w * DD::kBytes;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
-      sv[2 * r + k] = DD::load_col(row, (uint32_t)min(c0 + (int)threadIdx.x + 256 * k, c1));
+      sv[2 * r + k] = DD::template load_col<NT>(row, (uint32_t)min(c0 + (int)threadIdx.x + 256 * k, c1));
   }
   int32_t lv[3];  // the mirrored table's entries tid, tid + 256, tid + 512
 #pragma unroll
@@ -1697,8 +1710,12 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int vc = min(v0 + r, g.h - 1);
-    dpv[r] = (dplane + (size_t)vc * g.w)[(uint32_t)uc];
-    s[r] = DD::load_col(self_desc + (size_t)vc * g.w * DD::kBytes, (uint32_t)uc);
+    const int16_t* dprow = dplane + (size_t)vc * g.w;
+    if constexpr (NT)
+      dpv[r] = __builtin_nontemporal_load(&dprow[(uint32_t)uc]);
+    else
+      dpv[r] = dprow[(uint32_t)uc];
+    s[r] = DD::template load_col<NT>(self_desc + (size_t)vc * g.w * DD::kBytes, (uint32_t)uc);
     const int crow = grid_div(vc, g) * g.gw;  // wavefront-uniform
     cell[r] = crow + cu;
     rng[r] = (reinterpret_cast<const int2*>(grange) + crow)[(uint32_t)cu];
@@ -1730,7 +1747,11 @@ __device__ __forceinline__ void dense_rows(const Frame& F, const Geometry& g, co
   }
 }
 
-template <int R>
+// NT: the descriptors and the prior map are read with non-temporal loads (a
+// batch whose descriptors were written past the last-level cache: no line
+// of the reused descriptor buffers stays cached for the next batch's
+// non-temporal writes to meet).
+template <int R, bool NT = false>
 __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
   __shared__ int32_t s_lut[kLutSize];  // mirrored prior table, then zeros
   __shared__ int s_cnt[4];
@@ -1745,19 +1766,24 @@ __device__ __forceinline__ void dense_body(const Frame& F, int lb) {
   uint64_t* const s_stage64 = reinterpret_cast<uint64_t*>(s_stage);
   if (p.descriptor) {
     if (right)
-      dense_rows<CensusDense, true, R>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
+      dense_rows<CensusDense, true, R, NT>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
     else
-      dense_rows<CensusDense, false, R>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
+      dense_rows<CensusDense, false, R, NT>(F, g, p, v0, u0, s_lut, s_stage64, &cnt);
   } else {
     if (right)
-      dense_rows<GradDense, true, R>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
+      dense_rows<GradDense, true, R, NT>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
     else
-      dense_rows<GradDense, false, R>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
+      dense_rows<GradDense, false, R, NT>(F, g, p, v0, u0, s_lut, s_stage, &cnt);
   }
   cnt = wave_sum_i32(cnt);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) F.dense_counts[lb] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+}
+
+template <int R>
+__device__ __forceinline__ void dense_nt_body(const Frame& F, int lb) {
+  dense_body<R, true>(F, lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1939,6 +1965,23 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
 #define ELAS_NO_ATTR
 #define ELAS_STAGE_KERNELS(NAME, BODY, THREADS) \
   ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ELAS_NO_ATTR)
+// a batch launch only (the non-temporal variants: plain calls never need them)
+#define ELAS_BATCH_KERNEL_ATTR(NAME, BODY, THREADS, ATTR)                                \
+  __global__ __launch_bounds__(THREADS) ATTR void NAME##_batch(                         \
+      const Frame* __restrict__ frames, const int32_t* __restrict__ starts, int nf,      \
+      int bpf, uint32_t bmul) {                                                          \
+    const int b = xcd_remap(blockIdx.x, gridDim.x);                                     \
+    int f, lb;                                                                           \
+    if (bpf > 0) {                                                                       \
+      f = (int)__umulhi((uint32_t)b, bmul);                                              \
+      lb = b - f * bpf;                                                                  \
+    } else {                                                                             \
+      f = frame_of(starts, nf, b);                                                       \
+      lb = b - starts[f];                                                                \
+    }                                                                                    \
+    const Frame F = global_frame(frames[f], reinterpret_cast<const char*>(frames));     \
+    BODY(F, lb);                                                                         \
+  }
 // Eight wavefronts per SIMD: the register budget that lets the 1- and 2-row
 // dense tiles fill the SIMDs (their LDS allows it; the compiler would
 // otherwise take a few more VGPRs and stop at seven)
@@ -1947,9 +1990,9 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
 ELAS_STAGE_KERNELS(k_descriptor4, stage1_body<4>, 256)
 ELAS_STAGE_KERNELS(k_descriptor8, stage1_body<8>, 256)
 ELAS_STAGE_KERNELS(k_descriptor16, stage1_body<16>, 256)
-ELAS_STAGE_KERNELS(k_descriptor4nt, stage1_nt_body<4>, 256)
-ELAS_STAGE_KERNELS(k_descriptor8nt, stage1_nt_body<8>, 256)
-ELAS_STAGE_KERNELS(k_descriptor16nt, stage1_nt_body<16>, 256)
+ELAS_BATCH_KERNEL_ATTR(k_descriptor4nt, stage1_nt_body<4>, 256, ELAS_NO_ATTR)
+ELAS_BATCH_KERNEL_ATTR(k_descriptor8nt, stage1_nt_body<8>, 256, ELAS_NO_ATTR)
+ELAS_BATCH_KERNEL_ATTR(k_descriptor16nt, stage1_nt_body<16>, 256, ELAS_NO_ATTR)
 ELAS_STAGE_KERNELS(k_support, support_body, 256)
 ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
 ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
@@ -1958,12 +2001,16 @@ ELAS_STAGE_KERNELS(k_raster256, raster_body<256>, 256)
 ELAS_STAGE_KERNELS_ATTR(k_dense_r1, dense_body<1>, 256, ELAS_OCC8)
 ELAS_STAGE_KERNELS_ATTR(k_dense_r2, dense_body<2>, 256, ELAS_OCC8)
 ELAS_STAGE_KERNELS(k_dense_r4, dense_body<4>, 256)
+ELAS_BATCH_KERNEL_ATTR(k_dense_r1nt, dense_nt_body<1>, 256, ELAS_OCC8)
+ELAS_BATCH_KERNEL_ATTR(k_dense_r2nt, dense_nt_body<2>, 256, ELAS_OCC8)
+ELAS_BATCH_KERNEL_ATTR(k_dense_r4nt, dense_nt_body<4>, 256, ELAS_NO_ATTR)
 ELAS_STAGE_KERNELS(k_check, check_body, 256)
 ELAS_STAGE_KERNELS(k_redun, redun_body, 1024)
 ELAS_STAGE_KERNELS(k_median, median_body, 256)
 
 #undef ELAS_STAGE_KERNELS
 #undef ELAS_STAGE_KERNELS_ATTR
+#undef ELAS_BATCH_KERNEL_ATTR
 #undef ELAS_NO_ATTR
 #undef ELAS_OCC8
 
@@ -2120,11 +2167,11 @@ hipError_t launch_stage_batch(int32_t stage, const Frame* frames, const int32_t*
     case kStageRaster: go(k_raster256_batch, shm); break;
     case kStageDense:
       if (variant == 0)
-        go(k_dense_r1_batch, 0u);
+        desc_nt ? go(k_dense_r1nt_batch, 0u) : go(k_dense_r1_batch, 0u);
       else if (variant == 2)
-        go(k_dense_r4_batch, 0u);
+        desc_nt ? go(k_dense_r4nt_batch, 0u) : go(k_dense_r4_batch, 0u);
       else
-        go(k_dense_r2_batch, 0u);
+        desc_nt ? go(k_dense_r2nt_batch, 0u) : go(k_dense_r2_batch, 0u);
       break;
     case kStageCheck: go(k_check_batch, 0u); break;
     case kStageRedun: go(k_redun_batch, 0u); break;
