@@ -1943,29 +1943,8 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
 // A batch launch finds a block's frame as floor(b / bpf) = umulhi(b, bmul)
 // when every frame has bpf blocks (bmul = ceil(2^32 / bpf), exact for
 // b * bpf < 2^32, which the launcher checks), else by binary search.
-#define ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ATTR)                              \
-  __global__ __launch_bounds__(THREADS) ATTR void NAME(Frame F) {                       \
-    BODY(F, xcd_remap(blockIdx.x, gridDim.x));                                          \
-  }                                                                                     \
-  __global__ __launch_bounds__(THREADS) ATTR void NAME##_batch(                         \
-      const Frame* __restrict__ frames, const int32_t* __restrict__ starts, int nf,      \
-      int bpf, uint32_t bmul) {                                                          \
-    const int b = xcd_remap(blockIdx.x, gridDim.x);                                     \
-    int f, lb;                                                                           \
-    if (bpf > 0) {                                                                       \
-      f = (int)__umulhi((uint32_t)b, bmul);                                              \
-      lb = b - f * bpf;                                                                  \
-    } else {                                                                             \
-      f = frame_of(starts, nf, b);                                                       \
-      lb = b - starts[f];                                                                \
-    }                                                                                    \
-    const Frame F = global_frame(frames[f], reinterpret_cast<const char*>(frames));     \
-    BODY(F, lb);                                                                         \
-  }
-#define ELAS_NO_ATTR
-#define ELAS_STAGE_KERNELS(NAME, BODY, THREADS) \
-  ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ELAS_NO_ATTR)
-// a batch launch only (the non-temporal variants: plain calls never need them)
+// ELAS_BATCH_KERNEL_ATTR alone: the batch launch only (the non-temporal
+// variants: plain calls never need them).
 #define ELAS_BATCH_KERNEL_ATTR(NAME, BODY, THREADS, ATTR)                                \
   __global__ __launch_bounds__(THREADS) ATTR void NAME##_batch(                         \
       const Frame* __restrict__ frames, const int32_t* __restrict__ starts, int nf,      \
@@ -1982,6 +1961,14 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
     const Frame F = global_frame(frames[f], reinterpret_cast<const char*>(frames));     \
     BODY(F, lb);                                                                         \
   }
+#define ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ATTR)                              \
+  __global__ __launch_bounds__(THREADS) ATTR void NAME(Frame F) {                       \
+    BODY(F, xcd_remap(blockIdx.x, gridDim.x));                                          \
+  }                                                                                     \
+  ELAS_BATCH_KERNEL_ATTR(NAME, BODY, THREADS, ATTR)
+#define ELAS_NO_ATTR
+#define ELAS_STAGE_KERNELS(NAME, BODY, THREADS) \
+  ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ELAS_NO_ATTR)
 // Eight wavefronts per SIMD: the register budget that lets the 1- and 2-row
 // dense tiles fill the SIMDs (their LDS allows it; the compiler would
 // otherwise take a few more VGPRs and stop at seven)
