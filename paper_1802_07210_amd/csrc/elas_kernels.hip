@@ -1138,9 +1138,8 @@ __device__ __forceinline__ void clip_edge(int k, int c, int* lo, int* hi) {
 constexpr int kBandRowsMax = 4;
 constexpr int kWaveSpan = 64 * (2 + 2 * kBandRowsMax);  // per-wave span table in LDS
 
-// Two workgroup sizes: 1024 threads spread a band's span expansion over 16
-// waves (single frames whose bands all fit on the CUs at once), 256 threads
-// pack more bands per CU (larger frames, batches).
+// Two workgroup sizes: 1024 threads (single frames whose bands all fit on
+// the CUs at once), 256 threads (more bands per CU: larger frames, batches).
 template <int kRasterThreads>
 __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   // triangles per thread and gather step: 2048 per step with 1024 threads,
@@ -1156,7 +1155,7 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   int32_t* const tile = reinterpret_cast<int32_t*>(dyn_smem);  // band rows x width
   __shared__ int32_t rlist[kRasterList];
   __shared__ int32_t wspan[(kRasterThreads / 64) * kWaveSpan];
-  __shared__ int32_t s_wtot[kRasterThreads / 64];  // span pixels per wave (1024 threads)
+  __shared__ int32_t s_wtot[kRasterThreads / 64];  // span pixels per wave
   __shared__ int s_cnt, s_done;
   const Geometry g = F.g;
   const int band_rows = F.raster_rows;
@@ -1204,15 +1203,12 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
       __syncthreads();
       if (done || cnt > kRasterList - kRasterScan * kRasterThreads) break;
     }
-    // rasterise the gathered triangles into the tile. With 1024 threads,
-    // consecutive entries go to consecutive lanes, so only the first
-    // ceil(cnt / 64) waves work out spans, and every thread then takes an
-    // equal share of all span pixels; with 256 threads (several bands per
-    // CU), consecutive entries go to different waves and each wave expands
-    // its own spans
-    constexpr bool kShared = kRasterThreads == 1024;
+    // rasterise the gathered triangles into the tile: consecutive entries go
+    // to consecutive lanes, so only the first ceil(cnt / 64) waves work out
+    // spans (a wave's span setup costs the same for 1 entry as for 64), and
+    // every thread then takes an equal share of all span pixels
     for (int e0 = 0; e0 < cnt; e0 += kRasterThreads) {
-      const int e = kShared ? e0 + tid : e0 + lane * kRasterWaves + wid;
+      const int e = e0 + tid;
       int lo[kBandRowsMax], len[kBandRowsMax], tot = 0, rank = 0;
 #pragma unroll
       for (int q = 0; q < kBandRowsMax; ++q) {
@@ -1243,10 +1239,10 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
           tot += len[q];
         }
       }
-      // the spans (of all waves, wave by wave, or of this wave), lane by lane
-      // and row by row, form one pixel range; each thread takes a contiguous
-      // share of it, finds its first span by a search over the waves' and
-      // the lanes' offsets and walks on from there
+      // the spans of all waves, wave by wave, lane by lane and row by row,
+      // form one pixel range; each thread takes a contiguous share of it,
+      // finds its first span by a search over the waves' and the lanes'
+      // offsets and walks on from there
       const int incl = wave_scan_incl(tot);
       int32_t* W = wspan + wid * kWaveSpan;  // [offsets 64][lo 64x4][len 64x4][rank 64]
       W[lane] = incl - tot;
@@ -1256,27 +1252,17 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
         W[320 + 4 * lane + q] = len[q];
       }
       W[576 + lane] = rank;
-      int P, i;
-      if constexpr (kShared) {
-        if (lane == 63) s_wtot[wid] = incl;
-        __syncthreads();
-        P = 0;
+      if (lane == 63) s_wtot[wid] = incl;
+      __syncthreads();
+      int P = 0;
 #pragma unroll
-        for (int w = 0; w < kRasterWaves; ++w) P += s_wtot[w];
-        i = tid * ((P + kRasterThreads - 1) / kRasterThreads);
-      } else {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        P = __builtin_amdgcn_readlane(incl, 63);
-        i = lane * ((P + 63) >> 6);
-      }
-      const int iend = min(P, kShared ? i + (P + kRasterThreads - 1) / kRasterThreads
-                                      : i + ((P + 63) >> 6));
+      for (int w = 0; w < kRasterWaves; ++w) P += s_wtot[w];
+      const int share = (P + kRasterThreads - 1) / kRasterThreads;
+      int i = tid * share;
+      const int iend = min(P, i + share);
       if (i < iend) {
-        int w = kShared ? 0 : wid, wbase = 0;  // the wave holding pixel i
-        if constexpr (kShared)
-          while (wbase + s_wtot[w] <= i) wbase += s_wtot[w++];
+        int w = 0, wbase = 0;  // the wave holding pixel i
+        while (wbase + s_wtot[w] <= i) wbase += s_wtot[w++];
         const int32_t* Wt = wspan + w * kWaveSpan;
         const int li = i - wbase;
         int a = 0, b = 63;  // last lane whose pixels start at or before li
@@ -1310,10 +1296,7 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
           }
         }
       }
-      if constexpr (kShared)
-        __syncthreads();  // the span tables are written again by the next entries
-      else
-        __builtin_amdgcn_wave_barrier();
+      __syncthreads();  // the span tables are written again by the next entries
     }
     if (done || r0 >= nt) break;
   }
