@@ -764,7 +764,7 @@ __host__ __device__ __forceinline__ int filter_tiles_y(const Geometry& g) {
 // (the error term i * (m n - 2^32) / 2^32 stays below i n / 2^32 < 1)
 __device__ __forceinline__ int div_small(int i, uint32_t m) { return (int)__umulhi((uint32_t)i, m); }
 
-template <int RI, int RR>
+template <int RI, int RR, int T>
 __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
   const Geometry g = F.g;
   const KParams p = F.p;
@@ -804,20 +804,20 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
     const int gcount = g.gw * g.gh * g.gwords;
     uint32_t* gridL = F.gridL;
     uint32_t* gridR = F.gridR;
-    for (int i = lb * 1024 + tid; i < gcount; i += nblk * 1024) {
+    for (int i = lb * T + tid; i < gcount; i += nblk * T) {
       gridL[i] = 0u;
       gridR[i] = 0u;
     }
     const int rcount = 2 * g.gw * g.gh;
     int32_t* grL = F.grangeL;
     int32_t* grR = F.grangeR;
-    for (int i = lb * 1024 + tid; i < rcount; i += nblk * 1024) {
+    for (int i = lb * T + tid; i < rcount; i += nblk * T) {
       const int32_t init = (i & 1) ? -1 : kGridEmptyLo;
       grL[i] = init;
       grR[i] = init;
     }
   }
-  stage_copy<2, 1024>(
+  stage_copy<T == 1024 ? 2 : 3, T>(
       SR * SR,
       [&](int i) -> int {
         const int y = div_small(i, mSR), x = i - y * SR;
@@ -832,7 +832,7 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
   {
     const int npos = SI * SI;
     const int ntask = cdivd(npos * kFiltParts, 64) * 64;
-    for (int task = tid; task < ntask; task += 1024) {
+    for (int task = tid; task < ntask; task += T) {
       const int i = min(task / kFiltParts, npos - 1), part = task % kFiltParts;
       const int y = div_small(i, mSI), x = i - y * SI;
       const int d = sraw[(y + ri) * SR + (x + ri)];
@@ -878,7 +878,7 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
     }
     return;
   }
-  for (int i = tid; i < ft * SI; i += 1024) {
+  for (int i = tid; i < ft * SI; i += T) {
     const int y = div_small(i, mSI), x = i - y * SI;
     const int d = sinc[(y + rr) * SI + x];
     int res = d;
@@ -935,11 +935,15 @@ __device__ __forceinline__ void filter_windows(const Frame& F, int lb) {
 }
 
 // The default windows (5 and 5 lattice steps) at compile time, else any.
+// T threads per tile: 1024 for a single frame (few tiles, each alone on a
+// CU), 512 in batches (four tiles share a CU, so one tile's barrier phases
+// overlap another's work: 16 x 16 tiles over 32 pairs 34.4 -> 23.5 us)
+template <int T>
 __device__ __forceinline__ void filter_body(const Frame& F, int lb) {
   if (F.p.incon_window == 5 && F.p.redun_max_dist == 5)
-    filter_windows<5, 5>(F, lb);
+    filter_windows<5, 5, T>(F, lb);
   else
-    filter_windows<0, 0>(F, lb);
+    filter_windows<0, 0, T>(F, lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1944,10 +1948,12 @@ __device__ __forceinline__ void median_body(const Frame& F, int lb) {
     const Frame F = global_frame(frames[f], reinterpret_cast<const char*>(frames));     \
     BODY(F, lb);                                                                         \
   }
-#define ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ATTR)                              \
+#define ELAS_FRAME_KERNEL_ATTR(NAME, BODY, THREADS, ATTR)                              \
   __global__ __launch_bounds__(THREADS) ATTR void NAME(Frame F) {                       \
     BODY(F, xcd_remap(blockIdx.x, gridDim.x));                                          \
-  }                                                                                     \
+  }
+#define ELAS_STAGE_KERNELS_ATTR(NAME, BODY, THREADS, ATTR)                              \
+  ELAS_FRAME_KERNEL_ATTR(NAME, BODY, THREADS, ATTR)                                     \
   ELAS_BATCH_KERNEL_ATTR(NAME, BODY, THREADS, ATTR)
 #define ELAS_NO_ATTR
 #define ELAS_STAGE_KERNELS(NAME, BODY, THREADS) \
@@ -1964,7 +1970,8 @@ ELAS_BATCH_KERNEL_ATTR(k_descriptor4nt, stage1_nt_body<4>, 256, ELAS_NO_ATTR)
 ELAS_BATCH_KERNEL_ATTR(k_descriptor8nt, stage1_nt_body<8>, 256, ELAS_NO_ATTR)
 ELAS_BATCH_KERNEL_ATTR(k_descriptor16nt, stage1_nt_body<16>, 256, ELAS_NO_ATTR)
 ELAS_STAGE_KERNELS(k_support, support_body, 256)
-ELAS_STAGE_KERNELS(k_filter, filter_body, 1024)
+ELAS_FRAME_KERNEL_ATTR(k_filter, filter_body<1024>, 1024, ELAS_NO_ATTR)
+ELAS_BATCH_KERNEL_ATTR(k_filter, filter_body<512>, 512, ELAS_NO_ATTR)
 ELAS_STAGE_KERNELS(k_rows, rows_body, 64)
 ELAS_STAGE_KERNELS(k_raster, raster_body<1024>, 1024)
 ELAS_STAGE_KERNELS(k_raster256, raster_body<256>, 256)
@@ -1981,6 +1988,7 @@ ELAS_STAGE_KERNELS(k_median, median_body, 256)
 #undef ELAS_STAGE_KERNELS
 #undef ELAS_STAGE_KERNELS_ATTR
 #undef ELAS_BATCH_KERNEL_ATTR
+#undef ELAS_FRAME_KERNEL_ATTR
 #undef ELAS_NO_ATTR
 #undef ELAS_OCC8
 
@@ -1992,7 +2000,7 @@ size_t filter_lds_bytes(const Geometry& g, const KParams& p) {
 
 int stage_threads(int32_t stage) {
   switch (stage) {
-    case kStageFilter: return 1024;
+    case kStageFilter: return 512;  // the batched launch; single frames take 1024
     case kStageRedun: return 1024;
     case kStageRows: return 64;
     case kStageRaster: return 256;  // the batched launch; single frames choose in launch_stage
@@ -2049,7 +2057,8 @@ hipError_t launch_stage(int32_t stage, const Frame& f, int variant, hipStream_t 
   if (nb <= 0) return hipSuccess;
   // the wide raster workgroup when every band of the frame gets a CU
   const bool wide_raster = stage == kStageRaster && nb <= 256;
-  const dim3 grid(nb), block(wide_raster ? 1024 : stage_threads(stage));
+  const dim3 grid(nb),
+      block(wide_raster || stage == kStageFilter ? 1024 : stage_threads(stage));
   const uint32_t lds = (uint32_t)stage_lds(stage, f.g, f.p);
   const bool timed = start || stop;
   auto go = [&](auto kernel) {
