@@ -1128,39 +1128,61 @@ __device__ __forceinline__ int floordiv_pos(int a, int b) {
   return (int)floor(__ddiv_rn((double)a, (double)b));
 }
 
-// Narrows [lo, hi] to the u with k*u + c >= 0.
+// Byte offset of record t (24 B each; t * 24 < 2^32 for every admitted mesh)
+// as (t + 2t) << 3: two full-rate operations where a 32-bit multiply issues
+// at a quarter of the rate. The addition is written out so that it is not
+// folded back into a multiply.
+__device__ __forceinline__ uint32_t times24(int t) {
+  uint32_t x;
+  asm("v_lshl_add_u32 %0, %1, 1, %1" : "=v"(x) : "v"(t));
+  return x << 3;
+}
+
+// Narrows [lo, hi] to the u with k*u + c >= 0. One division whatever the
+// sign of k, and selects after it: a wavefront's lanes see both signs, and a
+// branch per sign would run both division sequences.
 __device__ __forceinline__ void clip_edge(int k, int c, int* lo, int* hi) {
-  if (k > 0) {
-    *lo = max(*lo, -floordiv_pos(c, k));  // u >= ceil(-c / k)
-  } else if (k < 0) {
-    *hi = min(*hi, floordiv_pos(c, -k));  // u <= floor(c / -k)
-  } else if (c < 0) {
+  const int x = floordiv_pos(c, k < 0 ? -k : (k > 0 ? k : 1));
+  const int nlo = max(*lo, -x);  // k > 0: u >= ceil(-c / k) = -floor(c / k)
+  const int nhi = min(*hi, x);   // k < 0: u <= floor(c / -k)
+  if (k > 0)
+    *lo = nlo;
+  else if (k < 0)
+    *hi = nhi;
+  else if (c < 0)
     *hi = *lo - 1;
-  }
 }
 
 constexpr int kBandRowsMax = 4;
-constexpr int kWaveSpan = 64 * (2 + 2 * kBandRowsMax);  // per-wave span table in LDS
+// per-wave span table in LDS: pixel offsets of the lanes, one packed span
+// (first column | length << 16; 0 when empty) per lane and band row, ranks
+constexpr int kWaveSpan = 64 * (2 + kBandRowsMax);
 
 // Two workgroup sizes: 1024 threads (single frames whose bands all fit on
 // the CUs at once), 256 threads (more bands per CU: larger frames, batches).
 template <int kRasterThreads>
 __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   // triangles per thread and gather step: 2048 per step with 1024 threads,
-  // 1024 with 256
-  constexpr int kRasterScan = kRasterThreads == 1024 ? 2 : 4;
+  // 768 with 256
+  constexpr int kRasterScan = kRasterThreads == 1024 ? 2 : 3;
   constexpr int kRasterOut = 2048 / kRasterThreads < 4 ? 4 : 2048 / kRasterThreads;
   constexpr int kRasterWaves = kRasterThreads / 64;
-  // ranks of gathered triangles per pass: the 256-thread variant keeps its
-  // LDS small, so that more bands share a CU (a band of a few rows overlaps
-  // tens of triangles; a pass ends when the list could overflow)
-  constexpr int kRasterList = kRasterThreads == 1024 ? 4096 : 1280;
+  // ranks of gathered triangles per pass (a band of a few rows overlaps tens
+  // of triangles; a pass ends when the list could overflow). The 256-thread
+  // variant keeps its static LDS at 10 KB: with the 10 KB owner tile of a
+  // 640-wide band of four rows a workgroup takes 20 KB, and eight of them
+  // (32 wavefronts) share a CU's 160 KB.
+  constexpr int kRasterSmall = 10240 - 4 * kRasterWaves * (kWaveSpan + 1) - 8;
+  constexpr int kRasterList = kRasterThreads == 1024 ? 4096 : kRasterSmall / 4;
   static_assert(kRasterScan * kRasterThreads <= kRasterList, "a gather step must fit the list");
   int32_t* const tile = reinterpret_cast<int32_t*>(dyn_smem);  // band rows x width
   __shared__ int32_t rlist[kRasterList];
   __shared__ int32_t wspan[(kRasterThreads / 64) * kWaveSpan];
   __shared__ int32_t s_wtot[kRasterThreads / 64];  // span pixels per wave
   __shared__ int s_cnt, s_done;
+  static_assert(kRasterThreads == 1024 ||
+                    sizeof(rlist) + sizeof(wspan) + sizeof(s_wtot) + 2 * sizeof(int) == 10240,
+                "static LDS of the 256-thread raster");
   const Geometry g = F.g;
   const int band_rows = F.raster_rows;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1170,6 +1192,9 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   const int rows = v1 - v0 + 1;
   const int ntL = F.hdr->ntri[0], nt = view ? F.hdr->ntri[1] : ntL;
   const RasterTri* vt = F.tris + (view ? ntL : 0);
+  // the view's records as a wavefront-uniform base with 32-bit byte offsets
+  // (24 B per record)
+  const uint8_t* const vtb = reinterpret_cast<const uint8_t*>(vt);
   for (int i = tid; i < rows * g.w; i += kRasterThreads) tile[i] = kNoOwner;
   int r0 = 0;
   for (;;) {
@@ -1185,16 +1210,20 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
 #pragma unroll
       for (int k = 0; k < kRasterScan; ++k) {
         const int r = min(r0 + k * kRasterThreads + tid, nt - 1);  // in bounds: nt > 0 here
-        tv[k][0] = vt[r].v[0];
-        tv[k][1] = vt[r].v[1];
-        tv[k][2] = vt[r].v[2];
+        const RasterTri* T = reinterpret_cast<const RasterTri*>(vtb + times24(r));
+        tv[k][0] = T->v[0];
+        tv[k][1] = T->v[1];
+        tv[k][2] = T->v[2];
       }
 #pragma unroll
       for (int k = 0; k < kRasterScan; ++k) {
         const int r = r0 + k * kRasterThreads + tid;
-        if (r >= nt) continue;
-        const int vmin = min((int)tv[k][0], min((int)tv[k][1], (int)tv[k][2]));
-        const int vmax = max((int)tv[k][0], max((int)tv[k][1], (int)tv[k][2]));
+        int vmin = min((int)tv[k][0], min((int)tv[k][1], (int)tv[k][2]));
+        int vmax = max((int)tv[k][0], max((int)tv[k][1], (int)tv[k][2]));
+        if (r >= nt) {  // past the list: neither listed nor a stop (v0 >= 0)
+          vmin = 0;
+          vmax = -1;
+        }
         if (vmin > v1)
           s_done = 1;  // so does every later triangle
         else if (vmax >= v0)
@@ -1221,7 +1250,7 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
       }
       if (e < cnt) {
         rank = rlist[e];
-        const RasterTri T = vt[rank];
+        const RasterTri T = *reinterpret_cast<const RasterTri*>(vtb + times24(rank));
         // vertices lie in the image; the clamp only keeps every write inside it
         const int umin = max(0, min((int)T.u[0], min((int)T.u[1], (int)T.u[2])));
         const int umax = min(g.w - 1, max((int)T.u[0], max((int)T.u[1], (int)T.u[2])));
@@ -1248,14 +1277,12 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
       // finds its first span by a search over the waves' and the lanes'
       // offsets and walks on from there
       const int incl = wave_scan_incl(tot);
-      int32_t* W = wspan + wid * kWaveSpan;  // [offsets 64][lo 64x4][len 64x4][rank 64]
+      int32_t* W = wspan + wid * kWaveSpan;  // [offsets 64][spans 64x4][rank 64]
       W[lane] = incl - tot;
 #pragma unroll
-      for (int q = 0; q < kBandRowsMax; ++q) {
-        W[64 + 4 * lane + q] = lo[q];
-        W[320 + 4 * lane + q] = len[q];
-      }
-      W[576 + lane] = rank;
+      for (int q = 0; q < kBandRowsMax; ++q)  // a non-empty span lies in the row: 0 <= lo < w
+        W[64 + 4 * lane + q] = len[q] > 0 ? lo[q] | (len[q] << 16) : 0;
+      W[320 + lane] = rank;
       if (lane == 63) s_wtot[wid] = incl;
       __syncthreads();
       int P = 0;
@@ -1274,18 +1301,26 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
           const int mid = (a + b + 1) >> 1;
           if (Wt[mid] <= li) a = mid; else b = mid - 1;
         }
-        int j = a, off = li - Wt[a], q = 0;
-        while (off >= Wt[320 + 4 * j + q]) {
-          off -= Wt[320 + 4 * j + q];
+        int j = a, off = li - Wt[a], q = 0, sp;
+        while (off >= ((sp = Wt[64 + 4 * j + q]) >> 16)) {
+          off -= sp >> 16;
           ++q;
         }
-        int L = Wt[320 + 4 * j + q], S = Wt[64 + 4 * j + q], R = Wt[576 + j];
+        // the rest of the current span from px on, then span after span
+        int32_t* px = tile + q * g.w + (sp & 0xFFFF) + off;
+        int R = Wt[320 + j];
+        int left = (sp >> 16) - off;  // >= 1
+        int n = iend - i;                       // >= 1
+        // R comes from an LDS read: wait for it once per span, not before
+        // every atomic of the loop (the atomics return nothing, so nothing
+        // else in the loop waits)
+        asm volatile("" ::"v"(R));
         for (;;) {
-          atomicMin(&tile[q * g.w + S + off], R);
-          if (++i >= iend) break;
-          if (++off == L) {  // on to the next non-empty span (one exists: i < P)
-            off = 0;
-            do {
+          atomicMin(px, R);
+          if (--n == 0) break;
+          ++px;
+          if (--left == 0) {
+            do {  // on to the next non-empty span (one exists: pixels remain)
               if (++q == kBandRowsMax) {
                 q = 0;
                 if (++j == 64) {
@@ -1293,10 +1328,12 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
                   Wt += kWaveSpan;
                 }
               }
-              L = Wt[320 + 4 * j + q];
-            } while (L == 0);
-            S = Wt[64 + 4 * j + q];
-            R = Wt[576 + j];
+              sp = Wt[64 + 4 * j + q];
+            } while (sp == 0);
+            px = tile + q * g.w + (sp & 0xFFFF);
+            left = sp >> 16;
+            R = Wt[320 + j];
+            asm volatile("" ::"v"(R));
           }
         }
       }
@@ -1312,10 +1349,18 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
   int32_t* ownR = F.ownerR;
   int16_t* dplL = F.dplaneL;
   int16_t* dplR = F.dplaneR;
-  int32_t* owner = (view ? ownR : ownL) + (size_t)v0 * g.w;
-  int16_t* dpl = (view ? dplR : dplL) + (size_t)v0 * g.w;
+  // band rows as wavefront-uniform bases with 32-bit byte offsets
+  uint8_t* const owner = reinterpret_cast<uint8_t*>((view ? ownR : ownL) + (size_t)v0 * g.w);
+  uint8_t* const dpl = reinterpret_cast<uint8_t*>((view ? dplR : dplL) + (size_t)v0 * g.w);
   const int dmin = F.p.dmin, dmax = F.p.dmax;
   const int npx = rows * g.w;
+  // a thread's pixels are tid, tid + T, tid + 2T, ... (T threads): the column
+  // u and band row q of each follow from the previous by adding T mod w and
+  // T div w and one wrap (row of a band index by the width multiplier, exact
+  // for T * w < 2^40)
+  const int qstep = (int)(((uint64_t)kRasterThreads * g.rowmul) >> 40);
+  const int ustep = kRasterThreads - qstep * g.w;
+  int q = (int)(((uint64_t)tid * g.rowmul) >> 40), u = tid - q * g.w;
   // kRasterOut pixels per thread at a time: their plane loads (from an
   // in-bounds triangle even without an owner) are all in flight together
   for (int i0 = 0; i0 < npx; i0 += kRasterOut * kRasterThreads) {
@@ -1326,29 +1371,33 @@ __device__ __forceinline__ void raster_body(const Frame& F, int lb) {
       const int i = i0 + k * kRasterThreads + tid;
       o[k] = i < npx ? tile[i] : kNoOwner;
       const int t = (o[k] != kNoOwner) ? o[k] : 0;
-      a[k] = vt[t].a;
-      b[k] = vt[t].b;
-      c[k] = vt[t].c;
+      const RasterTri* T = reinterpret_cast<const RasterTri*>(vtb + times24(t));
+      a[k] = T->a;
+      b[k] = T->b;
+      c[k] = T->c;
     }
 #pragma unroll
     for (int k = 0; k < kRasterOut; ++k) {
       const int i = i0 + k * kRasterThreads + tid;
-      if (i >= npx) continue;
-      int dp = -1;
-      if (o[k] != kNoOwner) {
-        int q = 0;  // band row: i / g.w for i < rows * g.w, by comparisons
-#pragma unroll
-        for (int rr = 1; rr < kBandRowsMax; ++rr) q += i >= rr * g.w ? 1 : 0;
-        const int u = i - q * g.w, v = v0 + q;
-        const float mu = __fadd_rn(__fadd_rn(__fmul_rn(a[k], (float)u), __fmul_rn(b[k], (float)v)),
-                                   c[k]);
-        const float f = floorf(__fadd_rn(mu, 0.5f));
-        dp = f < (float)dmin ? dmin : (f > (float)dmax ? dmax : (int)f);
+      if (i < npx) {
+        int dp = -1;
+        if (o[k] != kNoOwner) {
+          const float mu = __fadd_rn(
+              __fadd_rn(__fmul_rn(a[k], (float)u), __fmul_rn(b[k], (float)(v0 + q))), c[k]);
+          const float f = floorf(__fadd_rn(mu, 0.5f));
+          dp = f < (float)dmin ? dmin : (f > (float)dmax ? dmax : (int)f);
+        }
+        // the owner map is read by no later stage: it goes straight to HBM
+        // (non-temporal), leaving the caches to the prior and the descriptors
+        __builtin_nontemporal_store(o[k], reinterpret_cast<int32_t*>(owner + (uint32_t)i * 4u));
+        *reinterpret_cast<int16_t*>(dpl + (uint32_t)i * 2u) = (int16_t)dp;
       }
-      // the owner map is read by no later stage: it goes straight to HBM
-      // (non-temporal), leaving the caches to the prior and the descriptors
-      __builtin_nontemporal_store(o[k], &owner[i]);
-      dpl[i] = (int16_t)dp;
+      u += ustep;
+      q += qstep;
+      if (u >= g.w) {
+        u -= g.w;
+        ++q;
+      }
     }
   }
 }
