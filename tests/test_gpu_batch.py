@@ -311,3 +311,39 @@ def test_support_run_lengths_bit_exact(E, run):
     t = ref.process(ref.params(disp_max=D - 1), p.left, p.right)
     assert np.array_equal(sL.cpu().numpy(), t.outL)
     assert np.array_equal(sR.cpu().numpy(), t.outR)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_dense_support_many_triangles_per_band(E, graph):
+    # a unit lattice with the support filters off keeps ~12 k points and
+    # ~24 k triangles per view, ~1200-1400 of them over every 4-row raster
+    # band: the batched raster gathers and rasterises each band in several
+    # passes, the single-frame raster in many gather steps. Batched (beside an
+    # ordinary pair) and single calls both give the oracle's maps.
+    dev = torch.device("cuda:0")
+    dense = dict(disp_max=31, candidate_stepsize=1, redun_max_dist=0, incon_min_support=0)
+    plain = dict(disp_max=63)
+    hd, hp = E.Elas(**dense), E.Elas(**plain)
+    pd = synth.make_pair(synth.SceneConfig(160, 120, 32, 4, 0.05, 4.0, 27.0, 2.0, 0.05, seed=5))
+    pp = synth.make_pair(synth.SceneConfig(160, 96, 64, 4, 0.05, 4.0, 59.0, 2.0, 0.1, seed=21))
+    cases = [(pd, dense, hd), (pp, plain, hp)]
+    hp.set_batch_flags(graph=graph, autotune=False)
+    items, outs = [], []
+    for p, _, h in cases:
+        L = torch.from_numpy(p.left).to(dev)
+        R = torch.from_numpy(p.right).to(dev)
+        oL = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        oR = torch.full(p.left.shape, -7, dtype=torch.int16, device=dev)
+        items.append((L, R, oL, oR, h))
+        outs.append((oL, oR))
+    for _ in range(2):
+        hp.process_batch(items)
+    sL, sR = hd.process(items[0][0], items[0][1])
+    torch.cuda.synchronize()
+    refs = [ref.process(ref.params(**kw), p.left, p.right) for p, kw, _ in cases]
+    assert len(refs[0].recL) > 20000 and len(refs[0].recR) > 20000
+    for t, (oL, oR) in zip(refs, outs):
+        assert np.array_equal(oL.cpu().numpy(), t.outL)
+        assert np.array_equal(oR.cpu().numpy(), t.outR)
+    assert np.array_equal(sL.cpu().numpy(), refs[0].outL)
+    assert np.array_equal(sR.cpu().numpy(), refs[0].outR)
