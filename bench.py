@@ -71,7 +71,10 @@ KERNEL_NAMES = {"descriptor": "k_descriptor8", "support": "k_support", "filter":
 
 
 COPY_BYTES = 256 << 20
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1802_07210_amd", "csrc", "elas_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1802_07210_amd", "csrc")
+# the kernels' source and the headers compiled into them (the stored
+# profiles carry the same hash)
+KERNEL_SOURCES = [os.path.join(CSRC, n) for n in ("elas_kernels.hip", "elas_internal.h", "elas_wave.h")]
 PROFILES = os.path.join(ROOT, "profiles")
 
 # Variants measured beside the headline configuration (parameter overrides).
@@ -89,8 +92,11 @@ VARIANTS = {
 
 
 def source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_file(kernel: str, workload: str) -> str:

@@ -1224,7 +1224,9 @@ int autotune(elas_handle* h, BatchCtx* c, const std::vector<Frame>& frames,
         starts.push_back(starts.back() + stage_blocks(stages[k], f.g, f.p, lv));
       uint8_t* dev = static_cast<uint8_t*>(c->tune_dev);
       const size_t soff = align256(fr.size() * sizeof(Frame));
-      HIP_TRY(hipMemcpy(dev, fr.data(), fr.size() * sizeof(Frame), hipMemcpyHostToDevice));
+      std::vector<Frame> table(fr);  // pointers as offsets from the table's address
+      for (Frame& f : table) frame_to_table(&f, reinterpret_cast<uintptr_t>(dev));
+      HIP_TRY(hipMemcpy(dev, table.data(), table.size() * sizeof(Frame), hipMemcpyHostToDevice));
       HIP_TRY(hipMemcpy(dev + soff, starts.data(), starts.size() * 4, hipMemcpyHostToDevice));
       size_t lds = 0;
       for (const Frame& f : fr) lds = std::max(lds, stage_lds(stages[k], f.g, f.p));
@@ -1351,6 +1353,21 @@ int elas::process_batch(elas_handle* h, int32_t n, const elas_pair* pairs, hipSt
     const size_t cap = align256(blob.size() * 2);
     HIP_TRY(hipHostMalloc(&c->host[k], cap, hipHostMallocDefault));
     c->host_cap[k] = cap;
+  }
+  // each frame table holds its pointers as offsets from its own device
+  // address (several launches share the main table: converted once)
+  std::vector<size_t> converted;
+  for (const LaunchRec& r : recs) {
+    if (std::find(converted.begin(), converted.end(), r.table_off) != converted.end()) continue;
+    converted.push_back(r.table_off);
+    const uintptr_t table = reinterpret_cast<uintptr_t>(c->dev) + r.table_off;
+    for (int32_t i = 0; i < r.nf; ++i) {
+      Frame f;
+      uint8_t* at = blob.data() + r.table_off + (size_t)i * sizeof(Frame);
+      std::memcpy(&f, at, sizeof(Frame));
+      frame_to_table(&f, table);
+      std::memcpy(at, &f, sizeof(Frame));
+    }
   }
   std::memcpy(c->host[k], blob.data(), blob.size());
   HIP_TRY(hipMemcpyAsync(c->dev, c->host[k], blob.size(), hipMemcpyHostToDevice, stream));

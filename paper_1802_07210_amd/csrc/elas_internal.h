@@ -152,56 +152,30 @@ struct Frame {
                          // status) when a view fails; null: the header only
 };
 
-// Pointers read from the frame table are rebuilt as offsets from the table's
-// own address (a kernel argument, so a global-memory pointer): the compiler
-// then emits global rather than flat memory instructions for them.
-template <class T>
-__device__ __forceinline__ T* rebase(const char* base, T* p) {
-  return reinterpret_cast<T*>(const_cast<char*>(base) + ((uintptr_t)p - (uintptr_t)base));
+// Every device pointer of a frame, as X(member).
+#define ELAS_FRAME_POINTERS(X) X(left) X(right) X(descL) X(descR) X(csupL) X(csupR) \
+  X(dcan_raw) X(dcan_incon) X(dcan_vert) X(dcan_final) X(evals) X(gridL) X(gridR) X(grangeL) \
+  X(grangeR) X(rowsL) X(rowsR) X(cnt) X(hdr) X(ptsL) X(ptsR) X(recsL) X(recsR) X(planesL) \
+  X(planesR) X(tris) X(mesh_scratch) X(ownerL) X(ownerR) X(dplaneL) X(dplaneR) X(rawL) X(rawR) \
+  X(lut) X(dense_counts) X(outL) X(outR) X(chkL) X(chkR) X(mfail)
+
+// A frame table in device memory holds each pointer as its byte offset from
+// the table's own address, and a batched kernel adds that address (a kernel
+// argument, so a global-memory pointer) back: the compiler then emits global
+// rather than flat memory instructions for them, at one 64-bit scalar add per
+// pointer. Offsets are taken modulo 2^64, so a null pointer comes back null.
+inline void frame_to_table(Frame* f, uintptr_t table) {
+#define ELAS_TO_OFFSET(m) f->m = reinterpret_cast<decltype(f->m)>((uintptr_t)f->m - table);
+  ELAS_FRAME_POINTERS(ELAS_TO_OFFSET)
+#undef ELAS_TO_OFFSET
 }
 
 __device__ __forceinline__ Frame global_frame(const Frame& t, const char* base) {
   Frame F = t;
-  F.left = rebase(base, F.left);
-  F.right = rebase(base, F.right);
-  F.descL = rebase(base, F.descL);
-  F.descR = rebase(base, F.descR);
-  F.csupL = rebase(base, F.csupL);
-  F.csupR = rebase(base, F.csupR);
-  F.dcan_raw = rebase(base, F.dcan_raw);
-  F.dcan_incon = rebase(base, F.dcan_incon);
-  F.dcan_vert = rebase(base, F.dcan_vert);
-  F.dcan_final = rebase(base, F.dcan_final);
-  F.evals = rebase(base, F.evals);
-  F.gridL = rebase(base, F.gridL);
-  F.gridR = rebase(base, F.gridR);
-  F.grangeL = rebase(base, F.grangeL);
-  F.grangeR = rebase(base, F.grangeR);
-  F.rowsL = rebase(base, F.rowsL);
-  F.rowsR = rebase(base, F.rowsR);
-  F.cnt = rebase(base, F.cnt);
-  F.hdr = rebase(base, F.hdr);
-  F.ptsL = rebase(base, F.ptsL);
-  F.ptsR = rebase(base, F.ptsR);
-  F.recsL = rebase(base, F.recsL);
-  F.recsR = rebase(base, F.recsR);
-  F.planesL = rebase(base, F.planesL);
-  F.planesR = rebase(base, F.planesR);
-  F.tris = rebase(base, F.tris);
-  F.mesh_scratch = rebase(base, F.mesh_scratch);
-  F.ownerL = rebase(base, F.ownerL);
-  F.ownerR = rebase(base, F.ownerR);
-  F.dplaneL = rebase(base, F.dplaneL);
-  F.dplaneR = rebase(base, F.dplaneR);
-  F.rawL = rebase(base, F.rawL);
-  F.rawR = rebase(base, F.rawR);
-  F.lut = rebase(base, F.lut);
-  F.dense_counts = rebase(base, F.dense_counts);
-  F.outL = rebase(base, F.outL);
-  F.outR = rebase(base, F.outR);
-  F.chkL = rebase(base, F.chkL);
-  F.chkR = rebase(base, F.chkR);
-  F.mfail = rebase(base, F.mfail);
+#define ELAS_FROM_OFFSET(m) \
+  F.m = reinterpret_cast<decltype(F.m)>(const_cast<char*>(base) + (uintptr_t)t.m);
+  ELAS_FRAME_POINTERS(ELAS_FROM_OFFSET)
+#undef ELAS_FROM_OFFSET
   return F;
 }
 

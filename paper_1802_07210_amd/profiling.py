@@ -42,7 +42,18 @@ import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1802_07210_amd", "csrc", "elas_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1802_07210_amd", "csrc")
+# the kernels' source and the headers compiled into them
+KERNEL_SOURCES = [os.path.join(CSRC, n) for n in ("elas_kernels.hip", "elas_internal.h", "elas_wave.h")]
+
+
+def kernel_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over the kernels' source files."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _one(dirpath: str, suffix: str) -> str:
@@ -128,8 +139,7 @@ def cmd_traffic(args):
         raise SystemExit(f"{args.kernel} not among {sorted(fetch)}")
     fb = fetch[args.kernel][0] * 1024.0 * f_fetch
     wb = write[args.kernel][0] * 1024.0 * f_write
-    with open(KERNEL_SOURCE, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    sha = kernel_source_hash()
     rec = {"kernel": args.kernel, "workload": args.workload,
            "bytes_per_launch": round(fb + wb), "fetch_bytes": round(fb), "write_bytes": round(wb),
            "fetch_kib_raw": fetch[args.kernel][0], "write_kib_raw": write[args.kernel][0],
@@ -187,8 +197,7 @@ def valu_record(dirpath: str) -> dict:
 
 def cmd_valu(args):
     rec = valu_record(args.dir)
-    with open(KERNEL_SOURCE, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    sha = kernel_source_hash()
     with open(args.json, "w") as f:
         json.dump({"workload": args.workload, "valu_issue_peak_per_s": VALU_ISSUE_PEAK,
                    "kernels": rec, "source_sha256_16": sha}, f, indent=1)
