@@ -1114,8 +1114,8 @@ __device__ __forceinline__ void rows_body(const Frame& F, int lb) {
 // triangles whose rows overlap the band (canonical order sorts triangles by
 // their top vertex, so the scan stops at the first triangle starting below
 // the band), computes the exact integer span of each of their band rows from
-// the three edge functions, spreads each wave's span pixels evenly over its
-// lanes, resolves each pixel with an LDS atomicMin, and finally writes the
+// the three edge functions, spreads all span pixels evenly over its
+// threads, resolves each pixel with an LDS atomicMin, and finally writes the
 // whole tile with coalesced stores, together with each pixel's prior
 // disparity (the owning plane's mean). Every pixel is written.
 // ---------------------------------------------------------------------------
@@ -1128,8 +1128,8 @@ __device__ __forceinline__ int floordiv_pos(int a, int b) {
   return (int)floor(__ddiv_rn((double)a, (double)b));
 }
 
-// Byte offset of record t (24 B each; t * 24 < 2^32 for every admitted mesh)
-// as (t + 2t) << 3: two full-rate operations where a 32-bit multiply issues
+// Byte offset of record t (24 B each; a view has at most 2 * 8192^2 + 2
+// triangles, so t * 24 < 2^32) as (t + 2t) << 3: two full-rate operations where a 32-bit multiply issues
 // at a quarter of the rate. The addition is written out so that it is not
 // folded back into a multiply.
 __device__ __forceinline__ uint32_t times24(int t) {
